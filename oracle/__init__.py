@@ -1,0 +1,250 @@
+"""CPU oracle of the adaptive k-NN query path (PUFFINN, ESA 2019) -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py``
+may import this package.  It wraps ``liboracle.so`` (plain C, see ``puffinn_oracle.c``)
+with numpy and shares no code with the GPU library in ``paper_1906_12211_amd``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "puffinn_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+RULE_EXACT = 0
+RULE_ALG1 = 1
+DEFAULT_K = 24
+DEFAULT_M = 32
+DEFAULT_B = 12
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so in place (gcc, OpenMP, no FMA contraction)."""
+    cmd = [
+        "gcc", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math",
+        "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm",
+    ]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+_D = ctypes.c_double
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.oracle_splitmix64.restype = _U64
+        L.oracle_splitmix64.argtypes = [_U64, _U64]
+        L.oracle_hyperplanes.restype = None
+        L.oracle_hyperplanes.argtypes = [_U64, _I64, _I32, _P]
+        L.oracle_normalize.restype = _I64
+        L.oracle_normalize.argtypes = [_P, _I64, _I32]
+        L.oracle_num_tables.restype = _I64
+        L.oracle_num_tables.argtypes = [_I64, _I32, _I32, _I32, _U64]
+        L.oracle_hash.restype = None
+        L.oracle_hash.argtypes = [_P, _I64, _I32, _P, _I32, _I32, _I32, _P, _P]
+        L.oracle_build_tables.restype = ctypes.c_int
+        L.oracle_build_tables.argtypes = [_P, _I64, _I32, _I32, _P, _P, _P]
+        L.oracle_table_sketches.restype = None
+        L.oracle_table_sketches.argtypes = [_P, _P, _I64, _I32, _I32, _P]
+        L.oracle_ip32.restype = ctypes.c_float
+        L.oracle_ip32.argtypes = [_P, _P, _I32]
+        L.oracle_ip64.restype = _D
+        L.oracle_ip64.argtypes = [_P, _P, _I32]
+        L.oracle_collision_prob.restype = _D
+        L.oracle_collision_prob.argtypes = [ctypes.c_float]
+        L.oracle_tau.restype = _D
+        L.oracle_tau.argtypes = [ctypes.c_float, _D]
+        L.oracle_stop.restype = ctypes.c_int
+        L.oracle_stop.argtypes = [ctypes.c_float, _I32, _I32, _D, _I32, ctypes.POINTER(_D)]
+        L.oracle_search.restype = ctypes.c_int
+        L.oracle_search.argtypes = [
+            _P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32,
+            _P, _I64, _I32, _D, _D, _I32, _I32, _I32,
+            _P, _P, _P, _P, _P, _P, _P, _P, _P,
+        ]
+        L.oracle_bruteforce.restype = ctypes.c_int
+        L.oracle_bruteforce.argtypes = [_P, _I64, _I32, _P, _I64, _I32, _P, _P]
+        L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ----------------------------------------------------------------------------- primitives
+def splitmix64(seed: int, s: int) -> int:
+    return int(lib().oracle_splitmix64(seed, s))
+
+
+def hyperplanes(seed: int, rows: int, d: int) -> np.ndarray:
+    out = np.empty((rows, d), dtype=np.float32)
+    lib().oracle_hyperplanes(seed, rows, d, _ptr(out))
+    return out
+
+
+def normalize(x: np.ndarray) -> np.ndarray:
+    y = np.ascontiguousarray(x, dtype=np.float32).copy()
+    bad = lib().oracle_normalize(_ptr(y), y.shape[0], y.shape[1])
+    if bad >= 0:
+        raise ValueError(f"row {bad} has zero or non-finite norm")
+    return y
+
+
+def num_tables(n: int, d: int, budget: int, K: int = DEFAULT_K, M: int = DEFAULT_M) -> int:
+    return int(lib().oracle_num_tables(n, d, K, M, budget))
+
+
+def hash_codes(x: np.ndarray, hp: np.ndarray, L: int, K: int, M: int):
+    """codes[L][n] (u32), sketches[M][n] (u64) of normalised rows x."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    n, d = x.shape
+    assert hp.shape == (L * K + 64 * M, d)
+    codes = np.empty((L, n), dtype=np.uint32)
+    sk = np.empty((M, n), dtype=np.uint64)
+    lib().oracle_hash(_ptr(x), n, d, _ptr(np.ascontiguousarray(hp)), L, K, M, _ptr(codes), _ptr(sk))
+    return codes, sk
+
+
+def build_tables(codes: np.ndarray, K: int):
+    L, n = codes.shape
+    P = min(13, K)
+    tcode = np.empty((L, n), dtype=np.uint32)
+    tidx = np.empty((L, n), dtype=np.uint32)
+    off = np.empty((L, (1 << P) + 1), dtype=np.uint32)
+    rc = lib().oracle_build_tables(_ptr(np.ascontiguousarray(codes)), n, L, K, _ptr(tcode), _ptr(tidx), _ptr(off))
+    if rc:
+        raise MemoryError("oracle_build_tables")
+    return tcode, tidx, off
+
+
+def table_sketches(tidx: np.ndarray, sketches: np.ndarray) -> np.ndarray:
+    L, n = tidx.shape
+    M = sketches.shape[0]
+    tsk = np.empty((L, n), dtype=np.uint64)
+    lib().oracle_table_sketches(_ptr(tidx), _ptr(np.ascontiguousarray(sketches)), n, L, M, _ptr(tsk))
+    return tsk
+
+
+def ip32(x: np.ndarray, q: np.ndarray) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    q = np.ascontiguousarray(q, dtype=np.float32)
+    return float(lib().oracle_ip32(_ptr(x), _ptr(q), x.shape[0]))
+
+
+def ip64(x: np.ndarray, q: np.ndarray) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    q = np.ascontiguousarray(q, dtype=np.float32)
+    return float(lib().oracle_ip64(_ptr(x), _ptr(q), x.shape[0]))
+
+
+def collision_prob(ip: float) -> float:
+    return float(lib().oracle_collision_prob(ip))
+
+
+def tau(ip_k: float, eps: float = 0.0) -> float:
+    return float(lib().oracle_tau(ip_k, eps))
+
+
+def stop(ip_k: float, i: int, L: int, delta: float, rule: int = RULE_EXACT):
+    m = _D()
+    r = lib().oracle_stop(ip_k, i, L, delta, rule, ctypes.byref(m))
+    return bool(r), float(m.value)
+
+
+def bruteforce(points_n: np.ndarray, queries_n: np.ndarray, k: int):
+    """Exact k-NN of normalised queries over normalised points: (ids, FP64 ips)."""
+    p = np.ascontiguousarray(points_n, dtype=np.float32)
+    q = np.ascontiguousarray(queries_n, dtype=np.float32)
+    m = q.shape[0]
+    ids = np.empty((m, k), dtype=np.int32)
+    ips = np.empty((m, k), dtype=np.float64)
+    rc = lib().oracle_bruteforce(_ptr(p), p.shape[0], p.shape[1], _ptr(q), m, k, _ptr(ids), _ptr(ips))
+    if rc:
+        raise ValueError(f"oracle_bruteforce rc={rc}")
+    return ids, ips
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+# ----------------------------------------------------------------------------- index
+@dataclass
+class SearchResult:
+    ids: np.ndarray
+    ips: np.ndarray
+    ips64: np.ndarray
+    stop_level: np.ndarray
+    c_scan: np.ndarray
+    c_pass: np.ndarray
+    c_rerank: np.ndarray
+    boundary: np.ndarray
+    trace: np.ndarray | None = None
+
+
+class OracleIndex:
+    """The index of Sec. 4.1-4.2 built step by step on the CPU."""
+
+    def __init__(self, points: np.ndarray, budget: int, seed: int = 42, K: int = DEFAULT_K,
+                 M: int = DEFAULT_M, L: int | None = None):
+        pts = np.ascontiguousarray(points, dtype=np.float32)
+        self.n, self.d = pts.shape
+        self.K, self.M = K, M
+        self.L = num_tables(self.n, self.d, budget, K, M) if L is None else int(L)
+        if self.L < 1:
+            raise ValueError("memory budget holds no table")
+        self.points = normalize(pts)
+        self.hp = hyperplanes(seed, self.L * K + 64 * M, self.d)
+        codes, self.sketches = hash_codes(self.points, self.hp, self.L, K, M)
+        self.codes = codes
+        self.tcode, self.tidx, self.off = build_tables(codes, K)
+        self.tsk = table_sketches(self.tidx, self.sketches)
+
+    def search(self, queries: np.ndarray, k: int, recall: float, eps: float = 0.0,
+               B: int = DEFAULT_B, rule: int = RULE_EXACT, filter_on: bool = True,
+               trace: bool = False) -> SearchResult:
+        q = np.ascontiguousarray(queries, dtype=np.float32)
+        m = q.shape[0]
+        ids = np.empty((m, k), dtype=np.int32)
+        ips = np.empty((m, k), dtype=np.float32)
+        ips64 = np.empty((m, k), dtype=np.float64)
+        sl = np.empty(m, dtype=np.int32)
+        cs = np.empty(m, dtype=np.int64)
+        cp = np.empty(m, dtype=np.int64)
+        cr = np.empty(m, dtype=np.int64)
+        bd = np.empty(m, dtype=np.int32)
+        tr = np.zeros((self.K + 1, self.L, 4), dtype=np.int64) if trace else None
+        rc = lib().oracle_search(
+            _ptr(self.points), self.n, self.d, _ptr(self.hp), _ptr(self.tcode), _ptr(self.tidx),
+            _ptr(self.tsk), self.L, self.K, self.M, _ptr(q), m, k, recall, eps, B, rule,
+            1 if filter_on else 0, _ptr(ids), _ptr(ips), _ptr(ips64), _ptr(sl), _ptr(cs),
+            _ptr(cp), _ptr(cr), _ptr(bd), _ptr(tr))
+        if rc:
+            raise ValueError(f"oracle_search rc={rc}")
+        return SearchResult(ids, ips, ips64, sl, cs, cp, cr, bd, tr)

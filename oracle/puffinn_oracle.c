@@ -1,0 +1,600 @@
+/*
+ * puffinn_oracle.c -- plain, slow CPU oracle for the adaptive k-NN query path of
+ * PUFFINN (Aumueller, Christiani, Pagh, Vesterli; "PUFFINN: Parameterless and
+ * Universally Fast FInding of Nearest Neighbors", ESA 2019).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark may load this library.  The GPU library never calls, links or
+ * includes anything from here, and this file includes nothing from the GPU library.
+ *
+ * Every function below follows a passage of the paper; where the paper is silent or
+ * ambiguous the reading taken is stated next to the code.  Floating point: hash
+ * projections, norms, collision probabilities, the filter threshold and the stopping
+ * bound are evaluated in FP64; the re-rank inner product is FP32 in one fixed
+ * summation order (see oracle_ip32) so that an FP32 implementation can match it bit
+ * for bit; an FP64 inner product is returned beside it for error reporting.
+ *
+ * Parity pins (what this code is checked against, in the CPU tests): the collision
+ * probability 1 - theta/pi of random-hyperplane bits, the expected sketch Hamming
+ * distance 64 theta/pi, textbook sorting, brute-force prefix counts, the B = 1 special
+ * case of the segment rule, the closed-form solution of the stopping inequality, exact
+ * k-NN in the linear-scan case (recall 1), the Higham error bound of the FP32 inner
+ * product, and the per-neighbour guarantee of Lemma 1 measured over many index seeds.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-3)
+
+#define OR_RULE_EXACT 0 /* L * log1p(-p^i) <= ln(delta): the bound in the proof of Lemma 1 */
+#define OR_RULE_ALG1 1  /* L >= ln(1/delta) / p^i: the test printed in Algorithm 1 */
+
+static const double OR_PI = 3.14159265358979323846264338327950288;
+
+/* ------------------------------------------------------------------------------------
+ * Random hyperplanes (Sec. 2.2, random-hyperplane LSH: every coordinate of a is an
+ * independent standard normal).  The paper fixes no generator.  Both the oracle and
+ * the GPU library implement the same published counter-based generator, SplitMix64
+ * (Steele, Lea, Flood, OOPSLA 2014), each from its definition, feeding the Box-Muller
+ * transform (Box, Muller 1958) in FP64:
+ *   output s of the stream seeded with `seed` is mix(seed + (s+1) * 0x9E3779B97F4A7C15)
+ *   element (r, c) of a d-column matrix uses t = r*d + c, outputs z1 = 2t, z2 = 2t+1
+ *   u1 = ((z1 >> 11) + 1) * 2^-53 in (0,1],  u2 = (z2 >> 11) * 2^-53 in [0,1)
+ *   a  = float( sqrt(-2 log u1) * cos(2 pi u2) )
+ * ---------------------------------------------------------------------------------- */
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t s) {
+    uint64_t z = seed + (s + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void oracle_hyperplanes(uint64_t seed, int64_t rows, int32_t d, float *out) {
+    for (int64_t r = 0; r < rows; ++r) {
+        for (int32_t c = 0; c < d; ++c) {
+            uint64_t t = (uint64_t)r * (uint64_t)d + (uint64_t)c;
+            uint64_t z1 = oracle_splitmix64(seed, 2u * t);
+            uint64_t z2 = oracle_splitmix64(seed, 2u * t + 1u);
+            double u1 = ((double)(z1 >> 11) + 1.0) * 0x1.0p-53;
+            double u2 = (double)(z2 >> 11) * 0x1.0p-53;
+            double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+            out[r * (int64_t)d + c] = (float)g;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * Vector storage (Sec. 4.2, "Vector storage"): every data and query vector is
+ * normalised to unit length.  The squared norm is summed in FP64 in index order, the
+ * square root and the division are FP64, and each quotient is rounded once to FP32.
+ * Returns -1 when every row is usable, else the index of the first row whose norm is
+ * zero or not finite (such a row has no direction, so it cannot be placed on the
+ * sphere).
+ * ---------------------------------------------------------------------------------- */
+int64_t oracle_normalize(float *x, int64_t n, int32_t d) {
+    for (int64_t i = 0; i < n; ++i) {
+        float *row = x + i * (int64_t)d;
+        double s = 0.0;
+        for (int32_t c = 0; c < d; ++c) s += (double)row[c] * (double)row[c];
+        double nrm = sqrt(s);
+        if (!(nrm > 0.0) || !isfinite(nrm)) return i;
+        for (int32_t c = 0; c < d; ++c) row[c] = (float)((double)row[c] / nrm);
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Index size (Sec. 1 and Sec. 5.2: the user gives only the memory the index may use,
+ * and that size counts the data set and the hash functions).  Resident bytes:
+ *   fixed     = 4 n d            (FP32 vectors) + 4 (64 M) d (sketch hyperplanes)
+ *   per table = 16 n             (u32 code, u32 position, u64 table-local sketch)
+ *             + 4 (2^P + 1)      (prefix-position table, P = min(13, K))
+ *             + 4 K d            (the K hash hyperplanes of the table)
+ * L = floor((budget - fixed) / per_table); 0 when the budget holds no table.
+ * ---------------------------------------------------------------------------------- */
+int64_t oracle_num_tables(int64_t n, int32_t d, int32_t K, int32_t M, uint64_t budget) {
+    int32_t P = K < 13 ? K : 13;
+    uint64_t fixed = 4ull * (uint64_t)n * (uint64_t)d + 4ull * 64ull * (uint64_t)M * (uint64_t)d;
+    uint64_t per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) + 4ull * (uint64_t)K * (uint64_t)d;
+    if (budget <= fixed) return 0;
+    return (int64_t)((budget - fixed) / per);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Hashing (Sec. 2.2): bit = 1 iff <a, x> >= 0.  The projection is the FP64 sum of the
+ * (exact) FP64 products a_c * x_c taken in index order c = 0..d-1.
+ * Layout of the hyperplane matrix: row j*K + (s-1) is h_{s,j} (s = 1..K) of table j;
+ * rows L*K + 64 m + b are the bits b = 0..63 of sketch m (Sec. 4.2, "Filtering
+ * candidate points": M sketches of 64 bits from random-hyperplane LSH).
+ * Codes: the K-bit code of table j is the bitstring h_{1,j} .. h_{K,j} read with h_{1,j}
+ * as its most significant bit (Sec. 4.2 views the hash code as a bitstring and sorts
+ * it lexicographically, so the first function is the leading character).
+ * Output layouts: codes[j][i] (u32), sketches[m][i] (u64, bit b = hyperplane b).
+ * Four rows are accumulated side by side only to keep four independent FP64 chains in
+ * flight; each row's sum is still the plain sequential one.
+ * ---------------------------------------------------------------------------------- */
+static double dot64(const float *a, const float *x, int32_t d) {
+    double s = 0.0;
+    for (int32_t c = 0; c < d; ++c) s += (double)a[c] * (double)x[c];
+    return s;
+}
+
+void oracle_hash(const float *x, int64_t n, int32_t d, const float *hp, int32_t L, int32_t K,
+                 int32_t M, uint32_t *codes, uint64_t *sketches) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        const float *xi = x + i * (int64_t)d;
+        for (int32_t j = 0; j < L; ++j) {
+            uint32_t code = 0;
+            for (int32_t s = 0; s < K; ++s) {
+                double p = dot64(hp + ((int64_t)j * K + s) * d, xi, d);
+                if (p >= 0.0) code |= 1u << (K - 1 - s);
+            }
+            codes[(int64_t)j * n + i] = code;
+        }
+        for (int32_t m = 0; m < M; ++m) {
+            uint64_t sk = 0;
+            for (int32_t b = 0; b < 64; ++b) {
+                double p = dot64(hp + ((int64_t)L * K + 64 * m + b) * d, xi, d);
+                if (p >= 0.0) sk |= 1ull << b;
+            }
+            sketches[(int64_t)m * n + i] = sk;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * LSH forest as sorted arrays (Sec. 4.1 and Sec. 4.2, "Retrieving candidate points"):
+ * repetition j is the array of (code, position) pairs sorted by code.  Equal codes
+ * are ordered by position (the paper leaves ties open; this makes the array unique).
+ * The prefix-position table (13-bit prefixes tabulated to speed up the search):
+ *   off[j][p] = number of entries whose leading P bits are < p, p = 0..2^P.
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t code;
+    uint32_t pos;
+} or_pair;
+
+static int cmp_pair(const void *a, const void *b) {
+    const or_pair *x = (const or_pair *)a, *y = (const or_pair *)b;
+    if (x->code != y->code) return x->code < y->code ? -1 : 1;
+    if (x->pos != y->pos) return x->pos < y->pos ? -1 : 1;
+    return 0;
+}
+
+int oracle_build_tables(const uint32_t *codes, int64_t n, int32_t L, int32_t K, uint32_t *tcode,
+                        uint32_t *tidx, uint32_t *off) {
+    int32_t P = K < 13 ? K : 13;
+    int64_t np = (int64_t)1 << P;
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t j = 0; j < L; ++j) {
+        or_pair *v = (or_pair *)malloc((size_t)n * sizeof(or_pair));
+        if (!v) {
+            err = 1;
+            continue;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            v[i].code = codes[(int64_t)j * n + i];
+            v[i].pos = (uint32_t)i;
+        }
+        qsort(v, (size_t)n, sizeof(or_pair), cmp_pair);
+        for (int64_t e = 0; e < n; ++e) {
+            tcode[(int64_t)j * n + e] = v[e].code;
+            tidx[(int64_t)j * n + e] = v[e].pos;
+        }
+        free(v);
+        uint32_t *o = off + (int64_t)j * (np + 1);
+        int64_t *cnt = (int64_t *)calloc((size_t)np, sizeof(int64_t));
+        if (!cnt) {
+            err = 1;
+            continue;
+        }
+        for (int64_t e = 0; e < n; ++e) cnt[tcode[(int64_t)j * n + e] >> (K - P)]++;
+        int64_t run = 0;
+        for (int64_t p = 0; p < np; ++p) {
+            o[p] = (uint32_t)run;
+            run += cnt[p];
+        }
+        o[np] = (uint32_t)run;
+        free(cnt);
+    }
+    return err ? OR_ENOMEM : OR_OK;
+}
+
+/* Sketch chosen for repetition j: "a pseudorandom transformation of the repetition
+ * number" (Sec. 4.2, "Filtering candidate points").  The sketch hyperplanes are
+ * independent, so any fixed map is equivalent in distribution; this oracle takes
+ * sigma(j) = j mod M and stores, per table, the sketch of each sorted entry. */
+void oracle_table_sketches(const uint32_t *tidx, const uint64_t *sketches, int64_t n, int32_t L,
+                           int32_t M, uint64_t *tsk) {
+    for (int32_t j = 0; j < L; ++j) {
+        const uint64_t *s = sketches + (int64_t)(j % M) * n;
+        for (int64_t e = 0; e < n; ++e) tsk[(int64_t)j * n + e] = s[tidx[(int64_t)j * n + e]];
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * Re-rank inner product (Sec. 4.2, "Computing distances": the exact distance of every
+ * candidate that passes the filter).  On unit vectors the inner product orders
+ * neighbours (Sec. 2.2, angular distance).  FP32, one fixed order so that results are
+ * reproducible bit for bit by any FP32 implementation that follows it:
+ *   partial r (r = 0..15) sums the FP32-rounded products x_i*q_i over the indices
+ *   i = 64t + 4r + c (t >= 0, c = 0..3, i < d) in increasing i, every add rounded to
+ *   FP32 and no fused multiply-add; then s_r <- s_r + s_{r xor h} for h = 8, 4, 2, 1
+ *   (all r at once), and the result is s_0.
+ * ---------------------------------------------------------------------------------- */
+float oracle_ip32(const float *x, const float *q, int32_t d) {
+    float s[16], t[16];
+    for (int r = 0; r < 16; ++r) s[r] = 0.0f;
+    for (int32_t i = 0; i < d; ++i) {
+        int r = (i & 63) >> 2;
+        float prod = x[i] * q[i];
+        s[r] = s[r] + prod;
+    }
+    for (int h = 8; h >= 1; h >>= 1) {
+        for (int r = 0; r < 16; ++r) t[r] = s[r] + s[r ^ h];
+        for (int r = 0; r < 16; ++r) s[r] = t[r];
+    }
+    return s[0];
+}
+
+double oracle_ip64(const float *x, const float *q, int32_t d) { return dot64(x, q, d); }
+
+/* ------------------------------------------------------------------------------------
+ * Collision probability of random-hyperplane LSH at inner product ip (Sec. 4.3 notes a
+ * closed form exists; it is Charikar's p = 1 - theta/pi, theta = arccos(ip)), FP64.
+ * ---------------------------------------------------------------------------------- */
+static double clamp1(double v) { return v > 1.0 ? 1.0 : (v < -1.0 ? -1.0 : v); }
+
+double oracle_collision_prob(float ip) { return 1.0 - acos(clamp1((double)ip)) / OR_PI; }
+
+/* Filter threshold (Sec. 4.2 "Filtering candidate points" and Sec. 5.1): a candidate
+ * passes when the Hamming distance of its sketch to the query's sketch is at most
+ * tau = (1 + eps) * (expected Hamming distance at the current k-th inner product).
+ * The expected distance of 64 random-hyperplane bits at angle theta is
+ * 64 * Pr[bits differ] = 64 theta / pi.  (The paper's footnote says "collide"; with
+ * that reading near neighbours would get tau near 64 and nothing would be filtered,
+ * so the differ-probability is taken.)  eps = 0 is the paper's setting. */
+double oracle_tau(float ip_k, double eps) {
+    return (1.0 + eps) * 64.0 * acos(clamp1((double)ip_k)) / OR_PI;
+}
+
+/* Stopping test after all L repetitions of level i have been inspected (Sec. 4.1: "the
+ * termination criterion is checked after all repetitions are inspected").
+ * OR_RULE_EXACT stops when the failure bound of Lemma 1's proof, (1 - p^i)^L, is at
+ * most delta, evaluated as L * log1p(-p^i) <= ln(delta) with ln p = log1p(-theta/pi)
+ * and p^i = exp(i ln p).  OR_RULE_ALG1 stops when L >= ln(1/delta) / p^i, the test
+ * written in Algorithm 1 (it implies the exact bound, so it never stops earlier).
+ * *margin receives the signed distance of the two sides (term - threshold). */
+int oracle_stop(float ip_k, int32_t i, int32_t L, double delta, int32_t rule, double *margin) {
+    double theta = acos(clamp1((double)ip_k));
+    double lnp = log1p(-theta / OR_PI);
+    double pi_ = exp((double)i * lnp);
+    double lnd = log(delta);
+    if (rule == OR_RULE_ALG1) {
+        /* L * p^i >= -ln(delta) */
+        double lhs = (double)L * pi_;
+        if (margin) *margin = -lnd - lhs;
+        return lhs >= -lnd;
+    }
+    double term = (double)L * log1p(-pi_);
+    if (margin) *margin = term - lnd;
+    return term <= lnd;
+}
+
+/* ------------------------------------------------------------------------------------
+ * The adaptive query (Algorithm 1, adaptive-kNN(q, k, delta), realised on sorted arrays
+ * as in Sec. 4.1-4.2).  Readings taken where the paper leaves freedom:
+ *  - rounds are level-synchronous: in level i every repetition j = 1..L contributes its
+ *    new entries, then the stopping test runs once (Sec. 4.1);
+ *  - the filter threshold tau_i is fixed for the whole level from the top-k as it stood
+ *    before the level (64, i.e. no filtering, while fewer than k points are known);
+ *  - retrieval (Sec. 4.2 and App. C): per repetition a consumed window [c_lo, c_hi)
+ *    starts empty at the insertion point of the query's code; at level i it grows by
+ *    whole segments of B entries to the left while the entry just left of it shares the
+ *    query's i-bit prefix, and to the right likewise, clipped to [0, n).  B = 1 gives
+ *    exactly the sets Pi_{i,j}(q) of Sec. 3.1;
+ *  - de-duplication (Sec. 4.2, "Computing distances") is against every point already
+ *    re-ranked, so a point is re-ranked at most once per query; a point filtered out in
+ *    one repetition may still pass in another;
+ *  - the top-k is ordered by (inner product descending, position ascending);
+ *  - level 0 is a linear scan (Lemma 1: at i = 0 the query degrades to a linear scan):
+ *    every point not yet re-ranked is re-ranked, unfiltered, and the exact top-k is
+ *    returned.
+ * Counters: c_scan = entries taken from the arrays, c_pass = entries that passed the
+ * filter (with multiplicity), c_rerank = distinct points re-ranked.
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    float ip;
+    double ip64;
+    int32_t id;
+} or_cand;
+
+static int cmp_cand(const void *a, const void *b) {
+    const or_cand *x = (const or_cand *)a, *y = (const or_cand *)b;
+    if (x->ip > y->ip) return -1;
+    if (x->ip < y->ip) return 1;
+    return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
+}
+
+typedef struct {
+    or_cand *v;
+    int64_t len, cap;
+} or_list;
+
+static int list_push(or_list *l, or_cand c) {
+    if (l->len == l->cap) {
+        int64_t nc = l->cap ? 2 * l->cap : 1024;
+        or_cand *nv = (or_cand *)realloc(l->v, (size_t)nc * sizeof(or_cand));
+        if (!nv) return OR_ENOMEM;
+        l->v = nv;
+        l->cap = nc;
+    }
+    l->v[l->len++] = c;
+    return OR_OK;
+}
+
+/* number of entries of the sorted array tc[0..n) whose leading i bits (of K) are
+ * smaller than those of the query code qc (below = 1) or at most those (below = 0) */
+static int64_t prefix_bound(const uint32_t *tc, int64_t n, int32_t K, int32_t i, uint32_t qc,
+                            int below) {
+    uint64_t qp = (uint64_t)qc >> (K - i);
+    int64_t lo = 0, hi = n; /* first e with pre(tc[e]) >= qp (below) or > qp (!below) */
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        uint64_t ep = (uint64_t)tc[mid] >> (K - i);
+        int go_right = below ? (ep < qp) : (ep <= qp);
+        if (go_right)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+typedef struct {
+    const float *points;
+    int64_t n;
+    int32_t d;
+    const uint32_t *tcode, *tidx;
+    const uint64_t *tsk;
+    int32_t L, K, M;
+} or_index;
+
+/* trace (optional, one query): per level i (row i of K+1) and table j:
+ * [0] lo_i [1] hi_i [2] c_lo after level i [3] c_hi after level i */
+static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, const uint64_t *qsk,
+                    int32_t k, double delta, double eps, int32_t B, int32_t rule, int32_t filter_on,
+                    uint8_t *seen, int64_t *clo, int64_t *chi, or_list *top, or_list *fresh,
+                    int32_t *stop_level, int64_t *cnt, int32_t *boundary, int64_t *trace) {
+    const int64_t n = ix->n;
+    const int32_t L = ix->L, K = ix->K, d = ix->d;
+    memset(seen, 0, (size_t)n);
+    top->len = 0;
+    cnt[0] = cnt[1] = cnt[2] = 0;
+    *boundary = 0;
+    for (int32_t j = 0; j < L; ++j) {
+        int64_t lk = prefix_bound(ix->tcode + (int64_t)j * n, n, K, K, qcode[j], 1);
+        clo[j] = chi[j] = lk;
+    }
+    for (int32_t i = K; i >= 1; --i) {
+        /* threshold fixed for the level, from the top-k before it */
+        double tau = 64.0;
+        if (filter_on && top->len == k) {
+            tau = oracle_tau(top->v[k - 1].ip, eps);
+            double fr = tau - floor(tau);
+            if (fr < 1e-9 || fr > 1.0 - 1e-9) *boundary = 1;
+        }
+        fresh->len = 0;
+        for (int32_t j = 0; j < L; ++j) {
+            const uint32_t *tc = ix->tcode + (int64_t)j * n;
+            const uint32_t *ti = ix->tidx + (int64_t)j * n;
+            const uint64_t *ts = ix->tsk + (int64_t)j * n;
+            const uint64_t qs = qsk[j % ix->M];
+            int64_t lo_i = prefix_bound(tc, n, K, i, qcode[j], 1);
+            int64_t hi_i = prefix_bound(tc, n, K, i, qcode[j], 0);
+            if (trace) {
+                trace[((int64_t)i * L + j) * 4 + 0] = lo_i;
+                trace[((int64_t)i * L + j) * 4 + 1] = hi_i;
+            }
+            /* new entries of this repetition at this level: whole segments outward */
+            int64_t seg[2][2];
+            int nseg = 0;
+            if (clo[j] > lo_i) {
+                int64_t a = clo[j];
+                while (a > lo_i) a = a - B > 0 ? a - B : 0;
+                seg[nseg][0] = a;
+                seg[nseg][1] = clo[j];
+                ++nseg;
+                clo[j] = a;
+            }
+            if (chi[j] < hi_i) {
+                int64_t b = chi[j];
+                while (b < hi_i) b = b + B < n ? b + B : n;
+                seg[nseg][0] = chi[j];
+                seg[nseg][1] = b;
+                ++nseg;
+                chi[j] = b;
+            }
+            if (trace) {
+                trace[((int64_t)i * L + j) * 4 + 2] = clo[j];
+                trace[((int64_t)i * L + j) * 4 + 3] = chi[j];
+            }
+            for (int s = 0; s < nseg; ++s) {
+                for (int64_t e = seg[s][0]; e < seg[s][1]; ++e) {
+                    cnt[0]++;
+                    int h = __builtin_popcountll(ts[e] ^ qs);
+                    if ((double)h > tau) continue;
+                    cnt[1]++;
+                    uint32_t x = ti[e];
+                    if (seen[x]) continue;
+                    seen[x] = 1;
+                    cnt[2]++;
+                    const float *px = ix->points + (int64_t)x * d;
+                    or_cand c = {oracle_ip32(px, q, d), oracle_ip64(px, q, d), (int32_t)x};
+                    if (list_push(fresh, c)) return OR_ENOMEM;
+                }
+            }
+        }
+        /* top <- best k of top u fresh */
+        for (int64_t t = 0; t < fresh->len; ++t)
+            if (list_push(top, fresh->v[t])) return OR_ENOMEM;
+        qsort(top->v, (size_t)top->len, sizeof(or_cand), cmp_cand);
+        if (top->len > k) top->len = k;
+        if (top->len == k) {
+            double margin;
+            int stop = oracle_stop(top->v[k - 1].ip, i, L, delta, rule, &margin);
+            if (fabs(margin) < 1e-9 * (1.0 + fabs(log(delta)))) *boundary = 1;
+            if (stop) {
+                *stop_level = i;
+                return OR_OK;
+            }
+        }
+    }
+    /* level 0: linear scan over everything not yet re-ranked */
+    for (int64_t x = 0; x < n; ++x) {
+        if (seen[x]) continue;
+        seen[x] = 1;
+        cnt[2]++;
+        const float *px = ix->points + x * d;
+        or_cand c = {oracle_ip32(px, q, d), oracle_ip64(px, q, d), (int32_t)x};
+        if (list_push(top, c)) return OR_ENOMEM;
+    }
+    qsort(top->v, (size_t)top->len, sizeof(or_cand), cmp_cand);
+    if (top->len > k) top->len = k;
+    *stop_level = 0;
+    return OR_OK;
+}
+
+/* Search m queries.  `queries` are raw rows (normalised here), `points` are the
+ * normalised data rows, hp the hyperplanes, (tcode, tidx, tsk) the L sorted tables.
+ * recall in (0,1] gives delta = 1 - recall (Sec. 2.1: expected recall (1 - delta)).
+ * Outputs per query: ids[k], ips[k] (FP32 order above), ips64[k], stop level, the three
+ * counters, and boundary = 1 when a decision came within 1e-9 of flipping (a test of an
+ * FP32 ip against an FP64 threshold computed with a different libm may then differ).
+ * trace (nullable) records the walk of query 0 only: (K+1) x L x 4 int64.
+ * Returns 0, OR_EINVAL (bad arguments or a zero / non-finite query row), OR_ENOMEM. */
+int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, const uint32_t *tcode,
+                  const uint32_t *tidx, const uint64_t *tsk, int32_t L, int32_t K, int32_t M,
+                  const float *queries, int64_t m, int32_t k, double recall, double eps, int32_t B,
+                  int32_t rule, int32_t filter_on, int32_t *ids, float *ips, double *ips64,
+                  int32_t *stop_level, int64_t *c_scan, int64_t *c_pass, int64_t *c_rerank,
+                  int32_t *boundary, int64_t *trace) {
+    if (n < 1 || d < 1 || L < 1 || K < 1 || K > 32 || M < 1 || m < 0 || k < 1 || k > n || B < 1)
+        return OR_EINVAL;
+    if (!(recall > 0.0 && recall <= 1.0)) return OR_EINVAL;
+    float *qn = (float *)malloc((size_t)(m > 0 ? m : 1) * (size_t)d * sizeof(float));
+    uint32_t *qc = (uint32_t *)malloc((size_t)(m > 0 ? m : 1) * (size_t)L * sizeof(uint32_t));
+    uint64_t *qs = (uint64_t *)malloc((size_t)(m > 0 ? m : 1) * (size_t)M * sizeof(uint64_t));
+    if (!qn || !qc || !qs) {
+        free(qn), free(qc), free(qs);
+        return OR_ENOMEM;
+    }
+    memcpy(qn, queries, (size_t)m * (size_t)d * sizeof(float));
+    if (oracle_normalize(qn, m, d) >= 0) {
+        free(qn), free(qc), free(qs);
+        return OR_EINVAL;
+    }
+    /* query codes: table-major like the data codes */
+    oracle_hash(qn, m, d, hp, L, K, M, qc, qs);
+    or_index ix = {points, n, d, tcode, tidx, tsk, L, K, M};
+    const double delta = 1.0 - recall;
+    int err = OR_OK;
+#pragma omp parallel
+    {
+        uint8_t *seen = (uint8_t *)malloc((size_t)n);
+        int64_t *clo = (int64_t *)malloc((size_t)L * sizeof(int64_t));
+        int64_t *chi = (int64_t *)malloc((size_t)L * sizeof(int64_t));
+        uint32_t *mycode = (uint32_t *)malloc((size_t)L * sizeof(uint32_t));
+        uint64_t *mysk = (uint64_t *)malloc((size_t)M * sizeof(uint64_t));
+        or_list top = {0, 0, 0}, fresh = {0, 0, 0};
+        if (!seen || !clo || !chi || !mycode || !mysk) err = OR_ENOMEM;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t t = 0; t < m; ++t) {
+            if (err) continue;
+            for (int32_t j = 0; j < L; ++j) mycode[j] = qc[(int64_t)j * m + t];
+            for (int32_t s = 0; s < M; ++s) mysk[s] = qs[(int64_t)s * m + t];
+            int64_t cnt[3];
+            int32_t sl = 0, bd = 0;
+            int rc = walk_one(&ix, qn + t * d, mycode, mysk, k, delta, eps, B, rule, filter_on, seen,
+                              clo, chi, &top, &fresh, &sl, cnt, &bd, t == 0 ? trace : NULL);
+            if (rc) {
+                err = rc;
+                continue;
+            }
+            for (int32_t r = 0; r < k; ++r) {
+                ids[t * k + r] = top.v[r].id;
+                if (ips) ips[t * k + r] = top.v[r].ip;
+                if (ips64) ips64[t * k + r] = top.v[r].ip64;
+            }
+            if (stop_level) stop_level[t] = sl;
+            if (c_scan) c_scan[t] = cnt[0];
+            if (c_pass) c_pass[t] = cnt[1];
+            if (c_rerank) c_rerank[t] = cnt[2];
+            if (boundary) boundary[t] = bd;
+        }
+        free(seen), free(clo), free(chi), free(mycode), free(mysk);
+        free(top.v), free(fresh.v);
+    }
+    free(qn), free(qc), free(qs);
+    return err;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Exact k-NN by brute force (the problem of Sec. 2.1 with delta = 0): FP64 inner
+ * products of the normalised rows, ordered by (inner product descending, position
+ * ascending).  `points` and `queries` must already be normalised.
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    double ip;
+    int32_t id;
+} or_bf;
+
+static int cmp_bf(const void *a, const void *b) {
+    const or_bf *x = (const or_bf *)a, *y = (const or_bf *)b;
+    if (x->ip > y->ip) return -1;
+    if (x->ip < y->ip) return 1;
+    return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
+}
+
+int oracle_bruteforce(const float *points, int64_t n, int32_t d, const float *queries, int64_t m,
+                      int32_t k, int32_t *ids, double *ips64) {
+    if (k < 1 || k > n) return OR_EINVAL;
+    int err = OR_OK;
+#pragma omp parallel
+    {
+        or_bf *all = (or_bf *)malloc((size_t)n * sizeof(or_bf));
+        if (!all) err = OR_ENOMEM;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t t = 0; t < m; ++t) {
+            if (err) continue;
+            for (int64_t x = 0; x < n; ++x) {
+                all[x].ip = dot64(points + x * d, queries + t * d, d);
+                all[x].id = (int32_t)x;
+            }
+            qsort(all, (size_t)n, sizeof(or_bf), cmp_bf);
+            for (int32_t r = 0; r < k; ++r) {
+                ids[t * k + r] = all[r].id;
+                if (ips64) ips64[t * k + r] = all[r].ip;
+            }
+        }
+        free(all);
+    }
+    return err;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
