@@ -1,0 +1,165 @@
+/*
+ * pfhip.h -- C-ABI of the MI355X (gfx950) adaptive k-NN index after PUFFINN
+ * (Aumueller, Christiani, Pagh, Vesterli, ESA 2019).
+ *
+ * The user supplies only a memory budget for the index and the recall a query must
+ * reach (Sec. 1, Sec. 5 "Parameter Choices"); everything else has a default.
+ *
+ * Conventions for every entry point
+ *  - Return value: PF_OK (0) or a negative PF_E* code; on error the outputs are left
+ *    untouched and pf_last_error() returns a message (thread-local).
+ *  - `mem` says where the caller's buffers live: PF_HOST (ordinary host memory; the
+ *    call copies through device memory and returns after the results are on the host)
+ *    or PF_DEVICE (device pointers on the current HIP device; the call is ordered on
+ *    `stream` and returns after queueing unless stated otherwise).  A call never keeps
+ *    a caller pointer after it returns; the caller owns every input and output buffer.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Streams must
+ *    have the default priority.
+ *  - An index is not thread-safe: calls on the same index must not overlap.
+ *  - Layouts are row-major; "n x d" means n rows of d contiguous FP32 values.
+ */
+#ifndef PFHIP_H
+#define PFHIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_OK 0
+#define PF_EINVAL (-1)       /* bad argument, zero or non-finite vector row          */
+#define PF_EBUDGET (-2)      /* the memory budget holds no table (L < 1)             */
+#define PF_ENOMEM (-3)       /* device or host allocation failed                     */
+#define PF_EDEVICE (-4)      /* a HIP runtime call failed                            */
+#define PF_EUNSUPPORTED (-5) /* outside the implemented limits (see each call)       */
+
+#define PF_HOST 0
+#define PF_DEVICE 1
+
+/* stopping rules, see pf_search_opts.rule */
+#define PF_RULE_EXACT 0
+#define PF_RULE_ALG1 1
+
+/* hashing arithmetic, see pf_build_opts.hash_mode */
+#define PF_HASH_BF16X3 0 /* BF16 MFMA (three split products, FP32 accumulate), bits whose
+                            |projection| is within the derived error bound recomputed in FP64 */
+#define PF_HASH_FP64 1   /* every projection as a sequential FP64 sum */
+
+/* what pf_export copies */
+#define PF_EXPORT_POINTS 0      /* n x d FP32, the normalised vectors                  */
+#define PF_EXPORT_HYPERPLANES 1 /* (L*K + 64*M) x d FP32                               */
+#define PF_EXPORT_CODES 2       /* L x n u32, sorted codes of each table               */
+#define PF_EXPORT_IDX 3         /* L x n u32, point position of each sorted entry      */
+#define PF_EXPORT_SKETCHES 4    /* L x n u64, table-local sketches                     */
+#define PF_EXPORT_OFFSETS 5     /* L x (2^P + 1) u32, P = min(13, K), prefix table     */
+
+/* limits of this implementation */
+#define PF_MAX_TABLES 512
+#define PF_MAX_K 256 /* neighbours per query */
+#define PF_MAX_DIM 4096
+
+typedef struct pf_index pf_index; /* opaque; owns all of its device memory */
+
+typedef struct {
+    uint64_t seed;      /* hyperplane seed (counter-based SplitMix64 + Box-Muller)  */
+    int32_t K;          /* bits per table code, 1..32; 0 selects 24                 */
+    int32_t M;          /* 64-bit sketches per point, 1..64; 0 selects 32           */
+    int32_t hash_mode;  /* PF_HASH_BF16X3 (default) or PF_HASH_FP64                  */
+    int32_t L_override; /* > 0: use exactly this many tables, ignore the budget rule  */
+} pf_build_opts;
+
+typedef struct {
+    double eps;     /* filter slack: tau = (1 + eps) * 64 * theta_k / pi; default 0  */
+    int32_t B;      /* segment size of every array access; 0 selects 12              */
+    int32_t rule;   /* PF_RULE_EXACT (default) or PF_RULE_ALG1                       */
+    int32_t filter; /* 1 (default) sketch filter on, 0 off (every candidate re-ranked) */
+    int32_t timing; /* 1: record per-kernel durations of this call (pf_last_timing)  */
+} pf_search_opts;
+
+typedef struct {
+    int32_t stop_level; /* prefix length at which the query stopped (0 = linear scan) */
+    int32_t reserved;
+    int64_t c_scan;   /* entries taken from the sorted arrays                        */
+    int64_t c_pass;   /* entries that passed the sketch filter (with multiplicity)   */
+    int64_t c_rerank; /* distinct points whose inner product was computed            */
+} pf_query_stats;
+
+typedef struct {
+    int64_t n;
+    int32_t d, L, K, M, P, reserved;
+    uint64_t bytes_budget_rule; /* bytes the budget rule counts for this index        */
+    uint64_t bytes_device;      /* device bytes the index actually holds              */
+    double build_ms;            /* device time of the last build, if measured         */
+} pf_info;
+
+typedef struct {
+    double normalize_ms, hash_ms, ranges_ms, search_ms, total_ms;
+} pf_timing;
+
+/* Normalise n rows to unit length (Sec. 4.2, "Vector storage"): squared norm summed in
+ * FP64 in index order, FP64 square root and division, each quotient rounded once to
+ * FP32.  x and out are n x d (may alias).  PF_EINVAL when a row has zero or non-finite
+ * norm (out is then unspecified). */
+int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, void *stream);
+
+/* Build the index of Sec. 4.1-4.2 over n points of dimension d:
+ *  L = floor((budget - 4nd - 4*64*M*d) / (16n + 4*(2^P+1) + 4Kd)) tables (the budget
+ *  counts the vectors, the hash functions, the sorted (code, position) arrays, the
+ *  table-local sketches and the prefix tables; Sec. 5.2), capped at PF_MAX_TABLES;
+ *  K random-hyperplane functions per table (Sec. 2.2), M 64-bit sketches per point
+ *  (Sec. 4.2), each table sorted by its K-bit code with equal codes by position, and a
+ *  table of the positions of every P-bit prefix (Sec. 4.2, P = min(13, K)).
+ * `points` n x d (caller-owned, copied).  Errors: PF_EINVAL (n < 1, n >= 2^31, d < 1,
+ * d > PF_MAX_DIM, bad row, K or M out of range), PF_EBUDGET, PF_ENOMEM, PF_EDEVICE.
+ * Synchronises the stream before returning. */
+int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t memory_budget_bytes,
+                   const pf_build_opts *opts, int32_t mem, void *stream, pf_index **out);
+
+/* Answer m queries (Algorithm 1, adaptive-kNN(q, k, delta), with delta = 1 - recall,
+ * Sec. 2.1), level-synchronously as in Sec. 4.1: in each round every table contributes
+ * the new entries sharing the query's i-bit prefix, read in whole segments of B
+ * entries (Sec. 4.2, App. C); candidates pass when the Hamming distance of their
+ * sketch is at most the threshold of the round (Sec. 4.2, Sec. 5.1); survivors not
+ * yet seen are re-ranked by exact FP32 inner product into the top-k; after all tables
+ * the stopping bound of Lemma 1 is tested in FP64; at prefix length 0 the query is a
+ * linear scan.  `queries` m x d; out_ids m x k (int32, best first: inner product
+ * descending, position ascending); out_ips m x k FP32 (nullable); stats m (nullable).
+ * Errors: PF_EINVAL (k < 1, k > n, k > PF_MAX_K, recall outside (0, 1], bad row, d
+ * mismatch), PF_ENOMEM, PF_EDEVICE.  With PF_HOST the call synchronises. */
+int pf_search(pf_index *ix, const float *queries, int64_t m, int32_t k, double recall,
+              int32_t *out_ids, float *out_ips, pf_query_stats *stats, int32_t mem,
+              void *stream);
+
+/* pf_search with explicit options (opts may be NULL for the defaults). */
+int pf_search_ex(pf_index *ix, const float *queries, int64_t m, int32_t k, double recall,
+                 const pf_search_opts *opts, int32_t *out_ids, float *out_ips,
+                 pf_query_stats *stats, int32_t mem, void *stream);
+
+/* Hash m rows with the index's functions (Sec. 2.2: bit = 1 iff <a, x> >= 0) after
+ * normalising them: codes L x m (u32, table-major, h_{1,j} the most significant of the
+ * K bits), sketches M x m (u64, bit b from sketch hyperplane b).  Either output may be
+ * NULL.  Errors: PF_EINVAL, PF_ENOMEM, PF_EDEVICE. */
+int pf_hash(pf_index *ix, const float *x, int64_t m, uint32_t *codes, uint64_t *sketches,
+            int32_t mem, void *stream);
+
+/* Copy one resident structure of the index (PF_EXPORT_*) into dst, which must hold
+ * dst_bytes >= the structure's size (PF_EINVAL otherwise).  Synchronises. */
+int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_bytes, int32_t mem,
+              void *stream);
+
+int pf_index_info(const pf_index *ix, pf_info *info);
+
+/* Per-kernel device durations of the last pf_search* call made with opts.timing = 1,
+ * measured with HIP events recorded on the call's stream around each launch. */
+int pf_last_timing(const pf_index *ix, pf_timing *t);
+
+void pf_free_index(pf_index *ix);
+
+const char *pf_last_error(void);
+const char *pf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFHIP_H */

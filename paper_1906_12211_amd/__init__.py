@@ -1,0 +1,271 @@
+"""Python binding of libpfhip.so, the gfx950 adaptive k-NN index (PUFFINN, ESA 2019).
+
+Argument marshalling only: every step of build and search runs in the HIP library.
+Functions carry the C-ABI names of ``include/pfhip.h``; ``Index`` wraps them for numpy
+arrays (host memory) and torch tensors (device memory on the current HIP stream).
+The library must be built first (``python -m paper_1906_12211_amd.build``); importing
+works without it, but every call raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libpfhip.so")
+
+PF_OK, PF_EINVAL, PF_EBUDGET, PF_ENOMEM, PF_EDEVICE, PF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+PF_HOST, PF_DEVICE = 0, 1
+PF_RULE_EXACT, PF_RULE_ALG1 = 0, 1
+PF_HASH_BF16X3, PF_HASH_FP64 = 0, 1
+(PF_EXPORT_POINTS, PF_EXPORT_HYPERPLANES, PF_EXPORT_CODES, PF_EXPORT_IDX,
+ PF_EXPORT_SKETCHES, PF_EXPORT_OFFSETS) = range(6)
+PF_MAX_TABLES, PF_MAX_K, PF_MAX_DIM = 512, 256, 4096
+
+EXPORTED = ["pf_normalize", "pf_build_index", "pf_search", "pf_search_ex", "pf_hash", "pf_export",
+            "pf_index_info", "pf_last_timing", "pf_free_index", "pf_last_error", "pf_version"]
+
+
+class PfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class pf_build_opts(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("K", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("hash_mode", ctypes.c_int32), ("L_override", ctypes.c_int32)]
+
+
+class pf_search_opts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("B", ctypes.c_int32), ("rule", ctypes.c_int32),
+                ("filter", ctypes.c_int32), ("timing", ctypes.c_int32)]
+
+
+class pf_query_stats(ctypes.Structure):
+    _fields_ = [("stop_level", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("c_scan", ctypes.c_int64), ("c_pass", ctypes.c_int64), ("c_rerank", ctypes.c_int64)]
+
+
+class pf_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("M", ctypes.c_int32), ("P", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("bytes_budget_rule", ctypes.c_uint64),
+                ("bytes_device", ctypes.c_uint64), ("build_ms", ctypes.c_double)]
+
+
+class pf_timing(ctypes.Structure):
+    _fields_ = [("normalize_ms", ctypes.c_double), ("hash_ms", ctypes.c_double),
+                ("ranges_ms", ctypes.c_double), ("search_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32, _I64, _U64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+
+
+def lib():
+    """Load libpfhip.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1906_12211_amd.build`")
+        # torch ships its own HIP runtime under the same soname; load it first so that the
+        # process holds one runtime, shared by torch's tensors/streams and this library
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        L.pf_last_error.restype = ctypes.c_char_p
+        L.pf_last_error.argtypes = []
+        L.pf_version.restype = ctypes.c_char_p
+        L.pf_version.argtypes = []
+        L.pf_normalize.restype = ctypes.c_int
+        L.pf_normalize.argtypes = [_P, _I64, _I32, _P, _I32, _P]
+        L.pf_build_index.restype = ctypes.c_int
+        L.pf_build_index.argtypes = [_P, _I64, _I32, _U64, ctypes.POINTER(pf_build_opts), _I32, _P,
+                                     ctypes.POINTER(_P)]
+        L.pf_search.restype = ctypes.c_int
+        L.pf_search.argtypes = [_P, _P, _I64, _I32, _D, _P, _P, _P, _I32, _P]
+        L.pf_search_ex.restype = ctypes.c_int
+        L.pf_search_ex.argtypes = [_P, _P, _I64, _I32, _D, ctypes.POINTER(pf_search_opts), _P, _P, _P,
+                                   _I32, _P]
+        L.pf_hash.restype = ctypes.c_int
+        L.pf_hash.argtypes = [_P, _P, _I64, _P, _P, _I32, _P]
+        L.pf_export.restype = ctypes.c_int
+        L.pf_export.argtypes = [_P, _I32, _P, _I64, _I32, _P]
+        L.pf_index_info.restype = ctypes.c_int
+        L.pf_index_info.argtypes = [_P, ctypes.POINTER(pf_info)]
+        L.pf_last_timing.restype = ctypes.c_int
+        L.pf_last_timing.argtypes = [_P, ctypes.POINTER(pf_timing)]
+        L.pf_free_index.restype = None
+        L.pf_free_index.argtypes = [_P]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PF_OK:
+        raise PfError(rc, lib().pf_last_error().decode())
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _buf(a):
+    """(pointer, mem, stream) of a contiguous numpy array or torch tensor."""
+    if a is None:
+        return None, PF_HOST, None
+    if _is_torch(a):
+        import torch
+
+        assert a.is_contiguous()
+        if a.is_cuda:
+            return ctypes.c_void_p(a.data_ptr()), PF_DEVICE, ctypes.c_void_p(
+                torch.cuda.current_stream(a.device).cuda_stream)
+        return ctypes.c_void_p(a.data_ptr()), PF_HOST, None
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p), PF_HOST, None
+
+
+def _empty_like_input(x, shape, np_dtype, torch_dtype):
+    if _is_torch(x):
+        import torch
+
+        return torch.empty(shape, dtype=torch_dtype, device=x.device)
+    return np.empty(shape, dtype=np_dtype)
+
+
+def _f32(x):
+    if _is_torch(x):
+        import torch
+
+        return x.to(torch.float32).contiguous()
+    return np.ascontiguousarray(x, dtype=np.float32)
+
+
+def pf_version() -> str:
+    return lib().pf_version().decode()
+
+
+def pf_normalize(x):
+    x = _f32(x)
+    out = _empty_like_input(x, tuple(x.shape), np.float32, x.dtype if _is_torch(x) else None)
+    px, mem, st = _buf(x)
+    po, _, _ = _buf(out)
+    _check(lib().pf_normalize(px, x.shape[0], x.shape[1], po, mem, st))
+    return out
+
+
+@dataclass
+class SearchResult:
+    ids: object
+    ips: object
+    stats: object  # (m, 4) int64: stop_level, c_scan, c_pass, c_rerank
+
+    @property
+    def stop_level(self):
+        return self.stats[:, 0]
+
+
+def _stats_view(raw):
+    """pf_query_stats array (m x 32 bytes) as (m, 4) int64 columns."""
+    if _is_torch(raw):
+        s = raw.clone()
+        s[:, 0] = s[:, 0] & 0xFFFFFFFF
+        return s
+    s = raw.copy()
+    s[:, 0] &= 0xFFFFFFFF
+    return s
+
+
+class Index:
+    """An index over the rows of `points` (numpy on the host or a torch device tensor)."""
+
+    def __init__(self, points, budget: int, seed: int = 42, K: int = 24, M: int = 32,
+                 hash_mode: int = PF_HASH_BF16X3, L: int | None = None):
+        pts = _f32(points)
+        n, d = pts.shape
+        opts = pf_build_opts(seed, K, M, hash_mode, int(L or 0))
+        pp, mem, st = _buf(pts)
+        h = ctypes.c_void_p()
+        _check(lib().pf_build_index(pp, n, d, int(budget), ctypes.byref(opts), mem, st, ctypes.byref(h)))
+        self._h = h
+        self.n, self.d = n, d
+        info = self.info()
+        self.L, self.K, self.M, self.P = info.L, info.K, info.M, info.P
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pf_free_index(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> pf_info:
+        i = pf_info()
+        _check(lib().pf_index_info(self._h, ctypes.byref(i)))
+        return i
+
+    def last_timing(self) -> pf_timing:
+        t = pf_timing()
+        _check(lib().pf_last_timing(self._h, ctypes.byref(t)))
+        return t
+
+    def search(self, queries, k: int, recall: float, eps: float = 0.0, B: int = 12,
+               rule: int = PF_RULE_EXACT, filter: bool = True, timing: bool = False,
+               want_ips: bool = True, want_stats: bool = True) -> SearchResult:
+        q = _f32(queries)
+        m = q.shape[0]
+        ids = _empty_like_input(q, (m, k), np.int32, _torch_dtype("int32"))
+        ips = _empty_like_input(q, (m, k), np.float32, _torch_dtype("float32")) if want_ips else None
+        st = _empty_like_input(q, (m, 4), np.int64, _torch_dtype("int64")) if want_stats else None
+        opts = pf_search_opts(eps, B, rule, 1 if filter else 0, 1 if timing else 0)
+        pq, mem, stream = _buf(q)
+        _check(lib().pf_search_ex(self._h, pq, m, k, recall, ctypes.byref(opts), _buf(ids)[0],
+                                  _buf(ips)[0], _buf(st)[0], mem, stream))
+        return SearchResult(ids, ips, _stats_view(st) if st is not None else None)
+
+    def hash(self, x):
+        x = _f32(x)
+        m = x.shape[0]
+        codes = _empty_like_input(x, (self.L, m), np.uint32, _torch_dtype("int32"))
+        sk = _empty_like_input(x, (self.M, m), np.uint64, _torch_dtype("int64"))
+        px, mem, st = _buf(x)
+        _check(lib().pf_hash(self._h, px, m, _buf(codes)[0], _buf(sk)[0], mem, st))
+        return codes, sk
+
+    _EXPORT = {
+        PF_EXPORT_POINTS: (np.float32, lambda s: (s.n, s.d)),
+        PF_EXPORT_HYPERPLANES: (np.float32, lambda s: (s.L * s.K + 64 * s.M, s.d)),
+        PF_EXPORT_CODES: (np.uint32, lambda s: (s.L, s.n)),
+        PF_EXPORT_IDX: (np.uint32, lambda s: (s.L, s.n)),
+        PF_EXPORT_SKETCHES: (np.uint64, lambda s: (s.L, s.n)),
+        PF_EXPORT_OFFSETS: (np.uint32, lambda s: (s.L, (1 << s.P) + 1)),
+    }
+
+    def export(self, what: int) -> np.ndarray:
+        dt, shp = self._EXPORT[what]
+        out = np.empty(shp(self), dtype=dt)
+        _check(lib().pf_export(self._h, what, _buf(out)[0], out.nbytes, PF_HOST, None))
+        return out
+
+
+def _torch_dtype(name: str):
+    try:
+        import torch
+
+        return getattr(torch, name)
+    except Exception:  # numpy-only callers never use it
+        return None

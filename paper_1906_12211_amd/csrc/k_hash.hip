@@ -1,0 +1,271 @@
+// Random-hyperplane hashing (Sec. 2.2: bit = 1 iff <a, x> >= 0) of many rows at once.
+//
+// The projection P = X . H^T is a dense contraction, so it runs on the gfx950 matrix
+// cores: every FP32 operand v is split into two BF16 parts v = hi + lo + r with
+// hi = bf16(v), lo = bf16(v - hi), |r| <= 2^-16 |v|, and the three products hi.hi,
+// hi.lo and lo.hi are accumulated in FP32 by v_mfma_f32_32x32x16_bf16.  The dropped
+// terms and the FP32 accumulation bound the error of every projection by a per-column
+// beta (computed on the host, see pf_api.cpp); a bit whose |P| <= beta may have the
+// wrong sign and is recomputed exactly as the FP64 sequential sum that defines it.
+// Output is written word-wise: each 32-column block of the GEMM is one u32 word per
+// row (a table code or half of a 64-bit sketch), packed with wave ballots.
+#include "pf_internal.h"
+
+namespace pf {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+static constexpr int kFlagBuf = 512; // per-workgroup LDS buffer of flagged (row, col)
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ uint32_t *word_ptr(uint32_t *codes, uint32_t *skw, int64_t n, int32_t L,
+                                              int32_t wb, int64_t row) {
+    if (wb < L) return codes + (int64_t)wb * n + row;
+    const int32_t s = wb - L;
+    return skw + 2 * ((int64_t)(s >> 1) * n + row) + (s & 1);
+}
+
+// One workgroup: ROWS rows of X (kept in LDS as BF16 hi/lo) against the word blocks
+// [blockIdx.y * wpy, ...); wave w takes every fourth word block.  MFMA operand layout
+// (32x32x16 BF16): lane l supplies A[l % 32][8 (l / 32) .. +8) and B[8 (l / 32) .. +8)[l % 32];
+// accumulator register r of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+template <int ROWS>
+__global__ __launch_bounds__(256) void k_hash_bf16x3(
+    const float *__restrict__ X, int64_t n, int32_t dpad, int32_t kp, const uint16_t *__restrict__ Hhi,
+    const uint16_t *__restrict__ Hlo, const float *__restrict__ beta, int32_t words, int32_t L,
+    uint32_t kmask, int32_t wpy, uint32_t *__restrict__ codes, uint32_t *__restrict__ skw,
+    uint32_t *__restrict__ flist, unsigned int *__restrict__ fcount, uint32_t fcap) {
+    extern __shared__ __align__(16) uint16_t lds_x[];
+    __shared__ uint32_t fbuf[2 * kFlagBuf];
+    __shared__ unsigned int fcnt, fbase;
+    uint16_t *xhi = lds_x;
+    uint16_t *xlo = lds_x + ROWS * kp;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+
+    for (int idx = tid; idx < ROWS * kp; idx += 256) {
+        const int r = idx / kp, c = idx - r * kp;
+        const int64_t gr = row0 + r;
+        float v = 0.0f;
+        if (gr < n && c < dpad) v = X[gr * dpad + c];
+        const uint16_t h = bf16_rne(v);
+        const float hf = __uint_as_float((uint32_t)h << 16);
+        xhi[idx] = h;
+        xlo[idx] = bf16_rne(v - hf);
+    }
+    if (tid == 0) fcnt = 0;
+    __syncthreads();
+
+    const int wb0 = blockIdx.y * wpy;
+    const int wb1 = min(words, wb0 + wpy);
+    const int cl = lane & 31, kh = lane >> 5;
+    constexpr int RT = ROWS / 32;
+
+    for (int wb = wb0 + w; wb < wb1; wb += 4) {
+        f32x16_t acc[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[rt][r] = 0.0f;
+        const int col = wb * 32 + cl;
+        const uint16_t *bh = Hhi + (int64_t)col * kp + 8 * kh;
+        const uint16_t *bl = Hlo + (int64_t)col * kp + 8 * kh;
+        for (int ks = 0; ks < kp; ks += 16) {
+            const bf16x8_t b_h = *(const bf16x8_t *)(bh + ks);
+            const bf16x8_t b_l = *(const bf16x8_t *)(bl + ks);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const int ao = (rt * 32 + cl) * kp + ks + 8 * kh;
+                const bf16x8_t a_h = *(const bf16x8_t *)(xhi + ao);
+                const bf16x8_t a_l = *(const bf16x8_t *)(xlo + ao);
+                acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc[rt], 0, 0, 0);
+                acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc[rt], 0, 0, 0);
+                acc[rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc[rt], 0, 0, 0);
+            }
+        }
+        const float bta = beta[col];
+        uint32_t wordv = 0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float P = acc[rt][r];
+                const uint64_t mb = __ballot(P >= 0.0f);
+                const uint64_t mf = __ballot(fabsf(P) <= bta);
+                // lane l assembles the word of tile row l % 32 of row tile l / 32
+                if ((lane >> 5) == rt && ((lane & 31) >> 3) == (r >> 2) && (lane & 3) == (r & 3))
+                    wordv = ((lane >> 2) & 1) ? (uint32_t)(mb >> 32) : (uint32_t)mb;
+                if (mf) {
+                    if ((mf >> lane) & 1ull) {
+                        const int64_t grow = row0 + rt * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                        if (grow < n) {
+                            const unsigned pos = atomicAdd(&fcnt, 1u);
+                            if (pos < (unsigned)kFlagBuf) {
+                                fbuf[2 * pos] = (uint32_t)grow;
+                                fbuf[2 * pos + 1] = (uint32_t)col;
+                            } else {
+                                const unsigned gp = atomicAdd(fcount, 1u);
+                                if (gp < fcap) {
+                                    flist[2 * (int64_t)gp] = (uint32_t)grow;
+                                    flist[2 * (int64_t)gp + 1] = (uint32_t)col;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        const int64_t grow = row0 + lane;
+        if (lane < ROWS && grow < n) {
+            uint32_t *wp = word_ptr(codes, skw, n, L, wb, grow);
+            *wp = (wb < L) ? (wordv & kmask) : wordv;
+        }
+    }
+    __syncthreads();
+    const unsigned nf = min(fcnt, (unsigned)kFlagBuf);
+    if (tid == 0) fbase = nf ? atomicAdd(fcount, nf) : 0u;
+    __syncthreads();
+    for (unsigned t = tid; t < nf; t += 256) {
+        const unsigned gp = fbase + t;
+        if (gp < fcap) {
+            flist[2 * (int64_t)gp] = fbuf[2 * t];
+            flist[2 * (int64_t)gp + 1] = fbuf[2 * t + 1];
+        }
+    }
+}
+
+__device__ __forceinline__ double dot_seq64(const float *__restrict__ a, const float *__restrict__ x,
+                                            int32_t d) {
+    double s = 0.0;
+    for (int32_t c = 0; c < d; ++c) s = s + (double)a[c] * (double)x[c];
+    return s;
+}
+
+// Fix the flagged bits with the FP64 sequential projection.  If more bits were flagged
+// than the list holds, every word is recomputed in FP64 instead.
+__global__ __launch_bounds__(256) void k_hash_fix(const float *__restrict__ X, int64_t n, int32_t dpad,
+                                                  int32_t d, const float *__restrict__ hp,
+                                                  const int32_t *__restrict__ colrow, int32_t words,
+                                                  int32_t L, uint32_t kmask, uint32_t *codes,
+                                                  uint32_t *skw, const uint32_t *__restrict__ flist,
+                                                  const unsigned int *__restrict__ fcount,
+                                                  uint32_t fcap) {
+    const unsigned cnt = *fcount;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cnt <= fcap) {
+        for (int64_t t = t0; t < (int64_t)cnt; t += stride) {
+            const int64_t row = flist[2 * t];
+            const int32_t col = (int32_t)flist[2 * t + 1];
+            const int32_t hr = colrow[col];
+            const double s = dot_seq64(hp + (int64_t)hr * d, X + row * dpad, d);
+            const uint32_t bit = 1u << (col & 31);
+            uint32_t *wp = word_ptr(codes, skw, n, L, col >> 5, row);
+            if (s >= 0.0)
+                atomicOr(wp, bit);
+            else
+                atomicAnd(wp, ~bit);
+        }
+    } else {
+        for (int64_t t = t0; t < n * (int64_t)words; t += stride) {
+            const int64_t row = t / words;
+            const int32_t wb = (int32_t)(t - row * words);
+            uint32_t wv = 0;
+            for (int b = 0; b < 32; ++b) {
+                const int32_t hr = colrow[wb * 32 + b];
+                if (hr < 0) continue;
+                if (dot_seq64(hp + (int64_t)hr * d, X + row * dpad, d) >= 0.0) wv |= 1u << b;
+            }
+            *word_ptr(codes, skw, n, L, wb, row) = (wb < L) ? (wv & kmask) : wv;
+        }
+    }
+}
+
+// Reference arithmetic: every projection as the FP64 sequential sum.  One wave per
+// (row, pair of words); lane l owns column 64 p + l.
+__global__ __launch_bounds__(256) void k_hash_fp64(const float *__restrict__ X, int64_t n, int32_t dpad,
+                                                   int32_t d, const float *__restrict__ hp,
+                                                   const int32_t *__restrict__ colrow, int32_t words,
+                                                   int32_t L, uint32_t kmask, uint32_t *codes,
+                                                   uint32_t *skw) {
+    const int lane = threadIdx.x & 63;
+    const int64_t task = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int32_t pairs = (words + 1) / 2;
+    if (task >= n * (int64_t)pairs) return;
+    const int64_t row = task / pairs;
+    const int32_t pw = (int32_t)(task - row * pairs);
+    const int32_t col = pw * 64 + lane;
+    bool bit = false;
+    if (col < words * 32) {
+        const int32_t hr = colrow[col];
+        if (hr >= 0) bit = dot_seq64(hp + (int64_t)hr * d, X + row * dpad, d) >= 0.0;
+    }
+    const uint64_t mb = __ballot(bit);
+    if (lane < 2) {
+        const int32_t wb = 2 * pw + lane;
+        if (wb < words) {
+            const uint32_t wv = lane ? (uint32_t)(mb >> 32) : (uint32_t)mb;
+            *word_ptr(codes, skw, n, L, wb, row) = (wb < L) ? (wv & kmask) : wv;
+        }
+    }
+}
+
+void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
+               DevBuf &scratch, hipStream_t s) {
+    if (n <= 0) return;
+    const HashPlan &hp = ix.plan;
+    launch_fill_u32(codes, n * (int64_t)hp.L, 0u, s);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(sketches), 2 * n * (int64_t)hp.M, 0u, s);
+    const uint32_t kmask = hp.K >= 32 ? 0xFFFFFFFFu : ((1u << hp.K) - 1u);
+    uint32_t *skw = reinterpret_cast<uint32_t *>(sketches);
+    const int32_t *colrow = ix.hcolrow.as<int32_t>();
+    if (ix.hash_mode == PF_HASH_FP64 || hp.kp > 512) {
+        const int64_t tasks = n * (int64_t)((hp.words + 1) / 2);
+        hipLaunchKernelGGL(k_hash_fp64, dim3((unsigned)((tasks + 3) / 4)), dim3(256), 0, s, X, n,
+                           ix.dpad, hp.d, ix.hp.as<float>(), colrow, hp.words, hp.L, kmask, codes, skw);
+        PF_HIP(hipGetLastError());
+        return;
+    }
+    const uint64_t want = (uint64_t)n * (uint64_t)hp.ncols / 64u + 65536u;
+    const uint32_t fcap = (uint32_t)std::min<uint64_t>(want, 1ull << 30);
+    scratch.ensure(256 + (size_t)fcap * 8);
+    unsigned int *fcount = reinterpret_cast<unsigned int *>(scratch.p);
+    uint32_t *flist = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch.p) + 256);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(fcount), 1, 0u, s);
+
+    const uint16_t *Hhi = ix.hbf.as<uint16_t>();
+    const uint16_t *Hlo = Hhi + (size_t)hp.ncols * hp.kp;
+    const bool big = hp.kp > 256;
+    const int rows = big ? 32 : 64;
+    const int64_t bx = (n + rows - 1) / rows;
+    int32_t gy = 1;
+    if (bx < 4096) gy = (int32_t)std::min<int64_t>((hp.words + 3) / 4, (4096 + bx - 1) / bx);
+    const int32_t wpy = (hp.words + gy - 1) / gy;
+    gy = (hp.words + wpy - 1) / wpy;
+    const size_t lds = (size_t)2 * rows * hp.kp * sizeof(uint16_t);
+    if (big) {
+        PF_HIP(hipFuncSetAttribute((const void *)k_hash_bf16x3<32>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_hash_bf16x3<32>, dim3((unsigned)bx, (unsigned)gy), dim3(256), lds, s, X, n,
+                           ix.dpad, hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.L, kmask, wpy,
+                           codes, skw, flist, fcount, fcap);
+    } else {
+        PF_HIP(hipFuncSetAttribute((const void *)k_hash_bf16x3<64>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_hash_bf16x3<64>, dim3((unsigned)bx, (unsigned)gy), dim3(256), lds, s, X, n,
+                           ix.dpad, hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.L, kmask, wpy,
+                           codes, skw, flist, fcount, fcap);
+    }
+    PF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_hash_fix, dim3(1024), dim3(256), 0, s, X, n, ix.dpad, hp.d, ix.hp.as<float>(),
+                       colrow, hp.words, hp.L, kmask, codes, skw, flist, fcount, fcap);
+    PF_HIP(hipGetLastError());
+}
+
+} // namespace pf

@@ -1,0 +1,515 @@
+// C-ABI of the gfx950 adaptive k-NN index (declared in include/pfhip.h): argument
+// checks, device memory, the host-side hyperplane generator and hash plan, and the
+// order of kernel launches for build and search.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pf_internal.h"
+
+#define PF_API extern "C" __attribute__((visibility("default")))
+
+namespace pf {
+
+static thread_local std::string g_err;
+
+template <class F> static int guard(F &&f) {
+    try {
+        f();
+        return PF_OK;
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return PF_ENOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return PF_EDEVICE;
+    }
+}
+
+// ------------------------------------------------------------------ hyperplanes
+// Random hyperplanes (Sec. 2.2: independent standard normal coordinates).  Counter-based
+// SplitMix64 (Steele, Lea, Flood 2014): output s of the stream with seed S is
+// mix(S + (s + 1) * 0x9E3779B97F4A7C15).  Element (r, c) of the d-column matrix uses
+// outputs 2t and 2t+1, t = r d + c, in the Box-Muller transform evaluated in FP64:
+// u1 = ((z1 >> 11) + 1) 2^-53, u2 = (z2 >> 11) 2^-53, a = sqrt(-2 ln u1) cos(2 pi u2).
+static inline uint64_t splitmix64_at(uint64_t seed, uint64_t s) {
+    uint64_t z = seed + (s + 1u) * 0x9E3779B97F4A7C15ull;
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+
+static void make_hyperplanes(uint64_t seed, int64_t rows, int32_t d, float *out) {
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t r = 0; r < rows; ++r)
+        for (int32_t c = 0; c < d; ++c) {
+            const uint64_t t = (uint64_t)r * (uint64_t)d + (uint64_t)c;
+            const uint64_t z1 = splitmix64_at(seed, 2u * t);
+            const uint64_t z2 = splitmix64_at(seed, 2u * t + 1u);
+            const double u1 = ((double)(z1 >> 11) + 1.0) * 0x1.0p-53;
+            const double u2 = (double)(z2 >> 11) * 0x1.0p-53;
+            out[r * d + c] = (float)(std::sqrt(-2.0 * std::log(u1)) * std::cos(two_pi * u2));
+        }
+}
+
+static inline uint16_t bf16_rne_host(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Error bound of the split-BF16 projection (see k_hash.hip).  For one column a and a
+// unit row x: the three dropped split products are at most 3.01 * 2^-16 * sum|a_i x_i|,
+// and the FP32 accumulation of 3 kp exact products adds at most 1.02 * gamma_{3 kp} *
+// sum|a_i x_i| (Higham's bound, gamma_m = m u / (1 - m u), u = 2^-24); sum|a_i x_i| <=
+// |a| |x| and |x| <= 1.0001 after normalisation.  The bound is doubled to allow for
+// truncating accumulation inside the matrix core.
+static double split_bf16_bound(int32_t kp, double norm_a) {
+    const double u = 0x1.0p-24;
+    const double m = 3.0 * kp;
+    const double gamma = m * u / (1.0 - m * u);
+    return 2.0 * (3.01 * 0x1.0p-16 + 1.02 * gamma) * norm_a * 1.0001 + 1e-30 * kp;
+}
+
+static void build_plan(Index &ix, const std::vector<float> &hp) {
+    HashPlan &p = ix.plan;
+    p.d = ix.d;
+    p.dpad = ix.dpad;
+    p.kp = (ix.d + 15) / 16 * 16;
+    p.L = ix.L;
+    p.K = ix.K;
+    p.M = ix.M;
+    p.words = ix.L + 2 * ix.M;
+    p.ncols = 32 * p.words;
+    std::vector<int32_t> colrow(p.ncols, -1);
+    std::vector<float> beta(p.ncols, -1.0f);
+    for (int32_t wb = 0; wb < p.words; ++wb)
+        for (int32_t c = 0; c < 32; ++c) {
+            int64_t row = -1;
+            if (wb < ix.L) {
+                if (c < ix.K) row = (int64_t)wb * ix.K + (ix.K - 1 - c);
+            } else {
+                const int32_t s = wb - ix.L;
+                row = (int64_t)ix.L * ix.K + 64 * (s >> 1) + 32 * (s & 1) + c;
+            }
+            colrow[wb * 32 + c] = (int32_t)row;
+        }
+    std::vector<uint16_t> hb((size_t)2 * p.ncols * p.kp, 0);
+    for (int32_t col = 0; col < p.ncols; ++col) {
+        const int64_t row = colrow[col];
+        if (row < 0) continue;
+        double s2 = 0.0;
+        for (int32_t c = 0; c < ix.d; ++c) {
+            const float v = hp[row * ix.d + c];
+            s2 += (double)v * (double)v;
+            const uint16_t h = bf16_rne_host(v);
+            uint32_t hu = (uint32_t)h << 16;
+            float hf;
+            std::memcpy(&hf, &hu, 4);
+            hb[(size_t)col * p.kp + c] = h;
+            hb[(size_t)p.ncols * p.kp + (size_t)col * p.kp + c] = bf16_rne_host(v - hf);
+        }
+        beta[col] = (float)(split_bf16_bound(p.kp, std::sqrt(s2)) * (1.0 + 0x1.0p-20));
+    }
+    ix.hcolrow.alloc(colrow.size() * sizeof(int32_t));
+    PF_HIP(hipMemcpy(ix.hcolrow.p, colrow.data(), colrow.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    ix.hbeta.alloc(beta.size() * sizeof(float));
+    PF_HIP(hipMemcpy(ix.hbeta.p, beta.data(), beta.size() * sizeof(float), hipMemcpyHostToDevice));
+    ix.hbf.alloc(hb.size() * sizeof(uint16_t));
+    PF_HIP(hipMemcpy(ix.hbf.p, hb.data(), hb.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+}
+
+// budget rule: bytes of the vectors and sketch functions, and bytes per table
+static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, uint64_t &fixed, uint64_t &per) {
+    const int32_t P = std::min(13, K);
+    fixed = 4ull * (uint64_t)n * (uint64_t)d + 4ull * 64ull * (uint64_t)M * (uint64_t)d;
+    per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) + 4ull * (uint64_t)K * (uint64_t)d;
+}
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// normalise caller rows (host or device) into dst (rows x dpad); throws PF_EINVAL on a bad row
+static void normalize_into(const float *src, int64_t rows, int32_t d, int32_t mem, float *dst, int32_t dpad,
+                           DevBuf &staging, DevBuf &flag, hipStream_t s) {
+    const float *in = src;
+    if (mem == PF_HOST) {
+        staging.ensure((size_t)rows * d * sizeof(float));
+        PF_HIP(hipMemcpyAsync(staging.p, src, (size_t)rows * d * sizeof(float), hipMemcpyHostToDevice, s));
+        in = staging.as<float>();
+    }
+    flag.ensure(sizeof(unsigned long long));
+    const unsigned long long init = ~0ull;
+    PF_HIP(hipMemcpyAsync(flag.p, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    launch_normalize(in, rows, d, d, dst, dpad, flag.as<unsigned long long>(), s);
+    unsigned long long bad = 0;
+    PF_HIP(hipMemcpyAsync(&bad, flag.p, sizeof(bad), hipMemcpyDeviceToHost, s));
+    PF_HIP(hipStreamSynchronize(s));
+    if (bad != ~0ull)
+        throw Error(PF_EINVAL, "row " + std::to_string(bad) + " has zero or non-finite norm");
+}
+
+} // namespace pf
+
+using namespace pf;
+
+struct pf_index : public pf::Index {};
+
+PF_API const char *pf_last_error(void) { return g_err.c_str(); }
+PF_API const char *pf_version(void) { return "pfhip 0.1 (gfx950)"; }
+
+PF_API int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, void *stream) {
+    return guard([&] {
+        PF_CHECK(x && out && n >= 0 && d >= 1 && d <= PF_MAX_DIM, PF_EINVAL, "pf_normalize: bad arguments");
+        PF_CHECK(mem == PF_HOST || mem == PF_DEVICE, PF_EINVAL, "pf_normalize: bad mem");
+        if (n == 0) return;
+        hipStream_t s = as_stream(stream);
+        DevBuf staging, flag, dst;
+        float *o = out;
+        if (mem == PF_HOST) {
+            dst.alloc((size_t)n * d * sizeof(float));
+            o = dst.as<float>();
+        }
+        normalize_into(x, n, d, mem, o, d, staging, flag, s);
+        if (mem == PF_HOST) {
+            PF_HIP(hipMemcpyAsync(out, o, (size_t)n * d * sizeof(float), hipMemcpyDeviceToHost, s));
+            PF_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t budget,
+                          const pf_build_opts *opts, int32_t mem, void *stream, pf_index **out) {
+    return guard([&] {
+        PF_CHECK(out && points, PF_EINVAL, "pf_build_index: null argument");
+        PF_CHECK(n >= 1 && n < (1ll << 31), PF_EINVAL, "pf_build_index: n must be in [1, 2^31)");
+        PF_CHECK(d >= 1 && d <= PF_MAX_DIM, PF_EINVAL, "pf_build_index: d out of range");
+        PF_CHECK(mem == PF_HOST || mem == PF_DEVICE, PF_EINVAL, "pf_build_index: bad mem");
+        pf_build_opts o{};
+        if (opts) o = *opts;
+        const int32_t K = o.K ? o.K : 24;
+        const int32_t M = o.M ? o.M : 32;
+        PF_CHECK(K >= 1 && K <= 32, PF_EINVAL, "pf_build_index: K must be in [1, 32]");
+        PF_CHECK(M >= 1 && M <= 64, PF_EINVAL, "pf_build_index: M must be in [1, 64]");
+        PF_CHECK(o.hash_mode == PF_HASH_BF16X3 || o.hash_mode == PF_HASH_FP64, PF_EINVAL,
+                 "pf_build_index: bad hash_mode");
+        uint64_t fixed, per;
+        budget_terms(n, d, K, M, fixed, per);
+        int64_t L = o.L_override;
+        if (L <= 0) L = budget > fixed ? (int64_t)((budget - fixed) / per) : 0;
+        PF_CHECK(L >= 1, PF_EBUDGET, "pf_build_index: the memory budget holds no table");
+        L = std::min<int64_t>(L, PF_MAX_TABLES);
+        PF_CHECK((uint64_t)L * (uint64_t)n < (1ull << 32), PF_EUNSUPPORTED,
+                 "pf_build_index: L * n must be below 2^32");
+
+        auto ix = std::make_unique<pf_index>();
+        hipStream_t s = as_stream(stream);
+        PF_HIP(hipGetDevice(&ix->device));
+        hipDeviceProp_t prop;
+        PF_HIP(hipGetDeviceProperties(&prop, ix->device));
+        ix->num_cus = prop.multiProcessorCount;
+        ix->n = n;
+        ix->d = d;
+        ix->dpad = (d + 3) / 4 * 4;
+        ix->K = K;
+        ix->M = M;
+        ix->P = std::min(13, K);
+        ix->L = (int32_t)L;
+        ix->seed = o.seed;
+        ix->hash_mode = o.hash_mode;
+        ix->bytes_rule = fixed + (uint64_t)L * per;
+
+        hipEvent_t e0, e1;
+        PF_HIP(hipEventCreate(&e0));
+        PF_HIP(hipEventCreate(&e1));
+        PF_HIP(hipEventRecord(e0, s));
+        // a1: normalised vectors
+        ix->X.alloc((size_t)n * ix->dpad * sizeof(float));
+        normalize_into(points, n, d, mem, ix->X.as<float>(), ix->dpad, ix->tmp, ix->flags, s);
+        ix->tmp.release();
+        // a3: hyperplanes (host generator), device copies and hash plan
+        const int64_t rows = L * K + 64ll * M;
+        std::vector<float> hp((size_t)rows * d);
+        make_hyperplanes(o.seed, rows, d, hp.data());
+        ix->hp.alloc(hp.size() * sizeof(float));
+        PF_HIP(hipMemcpy(ix->hp.p, hp.data(), hp.size() * sizeof(float), hipMemcpyHostToDevice));
+        build_plan(*ix, hp);
+        // a4/a5: codes (L x n) and sketches (M x n)
+        DevBuf codes, sk, scratch;
+        codes.alloc((size_t)L * n * sizeof(uint32_t));
+        sk.alloc((size_t)M * n * sizeof(uint64_t));
+        hash_rows(*ix, ix->X.as<float>(), n, codes.as<uint32_t>(), sk.as<uint64_t>(), scratch, s);
+        // a6: sorted tables
+        ix->tcode.alloc((size_t)L * n * sizeof(uint32_t));
+        ix->tidx.alloc((size_t)L * n * sizeof(uint32_t));
+        sort_tables(codes.as<uint32_t>(), n, (int32_t)L, K, ix->tcode.as<uint32_t>(), ix->tidx.as<uint32_t>(),
+                    scratch, s);
+        // a7: prefix tables
+        ix->off.alloc((size_t)L * ((1ull << ix->P) + 1) * sizeof(uint32_t));
+        prefix_tables(ix->tcode.as<uint32_t>(), n, (int32_t)L, K, ix->P, ix->off.as<uint32_t>(), s);
+        // a8: table-local sketches
+        ix->tsk.alloc((size_t)L * n * sizeof(uint64_t));
+        gather_sketches(ix->tidx.as<uint32_t>(), sk.as<uint64_t>(), n, (int32_t)L, M, ix->tsk.as<uint64_t>(), s);
+        PF_HIP(hipEventRecord(e1, s));
+        PF_HIP(hipStreamSynchronize(s));
+        float ms = 0;
+        PF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ix->build_ms = ms;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *out = ix.release();
+    });
+}
+
+namespace pf {
+// normalise + hash rows into qX / codes / sketches held by the index
+static void prepare_rows(pf_index *ix, const float *x, int64_t m, int32_t mem, hipStream_t s,
+                         float **qX, uint32_t **qcode, uint64_t **qsk) {
+    ix->qX.ensure((size_t)m * ix->dpad * sizeof(float));
+    normalize_into(x, m, ix->d, mem, ix->qX.as<float>(), ix->dpad, ix->tmp, ix->flags, s);
+    ix->qcode.ensure((size_t)m * ix->L * sizeof(uint32_t));
+    ix->qsk.ensure((size_t)m * ix->M * sizeof(uint64_t));
+    DevBuf scratch;
+    hash_rows(*ix, ix->qX.as<float>(), m, ix->qcode.as<uint32_t>(), ix->qsk.as<uint64_t>(), scratch, s);
+    // scratch must outlive the queued kernels
+    PF_HIP(hipStreamSynchronize(s));
+    *qX = ix->qX.as<float>();
+    *qcode = ix->qcode.as<uint32_t>();
+    *qsk = ix->qsk.as<uint64_t>();
+}
+
+static void search_impl(pf_index *ix, const float *queries, int64_t m, const int32_t *ks, int32_t kconst,
+                        int32_t kmax, const double *recalls, double recall_const, const pf_search_opts *opts,
+                        int32_t *out_ids, float *out_ips, pf_query_stats *stats, int32_t mem, void *stream) {
+    PF_CHECK(ix, PF_EINVAL, "null index");
+    PF_CHECK(queries && out_ids && m >= 0, PF_EINVAL, "search: bad arguments");
+    PF_CHECK(mem == PF_HOST || mem == PF_DEVICE, PF_EINVAL, "search: bad mem");
+    PF_CHECK(kmax >= 1 && kmax <= PF_MAX_K && kmax <= ix->n, PF_EINVAL, "search: k must be in [1, min(n, 256)]");
+    pf_search_opts o{0.0, 12, PF_RULE_EXACT, 1, 0};
+    if (opts) {
+        o = *opts;
+        if (o.B == 0) o.B = 12;
+    }
+    PF_CHECK(o.B >= 1, PF_EINVAL, "search: B must be >= 1");
+    PF_CHECK(o.rule == PF_RULE_EXACT || o.rule == PF_RULE_ALG1, PF_EINVAL, "search: bad rule");
+    if (!recalls)
+        PF_CHECK(recall_const > 0.0 && recall_const <= 1.0, PF_EINVAL, "search: recall must be in (0, 1]");
+    if (m == 0) return;
+    hipStream_t s = as_stream(stream);
+    if (mem == PF_HOST && ks) {
+        for (int64_t i = 0; i < m; ++i)
+            PF_CHECK(ks[i] >= 1 && ks[i] <= kmax, PF_EINVAL, "search: per-query k out of range");
+    }
+    if (mem == PF_HOST && recalls) {
+        for (int64_t i = 0; i < m; ++i)
+            PF_CHECK(recalls[i] > 0.0 && recalls[i] <= 1.0, PF_EINVAL, "search: recall must be in (0, 1]");
+    }
+    hipEvent_t ev[5];
+    if (o.timing)
+        for (auto &e : ev) PF_HIP(hipEventCreate(&e));
+    if (o.timing) PF_HIP(hipEventRecord(ev[0], s));
+    float *qX;
+    uint32_t *qcode;
+    uint64_t *qsk;
+    prepare_rows(ix, queries, m, mem, s, &qX, &qcode, &qsk);
+    if (o.timing) PF_HIP(hipEventRecord(ev[1], s));
+    // outputs and per-query parameters on the device
+    DevBuf dids, dips, dstats, dks, drec;
+    int32_t *oid = out_ids;
+    float *oip = out_ips;
+    pf_query_stats *ost = stats;
+    const int32_t *dk = ks;
+    const double *dr = recalls;
+    if (mem == PF_HOST) {
+        dids.alloc((size_t)m * kmax * sizeof(int32_t));
+        oid = dids.as<int32_t>();
+        if (out_ips) {
+            dips.alloc((size_t)m * kmax * sizeof(float));
+            oip = dips.as<float>();
+        }
+        if (stats) {
+            dstats.alloc((size_t)m * sizeof(pf_query_stats));
+            ost = dstats.as<pf_query_stats>();
+        }
+        if (ks) {
+            dks.alloc((size_t)m * sizeof(int32_t));
+            PF_HIP(hipMemcpyAsync(dks.p, ks, (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            dk = dks.as<int32_t>();
+        }
+        if (recalls) {
+            drec.alloc((size_t)m * sizeof(double));
+            PF_HIP(hipMemcpyAsync(drec.p, recalls, (size_t)m * sizeof(double), hipMemcpyHostToDevice, s));
+            dr = drec.as<double>();
+        }
+    }
+    SearchArgs a;
+    a.Q = qX;
+    a.qcode = qcode;
+    a.qsk = qsk;
+    a.m = m;
+    a.ks = dk;
+    a.kconst = kconst;
+    a.kmax = kmax;
+    a.recalls = dr;
+    a.recall_const = recall_const;
+    a.eps = o.eps;
+    a.B = o.B;
+    a.rule = o.rule;
+    a.filter = o.filter ? 1 : 0;
+    a.out_ids = oid;
+    a.out_ips = oip;
+    a.stats = ost;
+    const int32_t nl = ix->K - ix->P;
+    uint32_t *rg = nullptr;
+    if (nl > 0) {
+        ix->ranges.ensure((size_t)m * ix->L * nl * 2 * sizeof(uint32_t));
+        rg = ix->ranges.as<uint32_t>();
+    }
+    launch_ranges(*ix, a, rg, s);
+    if (o.timing) PF_HIP(hipEventRecord(ev[2], s));
+    launch_search(*ix, a, rg, s);
+    if (o.timing) PF_HIP(hipEventRecord(ev[3], s));
+    if (mem == PF_HOST) {
+        PF_HIP(hipMemcpyAsync(out_ids, oid, (size_t)m * kmax * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (out_ips)
+            PF_HIP(hipMemcpyAsync(out_ips, oip, (size_t)m * kmax * sizeof(float), hipMemcpyDeviceToHost, s));
+        if (stats)
+            PF_HIP(hipMemcpyAsync(stats, ost, (size_t)m * sizeof(pf_query_stats), hipMemcpyDeviceToHost, s));
+        PF_HIP(hipStreamSynchronize(s));
+    }
+    if (o.timing) {
+        PF_HIP(hipEventSynchronize(ev[3]));
+        float t01, t12, t23, t03;
+        PF_HIP(hipEventElapsedTime(&t01, ev[0], ev[1]));
+        PF_HIP(hipEventElapsedTime(&t12, ev[1], ev[2]));
+        PF_HIP(hipEventElapsedTime(&t23, ev[2], ev[3]));
+        PF_HIP(hipEventElapsedTime(&t03, ev[0], ev[3]));
+        ix->timing.normalize_ms = 0.0;
+        ix->timing.hash_ms = t01;
+        ix->timing.ranges_ms = t12;
+        ix->timing.search_ms = t23;
+        ix->timing.total_ms = t03;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    } else if (mem == PF_DEVICE) {
+        // temporaries above are released on return: make sure the kernels are done
+        PF_HIP(hipStreamSynchronize(s));
+    }
+}
+} // namespace pf
+
+PF_API int pf_search_ex(pf_index *ix, const float *queries, int64_t m, int32_t k, double recall,
+                        const pf_search_opts *opts, int32_t *out_ids, float *out_ips, pf_query_stats *stats,
+                        int32_t mem, void *stream) {
+    return guard([&] {
+        search_impl(ix, queries, m, nullptr, k, k, nullptr, recall, opts, out_ids, out_ips, stats, mem, stream);
+    });
+}
+
+PF_API int pf_search(pf_index *ix, const float *queries, int64_t m, int32_t k, double recall, int32_t *out_ids,
+                     float *out_ips, pf_query_stats *stats, int32_t mem, void *stream) {
+    return pf_search_ex(ix, queries, m, k, recall, nullptr, out_ids, out_ips, stats, mem, stream);
+}
+
+PF_API int pf_hash(pf_index *ix, const float *x, int64_t m, uint32_t *codes, uint64_t *sketches, int32_t mem,
+                   void *stream) {
+    return guard([&] {
+        PF_CHECK(ix && x && m >= 0, PF_EINVAL, "pf_hash: bad arguments");
+        PF_CHECK(mem == PF_HOST || mem == PF_DEVICE, PF_EINVAL, "pf_hash: bad mem");
+        if (m == 0) return;
+        hipStream_t s = as_stream(stream);
+        float *qX;
+        uint32_t *qc;
+        uint64_t *qs;
+        prepare_rows(ix, x, m, mem, s, &qX, &qc, &qs);
+        const hipMemcpyKind kind = mem == PF_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+        if (codes) PF_HIP(hipMemcpyAsync(codes, qc, (size_t)m * ix->L * sizeof(uint32_t), kind, s));
+        if (sketches) PF_HIP(hipMemcpyAsync(sketches, qs, (size_t)m * ix->M * sizeof(uint64_t), kind, s));
+        PF_HIP(hipStreamSynchronize(s));
+    });
+}
+
+PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_bytes, int32_t mem, void *stream) {
+    return guard([&] {
+        PF_CHECK(ix && dst, PF_EINVAL, "pf_export: null argument");
+        PF_CHECK(mem == PF_HOST || mem == PF_DEVICE, PF_EINVAL, "pf_export: bad mem");
+        hipStream_t s = as_stream(stream);
+        const hipMemcpyKind kind = mem == PF_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+        const int64_t n = ix->n;
+        auto need = [&](int64_t b) {
+            PF_CHECK(dst_bytes >= b, PF_EINVAL, "pf_export: destination too small");
+        };
+        switch (what) {
+        case PF_EXPORT_POINTS:
+            need(n * ix->d * 4);
+            PF_HIP(hipMemcpy2DAsync(dst, (size_t)ix->d * 4, ix->X.p, (size_t)ix->dpad * 4, (size_t)ix->d * 4,
+                                    (size_t)n, kind, s));
+            break;
+        case PF_EXPORT_HYPERPLANES: {
+            const int64_t b = ((int64_t)ix->L * ix->K + 64ll * ix->M) * ix->d * 4;
+            need(b);
+            PF_HIP(hipMemcpyAsync(dst, ix->hp.p, (size_t)b, kind, s));
+            break;
+        }
+        case PF_EXPORT_CODES:
+            need((int64_t)ix->L * n * 4);
+            PF_HIP(hipMemcpyAsync(dst, ix->tcode.p, (size_t)ix->L * n * 4, kind, s));
+            break;
+        case PF_EXPORT_IDX:
+            need((int64_t)ix->L * n * 4);
+            PF_HIP(hipMemcpyAsync(dst, ix->tidx.p, (size_t)ix->L * n * 4, kind, s));
+            break;
+        case PF_EXPORT_SKETCHES:
+            need((int64_t)ix->L * n * 8);
+            PF_HIP(hipMemcpyAsync(dst, ix->tsk.p, (size_t)ix->L * n * 8, kind, s));
+            break;
+        case PF_EXPORT_OFFSETS: {
+            const int64_t b = (int64_t)ix->L * ((1ll << ix->P) + 1) * 4;
+            need(b);
+            PF_HIP(hipMemcpyAsync(dst, ix->off.p, (size_t)b, kind, s));
+            break;
+        }
+        default:
+            throw Error(PF_EINVAL, "pf_export: unknown structure");
+        }
+        PF_HIP(hipStreamSynchronize(s));
+    });
+}
+
+PF_API int pf_index_info(const pf_index *ix, pf_info *info) {
+    return guard([&] {
+        PF_CHECK(ix && info, PF_EINVAL, "pf_index_info: null argument");
+        pf_info r{};
+        r.n = ix->n;
+        r.d = ix->d;
+        r.L = ix->L;
+        r.K = ix->K;
+        r.M = ix->M;
+        r.P = ix->P;
+        r.bytes_budget_rule = ix->bytes_rule;
+        r.bytes_device = ix->X.bytes + ix->hp.bytes + ix->hcolrow.bytes + ix->hbf.bytes + ix->hbeta.bytes +
+                         ix->tcode.bytes + ix->tidx.bytes + ix->tsk.bytes + ix->off.bytes;
+        r.build_ms = ix->build_ms;
+        *info = r;
+    });
+}
+
+PF_API int pf_last_timing(const pf_index *ix, pf_timing *t) {
+    return guard([&] {
+        PF_CHECK(ix && t, PF_EINVAL, "pf_last_timing: null argument");
+        *t = ix->timing;
+    });
+}
+
+PF_API void pf_free_index(pf_index *ix) { delete ix; }

@@ -1,0 +1,134 @@
+// Internal declarations of the gfx950 library: the index object, kernel launchers and
+// small device helpers.  Not part of the C-ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/pfhip.h"
+
+namespace pf {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define PF_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw ::pf::Error(e_ == hipErrorOutOfMemory ? PF_ENOMEM : PF_EDEVICE,        \
+                              std::string(#call) + ": " + hipGetErrorString(e_));        \
+        } while (0)
+
+#define PF_CHECK(cond, code, msg)                                                        \
+    do {                                                                                 \
+        if (!(cond)) throw ::pf::Error((code), (msg));                                   \
+    } while (0)
+
+// Device allocation held by the index (RAII, freed with hipFree).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t b) {
+        release();
+        if (b == 0) b = 16;
+        PF_HIP(hipMalloc(&p, b));
+        bytes = b;
+    }
+    void ensure(size_t b) {
+        if (bytes < b) alloc(b);
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Hyperplane matrix laid out for the hash GEMM: 32 output columns per 32-bit word.
+//   word w < L        : table w's code, column c of the word = code bit c
+//                       (c < K: hyperplane h_{K-c, w}; c >= K: zero padding)
+//   word L + 2m + h    : sketch m, bits 32h .. 32h+31
+struct HashPlan {
+    int32_t d = 0, dpad = 0, kp = 0; // kp: reduction length padded to the MFMA step
+    int32_t L = 0, K = 0, M = 0;
+    int32_t words = 0;  // L + 2M
+    int32_t ncols = 0;  // 32 * words
+};
+
+struct Index {
+    int64_t n = 0;
+    int32_t d = 0, dpad = 0, L = 0, K = 0, M = 0, P = 0;
+    int32_t hash_mode = PF_HASH_BF16X3;
+    uint64_t seed = 0;
+    uint64_t bytes_rule = 0;
+    double build_ms = 0.0;
+    HashPlan plan;
+    int device = 0;
+    int num_cus = 0;
+
+    DevBuf X;      // n x dpad FP32 normalised vectors (zero padded)
+    DevBuf hp;     // (L*K + 64*M) x d FP32 hyperplanes (paper order)
+    DevBuf hcolrow;// ncols int32: hyperplane row of each GEMM column (-1 = padding)
+    DevBuf hbf;    // ncols x kp bf16 hi parts, then ncols x kp bf16 lo parts
+    DevBuf hbeta;  // ncols FP32 flag bounds (negative = never flagged)
+    DevBuf tcode;  // L x n u32
+    DevBuf tidx;   // L x n u32
+    DevBuf tsk;    // L x n u64
+    DevBuf off;    // L x (2^P + 1) u32
+
+    // search scratch (grown on demand)
+    DevBuf qX, qcode, qsk, ranges, bitmap, rlist, qstats, flags, tmp;
+    pf_timing timing{};
+};
+
+// ----------------------------------------------------------------- launchers
+// normalise: out[i][0..d) = x[i]/|x[i]|, zero-filled to dpad; *bad = min bad row (or n)
+void launch_normalize(const float *x, int64_t n, int32_t d, int32_t ld_in, float *out,
+                      int32_t dpad, unsigned long long *bad, hipStream_t s);
+
+void launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s);
+
+// hashing of rows X (n x dpad) into code words; see k_hash.hip
+void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
+               DevBuf &scratch, hipStream_t s);
+
+// sorting and derived tables; see k_sort.hip
+void sort_tables(const uint32_t *codes, int64_t n, int32_t L, int32_t K, uint32_t *tcode,
+                 uint32_t *tidx, DevBuf &scratch, hipStream_t s);
+void prefix_tables(const uint32_t *tcode, int64_t n, int32_t L, int32_t K, int32_t P,
+                   uint32_t *off, hipStream_t s);
+void gather_sketches(const uint32_t *tidx, const uint64_t *sk, int64_t n, int32_t L,
+                     int32_t M, uint64_t *tsk, hipStream_t s);
+
+// search; see k_search.hip
+struct SearchArgs {
+    const float *Q;        // m x dpad normalised
+    const uint32_t *qcode; // L x m
+    const uint64_t *qsk;   // M x m
+    int64_t m;
+    const int32_t *ks;     // per-query k (nullable: kconst)
+    int32_t kconst, kmax;
+    const double *recalls; // per-query recall (nullable: recall_const)
+    double recall_const;
+    double eps;
+    int32_t B, rule, filter;
+    int32_t *out_ids;      // m x kmax
+    float *out_ips;        // m x kmax (nullable)
+    pf_query_stats *stats; // m (nullable)
+};
+void launch_ranges(const Index &ix, const SearchArgs &a, uint32_t *ranges, hipStream_t s);
+void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s);
+int64_t search_slots(const Index &ix, int64_t m);
+
+} // namespace pf

@@ -1,0 +1,178 @@
+"""Parity of the gfx950 library with the CPU oracle (needs an MI355X).
+
+Bar: bit-exact for normalised vectors, hash bits, sorted tables, prefix tables,
+table-local sketches, returned ids, FP32 inner products (one fixed summation order on
+both sides) and the per-query counters; queries whose FP64 filter threshold or stopping
+test came within 1e-9 of flipping are reported by the oracle and excluded (the two
+sides use different libm implementations there).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1906_12211_amd as pf
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _build_both(X, budget=0, L=None, seed=42, K=24, M=32, hash_mode=pf.PF_HASH_BF16X3):
+    print(f"[build] n={len(X)} d={X.shape[1]} L={L} budget={budget} K={K} M={M} mode={hash_mode}", flush=True)
+    g = pf.Index(X, budget, seed=seed, K=K, M=M, hash_mode=hash_mode, L=L)
+    o = oracle.OracleIndex(X, budget, seed=seed, K=K, M=M, L=g.L)
+    return g, o
+
+
+def _assert_index_equal(g, o):
+    assert (g.L, g.K, g.M) == (o.L, o.K, o.M)
+    assert np.array_equal(g.export(pf.PF_EXPORT_POINTS), o.points), "normalised points"
+    assert np.array_equal(g.export(pf.PF_EXPORT_HYPERPLANES), o.hp), "hyperplanes"
+    gc, gi = g.export(pf.PF_EXPORT_CODES), g.export(pf.PF_EXPORT_IDX)
+    bad = np.argwhere(gc != o.tcode)
+    assert bad.size == 0, f"{len(bad)} code mismatches, first {bad[:5]}"
+    assert np.array_equal(gi, o.tidx), "table order"
+    assert np.array_equal(g.export(pf.PF_EXPORT_OFFSETS), o.off), "prefix tables"
+    assert np.array_equal(g.export(pf.PF_EXPORT_SKETCHES), o.tsk), "table-local sketches"
+
+
+def _assert_search_equal(gr, orr, label=""):
+    ok = orr.boundary == 0
+    print(f"[search {label}] boundary cases: {int((~ok).sum())} of {len(ok)}", flush=True)
+    st = gr.stats
+    for name, gv, ov in [("stop_level", st[:, 0], orr.stop_level), ("c_scan", st[:, 1], orr.c_scan),
+                         ("c_pass", st[:, 2], orr.c_pass), ("c_rerank", st[:, 3], orr.c_rerank)]:
+        bad = np.nonzero((gv != ov) & ok)[0]
+        assert bad.size == 0, f"{label} {name}: {bad.size} mismatches, q={bad[:5]} gpu={gv[bad[:5]]} oracle={ov[bad[:5]]}"
+    bad = np.nonzero(np.any(gr.ids != orr.ids, axis=1) & ok)[0]
+    assert bad.size == 0, f"{label} ids differ for {bad.size} queries, first {bad[:5]}"
+    assert np.array_equal(gr.ips[ok].view(np.uint32), orr.ips[ok].view(np.uint32)), f"{label} ips"
+    assert ok.mean() > 0.99
+
+
+def test_normalize_bit_exact():
+    for (n, d) in [(1, 1), (7, 3), (513, 17), (1000, 64), (257, 100), (64, 256), (5, 1000)]:
+        X = workloads.gaussian_unit(n, d, 100 + d) * np.float32(1.7)
+        X[0] *= np.float32(1e-3)
+        print(f"[normalize] n={n} d={d}", flush=True)
+        assert np.array_equal(pf.pf_normalize(X), oracle.normalize(X))
+
+
+def test_normalize_rejects_bad_rows():
+    X = workloads.gaussian_unit(10, 8, 1)
+    X[4] = 0
+    with pytest.raises(pf.PfError) as e:
+        pf.pf_normalize(X)
+    assert e.value.code == pf.PF_EINVAL
+
+
+@pytest.mark.parametrize("mode", [pf.PF_HASH_BF16X3, pf.PF_HASH_FP64])
+def test_build_small_bit_exact(mode):
+    X = workloads.gaussian_unit(3000, 64, 7)
+    g, o = _build_both(X, L=20, seed=7, hash_mode=mode)
+    _assert_index_equal(g, o)
+
+
+@pytest.mark.parametrize("n,d,K,M,L", [(4097, 17, 24, 3, 9), (50, 3, 8, 1, 5), (1200, 100, 13, 2, 7),
+                                       (900, 33, 32, 1, 3), (4096, 130, 24, 2, 4), (700, 300, 20, 1, 3)])
+def test_build_shapes_bit_exact(n, d, K, M, L):
+    """ragged tiles, d not a multiple of 4 / 16, K below and at the 13-bit prefix,
+    K = 32 (no padding bits), d above 256 (32-row GEMM tiles)"""
+    X = workloads.gaussian_unit(n, d, n + d)
+    g, o = _build_both(X, L=L, seed=n, K=K, M=M)
+    _assert_index_equal(g, o)
+
+
+def test_hash_queries_bit_exact():
+    X = workloads.gaussian_unit(2000, 100, 3)
+    Q = workloads.gaussian_unit(777, 100, 4)
+    g, o = _build_both(X, L=15, seed=11, M=4)
+    gc, gs = g.hash(Q)
+    oc, os_ = oracle.hash_codes(oracle.normalize(Q), o.hp, o.L, o.K, o.M)
+    assert np.array_equal(gc, oc)
+    assert np.array_equal(gs, os_)
+
+
+def test_config1_parity():
+    """gauss-10k-d64, 64 MiB budget -> L = 321, 1000 queries, k = 10, recall .9"""
+    c = workloads.config(1)
+    g, o = _build_both(c["points"], budget=c["budget"])
+    assert g.L == 321
+    _assert_index_equal(g, o)
+    gr = g.search(c["queries"], 10, 0.9)
+    orr = o.search(c["queries"], 10, 0.9)
+    _assert_search_equal(gr, orr, "config1")
+
+
+@pytest.mark.parametrize("k,recall,kw", [
+    (1, 0.9, {}), (10, 0.5, {}), (10, 0.99, {}), (37, 0.9, {}), (10, 0.9, {"B": 1}),
+    (10, 0.9, {"filter": False}), (10, 0.9, {"rule": pf.PF_RULE_ALG1}), (10, 0.9, {"eps": 0.1}),
+    (5, 1.0, {}), (128, 0.7, {}),
+])
+def test_search_variants(k, recall, kw):
+    X = workloads.gaussian_unit(5000, 48, 21)
+    Q = workloads.gaussian_unit(300, 48, 22)
+    g, o = _build_both(X, L=40, seed=5)
+    okw = dict(kw)
+    if "filter" in okw:
+        okw["filter_on"] = okw.pop("filter")
+    gr = g.search(Q, k, recall, **kw)
+    orr = o.search(Q, k, recall, **okw)
+    _assert_search_equal(gr, orr, f"k={k} r={recall} {kw}")
+
+
+def test_linear_scan_equals_bruteforce():
+    """recall 1: every query walks to level 0 and returns the exact k-NN (Lemma 1)."""
+    X = workloads.gaussian_unit(3000, 32, 31)
+    Q = workloads.gaussian_unit(100, 32, 32)
+    g = pf.Index(X, 0, seed=3, L=8)
+    r = g.search(Q, 10, 1.0)
+    assert np.all(r.stats[:, 0] == 0)
+    assert np.all(r.stats[:, 3] == len(X))
+    ids, _ = oracle.bruteforce(oracle.normalize(X), oracle.normalize(Q), 10)
+    assert np.mean(np.all(r.ids == ids, axis=1)) > 0.95
+
+
+def test_small_n_and_k_equals_n():
+    X = workloads.gaussian_unit(40, 6, 41)
+    Q = workloads.gaussian_unit(20, 6, 42)
+    g, o = _build_both(X, L=6, seed=9)
+    _assert_search_equal(g.search(Q, 40, 0.9), o.search(Q, 40, 0.9), "k=n")
+    _assert_search_equal(g.search(Q, 1, 0.6), o.search(Q, 1, 0.6), "n=40 k=1")
+
+
+def test_device_tensors_path():
+    torch = pytest.importorskip("torch")
+    X = workloads.gaussian_unit(4000, 64, 51)
+    Q = workloads.gaussian_unit(200, 64, 52)
+    g = pf.Index(torch.from_numpy(X).cuda(), 0, seed=13, L=30)
+    o = oracle.OracleIndex(X, 0, seed=13, L=30)
+    _assert_index_equal(g, o)
+    r = g.search(torch.from_numpy(Q).cuda(), 10, 0.9)
+    torch.cuda.synchronize()
+    gr = pf.SearchResult(r.ids.cpu().numpy(), r.ips.cpu().numpy(), r.stats.cpu().numpy())
+    _assert_search_equal(gr, o.search(Q, 10, 0.9), "device tensors")
+
+
+def test_errors():
+    X = workloads.gaussian_unit(100, 8, 61)
+    with pytest.raises(pf.PfError) as e:
+        pf.Index(X, 1000)
+    assert e.value.code == pf.PF_EBUDGET
+    bad = X.copy()
+    bad[7] = np.nan
+    with pytest.raises(pf.PfError) as e:
+        pf.Index(bad, 0, L=4)
+    assert e.value.code == pf.PF_EINVAL
+    g = pf.Index(X, 0, L=4)
+    for k, rec in [(0, 0.9), (101, 0.9), (10, 0.0), (10, 1.5)]:
+        with pytest.raises(pf.PfError) as e:
+            g.search(X[:3], k, rec)
+        assert e.value.code == pf.PF_EINVAL
+    q = X[:3].copy()
+    q[1] = 0
+    with pytest.raises(pf.PfError) as e:
+        g.search(q, 5, 0.9)
+    assert e.value.code == pf.PF_EINVAL
+    # the index still answers after the errors
+    r = g.search(X[:3], 5, 0.9)
+    assert np.all(r.ids[:, 0] == np.arange(3))
