@@ -38,8 +38,9 @@ extern "C" {
 #define PF_DEVICE 1
 
 /* stopping rules, see pf_search_opts.rule */
-#define PF_RULE_EXACT 0
-#define PF_RULE_ALG1 1
+#define PF_RULE_FILTER 0 /* Lemma 1's bound with the sketch filter's misses (default)    */
+#define PF_RULE_EXACT 1  /* Lemma 1's bound (1 - p^i)^L <= delta, filter not accounted   */
+#define PF_RULE_ALG1 2   /* Algorithm 1's printed test L >= ln(1/delta) / p^i            */
 
 /* hashing arithmetic, see pf_build_opts.hash_mode */
 #define PF_HASH_BF16X3 0 /* BF16 MFMA (three split products, FP32 accumulate), bits whose
@@ -69,12 +70,13 @@ typedef struct {
     int32_t L_override; /* > 0: use exactly this many tables, ignore the budget rule  */
 } pf_build_opts;
 
+/* All-zero options are the defaults. */
 typedef struct {
-    double eps;     /* filter slack: tau = (1 + eps) * 64 * theta_k / pi; default 0  */
-    int32_t B;      /* segment size of every array access; 0 selects 12              */
-    int32_t rule;   /* PF_RULE_EXACT (default) or PF_RULE_ALG1                       */
-    int32_t filter; /* 1 (default) sketch filter on, 0 off (every candidate re-ranked) */
-    int32_t timing; /* 1: record per-kernel durations of this call (pf_last_timing)  */
+    double eps;        /* filter slack: tau = (1 + eps) * 64 * theta_k / pi; default 0 */
+    int32_t B;         /* segment size of every array access; 0 selects 12             */
+    int32_t rule;      /* PF_RULE_FILTER (default), PF_RULE_EXACT or PF_RULE_ALG1       */
+    int32_t no_filter; /* 1: sketch filter off (every retrieved candidate re-ranked)   */
+    int32_t timing;    /* 1: record per-kernel durations of this call (pf_last_timing) */
 } pf_search_opts;
 
 typedef struct {
@@ -122,8 +124,10 @@ int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t memory_bu
  * entries (Sec. 4.2, App. C); candidates pass when the Hamming distance of their
  * sketch is at most the threshold of the round (Sec. 4.2, Sec. 5.1); survivors not
  * yet seen are re-ranked by exact FP32 inner product into the top-k; after all tables
- * the stopping bound of Lemma 1 is tested in FP64; at prefix length 0 the query is a
- * linear scan.  `queries` m x d; out_ids m x k (int32, best first: inner product
+ * the stopping bound of Lemma 1 is tested in FP64 -- by default extended by the
+ * probability that the filter rejects a true neighbour, so that each returned point
+ * is a true k-NN with probability at least 1 - delta with the filter on; at prefix
+ * length 0 the query is a linear scan.  `queries` m x d; out_ids m x k (int32, best first: inner product
  * descending, position ascending); out_ips m x k FP32 (nullable); stats m (nullable).
  * Errors: PF_EINVAL (k < 1, k > n, k > PF_MAX_K, recall outside (0, 1], bad row, d
  * mismatch), PF_ENOMEM, PF_EDEVICE.  With PF_HOST the call synchronises. */

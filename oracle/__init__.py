@@ -17,8 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "puffinn_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-RULE_EXACT = 0
-RULE_ALG1 = 1
+RULE_FILTER = 0
+RULE_EXACT = 1
+RULE_ALG1 = 2
 DEFAULT_K = 24
 DEFAULT_M = 32
 DEFAULT_B = 12
@@ -75,7 +76,9 @@ def lib():
         L.oracle_tau.restype = _D
         L.oracle_tau.argtypes = [ctypes.c_float, _D]
         L.oracle_stop.restype = ctypes.c_int
-        L.oracle_stop.argtypes = [ctypes.c_float, _I32, _I32, _D, _I32, ctypes.POINTER(_D)]
+        L.oracle_stop.argtypes = [ctypes.c_float, _I32, _I32, _I32, _D, _I32, _I32, ctypes.POINTER(_D)]
+        L.oracle_binom_cdf64.restype = _D
+        L.oracle_binom_cdf64.argtypes = [_D, _I32]
         L.oracle_search.restype = ctypes.c_int
         L.oracle_search.argtypes = [
             _P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32,
@@ -171,10 +174,15 @@ def tau(ip_k: float, eps: float = 0.0) -> float:
     return float(lib().oracle_tau(ip_k, eps))
 
 
-def stop(ip_k: float, i: int, L: int, delta: float, rule: int = RULE_EXACT):
+def stop(ip_k: float, i: int, L: int, delta: float, rule: int = RULE_EXACT, M: int = DEFAULT_M,
+         tau_int: int = 64):
     m = _D()
-    r = lib().oracle_stop(ip_k, i, L, delta, rule, ctypes.byref(m))
+    r = lib().oracle_stop(ip_k, i, L, M, delta, rule, tau_int, ctypes.byref(m))
     return bool(r), float(m.value)
+
+
+def binom_cdf64(t: float, T: int) -> float:
+    return float(lib().oracle_binom_cdf64(t, T))
 
 
 def bruteforce(points_n: np.ndarray, queries_n: np.ndarray, k: int):
@@ -227,7 +235,7 @@ class OracleIndex:
         self.tsk = table_sketches(self.tidx, self.sketches)
 
     def search(self, queries: np.ndarray, k: int, recall: float, eps: float = 0.0,
-               B: int = DEFAULT_B, rule: int = RULE_EXACT, filter_on: bool = True,
+               B: int = DEFAULT_B, rule: int = RULE_FILTER, filter_on: bool = True,
                trace: bool = False) -> SearchResult:
         q = np.ascontiguousarray(queries, dtype=np.float32)
         m = q.shape[0]

@@ -33,8 +33,9 @@
 #define OR_EINVAL (-1)
 #define OR_ENOMEM (-3)
 
-#define OR_RULE_EXACT 0 /* L * log1p(-p^i) <= ln(delta): the bound in the proof of Lemma 1 */
-#define OR_RULE_ALG1 1  /* L >= ln(1/delta) / p^i: the test printed in Algorithm 1 */
+#define OR_RULE_FILTER 0 /* the bound of Lemma 1 with the sketch filter's misses included */
+#define OR_RULE_EXACT 1  /* L * log1p(-p^i) <= ln(delta): the bound in the proof of Lemma 1 */
+#define OR_RULE_ALG1 2   /* L >= ln(1/delta) / p^i: the test printed in Algorithm 1 */
 
 static const double OR_PI = 3.14159265358979323846264338327950288;
 
@@ -126,27 +127,50 @@ static double dot64(const float *a, const float *x, int32_t d) {
     return s;
 }
 
+/* projections of x onto the rows r0 .. r0+cnt-1 (cnt <= 4) of hp */
+static void dot64_rows(const float *hp, int64_t r0, int cnt, const float *x, int32_t d, double *out) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const float *a0 = hp + r0 * d;
+    const float *a1 = cnt > 1 ? a0 + d : a0, *a2 = cnt > 2 ? a0 + 2 * d : a0, *a3 = cnt > 3 ? a0 + 3 * d : a0;
+    for (int32_t c = 0; c < d; ++c) {
+        const double xc = (double)x[c];
+        s0 += (double)a0[c] * xc;
+        s1 += (double)a1[c] * xc;
+        s2 += (double)a2[c] * xc;
+        s3 += (double)a3[c] * xc;
+    }
+    out[0] = s0, out[1] = s1, out[2] = s2, out[3] = s3;
+}
+
 void oracle_hash(const float *x, int64_t n, int32_t d, const float *hp, int32_t L, int32_t K,
                  int32_t M, uint32_t *codes, uint64_t *sketches) {
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t i = 0; i < n; ++i) {
-        const float *xi = x + i * (int64_t)d;
-        for (int32_t j = 0; j < L; ++j) {
-            uint32_t code = 0;
-            for (int32_t s = 0; s < K; ++s) {
-                double p = dot64(hp + ((int64_t)j * K + s) * d, xi, d);
-                if (p >= 0.0) code |= 1u << (K - 1 - s);
+    const int64_t rows = (int64_t)L * K + 64 * (int64_t)M;
+#pragma omp parallel
+    {
+        uint8_t *bit = (uint8_t *)malloc((size_t)rows);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            const float *xi = x + i * (int64_t)d;
+            for (int64_t r = 0; r < rows; r += 4) {
+                double p[4];
+                const int cnt = rows - r < 4 ? (int)(rows - r) : 4;
+                dot64_rows(hp, r, cnt, xi, d, p);
+                for (int t = 0; t < cnt; ++t) bit[r + t] = p[t] >= 0.0;
             }
-            codes[(int64_t)j * n + i] = code;
-        }
-        for (int32_t m = 0; m < M; ++m) {
-            uint64_t sk = 0;
-            for (int32_t b = 0; b < 64; ++b) {
-                double p = dot64(hp + ((int64_t)L * K + 64 * m + b) * d, xi, d);
-                if (p >= 0.0) sk |= 1ull << b;
+            for (int32_t j = 0; j < L; ++j) {
+                uint32_t code = 0;
+                for (int32_t s = 0; s < K; ++s)
+                    if (bit[(int64_t)j * K + s]) code |= 1u << (K - 1 - s);
+                codes[(int64_t)j * n + i] = code;
             }
-            sketches[(int64_t)m * n + i] = sk;
+            for (int32_t m = 0; m < M; ++m) {
+                uint64_t sk = 0;
+                for (int32_t b = 0; b < 64; ++b)
+                    if (bit[(int64_t)L * K + 64 * m + b]) sk |= 1ull << b;
+                sketches[(int64_t)m * n + i] = sk;
+            }
         }
+        free(bit);
     }
 }
 
@@ -267,14 +291,45 @@ double oracle_tau(float ip_k, double eps) {
     return (1.0 + eps) * 64.0 * acos(clamp1((double)ip_k)) / OR_PI;
 }
 
+/* Probability that two points at angle theta = t * pi pass the sketch filter, i.e. that
+ * the Hamming distance of their 64-bit sketches (a Binomial(64, t) variable, each
+ * random-hyperplane bit differing with probability t) is at most T:
+ *   sum_{h=0..T} C(64,h) t^h (1-t)^(64-h),
+ * with C(64,h) built by the recurrence C(64,h+1) = C(64,h) (64-h)/(h+1) in FP64. */
+double oracle_binom_cdf64(double t, int32_t T) {
+    if (T < 0) return 0.0;
+    if (T >= 64 || t <= 0.0) return 1.0;
+    if (t >= 1.0) return 0.0;
+    const double lt = log(t), l1t = log1p(-t);
+    double c = 1.0, s = 0.0;
+    for (int32_t h = 0; h <= T; ++h) {
+        s += c * exp((double)h * lt + (double)(64 - h) * l1t);
+        c = c * (double)(64 - h) / (double)(h + 1);
+    }
+    return s < 1.0 ? s : 1.0;
+}
+
 /* Stopping test after all L repetitions of level i have been inspected (Sec. 4.1: "the
  * termination criterion is checked after all repetitions are inspected").
  * OR_RULE_EXACT stops when the failure bound of Lemma 1's proof, (1 - p^i)^L, is at
  * most delta, evaluated as L * log1p(-p^i) <= ln(delta) with ln p = log1p(-theta/pi)
  * and p^i = exp(i ln p).  OR_RULE_ALG1 stops when L >= ln(1/delta) / p^i, the test
  * written in Algorithm 1 (it implies the exact bound, so it never stops earlier).
- * *margin receives the signed distance of the two sides (term - threshold). */
-int oracle_stop(float ip_k, int32_t i, int32_t L, double delta, int32_t rule, double *margin) {
+ * OR_RULE_FILTER extends the bound to the sketch filter (Sec. 4.2), which the proof
+ * of Lemma 1 does not cover: a true neighbour x (angle <= theta_k) is missed only if,
+ * for every sketch s, either x's sketch s fails the filter or none of the g_s tables
+ * reading sketch s (tables j with j mod M = s) holds x in its window at level i.  Table
+ * windows and sketches use independent hyperplanes; the threshold never grows from
+ * level to level, so x passes sketch s with probability at least
+ * q = P[Binomial(64, theta_k/pi) <= T], T the integer threshold of level i.  Hence the
+ * failure probability is at most prod_s (1 - q + q (1 - p^i)^{g_s}).  Each factor is
+ * evaluated without cancellation: with a = g_s log1p(-p^i) and x = q expm1(a), the log
+ * of the factor is log1p(x) when x > -1/2, else log((1 - q) + q exp(a)) (two
+ * non-negative terms).  The test is sum_s log(factor_s) <= ln(delta).  With q = 1 (no
+ * filtering) this is the exact rule.  *margin receives the signed distance of the two
+ * sides (term - threshold). */
+int oracle_stop(float ip_k, int32_t i, int32_t L, int32_t M, double delta, int32_t rule,
+                int32_t tau_int, double *margin) {
     double theta = acos(clamp1((double)ip_k));
     double lnp = log1p(-theta / OR_PI);
     double pi_ = exp((double)i * lnp);
@@ -284,6 +339,19 @@ int oracle_stop(float ip_k, int32_t i, int32_t L, double delta, int32_t rule, do
         double lhs = (double)L * pi_;
         if (margin) *margin = -lnd - lhs;
         return lhs >= -lnd;
+    }
+    if (rule == OR_RULE_FILTER) {
+        const double q = oracle_binom_cdf64(theta / OR_PI, tau_int);
+        const double l1p = log1p(-pi_);
+        double term = 0.0;
+        for (int32_t s = 0; s < M && s < L; ++s) {
+            const int32_t g = L / M + (s < L % M ? 1 : 0);
+            const double a = (double)g * l1p;
+            const double x = q * expm1(a);
+            term += (x > -0.5) ? log1p(x) : log((1.0 - q) + q * exp(a));
+        }
+        if (margin) *margin = term - lnd;
+        return term <= lnd;
     }
     double term = (double)L * log1p(-pi_);
     if (margin) *margin = term - lnd;
@@ -388,10 +456,12 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
     for (int32_t i = K; i >= 1; --i) {
         /* threshold fixed for the level, from the top-k before it */
         double tau = 64.0;
+        int32_t tau_int = 64;
         if (filter_on && top->len == k) {
             tau = oracle_tau(top->v[k - 1].ip, eps);
             double fr = tau - floor(tau);
             if (fr < 1e-9 || fr > 1.0 - 1e-9) *boundary = 1;
+            tau_int = tau >= 64.0 ? 64 : (tau < -1.0 ? -1 : (int32_t)floor(tau));
         }
         fresh->len = 0;
         for (int32_t j = 0; j < L; ++j) {
@@ -451,7 +521,7 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
         if (top->len > k) top->len = k;
         if (top->len == k) {
             double margin;
-            int stop = oracle_stop(top->v[k - 1].ip, i, L, delta, rule, &margin);
+            int stop = oracle_stop(top->v[k - 1].ip, i, L, ix->M, delta, rule, tau_int, &margin);
             if (fabs(margin) < 1e-9 * (1.0 + fabs(log(delta)))) *boundary = 1;
             if (stop) {
                 *stop_level = i;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libpfhip.so")
 
 PF_OK, PF_EINVAL, PF_EBUDGET, PF_ENOMEM, PF_EDEVICE, PF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PF_HOST, PF_DEVICE = 0, 1
-PF_RULE_EXACT, PF_RULE_ALG1 = 0, 1
+PF_RULE_FILTER, PF_RULE_EXACT, PF_RULE_ALG1 = 0, 1, 2
 PF_HASH_BF16X3, PF_HASH_FP64 = 0, 1
 (PF_EXPORT_POINTS, PF_EXPORT_HYPERPLANES, PF_EXPORT_CODES, PF_EXPORT_IDX,
  PF_EXPORT_SKETCHES, PF_EXPORT_OFFSETS) = range(6)
@@ -42,7 +42,7 @@ class pf_build_opts(ctypes.Structure):
 
 class pf_search_opts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("B", ctypes.c_int32), ("rule", ctypes.c_int32),
-                ("filter", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("no_filter", ctypes.c_int32), ("timing", ctypes.c_int32)]
 
 
 class pf_query_stats(ctypes.Structure):
@@ -224,14 +224,14 @@ class Index:
         return t
 
     def search(self, queries, k: int, recall: float, eps: float = 0.0, B: int = 12,
-               rule: int = PF_RULE_EXACT, filter: bool = True, timing: bool = False,
+               rule: int = PF_RULE_FILTER, filter: bool = True, timing: bool = False,
                want_ips: bool = True, want_stats: bool = True) -> SearchResult:
         q = _f32(queries)
         m = q.shape[0]
         ids = _empty_like_input(q, (m, k), np.int32, _torch_dtype("int32"))
         ips = _empty_like_input(q, (m, k), np.float32, _torch_dtype("float32")) if want_ips else None
         st = _empty_like_input(q, (m, 4), np.int64, _torch_dtype("int64")) if want_stats else None
-        opts = pf_search_opts(eps, B, rule, 1 if filter else 0, 1 if timing else 0)
+        opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0)
         pq, mem, stream = _buf(q)
         _check(lib().pf_search_ex(self._h, pq, m, k, recall, ctypes.byref(opts), _buf(ids)[0],
                                   _buf(ips)[0], _buf(st)[0], mem, stream))

@@ -175,6 +175,41 @@ __device__ __forceinline__ float dot_canon(const float *__restrict__ xrow, const
     return s;
 }
 
+// P[Binomial(64, t) <= T]: probability that a point at angle t*pi passes a sketch
+// filter of integer threshold T (each of the 64 random-hyperplane bits differs with
+// probability t); C(64,h) by the recurrence C(64,h+1) = C(64,h) (64-h)/(h+1).
+__device__ double binom_cdf64(double t, int T) {
+    if (T < 0) return 0.0;
+    if (T >= 64 || t <= 0.0) return 1.0;
+    if (t >= 1.0) return 0.0;
+    const double lt = log(t), l1t = log1p(-t);
+    double c = 1.0, s = 0.0;
+    for (int h = 0; h <= T; ++h) {
+        s = s + c * exp((double)h * lt + (double)(64 - h) * l1t);
+        c = c * (double)(64 - h) / (double)(h + 1);
+    }
+    return s < 1.0 ? s : 1.0;
+}
+
+// Failure bound of Lemma 1 with the sketch filter (log of an upper bound on the
+// probability of missing a true neighbour after level i): a true neighbour at angle
+// <= theta_k is missed only if, for each sketch s, its sketch fails the filter (pass
+// probability >= q, the threshold only shrinks over levels) or none of the g_s tables
+// reading sketch s (j mod M = s) holds it in its window (probability (1 - p^i)^{g_s}).
+// Each factor 1 - q + q (1 - p^i)^{g_s} is evaluated without cancellation.
+__device__ double filter_bound(double theta, double pw, int tau_int, int L, int M) {
+    const double q = binom_cdf64(theta / kPi, tau_int);
+    const double l1p = log1p(-pw);
+    double term = 0.0;
+    for (int s = 0; s < M && s < L; ++s) {
+        const int g = L / M + (s < L % M ? 1 : 0);
+        const double a = (double)g * l1p;
+        const double x = q * expm1(a);
+        term = term + ((x > -0.5) ? log1p(x) : log((1.0 - q) + q * exp(a)));
+    }
+    return term;
+}
+
 // inclusive scan of a[0..N) in LDS by all NT threads
 __device__ void block_scan_incl(uint32_t *a, int N, uint32_t *wsum) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -461,8 +496,10 @@ __global__ __launch_bounds__(NT) void k_search(SearchK p) {
                     const double pw = exp((double)i * lnp);
                     if (p.rule == PF_RULE_ALG1)
                         stop = ((double)L * pw >= -lndelta);
-                    else
+                    else if (p.rule == PF_RULE_EXACT)
                         stop = ((double)L * log1p(-pw) <= lndelta);
+                    else
+                        stop = filter_bound(theta, pw, sh.tau_int, L, p.M) <= lndelta;
                     if (p.filter) {
                         const double t = (1.0 + p.eps) * 64.0 * theta / kPi;
                         const double ft = floor(t);

@@ -297,13 +297,13 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     PF_CHECK(queries && out_ids && m >= 0, PF_EINVAL, "search: bad arguments");
     PF_CHECK(mem == PF_HOST || mem == PF_DEVICE, PF_EINVAL, "search: bad mem");
     PF_CHECK(kmax >= 1 && kmax <= PF_MAX_K && kmax <= ix->n, PF_EINVAL, "search: k must be in [1, min(n, 256)]");
-    pf_search_opts o{0.0, 12, PF_RULE_EXACT, 1, 0};
-    if (opts) {
-        o = *opts;
-        if (o.B == 0) o.B = 12;
-    }
+    pf_search_opts o{};
+    if (opts) o = *opts;
+    if (o.B == 0) o.B = 12;
     PF_CHECK(o.B >= 1, PF_EINVAL, "search: B must be >= 1");
-    PF_CHECK(o.rule == PF_RULE_EXACT || o.rule == PF_RULE_ALG1, PF_EINVAL, "search: bad rule");
+    PF_CHECK(o.rule == PF_RULE_FILTER || o.rule == PF_RULE_EXACT || o.rule == PF_RULE_ALG1, PF_EINVAL,
+             "search: bad rule");
+    PF_CHECK(std::isfinite(o.eps) && o.eps > -1.0, PF_EINVAL, "search: eps must be finite and > -1");
     if (!recalls)
         PF_CHECK(recall_const > 0.0 && recall_const <= 1.0, PF_EINVAL, "search: recall must be in (0, 1]");
     if (m == 0) return;
@@ -367,7 +367,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     a.eps = o.eps;
     a.B = o.B;
     a.rule = o.rule;
-    a.filter = o.filter ? 1 : 0;
+    a.filter = o.no_filter ? 0 : 1;
     a.out_ids = oid;
     a.out_ips = oip;
     a.stats = ost;

@@ -1,0 +1,85 @@
+"""The C-ABI boundary, checked without a GPU: the library loads, exports every function
+that include/pfhip.h declares, and the binding's constants and struct layouts match the
+header (compiled with gcc).  No compute call is made here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1906_12211_amd as pf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfhip.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_]+)\s*\(", src)))
+
+
+def _defines():
+    out = {}
+    for m in re.finditer(r"#define\s+(PF_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", open(HEADER).read()):
+        out[m.group(1)] = int(m.group(2))
+    return out
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pf.lib()
+    names = _declared_functions()
+    assert len(names) >= 10
+    nm = subprocess.run(["nm", "-D", "--defined-only", pf.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (pf_\w+)", nm))
+    assert set(names) == exported, (set(names) ^ exported)
+    for n in names:
+        assert hasattr(lib, n)
+    assert sorted(pf.EXPORTED) == names
+    assert pf.pf_version().startswith("pfhip")
+
+
+def test_binding_constants_match_header():
+    d = _defines()
+    for name, val in d.items():
+        if hasattr(pf, name):
+            assert getattr(pf, name) == val, name
+    for name in ["PF_OK", "PF_EINVAL", "PF_EBUDGET", "PF_HOST", "PF_DEVICE", "PF_HASH_FP64",
+                 "PF_EXPORT_OFFSETS", "PF_MAX_TABLES", "PF_MAX_K"]:
+        assert getattr(pf, name) == d[name]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    structs = {"pf_build_opts": pf.pf_build_opts, "pf_search_opts": pf.pf_search_opts,
+               "pf_query_stats": pf.pf_query_stats, "pf_info": pf.pf_info, "pf_timing": pf.pf_timing}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for s, cls in structs.items():
+        lines.append(f'printf("{s} size %zu\\n", sizeof({s}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{s}.{fname} %zu\\n", offsetof({s}, {fname}));')
+    lines.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(c)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(l.rsplit(" ", 1) for l in out if l)
+    for s, cls in structs.items():
+        assert int(got[f"{s} size"]) == ctypes.sizeof(cls), s
+        for fname, _ in cls._fields_:
+            assert int(got[f"{s}.{fname}"]) == getattr(cls, fname).offset, f"{s}.{fname}"
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(pf, "_lib", None)
+    monkeypatch.setattr(pf, "LIB_PATH", "/nonexistent/libpfhip.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        pf.lib()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

@@ -232,7 +232,7 @@ def test_ip32_short_vectors_are_sequential_sums(oracle_mod):
 
 
 # ----------------------------------------------------------------------- stopping rule
-@pytest.mark.parametrize("rule", [0, 1])
+@pytest.mark.parametrize("rule", ["exact", "alg1"])
 def test_stop_rule_closed_form(oracle_mod, rule):
     """Lemma 1: failure after L repetitions at level i is at most (1 - p^i)^L.
     Exact rule: stop iff (1 - p^i)^L <= delta, whose solution in i is
@@ -243,14 +243,15 @@ def test_stop_rule_closed_form(oracle_mod, rule):
         p = 1 - math.acos(ipf) / math.pi
         for L in (2, 10, 69, 100, 108, 321):
             for delta in (0.5, 0.1, 0.01, 0.001):
-                if rule == 0:
+                if rule == "exact":
                     istar = math.log(1 - delta ** (1.0 / L)) / math.log(p)
                 else:
                     istar = math.log(math.log(1 / delta) / L) / math.log(p)
                 for i in range(1, 25):
                     if abs(i - istar) < 1e-6:
                         continue
-                    got, _ = oracle_mod.stop(ipf, i, L, delta, rule)
+                    r = oracle_mod.RULE_EXACT if rule == "exact" else oracle_mod.RULE_ALG1
+                    got, _ = oracle_mod.stop(ipf, i, L, delta, r)
                     assert got == (i <= istar), (ipk, L, delta, i, istar)
 
 
@@ -260,8 +261,8 @@ def test_exact_rule_never_later_than_alg1(oracle_mod):
         for L in (1, 3, 10, 100):
             for delta in (0.5, 0.2, 0.05):
                 for i in range(1, 25):
-                    a1, _ = oracle_mod.stop(float(ipk), i, L, delta, 1)
-                    ex, _ = oracle_mod.stop(float(ipk), i, L, delta, 0)
+                    a1, _ = oracle_mod.stop(float(ipk), i, L, delta, oracle_mod.RULE_ALG1)
+                    ex, _ = oracle_mod.stop(float(ipk), i, L, delta, oracle_mod.RULE_EXACT)
                     assert ex or not a1
 
 
@@ -413,3 +414,93 @@ def test_paper_synthetic_known_answer(oracle_mod):
     ix = oracle_mod.OracleIndex(X, budget=0, L=40, seed=3)
     r = ix.search(Q, 1, 0.9)
     assert np.mean(r.ids[:, 0] == len(X) - 1) >= 0.9 - 4 * math.sqrt(0.09 / 40)
+
+
+# ----------------------------------------------------------------------- filter-aware bound
+def test_binom_cdf_matches_scipy(oracle_mod):
+    """Pass probability of the sketch filter: the Binomial(64, t) CDF (library routine)."""
+    for t in (1e-3, 0.05, 0.2, 0.3333, 0.366, 0.5, 0.77, 0.999):
+        for T in (-1, 0, 1, 10, 21, 23, 32, 50, 63, 64):
+            assert abs(oracle_mod.binom_cdf64(t, T) - stats.binom.cdf(T, 64, t)) < 1e-12, (t, T)
+    assert oracle_mod.binom_cdf64(0.0, 0) == 1.0
+    assert oracle_mod.binom_cdf64(1.0, 63) == 0.0
+
+
+def test_filter_rule_without_filtering_is_the_exact_rule(oracle_mod):
+    """Special case: threshold 64 passes everything (q = 1), and the bound collapses to
+    (1 - p^i)^L whatever the sketch grouping."""
+    for ipk in (0.2, 0.41, 0.8, 0.95):
+        for L, M in ((108, 32), (10, 32), (321, 32), (7, 3)):
+            for delta in (0.5, 0.1, 0.01):
+                for i in range(1, 25):
+                    a, ma = oracle_mod.stop(ipk, i, L, delta, oracle_mod.RULE_EXACT)
+                    b, mb = oracle_mod.stop(ipk, i, L, delta, oracle_mod.RULE_FILTER, M=M, tau_int=64)
+                    assert a == b and abs(ma - mb) < 1e-9 * (1 + abs(ma))
+
+
+def test_filter_rule_closed_form_independent_sketches(oracle_mod):
+    """With one sketch per table (M >= L) the bound is (1 - q p^i)^L <= delta, solved in
+    closed form as i <= ln((1 - delta^(1/L)) / q) / ln p, q from scipy's binomial CDF."""
+    for ipk in (0.3, 0.41, 0.6, 0.9):
+        ipf = float(np.float32(ipk))
+        theta = math.acos(ipf)
+        p = 1 - theta / math.pi
+        for T in (10, 20, 23, 30, 40):
+            q = stats.binom.cdf(T, 64, theta / math.pi)
+            for L in (5, 20, 60):
+                for delta in (0.5, 0.1, 0.01):
+                    arg = (1 - delta ** (1.0 / L)) / q
+                    istar = math.log(arg) / math.log(p) if arg < 1 else -1
+                    for i in range(1, 25):
+                        if abs(i - istar) < 1e-6:
+                            continue
+                        got, _ = oracle_mod.stop(ipf, i, L, delta, oracle_mod.RULE_FILTER, M=64, tau_int=T)
+                        assert got == (i <= istar), (ipk, T, L, delta, i, istar)
+
+
+def test_filter_rule_shared_sketches_stop_no_earlier(oracle_mod):
+    """Invariant: tables that share a sketch fail the filter together, so grouping L
+    tables onto M < L sketches can only weaken the bound (stop at the same level or
+    later than with independent sketches), and always stops later than ignoring the
+    filter when q < 1."""
+    for ipk in (0.3, 0.41, 0.7):
+        for T in (15, 23, 35):
+            for L, M in ((108, 32), (40, 8), (10, 3)):
+                for delta in (0.1, 0.01):
+                    for i in range(1, 25):
+                        grp, _ = oracle_mod.stop(ipk, i, L, delta, oracle_mod.RULE_FILTER, M=M, tau_int=T)
+                        ind, _ = oracle_mod.stop(ipk, i, L, delta, oracle_mod.RULE_FILTER, M=L, tau_int=T)
+                        exact, _ = oracle_mod.stop(ipk, i, L, delta, oracle_mod.RULE_EXACT)
+                        assert (not grp) or ind
+                        assert (not ind) or exact
+
+
+def test_lemma1_guarantee_with_filter_statistical(oracle_mod):
+    """Lemma 1 with the sketch filter on and the filter-aware bound: each of the k true
+    neighbours is returned with probability at least 1 - delta (300 independent index
+    seeds; neighbours at 60-70 degrees, so the filter often rejects a true neighbour it
+    sees; four sketches shared by twenty tables).  Negative control: the bound without
+    the filter's misses (the paper's rule) falls visibly short on the same instance."""
+    X = workloads.gaussian_unit(400, 32, 71)
+    Q = workloads.gaussian_unit(4, 32, 72)
+    k, recall = 3, 0.8
+    qn = oracle_mod.normalize(Q)
+    true_ids, _ = oracle_mod.bruteforce(oracle_mod.normalize(X), qn, k)
+    seeds = 300
+    hits = np.zeros((len(Q), k))
+    hits_paper = np.zeros((len(Q), k))
+    levels = []
+    for s in range(seeds):
+        ix = oracle_mod.OracleIndex(X, budget=0, L=20, seed=5000 + s, M=4)
+        r = ix.search(Q, k, recall, rule=oracle_mod.RULE_FILTER, filter_on=True)
+        rp = ix.search(Q, k, recall, rule=oracle_mod.RULE_EXACT, filter_on=True)
+        levels.append(r.stop_level)
+        for t in range(len(Q)):
+            hits[t] += np.isin(true_ids[t], r.ids[t])
+            hits_paper[t] += np.isin(true_ids[t], rp.ids[t])
+    rate = hits / seeds
+    delta = 1 - recall
+    sd = math.sqrt(delta * (1 - delta) / seeds)
+    assert np.all(rate >= 1 - delta - 4 * sd), rate
+    assert np.all(np.concatenate(levels) > 0)
+    assert (hits_paper / seeds).min() < rate.min() - 0.05
