@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--recall-sample", type=int, default=1000)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -117,6 +119,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe_mib:
+        # a plain device-to-device copy of known size: what FETCH_SIZE / WRITE_SIZE read
+        # for it calibrates the counters of the search kernel
+        x = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 4}))
+        return
 
     log("generating workload")
     c = workloads.config(2, scale=args.scale)

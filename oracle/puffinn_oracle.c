@@ -370,15 +370,15 @@ int oracle_stop(float ip_k, int32_t i, int32_t L, int32_t M, double delta, int32
  *    whole segments of B entries to the left while the entry just left of it shares the
  *    query's i-bit prefix, and to the right likewise, clipped to [0, n).  B = 1 gives
  *    exactly the sets Pi_{i,j}(q) of Sec. 3.1;
- *  - de-duplication (Sec. 4.2, "Computing distances") is against every point already
- *    re-ranked, so a point is re-ranked at most once per query; a point filtered out in
- *    one repetition may still pass in another;
+ *  - every entry that passes the filter has its distance computed and enters the
+ *    accumulator (Sec. 4.1), which de-duplicates (Sec. 4.2, "Computing distances"): the
+ *    top-k holds distinct points, a point seen in several repetitions counts once;
  *  - the top-k is ordered by (inner product descending, position ascending);
  *  - level 0 is a linear scan (Lemma 1: at i = 0 the query degrades to a linear scan):
- *    every point not yet re-ranked is re-ranked, unfiltered, and the exact top-k is
- *    returned.
+ *    every point is re-ranked, unfiltered, and the exact top-k is returned.
  * Counters: c_scan = entries taken from the arrays, c_pass = entries that passed the
- * filter (with multiplicity), c_rerank = distinct points re-ranked.
+ * filter (with multiplicity), c_rerank = distance computations (c_pass, plus n when
+ * the linear scan runs).
  * ---------------------------------------------------------------------------------- */
 typedef struct {
     float ip;
@@ -439,13 +439,26 @@ typedef struct {
 
 /* trace (optional, one query): per level i (row i of K+1) and table j:
  * [0] lo_i [1] hi_i [2] c_lo after level i [3] c_hi after level i */
+/* top <- best k distinct points of top u fresh (the accumulator's flush): sort by
+ * (ip desc, id asc); copies of one point carry the same inner product, so they are
+ * adjacent and all but the first are dropped. */
+static int accumulate(or_list *top, const or_list *fresh, int32_t k) {
+    for (int64_t t = 0; t < fresh->len; ++t)
+        if (list_push(top, fresh->v[t])) return OR_ENOMEM;
+    qsort(top->v, (size_t)top->len, sizeof(or_cand), cmp_cand);
+    int64_t w = 0;
+    for (int64_t t = 0; t < top->len && w < k; ++t)
+        if (w == 0 || top->v[t].id != top->v[w - 1].id) top->v[w++] = top->v[t];
+    top->len = w;
+    return OR_OK;
+}
+
 static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, const uint64_t *qsk,
                     int32_t k, double delta, double eps, int32_t B, int32_t rule, int32_t filter_on,
-                    uint8_t *seen, int64_t *clo, int64_t *chi, or_list *top, or_list *fresh,
+                    int64_t *clo, int64_t *chi, or_list *top, or_list *fresh,
                     int32_t *stop_level, int64_t *cnt, int32_t *boundary, int64_t *trace) {
     const int64_t n = ix->n;
     const int32_t L = ix->L, K = ix->K, d = ix->d;
-    memset(seen, 0, (size_t)n);
     top->len = 0;
     cnt[0] = cnt[1] = cnt[2] = 0;
     *boundary = 0;
@@ -504,21 +517,15 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
                     int h = __builtin_popcountll(ts[e] ^ qs);
                     if ((double)h > tau) continue;
                     cnt[1]++;
-                    uint32_t x = ti[e];
-                    if (seen[x]) continue;
-                    seen[x] = 1;
                     cnt[2]++;
+                    uint32_t x = ti[e];
                     const float *px = ix->points + (int64_t)x * d;
                     or_cand c = {oracle_ip32(px, q, d), oracle_ip64(px, q, d), (int32_t)x};
                     if (list_push(fresh, c)) return OR_ENOMEM;
                 }
             }
         }
-        /* top <- best k of top u fresh */
-        for (int64_t t = 0; t < fresh->len; ++t)
-            if (list_push(top, fresh->v[t])) return OR_ENOMEM;
-        qsort(top->v, (size_t)top->len, sizeof(or_cand), cmp_cand);
-        if (top->len > k) top->len = k;
+        if (accumulate(top, fresh, k)) return OR_ENOMEM;
         if (top->len == k) {
             double margin;
             int stop = oracle_stop(top->v[k - 1].ip, i, L, ix->M, delta, rule, tau_int, &margin);
@@ -529,17 +536,15 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
             }
         }
     }
-    /* level 0: linear scan over everything not yet re-ranked */
+    /* level 0: linear scan, every point re-ranked */
+    fresh->len = 0;
     for (int64_t x = 0; x < n; ++x) {
-        if (seen[x]) continue;
-        seen[x] = 1;
         cnt[2]++;
         const float *px = ix->points + x * d;
         or_cand c = {oracle_ip32(px, q, d), oracle_ip64(px, q, d), (int32_t)x};
-        if (list_push(top, c)) return OR_ENOMEM;
+        if (list_push(fresh, c)) return OR_ENOMEM;
     }
-    qsort(top->v, (size_t)top->len, sizeof(or_cand), cmp_cand);
-    if (top->len > k) top->len = k;
+    if (accumulate(top, fresh, k)) return OR_ENOMEM;
     *stop_level = 0;
     return OR_OK;
 }
@@ -580,13 +585,12 @@ int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, co
     int err = OR_OK;
 #pragma omp parallel
     {
-        uint8_t *seen = (uint8_t *)malloc((size_t)n);
         int64_t *clo = (int64_t *)malloc((size_t)L * sizeof(int64_t));
         int64_t *chi = (int64_t *)malloc((size_t)L * sizeof(int64_t));
         uint32_t *mycode = (uint32_t *)malloc((size_t)L * sizeof(uint32_t));
         uint64_t *mysk = (uint64_t *)malloc((size_t)M * sizeof(uint64_t));
         or_list top = {0, 0, 0}, fresh = {0, 0, 0};
-        if (!seen || !clo || !chi || !mycode || !mysk) err = OR_ENOMEM;
+        if (!clo || !chi || !mycode || !mysk) err = OR_ENOMEM;
 #pragma omp for schedule(dynamic, 1)
         for (int64_t t = 0; t < m; ++t) {
             if (err) continue;
@@ -594,8 +598,8 @@ int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, co
             for (int32_t s = 0; s < M; ++s) mysk[s] = qs[(int64_t)s * m + t];
             int64_t cnt[3];
             int32_t sl = 0, bd = 0;
-            int rc = walk_one(&ix, qn + t * d, mycode, mysk, k, delta, eps, B, rule, filter_on, seen,
-                              clo, chi, &top, &fresh, &sl, cnt, &bd, t == 0 ? trace : NULL);
+            int rc = walk_one(&ix, qn + t * d, mycode, mysk, k, delta, eps, B, rule, filter_on, clo, chi,
+                              &top, &fresh, &sl, cnt, &bd, t == 0 ? trace : NULL);
             if (rc) {
                 err = rc;
                 continue;
@@ -611,7 +615,7 @@ int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, co
             if (c_rerank) c_rerank[t] = cnt[2];
             if (boundary) boundary[t] = bd;
         }
-        free(seen), free(clo), free(chi), free(mycode), free(mysk);
+        free(clo), free(chi), free(mycode), free(mysk);
         free(top.v), free(fresh.v);
     }
     free(qn), free(qc), free(qs);

@@ -93,86 +93,32 @@ void launch_ranges(const Index &ix, const SearchArgs &a, uint32_t *ranges, hipSt
     }
 }
 
-// --------------------------------------------------------------------------- search
-static constexpr int NT = 256;
-static constexpr int EPT = 2;              // flat entries per thread per filter chunk
-static constexpr int CH = NT * EPT;        // entries per filter chunk
-static constexpr int RB = 256;             // re-rank once this many candidates wait
-static constexpr int PCAP = CH + RB;       // pending capacity
-static constexpr int CC = 1024;            // candidate buffer (power of two)
-static constexpr int RCAP = 16384;         // per-slot list of re-ranked ids (for clearing)
+// --------------------------------------------------------------------------- decision tables
+// The FP64 decisions of a round -- the integer filter threshold and the stopping test
+// -- depend on the query only through the FP32 k-th inner product ip_k, and both are
+// monotone in it.  A small kernel bisects, over the ordered FP32 values in [-1, 1], the
+// boundaries at which they change (FP64 evaluation, as in the definitions below), so
+// the search kernel decides by FP32 comparisons:
+//   tauv[h]  (h = 0..64): largest ip with T(ip) >= h, T(ip) = floor((1+eps) 64 theta/pi)
+//                         clipped to [-1, 64]; +2 if even ip = 1 has T >= h, -2 if none
+//   stopw[d][i-1][T+1]  : smallest ip at which level i with filter threshold T stops
+//                         for the d-th distinct delta; -2 if every ip stops, +2 if none
 static constexpr double kPi = 3.14159265358979323846264338327950288;
+static constexpr int kTauCols = 66; // T = -1..64
 
-struct SearchK {
-    const float *X;
-    const uint32_t *tcode, *tidx, *off;
-    const uint64_t *tsk;
-    int64_t n;
-    int32_t dpad, L, K, M, P, B;
-    const float *Q;
-    const uint32_t *qcode;
-    const uint64_t *qsk;
-    const uint32_t *ranges;
-    int64_t m;
-    const int32_t *ks;
-    int32_t kconst, kmax;
-    const double *recalls;
-    double recall_const, eps;
-    int32_t rule, filter;
-    uint32_t *bitmap;
-    int64_t bwords;
-    uint32_t *rlist;
-    int32_t *out_ids;
-    float *out_ips;
-    pf_query_stats *stats;
-};
-
-struct SearchShared {
-    unsigned long long c_pass;
-    long long c_scan, c_rerank;
-    unsigned long long thr;
-    int pend_cnt, rr_cnt, cand_cnt, top_cnt;
-    int tau_int, stop;
-    uint32_t wsum[4];
-};
-
-__device__ __forceinline__ uint32_t f2ord(float f) {
+__device__ __forceinline__ uint32_t ord_of(float f) {
     const uint32_t u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
-__device__ __forceinline__ float key_ip(unsigned long long key) {
-    const uint32_t o = (uint32_t)(key >> 32);
-    const uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
-    return __uint_as_float(u);
-}
-__device__ __forceinline__ uint32_t key_id(unsigned long long key) {
-    return 0xFFFFFFFFu - (uint32_t)key;
-}
-// larger key = better: inner product descending, then position ascending
-__device__ __forceinline__ unsigned long long mkkey(float ip, uint32_t id) {
-    return ((unsigned long long)f2ord(ip) << 32) | (unsigned long long)(0xFFFFFFFFu - id);
+__device__ __forceinline__ float float_of(uint32_t o) {
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
 }
 
-// Inner product in the fixed FP32 order: lane r (of a 16-lane group) sums the products
-// of the elements 64 t + 4 r + c in increasing order, no fused multiply-add; the sixteen
-// partial sums are combined by s_r + s_{r^8}, then ^4, ^2, ^1.  Rows are zero padded to
-// dpad; zero products leave a partial sum unchanged.
-__device__ __forceinline__ float dot_canon(const float *__restrict__ xrow, const float *qv, int32_t dpad,
-                                           int r) {
-    float s = 0.0f;
-    for (int base = 4 * r; base < dpad; base += 64) {
-        const float4 xv = *reinterpret_cast<const float4 *>(xrow + base);
-        const float4 qq = *reinterpret_cast<const float4 *>(qv + base);
-        s = s + xv.x * qq.x;
-        s = s + xv.y * qq.y;
-        s = s + xv.z * qq.z;
-        s = s + xv.w * qq.w;
-    }
-    s = s + __shfl_xor(s, 8, 16);
-    s = s + __shfl_xor(s, 4, 16);
-    s = s + __shfl_xor(s, 2, 16);
-    s = s + __shfl_xor(s, 1, 16);
-    return s;
+__device__ int tau_of(float ip, double eps) {
+    double v = (double)ip;
+    v = v > 1.0 ? 1.0 : (v < -1.0 ? -1.0 : v);
+    const double ft = floor((1.0 + eps) * 64.0 * acos(v) / kPi);
+    return ft >= 64.0 ? 64 : (ft < -1.0 ? -1 : (int)ft);
 }
 
 // P[Binomial(64, t) <= T]: probability that a point at angle t*pi passes a sketch
@@ -191,14 +137,23 @@ __device__ double binom_cdf64(double t, int T) {
     return s < 1.0 ? s : 1.0;
 }
 
-// Failure bound of Lemma 1 with the sketch filter (log of an upper bound on the
-// probability of missing a true neighbour after level i): a true neighbour at angle
-// <= theta_k is missed only if, for each sketch s, its sketch fails the filter (pass
-// probability >= q, the threshold only shrinks over levels) or none of the g_s tables
-// reading sketch s (j mod M = s) holds it in its window (probability (1 - p^i)^{g_s}).
-// Each factor 1 - q + q (1 - p^i)^{g_s} is evaluated without cancellation.
-__device__ double filter_bound(double theta, double pw, int tau_int, int L, int M) {
-    const double q = binom_cdf64(theta / kPi, tau_int);
+// Stopping test after level i (Sec. 4.1: checked once all repetitions are inspected).
+// EXACT: failure bound of Lemma 1, L log1p(-p^i) <= ln(delta).  ALG1: Algorithm 1's test
+// L p^i >= ln(1/delta).  FILTER: Lemma 1 with the sketch filter -- a true neighbour at
+// angle <= theta_k is missed only if, for each sketch s, its sketch fails the filter
+// (pass probability >= q = P[Bin(64, theta_k/pi) <= T], the threshold only shrinks over
+// levels) or none of the g_s tables reading sketch s (j mod M = s) holds it in its
+// window (probability (1 - p^i)^{g_s}); each factor 1 - q + q (1 - p^i)^{g_s} is
+// evaluated without cancellation.  p = 1 - theta_k/pi, FP64.
+__device__ bool stop_of(float ip, int i, int T, double lndelta, int rule, int L, int M) {
+    double v = (double)ip;
+    v = v > 1.0 ? 1.0 : (v < -1.0 ? -1.0 : v);
+    const double theta = acos(v);
+    const double lnp = log1p(-theta / kPi);
+    const double pw = exp((double)i * lnp);
+    if (rule == PF_RULE_ALG1) return (double)L * pw >= -lndelta;
+    if (rule == PF_RULE_EXACT) return (double)L * log1p(-pw) <= lndelta;
+    const double q = binom_cdf64(theta / kPi, T);
     const double l1p = log1p(-pw);
     double term = 0.0;
     for (int s = 0; s < M && s < L; ++s) {
@@ -207,35 +162,141 @@ __device__ double filter_bound(double theta, double pw, int tau_int, int L, int 
         const double x = q * expm1(a);
         term = term + ((x > -0.5) ? log1p(x) : log((1.0 - q) + q * exp(a)));
     }
-    return term;
+    return term <= lndelta;
 }
 
-// inclusive scan of a[0..N) in LDS by all NT threads
-__device__ void block_scan_incl(uint32_t *a, int N, uint32_t *wsum) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int per = (N + NT - 1) / NT;
-    const int s0 = tid * per, s1 = min(N, s0 + per);
-    uint32_t tot = 0;
-    for (int i = s0; i < s1; ++i) tot += a[i];
-    uint32_t v = tot;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(v, o);
-        if (lane >= o) v += t;
+__global__ __launch_bounds__(64) void k_rule_tables(const double *__restrict__ lndeltas, int32_t ndelta,
+                                                    double eps, int32_t rule, int32_t L, int32_t M,
+                                                    int32_t K, float *__restrict__ tauv,
+                                                    float *__restrict__ stopw) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t olo = ord_of(-1.0f), ohi = ord_of(1.0f);
+    if (t < 65) {
+        const int h = (int)t;
+        float v;
+        if (tau_of(1.0f, eps) >= h) {
+            v = 2.0f;
+        } else if (tau_of(-1.0f, eps) < h) {
+            v = -2.0f;
+        } else {
+            uint32_t lo = olo, hi = ohi; // T(lo) >= h, T(hi) < h
+            while (hi - lo > 1) {
+                const uint32_t mid = lo + (hi - lo) / 2;
+                if (tau_of(float_of(mid), eps) >= h)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            v = float_of(lo);
+        }
+        tauv[h] = v;
+        return;
     }
-    if (lane == 63) wsum[w] = v;
-    __syncthreads();
-    uint32_t pre = v - tot;
-    for (int i = 0; i < w; ++i) pre += wsum[i];
-    for (int i = s0; i < s1; ++i) {
-        pre += a[i];
-        a[i] = pre;
+    const int64_t e = t - 65;
+    if (e >= (int64_t)ndelta * K * kTauCols) return;
+    const int32_t dl = (int32_t)(e / ((int64_t)K * kTauCols));
+    const int32_t rem = (int32_t)(e - (int64_t)dl * K * kTauCols);
+    const int32_t i = rem / kTauCols + 1;
+    const int32_t T = rem % kTauCols - 1;
+    const double lnd = lndeltas[dl];
+    float w;
+    if (stop_of(-1.0f, i, T, lnd, rule, L, M)) {
+        w = -2.0f;
+    } else if (!stop_of(1.0f, i, T, lnd, rule, L, M)) {
+        w = 2.0f;
+    } else {
+        uint32_t lo = olo, hi = ohi; // stop(lo) false, stop(hi) true
+        while (hi - lo > 1) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (stop_of(float_of(mid), i, T, lnd, rule, L, M))
+                hi = mid;
+            else
+                lo = mid;
+        }
+        w = float_of(hi);
     }
-    __syncthreads();
+    stopw[e] = w;
 }
+
+void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, int32_t rule, int32_t L,
+                        int32_t M, int32_t K, float *tauv, float *stopw, hipStream_t s) {
+    const int64_t total = 65 + (int64_t)ndelta * K * kTauCols;
+    hipLaunchKernelGGL(k_rule_tables, dim3((unsigned)((total + 63) / 64)), dim3(64), 0, s, lndeltas_dev, ndelta,
+                       eps, rule, L, M, K, tauv, stopw);
+    PF_HIP(hipGetLastError());
+}
+
+int32_t rule_table_cols() { return kTauCols; }
+
+
+// --------------------------------------------------------------------------- search
+// One wave (a 64-lane workgroup) per query slot.  A query's whole walk -- segments,
+// sketch filter, de-duplication, re-rank, top-k, stopping test -- runs inside its wave
+// without workgroup barriers (lanes exchange data through the wave's own LDS region in
+// program order, compaction by ballot), so the many query waves resident on a CU hide
+// each other's memory latency.  Slot s answers queries s, s + G, s + 2G, ...
+#ifndef PF_SEARCH_EPT
+#define PF_SEARCH_EPT 8
+#endif
+#ifndef PF_SEARCH_U
+#define PF_SEARCH_U 8
+#endif
+#ifndef PF_SEARCH_RB
+#define PF_SEARCH_RB 64
+#endif
+#ifndef PF_SEARCH_CW
+#define PF_SEARCH_CW 256
+#endif
+static constexpr int WV = 64;                // lanes per query wave
+static constexpr int EPT = PF_SEARCH_EPT;    // sketch loads in flight per lane
+static constexpr int WCH = WV * EPT;         // entries per filter chunk
+static constexpr int RB = PF_SEARCH_RB;      // re-rank once this many candidates wait
+static constexpr int PCAP = WCH + RB;        // pending capacity
+static constexpr int CW = PF_SEARCH_CW;      // candidate buffer (power of two)
+static constexpr int U = PF_SEARCH_U;        // rows in flight per 16-lane group
+static constexpr int RROWS = 4 * U;          // rows re-ranked per wave iteration
+static_assert(PCAP % WV == 0, "pending capacity must be a multiple of the wave size");
+static_assert((CW & (CW - 1)) == 0 && CW >= 4 * RROWS, "candidate buffer: power of two, >= 4 slices");
+
+struct SearchK {
+    const float *X;
+    const uint32_t *tidx, *off;
+    const uint64_t *tsk;
+    int64_t n;
+    int32_t dpad, L, K, M, P, B;
+    const float *Q;
+    const uint32_t *qcode;
+    const uint64_t *qsk;
+    const uint32_t *ranges;
+    int64_t m;
+    const int32_t *ks;
+    int32_t kconst, kmax;
+    const int32_t *qtab; // per-query row of stopw (nullable: 0)
+    const float *tauv, *stopw;
+    int32_t filter;
+    int32_t *out_ids;
+    float *out_ips;
+    pf_query_stats *stats;
+};
+
+__device__ __forceinline__ float key_ip(unsigned long long key) { return float_of((uint32_t)(key >> 32)); }
+__device__ __forceinline__ uint32_t key_id(unsigned long long key) { return 0xFFFFFFFFu - (uint32_t)key; }
+// larger key = better: inner product descending, then position ascending
+__device__ __forceinline__ unsigned long long mkkey(float ip, uint32_t id) {
+    return ((unsigned long long)ord_of(ip) << 32) | (unsigned long long)(0xFFFFFFFFu - id);
+}
+
+// order this wave's LDS accesses: everything before is visible to every lane after
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
 
 // number of elements of the descending array arr[0..len) that are greater than key
-__device__ __forceinline__ int count_greater(const unsigned long long *arr, int len,
-                                             unsigned long long key) {
+__device__ __forceinline__ int count_greater(const unsigned long long *arr, int len, unsigned long long key) {
     int lo = 0, hi = len;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -247,62 +308,15 @@ __device__ __forceinline__ int count_greater(const unsigned long long *arr, int 
     return lo;
 }
 
-// top <- best k of top u cand (cand unsorted); called by all threads
-__device__ void merge_all(unsigned long long *top, unsigned long long *ntop, unsigned long long *cand,
-                          SearchShared &sh, int k) {
-    __syncthreads();
-    const int c = sh.cand_cnt;
-    if (c == 0) return;
-    int P2 = 1;
-    while (P2 < c) P2 <<= 1;
-    for (int t = c + threadIdx.x; t < P2; t += NT) cand[t] = 0ull;
-    __syncthreads();
-    for (int size = 2; size <= P2; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < (P2 >> 1); t += NT) {
-                const int i = 2 * t - (t & (stride - 1));
-                const int l = i + stride;
-                const unsigned long long a = cand[i], b = cand[l];
-                const bool desc = (i & size) == 0;
-                if (desc ? (a < b) : (a > b)) {
-                    cand[i] = b;
-                    cand[l] = a;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    const int tc = sh.top_cnt;
-    const int newc = min(k, tc + c);
-    for (int t = threadIdx.x; t < c; t += NT) {
-        const int r = t + count_greater(top, tc, cand[t]);
-        if (r < k) ntop[r] = cand[t];
-    }
-    for (int t = threadIdx.x; t < tc; t += NT) {
-        const int r = t + count_greater(cand, c, top[t]);
-        if (r < k) ntop[r] = top[t];
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < newc; t += NT) top[t] = ntop[t];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        sh.top_cnt = newc;
-        sh.cand_cnt = 0;
-        sh.thr = (newc == k) ? top[k - 1] : 0ull;
-    }
-    __syncthreads();
-}
-
-struct Lds {
+struct WLds {
     unsigned long long *top, *ntop, *cand, *tq;
-    uint32_t *pending, *rr, *clo, *chi, *qc, *segBeg, *segStart;
+    uint32_t *pending, *clo, *chi, *qc, *segBeg, *segStart;
     float *qv;
-    SearchShared *sh;
 };
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t search_lds_layout(int L, int kmax, int dpad, Lds *o, void *base) {
+__host__ __device__ inline size_t search_lds_layout(int L, int kmax, int dpad, WLds *o, void *base) {
     size_t off = 0;
     char *b = static_cast<char *>(base);
     auto take = [&](size_t bytes) {
@@ -310,14 +324,12 @@ __host__ __device__ inline size_t search_lds_layout(int L, int kmax, int dpad, L
         off = align16(off + bytes);
         return p;
     };
-    Lds l;
-    l.sh = reinterpret_cast<SearchShared *>(take(sizeof(SearchShared)));
+    WLds l;
     l.top = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * kmax));
     l.ntop = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * kmax));
-    l.cand = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * CC));
+    l.cand = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * CW));
     l.tq = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * L));
     l.pending = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * PCAP));
-    l.rr = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * PCAP));
     l.clo = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * L));
     l.chi = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * L));
     l.qc = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * L));
@@ -326,6 +338,194 @@ __host__ __device__ inline size_t search_lds_layout(int L, int kmax, int dpad, L
     l.qv = reinterpret_cast<float *>(take(sizeof(float) * dpad));
     if (o) *o = l;
     return off;
+}
+
+// Per-query state kept in registers; every lane holds the same (wave-uniform) values.
+struct QState {
+    int k;
+    int pend, cand, top;
+    unsigned long long thr;
+    long long c_scan, c_pass, c_rerank;
+};
+
+// top <- best k distinct points of top u cand[0..cand) (the accumulator's flush; cand
+// unsorted): bitonic sort of the candidates, then copies of a point -- equal keys,
+// since a point's inner product is the same each time it is re-ranked -- are dropped
+// (adjacent in the sorted candidates, or already in the top-k), and every remaining
+// element's rank in the union is its index in its own list plus the count of greater
+// elements in the other.
+__device__ void wave_merge(WLds &l, QState &st) {
+    const int lane = threadIdx.x;
+    int c = st.cand;
+    if (c == 0) return;
+    wsync();
+    unsigned long long *cand = l.cand;
+    int P2 = 1;
+    while (P2 < c) P2 <<= 1;
+    for (int t = c + lane; t < P2; t += WV) cand[t] = 0ull;
+    wsync();
+    for (int size = 2; size <= P2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = lane; t < (P2 >> 1); t += WV) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const unsigned long long a = cand[i], b = cand[j];
+                const bool desc = (i & size) == 0;
+                if (desc ? (a < b) : (a > b)) {
+                    cand[i] = b;
+                    cand[j] = a;
+                }
+            }
+            wsync();
+        }
+    }
+    const int tc = st.top, k = st.k;
+    {
+        // drop copies; in place, one 64-element block at a time (reads before writes)
+        const uint64_t lt = lanemask_lt(lane);
+        int w = 0;
+        for (int t0 = 0; t0 < c; t0 += WV) {
+            const int t = t0 + lane;
+            unsigned long long key = 0;
+            bool keep = false;
+            if (t < c) {
+                key = cand[t];
+                keep = (t == 0 || cand[t - 1] != key);
+                if (keep) {
+                    const int g = count_greater(l.top, tc, key);
+                    keep = !(g < tc && l.top[g] == key);
+                }
+            }
+            wsync();
+            const uint64_t mk = __ballot(keep);
+            if (keep) cand[w + __popcll(mk & lt)] = key;
+            w += __popcll(mk);
+            wsync();
+        }
+        c = w;
+    }
+    const int newc = min(k, tc + c);
+    for (int t = lane; t < c; t += WV) {
+        const int r = t + count_greater(l.top, tc, cand[t]);
+        if (r < k) l.ntop[r] = cand[t];
+    }
+    for (int t = lane; t < tc; t += WV) {
+        const int r = t + count_greater(cand, c, l.top[t]);
+        if (r < k) l.ntop[r] = l.top[t];
+    }
+    wsync();
+    for (int t = lane; t < newc; t += WV) l.top[t] = l.ntop[t];
+    wsync();
+    st.top = newc;
+    st.cand = 0;
+    st.thr = (newc == k) ? l.top[k - 1] : 0ull;
+}
+
+// Inner products of up to U rows per 16-lane group in the fixed FP32 order: lane r sums
+// the products of the elements 64 t + 4 r + c in increasing order with no fused
+// multiply-add; the sixteen partial sums are combined by s_r + s_{r^8}, then ^4, ^2, ^1.
+// Rows are zero padded to dpad; a zero product leaves a partial sum unchanged.
+// DT > 0: rows of at most 64 DT floats, every load of the group issued before any use;
+// DT = 0: any length, one 64-float chunk at a time.
+template <int DT>
+__device__ __forceinline__ void dot_rows(const float *__restrict__ X, int32_t dpad, const float *qv,
+                                         const uint32_t *ids, int cnt, int r, float *out) {
+    float acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0.0f;
+    if constexpr (DT > 0) {
+        float4 xv[U][DT];
+#pragma unroll
+        for (int t = 0; t < DT; ++t) {
+            const int base = 64 * t + 4 * r;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                xv[u][t] = (u < cnt && base < dpad)
+                               ? *reinterpret_cast<const float4 *>(X + (int64_t)ids[u] * dpad + base)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int t = 0; t < DT; ++t) {
+            const int base = 64 * t + 4 * r;
+            const float4 qq = base < dpad ? *reinterpret_cast<const float4 *>(qv + base)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                acc[u] = acc[u] + xv[u][t].x * qq.x;
+                acc[u] = acc[u] + xv[u][t].y * qq.y;
+                acc[u] = acc[u] + xv[u][t].z * qq.z;
+                acc[u] = acc[u] + xv[u][t].w * qq.w;
+            }
+        }
+    } else {
+        for (int base = 4 * r; base < dpad; base += 64) {
+            const float4 qq = *reinterpret_cast<const float4 *>(qv + base);
+            float4 xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                xv[u] = u < cnt ? *reinterpret_cast<const float4 *>(X + (int64_t)ids[u] * dpad + base)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                acc[u] = acc[u] + xv[u].x * qq.x;
+                acc[u] = acc[u] + xv[u].y * qq.y;
+                acc[u] = acc[u] + xv[u].z * qq.z;
+                acc[u] = acc[u] + xv[u].w * qq.w;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        float s = acc[u];
+        s = s + __shfl_xor(s, 8, 16);
+        s = s + __shfl_xor(s, 4, 16);
+        s = s + __shfl_xor(s, 2, 16);
+        s = s + __shfl_xor(s, 1, 16);
+        out[u] = s;
+    }
+}
+
+// Re-rank rows ids[0..rc); candidates better than the current k-th enter the buffer,
+// which is merged into the top-k whenever it could overflow.
+template <int DT>
+__device__ void wave_rerank(const SearchK &p, WLds &l, const uint32_t *ids, int rc, QState &st) {
+    const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
+    const uint64_t lt = lanemask_lt(lane);
+    for (int t0 = 0; t0 < rc; t0 += RROWS) {
+        const int first = t0 + g * U;
+        const int cnt = max(0, min(U, rc - first));
+        uint32_t x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = u < cnt ? ids[first + u] : 0u;
+        float ip[U];
+        dot_rows<DT>(p.X, p.dpad, l.qv, x, cnt, r, ip);
+        bool emit = false;
+        unsigned long long key = 0;
+        if (r < cnt) {
+            float myip = ip[0];
+            uint32_t myx = x[0];
+#pragma unroll
+            for (int u = 1; u < U; ++u)
+                if (r == u) {
+                    myip = ip[u];
+                    myx = x[u];
+                }
+            key = mkkey(myip, myx);
+            emit = st.top < st.k || key > st.thr;
+        }
+        const uint64_t mk = __ballot(emit);
+        if (emit) l.cand[st.cand + __popcll(mk & lt)] = key;
+        st.cand += __popcll(mk);
+        if (st.cand > CW - RROWS) wave_merge(l, st);
+    }
+}
+
+// Candidates waiting in pending[0..pend) (point positions) are re-ranked; the top-k
+// merge drops points seen before.
+template <int DT> __device__ void wave_process(const SearchK &p, WLds &l, QState &st) {
+    wave_rerank<DT>(p, l, l.pending, st.pend, st);
+    st.c_rerank += st.pend;
+    st.pend = 0;
 }
 
 __device__ __forceinline__ void level_range(const SearchK &p, int32_t j, int32_t i, uint32_t qc, int64_t q,
@@ -343,66 +543,58 @@ __device__ __forceinline__ void level_range(const SearchK &p, int32_t j, int32_t
     }
 }
 
-// Re-rank the waiting candidates: position lookup, de-duplication against every point
-// already re-ranked (one bit per point, per slot), inner product, top-k candidates.
-__device__ void process_pending(const SearchK &p, Lds &l, int k, uint32_t *bm, uint32_t *rl) {
-    SearchShared &sh = *l.sh;
-    const int tid = threadIdx.x;
-    const int pc = sh.pend_cnt;
-    for (int t = tid; t < pc; t += NT) {
-        const uint32_t x = p.tidx[l.pending[t]];
-        const uint32_t bit = 1u << (x & 31u);
-        const uint32_t old = atomicOr(&bm[x >> 5], bit);
-        if (!(old & bit)) {
-            const int r = atomicAdd(&sh.rr_cnt, 1);
-            l.rr[r] = x;
-        }
+// largest s with segStart[s] <= f (segStart[0] = 0 <= f < segStart[ns])
+__device__ __forceinline__ int find_seg(const uint32_t *segStart, int ns, uint32_t f) {
+    int lo = 0, hi = ns;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (segStart[mid] <= f)
+            lo = mid;
+        else
+            hi = mid;
     }
-    __syncthreads();
-    const int rc = sh.rr_cnt;
-    const long long done = sh.c_rerank;
-    for (int t = tid; t < rc; t += NT)
-        if (done + t < RCAP) rl[done + t] = l.rr[t];
-    const int g = tid >> 4, r = tid & 15;
-    const bool full = sh.top_cnt == k;
-    const unsigned long long thr = sh.thr;
-    for (int t = g; t < rc; t += NT / 16) {
-        const uint32_t x = l.rr[t];
-        const float ip = dot_canon(p.X + (int64_t)x * p.dpad, l.qv, p.dpad, r);
-        if (r == 0) {
-            const unsigned long long key = mkkey(ip, x);
-            if (!full || key > thr) {
-                const int c = atomicAdd(&sh.cand_cnt, 1);
-                l.cand[c] = key;
-            }
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {
-        sh.c_rerank += rc;
-        sh.rr_cnt = 0;
-        sh.pend_cnt = 0;
-    }
-    __syncthreads();
+    return lo;
 }
 
-__global__ __launch_bounds__(NT) void k_search(SearchK p) {
+// inclusive scan of a[0..N) in this wave's LDS
+__device__ void wave_scan_incl(uint32_t *a, int N) {
+    const int lane = threadIdx.x;
+    const int per = (N + WV - 1) / WV;
+    const int s0 = lane * per, s1 = min(N, s0 + per);
+    uint32_t tot = 0;
+    for (int i = s0; i < s1; ++i) tot += a[i];
+    uint32_t v = tot;
+    for (int o = 1; o < WV; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    uint32_t pre = v - tot;
+    for (int i = s0; i < s1; ++i) {
+        pre += a[i];
+        a[i] = pre;
+    }
+    wsync();
+}
+
+template <int DT> __global__ __launch_bounds__(WV) void k_search(SearchK p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    Lds l;
+    WLds l;
     search_lds_layout(p.L, p.kmax, p.dpad, &l, smem);
-    SearchShared &sh = *l.sh;
-    const int tid = threadIdx.x;
-    uint32_t *bm = p.bitmap + (int64_t)blockIdx.x * p.bwords;
-    uint32_t *rl = p.rlist + (int64_t)blockIdx.x * RCAP;
+    const int lane = threadIdx.x;
+    const uint64_t lt = lanemask_lt(lane);
     const int32_t L = p.L, K = p.K;
     const int64_t n = p.n;
+    const int ns = 2 * L;
 
     for (int64_t q = blockIdx.x; q < p.m; q += gridDim.x) {
-        const int k = p.ks ? max(1, min(p.ks[q], p.kmax)) : p.kconst;
-        const double recall = p.recalls ? p.recalls[q] : p.recall_const;
-        const double lndelta = log(1.0 - recall);
-        for (int c = tid; c < p.dpad; c += NT) l.qv[c] = p.Q[q * p.dpad + c];
-        for (int32_t j = tid; j < L; j += NT) {
+        QState st;
+        st.k = p.ks ? max(1, min(p.ks[q], p.kmax)) : p.kconst;
+        st.pend = st.cand = st.top = 0;
+        st.thr = 0;
+        st.c_scan = st.c_pass = st.c_rerank = 0;
+        const float *stopw = p.stopw + (int64_t)(p.qtab ? p.qtab[q] : 0) * K * kTauCols;
+        for (int c = lane; c < p.dpad; c += WV) l.qv[c] = p.Q[q * p.dpad + c];
+        for (int32_t j = lane; j < L; j += WV) {
             const uint32_t qc = p.qcode[(int64_t)j * p.m + q];
             l.qc[j] = qc;
             l.tq[j] = p.qsk[(int64_t)(j % p.M) * p.m + q];
@@ -411,32 +603,25 @@ __global__ __launch_bounds__(NT) void k_search(SearchK p) {
             l.clo[j] = lo;
             l.chi[j] = lo;
         }
-        if (tid == 0) {
-            sh.c_pass = 0;
-            sh.c_scan = 0;
-            sh.c_rerank = 0;
-            sh.thr = 0;
-            sh.pend_cnt = sh.rr_cnt = sh.cand_cnt = sh.top_cnt = 0;
-            sh.tau_int = 64;
-            sh.stop = 0;
-        }
-        __syncthreads();
-        unsigned long long my_pass = 0;
+        if (lane == 0) l.segStart[0] = 0;
+        wsync();
+        int tau = 64;
+        bool stopped = false;
         int stop_level = 0;
         for (int32_t i = K; i >= 1; --i) {
             // new segments of every table for this level
-            for (int32_t j = tid; j < L; j += NT) {
+            for (int32_t j = lane; j < L; j += WV) {
                 uint32_t lo, hi;
                 level_range(p, j, i, l.qc[j], q, lo, hi);
                 const uint32_t a = l.clo[j], b = l.chi[j];
                 uint32_t na = a, nb = b;
                 if (a > lo) {
-                    const uint64_t st = ((uint64_t)(a - lo) + p.B - 1) / p.B * (uint64_t)p.B;
-                    na = (a > st) ? (uint32_t)(a - st) : 0u;
+                    const uint64_t sz = ((uint64_t)(a - lo) + p.B - 1) / p.B * (uint64_t)p.B;
+                    na = (a > sz) ? (uint32_t)(a - sz) : 0u;
                 }
                 if (b < hi) {
-                    const uint64_t st = ((uint64_t)(hi - b) + p.B - 1) / p.B * (uint64_t)p.B;
-                    const uint64_t e = (uint64_t)b + st;
+                    const uint64_t sz = ((uint64_t)(hi - b) + p.B - 1) / p.B * (uint64_t)p.B;
+                    const uint64_t e = (uint64_t)b + sz;
                     nb = e < (uint64_t)n ? (uint32_t)e : (uint32_t)n;
                 }
                 l.segBeg[2 * j] = na;
@@ -446,109 +631,85 @@ __global__ __launch_bounds__(NT) void k_search(SearchK p) {
                 l.clo[j] = na;
                 l.chi[j] = nb;
             }
-            if (tid == 0) l.segStart[0] = 0;
-            __syncthreads();
-            block_scan_incl(l.segStart + 1, 2 * L, sh.wsum);
-            const uint32_t total = l.segStart[2 * L];
-            const int tau = sh.tau_int;
-            if (tid == 0) sh.c_scan += total;
-            for (uint32_t base = 0; base < total; base += CH) {
+            wsync();
+            wave_scan_incl(l.segStart + 1, ns);
+            const uint32_t total = l.segStart[ns];
+            st.c_scan += total;
+            for (uint32_t base = 0; base < total; base += WCH) {
+                int s = find_seg(l.segStart, ns, base);
+                uint32_t xv[EPT];
+                int32_t tj[EPT];
+                uint64_t skv[EPT];
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
-                    const uint32_t f = base + u * NT + tid;
+                    const uint32_t f = base + u * WV + lane;
+                    xv[u] = 0xFFFFFFFFu;
+                    tj[u] = 0;
+                    skv[u] = 0;
                     if (f < total) {
-                        int lo = 0, hi = 2 * L;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (l.segStart[mid] <= f)
-                                lo = mid;
-                            else
-                                hi = mid;
-                        }
-                        const int32_t j = lo >> 1;
-                        const uint32_t pos = l.segBeg[lo] + (f - l.segStart[lo]);
-                        const uint32_t e = (uint32_t)j * (uint32_t)n + pos;
-                        const int h = __popcll(p.tsk[e] ^ l.tq[j]);
-                        if (h <= tau) {
-                            ++my_pass;
-                            const int slot = atomicAdd(&sh.pend_cnt, 1);
-                            l.pending[slot] = e;
-                        }
+                        while (l.segStart[s + 1] <= f) ++s;
+                        const uint32_t pos = l.segBeg[s] + (f - l.segStart[s]);
+                        tj[u] = s >> 1;
+                        const uint32_t e = (uint32_t)tj[u] * (uint32_t)n + pos;
+                        skv[u] = p.tsk[e];
+                        xv[u] = p.tidx[e];
                     }
                 }
-                // decide from a value no thread can change until the second barrier
-                __syncthreads();
-                const bool proc = sh.pend_cnt >= RB || base + CH >= total;
-                __syncthreads();
-                if (proc) {
-                    process_pending(p, l, k, bm, rl);
-                    if (sh.cand_cnt > CC - PCAP) merge_all(l.top, l.ntop, l.cand, sh, k);
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    const bool pass = xv[u] != 0xFFFFFFFFu && __popcll(skv[u] ^ l.tq[tj[u]]) <= tau;
+                    const uint64_t mk = __ballot(pass);
+                    if (pass) l.pending[st.pend + __popcll(mk & lt)] = xv[u];
+                    st.pend += __popcll(mk);
+                }
+                if (st.pend >= RB) {
+                    st.c_pass += st.pend;
+                    wsync();
+                    wave_process<DT>(p, l, st);
                 }
             }
-            merge_all(l.top, l.ntop, l.cand, sh, k);
-            if (tid == 0) {
-                int stop = 0;
-                if (sh.top_cnt == k) {
-                    double ipk = (double)key_ip(l.top[k - 1]);
-                    ipk = ipk > 1.0 ? 1.0 : (ipk < -1.0 ? -1.0 : ipk);
-                    const double theta = acos(ipk);
-                    const double lnp = log1p(-theta / kPi);
-                    const double pw = exp((double)i * lnp);
-                    if (p.rule == PF_RULE_ALG1)
-                        stop = ((double)L * pw >= -lndelta);
-                    else if (p.rule == PF_RULE_EXACT)
-                        stop = ((double)L * log1p(-pw) <= lndelta);
-                    else
-                        stop = filter_bound(theta, pw, sh.tau_int, L, p.M) <= lndelta;
-                    if (p.filter) {
-                        const double t = (1.0 + p.eps) * 64.0 * theta / kPi;
-                        const double ft = floor(t);
-                        sh.tau_int = ft >= 64.0 ? 64 : (ft < -1.0 ? -1 : (int)ft);
-                    }
-                }
-                sh.stop = stop;
+            if (st.pend > 0) {
+                st.c_pass += st.pend;
+                wsync();
+                wave_process<DT>(p, l, st);
             }
-            __syncthreads();
-            if (sh.stop) {
+            wave_merge(l, st);
+            bool stop = false;
+            if (st.top == st.k) {
+                const float ipk = key_ip(l.top[st.k - 1]);
+                stop = ipk >= stopw[(i - 1) * kTauCols + (tau + 1)];
+                if (!stop && p.filter) {
+                    int T = -1;
+                    for (int h = 64; h >= 0; --h)
+                        if (ipk <= p.tauv[h]) {
+                            T = h;
+                            break;
+                        }
+                    tau = T;
+                }
+            }
+            if (stop) {
+                stopped = true;
                 stop_level = i;
                 break;
             }
         }
-        if (!sh.stop) {
-            // level 0: linear scan over every point not yet re-ranked
-            const int g = tid >> 4, r = tid & 15;
-            for (int64_t base = 0; base < n; base += 16 * 16) {
-                const bool full = sh.top_cnt == k;
-                const unsigned long long thr = sh.thr;
-                for (int u = 0; u < 16; ++u) {
-                    const int64_t x = base + u * 16 + g;
-                    if (x >= n) break;
-                    const uint32_t w = __hip_atomic_load(&bm[x >> 5], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                    if ((w >> (x & 31)) & 1u) continue;
-                    const float ip = dot_canon(p.X + x * p.dpad, l.qv, p.dpad, r);
-                    if (r == 0) {
-                        const unsigned long long key = mkkey(ip, (uint32_t)x);
-                        if (!full || key > thr) {
-                            const int c = atomicAdd(&sh.cand_cnt, 1);
-                            l.cand[c] = key;
-                        }
-                    }
-                }
-                __syncthreads();
-                const bool flush = sh.cand_cnt > CC - 256;
-                __syncthreads();
-                if (flush) merge_all(l.top, l.ntop, l.cand, sh, k);
+        if (!stopped) {
+            // level 0: linear scan, every point re-ranked, in blocks of PCAP positions
+            for (int64_t base = 0; base < n; base += PCAP) {
+                const int rc = (int)min((int64_t)PCAP, n - base);
+                for (int t = lane; t < rc; t += WV) l.pending[t] = (uint32_t)(base + t);
+                wsync();
+                wave_rerank<DT>(p, l, l.pending, rc, st);
+                wsync();
             }
-            merge_all(l.top, l.ntop, l.cand, sh, k);
-            if (tid == 0) sh.c_rerank = n;
+            wave_merge(l, st);
+            st.c_rerank += n;
             stop_level = 0;
         }
-        atomicAdd(&sh.c_pass, my_pass);
-        __syncthreads();
-        for (int t = tid; t < p.kmax; t += NT) {
+        for (int t = lane; t < p.kmax; t += WV) {
             const int64_t o = q * p.kmax + t;
-            if (t < k) {
+            if (t < st.k) {
                 const unsigned long long key = l.top[t];
                 p.out_ids[o] = (int32_t)key_id(key);
                 if (p.out_ips) p.out_ips[o] = key_ip(key);
@@ -557,46 +718,52 @@ __global__ __launch_bounds__(NT) void k_search(SearchK p) {
                 if (p.out_ips) p.out_ips[o] = -INFINITY;
             }
         }
-        if (tid == 0 && p.stats) {
-            pf_query_stats st;
-            st.stop_level = stop_level;
-            st.reserved = 0;
-            st.c_scan = sh.c_scan;
-            st.c_pass = (int64_t)sh.c_pass;
-            st.c_rerank = sh.c_rerank;
-            p.stats[q] = st;
+        if (lane == 0 && p.stats) {
+            pf_query_stats s;
+            s.stop_level = stop_level;
+            s.reserved = 0;
+            s.c_scan = st.c_scan;
+            s.c_pass = st.c_pass;
+            s.c_rerank = st.c_rerank;
+            p.stats[q] = s;
         }
-        // clear this slot's de-duplication bits for the next query
-        const long long nr = sh.c_rerank;
-        if (sh.stop && nr <= RCAP) {
-            for (long long t = tid; t < nr; t += NT) bm[rl[t] >> 5] = 0u;
-        } else {
-            for (int64_t t = tid; t < p.bwords; t += NT) bm[t] = 0u;
-        }
-        __threadfence();
-        __syncthreads();
+        wsync();
+    }
+}
+
+// chunks of 64 floats per row, as a kernel specialisation (0 = any length)
+static int row_chunks(int32_t dpad) {
+    const int t = (dpad + 63) / 64;
+    return t <= 1 ? 1 : t <= 2 ? 2 : t <= 4 ? 4 : 0;
+}
+
+static const void *search_kernel(int dt) {
+    switch (dt) {
+    case 1: return (const void *)k_search<1>;
+    case 2: return (const void *)k_search<2>;
+    case 4: return (const void *)k_search<4>;
+    default: return (const void *)k_search<0>;
     }
 }
 
 int64_t search_slots(const Index &ix, int64_t m) {
-    const int64_t per_cu = 8;
+    int per_cu = 0;
+    const size_t lds = search_lds_layout(ix.L, PF_MAX_K, ix.dpad, nullptr, nullptr);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel(row_chunks(ix.dpad)), WV, lds) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 8;
     return std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)ix.num_cus * per_cu));
 }
 
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s) {
     if (a.m <= 0) return;
+    const size_t lds = search_lds_layout(ix.L, a.kmax, ix.dpad, nullptr, nullptr);
+    const int dt = row_chunks(ix.dpad);
+    PF_HIP(hipFuncSetAttribute(search_kernel(dt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int64_t slots = search_slots(ix, a.m);
-    const int64_t bwords = (ix.n + 31) / 32;
-    const size_t bm_bytes = (size_t)slots * bwords * sizeof(uint32_t);
-    if (ix.bitmap.bytes < bm_bytes) {
-        // every query leaves its slot's bits cleared, so zero only a fresh allocation
-        ix.bitmap.alloc(bm_bytes);
-        launch_fill_u32(ix.bitmap.as<uint32_t>(), (int64_t)(ix.bitmap.bytes / 4), 0u, s);
-    }
-    ix.rlist.ensure((size_t)slots * RCAP * sizeof(uint32_t));
     SearchK p;
     p.X = ix.X.as<float>();
-    p.tcode = ix.tcode.as<uint32_t>();
     p.tidx = ix.tidx.as<uint32_t>();
     p.off = ix.off.as<uint32_t>();
     p.tsk = ix.tsk.as<uint64_t>();
@@ -615,21 +782,19 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     p.ks = a.ks;
     p.kconst = a.kconst;
     p.kmax = a.kmax;
-    p.recalls = a.recalls;
-    p.recall_const = a.recall_const;
-    p.eps = a.eps;
-    p.rule = a.rule;
+    p.qtab = a.qtab;
+    p.tauv = a.tauv;
+    p.stopw = a.stopw;
     p.filter = a.filter;
-    p.bitmap = ix.bitmap.as<uint32_t>();
-    p.bwords = bwords;
-    p.rlist = ix.rlist.as<uint32_t>();
     p.out_ids = a.out_ids;
     p.out_ips = a.out_ips;
     p.stats = a.stats;
-    const size_t lds = search_lds_layout(ix.L, a.kmax, ix.dpad, nullptr, nullptr);
-    PF_HIP(hipFuncSetAttribute((const void *)k_search, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    hipLaunchKernelGGL(k_search, dim3((unsigned)slots), dim3(NT), lds, s, p);
+    switch (dt) {
+    case 1: hipLaunchKernelGGL(k_search<1>, dim3((unsigned)slots), dim3(WV), lds, s, p); break;
+    case 2: hipLaunchKernelGGL(k_search<2>, dim3((unsigned)slots), dim3(WV), lds, s, p); break;
+    case 4: hipLaunchKernelGGL(k_search<4>, dim3((unsigned)slots), dim3(WV), lds, s, p); break;
+    default: hipLaunchKernelGGL(k_search<0>, dim3((unsigned)slots), dim3(WV), lds, s, p); break;
+    }
     PF_HIP(hipGetLastError());
 }
 

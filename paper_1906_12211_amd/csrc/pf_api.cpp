@@ -308,14 +308,26 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         PF_CHECK(recall_const > 0.0 && recall_const <= 1.0, PF_EINVAL, "search: recall must be in (0, 1]");
     if (m == 0) return;
     hipStream_t s = as_stream(stream);
-    if (mem == PF_HOST && ks) {
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+
+    // per-query parameters are checked on the host (copied there when device-resident)
+    std::vector<int32_t> ks_host;
+    std::vector<double> rec_host;
+    if (ks) {
+        ks_host.resize(m);
+        PF_HIP(hipMemcpy(ks_host.data(), ks, (size_t)m * sizeof(int32_t),
+                         mem == PF_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < m; ++i)
-            PF_CHECK(ks[i] >= 1 && ks[i] <= kmax, PF_EINVAL, "search: per-query k out of range");
+            PF_CHECK(ks_host[i] >= 1 && ks_host[i] <= kmax, PF_EINVAL, "search: per-query k out of [1, kmax]");
     }
-    if (mem == PF_HOST && recalls) {
+    if (recalls) {
+        rec_host.resize(m);
+        PF_HIP(hipMemcpy(rec_host.data(), recalls, (size_t)m * sizeof(double),
+                         mem == PF_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < m; ++i)
-            PF_CHECK(recalls[i] > 0.0 && recalls[i] <= 1.0, PF_EINVAL, "search: recall must be in (0, 1]");
+            PF_CHECK(rec_host[i] > 0.0 && rec_host[i] <= 1.0, PF_EINVAL, "search: recall must be in (0, 1]");
     }
+
     hipEvent_t ev[5];
     if (o.timing)
         for (auto &e : ev) PF_HIP(hipEventCreate(&e));
@@ -325,13 +337,45 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     uint64_t *qsk;
     prepare_rows(ix, queries, m, mem, s, &qX, &qcode, &qsk);
     if (o.timing) PF_HIP(hipEventRecord(ev[1], s));
+
+    // decision tables for this call's (rule, eps, distinct deltas): delta = 1 - recall
+    std::vector<double> lnd;
+    std::vector<int32_t> qtab_host;
+    if (recalls) {
+        std::vector<double> uniq(rec_host);
+        std::sort(uniq.begin(), uniq.end());
+        uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+        PF_CHECK(uniq.size() <= 4096, PF_EUNSUPPORTED, "search: at most 4096 distinct recall values per call");
+        for (double r : uniq) lnd.push_back(std::log(1.0 - r));
+        qtab_host.resize(m);
+        for (int64_t i = 0; i < m; ++i)
+            qtab_host[i] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), rec_host[i]) - uniq.begin());
+    } else {
+        lnd.push_back(std::log(1.0 - recall_const));
+    }
+    const int32_t cols = rule_table_cols();
+    const int32_t filt = o.no_filter ? 0 : 1;
+    if (ix->rule_key_rule != o.rule || ix->rule_key_eps != o.eps || ix->rule_key_filter != filt ||
+        ix->rule_key_lndeltas != lnd) {
+        const size_t tab_floats = 65 + (size_t)lnd.size() * ix->K * cols;
+        const size_t dl_off = (tab_floats * sizeof(float) + 15) & ~(size_t)15;
+        ix->rule_tab.alloc(dl_off + lnd.size() * sizeof(double));
+        double *dl = reinterpret_cast<double *>(ix->rule_tab.as<char>() + dl_off);
+        PF_HIP(hipMemcpyAsync(dl, lnd.data(), lnd.size() * sizeof(double), h2d, s));
+        float *tab = ix->rule_tab.as<float>();
+        launch_rule_tables(dl, (int32_t)lnd.size(), o.eps, o.rule, ix->L, ix->M, ix->K, tab, tab + 65, s);
+        PF_HIP(hipStreamSynchronize(s));
+        ix->rule_key_rule = o.rule;
+        ix->rule_key_eps = o.eps;
+        ix->rule_key_filter = filt;
+        ix->rule_key_lndeltas = lnd;
+    }
+
     // outputs and per-query parameters on the device
-    DevBuf dids, dips, dstats, dks, drec;
+    DevBuf dids, dips, dstats, dks, dqtab;
     int32_t *oid = out_ids;
     float *oip = out_ips;
     pf_query_stats *ost = stats;
-    const int32_t *dk = ks;
-    const double *dr = recalls;
     if (mem == PF_HOST) {
         dids.alloc((size_t)m * kmax * sizeof(int32_t));
         oid = dids.as<int32_t>();
@@ -343,31 +387,28 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
             dstats.alloc((size_t)m * sizeof(pf_query_stats));
             ost = dstats.as<pf_query_stats>();
         }
-        if (ks) {
-            dks.alloc((size_t)m * sizeof(int32_t));
-            PF_HIP(hipMemcpyAsync(dks.p, ks, (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            dk = dks.as<int32_t>();
-        }
-        if (recalls) {
-            drec.alloc((size_t)m * sizeof(double));
-            PF_HIP(hipMemcpyAsync(drec.p, recalls, (size_t)m * sizeof(double), hipMemcpyHostToDevice, s));
-            dr = drec.as<double>();
-        }
+    }
+    if (ks) {
+        dks.alloc((size_t)m * sizeof(int32_t));
+        PF_HIP(hipMemcpyAsync(dks.p, ks_host.data(), (size_t)m * sizeof(int32_t), h2d, s));
+    }
+    if (!qtab_host.empty()) {
+        dqtab.alloc(qtab_host.size() * sizeof(int32_t));
+        PF_HIP(hipMemcpyAsync(dqtab.p, qtab_host.data(), qtab_host.size() * sizeof(int32_t), h2d, s));
     }
     SearchArgs a;
     a.Q = qX;
     a.qcode = qcode;
     a.qsk = qsk;
     a.m = m;
-    a.ks = dk;
+    a.ks = ks ? dks.as<int32_t>() : nullptr;
     a.kconst = kconst;
     a.kmax = kmax;
-    a.recalls = dr;
-    a.recall_const = recall_const;
-    a.eps = o.eps;
+    a.qtab = qtab_host.empty() ? nullptr : dqtab.as<int32_t>();
+    a.tauv = ix->rule_tab.as<float>();
+    a.stopw = ix->rule_tab.as<float>() + 65;
     a.B = o.B;
-    a.rule = o.rule;
-    a.filter = o.no_filter ? 0 : 1;
+    a.filter = filt;
     a.out_ids = oid;
     a.out_ips = oip;
     a.stats = ost;
@@ -387,10 +428,10 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
             PF_HIP(hipMemcpyAsync(out_ips, oip, (size_t)m * kmax * sizeof(float), hipMemcpyDeviceToHost, s));
         if (stats)
             PF_HIP(hipMemcpyAsync(stats, ost, (size_t)m * sizeof(pf_query_stats), hipMemcpyDeviceToHost, s));
-        PF_HIP(hipStreamSynchronize(s));
     }
+    // temporaries above are released on return: the kernels must be done
+    PF_HIP(hipStreamSynchronize(s));
     if (o.timing) {
-        PF_HIP(hipEventSynchronize(ev[3]));
         float t01, t12, t23, t03;
         PF_HIP(hipEventElapsedTime(&t01, ev[0], ev[1]));
         PF_HIP(hipEventElapsedTime(&t12, ev[1], ev[2]));
@@ -402,9 +443,6 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         ix->timing.search_ms = t23;
         ix->timing.total_ms = t03;
         for (auto &e : ev) (void)hipEventDestroy(e);
-    } else if (mem == PF_DEVICE) {
-        // temporaries above are released on return: make sure the kernels are done
-        PF_HIP(hipStreamSynchronize(s));
     }
 }
 } // namespace pf

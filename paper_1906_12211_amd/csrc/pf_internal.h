@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <vector>
 
 #include "../../include/pfhip.h"
 
@@ -89,6 +90,11 @@ struct Index {
 
     // search scratch (grown on demand)
     DevBuf qX, qcode, qsk, ranges, bitmap, rlist, qstats, flags, tmp;
+    // decision tables of the last (rule, eps, deltas) searched
+    DevBuf rule_tab;
+    int32_t rule_key_rule = -1, rule_key_filter = -1;
+    double rule_key_eps = 0.0;
+    std::vector<double> rule_key_lndeltas;
     pf_timing timing{};
 };
 
@@ -119,15 +125,18 @@ struct SearchArgs {
     int64_t m;
     const int32_t *ks;     // per-query k (nullable: kconst)
     int32_t kconst, kmax;
-    const double *recalls; // per-query recall (nullable: recall_const)
-    double recall_const;
-    double eps;
-    int32_t B, rule, filter;
+    const int32_t *qtab;   // per-query row of stopw (nullable: row 0)
+    const float *tauv;     // 65 filter-threshold boundaries (see k_search.hip)
+    const float *stopw;    // ndelta x K x 66 stopping thresholds
+    int32_t B, filter;
     int32_t *out_ids;      // m x kmax
     float *out_ips;        // m x kmax (nullable)
     pf_query_stats *stats; // m (nullable)
 };
 void launch_ranges(const Index &ix, const SearchArgs &a, uint32_t *ranges, hipStream_t s);
+void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, int32_t rule, int32_t L,
+                        int32_t M, int32_t K, float *tauv, float *stopw, hipStream_t s);
+int32_t rule_table_cols();
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s);
 int64_t search_slots(const Index &ix, int64_t m);
 
