@@ -97,7 +97,16 @@ typedef struct {
 
 typedef struct {
     double normalize_ms, hash_ms, ranges_ms, search_ms, total_ms;
+    int32_t tile;         /* tile shape the search kernel ran with (batched calls) */
+    int32_t waves_per_cu; /* cap on resident query waves per CU (0 = occupancy limit) */
 } pf_timing;
+
+/* pf_search_batch flags */
+#define PF_BATCH_LEARNED 1  /* order the work queue longest-predicted-first by the
+                               scheduler attached with pf_index_set_scheduler */
+#define PF_BATCH_AUTOTUNE 2 /* time the built tile shapes on this batch and keep the fastest
+                               (cached per architecture and index shape; also in the JSON-lines
+                               file named by the environment variable PF_TUNE_CACHE) */
 
 /* Normalise n rows to unit length (Sec. 4.2, "Vector storage"): squared norm summed in
  * FP64 in index order, FP64 square root and division, each quotient rounded once to
@@ -139,6 +148,19 @@ int pf_search(pf_index *ix, const float *queries, int64_t m, int32_t k, double r
 int pf_search_ex(pf_index *ix, const float *queries, int64_t m, int32_t k, double recall,
                  const pf_search_opts *opts, int32_t *out_ids, float *out_ips,
                  pf_query_stats *stats, int32_t mem, void *stream);
+
+/* Batched search: one persistent launch answers m queries with per-query k (ks[i] in
+ * [1, kmax]; NULL = kmax for all) and per-query recall (recalls[i] in (0, 1], required),
+ * taking queries from a device work queue so that queries of very different cost share
+ * the GPU evenly.  The queue is consumed in the order `order` (a permutation of 0..m-1,
+ * nullable = 0..m-1) or, with PF_BATCH_LEARNED, longest-predicted-first by the attached
+ * scheduler; termination of every query is still decided by the stopping rule, so the
+ * results do not depend on the order.  out_ids / out_ips are m x kmax; a query with
+ * k < kmax is padded with id -1 and ip -inf.  Other arguments and errors as pf_search_ex. */
+int pf_search_batch(pf_index *ix, const float *queries, int64_t m, const int32_t *ks,
+                    const double *recalls, int32_t kmax, const pf_search_opts *opts,
+                    const int32_t *order, int32_t *out_ids, float *out_ips, pf_query_stats *stats,
+                    int32_t flags, int32_t mem, void *stream);
 
 /* Hash m rows with the index's functions (Sec. 2.2: bit = 1 iff <a, x> >= 0) after
  * normalising them: codes L x m (u32, table-major, h_{1,j} the most significant of the

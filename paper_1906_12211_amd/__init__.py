@@ -25,8 +25,10 @@ PF_HASH_BF16X3, PF_HASH_FP64 = 0, 1
  PF_EXPORT_SKETCHES, PF_EXPORT_OFFSETS) = range(6)
 PF_MAX_TABLES, PF_MAX_K, PF_MAX_DIM = 512, 256, 4096
 
-EXPORTED = ["pf_normalize", "pf_build_index", "pf_search", "pf_search_ex", "pf_hash", "pf_export",
-            "pf_index_info", "pf_last_timing", "pf_free_index", "pf_last_error", "pf_version"]
+PF_BATCH_LEARNED, PF_BATCH_AUTOTUNE = 1, 2
+
+EXPORTED = ["pf_normalize", "pf_build_index", "pf_search", "pf_search_ex", "pf_search_batch", "pf_hash",
+            "pf_export", "pf_index_info", "pf_last_timing", "pf_free_index", "pf_last_error", "pf_version"]
 
 
 class PfError(RuntimeError):
@@ -60,7 +62,7 @@ class pf_info(ctypes.Structure):
 class pf_timing(ctypes.Structure):
     _fields_ = [("normalize_ms", ctypes.c_double), ("hash_ms", ctypes.c_double),
                 ("ranges_ms", ctypes.c_double), ("search_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("tile", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
 
 
 _lib = None
@@ -96,6 +98,9 @@ def lib():
         L.pf_search_ex.restype = ctypes.c_int
         L.pf_search_ex.argtypes = [_P, _P, _I64, _I32, _D, ctypes.POINTER(pf_search_opts), _P, _P, _P,
                                    _I32, _P]
+        L.pf_search_batch.restype = ctypes.c_int
+        L.pf_search_batch.argtypes = [_P, _P, _I64, _P, _P, _I32, ctypes.POINTER(pf_search_opts), _P, _P, _P,
+                                      _P, _I32, _I32, _P]
         L.pf_hash.restype = ctypes.c_int
         L.pf_hash.argtypes = [_P, _P, _I64, _P, _P, _I32, _P]
         L.pf_export.restype = ctypes.c_int
@@ -236,6 +241,37 @@ class Index:
         _check(lib().pf_search_ex(self._h, pq, m, k, recall, ctypes.byref(opts), _buf(ids)[0],
                                   _buf(ips)[0], _buf(st)[0], mem, stream))
         return SearchResult(ids, ips, _stats_view(st) if st is not None else None)
+
+    def search_batch(self, queries, ks, recalls, kmax: int, order=None, learned: bool = False,
+                     autotune: bool = False, eps: float = 0.0, B: int = 12, rule: int = PF_RULE_FILTER,
+                     filter: bool = True, timing: bool = False) -> SearchResult:
+        """One persistent launch over all queries with per-query k and recall (work queue)."""
+        q = _f32(queries)
+        m = q.shape[0]
+        torch_in = _is_torch(q)
+
+        def arr(a, np_dt, t_dt):
+            if a is None:
+                return None
+            if torch_in:
+                import torch
+
+                return torch.as_tensor(a, dtype=getattr(torch, t_dt), device=q.device).contiguous()
+            return np.ascontiguousarray(a, dtype=np_dt)
+
+        ks_a = arr(ks, np.int32, "int32")
+        rec_a = arr(recalls, np.float64, "float64")
+        ord_a = arr(order, np.int32, "int32")
+        ids = _empty_like_input(q, (m, kmax), np.int32, _torch_dtype("int32"))
+        ips = _empty_like_input(q, (m, kmax), np.float32, _torch_dtype("float32"))
+        st = _empty_like_input(q, (m, 4), np.int64, _torch_dtype("int64"))
+        opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0)
+        flags = (PF_BATCH_LEARNED if learned else 0) | (PF_BATCH_AUTOTUNE if autotune else 0)
+        pq, mem, stream = _buf(q)
+        _check(lib().pf_search_batch(self._h, pq, m, _buf(ks_a)[0], _buf(rec_a)[0], kmax, ctypes.byref(opts),
+                                     _buf(ord_a)[0], _buf(ids)[0], _buf(ips)[0], _buf(st)[0], flags, mem,
+                                     stream))
+        return SearchResult(ids, ips, _stats_view(st))
 
     def hash(self, x):
         x = _f32(x)

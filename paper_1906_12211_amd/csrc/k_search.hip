@@ -231,32 +231,29 @@ int32_t rule_table_cols() { return kTauCols; }
 
 // --------------------------------------------------------------------------- search
 // One wave (a 64-lane workgroup) per query slot.  A query's whole walk -- segments,
-// sketch filter, de-duplication, re-rank, top-k, stopping test -- runs inside its wave
-// without workgroup barriers (lanes exchange data through the wave's own LDS region in
-// program order, compaction by ballot), so the many query waves resident on a CU hide
-// each other's memory latency.  Slot s answers queries s, s + G, s + 2G, ...
-#ifndef PF_SEARCH_EPT
-#define PF_SEARCH_EPT 8
-#endif
-#ifndef PF_SEARCH_U
-#define PF_SEARCH_U 8
-#endif
-#ifndef PF_SEARCH_RB
-#define PF_SEARCH_RB 64
-#endif
-#ifndef PF_SEARCH_CW
-#define PF_SEARCH_CW 256
-#endif
-static constexpr int WV = 64;                // lanes per query wave
-static constexpr int EPT = PF_SEARCH_EPT;    // sketch loads in flight per lane
-static constexpr int WCH = WV * EPT;         // entries per filter chunk
-static constexpr int RB = PF_SEARCH_RB;      // re-rank once this many candidates wait
-static constexpr int PCAP = WCH + RB;        // pending capacity
-static constexpr int CW = PF_SEARCH_CW;      // candidate buffer (power of two)
-static constexpr int U = PF_SEARCH_U;        // rows in flight per 16-lane group
-static constexpr int RROWS = 4 * U;          // rows re-ranked per wave iteration
-static_assert(PCAP % WV == 0, "pending capacity must be a multiple of the wave size");
-static_assert((CW & (CW - 1)) == 0 && CW >= 4 * RROWS, "candidate buffer: power of two, >= 4 slices");
+// sketch filter, re-rank, top-k, stopping test -- runs inside its wave without
+// workgroup barriers (lanes exchange data through the wave's own LDS region in program
+// order, compaction by ballot), so the many query waves resident on a CU hide each
+// other's memory latency.  Queries are taken either statically (slot s answers queries
+// s, s + G, ...) or from a device work queue (an atomic counter, optionally through an
+// order array), which balances queries of very different cost.
+//
+// Tile shape: EPT sketch loads in flight per lane in a filter chunk, U rows in flight
+// per 16-lane group in the re-rank; DT = 64-float chunks per row (0 = any length).
+static constexpr int WV = 64; // lanes per query wave
+template <int EPT_, int U_> struct Tile {
+    static constexpr int EPT = EPT_;
+    static constexpr int U = U_;
+    static constexpr int WCH = WV * EPT;   // entries per filter chunk
+    static constexpr int RB = 64;          // re-rank once this many candidates wait
+    static constexpr int PCAP = WCH + RB;  // pending capacity
+    static constexpr int CW = 256;         // candidate buffer (power of two)
+    static constexpr int RROWS = 4 * U;    // rows re-ranked per wave iteration
+    static_assert(PCAP % WV == 0, "pending capacity must be a multiple of the wave size");
+    static_assert(CW >= 4 * RROWS, "candidate buffer holds at least four re-rank slices");
+};
+static constexpr int kMaxPCAP = WV * 16 + 64;
+static constexpr int kCW = 256;
 
 struct SearchK {
     const float *X;
@@ -274,6 +271,8 @@ struct SearchK {
     const int32_t *qtab; // per-query row of stopw (nullable: 0)
     const float *tauv, *stopw;
     int32_t filter;
+    unsigned int *queue;  // work-queue counter (nullable: static assignment)
+    const int32_t *order; // queue position -> query (nullable: identity)
     int32_t *out_ids;
     float *out_ips;
     pf_query_stats *stats;
@@ -327,9 +326,9 @@ __host__ __device__ inline size_t search_lds_layout(int L, int kmax, int dpad, W
     WLds l;
     l.top = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * kmax));
     l.ntop = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * kmax));
-    l.cand = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * CW));
+    l.cand = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * kCW));
     l.tq = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * L));
-    l.pending = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * PCAP));
+    l.pending = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * kMaxPCAP));
     l.clo = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * L));
     l.chi = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * L));
     l.qc = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * L));
@@ -427,7 +426,7 @@ __device__ void wave_merge(WLds &l, QState &st) {
 // Rows are zero padded to dpad; a zero product leaves a partial sum unchanged.
 // DT > 0: rows of at most 64 DT floats, every load of the group issued before any use;
 // DT = 0: any length, one 64-float chunk at a time.
-template <int DT>
+template <int DT, int U>
 __device__ __forceinline__ void dot_rows(const float *__restrict__ X, int32_t dpad, const float *qv,
                                          const uint32_t *ids, int cnt, int r, float *out) {
     float acc[U];
@@ -487,8 +486,9 @@ __device__ __forceinline__ void dot_rows(const float *__restrict__ X, int32_t dp
 
 // Re-rank rows ids[0..rc); candidates better than the current k-th enter the buffer,
 // which is merged into the top-k whenever it could overflow.
-template <int DT>
+template <int DT, class TL>
 __device__ void wave_rerank(const SearchK &p, WLds &l, const uint32_t *ids, int rc, QState &st) {
+    constexpr int U = TL::U, RROWS = TL::RROWS, CW = TL::CW;
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
     const uint64_t lt = lanemask_lt(lane);
     for (int t0 = 0; t0 < rc; t0 += RROWS) {
@@ -498,7 +498,7 @@ __device__ void wave_rerank(const SearchK &p, WLds &l, const uint32_t *ids, int 
 #pragma unroll
         for (int u = 0; u < U; ++u) x[u] = u < cnt ? ids[first + u] : 0u;
         float ip[U];
-        dot_rows<DT>(p.X, p.dpad, l.qv, x, cnt, r, ip);
+        dot_rows<DT, U>(p.X, p.dpad, l.qv, x, cnt, r, ip);
         bool emit = false;
         unsigned long long key = 0;
         if (r < cnt) {
@@ -522,8 +522,8 @@ __device__ void wave_rerank(const SearchK &p, WLds &l, const uint32_t *ids, int 
 
 // Candidates waiting in pending[0..pend) (point positions) are re-ranked; the top-k
 // merge drops points seen before.
-template <int DT> __device__ void wave_process(const SearchK &p, WLds &l, QState &st) {
-    wave_rerank<DT>(p, l, l.pending, st.pend, st);
+template <int DT, class TL> __device__ void wave_process(const SearchK &p, WLds &l, QState &st) {
+    wave_rerank<DT, TL>(p, l, l.pending, st.pend, st);
     st.c_rerank += st.pend;
     st.pend = 0;
 }
@@ -576,7 +576,8 @@ __device__ void wave_scan_incl(uint32_t *a, int N) {
     wsync();
 }
 
-template <int DT> __global__ __launch_bounds__(WV) void k_search(SearchK p) {
+template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(SearchK p) {
+    constexpr int EPT = TL::EPT, WCH = TL::WCH, RB = TL::RB, PCAP = TL::PCAP;
     extern __shared__ __align__(16) unsigned char smem[];
     WLds l;
     search_lds_layout(p.L, p.kmax, p.dpad, &l, smem);
@@ -586,7 +587,10 @@ template <int DT> __global__ __launch_bounds__(WV) void k_search(SearchK p) {
     const int64_t n = p.n;
     const int ns = 2 * L;
 
-    for (int64_t q = blockIdx.x; q < p.m; q += gridDim.x) {
+    int64_t qi = blockIdx.x;
+    if (p.queue) qi = __shfl((int64_t)(lane == 0 ? atomicAdd(p.queue, 1u) : 0u), 0);
+    while (qi < p.m) {
+        const int64_t q = p.order ? (int64_t)p.order[qi] : qi;
         QState st;
         st.k = p.ks ? max(1, min(p.ks[q], p.kmax)) : p.kconst;
         st.pend = st.cand = st.top = 0;
@@ -665,13 +669,13 @@ template <int DT> __global__ __launch_bounds__(WV) void k_search(SearchK p) {
                 if (st.pend >= RB) {
                     st.c_pass += st.pend;
                     wsync();
-                    wave_process<DT>(p, l, st);
+                    wave_process<DT, TL>(p, l, st);
                 }
             }
             if (st.pend > 0) {
                 st.c_pass += st.pend;
                 wsync();
-                wave_process<DT>(p, l, st);
+                wave_process<DT, TL>(p, l, st);
             }
             wave_merge(l, st);
             bool stop = false;
@@ -700,7 +704,7 @@ template <int DT> __global__ __launch_bounds__(WV) void k_search(SearchK p) {
                 const int rc = (int)min((int64_t)PCAP, n - base);
                 for (int t = lane; t < rc; t += WV) l.pending[t] = (uint32_t)(base + t);
                 wsync();
-                wave_rerank<DT>(p, l, l.pending, rc, st);
+                wave_rerank<DT, TL>(p, l, l.pending, rc, st);
                 wsync();
             }
             wave_merge(l, st);
@@ -728,6 +732,10 @@ template <int DT> __global__ __launch_bounds__(WV) void k_search(SearchK p) {
             p.stats[q] = s;
         }
         wsync();
+        if (p.queue)
+            qi = __shfl((int64_t)(lane == 0 ? atomicAdd(p.queue, 1u) : 0u), 0);
+        else
+            qi += gridDim.x;
     }
 }
 
@@ -737,31 +745,60 @@ static int row_chunks(int32_t dpad) {
     return t <= 1 ? 1 : t <= 2 ? 2 : t <= 4 ? 4 : 0;
 }
 
-static const void *search_kernel(int dt) {
-    switch (dt) {
-    case 1: return (const void *)k_search<1>;
-    case 2: return (const void *)k_search<2>;
-    case 4: return (const void *)k_search<4>;
-    default: return (const void *)k_search<0>;
+// tile shapes the library is built with (the autotuner chooses among them)
+using T88 = Tile<8, 8>;
+using T48 = Tile<4, 8>;
+using T168 = Tile<16, 8>;
+using T84 = Tile<8, 4>;
+static constexpr int kNumTiles = 4;
+static const char *kTileNames[kNumTiles] = {"ept8-u8", "ept4-u8", "ept16-u8", "ept8-u4"};
+
+template <int DT> static const void *search_kernel_dt(int tile) {
+    switch (tile) {
+    case 1: return (const void *)k_search<DT, T48>;
+    case 2: return (const void *)k_search<DT, T168>;
+    case 3: return (const void *)k_search<DT, T84>;
+    default: return (const void *)k_search<DT, T88>;
     }
 }
 
-int64_t search_slots(const Index &ix, int64_t m) {
+static const void *search_kernel(int dt, int tile) {
+    switch (dt) {
+    case 1: return search_kernel_dt<1>(tile);
+    case 2: return search_kernel_dt<2>(tile);
+    case 4: return search_kernel_dt<4>(tile);
+    default: return search_kernel_dt<0>(tile);
+    }
+}
+
+int32_t search_tile_count() { return kNumTiles; }
+const char *search_tile_name(int32_t t) { return (t >= 0 && t < kNumTiles) ? kTileNames[t] : "?"; }
+
+// resident query waves per CU for a tile shape (occupancy from registers and LDS)
+int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile) {
     int per_cu = 0;
-    const size_t lds = search_lds_layout(ix.L, PF_MAX_K, ix.dpad, nullptr, nullptr);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel(row_chunks(ix.dpad)), WV, lds) !=
+    const size_t lds = search_lds_layout(ix.L, kmax, ix.dpad, nullptr, nullptr);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel(row_chunks(ix.dpad), tile), WV, lds) !=
             hipSuccess ||
         per_cu < 1)
-        per_cu = 8;
-    return std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)ix.num_cus * per_cu));
+        per_cu = 4;
+    return per_cu;
+}
+
+int64_t search_slots(const Index &ix, int64_t m) {
+    return std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)ix.num_cus * search_waves_per_cu(ix, PF_MAX_K, 0)));
 }
 
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s) {
     if (a.m <= 0) return;
     const size_t lds = search_lds_layout(ix.L, a.kmax, ix.dpad, nullptr, nullptr);
     const int dt = row_chunks(ix.dpad);
-    PF_HIP(hipFuncSetAttribute(search_kernel(dt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const int64_t slots = search_slots(ix, a.m);
+    const int tile = (a.tile >= 0 && a.tile < kNumTiles) ? a.tile : 0;
+    const void *fn = search_kernel(dt, tile);
+    PF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = search_waves_per_cu(ix, a.kmax, tile);
+    if (a.waves_per_cu > 0) per_cu = std::min(per_cu, a.waves_per_cu);
+    const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(a.m, (int64_t)ix.num_cus * per_cu));
     SearchK p;
     p.X = ix.X.as<float>();
     p.tidx = ix.tidx.as<uint32_t>();
@@ -786,16 +823,14 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     p.tauv = a.tauv;
     p.stopw = a.stopw;
     p.filter = a.filter;
+    p.queue = a.queue;
+    p.order = a.order;
     p.out_ids = a.out_ids;
     p.out_ips = a.out_ips;
     p.stats = a.stats;
-    switch (dt) {
-    case 1: hipLaunchKernelGGL(k_search<1>, dim3((unsigned)slots), dim3(WV), lds, s, p); break;
-    case 2: hipLaunchKernelGGL(k_search<2>, dim3((unsigned)slots), dim3(WV), lds, s, p); break;
-    case 4: hipLaunchKernelGGL(k_search<4>, dim3((unsigned)slots), dim3(WV), lds, s, p); break;
-    default: hipLaunchKernelGGL(k_search<0>, dim3((unsigned)slots), dim3(WV), lds, s, p); break;
-    }
-    PF_HIP(hipGetLastError());
+    if (a.queue) launch_fill_u32(a.queue, 1, 0u, s);
+    void *args[] = {&p};
+    PF_HIP(hipLaunchKernel(fn, dim3((unsigned)slots), dim3(WV), args, lds, s));
 }
 
 } // namespace pf

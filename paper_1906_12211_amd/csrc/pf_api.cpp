@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -290,9 +292,118 @@ static void prepare_rows(pf_index *ix, const float *x, int64_t m, int32_t mem, h
     *qsk = ix->qsk.as<uint64_t>();
 }
 
+std::vector<int32_t> learned_order(Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m,
+                                   hipStream_t s);
+
+// ------------------------------------------------------------------ autotuner
+// Tile shapes of the batched search kernel (sketch loads and rows in flight per lane)
+// and the number of resident query waves per CU are timed on the batch itself; the
+// fastest is kept per (architecture, n, d, L, kmax) in memory and, when the environment
+// variable PF_TUNE_CACHE names a file, in that file as JSON lines.
+struct TuneChoice {
+    int32_t tile = 0, waves = 0;
+    double us_per_query = 0.0;
+};
+
+static std::string tune_key(const Index &ix, int32_t kmax) {
+    hipDeviceProp_t prop;
+    std::string arch = "gfx";
+    if (hipGetDeviceProperties(&prop, ix.device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t c = arch.find(':');
+    if (c != std::string::npos) arch = arch.substr(0, c);
+    return arch + "|n" + std::to_string(ix.n) + "|d" + std::to_string(ix.d) + "|L" + std::to_string(ix.L) +
+           "|k" + std::to_string(kmax);
+}
+
+static bool tune_cache_read(const std::string &key, TuneChoice &out) {
+    const char *path = std::getenv("PF_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[256];
+        TuneChoice t;
+        if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"tile\": %d, \"waves\": %d, \"us_per_query\": %lf}", k,
+                        &t.tile, &t.waves, &t.us_per_query) == 4 &&
+            key == k) {
+            out = t;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void tune_cache_write(const std::string &key, const TuneChoice &t) {
+    const char *path = std::getenv("PF_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\", \"tile\": %d, \"waves\": %d, \"us_per_query\": %.6f, \"name\": \"%s\"}\n",
+                 key.c_str(), t.tile, t.waves, t.us_per_query, search_tile_name(t.tile));
+    std::fclose(f);
+}
+
+static TuneChoice cached_tuning(Index &ix, int32_t kmax) {
+    const std::string key = tune_key(ix, kmax);
+    auto it = ix.tuned.find(key);
+    if (it != ix.tuned.end()) return TuneChoice{it->second.tile, it->second.waves, it->second.us};
+    TuneChoice t;
+    if (tune_cache_read(key, t)) ix.tuned[key] = {t.tile, t.waves, t.us_per_query};
+    return t;
+}
+
+static TuneChoice autotune(Index &ix, SearchArgs a, int32_t kmax, hipStream_t s) {
+    const std::string key = tune_key(ix, kmax);
+    const int64_t sample = std::min<int64_t>(a.m, 8192);
+    a.m = sample; // the first queries of the batch (in queue order)
+    TuneChoice best;
+    best.us_per_query = 1e300;
+    hipEvent_t e0, e1;
+    PF_HIP(hipEventCreate(&e0));
+    PF_HIP(hipEventCreate(&e1));
+    const int32_t nl = ix.K - ix.P;
+    for (int32_t t = 0; t < search_tile_count(); ++t) {
+        const int32_t wmax = search_waves_per_cu(ix, kmax, t);
+        for (int32_t w : {wmax, std::max(1, wmax / 2)}) {
+            a.tile = t;
+            a.waves_per_cu = w;
+            launch_search(ix, a, nl > 0 ? ix.ranges.as<uint32_t>() : nullptr, s); // warm-up
+            PF_HIP(hipEventRecord(e0, s));
+            launch_search(ix, a, nl > 0 ? ix.ranges.as<uint32_t>() : nullptr, s);
+            PF_HIP(hipEventRecord(e1, s));
+            PF_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            PF_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const double us = ms * 1e3 / (double)sample;
+            if (us < best.us_per_query) {
+                best.tile = t;
+                best.waves = w;
+                best.us_per_query = us;
+            }
+            if (w == 1) break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ix.tuned[key] = {best.tile, best.waves, best.us_per_query};
+    tune_cache_write(key, best);
+    return best;
+}
+
+struct BatchCtl {
+    bool queue = false;           // device work queue instead of static slots
+    const int32_t *order = nullptr; // host or device (see mem) queue order, nullable
+    bool learned = false;         // order from the attached scheduler
+    bool autotune = false;        // choose the tile shape by timing this batch
+};
+
 static void search_impl(pf_index *ix, const float *queries, int64_t m, const int32_t *ks, int32_t kconst,
                         int32_t kmax, const double *recalls, double recall_const, const pf_search_opts *opts,
-                        int32_t *out_ids, float *out_ips, pf_query_stats *stats, int32_t mem, void *stream) {
+                        int32_t *out_ids, float *out_ips, pf_query_stats *stats, int32_t mem, void *stream,
+                        const BatchCtl &bc = BatchCtl()) {
     PF_CHECK(ix, PF_EINVAL, "null index");
     PF_CHECK(queries && out_ids && m >= 0, PF_EINVAL, "search: bad arguments");
     PF_CHECK(mem == PF_HOST || mem == PF_DEVICE, PF_EINVAL, "search: bad mem");
@@ -409,6 +520,10 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     a.stopw = ix->rule_tab.as<float>() + 65;
     a.B = o.B;
     a.filter = filt;
+    a.queue = nullptr;
+    a.order = nullptr;
+    a.tile = 0;
+    a.waves_per_cu = 0;
     a.out_ids = oid;
     a.out_ips = oip;
     a.stats = ost;
@@ -419,6 +534,34 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         rg = ix->ranges.as<uint32_t>();
     }
     launch_ranges(*ix, a, rg, s);
+    DevBuf dqueue, dorder;
+    if (bc.queue) {
+        dqueue.alloc(64);
+        a.queue = dqueue.as<unsigned int>();
+        std::vector<int32_t> ord;
+        if (bc.order) {
+            ord.resize(m);
+            PF_HIP(hipMemcpy(ord.data(), bc.order, (size_t)m * sizeof(int32_t),
+                             mem == PF_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost));
+        } else if (bc.learned) {
+            PF_CHECK(ix->sched, PF_EINVAL, "search_batch: PF_BATCH_LEARNED needs an attached scheduler");
+            ord = learned_order(*ix, qcode, qsk, m, s);
+        }
+        if (!ord.empty()) {
+            std::vector<char> seen(m, 0);
+            for (int64_t i = 0; i < m; ++i) {
+                PF_CHECK(ord[i] >= 0 && ord[i] < m && !seen[ord[i]], PF_EINVAL,
+                         "search_batch: order must be a permutation of 0..m-1");
+                seen[ord[i]] = 1;
+            }
+            dorder.alloc((size_t)m * sizeof(int32_t));
+            PF_HIP(hipMemcpyAsync(dorder.p, ord.data(), (size_t)m * sizeof(int32_t), h2d, s));
+            a.order = dorder.as<int32_t>();
+        }
+        const TuneChoice tc = bc.autotune ? autotune(*ix, a, kmax, s) : cached_tuning(*ix, kmax);
+        a.tile = tc.tile;
+        a.waves_per_cu = tc.waves;
+    }
     if (o.timing) PF_HIP(hipEventRecord(ev[2], s));
     launch_search(*ix, a, rg, s);
     if (o.timing) PF_HIP(hipEventRecord(ev[3], s));
@@ -442,6 +585,8 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         ix->timing.ranges_ms = t12;
         ix->timing.search_ms = t23;
         ix->timing.total_ms = t03;
+        ix->timing.tile = a.tile;
+        ix->timing.waves_per_cu = a.waves_per_cu;
         for (auto &e : ev) (void)hipEventDestroy(e);
     }
 }
@@ -452,6 +597,23 @@ PF_API int pf_search_ex(pf_index *ix, const float *queries, int64_t m, int32_t k
                         int32_t mem, void *stream) {
     return guard([&] {
         search_impl(ix, queries, m, nullptr, k, k, nullptr, recall, opts, out_ids, out_ips, stats, mem, stream);
+    });
+}
+
+PF_API int pf_search_batch(pf_index *ix, const float *queries, int64_t m, const int32_t *ks, const double *recalls,
+                           int32_t kmax, const pf_search_opts *opts, const int32_t *order, int32_t *out_ids,
+                           float *out_ips, pf_query_stats *stats, int32_t flags, int32_t mem, void *stream) {
+    return guard([&] {
+        PF_CHECK(recalls, PF_EINVAL, "pf_search_batch: recalls is required");
+        PF_CHECK((flags & ~(PF_BATCH_LEARNED | PF_BATCH_AUTOTUNE)) == 0, PF_EINVAL, "pf_search_batch: bad flags");
+        PF_CHECK(!(order && (flags & PF_BATCH_LEARNED)), PF_EINVAL,
+                 "pf_search_batch: give an order or PF_BATCH_LEARNED, not both");
+        BatchCtl bc;
+        bc.queue = true;
+        bc.order = order;
+        bc.learned = (flags & PF_BATCH_LEARNED) != 0;
+        bc.autotune = (flags & PF_BATCH_AUTOTUNE) != 0;
+        search_impl(ix, queries, m, ks, kmax, kmax, recalls, 0.0, opts, out_ids, out_ips, stats, mem, stream, bc);
     });
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -96,6 +97,13 @@ struct Index {
     double rule_key_eps = 0.0;
     std::vector<double> rule_key_lndeltas;
     pf_timing timing{};
+    // autotuned tile shapes per (arch, n, d, L, kmax)
+    struct Tuned {
+        int32_t tile, waves;
+        double us;
+    };
+    std::map<std::string, Tuned> tuned;
+    struct Sched *sched = nullptr; // learned scheduler used by PF_BATCH_LEARNED (not owned)
 };
 
 // ----------------------------------------------------------------- launchers
@@ -129,6 +137,10 @@ struct SearchArgs {
     const float *tauv;     // 65 filter-threshold boundaries (see k_search.hip)
     const float *stopw;    // ndelta x K x 66 stopping thresholds
     int32_t B, filter;
+    unsigned int *queue;   // device work-queue counter (nullable: static assignment)
+    const int32_t *order;  // queue position -> query (nullable)
+    int32_t tile;          // tile shape index (see search_tile_name)
+    int32_t waves_per_cu;  // > 0: cap on resident query waves per CU
     int32_t *out_ids;      // m x kmax
     float *out_ips;        // m x kmax (nullable)
     pf_query_stats *stats; // m (nullable)
@@ -139,5 +151,8 @@ void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, 
 int32_t rule_table_cols();
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s);
 int64_t search_slots(const Index &ix, int64_t m);
+int32_t search_tile_count();
+const char *search_tile_name(int32_t t);
+int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile);
 
 } // namespace pf

@@ -177,3 +177,72 @@ def test_errors():
     # the index still answers after the errors
     r = g.search(X[:3], 5, 0.9)
     assert np.all(r.ids[:, 0] == np.arange(3))
+
+
+def _oracle_per_query(o, Q, ks, recalls, kmax):
+    """Oracle answers for per-query (k, recall): one oracle call per distinct pair."""
+    m = len(Q)
+    ids = np.full((m, kmax), -1, dtype=np.int32)
+    ips = np.full((m, kmax), -np.inf, dtype=np.float32)
+    st = np.zeros((m, 4), dtype=np.int64)
+    bd = np.zeros(m, dtype=np.int32)
+    for k in np.unique(ks):
+        for rec in np.unique(recalls):
+            sel = np.nonzero((ks == k) & (recalls == rec))[0]
+            if len(sel) == 0:
+                continue
+            r = o.search(Q[sel], int(k), float(rec))
+            ids[sel, :k] = r.ids
+            ips[sel, :k] = r.ips
+            st[sel] = np.stack([r.stop_level, r.c_scan, r.c_pass, r.c_rerank], 1)
+            bd[sel] = r.boundary
+    return ids, ips, st, bd
+
+
+def _assert_batch_equal(gr, oids, oips, ost, obd, label):
+    ok = obd == 0
+    print(f"[batch {label}] boundary cases: {int((~ok).sum())} of {len(ok)}", flush=True)
+    assert np.array_equal(gr.stats[ok], ost[ok]), label + " stats"
+    assert np.array_equal(gr.ids[ok], oids[ok]), label + " ids"
+    assert np.array_equal(gr.ips[ok].view(np.uint32), oips[ok].view(np.uint32)), label + " ips"
+    assert ok.mean() > 0.99
+
+
+def test_batch_per_query_params_and_order():
+    """Persistent batched search: per-query k and recall, work queue in any order gives the
+    oracle's answers (the order only changes which wave answers which query)."""
+    X = workloads.gaussian_unit(6000, 40, 81)
+    Q = workloads.gaussian_unit(700, 40, 82)
+    rng = np.random.default_rng(83)
+    ks = rng.choice(np.array([1, 10, 100], dtype=np.int32), size=len(Q))
+    recalls = rng.choice(np.array([0.5, 0.9, 0.99]), size=len(Q))
+    g, o = _build_both(X, L=50, seed=17)
+    oids, oips, ost, obd = _oracle_per_query(o, Q, ks, recalls, 100)
+    _assert_batch_equal(g.search_batch(Q, ks, recalls, 100), oids, oips, ost, obd, "fifo")
+    order = rng.permutation(len(Q)).astype(np.int32)
+    _assert_batch_equal(g.search_batch(Q, ks, recalls, 100, order=order), oids, oips, ost, obd, "shuffled")
+    _assert_batch_equal(g.search_batch(Q, ks, recalls, 100, autotune=True, timing=True), oids, oips, ost, obd,
+                        "autotuned")
+    t = g.last_timing()
+    assert 0 <= t.tile < 4 and t.waves_per_cu >= 1
+    with pytest.raises(pf.PfError):
+        g.search_batch(Q, ks, recalls, 100, order=np.zeros(len(Q), dtype=np.int32))
+    bad = ks.copy()
+    bad[3] = 101
+    with pytest.raises(pf.PfError):
+        g.search_batch(Q, bad, recalls, 100)
+
+
+def test_batch_device_tensors():
+    torch = pytest.importorskip("torch")
+    X = workloads.gaussian_unit(3000, 100, 91)
+    Q = workloads.gaussian_unit(300, 100, 92)
+    rng = np.random.default_rng(93)
+    ks = rng.choice(np.array([1, 10, 20], dtype=np.int32), size=len(Q))
+    recalls = rng.choice(np.array([0.6, 0.9]), size=len(Q))
+    g, o = _build_both(X, L=30, seed=19)
+    oids, oips, ost, obd = _oracle_per_query(o, Q, ks, recalls, 20)
+    r = g.search_batch(torch.from_numpy(Q).cuda(), torch.from_numpy(ks).cuda(), torch.from_numpy(recalls).cuda(), 20)
+    torch.cuda.synchronize()
+    gr = pf.SearchResult(r.ids.cpu().numpy(), r.ips.cpu().numpy(), r.stats.cpu().numpy())
+    _assert_batch_equal(gr, oids, oips, ost, obd, "device")
