@@ -27,8 +27,12 @@ PF_MAX_TABLES, PF_MAX_K, PF_MAX_DIM = 512, 256, 4096
 
 PF_BATCH_LEARNED, PF_BATCH_AUTOTUNE = 1, 2
 
+PF_SCHED_IN, PF_SCHED_OUT, PF_SCHED_PARAMS = 96, 2, 29186
+
 EXPORTED = ["pf_normalize", "pf_build_index", "pf_search", "pf_search_ex", "pf_search_batch", "pf_hash",
-            "pf_export", "pf_index_info", "pf_last_timing", "pf_free_index", "pf_last_error", "pf_version"]
+            "pf_export", "pf_index_info", "pf_last_timing", "pf_free_index", "pf_last_error", "pf_version",
+            "pf_sched_create", "pf_sched_free", "pf_sched_params", "pf_features", "pf_sched_predict",
+            "pf_sched_grad", "pf_sched_train", "pf_sched_save", "pf_sched_load", "pf_index_set_scheduler"]
 
 
 class PfError(RuntimeError):
@@ -111,6 +115,26 @@ def lib():
         L.pf_last_timing.argtypes = [_P, ctypes.POINTER(pf_timing)]
         L.pf_free_index.restype = None
         L.pf_free_index.argtypes = [_P]
+        L.pf_sched_create.restype = ctypes.c_int
+        L.pf_sched_create.argtypes = [_U64, ctypes.POINTER(_P)]
+        L.pf_sched_free.restype = None
+        L.pf_sched_free.argtypes = [_P]
+        L.pf_sched_params.restype = ctypes.c_int
+        L.pf_sched_params.argtypes = [_P, _P, _I32]
+        L.pf_features.restype = ctypes.c_int
+        L.pf_features.argtypes = [_P, _P, _I64, _P, _I32, _P]
+        L.pf_sched_predict.restype = ctypes.c_int
+        L.pf_sched_predict.argtypes = [_P, _P, _I64, _P, _I32, _P]
+        L.pf_sched_grad.restype = ctypes.c_int
+        L.pf_sched_grad.argtypes = [_P, _P, _P, _I64, _P, ctypes.POINTER(_D), _I32, _P]
+        L.pf_sched_train.restype = ctypes.c_int
+        L.pf_sched_train.argtypes = [_P, _P, _P, _I64, _I32, _I32, ctypes.c_float, _U64, _P, _I32, _P]
+        L.pf_sched_save.restype = ctypes.c_int
+        L.pf_sched_save.argtypes = [_P, ctypes.c_char_p]
+        L.pf_sched_load.restype = ctypes.c_int
+        L.pf_sched_load.argtypes = [_P, ctypes.c_char_p]
+        L.pf_index_set_scheduler.restype = ctypes.c_int
+        L.pf_index_set_scheduler.argtypes = [_P, _P]
         _lib = L
     return _lib
 
@@ -282,6 +306,19 @@ class Index:
         _check(lib().pf_hash(self._h, px, m, _buf(codes)[0], _buf(sk)[0], mem, st))
         return codes, sk
 
+    def features(self, x):
+        """Scheduler features (m x 96 FP32) of the rows x under this index."""
+        x = _f32(x)
+        m = x.shape[0]
+        f = _empty_like_input(x, (m, PF_SCHED_IN), np.float32, _torch_dtype("float32"))
+        px, mem, st = _buf(x)
+        _check(lib().pf_features(self._h, px, m, _buf(f)[0], mem, st))
+        return f
+
+    def set_scheduler(self, sched):
+        _check(lib().pf_index_set_scheduler(self._h, sched._h if sched is not None else None))
+        self._sched = sched
+
     _EXPORT = {
         PF_EXPORT_POINTS: (np.float32, lambda s: (s.n, s.d)),
         PF_EXPORT_HYPERPLANES: (np.float32, lambda s: (s.L * s.K + 64 * s.M, s.d)),
@@ -305,3 +342,69 @@ def _torch_dtype(name: str):
         return getattr(torch, name)
     except Exception:  # numpy-only callers never use it
         return None
+
+
+class Scheduler:
+    """The learned query-cost model (96 -> 128 -> 128 -> 2 MLP) trained by the library."""
+
+    def __init__(self, seed: int = 1):
+        h = ctypes.c_void_p()
+        _check(lib().pf_sched_create(seed, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pf_sched_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        p = np.empty(PF_SCHED_PARAMS, dtype=np.float32)
+        _check(lib().pf_sched_params(self._h, _buf(p)[0], 1))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == PF_SCHED_PARAMS
+        _check(lib().pf_sched_params(self._h, _buf(p)[0], 0))
+
+    def predict(self, feat):
+        f = _f32(feat)
+        out = _empty_like_input(f, (f.shape[0], PF_SCHED_OUT), np.float32, _torch_dtype("float32"))
+        pf_, mem, st = _buf(f)
+        _check(lib().pf_sched_predict(self._h, pf_, f.shape[0], _buf(out)[0], mem, st))
+        return out
+
+    def grad(self, feat, target):
+        f, t = _f32(feat), _f32(target)
+        g = np.empty(PF_SCHED_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        if _is_torch(f):
+            import torch
+
+            gd = torch.empty(PF_SCHED_PARAMS, dtype=torch.float32, device=f.device)
+            _check(lib().pf_sched_grad(self._h, _buf(f)[0], _buf(t)[0], f.shape[0], _buf(gd)[0],
+                                       ctypes.byref(loss), PF_DEVICE, _buf(f)[2]))
+            return gd, loss.value
+        _check(lib().pf_sched_grad(self._h, _buf(f)[0], _buf(t)[0], f.shape[0], _buf(g)[0], ctypes.byref(loss),
+                                   PF_HOST, None))
+        return g, loss.value
+
+    def train(self, feat, target, epochs: int = 10, batch: int = 1024, lr: float = 1e-3, seed: int = 7):
+        f, t = _f32(feat), _f32(target)
+        losses = np.empty(epochs, dtype=np.float32)
+        pf_, mem, st = _buf(f)
+        _check(lib().pf_sched_train(self._h, pf_, _buf(t)[0], f.shape[0], epochs, batch, lr, seed,
+                                    _buf(losses)[0], mem, st))
+        return losses
+
+    def save(self, path: str):
+        _check(lib().pf_sched_save(self._h, path.encode()))
+
+    def load(self, path: str):
+        _check(lib().pf_sched_load(self._h, path.encode()))

@@ -1,0 +1,166 @@
+// Kernels of the learned scheduler: per-query features and a 96-128-128-2 FP32 MLP
+// (forward, mean-squared-error gradient, backward, Adam).  The network only orders the
+// batched search's work queue; the stopping rule alone decides when a query ends.
+#include "pf_internal.h"
+
+namespace pf {
+
+// Features of query q (96 FP32): the 64 bits of its sketch 0 as +1 / -1, then
+// log2(1 + size of the query's 13-bit prefix bucket) in tables 0..31 (0 when L < 32).
+__global__ __launch_bounds__(256) void k_features(const uint32_t *__restrict__ qcode,
+                                                  const uint64_t *__restrict__ qsk,
+                                                  const uint32_t *__restrict__ off, int64_t m, int32_t L,
+                                                  int32_t K, int32_t P, float *__restrict__ feat) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m * kSchedIn) return;
+    const int64_t q = t / kSchedIn;
+    const int f = (int)(t - q * kSchedIn);
+    float v = 0.0f;
+    if (f < 64) {
+        v = ((qsk[q] >> f) & 1ull) ? 1.0f : -1.0f; // sketch 0 is the first M x m row block
+    } else {
+        const int j = f - 64;
+        if (j < L) {
+            const int64_t np1 = ((int64_t)1 << P) + 1;
+            const uint32_t b = qcode[(int64_t)j * m + q] >> (K - P);
+            const uint32_t sz = off[(int64_t)j * np1 + b + 1] - off[(int64_t)j * np1 + b];
+            v = log2f(1.0f + (float)sz);
+        }
+    }
+    feat[t] = v;
+}
+
+// out[r][o] = act(sum_i in[row(r)][i] W[i][o] + b[o]); row(r) = rows ? rows[r] : r
+__global__ __launch_bounds__(256) void k_dense(const float *__restrict__ in, const int32_t *__restrict__ rows,
+                                               int32_t nin, const float *__restrict__ W,
+                                               const float *__restrict__ b, int32_t nout, int64_t B, int32_t relu,
+                                               float *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B * nout) return;
+    const int64_t r = t / nout;
+    const int o = (int)(t - r * nout);
+    const float *x = in + (rows ? (int64_t)rows[r] : r) * nin;
+    float s = 0.0f;
+    for (int i = 0; i < nin; ++i) s = s + x[i] * W[(int64_t)i * nout + o];
+    s = s + b[o];
+    out[t] = (relu && s < 0.0f) ? 0.0f : s;
+}
+
+// dy = d(loss)/dy for loss = mean over the B x 2 outputs of (y - target)^2; loss summed
+// into *acc (FP64) in one fixed order by a single wave
+__global__ __launch_bounds__(64) void k_mse(const float *__restrict__ y, const float *__restrict__ tgt,
+                                            const int32_t *__restrict__ rows, int64_t B, float *__restrict__ dy,
+                                            double *acc) {
+    const int lane = threadIdx.x;
+    const double inv = 1.0 / (double)(B * kSchedOut);
+    double part = 0.0;
+    for (int64_t t = lane; t < B * kSchedOut; t += 64) {
+        const int64_t r = t / kSchedOut;
+        const int c = (int)(t - r * kSchedOut);
+        const float e = y[t] - tgt[(rows ? (int64_t)rows[r] : r) * kSchedOut + c];
+        dy[t] = (float)(2.0 * inv) * e;
+        part += (double)e * (double)e;
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (lane == 0) *acc += part * inv;
+}
+
+// din[r][i] = (sum_o dout[r][o] W[i][o]) * [h[r][i] > 0]   (h: the layer input, post-ReLU)
+__global__ __launch_bounds__(256) void k_dense_bwd_in(const float *__restrict__ dout, const float *__restrict__ W,
+                                                      const float *__restrict__ h, int32_t nin, int32_t nout,
+                                                      int64_t B, float *__restrict__ din) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B * nin) return;
+    const int64_t r = t / nin;
+    const int i = (int)(t - r * nin);
+    float s = 0.0f;
+    const float *g = dout + r * nout;
+    const float *w = W + (int64_t)i * nout;
+    for (int o = 0; o < nout; ++o) s = s + g[o] * w[o];
+    din[t] = h[t] > 0.0f ? s : 0.0f;
+}
+
+// dW[i][o] = sum_r in[row(r)][i] dout[r][o],  db[o] = sum_r dout[r][o]  (r in order)
+__global__ __launch_bounds__(256) void k_dense_wgrad(const float *__restrict__ in, const int32_t *__restrict__ rows,
+                                                     const float *__restrict__ dout, int32_t nin, int32_t nout,
+                                                     int64_t B, float *__restrict__ dW, float *__restrict__ db) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (int64_t)nin * nout) {
+        const int i = (int)(t / nout), o = (int)(t - (int64_t)(t / nout) * nout);
+        float s = 0.0f;
+        for (int64_t r = 0; r < B; ++r) s = s + in[(rows ? (int64_t)rows[r] : r) * nin + i] * dout[r * nout + o];
+        dW[t] = s;
+    } else if (t < (int64_t)nin * nout + nout) {
+        const int o = (int)(t - (int64_t)nin * nout);
+        float s = 0.0f;
+        for (int64_t r = 0; r < B; ++r) s = s + dout[r * nout + o];
+        db[o] = s;
+    }
+}
+
+// Adam (Kingma, Ba 2015) with bias correction, step t >= 1
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, const float *__restrict__ g,
+                                              float *__restrict__ m1, float *__restrict__ m2, int64_t count,
+                                              float lr, float b1, float b2, float eps, int32_t t) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float a = b1 * m1[i] + (1.0f - b1) * gi;
+    const float v = b2 * m2[i] + (1.0f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = v;
+    const float ah = a / (1.0f - powf(b1, (float)t));
+    const float vh = v / (1.0f - powf(b2, (float)t));
+    p[i] = p[i] - lr * ah / (sqrtf(vh) + eps);
+}
+
+static unsigned grid_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_features(const Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m, float *feat,
+                     hipStream_t s) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_features, dim3(grid_for(m * kSchedIn)), dim3(256), 0, s, qcode, qsk, ix.off.as<uint32_t>(),
+                       m, ix.L, ix.K, ix.P, feat);
+    PF_HIP(hipGetLastError());
+}
+
+void mlp_forward(const float *params, const float *x, const int32_t *rows, int64_t B, float *h1, float *h2,
+                 float *y, hipStream_t s) {
+    const float *W1 = params + kOffW1, *b1 = params + kOffB1, *W2 = params + kOffW2, *b2 = params + kOffB2,
+                *W3 = params + kOffW3, *b3 = params + kOffB3;
+    hipLaunchKernelGGL(k_dense, dim3(grid_for(B * kSchedHidden)), dim3(256), 0, s, x, rows, kSchedIn, W1, b1,
+                       kSchedHidden, B, 1, h1);
+    hipLaunchKernelGGL(k_dense, dim3(grid_for(B * kSchedHidden)), dim3(256), 0, s, (const float *)h1,
+                       (const int32_t *)nullptr, kSchedHidden, W2, b2, kSchedHidden, B, 1, h2);
+    hipLaunchKernelGGL(k_dense, dim3(grid_for(B * kSchedOut)), dim3(256), 0, s, (const float *)h2,
+                       (const int32_t *)nullptr, kSchedHidden, W3, b3, kSchedOut, B, 0, y);
+    PF_HIP(hipGetLastError());
+}
+
+void mlp_backward(const float *params, const float *x, const int32_t *rows, const float *tgt, int64_t B,
+                  const float *h1, const float *h2, const float *y, float *dy, float *dh2, float *dh1, float *grad,
+                  double *loss_acc, hipStream_t s) {
+    const float *W2 = params + kOffW2, *W3 = params + kOffW3;
+    hipLaunchKernelGGL(k_mse, dim3(1), dim3(64), 0, s, y, tgt, rows, B, dy, loss_acc);
+    hipLaunchKernelGGL(k_dense_wgrad, dim3(grid_for((int64_t)kSchedHidden * kSchedOut + kSchedOut)), dim3(256), 0,
+                       s, h2, (const int32_t *)nullptr, (const float *)dy, kSchedHidden, kSchedOut, B,
+                       grad + kOffW3, grad + kOffB3);
+    hipLaunchKernelGGL(k_dense_bwd_in, dim3(grid_for(B * kSchedHidden)), dim3(256), 0, s, (const float *)dy, W3, h2,
+                       kSchedHidden, kSchedOut, B, dh2);
+    hipLaunchKernelGGL(k_dense_wgrad, dim3(grid_for((int64_t)kSchedHidden * kSchedHidden + kSchedHidden)),
+                       dim3(256), 0, s, h1, (const int32_t *)nullptr, (const float *)dh2, kSchedHidden,
+                       kSchedHidden, B, grad + kOffW2, grad + kOffB2);
+    hipLaunchKernelGGL(k_dense_bwd_in, dim3(grid_for(B * kSchedHidden)), dim3(256), 0, s, (const float *)dh2, W2,
+                       h1, kSchedHidden, kSchedHidden, B, dh1);
+    hipLaunchKernelGGL(k_dense_wgrad, dim3(grid_for((int64_t)kSchedIn * kSchedHidden + kSchedHidden)), dim3(256),
+                       0, s, x, rows, (const float *)dh1, kSchedIn, kSchedHidden, B, grad + kOffW1, grad + kOffB1);
+    PF_HIP(hipGetLastError());
+}
+
+void mlp_adam(float *params, const float *grad, float *m1, float *m2, float lr, int32_t t, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(kSchedParams)), dim3(256), 0, s, params, grad, m1, m2,
+                       (int64_t)kSchedParams, lr, 0.9f, 0.999f, 1e-8f, t);
+    PF_HIP(hipGetLastError());
+}
+
+} // namespace pf

@@ -21,6 +21,8 @@ namespace pf {
 
 static thread_local std::string g_err;
 
+void set_last_error(const std::string &msg) { g_err = msg; }
+
 template <class F> static int guard(F &&f) {
     try {
         f();
@@ -167,7 +169,6 @@ static void normalize_into(const float *src, int64_t rows, int32_t d, int32_t me
 
 using namespace pf;
 
-struct pf_index : public pf::Index {};
 
 PF_API const char *pf_last_error(void) { return g_err.c_str(); }
 PF_API const char *pf_version(void) { return "pfhip 0.1 (gfx950)"; }
@@ -277,8 +278,9 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
 
 namespace pf {
 // normalise + hash rows into qX / codes / sketches held by the index
-static void prepare_rows(pf_index *ix, const float *x, int64_t m, int32_t mem, hipStream_t s,
-                         float **qX, uint32_t **qcode, uint64_t **qsk) {
+void prepare_rows_for(Index &ixr, const float *x, int64_t m, int32_t mem, hipStream_t s, float **qX,
+                      uint32_t **qcode, uint64_t **qsk) {
+    Index *ix = &ixr;
     ix->qX.ensure((size_t)m * ix->dpad * sizeof(float));
     normalize_into(x, m, ix->d, mem, ix->qX.as<float>(), ix->dpad, ix->tmp, ix->flags, s);
     ix->qcode.ensure((size_t)m * ix->L * sizeof(uint32_t));
@@ -446,7 +448,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     float *qX;
     uint32_t *qcode;
     uint64_t *qsk;
-    prepare_rows(ix, queries, m, mem, s, &qX, &qcode, &qsk);
+    prepare_rows_for(*ix, queries, m, mem, s, &qX, &qcode, &qsk);
     if (o.timing) PF_HIP(hipEventRecord(ev[1], s));
 
     // decision tables for this call's (rule, eps, distinct deltas): delta = 1 - recall
@@ -632,7 +634,7 @@ PF_API int pf_hash(pf_index *ix, const float *x, int64_t m, uint32_t *codes, uin
         float *qX;
         uint32_t *qc;
         uint64_t *qs;
-        prepare_rows(ix, x, m, mem, s, &qX, &qc, &qs);
+        prepare_rows_for(*ix, x, m, mem, s, &qX, &qc, &qs);
         const hipMemcpyKind kind = mem == PF_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
         if (codes) PF_HIP(hipMemcpyAsync(codes, qc, (size_t)m * ix->L * sizeof(uint32_t), kind, s));
         if (sketches) PF_HIP(hipMemcpyAsync(sketches, qs, (size_t)m * ix->M * sizeof(uint64_t), kind, s));

@@ -106,6 +106,28 @@ struct Index {
     struct Sched *sched = nullptr; // learned scheduler used by PF_BATCH_LEARNED (not owned)
 };
 
+// ----------------------------------------------------------------- learned scheduler
+// MLP 96 -> 128 (ReLU) -> 128 (ReLU) -> 2, FP32, parameters in one flat array:
+// W1 [96][128], b1 [128], W2 [128][128], b2 [128], W3 [128][2], b3 [2]
+constexpr int kSchedIn = 96, kSchedHidden = 128, kSchedOut = 2;
+constexpr int64_t kOffW1 = 0;
+constexpr int64_t kOffB1 = kOffW1 + (int64_t)kSchedIn * kSchedHidden;
+constexpr int64_t kOffW2 = kOffB1 + kSchedHidden;
+constexpr int64_t kOffB2 = kOffW2 + (int64_t)kSchedHidden * kSchedHidden;
+constexpr int64_t kOffW3 = kOffB2 + kSchedHidden;
+constexpr int64_t kOffB3 = kOffW3 + (int64_t)kSchedHidden * kSchedOut;
+constexpr int64_t kSchedParams = kOffB3 + kSchedOut; // 29,186
+
+struct Index;
+void launch_features(const Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m, float *feat,
+                     hipStream_t s);
+void mlp_forward(const float *params, const float *x, const int32_t *rows, int64_t B, float *h1, float *h2,
+                 float *y, hipStream_t s);
+void mlp_backward(const float *params, const float *x, const int32_t *rows, const float *tgt, int64_t B,
+                  const float *h1, const float *h2, const float *y, float *dy, float *dh2, float *dh1, float *grad,
+                  double *loss_acc, hipStream_t s);
+void mlp_adam(float *params, const float *grad, float *m1, float *m2, float lr, int32_t t, hipStream_t s);
+
 // ----------------------------------------------------------------- launchers
 // normalise: out[i][0..d) = x[i]/|x[i]|, zero-filled to dpad; *bad = min bad row (or n)
 void launch_normalize(const float *x, int64_t n, int32_t d, int32_t ld_in, float *out,
@@ -155,4 +177,12 @@ int32_t search_tile_count();
 const char *search_tile_name(int32_t t);
 int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile);
 
+// normalise + hash caller rows into the index's query buffers (pf_api.cpp)
+void prepare_rows_for(Index &ix, const float *x, int64_t m, int32_t mem, hipStream_t s, float **qX,
+                      uint32_t **qcode, uint64_t **qsk);
+// the thread-local message returned by pf_last_error
+void set_last_error(const std::string &msg);
+
 } // namespace pf
+
+struct pf_index : public pf::Index {};

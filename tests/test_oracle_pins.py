@@ -505,3 +505,36 @@ def test_lemma1_guarantee_with_filter_statistical(oracle_mod):
     assert np.all(rate >= 1 - delta - 4 * sd), rate
     assert np.all(np.concatenate(levels) > 0)
     assert (hits_paper / seeds).min() < rate.min() - 0.05
+
+
+# ----------------------------------------------------------------------- scheduler network
+def test_mlp_gradient_finite_differences():
+    """The FP64 reference gradient of the scheduler network against central finite
+    differences (closed form of the derivative, relative error <= 1e-6)."""
+    from oracle import mlp
+
+    rng = np.random.default_rng(3)
+    p = rng.standard_normal(mlp.NPARAMS) * 0.1
+    x = rng.standard_normal((20, mlp.IN))
+    t = rng.standard_normal((20, mlp.OUT))
+    loss, g = mlp.loss_and_grad(p, x, t)
+    idx = np.concatenate([rng.choice(mlp.NPARAMS, 200, replace=False), [mlp.NPARAMS - 1, mlp.NPARAMS - 2]])
+    h = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (mlp.loss_and_grad(pp, x, t)[0] - mlp.loss_and_grad(pm, x, t)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(g[i])) + 1e-9, (i, fd, g[i])
+    assert mlp.NPARAMS == 29186
+
+
+def test_scheduler_features_special_case():
+    """Features: sketch bits as +1/-1 in bit order, log2(1 + bucket size) per table."""
+    from oracle import mlp
+
+    f = mlp.features(np.array([0b1011], dtype=np.uint64), np.array([[0, 1, 3, 7]]))
+    assert list(f[0, :5]) == [1.0, 1.0, -1.0, 1.0, -1.0]
+    assert np.all(f[0, 5:64] == -1.0)
+    assert list(f[0, 64:68]) == [0.0, 1.0, 2.0, 3.0]
+    assert np.all(f[0, 68:] == 0.0)
