@@ -10,8 +10,13 @@ memory budget 2 GiB (L = 108 tables of K = 24 bits, M = 32 sketches).
 The index is built once (its device time is reported as build_ms) and stays resident
 in HBM with the queries; one timed step answers the whole batch of queries: query
 normalisation, hashing, prefix ranges and the adaptive search kernel.
-Prints one JSON line.  The roofline entry is for the search kernel, whose average
-launch duration is measured with HIP events on the launch stream.
+Three query paths are timed on the same batch: the plain search (static query slots),
+the persistent batched search with a FIFO work queue, and the learned-batched search
+(work queue ordered longest-predicted-first by the scheduler network, trained first on
+traces of the plain method for other queries of the same distribution).  `value` is the
+learned-batched rate; the others are reported beside it.
+Prints one JSON line.  The roofline entry is for the search kernel in the learned-batched
+path, whose average launch duration is measured with HIP events on the launch stream.
 """
 from __future__ import annotations
 
@@ -110,6 +115,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--recall-sample", type=int, default=1000)
+    ap.add_argument("--paths", default="plain,batched_fifo,learned_batched",
+                    help="query paths to time (comma separated); the last one is the headline")
+    ap.add_argument("--train-frac", type=float, default=2.0,
+                    help="scheduler training queries as a multiple of the benchmark query count")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -145,22 +154,53 @@ def main():
     del Xd
     log(f"index built: L={info.L} device build {info.build_ms:.1f} ms")
 
-    for _ in range(args.warmup):
-        r = ix.search(Qd, k, recall, timing=True)
-    torch.cuda.synchronize()
-    search_ms, hash_ms, ranges_ms = [], [], []
+    # learned scheduler: traces of the plain method on training queries from the same
+    # distribution (their own seed), features, training on the GPU (not timed)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = ix.search(Qd, k, recall, timing=True)
-        tm = ix.last_timing()
-        search_ms.append(tm.search_ms)
-        hash_ms.append(tm.hash_ms)
-        ranges_ms.append(tm.ranges_ms)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall / args.steps * 1e3
-    qps = m / (ms_per_step / 1e3)
+    Qtr = workloads.queries_like(2, max(1, int(round(m * args.train_frac))), seed_offset=100)
+    rtr = ix.search(torch.from_numpy(Qtr).to(dev), k, recall)
+    st_tr = rtr.stats.cpu().numpy()
+    target = np.stack([st_tr[:, 0], np.log2(1.0 + st_tr[:, 1])], 1).astype(np.float32)
+    sched = pf.Scheduler(seed=1)
+    losses = sched.train(ix.features(torch.from_numpy(Qtr).to(dev)), torch.from_numpy(target).to(dev),
+                         epochs=20, batch=512, lr=2e-3)
+    ix.set_scheduler(sched)
+    train_s = time.perf_counter() - t0
+    log(f"scheduler trained on {len(Qtr)} traces in {train_s:.1f} s, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
 
+    ks_d = torch.full((m,), k, dtype=torch.int32, device=dev)
+    rec_d = torch.full((m,), recall, dtype=torch.float64, device=dev)
+    modes = {
+        "plain": lambda: ix.search(Qd, k, recall, timing=True),
+        "batched_fifo": lambda: ix.search_batch(Qd, ks_d, rec_d, k, timing=True),
+        "learned_batched": lambda: ix.search_batch(Qd, ks_d, rec_d, k, learned=True, timing=True),
+    }
+    ix.search_batch(Qd, ks_d, rec_d, k, autotune=True)  # pick the batched tile shape once
+    res = {}
+    wanted = [p for p in args.paths.split(",") if p]
+    for name in wanted:
+        fn = modes[name]
+        for _ in range(args.warmup):
+            r = fn()
+        torch.cuda.synchronize()
+        search_ms, hash_ms, ranges_ms = [], [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = fn()
+            tm = ix.last_timing()
+            search_ms.append(tm.search_ms)
+            hash_ms.append(tm.hash_ms)
+            ranges_ms.append(tm.ranges_ms)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[name] = dict(r=r, ms=wall / args.steps * 1e3, search_ms=search_ms, hash_ms=hash_ms,
+                         ranges_ms=ranges_ms, tile=tm.tile, waves=tm.waves_per_cu)
+        log(f"{name}: {res[name]['ms']:.3f} ms/step, search kernel {np.mean(search_ms):.3f} ms")
+    head = res[wanted[-1]]
+    r = head["r"]
+    ms_per_step = head["ms"]
+    qps = m / (ms_per_step / 1e3)
+    search_ms, hash_ms, ranges_ms = head["search_ms"], head["hash_ms"], head["ranges_ms"]
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
     stats = r.stats.cpu().numpy()
     ids = r.ids.cpu().numpy()
@@ -189,7 +229,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": c["name"], "n": n, "d": d, "queries": m, "k": k, "recall_target": recall,
                    "budget_bytes": budget, "L": info.L, "K": info.K, "M": info.M, "B": 12,
-                   "path": "plain GPU (one workgroup per query slot)"},
+                   "path": wanted[-1]},
+        "paths_qps": {name: m / (v["ms"] / 1e3) for name, v in res.items()},
+        "paths_search_kernel_ms": {name: float(np.mean(v["search_ms"])) for name, v in res.items()},
+        "learned_vs_plain": (res["learned_batched"]["ms"] and res["plain"]["ms"] / res["learned_batched"]["ms"])
+        if "plain" in res and "learned_batched" in res else None,
+        "batched_tile": {"tile": head["tile"], "waves_per_cu": head["waves"]},
+        "scheduler": {"train_queries": int(len(Qtr)), "train_s": train_s, "loss_first": float(losses[0]),
+                      "loss_last": float(losses[-1])},
         "recall_measured": rec,
         "recall_sample": ns,
         "build_ms": info.build_ms,

@@ -265,7 +265,8 @@ struct SearchK {
     const uint32_t *qcode;
     const uint64_t *qsk;
     const uint32_t *ranges;
-    int64_t m;
+    int64_t m;       // queries to answer (queue positions 0..m-1)
+    int64_t qstride; // row stride of qcode / qsk (the batch size they were computed for)
     const int32_t *ks;
     int32_t kconst, kmax;
     const int32_t *qtab; // per-query row of stopw (nullable: 0)
@@ -599,9 +600,9 @@ template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(Searc
         const float *stopw = p.stopw + (int64_t)(p.qtab ? p.qtab[q] : 0) * K * kTauCols;
         for (int c = lane; c < p.dpad; c += WV) l.qv[c] = p.Q[q * p.dpad + c];
         for (int32_t j = lane; j < L; j += WV) {
-            const uint32_t qc = p.qcode[(int64_t)j * p.m + q];
+            const uint32_t qc = p.qcode[(int64_t)j * p.qstride + q];
             l.qc[j] = qc;
-            l.tq[j] = p.qsk[(int64_t)(j % p.M) * p.m + q];
+            l.tq[j] = p.qsk[(int64_t)(j % p.M) * p.qstride + q];
             uint32_t lo, hi;
             level_range(p, j, K, qc, q, lo, hi);
             l.clo[j] = lo;
@@ -816,6 +817,7 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     p.qsk = a.qsk;
     p.ranges = ranges;
     p.m = a.m;
+    p.qstride = a.qstride > 0 ? a.qstride : a.m;
     p.ks = a.ks;
     p.kconst = a.kconst;
     p.kmax = a.kmax;

@@ -360,7 +360,8 @@ static TuneChoice cached_tuning(Index &ix, int32_t kmax) {
 static TuneChoice autotune(Index &ix, SearchArgs a, int32_t kmax, hipStream_t s) {
     const std::string key = tune_key(ix, kmax);
     const int64_t sample = std::min<int64_t>(a.m, 8192);
-    a.m = sample; // the first queries of the batch (in queue order)
+    a.qstride = a.m; // query codes were computed for the whole batch
+    a.m = sample;    // time the first queries of the batch (in queue order)
     TuneChoice best;
     best.us_per_query = 1e300;
     hipEvent_t e0, e1;
@@ -369,7 +370,7 @@ static TuneChoice autotune(Index &ix, SearchArgs a, int32_t kmax, hipStream_t s)
     const int32_t nl = ix.K - ix.P;
     for (int32_t t = 0; t < search_tile_count(); ++t) {
         const int32_t wmax = search_waves_per_cu(ix, kmax, t);
-        for (int32_t w : {wmax, std::max(1, wmax / 2)}) {
+        for (int32_t w : {wmax, std::max(1, (3 * wmax) / 4), std::max(1, wmax / 2)}) {
             a.tile = t;
             a.waves_per_cu = w;
             launch_search(ix, a, nl > 0 ? ix.ranges.as<uint32_t>() : nullptr, s); // warm-up
@@ -514,6 +515,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     a.qcode = qcode;
     a.qsk = qsk;
     a.m = m;
+    a.qstride = m;
     a.ks = ks ? dks.as<int32_t>() : nullptr;
     a.kconst = kconst;
     a.kmax = kmax;

@@ -153,6 +153,7 @@ struct SearchArgs {
     const uint32_t *qcode; // L x m
     const uint64_t *qsk;   // M x m
     int64_t m;
+    int64_t qstride;       // row stride of qcode / qsk (0 = m)
     const int32_t *ks;     // per-query k (nullable: kconst)
     int32_t kconst, kmax;
     const int32_t *qtab;   // per-query row of stopw (nullable: row 0)

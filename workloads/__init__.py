@@ -125,7 +125,7 @@ def paper_synthetic(n: int, d: int, m: int, seed: int):
 
 
 # ------------------------------------------------------------------ the five configurations
-def config(c: int, scale: float = 1.0, sigma_mode: str = "coord"):
+def config(c: int, scale: float = 1.0, sigma_mode: str = "coord", query_seed_offset: int = 0):
     """Points, queries and parameters of configuration c (1..5).
 
     scale < 1 shrinks n and the query count (for quick tests); sizes otherwise as
@@ -136,13 +136,14 @@ def config(c: int, scale: float = 1.0, sigma_mode: str = "coord"):
 
     if c == 1:
         n, d, m = sz(10_000), 64, sz(1_000)
-        return dict(points=gaussian_unit(n, d, DATA_SEED + 1), queries=gaussian_unit(m, d, QUERY_SEED + 1),
+        return dict(points=gaussian_unit(n, d, DATA_SEED + 1),
+                    queries=gaussian_unit(m, d, QUERY_SEED + 1 + query_seed_offset),
                     k=10, recall=0.9, budget=64 << 20, name="gauss-10k-d64")
     if c == 2:
         n, d, m = sz(1_000_000), 100, sz(10_000)
         cen = mixture_centers(10_000, d, CENTER_SEED + 2)
         return dict(points=mixture(n, d, cen, 0.3, DATA_SEED + 2, sigma_mode),
-                    queries=mixture(m, d, cen, 0.3, QUERY_SEED + 2, sigma_mode),
+                    queries=mixture(m, d, cen, 0.3, QUERY_SEED + 2 + query_seed_offset, sigma_mode),
                     k=10, recall=0.9, budget=2 << 30, name="mixture-1M-d100")
     if c == 3:
         n, d = sz(1_000_000), 256
@@ -172,3 +173,18 @@ def config(c: int, scale: float = 1.0, sigma_mode: str = "coord"):
                     queries=mixture(sz(100_000), d, cen, 0.3, QUERY_SEED + 50, sigma_mode),
                     k=10, recall=0.9, budget=16 << 30, name="mixture-10M-d128")
     raise ValueError(c)
+
+
+def queries_like(c: int, m: int, seed_offset: int = 100, sigma_mode: str = "coord") -> np.ndarray:
+    """m further queries of configuration c's query distribution (configs 1, 2, 5), drawn
+    with their own seed (query seed + seed_offset); used as training traces."""
+    if c == 1:
+        return gaussian_unit(m, 64, QUERY_SEED + 1 + seed_offset)
+    if c == 2:
+        cen = mixture_centers(10_000, 100, CENTER_SEED + 2)
+        return mixture(m, 100, cen, 0.3, QUERY_SEED + 2 + seed_offset, sigma_mode)
+    if c == 5:
+        cen = mixture_centers(100_000, 128, CENTER_SEED + 5)
+        return mixture(m, 128, cen, 0.3, QUERY_SEED + 5 + seed_offset, sigma_mode)
+    raise ValueError(c)
+
