@@ -10,11 +10,12 @@ memory budget 2 GiB (L = 108 tables of K = 24 bits, M = 32 sketches).
 The index is built once (its device time is reported as build_ms) and stays resident
 in HBM with the queries; one timed step answers the whole batch of queries: query
 normalisation, hashing, prefix ranges and the adaptive search kernel.
-Three query paths are timed on the same batch: the plain search (static query slots),
-the persistent batched search with a FIFO work queue, and the learned-batched search
-(work queue ordered longest-predicted-first by the scheduler network, trained first on
-traces of the plain method for other queries of the same distribution).  `value` is the
-learned-batched rate; the others are reported beside it.
+Four query paths are timed on the same batch: the plain search (static query slots),
+the persistent batched search with a FIFO work queue (with every re-ranked vector read
+from both 16-bit planes, and with the upper-plane bound first), and the learned-batched
+search (work queue ordered longest-predicted-first by the scheduler network, trained
+first on traces of the plain method for other queries of the same distribution).
+`value` is the learned-batched rate; the others are reported beside it.
 Prints one JSON line.  The roofline entry is for the search kernel in the learned-batched
 path, whose average launch duration is measured with HIP events on the launch stream.
 """
@@ -43,12 +44,13 @@ SEARCH_SRC = os.path.join(ROOT, "paper_1906_12211_amd", "csrc", "k_search.hip")
 
 def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> float:
     """Bytes the method must move for the queries of one launch of the search kernel:
-    8 B per scanned table-local sketch, 4 B per position of a passing entry, 4d B per
-    re-ranked vector, the query (4d) and its result (8k), and the two range bounds
-    (8 B) of every table at every visited level."""
+    8 B per scanned table-local sketch, 4 B per position of a passing entry, the upper
+    16-bit plane (2d B) of every re-ranked vector and the lower plane (2d B) of those
+    whose exact inner product was needed, the query (4d) and its result (8k), and the
+    two range bounds (8 B) of every table at every visited level."""
     stop = stats[:, 0].astype(np.float64)
-    per_q = (8.0 * stats[:, 1] + 4.0 * stats[:, 2] + 4.0 * d * stats[:, 3] + 4.0 * d + 8.0 * k
-             + 8.0 * L * (K + 1 - np.maximum(stop, 1)))
+    per_q = (8.0 * stats[:, 1] + 4.0 * stats[:, 2] + 2.0 * d * (stats[:, 3] + stats[:, 4]) + 4.0 * d
+             + 8.0 * k + 8.0 * L * (K + 1 - np.maximum(stop, 1)))
     return float(per_q.sum())
 
 
@@ -115,7 +117,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--recall-sample", type=int, default=1000)
-    ap.add_argument("--paths", default="plain,batched_fifo,learned_batched",
+    ap.add_argument("--paths", default="plain,batched_fifo_both_planes,batched_fifo,learned_batched",
                     help="query paths to time (comma separated); the last one is the headline")
     ap.add_argument("--train-frac", type=float, default=2.0,
                     help="scheduler training queries as a multiple of the benchmark query count")
@@ -173,6 +175,7 @@ def main():
     modes = {
         "plain": lambda: ix.search(Qd, k, recall, timing=True),
         "batched_fifo": lambda: ix.search_batch(Qd, ks_d, rec_d, k, timing=True),
+        "batched_fifo_both_planes": lambda: ix.search_batch(Qd, ks_d, rec_d, k, timing=True, prefilter=False),
         "learned_batched": lambda: ix.search_batch(Qd, ks_d, rec_d, k, learned=True, timing=True),
     }
     ix.search_batch(Qd, ks_d, rec_d, k, autotune=True)  # pick the batched tile shape once
@@ -244,7 +247,7 @@ def main():
                      "search": avg_search_ms},
         "stop_level_hist": np.bincount(stats[:, 0], minlength=info.K + 1).tolist(),
         "mean_counts": {"c_scan": float(stats[:, 1].mean()), "c_pass": float(stats[:, 2].mean()),
-                        "c_rerank": float(stats[:, 3].mean())},
+                        "c_rerank": float(stats[:, 3].mean()), "c_exact": float(stats[:, 4].mean())},
         "roofline": {"kernel": "k_search", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
                      "algorithmic_bytes_per_launch": A, "avg_launch_ms": avg_search_ms},

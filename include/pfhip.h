@@ -77,6 +77,9 @@ typedef struct {
     int32_t rule;      /* PF_RULE_FILTER (default), PF_RULE_EXACT or PF_RULE_ALG1       */
     int32_t no_filter; /* 1: sketch filter off (every retrieved candidate re-ranked)   */
     int32_t timing;    /* 1: record per-kernel durations of this call (pf_last_timing) */
+    int32_t no_prefilter; /* 1: compute every re-ranked inner product from both 16-bit
+                             planes (the upper-plane bound rules nothing out); results
+                             are the same either way, only the bytes read differ       */
 } pf_search_opts;
 
 typedef struct {
@@ -84,7 +87,11 @@ typedef struct {
     int32_t reserved;
     int64_t c_scan;   /* entries taken from the sorted arrays                        */
     int64_t c_pass;   /* entries that passed the sketch filter (with multiplicity)   */
-    int64_t c_rerank; /* distinct points whose inner product was computed            */
+    int64_t c_rerank; /* candidates re-ranked (with multiplicity; + n at a linear scan) */
+    int64_t c_exact;  /* of those, the ones whose exact FP32 inner product was needed:
+                         the rest were ruled out by the bound from the upper 16-bit
+                         plane alone (not part of the method's definition; depends on
+                         the order in which the kernel met the candidates)              */
 } pf_query_stats;
 
 typedef struct {

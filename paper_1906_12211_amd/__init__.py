@@ -48,12 +48,13 @@ class pf_build_opts(ctypes.Structure):
 
 class pf_search_opts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("B", ctypes.c_int32), ("rule", ctypes.c_int32),
-                ("no_filter", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("no_filter", ctypes.c_int32), ("timing", ctypes.c_int32), ("no_prefilter", ctypes.c_int32)]
 
 
 class pf_query_stats(ctypes.Structure):
     _fields_ = [("stop_level", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("c_scan", ctypes.c_int64), ("c_pass", ctypes.c_int64), ("c_rerank", ctypes.c_int64)]
+                ("c_scan", ctypes.c_int64), ("c_pass", ctypes.c_int64), ("c_rerank", ctypes.c_int64),
+                ("c_exact", ctypes.c_int64)]
 
 
 class pf_info(ctypes.Structure):
@@ -197,7 +198,7 @@ def pf_normalize(x):
 class SearchResult:
     ids: object
     ips: object
-    stats: object  # (m, 4) int64: stop_level, c_scan, c_pass, c_rerank
+    stats: object  # (m, 5) int64: stop_level, c_scan, c_pass, c_rerank, c_exact
 
     @property
     def stop_level(self):
@@ -205,7 +206,7 @@ class SearchResult:
 
 
 def _stats_view(raw):
-    """pf_query_stats array (m x 32 bytes) as (m, 4) int64 columns."""
+    """pf_query_stats array (m x 40 bytes) as (m, 5) int64 columns."""
     if _is_torch(raw):
         s = raw.clone()
         s[:, 0] = s[:, 0] & 0xFFFFFFFF
@@ -254,13 +255,13 @@ class Index:
 
     def search(self, queries, k: int, recall: float, eps: float = 0.0, B: int = 12,
                rule: int = PF_RULE_FILTER, filter: bool = True, timing: bool = False,
-               want_ips: bool = True, want_stats: bool = True) -> SearchResult:
+               want_ips: bool = True, want_stats: bool = True, prefilter: bool = True) -> SearchResult:
         q = _f32(queries)
         m = q.shape[0]
         ids = _empty_like_input(q, (m, k), np.int32, _torch_dtype("int32"))
         ips = _empty_like_input(q, (m, k), np.float32, _torch_dtype("float32")) if want_ips else None
-        st = _empty_like_input(q, (m, 4), np.int64, _torch_dtype("int64")) if want_stats else None
-        opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0)
+        st = _empty_like_input(q, (m, 5), np.int64, _torch_dtype("int64")) if want_stats else None
+        opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1)
         pq, mem, stream = _buf(q)
         _check(lib().pf_search_ex(self._h, pq, m, k, recall, ctypes.byref(opts), _buf(ids)[0],
                                   _buf(ips)[0], _buf(st)[0], mem, stream))
@@ -268,7 +269,7 @@ class Index:
 
     def search_batch(self, queries, ks, recalls, kmax: int, order=None, learned: bool = False,
                      autotune: bool = False, eps: float = 0.0, B: int = 12, rule: int = PF_RULE_FILTER,
-                     filter: bool = True, timing: bool = False) -> SearchResult:
+                     filter: bool = True, timing: bool = False, prefilter: bool = True) -> SearchResult:
         """One persistent launch over all queries with per-query k and recall (work queue)."""
         q = _f32(queries)
         m = q.shape[0]
@@ -288,8 +289,8 @@ class Index:
         ord_a = arr(order, np.int32, "int32")
         ids = _empty_like_input(q, (m, kmax), np.int32, _torch_dtype("int32"))
         ips = _empty_like_input(q, (m, kmax), np.float32, _torch_dtype("float32"))
-        st = _empty_like_input(q, (m, 4), np.int64, _torch_dtype("int64"))
-        opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0)
+        st = _empty_like_input(q, (m, 5), np.int64, _torch_dtype("int64"))
+        opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1)
         flags = (PF_BATCH_LEARNED if learned else 0) | (PF_BATCH_AUTOTUNE if autotune else 0)
         pq, mem, stream = _buf(q)
         _check(lib().pf_search_batch(self._h, pq, m, _buf(ks_a)[0], _buf(rec_a)[0], kmax, ctypes.byref(opts),

@@ -51,4 +51,39 @@ void launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s) {
     PF_HIP(hipGetLastError());
 }
 
+// Vector storage as two 16-bit planes: hi[i] = upper half of the FP32 bit pattern of
+// X[i] (X[i] truncated to bfloat16), lo[i] = lower half; (hi << 16) | lo is X[i] exactly.
+__global__ __launch_bounds__(256) void k_split_planes(const uint32_t *__restrict__ X, int64_t count,
+                                                      uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stride) {
+        const uint32_t v = X[t];
+        hi[t] = (uint16_t)(v >> 16);
+        lo[t] = (uint16_t)(v & 0xFFFFu);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_join_planes(const uint16_t *__restrict__ hi, const uint16_t *__restrict__ lo,
+                                                     int64_t count, uint32_t *__restrict__ X) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stride)
+        X[t] = ((uint32_t)hi[t] << 16) | (uint32_t)lo[t];
+}
+
+void launch_split_planes(const float *X, int64_t count, uint16_t *hi, uint16_t *lo, hipStream_t s) {
+    if (count <= 0) return;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_split_planes, dim3((unsigned)blocks), dim3(256), 0, s,
+                       reinterpret_cast<const uint32_t *>(X), count, hi, lo);
+    PF_HIP(hipGetLastError());
+}
+
+void launch_join_planes(const uint16_t *hi, const uint16_t *lo, int64_t count, float *X, hipStream_t s) {
+    if (count <= 0) return;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_join_planes, dim3((unsigned)blocks), dim3(256), 0, s, hi, lo, count,
+                       reinterpret_cast<uint32_t *>(X));
+    PF_HIP(hipGetLastError());
+}
+
 } // namespace pf

@@ -256,7 +256,9 @@ static constexpr int kMaxPCAP = WV * 16 + 64;
 static constexpr int kCW = 256;
 
 struct SearchK {
-    const float *X;
+    const uint16_t *Xh, *Xl; // upper / lower 16-bit planes of the n x dpad FP32 vectors
+    float rr_slack;          // rounding allowance of the upper-plane bound
+    int32_t prefilter;
     const uint32_t *tidx, *off;
     const uint64_t *tsk;
     int64_t n;
@@ -316,36 +318,42 @@ struct WLds {
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t search_lds_layout(int L, int kmax, int dpad, WLds *o, void *base) {
-    size_t off = 0;
-    char *b = static_cast<char *>(base);
+// Byte offsets of the wave's LDS arrays in the dynamic shared memory block.
+struct LdsOff {
+    uint32_t top, ntop, cand, tq, pending, clo, chi, qc, segBeg, segStart, qv, total;
+};
+
+__host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad) {
+    LdsOff o;
+    uint32_t off = 0;
     auto take = [&](size_t bytes) {
-        char *p = b ? b + off : nullptr;
-        off = align16(off + bytes);
-        return p;
+        const uint32_t at = off;
+        off = (uint32_t)align16(off + bytes);
+        return at;
     };
-    WLds l;
-    l.top = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * kmax));
-    l.ntop = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * kmax));
-    l.cand = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * kCW));
-    l.tq = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * L));
-    l.pending = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * kMaxPCAP));
-    l.clo = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * L));
-    l.chi = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * L));
-    l.qc = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * L));
-    l.segBeg = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * 2 * L));
-    l.segStart = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * (2 * L + 1)));
-    l.qv = reinterpret_cast<float *>(take(sizeof(float) * dpad));
-    if (o) *o = l;
-    return off;
+    o.top = take(sizeof(unsigned long long) * kmax);
+    o.ntop = take(sizeof(unsigned long long) * kmax);
+    o.cand = take(sizeof(unsigned long long) * kCW);
+    o.tq = take(sizeof(unsigned long long) * L);
+    o.pending = take(sizeof(uint32_t) * kMaxPCAP);
+    o.clo = take(sizeof(uint32_t) * L);
+    o.chi = take(sizeof(uint32_t) * L);
+    o.qc = take(sizeof(uint32_t) * L);
+    o.segBeg = take(sizeof(uint32_t) * 2 * L);
+    o.segStart = take(sizeof(uint32_t) * (2 * L + 1));
+    o.qv = take(sizeof(float) * dpad);
+    o.total = off;
+    return o;
 }
+
+inline size_t search_lds_bytes(int L, int kmax, int dpad) { return search_lds_offsets(L, kmax, dpad).total; }
 
 // Per-query state kept in registers; every lane holds the same (wave-uniform) values.
 struct QState {
     int k;
     int pend, cand, top;
     unsigned long long thr;
-    long long c_scan, c_pass, c_rerank;
+    long long c_scan, c_pass, c_rerank, c_exact;
 };
 
 // top <- best k distinct points of top u cand[0..cand) (the accumulator's flush; cand
@@ -421,6 +429,20 @@ __device__ void wave_merge(WLds &l, QState &st) {
     st.thr = (newc == k) ? l.top[k - 1] : 0ull;
 }
 
+// Element values of a row from its two planes: lane-local 4-element group, upper
+// halves h, lower halves w, two elements per 32-bit word (element 2j in the low half).
+__device__ __forceinline__ float4 join4(uint2 h, uint2 w) {
+    return make_float4(__uint_as_float((h.x << 16) | (w.x & 0xFFFFu)), __uint_as_float((h.x & 0xFFFF0000u) | (w.x >> 16)),
+                       __uint_as_float((h.y << 16) | (w.y & 0xFFFFu)), __uint_as_float((h.y & 0xFFFF0000u) | (w.y >> 16)));
+}
+__device__ __forceinline__ float4 upper4(uint2 h) {
+    return make_float4(__uint_as_float(h.x << 16), __uint_as_float(h.x & 0xFFFF0000u), __uint_as_float(h.y << 16),
+                       __uint_as_float(h.y & 0xFFFF0000u));
+}
+__device__ __forceinline__ uint2 ld4(const uint16_t *__restrict__ plane, uint32_t id, int32_t dpad, int base) {
+    return *reinterpret_cast<const uint2 *>(plane + (int64_t)id * dpad + base);
+}
+
 // Inner products of up to U rows per 16-lane group in the fixed FP32 order: lane r sums
 // the products of the elements 64 t + 4 r + c in increasing order with no fused
 // multiply-add; the sixteen partial sums are combined by s_r + s_{r^8}, then ^4, ^2, ^1.
@@ -428,21 +450,23 @@ __device__ void wave_merge(WLds &l, QState &st) {
 // DT > 0: rows of at most 64 DT floats, every load of the group issued before any use;
 // DT = 0: any length, one 64-float chunk at a time.
 template <int DT, int U>
-__device__ __forceinline__ void dot_rows(const float *__restrict__ X, int32_t dpad, const float *qv,
-                                         const uint32_t *ids, int cnt, int r, float *out) {
+__device__ __forceinline__ void dot_rows(const SearchK &p, const float *qv, const uint32_t *ids, int cnt, int r,
+                                         float *out) {
+    const int32_t dpad = p.dpad;
     float acc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[u] = 0.0f;
     if constexpr (DT > 0) {
-        float4 xv[U][DT];
+        uint2 hv[U][DT], wv[U][DT];
 #pragma unroll
         for (int t = 0; t < DT; ++t) {
             const int base = 64 * t + 4 * r;
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                xv[u][t] = (u < cnt && base < dpad)
-                               ? *reinterpret_cast<const float4 *>(X + (int64_t)ids[u] * dpad + base)
-                               : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int u = 0; u < U; ++u) {
+                const bool ok = u < cnt && base < dpad;
+                hv[u][t] = ok ? ld4(p.Xh, ids[u], dpad, base) : make_uint2(0u, 0u);
+                wv[u][t] = ok ? ld4(p.Xl, ids[u], dpad, base) : make_uint2(0u, 0u);
+            }
         }
 #pragma unroll
         for (int t = 0; t < DT; ++t) {
@@ -451,26 +475,29 @@ __device__ __forceinline__ void dot_rows(const float *__restrict__ X, int32_t dp
                                           : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                acc[u] = acc[u] + xv[u][t].x * qq.x;
-                acc[u] = acc[u] + xv[u][t].y * qq.y;
-                acc[u] = acc[u] + xv[u][t].z * qq.z;
-                acc[u] = acc[u] + xv[u][t].w * qq.w;
+                const float4 xv = join4(hv[u][t], wv[u][t]);
+                acc[u] = acc[u] + xv.x * qq.x;
+                acc[u] = acc[u] + xv.y * qq.y;
+                acc[u] = acc[u] + xv.z * qq.z;
+                acc[u] = acc[u] + xv.w * qq.w;
             }
         }
     } else {
         for (int base = 4 * r; base < dpad; base += 64) {
             const float4 qq = *reinterpret_cast<const float4 *>(qv + base);
-            float4 xv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                xv[u] = u < cnt ? *reinterpret_cast<const float4 *>(X + (int64_t)ids[u] * dpad + base)
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
+            uint2 hv[U], wv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                acc[u] = acc[u] + xv[u].x * qq.x;
-                acc[u] = acc[u] + xv[u].y * qq.y;
-                acc[u] = acc[u] + xv[u].z * qq.z;
-                acc[u] = acc[u] + xv[u].w * qq.w;
+                hv[u] = u < cnt ? ld4(p.Xh, ids[u], dpad, base) : make_uint2(0u, 0u);
+                wv[u] = u < cnt ? ld4(p.Xl, ids[u], dpad, base) : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float4 xv = join4(hv[u], wv[u]);
+                acc[u] = acc[u] + xv.x * qq.x;
+                acc[u] = acc[u] + xv.y * qq.y;
+                acc[u] = acc[u] + xv.z * qq.z;
+                acc[u] = acc[u] + xv.w * qq.w;
             }
         }
     }
@@ -485,13 +512,109 @@ __device__ __forceinline__ void dot_rows(const float *__restrict__ X, int32_t dp
     }
 }
 
+// Upper bounds of the exact inner products of up to U rows per 16-lane group from the
+// upper plane alone.  The upper half of an FP32 pattern is the value truncated to 8
+// significant bits, so |x_i - hi_i| <= 2^-7 |hi_i| (hi_i normal; a zero or subnormal
+// hi_i leaves less than 2^-126), hence
+//   <x, q> <= sum_i hi_i q_i + 2^-7 sum_i |hi_i q_i| + d 2^-126.
+// The exact value the kernel would compute (FP32, fixed order) differs from <x, q> by
+// at most gamma_(chain) sum |x_i q_i|, and the two FP32 sums below by as much again;
+// with unit vectors these and the d 2^-126 term are inside rr_slack, and the relative
+// rounding of the second sum inside the added 2^-20.
+template <int DT, int U>
+__device__ __forceinline__ void bound_rows(const SearchK &p, const float *qv, const uint32_t *ids, int cnt, int r,
+                                           float *ub) {
+    const int32_t dpad = p.dpad;
+    float acc[U], mag[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = mag[u] = 0.0f;
+    if constexpr (DT > 0) {
+        uint2 hv[U][DT];
+#pragma unroll
+        for (int t = 0; t < DT; ++t) {
+            const int base = 64 * t + 4 * r;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                hv[u][t] = (u < cnt && base < dpad) ? ld4(p.Xh, ids[u], dpad, base) : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int t = 0; t < DT; ++t) {
+            const int base = 64 * t + 4 * r;
+            const float4 qq = base < dpad ? *reinterpret_cast<const float4 *>(qv + base)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float4 xv = upper4(hv[u][t]);
+                const float a = xv.x * qq.x, b = xv.y * qq.y, c = xv.z * qq.z, e = xv.w * qq.w;
+                acc[u] = acc[u] + ((a + b) + (c + e));
+                mag[u] = mag[u] + ((fabsf(a) + fabsf(b)) + (fabsf(c) + fabsf(e)));
+            }
+        }
+    } else {
+        for (int base = 4 * r; base < dpad; base += 64) {
+            const float4 qq = *reinterpret_cast<const float4 *>(qv + base);
+            uint2 hv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) hv[u] = u < cnt ? ld4(p.Xh, ids[u], dpad, base) : make_uint2(0u, 0u);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float4 xv = upper4(hv[u]);
+                const float a = xv.x * qq.x, b = xv.y * qq.y, c = xv.z * qq.z, e = xv.w * qq.w;
+                acc[u] = acc[u] + ((a + b) + (c + e));
+                mag[u] = mag[u] + ((fabsf(a) + fabsf(b)) + (fabsf(c) + fabsf(e)));
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        float s = acc[u], g = mag[u];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            s = s + __shfl_xor(s, o, 16);
+            g = g + __shfl_xor(g, o, 16);
+        }
+        ub[u] = s + g * (0.0078125f + 9.5367431640625e-07f) + p.rr_slack;
+    }
+}
+
 // Re-rank rows ids[0..rc); candidates better than the current k-th enter the buffer,
-// which is merged into the top-k whenever it could overflow.
+// which is merged into the top-k whenever it could overflow.  Once the top-k is full,
+// a first pass over the upper plane drops every row whose bound is below the k-th inner
+// product (it could not enter the top-k) and compacts the rest, in order, to the front
+// of ids; only those are read from both planes.
 template <int DT, class TL>
-__device__ void wave_rerank(const SearchK &p, WLds &l, const uint32_t *ids, int rc, QState &st) {
+__device__ void wave_rerank(const SearchK &p, WLds &l, uint32_t *ids, int rc, QState &st) {
     constexpr int U = TL::U, RROWS = TL::RROWS, CW = TL::CW;
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
     const uint64_t lt = lanemask_lt(lane);
+    if (p.prefilter && st.top == st.k) {
+        const float ipk = key_ip(st.thr);
+        int w = 0;
+        for (int t0 = 0; t0 < rc; t0 += RROWS) {
+            const int first = t0 + g * U;
+            const int cnt = max(0, min(U, rc - first));
+            uint32_t x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = u < cnt ? ids[first + u] : 0u;
+            float ub[U];
+            bound_rows<DT, U>(p, l.qv, x, cnt, r, ub);
+            bool keep = false;
+            uint32_t myx = x[0];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (r == u) {
+                    keep = u < cnt && ub[u] >= ipk;
+                    myx = x[u];
+                }
+            const uint64_t mk = __ballot(keep);
+            wsync();
+            if (keep) ids[w + __popcll(mk & lt)] = myx;
+            w += __popcll(mk);
+            wsync();
+        }
+        rc = w;
+    }
+    st.c_exact += rc;
     for (int t0 = 0; t0 < rc; t0 += RROWS) {
         const int first = t0 + g * U;
         const int cnt = max(0, min(U, rc - first));
@@ -499,7 +622,7 @@ __device__ void wave_rerank(const SearchK &p, WLds &l, const uint32_t *ids, int 
 #pragma unroll
         for (int u = 0; u < U; ++u) x[u] = u < cnt ? ids[first + u] : 0u;
         float ip[U];
-        dot_rows<DT, U>(p.X, p.dpad, l.qv, x, cnt, r, ip);
+        dot_rows<DT, U>(p, l.qv, x, cnt, r, ip);
         bool emit = false;
         unsigned long long key = 0;
         if (r < cnt) {
@@ -580,8 +703,23 @@ __device__ void wave_scan_incl(uint32_t *a, int N) {
 template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(SearchK p) {
     constexpr int EPT = TL::EPT, WCH = TL::WCH, RB = TL::RB, PCAP = TL::PCAP;
     extern __shared__ __align__(16) unsigned char smem[];
+    // every pointer below is derived from smem by a constant-free offset only, so the
+    // compiler keeps them in the LDS address space (ds_read / ds_write, counted by
+    // lgkmcnt alone); a generic pointer would turn each LDS access into a flat access
+    // that also waits for every global load in flight
+    const LdsOff lo_ = search_lds_offsets(p.L, p.kmax, p.dpad);
     WLds l;
-    search_lds_layout(p.L, p.kmax, p.dpad, &l, smem);
+    l.top = reinterpret_cast<unsigned long long *>(smem + lo_.top);
+    l.ntop = reinterpret_cast<unsigned long long *>(smem + lo_.ntop);
+    l.cand = reinterpret_cast<unsigned long long *>(smem + lo_.cand);
+    l.tq = reinterpret_cast<unsigned long long *>(smem + lo_.tq);
+    l.pending = reinterpret_cast<uint32_t *>(smem + lo_.pending);
+    l.clo = reinterpret_cast<uint32_t *>(smem + lo_.clo);
+    l.chi = reinterpret_cast<uint32_t *>(smem + lo_.chi);
+    l.qc = reinterpret_cast<uint32_t *>(smem + lo_.qc);
+    l.segBeg = reinterpret_cast<uint32_t *>(smem + lo_.segBeg);
+    l.segStart = reinterpret_cast<uint32_t *>(smem + lo_.segStart);
+    l.qv = reinterpret_cast<float *>(smem + lo_.qv);
     const int lane = threadIdx.x;
     const uint64_t lt = lanemask_lt(lane);
     const int32_t L = p.L, K = p.K;
@@ -596,7 +734,7 @@ template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(Searc
         st.k = p.ks ? max(1, min(p.ks[q], p.kmax)) : p.kconst;
         st.pend = st.cand = st.top = 0;
         st.thr = 0;
-        st.c_scan = st.c_pass = st.c_rerank = 0;
+        st.c_scan = st.c_pass = st.c_rerank = st.c_exact = 0;
         const float *stopw = p.stopw + (int64_t)(p.qtab ? p.qtab[q] : 0) * K * kTauCols;
         for (int c = lane; c < p.dpad; c += WV) l.qv[c] = p.Q[q * p.dpad + c];
         for (int32_t j = lane; j < L; j += WV) {
@@ -645,6 +783,9 @@ template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(Searc
                 uint32_t xv[EPT];
                 int32_t tj[EPT];
                 uint64_t skv[EPT];
+                // sketches and positions of the chunk's entries, all loads in flight together
+                // (a position load made to wait for its sketch test costs a second memory
+                // round trip per chunk, more than the position bytes it saves)
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
                     const uint32_t f = base + u * WV + lane;
@@ -684,13 +825,9 @@ template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(Searc
                 const float ipk = key_ip(l.top[st.k - 1]);
                 stop = ipk >= stopw[(i - 1) * kTauCols + (tau + 1)];
                 if (!stop && p.filter) {
-                    int T = -1;
-                    for (int h = 64; h >= 0; --h)
-                        if (ipk <= p.tauv[h]) {
-                            T = h;
-                            break;
-                        }
-                    tau = T;
+                    // largest h with ipk <= tauv[h] (-1 if none): lanes test h = lane, one load each
+                    const uint64_t mk = __ballot(ipk <= p.tauv[lane]);
+                    tau = (ipk <= p.tauv[64]) ? 64 : (mk ? 63 - __clzll((long long)mk) : -1);
                 }
             }
             if (stop) {
@@ -730,6 +867,7 @@ template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(Searc
             s.c_scan = st.c_scan;
             s.c_pass = st.c_pass;
             s.c_rerank = st.c_rerank;
+            s.c_exact = st.c_exact;
             p.stats[q] = s;
         }
         wsync();
@@ -778,7 +916,7 @@ const char *search_tile_name(int32_t t) { return (t >= 0 && t < kNumTiles) ? kTi
 // resident query waves per CU for a tile shape (occupancy from registers and LDS)
 int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile) {
     int per_cu = 0;
-    const size_t lds = search_lds_layout(ix.L, kmax, ix.dpad, nullptr, nullptr);
+    const size_t lds = search_lds_bytes(ix.L, kmax, ix.dpad);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel(row_chunks(ix.dpad), tile), WV, lds) !=
             hipSuccess ||
         per_cu < 1)
@@ -792,7 +930,7 @@ int64_t search_slots(const Index &ix, int64_t m) {
 
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s) {
     if (a.m <= 0) return;
-    const size_t lds = search_lds_layout(ix.L, a.kmax, ix.dpad, nullptr, nullptr);
+    const size_t lds = search_lds_bytes(ix.L, a.kmax, ix.dpad);
     const int dt = row_chunks(ix.dpad);
     const int tile = (a.tile >= 0 && a.tile < kNumTiles) ? a.tile : 0;
     const void *fn = search_kernel(dt, tile);
@@ -801,7 +939,12 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     if (a.waves_per_cu > 0) per_cu = std::min(per_cu, a.waves_per_cu);
     const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(a.m, (int64_t)ix.num_cus * per_cu));
     SearchK p;
-    p.X = ix.X.as<float>();
+    p.Xh = ix.Xh.as<uint16_t>();
+    p.Xl = ix.Xl.as<uint16_t>();
+    p.prefilter = a.prefilter;
+    // twice the rounding of the FP32 sums (chains of at most dpad/16 + 4 additions, unit
+    // vectors) plus the d 2^-126 of subnormal upper halves, with room to spare
+    p.rr_slack = (float)((double)(ix.dpad / 16 + 16) * std::ldexp(1.0, -21));
     p.tidx = ix.tidx.as<uint32_t>();
     p.off = ix.off.as<uint32_t>();
     p.tsk = ix.tsk.as<uint64_t>();

@@ -238,9 +238,10 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         PF_HIP(hipEventCreate(&e0));
         PF_HIP(hipEventCreate(&e1));
         PF_HIP(hipEventRecord(e0, s));
-        // a1: normalised vectors
-        ix->X.alloc((size_t)n * ix->dpad * sizeof(float));
-        normalize_into(points, n, d, mem, ix->X.as<float>(), ix->dpad, ix->tmp, ix->flags, s);
+        // a1: normalised vectors (FP32 while the index is built, then two 16-bit planes)
+        DevBuf X;
+        X.alloc((size_t)n * ix->dpad * sizeof(float));
+        normalize_into(points, n, d, mem, X.as<float>(), ix->dpad, ix->tmp, ix->flags, s);
         ix->tmp.release();
         // a3: hyperplanes (host generator), device copies and hash plan
         const int64_t rows = L * K + 64ll * M;
@@ -253,7 +254,10 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         DevBuf codes, sk, scratch;
         codes.alloc((size_t)L * n * sizeof(uint32_t));
         sk.alloc((size_t)M * n * sizeof(uint64_t));
-        hash_rows(*ix, ix->X.as<float>(), n, codes.as<uint32_t>(), sk.as<uint64_t>(), scratch, s);
+        hash_rows(*ix, X.as<float>(), n, codes.as<uint32_t>(), sk.as<uint64_t>(), scratch, s);
+        ix->Xh.alloc((size_t)n * ix->dpad * sizeof(uint16_t));
+        ix->Xl.alloc((size_t)n * ix->dpad * sizeof(uint16_t));
+        launch_split_planes(X.as<float>(), n * ix->dpad, ix->Xh.as<uint16_t>(), ix->Xl.as<uint16_t>(), s);
         // a6: sorted tables
         ix->tcode.alloc((size_t)L * n * sizeof(uint32_t));
         ix->tidx.alloc((size_t)L * n * sizeof(uint32_t));
@@ -524,6 +528,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     a.stopw = ix->rule_tab.as<float>() + 65;
     a.B = o.B;
     a.filter = filt;
+    a.prefilter = o.no_prefilter ? 0 : 1;
     a.queue = nullptr;
     a.order = nullptr;
     a.tile = 0;
@@ -655,11 +660,16 @@ PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_by
             PF_CHECK(dst_bytes >= b, PF_EINVAL, "pf_export: destination too small");
         };
         switch (what) {
-        case PF_EXPORT_POINTS:
+        case PF_EXPORT_POINTS: {
             need(n * ix->d * 4);
-            PF_HIP(hipMemcpy2DAsync(dst, (size_t)ix->d * 4, ix->X.p, (size_t)ix->dpad * 4, (size_t)ix->d * 4,
+            DevBuf X;
+            X.alloc((size_t)n * ix->dpad * sizeof(float));
+            launch_join_planes(ix->Xh.as<uint16_t>(), ix->Xl.as<uint16_t>(), n * ix->dpad, X.as<float>(), s);
+            PF_HIP(hipMemcpy2DAsync(dst, (size_t)ix->d * 4, X.p, (size_t)ix->dpad * 4, (size_t)ix->d * 4,
                                     (size_t)n, kind, s));
+            PF_HIP(hipStreamSynchronize(s));
             break;
+        }
         case PF_EXPORT_HYPERPLANES: {
             const int64_t b = ((int64_t)ix->L * ix->K + 64ll * ix->M) * ix->d * 4;
             need(b);
@@ -702,7 +712,7 @@ PF_API int pf_index_info(const pf_index *ix, pf_info *info) {
         r.M = ix->M;
         r.P = ix->P;
         r.bytes_budget_rule = ix->bytes_rule;
-        r.bytes_device = ix->X.bytes + ix->hp.bytes + ix->hcolrow.bytes + ix->hbf.bytes + ix->hbeta.bytes +
+        r.bytes_device = ix->Xh.bytes + ix->Xl.bytes + ix->hp.bytes + ix->hcolrow.bytes + ix->hbf.bytes + ix->hbeta.bytes +
                          ix->tcode.bytes + ix->tidx.bytes + ix->tsk.bytes + ix->off.bytes;
         r.build_ms = ix->build_ms;
         *info = r;

@@ -79,7 +79,11 @@ struct Index {
     int device = 0;
     int num_cus = 0;
 
-    DevBuf X;      // n x dpad FP32 normalised vectors (zero padded)
+    // n x dpad FP32 normalised vectors (zero padded), stored as two 16-bit planes: the
+    // upper halves of the bit patterns (the vectors truncated to bfloat16) and the lower
+    // halves; the re-rank reads the upper plane first and the lower one only where the
+    // truncated inner product cannot rule a candidate out
+    DevBuf Xh, Xl;
     DevBuf hp;     // (L*K + 64*M) x d FP32 hyperplanes (paper order)
     DevBuf hcolrow;// ncols int32: hyperplane row of each GEMM column (-1 = padding)
     DevBuf hbf;    // ncols x kp bf16 hi parts, then ncols x kp bf16 lo parts
@@ -134,6 +138,9 @@ void launch_normalize(const float *x, int64_t n, int32_t d, int32_t ld_in, float
                       int32_t dpad, unsigned long long *bad, hipStream_t s);
 
 void launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s);
+// X (count FP32) <-> upper / lower 16-bit halves of the bit patterns
+void launch_split_planes(const float *X, int64_t count, uint16_t *hi, uint16_t *lo, hipStream_t s);
+void launch_join_planes(const uint16_t *hi, const uint16_t *lo, int64_t count, float *X, hipStream_t s);
 
 // hashing of rows X (n x dpad) into code words; see k_hash.hip
 void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
@@ -160,6 +167,7 @@ struct SearchArgs {
     const float *tauv;     // 65 filter-threshold boundaries (see k_search.hip)
     const float *stopw;    // ndelta x K x 66 stopping thresholds
     int32_t B, filter;
+    int32_t prefilter;     // 1: rule candidates out on the upper-plane inner product bound
     unsigned int *queue;   // device work-queue counter (nullable: static assignment)
     const int32_t *order;  // queue position -> query (nullable)
     int32_t tile;          // tile shape index (see search_tile_name)

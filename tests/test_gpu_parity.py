@@ -45,6 +45,8 @@ def _assert_search_equal(gr, orr, label=""):
         assert bad.size == 0, f"{label} {name}: {bad.size} mismatches, q={bad[:5]} gpu={gv[bad[:5]]} oracle={ov[bad[:5]]}"
     bad = np.nonzero(np.any(gr.ids != orr.ids, axis=1) & ok)[0]
     assert bad.size == 0, f"{label} ids differ for {bad.size} queries, first {bad[:5]}"
+    # exact inner products: at most one per re-ranked candidate
+    assert np.all((st[:, 4] >= 0) & (st[:, 4] <= st[:, 3])), f"{label} c_exact"
     assert np.array_equal(gr.ips[ok].view(np.uint32), orr.ips[ok].view(np.uint32)), f"{label} ips"
     assert ok.mean() > 0.99
 
@@ -107,7 +109,7 @@ def test_config1_parity():
     (1, 0.9, {}), (10, 0.5, {}), (10, 0.99, {}), (37, 0.9, {}), (10, 0.9, {"B": 1}),
     (10, 0.9, {"filter": False}), (10, 0.9, {"rule": pf.PF_RULE_ALG1}), (10, 0.9, {"eps": 0.1}),
     (10, 0.9, {"rule": pf.PF_RULE_EXACT}), (10, 0.8, {"rule": pf.PF_RULE_EXACT, "eps": 0.3}),
-    (5, 1.0, {}), (128, 0.7, {}),
+    (5, 1.0, {}), (128, 0.7, {}), (10, 0.9, {"prefilter": False}), (10, 1.0, {"prefilter": False}),
 ])
 def test_search_variants(k, recall, kw):
     X = workloads.gaussian_unit(5000, 48, 21)
@@ -116,9 +118,51 @@ def test_search_variants(k, recall, kw):
     okw = dict(kw)
     if "filter" in okw:
         okw["filter_on"] = okw.pop("filter")
+    okw.pop("prefilter", None)
     gr = g.search(Q, k, recall, **kw)
     orr = o.search(Q, k, recall, **okw)
     _assert_search_equal(gr, orr, f"k={k} r={recall} {kw}")
+    if kw.get("prefilter", True) is False:
+        assert np.array_equal(gr.stats[:, 4], gr.stats[:, 3])
+
+
+@pytest.mark.parametrize("d", [48, 100, 200, 300])
+def test_prefilter_exact_and_effective(d):
+    """The upper-plane bound only decides which inner products are computed: ids, inner
+    products and counters equal the oracle's with it on and off, for every row-length
+    specialisation, and it rules most candidates out."""
+    X = workloads.gaussian_unit(6000, d, 300 + d)
+    Q = workloads.gaussian_unit(200, d, 400 + d)
+    g, o = _build_both(X, L=30, seed=d)
+    orr = o.search(Q, 10, 0.9)
+    on = g.search(Q, 10, 0.9)
+    off = g.search(Q, 10, 0.9, prefilter=False)
+    _assert_search_equal(on, orr, f"prefilter on d={d}")
+    _assert_search_equal(off, orr, f"prefilter off d={d}")
+    assert np.array_equal(off.stats[:, 4], off.stats[:, 3])
+    frac = on.stats[:, 4].sum() / on.stats[:, 3].sum()
+    print(f"[prefilter d={d}] exact inner products: {frac:.4f} of re-ranked", flush=True)
+    assert frac < 0.5
+
+
+def test_prefilter_low_bits_and_subnormals():
+    """Points that differ only in the lower 16 bits of their coordinates (identical upper
+    planes, so the bound cannot separate them), exact zeros and subnormal coordinates."""
+    rng = np.random.default_rng(501)
+    d = 64
+    base = workloads.gaussian_unit(40, d, 502)
+    X = [workloads.gaussian_unit(3000, d, 503)]
+    for b in base:
+        cp = np.repeat(b[None, :], 25, 0).view(np.uint32).copy()
+        cp ^= rng.integers(0, 1 << 12, size=cp.shape, dtype=np.uint32)  # low bits only
+        X.append(cp.view(np.float32))
+    X = np.concatenate(X)
+    X[:200, :8] = 0.0
+    X[200:400, 8:16] = np.float32(3e-39)  # subnormal before and after normalisation
+    Q = (base + np.float32(0.05) * workloads.gaussian_unit(40, d, 504)).astype(np.float32)
+    g, o = _build_both(X, L=24, seed=505)
+    for k, rec in [(1, 0.9), (10, 0.9), (30, 0.99)]:
+        _assert_search_equal(g.search(Q, k, rec), o.search(Q, k, rec), f"low bits k={k}")
 
 
 def test_linear_scan_equals_bruteforce():
@@ -202,7 +246,7 @@ def _oracle_per_query(o, Q, ks, recalls, kmax):
 def _assert_batch_equal(gr, oids, oips, ost, obd, label):
     ok = obd == 0
     print(f"[batch {label}] boundary cases: {int((~ok).sum())} of {len(ok)}", flush=True)
-    assert np.array_equal(gr.stats[ok], ost[ok]), label + " stats"
+    assert np.array_equal(gr.stats[ok][:, :4], ost[ok]), label + " stats"
     assert np.array_equal(gr.ids[ok], oids[ok]), label + " ids"
     assert np.array_equal(gr.ips[ok].view(np.uint32), oips[ok].view(np.uint32)), label + " ips"
     assert ok.mean() > 0.99

@@ -77,7 +77,7 @@ def test_training_learns_query_cost_and_keeps_results(tmp_path):
     rl = g.search_batch(Qte, ks, rec, 10, learned=True)
     rf = g.search_batch(Qte, ks, rec, 10)
     assert np.array_equal(rl.ids, rte.ids) and np.array_equal(rf.ids, rte.ids)
-    assert np.array_equal(rl.stats, rte.stats)
+    assert np.array_equal(rl.stats[:, :4], rte.stats[:, :4])
     path = str(tmp_path / "sched.bin")
     s.save(path)
     s2 = pf.Scheduler(seed=99)
