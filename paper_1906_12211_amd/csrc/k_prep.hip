@@ -51,37 +51,65 @@ void launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s) {
     PF_HIP(hipGetLastError());
 }
 
-// Vector storage as two 16-bit planes: hi[i] = upper half of the FP32 bit pattern of
-// X[i] (X[i] truncated to bfloat16), lo[i] = lower half; (hi << 16) | lo is X[i] exactly.
-__global__ __launch_bounds__(256) void k_split_planes(const uint32_t *__restrict__ X, int64_t count,
-                                                      uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+// Vector storage as two 16-bit planes.  Element c of row r (c < dpad) has its upper
+// half (the value truncated to bfloat16) at hi[r * hs + c] and its lower half at
+// hi[r * hs + dpad + c] when c < spare = hs - dpad (the padding of the upper row), else
+// at lo[r * ls + c - spare]; ls = dpad - spare.  ((upper << 16) | lower) is the FP32
+// value exactly, and the two planes hold 4 dpad bytes per row, as the FP32 array did.
+__global__ __launch_bounds__(256) void k_split_planes(const uint32_t *__restrict__ X, int64_t n, int32_t dpad,
+                                                      int32_t hs, int32_t ls, uint16_t *__restrict__ hi,
+                                                      uint16_t *__restrict__ lo) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stride) {
+    const int32_t spare = hs - dpad;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * dpad; t += stride) {
+        const int64_t r = t / dpad;
+        const int32_t c = (int32_t)(t - r * dpad);
         const uint32_t v = X[t];
-        hi[t] = (uint16_t)(v >> 16);
-        lo[t] = (uint16_t)(v & 0xFFFFu);
+        hi[r * hs + c] = (uint16_t)(v >> 16);
+        if (c < spare)
+            hi[r * hs + dpad + c] = (uint16_t)(v & 0xFFFFu);
+        else
+            lo[r * ls + c - spare] = (uint16_t)(v & 0xFFFFu);
     }
 }
 
 __global__ __launch_bounds__(256) void k_join_planes(const uint16_t *__restrict__ hi, const uint16_t *__restrict__ lo,
-                                                     int64_t count, uint32_t *__restrict__ X) {
+                                                     int64_t n, int32_t dpad, int32_t hs, int32_t ls,
+                                                     uint32_t *__restrict__ X) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stride)
-        X[t] = ((uint32_t)hi[t] << 16) | (uint32_t)lo[t];
+    const int32_t spare = hs - dpad;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * dpad; t += stride) {
+        const int64_t r = t / dpad;
+        const int32_t c = (int32_t)(t - r * dpad);
+        const uint32_t w = c < spare ? hi[r * hs + dpad + c] : lo[r * ls + c - spare];
+        X[t] = ((uint32_t)hi[r * hs + c] << 16) | w;
+    }
 }
 
-void launch_split_planes(const float *X, int64_t count, uint16_t *hi, uint16_t *lo, hipStream_t s) {
-    if (count <= 0) return;
-    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+void plane_strides(int32_t dpad, int32_t *hs, int32_t *ls) {
+    // upper rows padded to whole 128-byte lines when the padding can hold lower halves
+    // (at most dpad of them), so that a row is read as whole lines; else unpadded
+    const int32_t h = (dpad + 63) / 64 * 64;
+    *hs = h <= 2 * dpad ? h : dpad;
+    *ls = dpad - (*hs - dpad);
+}
+
+void launch_split_planes(const float *X, int64_t n, int32_t dpad, uint16_t *hi, uint16_t *lo, hipStream_t s) {
+    if (n <= 0) return;
+    int32_t hs, ls;
+    plane_strides(dpad, &hs, &ls);
+    const int64_t blocks = std::min<int64_t>((n * dpad + 255) / 256, 65536);
     hipLaunchKernelGGL(k_split_planes, dim3((unsigned)blocks), dim3(256), 0, s,
-                       reinterpret_cast<const uint32_t *>(X), count, hi, lo);
+                       reinterpret_cast<const uint32_t *>(X), n, dpad, hs, ls, hi, lo);
     PF_HIP(hipGetLastError());
 }
 
-void launch_join_planes(const uint16_t *hi, const uint16_t *lo, int64_t count, float *X, hipStream_t s) {
-    if (count <= 0) return;
-    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_join_planes, dim3((unsigned)blocks), dim3(256), 0, s, hi, lo, count,
+void launch_join_planes(const uint16_t *hi, const uint16_t *lo, int64_t n, int32_t dpad, float *X, hipStream_t s) {
+    if (n <= 0) return;
+    int32_t hs, ls;
+    plane_strides(dpad, &hs, &ls);
+    const int64_t blocks = std::min<int64_t>((n * dpad + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_join_planes, dim3((unsigned)blocks), dim3(256), 0, s, hi, lo, n, dpad, hs, ls,
                        reinterpret_cast<uint32_t *>(X));
     PF_HIP(hipGetLastError());
 }

@@ -257,6 +257,8 @@ static constexpr int kCW = 256;
 
 struct SearchK {
     const uint16_t *Xh, *Xl; // upper / lower 16-bit planes of the n x dpad FP32 vectors
+    int32_t hs, ls, spare;   // plane row lengths; lower halves of elements < spare sit in
+                             // the upper row after its dpad upper halves
     float rr_slack;          // rounding allowance of the upper-plane bound
     int32_t prefilter;
     const uint32_t *tidx, *off;
@@ -439,8 +441,14 @@ __device__ __forceinline__ float4 upper4(uint2 h) {
     return make_float4(__uint_as_float(h.x << 16), __uint_as_float(h.x & 0xFFFF0000u), __uint_as_float(h.y << 16),
                        __uint_as_float(h.y & 0xFFFF0000u));
 }
-__device__ __forceinline__ uint2 ld4(const uint16_t *__restrict__ plane, uint32_t id, int32_t dpad, int base) {
-    return *reinterpret_cast<const uint2 *>(plane + (int64_t)id * dpad + base);
+// upper / lower halves of elements base .. base+3 of row id (base a multiple of 4)
+__device__ __forceinline__ uint2 ld_hi(const SearchK &p, uint32_t id, int base) {
+    return *reinterpret_cast<const uint2 *>(p.Xh + (int64_t)id * p.hs + base);
+}
+__device__ __forceinline__ uint2 ld_lo(const SearchK &p, uint32_t id, int base) {
+    const uint16_t *a = base < p.spare ? p.Xh + (int64_t)id * p.hs + p.dpad + base
+                                       : p.Xl + (int64_t)id * p.ls + (base - p.spare);
+    return *reinterpret_cast<const uint2 *>(a);
 }
 
 // Inner products of up to U rows per 16-lane group in the fixed FP32 order: lane r sums
@@ -464,8 +472,8 @@ __device__ __forceinline__ void dot_rows(const SearchK &p, const float *qv, cons
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const bool ok = u < cnt && base < dpad;
-                hv[u][t] = ok ? ld4(p.Xh, ids[u], dpad, base) : make_uint2(0u, 0u);
-                wv[u][t] = ok ? ld4(p.Xl, ids[u], dpad, base) : make_uint2(0u, 0u);
+                hv[u][t] = ok ? ld_hi(p, ids[u], base) : make_uint2(0u, 0u);
+                wv[u][t] = ok ? ld_lo(p, ids[u], base) : make_uint2(0u, 0u);
             }
         }
 #pragma unroll
@@ -488,8 +496,8 @@ __device__ __forceinline__ void dot_rows(const SearchK &p, const float *qv, cons
             uint2 hv[U], wv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                hv[u] = u < cnt ? ld4(p.Xh, ids[u], dpad, base) : make_uint2(0u, 0u);
-                wv[u] = u < cnt ? ld4(p.Xl, ids[u], dpad, base) : make_uint2(0u, 0u);
+                hv[u] = u < cnt ? ld_hi(p, ids[u], base) : make_uint2(0u, 0u);
+                wv[u] = u < cnt ? ld_lo(p, ids[u], base) : make_uint2(0u, 0u);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -535,7 +543,7 @@ __device__ __forceinline__ void bound_rows(const SearchK &p, const float *qv, co
             const int base = 64 * t + 4 * r;
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                hv[u][t] = (u < cnt && base < dpad) ? ld4(p.Xh, ids[u], dpad, base) : make_uint2(0u, 0u);
+                hv[u][t] = (u < cnt && base < dpad) ? ld_hi(p, ids[u], base) : make_uint2(0u, 0u);
         }
 #pragma unroll
         for (int t = 0; t < DT; ++t) {
@@ -555,7 +563,7 @@ __device__ __forceinline__ void bound_rows(const SearchK &p, const float *qv, co
             const float4 qq = *reinterpret_cast<const float4 *>(qv + base);
             uint2 hv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) hv[u] = u < cnt ? ld4(p.Xh, ids[u], dpad, base) : make_uint2(0u, 0u);
+            for (int u = 0; u < U; ++u) hv[u] = u < cnt ? ld_hi(p, ids[u], base) : make_uint2(0u, 0u);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const float4 xv = upper4(hv[u]);
@@ -941,6 +949,9 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     SearchK p;
     p.Xh = ix.Xh.as<uint16_t>();
     p.Xl = ix.Xl.as<uint16_t>();
+    p.hs = ix.hs;
+    p.ls = ix.ls;
+    p.spare = ix.hs - ix.dpad;
     p.prefilter = a.prefilter;
     // twice the rounding of the FP32 sums (chains of at most dpad/16 + 4 additions, unit
     // vectors) plus the d 2^-126 of subnormal upper halves, with room to spare

@@ -255,9 +255,10 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         codes.alloc((size_t)L * n * sizeof(uint32_t));
         sk.alloc((size_t)M * n * sizeof(uint64_t));
         hash_rows(*ix, X.as<float>(), n, codes.as<uint32_t>(), sk.as<uint64_t>(), scratch, s);
-        ix->Xh.alloc((size_t)n * ix->dpad * sizeof(uint16_t));
-        ix->Xl.alloc((size_t)n * ix->dpad * sizeof(uint16_t));
-        launch_split_planes(X.as<float>(), n * ix->dpad, ix->Xh.as<uint16_t>(), ix->Xl.as<uint16_t>(), s);
+        plane_strides(ix->dpad, &ix->hs, &ix->ls);
+        ix->Xh.alloc((size_t)n * ix->hs * sizeof(uint16_t));
+        ix->Xl.alloc((size_t)n * std::max(ix->ls, 1) * sizeof(uint16_t));
+        launch_split_planes(X.as<float>(), n, ix->dpad, ix->Xh.as<uint16_t>(), ix->Xl.as<uint16_t>(), s);
         // a6: sorted tables
         ix->tcode.alloc((size_t)L * n * sizeof(uint32_t));
         ix->tidx.alloc((size_t)L * n * sizeof(uint32_t));
@@ -664,7 +665,7 @@ PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_by
             need(n * ix->d * 4);
             DevBuf X;
             X.alloc((size_t)n * ix->dpad * sizeof(float));
-            launch_join_planes(ix->Xh.as<uint16_t>(), ix->Xl.as<uint16_t>(), n * ix->dpad, X.as<float>(), s);
+            launch_join_planes(ix->Xh.as<uint16_t>(), ix->Xl.as<uint16_t>(), n, ix->dpad, X.as<float>(), s);
             PF_HIP(hipMemcpy2DAsync(dst, (size_t)ix->d * 4, X.p, (size_t)ix->dpad * 4, (size_t)ix->d * 4,
                                     (size_t)n, kind, s));
             PF_HIP(hipStreamSynchronize(s));

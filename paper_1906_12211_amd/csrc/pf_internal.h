@@ -80,10 +80,13 @@ struct Index {
     int num_cus = 0;
 
     // n x dpad FP32 normalised vectors (zero padded), stored as two 16-bit planes: the
-    // upper halves of the bit patterns (the vectors truncated to bfloat16) and the lower
-    // halves; the re-rank reads the upper plane first and the lower one only where the
-    // truncated inner product cannot rule a candidate out
+    // upper halves of the bit patterns (the vectors truncated to bfloat16; rows of hs
+    // elements, padded to whole lines where the padding holds lower halves) and the
+    // remaining lower halves (rows of ls elements); the re-rank reads the upper plane
+    // first and the lower halves only where the truncated inner product cannot rule a
+    // candidate out
     DevBuf Xh, Xl;
+    int32_t hs = 0, ls = 0;
     DevBuf hp;     // (L*K + 64*M) x d FP32 hyperplanes (paper order)
     DevBuf hcolrow;// ncols int32: hyperplane row of each GEMM column (-1 = padding)
     DevBuf hbf;    // ncols x kp bf16 hi parts, then ncols x kp bf16 lo parts
@@ -138,9 +141,11 @@ void launch_normalize(const float *x, int64_t n, int32_t d, int32_t ld_in, float
                       int32_t dpad, unsigned long long *bad, hipStream_t s);
 
 void launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s);
-// X (count FP32) <-> upper / lower 16-bit halves of the bit patterns
-void launch_split_planes(const float *X, int64_t count, uint16_t *hi, uint16_t *lo, hipStream_t s);
-void launch_join_planes(const uint16_t *hi, const uint16_t *lo, int64_t count, float *X, hipStream_t s);
+// X (n x dpad FP32) <-> upper / lower 16-bit planes (layout in k_prep.hip); hs, ls:
+// elements per row of the upper and lower plane
+void plane_strides(int32_t dpad, int32_t *hs, int32_t *ls);
+void launch_split_planes(const float *X, int64_t n, int32_t dpad, uint16_t *hi, uint16_t *lo, hipStream_t s);
+void launch_join_planes(const uint16_t *hi, const uint16_t *lo, int64_t n, int32_t dpad, float *X, hipStream_t s);
 
 // hashing of rows X (n x dpad) into code words; see k_hash.hip
 void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
