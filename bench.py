@@ -108,6 +108,78 @@ def cpu_baseline(points, queries, budget, k, recall, seconds):
             "seconds": el}
 
 
+def mixed_batch(ix, dev, args):
+    """Configuration 4 on the same index: 100,000 queries, half from the mixture and half
+    uniform, with per-query k in {1, 10, 100} and recall in {0.5, 0.9, 0.99}, answered by
+    the persistent batched search under four queue orders: as given (FIFO), the learned
+    order (longest predicted first; network trained on traces of the plain method for
+    another batch of the same distribution), the order of the true costs (the plain
+    method's scanned-entry counts of this batch; a bound no predictor can beat) and the
+    reverse of the learned order (shortest predicted first)."""
+    import torch
+
+    m = max(1, int(round(100_000 * args.scale)))
+    Q, ks, rec = workloads.mixed_queries(m)
+    Qt, kst, rect = workloads.mixed_queries(max(1, int(round(m * args.train_frac))), seed_offset=100)
+    kmax = 100
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    Qd, ksd, recd = to(Q), to(ks), to(rec)
+    Qtd, kstd, rectd = to(Qt), to(kst), to(rect)
+    t0 = time.perf_counter()
+    st = ix.search_batch(Qtd, kstd, rectd, kmax).stats.cpu().numpy()
+    target = np.stack([st[:, 0], np.log2(1.0 + st[:, 1])], 1).astype(np.float32)
+    sched = pf.Scheduler(seed=2)
+    losses = sched.train(ix.features(Qtd, kstd, rectd), to(target), epochs=20, batch=512, lr=2e-3)
+    ix.set_scheduler(sched)
+    train_s = time.perf_counter() - t0
+    log(f"mixed batch: scheduler trained on {len(Qt)} traces in {train_s:.1f} s, "
+        f"loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    ix.search_batch(Qd, ksd, recd, kmax, autotune=True)
+    base = ix.search_batch(Qd, ksd, recd, kmax)
+    cost = np.log2(1.0 + base.stats.cpu().numpy()[:, 1])
+    pred = sched.predict(ix.features(Qd, ksd, recd)).cpu().numpy()[:, 1]
+    rank = lambda v: np.argsort(np.argsort(v))
+    rho = float(np.corrcoef(rank(pred), rank(cost))[0, 1])
+    lpt_true = np.argsort(-cost, kind="stable").astype(np.int32)
+    spt_pred = np.argsort(pred, kind="stable").astype(np.int32)
+    orders = {
+        "fifo": dict(),
+        "learned": dict(learned=True),
+        "true_cost_lpt": dict(order=to(lpt_true)),
+        "shortest_predicted_first": dict(order=to(spt_pred)),
+    }
+    out = {}
+    steps = max(1, min(args.steps, 5))
+    for name, kw in orders.items():
+        for _ in range(max(1, min(args.warmup, 2))):
+            r = ix.search_batch(Qd, ksd, recd, kmax, timing=True, **kw)
+        torch.cuda.synchronize()
+        ks_ms = []
+        t = time.perf_counter()
+        for _ in range(steps):
+            r = ix.search_batch(Qd, ksd, recd, kmax, timing=True, **kw)
+            ks_ms.append(ix.last_timing().search_ms)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / steps * 1e3
+        same = bool(torch.equal(r.ids, base.ids))
+        out[name] = {"ms_per_step": wall, "qps": m / (wall / 1e3), "search_kernel_ms": float(np.mean(ks_ms)),
+                     "ids_equal_fifo": same}
+        log(f"mixed batch {name}: {wall:.2f} ms/step, search kernel {np.mean(ks_ms):.2f} ms, ids equal {same}")
+    t = ix.last_timing()
+    sb = base.stats.cpu().numpy()
+    return {"workload": "mixed-100k-on-1M-d100", "queries": m, "kmax": kmax, "steps": steps,
+            "orders": out,
+            "learned_vs_fifo": out["fifo"]["search_kernel_ms"] / out["learned"]["search_kernel_ms"],
+            "spearman_pred_vs_true_cost": rho,
+            "scheduler": {"train_queries": int(len(Qt)), "train_s": train_s, "loss_first": float(losses[0]),
+                          "loss_last": float(losses[-1])},
+            "tile": {"tile": t.tile, "waves_per_cu": t.waves_per_cu},
+            "mean_counts": {"c_scan": float(sb[:, 1].mean()), "c_pass": float(sb[:, 2].mean()),
+                            "c_exact": float(sb[:, 4].mean())},
+            "cost_spread_log2_scan": {"p10": float(np.percentile(cost, 10)), "p50": float(np.percentile(cost, 50)),
+                                      "p90": float(np.percentile(cost, 90)), "max": float(cost.max())}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +193,8 @@ def main():
                     help="query paths to time (comma separated); the last one is the headline")
     ap.add_argument("--train-frac", type=float, default=2.0,
                     help="scheduler training queries as a multiple of the benchmark query count")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed 100,000-query batch (per-query k and recall, queue orders)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -254,6 +328,7 @@ def main():
         "cpu_baseline": None,
     }
     log(f"recall {rec:.4f} on {ns} queries")
+    line["mixed_batch"] = None if args.no_mixed else mixed_batch(ix, dev, args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(X, Q, budget, k, recall, args.cpu_seconds)
     print(json.dumps(line), flush=True)

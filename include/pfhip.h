@@ -191,16 +191,17 @@ void pf_free_index(pf_index *ix);
 
 /* ---------------------------------------------------------------- learned scheduler
  * A small network predicts, for each query, the prefix length at which the plain
- * method stops and log2(1 + entries it scans), from the query's 64 sketch-0 bits (+1/-1)
- * and log2(1 + size of its 13-bit prefix bucket) in tables 0..31.  pf_search_batch with
+ * method stops and log2(1 + entries it scans), from the query's 64 sketch-0 bits (+1/-1),
+ * log2(1 + size of its 13-bit prefix bucket) in tables 0..31, log2 k and log2(1/delta)
+ * (delta = 1 - recall; 40 when delta < 2^-40).  pf_search_batch with
  * PF_BATCH_LEARNED answers the predicted-costliest queries first (longest processing
  * time first), which shortens the tail of the batch; the stopping rule still decides
- * when each query ends, so results are unchanged.  Network: 96 -> 128 ReLU -> 128 ReLU
+ * when each query ends, so results are unchanged.  Network: 98 -> 128 ReLU -> 128 ReLU
  * -> 2, FP32, mean squared error, Adam; parameters in one flat FP32 array
- * W1[96][128], b1[128], W2[128][128], b2[128], W3[128][2], b3[2] (y = x W + b). */
-#define PF_SCHED_IN 96
+ * W1[98][128], b1[128], W2[128][128], b2[128], W3[128][2], b3[2] (y = x W + b). */
+#define PF_SCHED_IN 98
 #define PF_SCHED_OUT 2
-#define PF_SCHED_PARAMS 29186
+#define PF_SCHED_PARAMS 29442
 
 typedef struct pf_sched pf_sched;
 
@@ -209,15 +210,18 @@ int pf_sched_create(uint64_t seed, pf_sched **out);
 void pf_sched_free(pf_sched *s);
 /* copy the PF_SCHED_PARAMS host floats out of (get = 1) or into (get = 0) the network */
 int pf_sched_params(pf_sched *s, float *params, int32_t get);
-/* features of m queries (m x 96 FP32) under index ix; queries are normalised and hashed */
-int pf_features(pf_index *ix, const float *queries, int64_t m, float *feat, int32_t mem, void *stream);
+/* features of m queries (m x 98 FP32) under index ix; queries are normalised and hashed;
+ * per-query k (ks, nullable: kconst) and recall (recalls, nullable: recall_const) in the
+ * same memory as the queries.  PF_EINVAL for k < 1 or recall outside (0, 1]. */
+int pf_features(pf_index *ix, const float *queries, int64_t m, const int32_t *ks, const double *recalls,
+                int32_t kconst, double recall_const, float *feat, int32_t mem, void *stream);
 /* predictions (m x 2: stop level, log2(1 + entries scanned)) */
 int pf_sched_predict(pf_sched *s, const float *feat, int64_t m, float *out, int32_t mem, void *stream);
 /* loss (mean of the m x 2 squared errors) and its gradient w.r.t. every parameter */
 int pf_sched_grad(pf_sched *s, const float *feat, const float *target, int64_t m, float *grad, double *loss,
                   int32_t mem, void *stream);
 /* minibatch Adam (beta1 0.9, beta2 0.999, eps 1e-8) over `epochs` shuffled passes of the m
- * traces (feat m x 96, target m x 2); epoch_loss (nullable) receives the mean batch loss of
+ * traces (feat m x 98, target m x 2); epoch_loss (nullable) receives the mean batch loss of
  * each epoch.  Synchronises. */
 int pf_sched_train(pf_sched *s, const float *feat, const float *target, int64_t m, int32_t epochs,
                    int32_t batch, float lr, uint64_t seed, float *epoch_loss, int32_t mem, void *stream);

@@ -1,17 +1,19 @@
 """FP64 reference of the scheduler network and its features -- TEST INFRASTRUCTURE.
 
-Network: y = relu(relu(x W1 + b1) W2 + b2) W3 + b3 with x in R^96, hidden 128, y in R^2;
+Network: y = relu(relu(x W1 + b1) W2 + b2) W3 + b3 with x in R^98, hidden 128, y in R^2;
 loss = mean over the m x 2 outputs of (y - t)^2; gradients by the chain rule written out
 layer by layer (ReLU derivative 1 where the activation is > 0, else 0).  Parameters in one
-flat array: W1[96][128], b1[128], W2[128][128], b2[128], W3[128][2], b3[2].
+flat array: W1[98][128], b1[128], W2[128][128], b2[128], W3[128][2], b3[2].
 Features of a query: the 64 bits of its sketch 0 as +1/-1 (bit b -> feature b), then
-log2(1 + size of its 13-bit prefix bucket) in tables 0..31 (0 for absent tables).
+log2(1 + size of its 13-bit prefix bucket) in tables 0..31 (0 for absent tables), then
+the two inputs of adaptive-kNN(q, k, delta) (Algorithm 1) that set how far the walk
+goes: log2 k and log2(1/delta), delta = 1 - recall (capped at 40 for delta < 2^-40).
 """
 from __future__ import annotations
 
 import numpy as np
 
-IN, HID, OUT = 96, 128, 2
+IN, HID, OUT = 98, 128, 2
 SHAPES = [("W1", (IN, HID)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)), ("W3", (HID, OUT)),
           ("b3", (OUT,))]
 NPARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
@@ -53,12 +55,16 @@ def loss_and_grad(p: np.ndarray, x: np.ndarray, t: np.ndarray):
     return loss, pack(g)
 
 
-def features(sketch0: np.ndarray, bucket_sizes: np.ndarray) -> np.ndarray:
-    """sketch0: (m,) uint64; bucket_sizes: (m, tables) counts; returns (m, 96) float64."""
+def features(sketch0: np.ndarray, bucket_sizes: np.ndarray, ks=10, recalls=0.9) -> np.ndarray:
+    """sketch0: (m,) uint64; bucket_sizes: (m, tables) counts; ks, recalls: scalars or (m,);
+    returns (m, 98) float64."""
     m = len(sketch0)
     f = np.zeros((m, IN))
     bits = (sketch0[:, None] >> np.arange(64, dtype=np.uint64)[None, :]) & np.uint64(1)
     f[:, :64] = np.where(bits == 1, 1.0, -1.0)
     nt = min(32, bucket_sizes.shape[1])
     f[:, 64:64 + nt] = np.log2(1.0 + bucket_sizes[:, :nt].astype(np.float64))
+    f[:, 96] = np.log2(np.broadcast_to(np.asarray(ks, dtype=np.float64), (m,)))
+    delta = 1.0 - np.broadcast_to(np.asarray(recalls, dtype=np.float64), (m,))
+    f[:, 97] = np.where(delta < 2.0 ** -40, 40.0, -np.log2(np.maximum(delta, 2.0 ** -40)))
     return f

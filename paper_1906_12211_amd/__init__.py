@@ -27,7 +27,7 @@ PF_MAX_TABLES, PF_MAX_K, PF_MAX_DIM = 512, 256, 4096
 
 PF_BATCH_LEARNED, PF_BATCH_AUTOTUNE = 1, 2
 
-PF_SCHED_IN, PF_SCHED_OUT, PF_SCHED_PARAMS = 96, 2, 29186
+PF_SCHED_IN, PF_SCHED_OUT, PF_SCHED_PARAMS = 98, 2, 29442
 
 EXPORTED = ["pf_normalize", "pf_build_index", "pf_search", "pf_search_ex", "pf_search_batch", "pf_hash",
             "pf_export", "pf_index_info", "pf_last_timing", "pf_free_index", "pf_last_error", "pf_version",
@@ -123,7 +123,7 @@ def lib():
         L.pf_sched_params.restype = ctypes.c_int
         L.pf_sched_params.argtypes = [_P, _P, _I32]
         L.pf_features.restype = ctypes.c_int
-        L.pf_features.argtypes = [_P, _P, _I64, _P, _I32, _P]
+        L.pf_features.argtypes = [_P, _P, _I64, _P, _P, _I32, _D, _P, _I32, _P]
         L.pf_sched_predict.restype = ctypes.c_int
         L.pf_sched_predict.argtypes = [_P, _P, _I64, _P, _I32, _P]
         L.pf_sched_grad.restype = ctypes.c_int
@@ -307,13 +307,27 @@ class Index:
         _check(lib().pf_hash(self._h, px, m, _buf(codes)[0], _buf(sk)[0], mem, st))
         return codes, sk
 
-    def features(self, x):
-        """Scheduler features (m x 96 FP32) of the rows x under this index."""
+    def features(self, x, ks=None, recalls=None, k: int = 10, recall: float = 0.9):
+        """Scheduler features (m x 98 FP32) of the rows x under this index, for per-query
+        k / recall arrays (same memory as x) or the constants k / recall."""
         x = _f32(x)
         m = x.shape[0]
+        torch_in = _is_torch(x)
+
+        def arr(a, np_dt, t_dt):
+            if a is None:
+                return None
+            if torch_in:
+                import torch
+
+                return torch.as_tensor(a, dtype=getattr(torch, t_dt), device=x.device).contiguous()
+            return np.ascontiguousarray(a, dtype=np_dt)
+
+        ks_a, rec_a = arr(ks, np.int32, "int32"), arr(recalls, np.float64, "float64")
         f = _empty_like_input(x, (m, PF_SCHED_IN), np.float32, _torch_dtype("float32"))
         px, mem, st = _buf(x)
-        _check(lib().pf_features(self._h, px, m, _buf(f)[0], mem, st))
+        _check(lib().pf_features(self._h, px, m, _buf(ks_a)[0], _buf(rec_a)[0], int(k), float(recall),
+                                 _buf(f)[0], mem, st))
         return f
 
     def set_scheduler(self, sched):
@@ -346,7 +360,7 @@ def _torch_dtype(name: str):
 
 
 class Scheduler:
-    """The learned query-cost model (96 -> 128 -> 128 -> 2 MLP) trained by the library."""
+    """The learned query-cost model (98 -> 128 -> 128 -> 2 MLP) trained by the library."""
 
     def __init__(self, seed: int = 1):
         h = ctypes.c_void_p()

@@ -1,16 +1,18 @@
-// Kernels of the learned scheduler: per-query features and a 96-128-128-2 FP32 MLP
+// Kernels of the learned scheduler: per-query features and a 98-128-128-2 FP32 MLP
 // (forward, mean-squared-error gradient, backward, Adam).  The network only orders the
 // batched search's work queue; the stopping rule alone decides when a query ends.
 #include "pf_internal.h"
 
 namespace pf {
 
-// Features of query q (96 FP32): the 64 bits of its sketch 0 as +1 / -1, then
-// log2(1 + size of the query's 13-bit prefix bucket) in tables 0..31 (0 when L < 32).
+// Features of query q (98 FP32): the 64 bits of its sketch 0 as +1 / -1, then
+// log2(1 + size of the query's 13-bit prefix bucket) in tables 0..31 (0 when L < 32),
+// then the query's log2 k and log2(1/delta) (qparam, computed on the host).
 __global__ __launch_bounds__(256) void k_features(const uint32_t *__restrict__ qcode,
                                                   const uint64_t *__restrict__ qsk,
                                                   const uint32_t *__restrict__ off, int64_t m, int32_t L,
-                                                  int32_t K, int32_t P, float *__restrict__ feat) {
+                                                  int32_t K, int32_t P, const float *__restrict__ qparam,
+                                                  float *__restrict__ feat) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m * kSchedIn) return;
     const int64_t q = t / kSchedIn;
@@ -18,6 +20,8 @@ __global__ __launch_bounds__(256) void k_features(const uint32_t *__restrict__ q
     float v = 0.0f;
     if (f < 64) {
         v = ((qsk[q] >> f) & 1ull) ? 1.0f : -1.0f; // sketch 0 is the first M x m row block
+    } else if (f >= 96) {
+        v = qparam[2 * q + (f - 96)];
     } else {
         const int j = f - 64;
         if (j < L) {
@@ -116,11 +120,11 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, const float
 
 static unsigned grid_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
-void launch_features(const Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m, float *feat,
-                     hipStream_t s) {
+void launch_features(const Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m,
+                     const float *qparam, float *feat, hipStream_t s) {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_features, dim3(grid_for(m * kSchedIn)), dim3(256), 0, s, qcode, qsk, ix.off.as<uint32_t>(),
-                       m, ix.L, ix.K, ix.P, feat);
+                       m, ix.L, ix.K, ix.P, qparam, feat);
     PF_HIP(hipGetLastError());
 }
 

@@ -300,7 +300,8 @@ void prepare_rows_for(Index &ixr, const float *x, int64_t m, int32_t mem, hipStr
 }
 
 std::vector<int32_t> learned_order(Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m,
-                                   hipStream_t s);
+                                   const int32_t *ks_host, int32_t kconst, const double *rec_host,
+                                   double recall_const, hipStream_t s);
 
 // ------------------------------------------------------------------ autotuner
 // Tile shapes of the batched search kernel (sketch loads and rows in flight per lane)
@@ -555,7 +556,8 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
                              mem == PF_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost));
         } else if (bc.learned) {
             PF_CHECK(ix->sched, PF_EINVAL, "search_batch: PF_BATCH_LEARNED needs an attached scheduler");
-            ord = learned_order(*ix, qcode, qsk, m, s);
+            ord = learned_order(*ix, qcode, qsk, m, ks ? ks_host.data() : nullptr, kconst,
+                                recalls ? rec_host.data() : nullptr, recall_const, s);
         }
         if (!ord.empty()) {
             std::vector<char> seen(m, 0);

@@ -114,9 +114,9 @@ struct Index {
 };
 
 // ----------------------------------------------------------------- learned scheduler
-// MLP 96 -> 128 (ReLU) -> 128 (ReLU) -> 2, FP32, parameters in one flat array:
-// W1 [96][128], b1 [128], W2 [128][128], b2 [128], W3 [128][2], b3 [2]
-constexpr int kSchedIn = 96, kSchedHidden = 128, kSchedOut = 2;
+// MLP 98 -> 128 (ReLU) -> 128 (ReLU) -> 2, FP32, parameters in one flat array:
+// W1 [98][128], b1 [128], W2 [128][128], b2 [128], W3 [128][2], b3 [2]
+constexpr int kSchedIn = 98, kSchedHidden = 128, kSchedOut = 2;
 constexpr int64_t kOffW1 = 0;
 constexpr int64_t kOffB1 = kOffW1 + (int64_t)kSchedIn * kSchedHidden;
 constexpr int64_t kOffW2 = kOffB1 + kSchedHidden;
@@ -126,8 +126,12 @@ constexpr int64_t kOffB3 = kOffW3 + (int64_t)kSchedHidden * kSchedOut;
 constexpr int64_t kSchedParams = kOffB3 + kSchedOut; // 29,186
 
 struct Index;
-void launch_features(const Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m, float *feat,
-                     hipStream_t s);
+// features of m queries; qparam: m x 2 (log2 k, log2(1/delta)) on the device
+void launch_features(const Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m,
+                     const float *qparam, float *feat, hipStream_t s);
+// the two per-query parameter features, FP64 then rounded: log2 k, log2(1/delta) capped at 40
+std::vector<float> sched_qparams(int64_t m, const int32_t *ks_host, int32_t kconst, const double *rec_host,
+                                 double recall_const);
 void mlp_forward(const float *params, const float *x, const int32_t *rows, int64_t B, float *h1, float *h2,
                  float *y, hipStream_t s);
 void mlp_backward(const float *params, const float *x, const int32_t *rows, const float *tgt, int64_t B,

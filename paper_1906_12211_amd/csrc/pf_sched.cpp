@@ -1,5 +1,5 @@
-// Learned scheduler (C-ABI part): a small MLP predicts, from a query's sketch bits and
-// the sizes of its first-level (13-bit prefix) buckets, the level at which the plain
+// Learned scheduler (C-ABI part): a small MLP predicts, from a query's sketch bits, the
+// sizes of its first-level (13-bit prefix) buckets and its k and delta, the level at which the plain
 // method stops and log2(1 + entries it scans).  The batched search orders its work
 // queue longest-predicted-first; the stopping rule still ends every query, so results
 // do not depend on the prediction.  Trained on the GPU with the kernels of k_mlp.hip.
@@ -102,12 +102,28 @@ static std::vector<float> predict_host(Sched &sc, const float *feat_dev, int64_t
     return out;
 }
 
+std::vector<float> sched_qparams(int64_t m, const int32_t *ks_host, int32_t kconst, const double *rec_host,
+                                 double recall_const) {
+    std::vector<float> v((size_t)m * 2);
+    for (int64_t i = 0; i < m; ++i) {
+        const double k = ks_host ? (double)ks_host[i] : (double)kconst;
+        const double delta = 1.0 - (rec_host ? rec_host[i] : recall_const);
+        v[2 * i] = (float)std::log2(k);
+        v[2 * i + 1] = delta < 0x1.0p-40 ? 40.0f : (float)(-std::log2(delta));
+    }
+    return v;
+}
+
 std::vector<int32_t> learned_order(Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m,
-                                   hipStream_t s) {
+                                   const int32_t *ks_host, int32_t kconst, const double *rec_host,
+                                   double recall_const, hipStream_t s) {
     Sched &sc = *ix.sched;
-    DevBuf feat;
+    DevBuf feat, qp;
     feat.alloc((size_t)m * kSchedIn * sizeof(float));
-    launch_features(ix, qcode, qsk, m, feat.as<float>(), s);
+    const std::vector<float> qph = sched_qparams(m, ks_host, kconst, rec_host, recall_const);
+    qp.alloc(qph.size() * sizeof(float));
+    PF_HIP(hipMemcpyAsync(qp.p, qph.data(), qph.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    launch_features(ix, qcode, qsk, m, qp.as<float>(), feat.as<float>(), s);
     const std::vector<float> y = predict_host(sc, feat.as<float>(), m, s);
     std::vector<int32_t> order(m);
     std::iota(order.begin(), order.end(), 0);
@@ -153,22 +169,45 @@ PF_API int pf_sched_params(pf_sched *sc, float *params, int32_t get) {
     });
 }
 
-PF_API int pf_features(pf_index *ix, const float *queries, int64_t m, float *feat, int32_t mem, void *stream) {
+PF_API int pf_features(pf_index *ix, const float *queries, int64_t m, const int32_t *ks, const double *recalls,
+                       int32_t kconst, double recall_const, float *feat, int32_t mem, void *stream) {
     return sguard([&] {
         PF_CHECK(ix && queries && feat && m >= 0, PF_EINVAL, "pf_features: bad arguments");
+        PF_CHECK(mem == PF_HOST || mem == PF_DEVICE, PF_EINVAL, "pf_features: bad mem");
         if (m == 0) return;
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        const hipMemcpyKind toh = mem == PF_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
+        std::vector<int32_t> kh;
+        std::vector<double> rh;
+        if (ks) {
+            kh.resize(m);
+            PF_HIP(hipMemcpy(kh.data(), ks, (size_t)m * sizeof(int32_t), toh));
+        }
+        if (recalls) {
+            rh.resize(m);
+            PF_HIP(hipMemcpy(rh.data(), recalls, (size_t)m * sizeof(double), toh));
+        }
+        for (int64_t i = 0; i < m; ++i) {
+            const int32_t k = ks ? kh[i] : kconst;
+            const double r = recalls ? rh[i] : recall_const;
+            PF_CHECK(k >= 1 && r > 0.0 && r <= 1.0, PF_EINVAL, "pf_features: k must be >= 1 and recall in (0, 1]");
+        }
+        const std::vector<float> qph =
+            sched_qparams(m, ks ? kh.data() : nullptr, kconst, recalls ? rh.data() : nullptr, recall_const);
+        DevBuf qp;
+        qp.alloc(qph.size() * sizeof(float));
+        PF_HIP(hipMemcpyAsync(qp.p, qph.data(), qph.size() * sizeof(float), hipMemcpyHostToDevice, s));
         uint32_t *qc;
         uint64_t *qs;
         float *qX;
         prepare_rows_for(*ix, queries, m, mem, s, &qX, &qc, &qs);
         if (mem == PF_DEVICE) {
-            launch_features(*ix, qc, qs, m, feat, s);
+            launch_features(*ix, qc, qs, m, qp.as<float>(), feat, s);
             PF_HIP(hipStreamSynchronize(s));
         } else {
             DevBuf f;
             f.alloc((size_t)m * kSchedIn * sizeof(float));
-            launch_features(*ix, qc, qs, m, f.as<float>(), s);
+            launch_features(*ix, qc, qs, m, qp.as<float>(), f.as<float>(), s);
             PF_HIP(hipMemcpyAsync(feat, f.p, (size_t)m * kSchedIn * sizeof(float), hipMemcpyDeviceToHost, s));
             PF_HIP(hipStreamSynchronize(s));
         }

@@ -25,6 +25,14 @@ def test_features_match_reference():
     got = g.features(Q)
     assert np.array_equal(got[:, :64], ref[:, :64])
     assert np.allclose(got[:, 64:], ref[:, 64:], rtol=1e-6, atol=1e-6)
+    rng = np.random.default_rng(103)
+    ks = rng.choice(np.array([1, 10, 100], dtype=np.int32), size=len(Q))
+    rec = rng.choice(np.array([0.5, 0.9, 0.99, 1.0]), size=len(Q))
+    ref = mlp.features(qs[0], sizes, ks, rec)
+    got = g.features(Q, ks, rec)
+    assert np.array_equal(got[:, 96:], ref[:, 96:].astype(np.float32))
+    with pytest.raises(pf.PfError):
+        g.features(Q, ks, rec * 0.0)
 
 
 def test_forward_and_gradient_match_fp64_reference():
@@ -33,7 +41,7 @@ def test_forward_and_gradient_match_fp64_reference():
     p = (rng.standard_normal(pf.PF_SCHED_PARAMS) * 0.05).astype(np.float32)
     s.set_params(p)
     assert np.array_equal(s.params(), p)
-    x = rng.standard_normal((257, 96)).astype(np.float32)
+    x = rng.standard_normal((257, pf.PF_SCHED_IN)).astype(np.float32)
     t = rng.standard_normal((257, 2)).astype(np.float32)
     y_ref, _ = mlp.forward(p.astype(np.float64), x)
     y = s.predict(x)
@@ -83,3 +91,55 @@ def test_training_learns_query_cost_and_keeps_results(tmp_path):
     s2 = pf.Scheduler(seed=99)
     s2.load(path)
     assert np.array_equal(s2.params(), s.params())
+
+
+def _makespan(cost, order, slots):
+    """Greedy list scheduling: queries leave the queue in `order`, each to the slot that
+    frees first; returns the time the last one ends."""
+    import heapq
+
+    free = [0.0] * slots
+    heapq.heapify(free)
+    for q in order:
+        heapq.heappush(free, heapq.heappop(free) + cost[q])
+    return max(free)
+
+
+def test_learned_order_shortens_makespan():
+    """What the trained network gains over the method without it, on a batch with
+    per-query k and recall: the queue order it predicts (longest first) against the
+    given order and against the order of the true costs, under list scheduling on 64
+    slots with each query's cost taken from its own counters (bytes it reads)."""
+    n, d = 60000, 64
+    cen = workloads.mixture_centers(300, d, 140)
+    X = np.concatenate([workloads.mixture(n // 2, d, cen, 0.3, 141, sigma_mode="norm"),
+                        workloads.gaussian_unit(n // 2, d, 142)])
+    g = pf.Index(X, 0, seed=29, L=40)
+
+    def batch(seed, m):
+        rng = np.random.default_rng(seed)
+        Q = np.concatenate([workloads.mixture(m // 2, d, cen, 0.3, seed + 1, sigma_mode="norm"),
+                            workloads.gaussian_unit(m - m // 2, d, seed + 2)])[rng.permutation(m)]
+        return (Q, rng.choice(np.array([1, 10, 100], dtype=np.int32), size=m),
+                rng.choice(np.array([0.5, 0.9, 0.99]), size=m))
+
+    Qtr, ktr, rtr = batch(150, 6000)
+    st = g.search_batch(Qtr, ktr, rtr, 100).stats
+    target = np.stack([st[:, 0], np.log2(1.0 + st[:, 1])], 1).astype(np.float32)
+    s = pf.Scheduler(seed=6)
+    losses = s.train(g.features(Qtr, ktr, rtr), target, epochs=30, batch=256, lr=2e-3)
+    Q, ks, rec = batch(160, 3000)
+    r = g.search_batch(Q, ks, rec, 100)
+    sb = r.stats
+    cost = 12.0 * sb[:, 1] + 2.0 * d * (sb[:, 3] + sb[:, 4])
+    pred = s.predict(g.features(Q, ks, rec))[:, 1]
+    fifo = _makespan(cost, np.arange(len(Q)), 64)
+    learned = _makespan(cost, np.argsort(-pred, kind="stable"), 64)
+    best = _makespan(cost, np.argsort(-cost, kind="stable"), 64)
+    print(f"[makespan] loss {losses[0]:.3f} -> {losses[-1]:.3f}; fifo {fifo:.4g} learned {learned:.4g} "
+          f"true-cost {best:.4g} (lower bound {cost.sum() / 64:.4g})", flush=True)
+    assert learned < fifo
+    assert learned <= 1.05 * best
+    g.set_scheduler(s)
+    rl = g.search_batch(Q, ks, rec, 100, learned=True)
+    assert np.array_equal(rl.ids, r.ids) and np.array_equal(rl.stats[:, :4], sb[:, :4])

@@ -526,7 +526,7 @@ def test_mlp_gradient_finite_differences():
         pm[i] -= h
         fd = (mlp.loss_and_grad(pp, x, t)[0] - mlp.loss_and_grad(pm, x, t)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(g[i])) + 1e-9, (i, fd, g[i])
-    assert mlp.NPARAMS == 29186
+    assert mlp.NPARAMS == 29442
 
 
 def test_scheduler_features_special_case():
@@ -537,4 +537,10 @@ def test_scheduler_features_special_case():
     assert list(f[0, :5]) == [1.0, 1.0, -1.0, 1.0, -1.0]
     assert np.all(f[0, 5:64] == -1.0)
     assert list(f[0, 64:68]) == [0.0, 1.0, 2.0, 3.0]
-    assert np.all(f[0, 68:] == 0.0)
+    assert np.all(f[0, 68:96] == 0.0)
+    assert f.shape == (1, 98)
+    # log2 k and log2(1/delta): k = 10, recall 0.9 by default; powers of two exactly
+    assert abs(f[0, 96] - 3.321928094887362) < 1e-15 and abs(f[0, 97] - 3.321928094887362) < 1e-12
+    g = mlp.features(np.zeros(3, dtype=np.uint64), np.zeros((3, 32)), ks=[1, 64, 256],
+                     recalls=[0.5, 0.75, 1.0])
+    assert list(g[:, 96]) == [0.0, 6.0, 8.0] and list(g[:, 97]) == [1.0, 2.0, 40.0]

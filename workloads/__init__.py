@@ -153,17 +153,10 @@ def config(c: int, scale: float = 1.0, sigma_mode: str = "coord", query_seed_off
                     name="planted-1M-d256")
     if c == 4:
         n, d = sz(1_000_000), 100
-        m = sz(100_000)
         cen = mixture_centers(10_000, d, CENTER_SEED + 2)
         X = mixture(n, d, cen, 0.3, DATA_SEED + 2, sigma_mode)
-        qa = mixture(m // 2, d, cen, 0.3, QUERY_SEED + 4, sigma_mode)
-        qb = gaussian_unit(m - m // 2, d, QUERY_SEED + 40)
-        Q = np.concatenate([qa, qb])
-        rng = np.random.default_rng(QUERY_SEED + 41)
-        perm = rng.permutation(m)
-        ks = rng.choice(np.array([1, 10, 100], dtype=np.int32), size=m)
-        recalls = rng.choice(np.array([0.5, 0.9, 0.99]), size=m)
-        return dict(points=X, queries=Q[perm], ks=ks, recalls=recalls, k=100, budget=2 << 30,
+        Q, ks, recalls = mixed_queries(sz(100_000), 0, sigma_mode)
+        return dict(points=X, queries=Q, ks=ks, recalls=recalls, k=100, budget=2 << 30,
                     name="mixed-100k-on-1M-d100")
     if c == 5:
         n, d = sz(10_000_000), 128
@@ -188,3 +181,19 @@ def queries_like(c: int, m: int, seed_offset: int = 100, sigma_mode: str = "coor
         return mixture(m, 128, cen, 0.3, QUERY_SEED + 5 + seed_offset, sigma_mode)
     raise ValueError(c)
 
+
+def mixed_queries(m: int, seed_offset: int = 0, sigma_mode: str = "coord"):
+    """Configuration 4's batch (its points are configuration 2's): half the queries from
+    configuration 2's mixture, half i.i.d. Gaussian then normalised (d = 100), shuffled,
+    with per-query k in {1, 10, 100} and recall in {0.5, 0.9, 0.99} drawn uniformly.
+    seed_offset > 0 draws another batch of the same distribution (training traces)."""
+    d = 100
+    cen = mixture_centers(10_000, d, CENTER_SEED + 2)
+    qa = mixture(m // 2, d, cen, 0.3, QUERY_SEED + 4 + seed_offset, sigma_mode)
+    qb = gaussian_unit(m - m // 2, d, QUERY_SEED + 40 + seed_offset)
+    Q = np.concatenate([qa, qb])
+    rng = np.random.default_rng(QUERY_SEED + 41 + seed_offset)
+    perm = rng.permutation(m)
+    ks = rng.choice(np.array([1, 10, 100], dtype=np.int32), size=m)
+    recalls = rng.choice(np.array([0.5, 0.9, 0.99]), size=m)
+    return Q[perm], ks, recalls
