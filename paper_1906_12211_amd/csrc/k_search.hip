@@ -259,7 +259,6 @@ struct SearchK {
     const uint16_t *Xh, *Xl; // upper / lower 16-bit planes of the n x dpad FP32 vectors
     int32_t hs, ls, spare;   // plane row lengths; lower halves of elements < spare sit in
                              // the upper row after its dpad upper halves
-    float rr_slack;          // rounding allowance of the upper-plane bound
     int32_t prefilter;
     const uint32_t *tidx, *off;
     const uint64_t *tsk;
@@ -314,7 +313,8 @@ __device__ __forceinline__ int count_greater(const unsigned long long *arr, int 
 
 struct WLds {
     unsigned long long *top, *ntop, *cand, *tq;
-    uint32_t *pending, *clo, *chi, *qc, *segBeg, *segStart;
+    uint32_t *pending, *clo, *chi, *qc, *segBeg, *segStart, *segTab;
+    uint32_t *qb, *qba; // query as bfloat16 pairs (round to nearest even) and their magnitudes
     float *qv;
 };
 
@@ -322,7 +322,7 @@ __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t
 
 // Byte offsets of the wave's LDS arrays in the dynamic shared memory block.
 struct LdsOff {
-    uint32_t top, ntop, cand, tq, pending, clo, chi, qc, segBeg, segStart, qv, total;
+    uint32_t top, ntop, cand, tq, pending, clo, chi, qc, segBeg, segStart, segTab, qb, qba, qv, total;
 };
 
 __host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad) {
@@ -343,6 +343,9 @@ __host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad) 
     o.qc = take(sizeof(uint32_t) * L);
     o.segBeg = take(sizeof(uint32_t) * 2 * L);
     o.segStart = take(sizeof(uint32_t) * (2 * L + 1));
+    o.segTab = take(sizeof(uint32_t) * 2 * L);
+    o.qb = take(sizeof(uint32_t) * (dpad / 2));
+    o.qba = take(sizeof(uint32_t) * (dpad / 2));
     o.qv = take(sizeof(float) * dpad);
     o.total = off;
     return o;
@@ -441,6 +444,33 @@ __device__ __forceinline__ float4 upper4(uint2 h) {
     return make_float4(__uint_as_float(h.x << 16), __uint_as_float(h.x & 0xFFFF0000u), __uint_as_float(h.y << 16),
                        __uint_as_float(h.y & 0xFFFF0000u));
 }
+// Sum over the 16 lanes of a DPP row in the order s_r + s_{r^8}, then ^4, ^2, ^1, left in
+// every lane.  row_ror:m hands lane r the value of lane (r + m) mod 16; after the steps
+// before it that value equals lane r^m's (the values are equal within each coset of the
+// bits already combined, and IEEE addition commutes), so the result is bit-identical to
+// the butterfly written with exchanges of lanes r and r^m.
+template <int CTRL> __device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row_sum16(float s) {
+    s = s + dpp_f<0x128>(s); // row_ror:8
+    s = s + dpp_f<0x124>(s); // row_ror:4
+    s = s + dpp_f<0x122>(s); // row_ror:2
+    s = s + dpp_f<0x121>(s); // row_ror:1
+    return s;
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+// c + a.lo * b.lo + a.hi * b.hi on bfloat16 pairs (v_dot2c_f32_bf16)
+__device__ __forceinline__ float dot2bf(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
+}
+// bfloat16 bits of a finite FP32 value, rounded to nearest even
+__device__ __forceinline__ uint32_t bf16_rne(float v) {
+    const uint32_t u = __float_as_uint(v);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
 // upper / lower halves of elements base .. base+3 of row id (base a multiple of 4)
 __device__ __forceinline__ uint2 ld_hi(const SearchK &p, uint32_t id, int base) {
     return *reinterpret_cast<const uint2 *>(p.Xh + (int64_t)id * p.hs + base);
@@ -465,29 +495,34 @@ __device__ __forceinline__ void dot_rows(const SearchK &p, const float *qv, cons
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[u] = 0.0f;
     if constexpr (DT > 0) {
-        uint2 hv[U][DT], wv[U][DT];
+        // rows in batches of UB, so that at most 16 (row, chunk) loads per plane are live
+        constexpr int UB = (DT * U > 16) ? 16 / DT : U;
 #pragma unroll
-        for (int t = 0; t < DT; ++t) {
-            const int base = 64 * t + 4 * r;
+        for (int u0 = 0; u0 < U; u0 += UB) {
+            uint2 hv[UB][DT], wv[UB][DT];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = u < cnt && base < dpad;
-                hv[u][t] = ok ? ld_hi(p, ids[u], base) : make_uint2(0u, 0u);
-                wv[u][t] = ok ? ld_lo(p, ids[u], base) : make_uint2(0u, 0u);
+            for (int t = 0; t < DT; ++t) {
+                const int base = 64 * t + 4 * r;
+#pragma unroll
+                for (int v = 0; v < UB; ++v) {
+                    const bool ok = u0 + v < cnt && base < dpad;
+                    hv[v][t] = ok ? ld_hi(p, ids[u0 + v], base) : make_uint2(0u, 0u);
+                    wv[v][t] = ok ? ld_lo(p, ids[u0 + v], base) : make_uint2(0u, 0u);
+                }
             }
-        }
 #pragma unroll
-        for (int t = 0; t < DT; ++t) {
-            const int base = 64 * t + 4 * r;
-            const float4 qq = base < dpad ? *reinterpret_cast<const float4 *>(qv + base)
-                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int t = 0; t < DT; ++t) {
+                const int base = 64 * t + 4 * r;
+                const float4 qq = base < dpad ? *reinterpret_cast<const float4 *>(qv + base)
+                                              : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const float4 xv = join4(hv[u][t], wv[u][t]);
-                acc[u] = acc[u] + xv.x * qq.x;
-                acc[u] = acc[u] + xv.y * qq.y;
-                acc[u] = acc[u] + xv.z * qq.z;
-                acc[u] = acc[u] + xv.w * qq.w;
+                for (int v = 0; v < UB; ++v) {
+                    const float4 xv = join4(hv[v][t], wv[v][t]);
+                    acc[u0 + v] = acc[u0 + v] + xv.x * qq.x;
+                    acc[u0 + v] = acc[u0 + v] + xv.y * qq.y;
+                    acc[u0 + v] = acc[u0 + v] + xv.z * qq.z;
+                    acc[u0 + v] = acc[u0 + v] + xv.w * qq.w;
+                }
             }
         }
     } else {
@@ -510,79 +545,77 @@ __device__ __forceinline__ void dot_rows(const SearchK &p, const float *qv, cons
         }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        float s = acc[u];
-        s = s + __shfl_xor(s, 8, 16);
-        s = s + __shfl_xor(s, 4, 16);
-        s = s + __shfl_xor(s, 2, 16);
-        s = s + __shfl_xor(s, 1, 16);
-        out[u] = s;
-    }
+    for (int u = 0; u < U; ++u) out[u] = row_sum16(acc[u]);
 }
 
 // Upper bounds of the exact inner products of up to U rows per 16-lane group from the
-// upper plane alone.  The upper half of an FP32 pattern is the value truncated to 8
-// significant bits, so |x_i - hi_i| <= 2^-7 |hi_i| (hi_i normal; a zero or subnormal
-// hi_i leaves less than 2^-126), hence
-//   <x, q> <= sum_i hi_i q_i + 2^-7 sum_i |hi_i q_i| + d 2^-126.
-// The exact value the kernel would compute (FP32, fixed order) differs from <x, q> by
-// at most gamma_(chain) sum |x_i q_i|, and the two FP32 sums below by as much again;
-// with unit vectors these and the d 2^-126 term are inside rr_slack, and the relative
-// rounding of the second sum inside the added 2^-20.
+// upper plane alone, with bfloat16 dot products against the query rounded to bfloat16
+// (q_b, |q - q_b| <= 2^-8 |q|).  The upper half of an FP32 pattern is the value truncated
+// to 8 significant bits, so |x_i - hi_i| <= 2^-7 |hi_i| (hi_i normal; a zero or subnormal
+// hi_i leaves less than 2^-126).  With M = sum_i |hi_i q_b,i|,
+//   |<x, q> - sum_i hi_i q_b,i| <= (2^-7 + 2^-8) M / (1 - 2^-8) + 2 d 2^-126.
+// Rounding: a v_dot2c_f32_bf16 step errs by at most 4 units of 2^-24 of the sum of its
+// terms' magnitudes (measured worst case 2.6), a chain of at most 128 of them per lane and
+// the 4 butterfly additions stay below 2^-15 M for both sums; the kernel's exact FP32
+// inner product differs from <x, q> by at most gamma_260 sum |x_i q_i| < 2^-16 M (unit
+// vectors, d <= 4096).  kBoundRel adds these to 0.0117647 and kBoundAbs covers the
+// subnormal terms and the two roundings of the final expression (|ub| <= 1.02).
+constexpr float kBoundRel = 0.011880f;
+constexpr float kBoundAbs = 9.5367431640625e-07f; // 2^-20
 template <int DT, int U>
-__device__ __forceinline__ void bound_rows(const SearchK &p, const float *qv, const uint32_t *ids, int cnt, int r,
+__device__ __forceinline__ void bound_rows(const SearchK &p, const WLds &l, const uint32_t *ids, int cnt, int r,
                                            float *ub) {
     const int32_t dpad = p.dpad;
     float acc[U], mag[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[u] = mag[u] = 0.0f;
     if constexpr (DT > 0) {
-        uint2 hv[U][DT];
+        constexpr int UB = (DT * U > 32) ? 32 / DT : U;
 #pragma unroll
-        for (int t = 0; t < DT; ++t) {
-            const int base = 64 * t + 4 * r;
+        for (int u0 = 0; u0 < U; u0 += UB) {
+            uint2 hv[UB][DT];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                hv[u][t] = (u < cnt && base < dpad) ? ld_hi(p, ids[u], base) : make_uint2(0u, 0u);
-        }
+            for (int t = 0; t < DT; ++t) {
+                const int base = 64 * t + 4 * r;
 #pragma unroll
-        for (int t = 0; t < DT; ++t) {
-            const int base = 64 * t + 4 * r;
-            const float4 qq = base < dpad ? *reinterpret_cast<const float4 *>(qv + base)
-                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int v = 0; v < UB; ++v)
+                    hv[v][t] = (u0 + v < cnt && base < dpad) ? ld_hi(p, ids[u0 + v], base) : make_uint2(0u, 0u);
+            }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const float4 xv = upper4(hv[u][t]);
-                const float a = xv.x * qq.x, b = xv.y * qq.y, c = xv.z * qq.z, e = xv.w * qq.w;
-                acc[u] = acc[u] + ((a + b) + (c + e));
-                mag[u] = mag[u] + ((fabsf(a) + fabsf(b)) + (fabsf(c) + fabsf(e)));
+            for (int t = 0; t < DT; ++t) {
+                const int base = 64 * t + 4 * r;
+                const uint2 qq =
+                    base < dpad ? *reinterpret_cast<const uint2 *>(l.qb + base / 2) : make_uint2(0u, 0u);
+                const uint2 qa =
+                    base < dpad ? *reinterpret_cast<const uint2 *>(l.qba + base / 2) : make_uint2(0u, 0u);
+#pragma unroll
+                for (int v = 0; v < UB; ++v) {
+                    const int u = u0 + v;
+                    acc[u] = dot2bf(hv[v][t].x, qq.x, acc[u]);
+                    acc[u] = dot2bf(hv[v][t].y, qq.y, acc[u]);
+                    mag[u] = dot2bf(hv[v][t].x & 0x7FFF7FFFu, qa.x, mag[u]);
+                    mag[u] = dot2bf(hv[v][t].y & 0x7FFF7FFFu, qa.y, mag[u]);
+                }
             }
         }
     } else {
         for (int base = 4 * r; base < dpad; base += 64) {
-            const float4 qq = *reinterpret_cast<const float4 *>(qv + base);
+            const uint2 qq = *reinterpret_cast<const uint2 *>(l.qb + base / 2);
+            const uint2 qa = *reinterpret_cast<const uint2 *>(l.qba + base / 2);
             uint2 hv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) hv[u] = u < cnt ? ld_hi(p, ids[u], base) : make_uint2(0u, 0u);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const float4 xv = upper4(hv[u]);
-                const float a = xv.x * qq.x, b = xv.y * qq.y, c = xv.z * qq.z, e = xv.w * qq.w;
-                acc[u] = acc[u] + ((a + b) + (c + e));
-                mag[u] = mag[u] + ((fabsf(a) + fabsf(b)) + (fabsf(c) + fabsf(e)));
+                acc[u] = dot2bf(hv[u].x, qq.x, acc[u]);
+                acc[u] = dot2bf(hv[u].y, qq.y, acc[u]);
+                mag[u] = dot2bf(hv[u].x & 0x7FFF7FFFu, qa.x, mag[u]);
+                mag[u] = dot2bf(hv[u].y & 0x7FFF7FFFu, qa.y, mag[u]);
             }
         }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        float s = acc[u], g = mag[u];
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-            s = s + __shfl_xor(s, o, 16);
-            g = g + __shfl_xor(g, o, 16);
-        }
-        ub[u] = s + g * (0.0078125f + 9.5367431640625e-07f) + p.rr_slack;
-    }
+    for (int u = 0; u < U; ++u) ub[u] = row_sum16(acc[u]) + row_sum16(mag[u]) * kBoundRel + kBoundAbs;
 }
 
 // Re-rank rows ids[0..rc); candidates better than the current k-th enter the buffer,
@@ -592,7 +625,10 @@ __device__ __forceinline__ void bound_rows(const SearchK &p, const float *qv, co
 // of ids; only those are read from both planes.
 template <int DT, class TL>
 __device__ void wave_rerank(const SearchK &p, WLds &l, uint32_t *ids, int rc, QState &st) {
-    constexpr int U = TL::U, RROWS = TL::RROWS, CW = TL::CW;
+    // rows of 256 floats (DT = 4) or of any length (DT = 0) take at most 4 rows per group in
+    // flight: 8 would exceed the register file
+    constexpr int U = (DT == 4 || DT == 0) && TL::U > 4 ? 4 : TL::U;
+    constexpr int RROWS = 4 * U, CW = TL::CW;
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
     const uint64_t lt = lanemask_lt(lane);
     if (p.prefilter && st.top == st.k) {
@@ -605,7 +641,7 @@ __device__ void wave_rerank(const SearchK &p, WLds &l, uint32_t *ids, int rc, QS
 #pragma unroll
             for (int u = 0; u < U; ++u) x[u] = u < cnt ? ids[first + u] : 0u;
             float ub[U];
-            bound_rows<DT, U>(p, l.qv, x, cnt, r, ub);
+            bound_rows<DT, U>(p, l, x, cnt, r, ub);
             bool keep = false;
             uint32_t myx = x[0];
 #pragma unroll
@@ -675,19 +711,6 @@ __device__ __forceinline__ void level_range(const SearchK &p, int32_t j, int32_t
     }
 }
 
-// largest s with segStart[s] <= f (segStart[0] = 0 <= f < segStart[ns])
-__device__ __forceinline__ int find_seg(const uint32_t *segStart, int ns, uint32_t f) {
-    int lo = 0, hi = ns;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (segStart[mid] <= f)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 // inclusive scan of a[0..N) in this wave's LDS
 __device__ void wave_scan_incl(uint32_t *a, int N) {
     const int lane = threadIdx.x;
@@ -727,12 +750,14 @@ template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(Searc
     l.qc = reinterpret_cast<uint32_t *>(smem + lo_.qc);
     l.segBeg = reinterpret_cast<uint32_t *>(smem + lo_.segBeg);
     l.segStart = reinterpret_cast<uint32_t *>(smem + lo_.segStart);
+    l.segTab = reinterpret_cast<uint32_t *>(smem + lo_.segTab);
+    l.qb = reinterpret_cast<uint32_t *>(smem + lo_.qb);
+    l.qba = reinterpret_cast<uint32_t *>(smem + lo_.qba);
     l.qv = reinterpret_cast<float *>(smem + lo_.qv);
     const int lane = threadIdx.x;
     const uint64_t lt = lanemask_lt(lane);
     const int32_t L = p.L, K = p.K;
     const int64_t n = p.n;
-    const int ns = 2 * L;
 
     int64_t qi = blockIdx.x;
     if (p.queue) qi = __shfl((int64_t)(lane == 0 ? atomicAdd(p.queue, 1u) : 0u), 0);
@@ -745,6 +770,11 @@ template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(Searc
         st.c_scan = st.c_pass = st.c_rerank = st.c_exact = 0;
         const float *stopw = p.stopw + (int64_t)(p.qtab ? p.qtab[q] : 0) * K * kTauCols;
         for (int c = lane; c < p.dpad; c += WV) l.qv[c] = p.Q[q * p.dpad + c];
+        for (int c = lane; c < p.dpad / 2; c += WV) {
+            const uint32_t w = bf16_rne(p.Q[q * p.dpad + 2 * c]) | (bf16_rne(p.Q[q * p.dpad + 2 * c + 1]) << 16);
+            l.qb[c] = w;
+            l.qba[c] = w & 0x7FFF7FFFu;
+        }
         for (int32_t j = lane; j < L; j += WV) {
             const uint32_t qc = p.qcode[(int64_t)j * p.qstride + q];
             l.qc[j] = qc;
@@ -760,58 +790,88 @@ template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(Searc
         bool stopped = false;
         int stop_level = 0;
         for (int32_t i = K; i >= 1; --i) {
-            // new segments of every table for this level
-            for (int32_t j = lane; j < L; j += WV) {
-                uint32_t lo, hi;
-                level_range(p, j, i, l.qc[j], q, lo, hi);
-                const uint32_t a = l.clo[j], b = l.chi[j];
-                uint32_t na = a, nb = b;
-                if (a > lo) {
-                    const uint64_t sz = ((uint64_t)(a - lo) + p.B - 1) / p.B * (uint64_t)p.B;
-                    na = (a > sz) ? (uint32_t)(a - sz) : 0u;
+            // new entries of this level: per table the whole segments of B added on the left
+            // and on the right of its window; only non-empty segments are listed, in table
+            // order (left before right), with their table
+            uint32_t nseg = 0;
+            for (int32_t j0 = 0; j0 < L; j0 += WV) {
+                const int32_t j = j0 + lane;
+                uint32_t a = 0, b = 0, na = 0, nb = 0;
+                if (j < L) {
+                    uint32_t lo, hi;
+                    level_range(p, j, i, l.qc[j], q, lo, hi);
+                    a = l.clo[j];
+                    b = l.chi[j];
+                    na = a;
+                    nb = b;
+                    if (a > lo) {
+                        const uint64_t sz = ((uint64_t)(a - lo) + p.B - 1) / p.B * (uint64_t)p.B;
+                        na = (a > sz) ? (uint32_t)(a - sz) : 0u;
+                    }
+                    if (b < hi) {
+                        const uint64_t sz = ((uint64_t)(hi - b) + p.B - 1) / p.B * (uint64_t)p.B;
+                        const uint64_t e = (uint64_t)b + sz;
+                        nb = e < (uint64_t)n ? (uint32_t)e : (uint32_t)n;
+                    }
+                    l.clo[j] = na;
+                    l.chi[j] = nb;
                 }
-                if (b < hi) {
-                    const uint64_t sz = ((uint64_t)(hi - b) + p.B - 1) / p.B * (uint64_t)p.B;
-                    const uint64_t e = (uint64_t)b + sz;
-                    nb = e < (uint64_t)n ? (uint32_t)e : (uint32_t)n;
+                const bool left = na < a, right = nb > b;
+                const uint64_t ml = __ballot(left), mr = __ballot(right);
+                uint32_t at = nseg + (uint32_t)(__popcll(ml & lt) + __popcll(mr & lt));
+                if (left) {
+                    l.segBeg[at] = na;
+                    l.segTab[at] = (uint32_t)j;
+                    l.segStart[at + 1] = a - na;
+                    ++at;
                 }
-                l.segBeg[2 * j] = na;
-                l.segBeg[2 * j + 1] = b;
-                l.segStart[2 * j + 1] = a - na;
-                l.segStart[2 * j + 2] = nb - b;
-                l.clo[j] = na;
-                l.chi[j] = nb;
+                if (right) {
+                    l.segBeg[at] = b;
+                    l.segTab[at] = (uint32_t)j;
+                    l.segStart[at + 1] = nb - b;
+                }
+                nseg += (uint32_t)(__popcll(ml) + __popcll(mr));
             }
             wsync();
-            wave_scan_incl(l.segStart + 1, ns);
-            const uint32_t total = l.segStart[ns];
+            wave_scan_incl(l.segStart + 1, (int)nseg);
+            const uint32_t total = l.segStart[nseg];
             st.c_scan += total;
+            // each lane's entries f = base + u * 64 + lane only grow, so it walks the segments
+            // once per level, keeping the current one's end and base offset in registers
+            int sg = -1;
+            uint32_t segEnd = 0, ebase = 0;
+            int32_t tjc = 0;
             for (uint32_t base = 0; base < total; base += WCH) {
-                int s = find_seg(l.segStart, ns, base);
                 uint32_t xv[EPT];
                 int32_t tj[EPT];
                 uint64_t skv[EPT];
                 // sketches and positions of the chunk's entries, all loads in flight together
                 // (a position load made to wait for its sketch test costs a second memory
                 // round trip per chunk, more than the position bytes it saves)
+                // (entries past the end load entry 0 of table 0 and are masked out, so that
+                // every load is unconditional and none waits for another)
+                uint32_t valid = 0;
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
                     const uint32_t f = base + u * WV + lane;
-                    xv[u] = 0xFFFFFFFFu;
-                    tj[u] = 0;
-                    skv[u] = 0;
-                    if (f < total) {
-                        while (l.segStart[s + 1] <= f) ++s;
-                        const uint32_t pos = l.segBeg[s] + (f - l.segStart[s]);
-                        tj[u] = s >> 1;
-                        const uint32_t e = (uint32_t)tj[u] * (uint32_t)n + pos;
-                        skv[u] = p.tsk[e];
-                        xv[u] = p.tidx[e];
+                    const bool in = f < total;
+                    if (in && f >= segEnd) {
+                        do {
+                            ++sg;
+                            segEnd = l.segStart[sg + 1];
+                        } while (f >= segEnd);
+                        tjc = (int32_t)l.segTab[sg];
+                        ebase = (uint32_t)tjc * (uint32_t)n + l.segBeg[sg] - l.segStart[sg];
                     }
+                    valid |= (in ? 1u : 0u) << u;
+                    tj[u] = tjc;
+                    const uint32_t e = in ? ebase + f : 0u;
+                    skv[u] = p.tsk[e];
+                    xv[u] = p.tidx[e];
                 }
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
-                    const bool pass = xv[u] != 0xFFFFFFFFu && __popcll(skv[u] ^ l.tq[tj[u]]) <= tau;
+                    const bool pass = ((valid >> u) & 1u) && __popcll(skv[u] ^ l.tq[tj[u]]) <= tau;
                     const uint64_t mk = __ballot(pass);
                     if (pass) l.pending[st.pend + __popcll(mk & lt)] = xv[u];
                     st.pend += __popcll(mk);
@@ -953,9 +1013,6 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     p.ls = ix.ls;
     p.spare = ix.hs - ix.dpad;
     p.prefilter = a.prefilter;
-    // twice the rounding of the FP32 sums (chains of at most dpad/16 + 4 additions, unit
-    // vectors) plus the d 2^-126 of subnormal upper halves, with room to spare
-    p.rr_slack = (float)((double)(ix.dpad / 16 + 16) * std::ldexp(1.0, -21));
     p.tidx = ix.tidx.as<uint32_t>();
     p.off = ix.off.as<uint32_t>();
     p.tsk = ix.tsk.as<uint64_t>();
