@@ -239,21 +239,21 @@ int32_t rule_table_cols() { return kTauCols; }
 // order array), which balances queries of very different cost.
 //
 // Tile shape: EPT sketch loads in flight per lane in a filter chunk, U rows in flight
-// per 16-lane group in the re-rank; DT = 64-float chunks per row (0 = any length).
+// per 16-lane group in the re-rank, WPE the query waves per SIMD the register allocation
+// must allow (1 = no constraint); DT = 64-float chunks per row (0 = any length).
 static constexpr int WV = 64; // lanes per query wave
-template <int EPT_, int U_> struct Tile {
+template <int EPT_, int U_, int WPE_ = 1> struct Tile {
     static constexpr int EPT = EPT_;
     static constexpr int U = U_;
-    static constexpr int WCH = WV * EPT;   // entries per filter chunk
-    static constexpr int RB = 64;          // re-rank once this many candidates wait
-    static constexpr int PCAP = WCH + RB;  // pending capacity
-    static constexpr int CW = 256;         // candidate buffer (power of two)
-    static constexpr int RROWS = 4 * U;    // rows re-ranked per wave iteration
+    static constexpr int WPE = WPE_;
+    static constexpr int WCH = WV * EPT;       // entries per filter chunk
+    static constexpr int RB = 64;              // re-rank once this many candidates wait
+    static constexpr int PCAP = WCH + RB;      // pending capacity
+    static constexpr int CW = U >= 8 ? 256 : 128; // candidate buffer (power of two)
+    static constexpr int RROWS = 4 * U;        // rows re-ranked per wave iteration
     static_assert(PCAP % WV == 0, "pending capacity must be a multiple of the wave size");
     static_assert(CW >= 4 * RROWS, "candidate buffer holds at least four re-rank slices");
 };
-static constexpr int kMaxPCAP = WV * 16 + 64;
-static constexpr int kCW = 256;
 
 struct SearchK {
     const uint16_t *Xh, *Xl; // upper / lower 16-bit planes of the n x dpad FP32 vectors
@@ -325,7 +325,8 @@ struct LdsOff {
     uint32_t top, ntop, cand, tq, pending, clo, chi, qc, segBeg, segStart, segTab, qb, qba, qv, total;
 };
 
-__host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad) {
+// pcap, cw: the tile's pending and candidate capacities
+__host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad, int pcap, int cw) {
     LdsOff o;
     uint32_t off = 0;
     auto take = [&](size_t bytes) {
@@ -335,9 +336,9 @@ __host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad) 
     };
     o.top = take(sizeof(unsigned long long) * kmax);
     o.ntop = take(sizeof(unsigned long long) * kmax);
-    o.cand = take(sizeof(unsigned long long) * kCW);
+    o.cand = take(sizeof(unsigned long long) * cw);
     o.tq = take(sizeof(unsigned long long) * L);
-    o.pending = take(sizeof(uint32_t) * kMaxPCAP);
+    o.pending = take(sizeof(uint32_t) * pcap);
     o.clo = take(sizeof(uint32_t) * L);
     o.chi = take(sizeof(uint32_t) * L);
     o.qc = take(sizeof(uint32_t) * L);
@@ -351,7 +352,7 @@ __host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad) 
     return o;
 }
 
-inline size_t search_lds_bytes(int L, int kmax, int dpad) { return search_lds_offsets(L, kmax, dpad).total; }
+
 
 // Per-query state kept in registers; every lane holds the same (wave-uniform) values.
 struct QState {
@@ -731,14 +732,15 @@ __device__ void wave_scan_incl(uint32_t *a, int N) {
     wsync();
 }
 
-template <int DT, class TL> __global__ __launch_bounds__(WV) void k_search(SearchK p) {
+template <int DT, class TL>
+__global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) void k_search(SearchK p) {
     constexpr int EPT = TL::EPT, WCH = TL::WCH, RB = TL::RB, PCAP = TL::PCAP;
     extern __shared__ __align__(16) unsigned char smem[];
     // every pointer below is derived from smem by a constant-free offset only, so the
     // compiler keeps them in the LDS address space (ds_read / ds_write, counted by
     // lgkmcnt alone); a generic pointer would turn each LDS access into a flat access
     // that also waits for every global load in flight
-    const LdsOff lo_ = search_lds_offsets(p.L, p.kmax, p.dpad);
+    const LdsOff lo_ = search_lds_offsets(p.L, p.kmax, p.dpad, TL::PCAP, TL::CW);
     WLds l;
     l.top = reinterpret_cast<unsigned long long *>(smem + lo_.top);
     l.ntop = reinterpret_cast<unsigned long long *>(smem + lo_.ntop);
@@ -957,14 +959,29 @@ using T88 = Tile<8, 8>;
 using T48 = Tile<4, 8>;
 using T168 = Tile<16, 8>;
 using T84 = Tile<8, 4>;
-static constexpr int kNumTiles = 4;
-static const char *kTileNames[kNumTiles] = {"ept8-u8", "ept4-u8", "ept16-u8", "ept8-u4"};
+using T84o4 = Tile<8, 4, 4>; // registers capped for 4 waves per SIMD (16 per CU)
+static constexpr int kNumTiles = 5;
+static const char *kTileNames[kNumTiles] = {"ept8-u8", "ept4-u8", "ept16-u8", "ept8-u4", "ept8-u4-o4"};
+
+template <class TL> static size_t tile_lds(const Index &ix, int32_t kmax) {
+    return search_lds_offsets(ix.L, kmax, ix.dpad, TL::PCAP, TL::CW).total;
+}
+static size_t search_lds_bytes(const Index &ix, int32_t kmax, int tile) {
+    switch (tile) {
+    case 1: return tile_lds<T48>(ix, kmax);
+    case 2: return tile_lds<T168>(ix, kmax);
+    case 3: return tile_lds<T84>(ix, kmax);
+    case 4: return tile_lds<T84o4>(ix, kmax);
+    default: return tile_lds<T88>(ix, kmax);
+    }
+}
 
 template <int DT> static const void *search_kernel_dt(int tile) {
     switch (tile) {
     case 1: return (const void *)k_search<DT, T48>;
     case 2: return (const void *)k_search<DT, T168>;
     case 3: return (const void *)k_search<DT, T84>;
+    case 4: return (const void *)k_search<DT, T84o4>;
     default: return (const void *)k_search<DT, T88>;
     }
 }
@@ -984,7 +1001,7 @@ const char *search_tile_name(int32_t t) { return (t >= 0 && t < kNumTiles) ? kTi
 // resident query waves per CU for a tile shape (occupancy from registers and LDS)
 int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile) {
     int per_cu = 0;
-    const size_t lds = search_lds_bytes(ix.L, kmax, ix.dpad);
+    const size_t lds = search_lds_bytes(ix, kmax, tile);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel(row_chunks(ix.dpad), tile), WV, lds) !=
             hipSuccess ||
         per_cu < 1)
@@ -998,9 +1015,9 @@ int64_t search_slots(const Index &ix, int64_t m) {
 
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s) {
     if (a.m <= 0) return;
-    const size_t lds = search_lds_bytes(ix.L, a.kmax, ix.dpad);
     const int dt = row_chunks(ix.dpad);
     const int tile = (a.tile >= 0 && a.tile < kNumTiles) ? a.tile : 0;
+    const size_t lds = search_lds_bytes(ix, a.kmax, tile);
     const void *fn = search_kernel(dt, tile);
     PF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = search_waves_per_cu(ix, a.kmax, tile);

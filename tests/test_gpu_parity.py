@@ -268,7 +268,7 @@ def test_batch_per_query_params_and_order():
     _assert_batch_equal(g.search_batch(Q, ks, recalls, 100, autotune=True, timing=True), oids, oips, ost, obd,
                         "autotuned")
     t = g.last_timing()
-    assert 0 <= t.tile < 4 and t.waves_per_cu >= 1
+    assert 0 <= t.tile < 5 and t.waves_per_cu >= 1
     with pytest.raises(pf.PfError):
         g.search_batch(Q, ks, recalls, 100, order=np.zeros(len(Q), dtype=np.int32))
     bad = ks.copy()
