@@ -54,22 +54,6 @@ def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> floa
     return float(per_q.sum())
 
 
-def exact_topk(X: np.ndarray, Q: np.ndarray, k: int, extra: int = 32) -> np.ndarray:
-    """Exact k-NN ids of normalised Q over normalised X: FP32 BLAS shortlist of k + extra,
-    re-scored in FP64 and ordered by (ip desc, id asc)."""
-    out = np.empty((len(Q), k), dtype=np.int64)
-    for s in range(0, len(Q), 128):
-        q = Q[s:s + 128]
-        G = q @ X.T
-        cand = np.argpartition(-G, k + extra, axis=1)[:, :k + extra]
-        for t in range(len(q)):
-            c = cand[t]
-            ip = X[c].astype(np.float64) @ q[t].astype(np.float64)
-            order = np.lexsort((c, -ip))[:k]
-            out[s + t] = c[order]
-    return out
-
-
 def traffic_entry():
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
     taken on the current search kernel source."""
@@ -180,6 +164,130 @@ def mixed_batch(ix, dev, args):
                                       "p90": float(np.percentile(cost, 90)), "max": float(cost.max())}}
 
 
+def exact_topk_gpu(Xd, Qd, k: int, extra: int = 8):
+    """Exact k-NN ids (ip desc, id asc) of normalised device rows Qd over Xd: every inner
+    product in FP64 on the GPU (the FP32 library GEMM is not used: its rounding reorders
+    the near-tied neighbours of large, nearly uniform point sets), the best k + extra per
+    query ordered on the host."""
+    import torch
+
+    Xd64 = None
+    out = np.empty((Qd.shape[0], k), dtype=np.int64)
+    step = max(1, int(2e9 // (8 * Xd.shape[0])))
+    for s in range(0, Qd.shape[0], step):
+        q = Qd[s:s + step].double()
+        G = torch.empty((q.shape[0], Xd.shape[0]), dtype=torch.float64, device=Xd.device)
+        for c0 in range(0, Xd.shape[0], 1 << 22):
+            G[:, c0:c0 + (1 << 22)] = q @ Xd[c0:c0 + (1 << 22)].double().T
+        v, ix = torch.topk(G, k + extra, dim=1)
+        v, ix = v.cpu().numpy(), ix.cpu().numpy()
+        del G
+        for t in range(len(q)):
+            out[s + t] = ix[t][np.lexsort((ix[t], -v[t]))[:k]]
+    return out
+
+
+def workload_c5(args):
+    """Configuration 5: n = 10,000,000 clustered unit vectors in d = 128 (100,000 clusters),
+    16 GiB budget; the scheduler is trained on 1,000,000 plain-method traces and the three
+    query paths are timed on 100,000 further queries (k = 10, recall 0.9)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    log("generating mixture-10M-d128")
+    c = workloads.config(5, scale=args.scale)
+    X, Qtr, Q = c["points"], c["train_queries"], c["queries"]
+    n, d = X.shape
+    m = len(Q)
+    k, recall = c["k"], c["recall"]
+    Xd = torch.from_numpy(X).to(dev)
+    del X
+    ix = pf.Index(Xd, c["budget"], seed=workloads.INDEX_SEED)
+    info = ix.info()
+    log(f"index built: L={info.L} device build {info.build_ms:.1f} ms, {info.bytes_device / 2**30:.2f} GiB")
+    t0 = time.perf_counter()
+    Qtrd = torch.from_numpy(Qtr).to(dev)
+    ks_t = torch.full((len(Qtr),), k, dtype=torch.int32, device=dev)
+    rec_t = torch.full((len(Qtr),), recall, dtype=torch.float64, device=dev)
+    st = ix.search_batch(Qtrd, ks_t, rec_t, k).stats.cpu().numpy()
+    trace_s = time.perf_counter() - t0
+    target = np.stack([st[:, 0], np.log2(1.0 + st[:, 1])], 1).astype(np.float32)
+    sched = pf.Scheduler(seed=5)
+    t0 = time.perf_counter()
+    losses = sched.train(ix.features(Qtrd), torch.from_numpy(target).to(dev), epochs=5, batch=1024, lr=2e-3)
+    train_s = time.perf_counter() - t0
+    ix.set_scheduler(sched)
+    del Qtrd
+    log(f"{len(Qtr)} traces in {trace_s:.1f} s; scheduler trained in {train_s:.1f} s, "
+        f"loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    Qd = torch.from_numpy(Q).to(dev)
+    ks_d = torch.full((m,), k, dtype=torch.int32, device=dev)
+    rec_d = torch.full((m,), recall, dtype=torch.float64, device=dev)
+    ix.search_batch(Qd, ks_d, rec_d, k, autotune=True)
+    modes = {
+        "plain": lambda: ix.search(Qd, k, recall, timing=True),
+        "batched_fifo": lambda: ix.search_batch(Qd, ks_d, rec_d, k, timing=True),
+        "learned_batched": lambda: ix.search_batch(Qd, ks_d, rec_d, k, learned=True, timing=True),
+    }
+    res = {}
+    steps = max(1, min(args.steps, 5))
+    for name, fn in modes.items():
+        r = fn()
+        torch.cuda.synchronize()
+        ks_ms = []
+        t = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+            ks_ms.append(ix.last_timing().search_ms)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / steps * 1e3
+        res[name] = {"ms_per_step": wall, "qps": m / (wall / 1e3), "search_kernel_ms": float(np.mean(ks_ms)),
+                     "r": r}
+        log(f"{name}: {wall:.2f} ms/step, search kernel {np.mean(ks_ms):.2f} ms")
+    r = res["learned_batched"].pop("r")
+    for v in res.values():
+        v.pop("r", None)
+    stats = r.stats.cpu().numpy()
+    cost = np.log2(1.0 + stats[:, 1])
+    pred = sched.predict(ix.features(Qd)).cpu().numpy()[:, 1]
+    rank = lambda v: np.argsort(np.argsort(v))
+    ns = min(args.recall_sample, m)
+    Xn = torch.from_numpy(ix.export(pf.PF_EXPORT_POINTS)).to(dev)
+    Qn = torch.from_numpy(pf.pf_normalize(Q[:ns])).to(dev)
+    truth = exact_topk_gpu(Xn, Qn, k)
+    del Xn
+    ids = r.ids.cpu().numpy()
+    rec = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(ids[:ns], truth)]))
+    log(f"recall {rec:.4f} on {ns} queries")
+    A = algorithmic_bytes(stats, d, k, info.L, info.K)
+    kms = res["learned_batched"]["search_kernel_ms"]
+    achieved = A / (kms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": res["learned_batched"]["qps"], "unit": "queries/s", "n_gpus": 1,
+        "steps": steps, "warmup": 1, "ms_per_step": res["learned_batched"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": c["name"], "n": n, "d": d, "queries": m, "k": k, "recall_target": recall,
+                   "budget_bytes": c["budget"], "L": info.L, "K": info.K, "M": info.M, "B": 12,
+                   "train_traces": len(Qtr), "path": "learned_batched"},
+        "paths": res,
+        "learned_vs_plain": res["plain"]["ms_per_step"] / res["learned_batched"]["ms_per_step"],
+        "learned_vs_fifo": res["batched_fifo"]["search_kernel_ms"] / kms,
+        "scheduler": {"trace_s": trace_s, "train_s": train_s, "loss_first": float(losses[0]),
+                      "loss_last": float(losses[-1]),
+                      "spearman_pred_vs_true_cost": float(np.corrcoef(rank(pred), rank(cost))[0, 1])},
+        "recall_measured": rec, "recall_sample": ns, "build_ms": info.build_ms,
+        "bytes_device": info.bytes_device,
+        "stop_level_hist": np.bincount(stats[:, 0], minlength=info.K + 1).tolist(),
+        "mean_counts": {"c_scan": float(stats[:, 1].mean()), "c_pass": float(stats[:, 2].mean()),
+                        "c_rerank": float(stats[:, 3].mean()), "c_exact": float(stats[:, 4].mean())},
+        "roofline": {"kernel": "k_search", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": A, "avg_launch_ms": kms},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +303,8 @@ def main():
                     help="scheduler training queries as a multiple of the benchmark query count")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed 100,000-query batch (per-query k and recall, queue orders)")
+    ap.add_argument("--workload", default="mixture-1M-d100", choices=["mixture-1M-d100", "mixture-10M-d128"],
+                    help="mixture-10M-d128: the learned scheduler's 10 M-point configuration (separate line)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -214,6 +324,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": x.numel() * 4}))
+        return
+
+    if args.workload == "mixture-10M-d128":
+        workload_c5(args)
         return
 
     log("generating workload")
@@ -282,9 +396,10 @@ def main():
     stats = r.stats.cpu().numpy()
     ids = r.ids.cpu().numpy()
     ns = min(args.recall_sample, m)
-    Xn = ix.export(pf.PF_EXPORT_POINTS)
-    Qn = pf.pf_normalize(Q[:ns])
-    truth = exact_topk(Xn, Qn, k)
+    Xn = torch.from_numpy(ix.export(pf.PF_EXPORT_POINTS)).to(dev)
+    Qn = torch.from_numpy(pf.pf_normalize(Q[:ns])).to(dev)
+    truth = exact_topk_gpu(Xn, Qn, k)
+    del Xn
     rec = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(ids[:ns], truth)]))
 
     A = algorithmic_bytes(stats, d, k, info.L, info.K)
