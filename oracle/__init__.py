@@ -20,6 +20,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 RULE_FILTER = 0
 RULE_EXACT = 1
 RULE_ALG1 = 2
+RULE_POOL = 3
+DEFAULT_POOL = 3072
 DEFAULT_K = 24
 DEFAULT_M = 32
 DEFAULT_B = 12
@@ -60,9 +62,11 @@ def lib():
         L.oracle_normalize.restype = _I64
         L.oracle_normalize.argtypes = [_P, _I64, _I32]
         L.oracle_num_tables.restype = _I64
-        L.oracle_num_tables.argtypes = [_I64, _I32, _I32, _I32, _U64]
+        L.oracle_num_tables.argtypes = [_I64, _I32, _I32, _I32, _I32, _U64]
+        L.oracle_pool_select.restype = ctypes.c_int
+        L.oracle_pool_select.argtypes = [_U64, _I32, _I32, _I32, _P]
         L.oracle_hash.restype = None
-        L.oracle_hash.argtypes = [_P, _I64, _I32, _P, _I32, _I32, _I32, _P, _P]
+        L.oracle_hash.argtypes = [_P, _I64, _I32, _P, _I32, _I32, _I32, _P, _I32, _P, _P]
         L.oracle_build_tables.restype = ctypes.c_int
         L.oracle_build_tables.argtypes = [_P, _I64, _I32, _I32, _P, _P, _P]
         L.oracle_table_sketches.restype = None
@@ -76,12 +80,12 @@ def lib():
         L.oracle_tau.restype = _D
         L.oracle_tau.argtypes = [ctypes.c_float, _D]
         L.oracle_stop.restype = ctypes.c_int
-        L.oracle_stop.argtypes = [ctypes.c_float, _I32, _I32, _I32, _D, _I32, _I32, ctypes.POINTER(_D)]
+        L.oracle_stop.argtypes = [ctypes.c_float, _I32, _I32, _I32, _D, _I32, _I32, _I32, ctypes.POINTER(_D)]
         L.oracle_binom_cdf64.restype = _D
         L.oracle_binom_cdf64.argtypes = [_D, _I32]
         L.oracle_search.restype = ctypes.c_int
         L.oracle_search.argtypes = [
-            _P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32,
+            _P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P, _I32,
             _P, _I64, _I32, _D, _D, _I32, _I32, _I32,
             _P, _P, _P, _P, _P, _P, _P, _P, _P,
         ]
@@ -119,18 +123,35 @@ def normalize(x: np.ndarray) -> np.ndarray:
     return y
 
 
-def num_tables(n: int, d: int, budget: int, K: int = DEFAULT_K, M: int = DEFAULT_M) -> int:
-    return int(lib().oracle_num_tables(n, d, K, M, budget))
+def num_tables(n: int, d: int, budget: int, K: int = DEFAULT_K, M: int = DEFAULT_M, pool: int = 0) -> int:
+    return int(lib().oracle_num_tables(n, d, K, M, pool, budget))
 
 
-def hash_codes(x: np.ndarray, hp: np.ndarray, L: int, K: int, M: int):
-    """codes[L][n] (u32), sketches[M][n] (u64) of normalised rows x."""
+def pool_select(seed: int, pool: int, L: int, K: int) -> np.ndarray:
+    """sel[L][K]: pool index of h_{t+1,j} for every trie j (pooling, Sec. 3.2)."""
+    sel = np.empty((L, K), dtype=np.int32)
+    rc = lib().oracle_pool_select(seed, pool, L, K, _ptr(sel))
+    if rc:
+        raise ValueError(f"oracle_pool_select rc={rc}")
+    return sel
+
+
+def hash_codes(x: np.ndarray, hp: np.ndarray, L: int, K: int, M: int, sel: np.ndarray | None = None):
+    """codes[L][n] (u32), sketches[M][n] (u64) of normalised rows x; with sel (pooling)
+    hp holds the pool functions, then the sketch functions."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     n, d = x.shape
-    assert hp.shape == (L * K + 64 * M, d)
+    pool = 0
+    if sel is None:
+        assert hp.shape == (L * K + 64 * M, d)
+    else:
+        sel = np.ascontiguousarray(sel, dtype=np.int32)
+        assert sel.shape == (L, K)
+        pool = hp.shape[0] - 64 * M
     codes = np.empty((L, n), dtype=np.uint32)
     sk = np.empty((M, n), dtype=np.uint64)
-    lib().oracle_hash(_ptr(x), n, d, _ptr(np.ascontiguousarray(hp)), L, K, M, _ptr(codes), _ptr(sk))
+    lib().oracle_hash(_ptr(x), n, d, _ptr(np.ascontiguousarray(hp)), L, K, M, _ptr(sel), pool, _ptr(codes),
+                      _ptr(sk))
     return codes, sk
 
 
@@ -175,9 +196,9 @@ def tau(ip_k: float, eps: float = 0.0) -> float:
 
 
 def stop(ip_k: float, i: int, L: int, delta: float, rule: int = RULE_EXACT, M: int = DEFAULT_M,
-         tau_int: int = 64):
+         tau_int: int = 64, pool: int = 0):
     m = _D()
-    r = lib().oracle_stop(ip_k, i, L, M, delta, rule, tau_int, ctypes.byref(m))
+    r = lib().oracle_stop(ip_k, i, L, M, delta, rule, tau_int, pool, ctypes.byref(m))
     return bool(r), float(m.value)
 
 
@@ -220,16 +241,22 @@ class OracleIndex:
     """The index of Sec. 4.1-4.2 built step by step on the CPU."""
 
     def __init__(self, points: np.ndarray, budget: int, seed: int = 42, K: int = DEFAULT_K,
-                 M: int = DEFAULT_M, L: int | None = None):
+                 M: int = DEFAULT_M, L: int | None = None, pool: int = 0):
+        """pool = m > 0: the tries sample their K functions from a pool of m (Sec. 3.2)."""
         pts = np.ascontiguousarray(points, dtype=np.float32)
         self.n, self.d = pts.shape
-        self.K, self.M = K, M
-        self.L = num_tables(self.n, self.d, budget, K, M) if L is None else int(L)
+        self.K, self.M, self.pool = K, M, int(pool)
+        self.L = num_tables(self.n, self.d, budget, K, M, self.pool) if L is None else int(L)
         if self.L < 1:
             raise ValueError("memory budget holds no table")
         self.points = normalize(pts)
-        self.hp = hyperplanes(seed, self.L * K + 64 * M, self.d)
-        codes, self.sketches = hash_codes(self.points, self.hp, self.L, K, M)
+        if self.pool:
+            self.sel = pool_select(seed, self.pool, self.L, K)
+            self.hp = hyperplanes(seed, self.pool + 64 * M, self.d)
+        else:
+            self.sel = None
+            self.hp = hyperplanes(seed, self.L * K + 64 * M, self.d)
+        codes, self.sketches = hash_codes(self.points, self.hp, self.L, K, M, self.sel)
         self.codes = codes
         self.tcode, self.tidx, self.off = build_tables(codes, K)
         self.tsk = table_sketches(self.tidx, self.sketches)
@@ -250,7 +277,8 @@ class OracleIndex:
         tr = np.zeros((self.K + 1, self.L, 4), dtype=np.int64) if trace else None
         rc = lib().oracle_search(
             _ptr(self.points), self.n, self.d, _ptr(self.hp), _ptr(self.tcode), _ptr(self.tidx),
-            _ptr(self.tsk), self.L, self.K, self.M, _ptr(q), m, k, recall, eps, B, rule,
+            _ptr(self.tsk), self.L, self.K, self.M, _ptr(getattr(self, "sel", None)), getattr(self, "pool", 0),
+            _ptr(q), m, k, recall, eps, B, rule,
             1 if filter_on else 0, _ptr(ids), _ptr(ips), _ptr(ips64), _ptr(sl), _ptr(cs),
             _ptr(cp), _ptr(cr), _ptr(bd), _ptr(tr))
         if rc:

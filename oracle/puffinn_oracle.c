@@ -36,6 +36,7 @@
 #define OR_RULE_FILTER 0 /* the bound of Lemma 1 with the sketch filter's misses included */
 #define OR_RULE_EXACT 1  /* L * log1p(-p^i) <= ln(delta): the bound in the proof of Lemma 1 */
 #define OR_RULE_ALG1 2   /* L >= ln(1/delta) / p^i: the test printed in Algorithm 1 */
+#define OR_RULE_POOL 3   /* L p^i >= 2 and m >= 5 i^2 / p: Algorithm 3 (pooling, delta <= 1/2) */
 
 static const double OR_PI = 3.14159265358979323846264338327950288;
 
@@ -95,17 +96,51 @@ int64_t oracle_normalize(float *x, int64_t n, int32_t d) {
  * Index size (Sec. 1 and Sec. 5.2: the user gives only the memory the index may use,
  * and that size counts the data set and the hash functions).  Resident bytes:
  *   fixed     = 4 n d            (FP32 vectors) + 4 (64 M) d (sketch hyperplanes)
+ *             + 4 m d            (with pooling: the m pool hyperplanes, shared)
  *   per table = 16 n             (u32 code, u32 position, u64 table-local sketch)
  *             + 4 (2^P + 1)      (prefix-position table, P = min(13, K))
- *             + 4 K d            (the K hash hyperplanes of the table)
+ *             + 4 K d            (independent functions: the K hyperplanes of the table)
+ *               or 4 K           (pooling: the indices of its K pool functions)
  * L = floor((budget - fixed) / per_table); 0 when the budget holds no table.
+ * pool = m (0: independent functions, Alg. 1).
  * ---------------------------------------------------------------------------------- */
-int64_t oracle_num_tables(int64_t n, int32_t d, int32_t K, int32_t M, uint64_t budget) {
+int64_t oracle_num_tables(int64_t n, int32_t d, int32_t K, int32_t M, int32_t pool, uint64_t budget) {
     int32_t P = K < 13 ? K : 13;
-    uint64_t fixed = 4ull * (uint64_t)n * (uint64_t)d + 4ull * 64ull * (uint64_t)M * (uint64_t)d;
-    uint64_t per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) + 4ull * (uint64_t)K * (uint64_t)d;
+    uint64_t fixed = 4ull * (uint64_t)n * (uint64_t)d + 4ull * 64ull * (uint64_t)M * (uint64_t)d +
+                     4ull * (uint64_t)(pool > 0 ? pool : 0) * (uint64_t)d;
+    uint64_t per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) +
+                   (pool > 0 ? 4ull * (uint64_t)K : 4ull * (uint64_t)K * (uint64_t)d);
     if (budget <= fixed) return 0;
     return (int64_t)((budget - fixed) / per);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Pooling (Sec. 3.2 "Pooling", App. B, Algorithm 3): a pool of m independent hash
+ * functions is shared by the tries, and each trie independently samples a random
+ * subset of K of them (without replacement).  sel[j*K + t] is the pool index of
+ * h_{t+1,j}.  The draws come from the SplitMix64 stream seeded with seed + 1 (the
+ * hyperplanes use the stream seeded with seed): for trie j a fresh array a = 0..m-1 is
+ * shuffled by the first K steps of Fisher-Yates (Knuth's Algorithm P), step t taking
+ * u = t + (z mod (m - t)) with z the output j*K + t, swapping a[t] and a[u], and
+ * selecting a[t].  Returns OR_EINVAL when m < K.
+ * ---------------------------------------------------------------------------------- */
+int oracle_pool_select(uint64_t seed, int32_t pool, int32_t L, int32_t K, int32_t *sel) {
+    if (pool < K || K < 1 || L < 1) return OR_EINVAL;
+    int32_t *a = (int32_t *)malloc((size_t)pool * sizeof(int32_t));
+    if (!a) return OR_ENOMEM;
+    for (int32_t j = 0; j < L; ++j) {
+        for (int32_t r = 0; r < pool; ++r) a[r] = r;
+        for (int32_t t = 0; t < K; ++t) {
+            const uint64_t z = oracle_splitmix64(seed + 1u, (uint64_t)j * (uint64_t)K + (uint64_t)t);
+            const int32_t u = t + (int32_t)(z % (uint64_t)(pool - t));
+            const int32_t tmp = a[t];
+            a[t] = a[u];
+            a[u] = tmp;
+            sel[(int64_t)j * K + t] = a[t];
+        }
+    }
+    free(a);
+    return OR_OK;
 }
 
 /* ------------------------------------------------------------------------------------
@@ -142,9 +177,12 @@ static void dot64_rows(const float *hp, int64_t r0, int cnt, const float *x, int
     out[0] = s0, out[1] = s1, out[2] = s2, out[3] = s3;
 }
 
+/* With pooling (sel != NULL) the hyperplane rows are the pool functions 0..pool-1, then
+ * the sketch bits pool + 64 m + b, and bit s of table j is pool function sel[j*K + s-1]. */
 void oracle_hash(const float *x, int64_t n, int32_t d, const float *hp, int32_t L, int32_t K,
-                 int32_t M, uint32_t *codes, uint64_t *sketches) {
-    const int64_t rows = (int64_t)L * K + 64 * (int64_t)M;
+                 int32_t M, const int32_t *sel, int32_t pool, uint32_t *codes, uint64_t *sketches) {
+    const int64_t srow = sel ? (int64_t)pool : (int64_t)L * K;
+    const int64_t rows = srow + 64 * (int64_t)M;
 #pragma omp parallel
     {
         uint8_t *bit = (uint8_t *)malloc((size_t)rows);
@@ -159,14 +197,16 @@ void oracle_hash(const float *x, int64_t n, int32_t d, const float *hp, int32_t 
             }
             for (int32_t j = 0; j < L; ++j) {
                 uint32_t code = 0;
-                for (int32_t s = 0; s < K; ++s)
-                    if (bit[(int64_t)j * K + s]) code |= 1u << (K - 1 - s);
+                for (int32_t s = 0; s < K; ++s) {
+                    const int64_t row = sel ? (int64_t)sel[(int64_t)j * K + s] : (int64_t)j * K + s;
+                    if (bit[row]) code |= 1u << (K - 1 - s);
+                }
                 codes[(int64_t)j * n + i] = code;
             }
             for (int32_t m = 0; m < M; ++m) {
                 uint64_t sk = 0;
                 for (int32_t b = 0; b < 64; ++b)
-                    if (bit[(int64_t)L * K + 64 * m + b]) sk |= 1ull << b;
+                    if (bit[srow + 64 * m + b]) sk |= 1ull << b;
                 sketches[(int64_t)m * n + i] = sk;
             }
         }
@@ -326,14 +366,26 @@ double oracle_binom_cdf64(double t, int32_t T) {
  * evaluated without cancellation: with a = g_s log1p(-p^i) and x = q expm1(a), the log
  * of the factor is log1p(x) when x > -1/2, else log((1 - q) + q exp(a)) (two
  * non-negative terms).  The test is sum_s log(factor_s) <= ln(delta).  With q = 1 (no
- * filtering) this is the exact rule.  *margin receives the signed distance of the two
- * sides (term - threshold). */
+ * filtering) this is the exact rule.
+ * OR_RULE_POOL is the test of Algorithm 3 (pooling; App. B proves failure probability at
+ * most 1/2 with it, for any delta): after all L tries, stop when the expected number of
+ * collisions with the k-th neighbour is at least two, L p^i >= 2, and the pool is large
+ * enough for Cantelli's inequality, pool >= 5 i^2 / p (evaluated as pool p >= 5 i^2).
+ * delta is not used.  *margin receives the signed distance of the two sides (term -
+ * threshold; for OR_RULE_POOL minus the smaller of the two slacks), <= 0 to stop. */
 int oracle_stop(float ip_k, int32_t i, int32_t L, int32_t M, double delta, int32_t rule,
-                int32_t tau_int, double *margin) {
+                int32_t tau_int, int32_t pool, double *margin) {
     double theta = acos(clamp1((double)ip_k));
     double lnp = log1p(-theta / OR_PI);
     double pi_ = exp((double)i * lnp);
     double lnd = log(delta);
+    if (rule == OR_RULE_POOL) {
+        const double p = 1.0 - theta / OR_PI;
+        const double a = (double)L * pi_ - 2.0, b = (double)pool * p - 5.0 * (double)i * (double)i;
+        const double slack = a < b ? a : b;
+        if (margin) *margin = -slack;
+        return slack >= 0.0;
+    }
     if (rule == OR_RULE_ALG1) {
         /* L * p^i >= -ln(delta) */
         double lhs = (double)L * pi_;
@@ -435,6 +487,7 @@ typedef struct {
     const uint32_t *tcode, *tidx;
     const uint64_t *tsk;
     int32_t L, K, M;
+    int32_t pool; /* pool size m for OR_RULE_POOL (0: independent functions) */
 } or_index;
 
 /* trace (optional, one query): per level i (row i of K+1) and table j:
@@ -528,7 +581,7 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
         if (accumulate(top, fresh, k)) return OR_ENOMEM;
         if (top->len == k) {
             double margin;
-            int stop = oracle_stop(top->v[k - 1].ip, i, L, ix->M, delta, rule, tau_int, &margin);
+            int stop = oracle_stop(top->v[k - 1].ip, i, L, ix->M, delta, rule, tau_int, ix->pool, &margin);
             if (fabs(margin) < 1e-9 * (1.0 + fabs(log(delta)))) *boundary = 1;
             if (stop) {
                 *stop_level = i;
@@ -552,6 +605,8 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
 /* Search m queries.  `queries` are raw rows (normalised here), `points` are the
  * normalised data rows, hp the hyperplanes, (tcode, tidx, tsk) the L sorted tables.
  * recall in (0,1] gives delta = 1 - recall (Sec. 2.1: expected recall (1 - delta)).
+ * sel / pool: the tries' pool functions (NULL / 0 for independent functions); pool is
+ * also the m of OR_RULE_POOL.
  * Outputs per query: ids[k], ips[k] (FP32 order above), ips64[k], stop level, the three
  * counters, and boundary = 1 when a decision came within 1e-9 of flipping (a test of an
  * FP32 ip against an FP64 threshold computed with a different libm may then differ).
@@ -559,12 +614,14 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
  * Returns 0, OR_EINVAL (bad arguments or a zero / non-finite query row), OR_ENOMEM. */
 int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, const uint32_t *tcode,
                   const uint32_t *tidx, const uint64_t *tsk, int32_t L, int32_t K, int32_t M,
+                  const int32_t *sel, int32_t pool,
                   const float *queries, int64_t m, int32_t k, double recall, double eps, int32_t B,
                   int32_t rule, int32_t filter_on, int32_t *ids, float *ips, double *ips64,
                   int32_t *stop_level, int64_t *c_scan, int64_t *c_pass, int64_t *c_rerank,
                   int32_t *boundary, int64_t *trace) {
     if (n < 1 || d < 1 || L < 1 || K < 1 || K > 32 || M < 1 || m < 0 || k < 1 || k > n || B < 1)
         return OR_EINVAL;
+    if (rule == OR_RULE_POOL && pool < 1) return OR_EINVAL;
     if (!(recall > 0.0 && recall <= 1.0)) return OR_EINVAL;
     float *qn = (float *)malloc((size_t)(m > 0 ? m : 1) * (size_t)d * sizeof(float));
     uint32_t *qc = (uint32_t *)malloc((size_t)(m > 0 ? m : 1) * (size_t)L * sizeof(uint32_t));
@@ -579,8 +636,8 @@ int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, co
         return OR_EINVAL;
     }
     /* query codes: table-major like the data codes */
-    oracle_hash(qn, m, d, hp, L, K, M, qc, qs);
-    or_index ix = {points, n, d, tcode, tidx, tsk, L, K, M};
+    oracle_hash(qn, m, d, hp, L, K, M, sel, pool, qc, qs);
+    or_index ix = {points, n, d, tcode, tidx, tsk, L, K, M, pool};
     const double delta = 1.0 - recall;
     int err = OR_OK;
 #pragma omp parallel

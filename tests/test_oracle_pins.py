@@ -544,3 +544,126 @@ def test_scheduler_features_special_case():
     g = mlp.features(np.zeros(3, dtype=np.uint64), np.zeros((3, 32)), ks=[1, 64, 256],
                      recalls=[0.5, 0.75, 1.0])
     assert list(g[:, 96]) == [0.0, 6.0, 8.0] and list(g[:, 97]) == [1.0, 2.0, 40.0]
+
+
+# ----------------------------------------------------------------------- pooling (Sec. 3.2, App. B)
+def test_pool_budget_closed_form(oracle_mod):
+    """With a pool of m functions the budget counts the m shared hyperplanes once and K
+    pool indices per trie: closed-form L at two configurations (hand-computed)."""
+    # n 10,000, d 64, 64 MiB, m 3072: fixed = 2,560,000 + 524,288 + 786,432; per = 160,000 + 32,772 + 96
+    assert oracle_mod.num_tables(10_000, 64, 64 << 20, pool=3072) == (67_108_864 - 3_870_720) // 192_868 == 327
+    # n 1,000,000, d 100, 2 GiB: fixed = 400,000,000 + 819,200 + 1,228,800; per = 16,000,000 + 32,772 + 96
+    assert oracle_mod.num_tables(1_000_000, 100, 2 << 30, pool=3072) == 1_745_435_648 // 16_032_868 == 108
+
+
+def test_pool_selection_is_a_uniform_subset(oracle_mod):
+    """Each trie's K functions are distinct pool indices, every position of the sample is
+    uniform over the pool and every ordered pair of positions uniform over distinct pairs
+    (chi-square over 30,000 tries, m = 12, K = 4), and K = m gives permutations."""
+    m, K, L = 12, 4, 30_000
+    sel = oracle_mod.pool_select(11, m, L, K)
+    assert sel.min() >= 0 and sel.max() < m
+    assert all(len(set(r)) == K for r in sel[:2000])
+    assert np.all(np.sort(sel, axis=1)[:, 1:] != np.sort(sel, axis=1)[:, :-1])
+    for t in range(K):
+        cnt = np.bincount(sel[:, t], minlength=m)
+        assert stats.chisquare(cnt).pvalue > 1e-4, (t, cnt)
+    pair = sel[:, 0] * m + sel[:, 2]
+    cnt = np.bincount(pair, minlength=m * m).reshape(m, m)
+    assert np.all(np.diag(cnt) == 0)
+    off = cnt[~np.eye(m, dtype=bool)]
+    assert stats.chisquare(off).pvalue > 1e-4
+    perm = oracle_mod.pool_select(3, 7, 50, 7)
+    assert np.all(np.sort(perm, axis=1) == np.arange(7))
+    with pytest.raises(ValueError):
+        oracle_mod.pool_select(3, 5, 2, 6)
+
+
+def test_pool_codes_are_pool_bits(oracle_mod):
+    """Bit s of trie j's code (most significant first) is [<a, x> >= 0] for the pool
+    hyperplane a = pool[sel[j][s-1]], recomputed here with numpy in FP64; sketches use the
+    rows after the pool."""
+    m, K, L, M, d = 96, 10, 7, 2, 20
+    hp = oracle_mod.hyperplanes(8, m + 64 * M, d)
+    sel = oracle_mod.pool_select(8, m, L, K)
+    x = oracle_mod.normalize(workloads.gaussian_unit(300, d, 9))
+    codes, sk = oracle_mod.hash_codes(x, hp, L, K, M, sel)
+    proj = x.astype(np.float64) @ hp.astype(np.float64).T
+    bits = proj >= 0
+    for j in range(L):
+        want = np.zeros(len(x), dtype=np.uint64)
+        for s in range(K):
+            want |= bits[:, sel[j, s]].astype(np.uint64) << np.uint64(K - 1 - s)
+        assert np.array_equal(codes[j].astype(np.uint64), want)
+    for mm in range(M):
+        want = np.zeros(len(x), dtype=np.uint64)
+        for b in range(64):
+            want |= bits[:, m + 64 * mm + b].astype(np.uint64) << np.uint64(b)
+        assert np.array_equal(sk[mm], want)
+
+
+def test_pool_prefix_collision_probability(oracle_mod):
+    """A trie's i-bit prefix under pooling collides with probability p^i (distinct pool
+    functions; over the random pool, each agrees with probability p = 1 - theta/pi):
+    pairs at 45 degrees, 400 pools of 256 functions, 24 tries each, i = 1..4."""
+    d, K, L, m = 16, 8, 24, 256
+    rng = np.random.default_rng(21)
+    q = rng.standard_normal(d)
+    q /= np.linalg.norm(q)
+    w = rng.standard_normal(d)
+    w -= (w @ q) * q
+    w /= np.linalg.norm(w)
+    x = np.cos(np.pi / 4) * q + np.sin(np.pi / 4) * w
+    pts = np.stack([q, x]).astype(np.float32)
+    p = 1 - 0.25
+    agree = np.zeros(4)
+    total = 0
+    for s in range(400):
+        hp = oracle_mod.hyperplanes(100 + s, m + 64, d)
+        sel = oracle_mod.pool_select(100 + s, m, L, K)
+        codes, _ = oracle_mod.hash_codes(pts, hp, L, K, 1, sel)
+        for i in range(1, 5):
+            agree[i - 1] += np.sum((codes[:, 0] >> (K - i)) == (codes[:, 1] >> (K - i)))
+        total += L
+    rate = agree / total
+    for i in range(1, 5):
+        sd = math.sqrt(p ** i * (1 - p ** i) / total) * 4  # pools make the trials dependent
+        assert abs(rate[i - 1] - p ** i) < 4 * sd + 0.01, (i, rate[i - 1], p ** i)
+
+
+def test_pool_stop_rule_closed_form(oracle_mod):
+    """Algorithm 3's test L p^i >= 2 and m >= 5 i^2 / p at ip = 0 (p = 1/2 exactly):
+    with L = 16 the first condition holds for i <= 3; m = 3072 allows i <= 17 and m = 40
+    only i <= 2.  delta plays no part."""
+    for delta in (0.9, 0.5, 0.01):
+        for i in range(1, 25):
+            got, _ = oracle_mod.stop(0.0, i, 16, delta, oracle_mod.RULE_POOL, pool=3072)
+            assert got == (i <= 3), i
+            got, _ = oracle_mod.stop(0.0, i, 16, delta, oracle_mod.RULE_POOL, pool=40)
+            assert got == (i <= 2), i
+    # larger ip, p = 1 - acos(ip)/pi; L = 100: L p^i >= 2 iff i <= ln(50)/ln(1/p)
+    for ipk in (0.3, 0.6, 0.9):
+        p = 1 - math.acos(float(np.float32(ipk))) / math.pi
+        for i in range(1, 25):
+            want = 100 * p ** i >= 2 and 3072 * p >= 5 * i * i
+            got, _ = oracle_mod.stop(ipk, i, 100, 0.1, oracle_mod.RULE_POOL, pool=3072)
+            assert got == want, (ipk, i)
+
+
+def test_pool_guarantee_statistical(oracle_mod):
+    """Appendix B: with pooling and Algorithm 3's test each true neighbour is found with
+    probability at least 1/2 (filter off; 200 index seeds, pool of 64 functions so that
+    the pool condition binds at deep levels)."""
+    X = workloads.gaussian_unit(400, 32, 81)
+    Q = workloads.gaussian_unit(4, 32, 82)
+    k = 3
+    true_ids, _ = oracle_mod.bruteforce(oracle_mod.normalize(X), oracle_mod.normalize(Q), k)
+    seeds = 200
+    hits = np.zeros((len(Q), k))
+    for s in range(seeds):
+        ix = oracle_mod.OracleIndex(X, budget=0, L=12, seed=7000 + s, M=2, pool=64)
+        r = ix.search(Q, k, 0.5, rule=oracle_mod.RULE_POOL, filter_on=False)
+        for t in range(len(Q)):
+            hits[t] += np.isin(true_ids[t], r.ids[t])
+    rate = hits / seeds
+    assert np.all(rate >= 0.5 - 4 * math.sqrt(0.25 / seeds)), rate
