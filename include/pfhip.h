@@ -41,6 +41,9 @@ extern "C" {
 #define PF_RULE_FILTER 0 /* Lemma 1's bound with the sketch filter's misses (default)    */
 #define PF_RULE_EXACT 1  /* Lemma 1's bound (1 - p^i)^L <= delta, filter not accounted   */
 #define PF_RULE_ALG1 2   /* Algorithm 1's printed test L >= ln(1/delta) / p^i            */
+#define PF_RULE_POOL 3   /* Algorithm 3 (pooling, App. B): L p^i >= 2 and m >= 5 i^2 / p;
+                            failure probability at most 1/2 whatever the recall; needs an
+                            index built with a pool                                       */
 
 /* hashing arithmetic, see pf_build_opts.hash_mode */
 #define PF_HASH_BF16X3 0 /* BF16 MFMA (three split products, FP32 accumulate), bits whose
@@ -49,11 +52,13 @@ extern "C" {
 
 /* what pf_export copies */
 #define PF_EXPORT_POINTS 0      /* n x d FP32, the normalised vectors                  */
-#define PF_EXPORT_HYPERPLANES 1 /* (L*K + 64*M) x d FP32                               */
+#define PF_EXPORT_HYPERPLANES 1 /* (L*K + 64*M) x d FP32; with a pool (m + 64*M) x d:
+                                   the pool functions, then the sketch functions        */
 #define PF_EXPORT_CODES 2       /* L x n u32, sorted codes of each table               */
 #define PF_EXPORT_IDX 3         /* L x n u32, point position of each sorted entry      */
 #define PF_EXPORT_SKETCHES 4    /* L x n u64, table-local sketches                     */
 #define PF_EXPORT_OFFSETS 5     /* L x (2^P + 1) u32, P = min(13, K), prefix table     */
+#define PF_EXPORT_POOL_SEL 6    /* L x K int32: pool index of h_{t+1,j} (pooled index) */
 
 /* limits of this implementation */
 #define PF_MAX_TABLES 512
@@ -68,13 +73,17 @@ typedef struct {
     int32_t M;          /* 64-bit sketches per point, 1..64; 0 selects 32           */
     int32_t hash_mode;  /* PF_HASH_BF16X3 (default) or PF_HASH_FP64                  */
     int32_t L_override; /* > 0: use exactly this many tables, ignore the budget rule  */
+    int32_t pool;       /* 0: K independent functions per table (Algorithm 1);
+                           m > 0: pooling (Sec. 3.2), every table samples K of m shared
+                           functions without replacement; m a multiple of 32 in [K, 65536] */
 } pf_build_opts;
 
 /* All-zero options are the defaults. */
 typedef struct {
     double eps;        /* filter slack: tau = (1 + eps) * 64 * theta_k / pi; default 0 */
     int32_t B;         /* segment size of every array access; 0 selects 12             */
-    int32_t rule;      /* PF_RULE_FILTER (default), PF_RULE_EXACT or PF_RULE_ALG1       */
+    int32_t rule;      /* PF_RULE_FILTER (default), PF_RULE_EXACT, PF_RULE_ALG1 or
+                          PF_RULE_POOL (pooled index only)                              */
     int32_t no_filter; /* 1: sketch filter off (every retrieved candidate re-ranked)   */
     int32_t timing;    /* 1: record per-kernel durations of this call (pf_last_timing) */
     int32_t no_prefilter; /* 1: compute every re-ranked inner product from both 16-bit
@@ -96,7 +105,7 @@ typedef struct {
 
 typedef struct {
     int64_t n;
-    int32_t d, L, K, M, P, reserved;
+    int32_t d, L, K, M, P, pool; /* pool: m of a pooled index, 0 otherwise */
     uint64_t bytes_budget_rule; /* bytes the budget rule counts for this index        */
     uint64_t bytes_device;      /* device bytes the index actually holds              */
     double build_ms;            /* device time of the last build, if measured         */
@@ -128,8 +137,12 @@ int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, 
  *  K random-hyperplane functions per table (Sec. 2.2), M 64-bit sketches per point
  *  (Sec. 4.2), each table sorted by its K-bit code with equal codes by position, and a
  *  table of the positions of every P-bit prefix (Sec. 4.2, P = min(13, K)).
+ *  With opts->pool = m (Sec. 3.2 "Pooling"): m shared hyperplanes, each table's K
+ *  functions drawn from them without replacement (Fisher-Yates on the SplitMix64 stream
+ *  seeded with seed + 1), and the budget counts 4md once and 4K per table instead of
+ *  4Kd.
  * `points` n x d (caller-owned, copied).  Errors: PF_EINVAL (n < 1, n >= 2^31, d < 1,
- * d > PF_MAX_DIM, bad row, K or M out of range), PF_EBUDGET, PF_ENOMEM, PF_EDEVICE.
+ * d > PF_MAX_DIM, bad row, K, M or pool out of range), PF_EBUDGET, PF_ENOMEM, PF_EDEVICE.
  * Synchronises the stream before returning. */
 int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t memory_budget_bytes,
                    const pf_build_opts *opts, int32_t mem, void *stream, pf_index **out);

@@ -216,22 +216,63 @@ __global__ __launch_bounds__(256) void k_hash_fp64(const float *__restrict__ X, 
     }
 }
 
+// Pooling (Sec. 3.2): table j's code from the pool bits, h_{t+1,j} = pool function
+// sel[j K + t] as bit K-1-t.  One thread per (point, table); pool bits word-major.
+__global__ __launch_bounds__(256) void k_pool_codes(const uint32_t *__restrict__ pbits, int64_t n,
+                                                    const int32_t *__restrict__ sel, int32_t L, int32_t K,
+                                                    uint32_t *__restrict__ codes) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t j = blockIdx.y;
+    if (i >= n || j >= L) return;
+    uint32_t code = 0;
+    for (int32_t t = 0; t < K; ++t) {
+        const int32_t f = sel[(int64_t)j * K + t];
+        code |= ((pbits[(int64_t)(f >> 5) * n + i] >> (f & 31)) & 1u) << (K - 1 - t);
+    }
+    codes[(int64_t)j * n + i] = code;
+}
+
+static void hash_gemm(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint32_t *skw, uint32_t kmask,
+                      const int32_t *colrow, DevBuf &scratch, hipStream_t s);
+
 void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
                DevBuf &scratch, hipStream_t s) {
     if (n <= 0) return;
     const HashPlan &hp = ix.plan;
-    launch_fill_u32(codes, n * (int64_t)hp.L, 0u, s);
+    DevBuf pool_bits;
+    uint32_t *table_codes = codes;
+    if (hp.pool) {
+        // the GEMM writes the pool bits; the codes are gathered from them at the end
+        pool_bits.alloc((size_t)n * hp.cw * sizeof(uint32_t));
+        codes = pool_bits.as<uint32_t>();
+    }
+    launch_fill_u32(codes, n * (int64_t)hp.cw, 0u, s);
     launch_fill_u32(reinterpret_cast<uint32_t *>(sketches), 2 * n * (int64_t)hp.M, 0u, s);
-    const uint32_t kmask = hp.K >= 32 ? 0xFFFFFFFFu : ((1u << hp.K) - 1u);
+    const uint32_t kmask = (hp.pool || hp.K >= 32) ? 0xFFFFFFFFu : ((1u << hp.K) - 1u);
     uint32_t *skw = reinterpret_cast<uint32_t *>(sketches);
     const int32_t *colrow = ix.hcolrow.as<int32_t>();
     if (ix.hash_mode == PF_HASH_FP64 || hp.kp > 512) {
         const int64_t tasks = n * (int64_t)((hp.words + 1) / 2);
         hipLaunchKernelGGL(k_hash_fp64, dim3((unsigned)((tasks + 3) / 4)), dim3(256), 0, s, X, n,
-                           ix.dpad, hp.d, ix.hp.as<float>(), colrow, hp.words, hp.L, kmask, codes, skw);
+                           ix.dpad, hp.d, ix.hp.as<float>(), colrow, hp.words, hp.cw, kmask, codes, skw);
         PF_HIP(hipGetLastError());
-        return;
+    } else {
+        hash_gemm(ix, X, n, codes, skw, kmask, colrow, scratch, s);
     }
+    if (hp.pool) {
+        hipLaunchKernelGGL(k_pool_codes, dim3((unsigned)((n + 255) / 256), (unsigned)hp.L), dim3(256), 0, s,
+                           (const uint32_t *)codes, n, ix.psel.as<int32_t>(), hp.L, hp.K, table_codes);
+        PF_HIP(hipGetLastError());
+        // pool_bits must outlive the kernels that read it
+        PF_HIP(hipStreamSynchronize(s));
+    }
+}
+
+// split-BF16 GEMM of the rows against the plan's columns, then the FP64 fix of the
+// flagged bits
+static void hash_gemm(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint32_t *skw, uint32_t kmask,
+                      const int32_t *colrow, DevBuf &scratch, hipStream_t s) {
+    const HashPlan &hp = ix.plan;
     const uint64_t want = (uint64_t)n * (uint64_t)hp.ncols / 64u + 65536u;
     const uint32_t fcap = (uint32_t)std::min<uint64_t>(want, 1ull << 30);
     scratch.ensure(256 + (size_t)fcap * 8);
@@ -253,18 +294,18 @@ void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint
         PF_HIP(hipFuncSetAttribute((const void *)k_hash_bf16x3<32>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k_hash_bf16x3<32>, dim3((unsigned)bx, (unsigned)gy), dim3(256), lds, s, X, n,
-                           ix.dpad, hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.L, kmask, wpy,
+                           ix.dpad, hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.cw, kmask, wpy,
                            codes, skw, flist, fcount, fcap);
     } else {
         PF_HIP(hipFuncSetAttribute((const void *)k_hash_bf16x3<64>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(k_hash_bf16x3<64>, dim3((unsigned)bx, (unsigned)gy), dim3(256), lds, s, X, n,
-                           ix.dpad, hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.L, kmask, wpy,
+                           ix.dpad, hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.cw, kmask, wpy,
                            codes, skw, flist, fcount, fcap);
     }
     PF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_hash_fix, dim3(1024), dim3(256), 0, s, X, n, ix.dpad, hp.d, ix.hp.as<float>(),
-                       colrow, hp.words, hp.L, kmask, codes, skw, flist, fcount, fcap);
+                       colrow, hp.words, hp.cw, kmask, codes, skw, flist, fcount, fcap);
     PF_HIP(hipGetLastError());
 }
 

@@ -96,18 +96,24 @@ static void build_plan(Index &ix, const std::vector<float> &hp) {
     p.L = ix.L;
     p.K = ix.K;
     p.M = ix.M;
-    p.words = ix.L + 2 * ix.M;
+    p.pool = ix.pool;
+    p.cw = ix.pool ? ix.pool / 32 : ix.L;
+    p.words = p.cw + 2 * ix.M;
     p.ncols = 32 * p.words;
+    const int64_t srow = ix.pool ? (int64_t)ix.pool : (int64_t)ix.L * ix.K; // first sketch row
     std::vector<int32_t> colrow(p.ncols, -1);
     std::vector<float> beta(p.ncols, -1.0f);
     for (int32_t wb = 0; wb < p.words; ++wb)
         for (int32_t c = 0; c < 32; ++c) {
             int64_t row = -1;
-            if (wb < ix.L) {
-                if (c < ix.K) row = (int64_t)wb * ix.K + (ix.K - 1 - c);
+            if (wb < p.cw) {
+                if (ix.pool)
+                    row = (int64_t)wb * 32 + c;
+                else if (c < ix.K)
+                    row = (int64_t)wb * ix.K + (ix.K - 1 - c);
             } else {
-                const int32_t s = wb - ix.L;
-                row = (int64_t)ix.L * ix.K + 64 * (s >> 1) + 32 * (s & 1) + c;
+                const int32_t s = wb - p.cw;
+                row = srow + 64 * (s >> 1) + 32 * (s & 1) + c;
             }
             colrow[wb * 32 + c] = (int32_t)row;
         }
@@ -136,11 +142,32 @@ static void build_plan(Index &ix, const std::vector<float> &hp) {
     PF_HIP(hipMemcpy(ix.hbf.p, hb.data(), hb.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
 }
 
-// budget rule: bytes of the vectors and sketch functions, and bytes per table
-static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, uint64_t &fixed, uint64_t &per) {
+// budget rule: bytes of the vectors, sketch functions and (pooled) pool functions, and
+// bytes per table (its K functions, or with a pool their K indices)
+static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, int32_t pool, uint64_t &fixed, uint64_t &per) {
     const int32_t P = std::min(13, K);
-    fixed = 4ull * (uint64_t)n * (uint64_t)d + 4ull * 64ull * (uint64_t)M * (uint64_t)d;
-    per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) + 4ull * (uint64_t)K * (uint64_t)d;
+    fixed = 4ull * (uint64_t)n * (uint64_t)d + 4ull * 64ull * (uint64_t)M * (uint64_t)d +
+            4ull * (uint64_t)pool * (uint64_t)d;
+    per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) +
+          (pool ? 4ull * (uint64_t)K : 4ull * (uint64_t)K * (uint64_t)d);
+}
+
+// Pooling (Sec. 3.2): table j's K functions, h_{t+1,j} = pool function sel[j K + t],
+// drawn without replacement by the first K steps of Fisher-Yates on a fresh 0..m-1
+// array; step t takes u = t + (z mod (m - t)) with z output j K + t of the SplitMix64
+// stream seeded with seed + 1.
+static std::vector<int32_t> pool_select(uint64_t seed, int32_t pool, int32_t L, int32_t K) {
+    std::vector<int32_t> sel((size_t)L * K), a(pool);
+    for (int32_t j = 0; j < L; ++j) {
+        for (int32_t r = 0; r < pool; ++r) a[r] = r;
+        for (int32_t t = 0; t < K; ++t) {
+            const uint64_t z = splitmix64_at(seed + 1u, (uint64_t)j * (uint64_t)K + (uint64_t)t);
+            const int32_t u = t + (int32_t)(z % (uint64_t)(pool - t));
+            std::swap(a[t], a[u]);
+            sel[(size_t)j * K + t] = a[t];
+        }
+    }
+    return sel;
 }
 
 static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -208,8 +235,10 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         PF_CHECK(M >= 1 && M <= 64, PF_EINVAL, "pf_build_index: M must be in [1, 64]");
         PF_CHECK(o.hash_mode == PF_HASH_BF16X3 || o.hash_mode == PF_HASH_FP64, PF_EINVAL,
                  "pf_build_index: bad hash_mode");
+        PF_CHECK(o.pool == 0 || (o.pool >= K && o.pool <= 65536 && o.pool % 32 == 0), PF_EINVAL,
+                 "pf_build_index: pool must be 0 or a multiple of 32 in [K, 65536]");
         uint64_t fixed, per;
-        budget_terms(n, d, K, M, fixed, per);
+        budget_terms(n, d, K, M, o.pool, fixed, per);
         int64_t L = o.L_override;
         if (L <= 0) L = budget > fixed ? (int64_t)((budget - fixed) / per) : 0;
         PF_CHECK(L >= 1, PF_EBUDGET, "pf_build_index: the memory budget holds no table");
@@ -232,6 +261,7 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         ix->L = (int32_t)L;
         ix->seed = o.seed;
         ix->hash_mode = o.hash_mode;
+        ix->pool = o.pool;
         ix->bytes_rule = fixed + (uint64_t)L * per;
 
         hipEvent_t e0, e1;
@@ -244,11 +274,16 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         normalize_into(points, n, d, mem, X.as<float>(), ix->dpad, ix->tmp, ix->flags, s);
         ix->tmp.release();
         // a3: hyperplanes (host generator), device copies and hash plan
-        const int64_t rows = L * K + 64ll * M;
+        const int64_t rows = (o.pool ? (int64_t)o.pool : L * K) + 64ll * M;
         std::vector<float> hp((size_t)rows * d);
         make_hyperplanes(o.seed, rows, d, hp.data());
         ix->hp.alloc(hp.size() * sizeof(float));
         PF_HIP(hipMemcpy(ix->hp.p, hp.data(), hp.size() * sizeof(float), hipMemcpyHostToDevice));
+        if (o.pool) {
+            const std::vector<int32_t> sel = pool_select(o.seed, o.pool, (int32_t)L, K);
+            ix->psel.alloc(sel.size() * sizeof(int32_t));
+            PF_HIP(hipMemcpy(ix->psel.p, sel.data(), sel.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        }
         build_plan(*ix, hp);
         // a4/a5: codes (L x n) and sketches (M x n)
         DevBuf codes, sk, scratch;
@@ -421,7 +456,9 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     if (opts) o = *opts;
     if (o.B == 0) o.B = 12;
     PF_CHECK(o.B >= 1, PF_EINVAL, "search: B must be >= 1");
-    PF_CHECK(o.rule == PF_RULE_FILTER || o.rule == PF_RULE_EXACT || o.rule == PF_RULE_ALG1, PF_EINVAL,
+    PF_CHECK(o.rule != PF_RULE_POOL || ix->pool > 0, PF_EINVAL, "search: PF_RULE_POOL needs a pooled index");
+    PF_CHECK(o.rule == PF_RULE_FILTER || o.rule == PF_RULE_EXACT || o.rule == PF_RULE_ALG1 || o.rule == PF_RULE_POOL,
+             PF_EINVAL,
              "search: bad rule");
     PF_CHECK(std::isfinite(o.eps) && o.eps > -1.0, PF_EINVAL, "search: eps must be finite and > -1");
     if (!recalls)
@@ -483,7 +520,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         double *dl = reinterpret_cast<double *>(ix->rule_tab.as<char>() + dl_off);
         PF_HIP(hipMemcpyAsync(dl, lnd.data(), lnd.size() * sizeof(double), h2d, s));
         float *tab = ix->rule_tab.as<float>();
-        launch_rule_tables(dl, (int32_t)lnd.size(), o.eps, o.rule, ix->L, ix->M, ix->K, tab, tab + 65, s);
+        launch_rule_tables(dl, (int32_t)lnd.size(), o.eps, o.rule, ix->L, ix->M, ix->K, ix->pool, tab, tab + 65, s);
         PF_HIP(hipStreamSynchronize(s));
         ix->rule_key_rule = o.rule;
         ix->rule_key_eps = o.eps;
@@ -674,7 +711,7 @@ PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_by
             break;
         }
         case PF_EXPORT_HYPERPLANES: {
-            const int64_t b = ((int64_t)ix->L * ix->K + 64ll * ix->M) * ix->d * 4;
+            const int64_t b = ((ix->pool ? (int64_t)ix->pool : (int64_t)ix->L * ix->K) + 64ll * ix->M) * ix->d * 4;
             need(b);
             PF_HIP(hipMemcpyAsync(dst, ix->hp.p, (size_t)b, kind, s));
             break;
@@ -697,6 +734,13 @@ PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_by
             PF_HIP(hipMemcpyAsync(dst, ix->off.p, (size_t)b, kind, s));
             break;
         }
+        case PF_EXPORT_POOL_SEL: {
+            PF_CHECK(ix->pool > 0, PF_EINVAL, "pf_export: the index has no pool");
+            const int64_t b = (int64_t)ix->L * ix->K * 4;
+            need(b);
+            PF_HIP(hipMemcpyAsync(dst, ix->psel.p, (size_t)b, kind, s));
+            break;
+        }
         default:
             throw Error(PF_EINVAL, "pf_export: unknown structure");
         }
@@ -714,9 +758,10 @@ PF_API int pf_index_info(const pf_index *ix, pf_info *info) {
         r.K = ix->K;
         r.M = ix->M;
         r.P = ix->P;
+        r.pool = ix->pool;
         r.bytes_budget_rule = ix->bytes_rule;
         r.bytes_device = ix->Xh.bytes + ix->Xl.bytes + ix->hp.bytes + ix->hcolrow.bytes + ix->hbf.bytes + ix->hbeta.bytes +
-                         ix->tcode.bytes + ix->tidx.bytes + ix->tsk.bytes + ix->off.bytes;
+                         ix->psel.bytes + ix->tcode.bytes + ix->tidx.bytes + ix->tsk.bytes + ix->off.bytes;
         r.build_ms = ix->build_ms;
         *info = r;
     });

@@ -61,10 +61,14 @@ struct DevBuf {
 //   word w < L        : table w's code, column c of the word = code bit c
 //                       (c < K: hyperplane h_{K-c, w}; c >= K: zero padding)
 //   word L + 2m + h    : sketch m, bits 32h .. 32h+31
+// With a pool of m functions the first m / 32 words hold the pool bits (column c of word
+// w = pool function 32 w + c) and table codes are gathered from them afterwards.
 struct HashPlan {
     int32_t d = 0, dpad = 0, kp = 0; // kp: reduction length padded to the MFMA step
     int32_t L = 0, K = 0, M = 0;
-    int32_t words = 0;  // L + 2M
+    int32_t cw = 0;     // code words: L, or m / 32 with a pool
+    int32_t pool = 0;   // m (0: independent functions)
+    int32_t words = 0;  // cw + 2M
     int32_t ncols = 0;  // 32 * words
 };
 
@@ -72,6 +76,7 @@ struct Index {
     int64_t n = 0;
     int32_t d = 0, dpad = 0, L = 0, K = 0, M = 0, P = 0;
     int32_t hash_mode = PF_HASH_BF16X3;
+    int32_t pool = 0; // m of a pooled index (0: independent functions)
     uint64_t seed = 0;
     uint64_t bytes_rule = 0;
     double build_ms = 0.0;
@@ -87,7 +92,8 @@ struct Index {
     // candidate out
     DevBuf Xh, Xl;
     int32_t hs = 0, ls = 0;
-    DevBuf hp;     // (L*K + 64*M) x d FP32 hyperplanes (paper order)
+    DevBuf hp;     // (L*K + 64*M) x d FP32 hyperplanes (paper order); pooled: (m + 64*M) x d
+    DevBuf psel;   // pooled: L x K int32, pool index of h_{t+1,j}
     DevBuf hcolrow;// ncols int32: hyperplane row of each GEMM column (-1 = padding)
     DevBuf hbf;    // ncols x kp bf16 hi parts, then ncols x kp bf16 lo parts
     DevBuf hbeta;  // ncols FP32 flag bounds (negative = never flagged)
@@ -187,7 +193,7 @@ struct SearchArgs {
 };
 void launch_ranges(const Index &ix, const SearchArgs &a, uint32_t *ranges, hipStream_t s);
 void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, int32_t rule, int32_t L,
-                        int32_t M, int32_t K, float *tauv, float *stopw, hipStream_t s);
+                        int32_t M, int32_t K, int32_t pool, float *tauv, float *stopw, hipStream_t s);
 int32_t rule_table_cols();
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s);
 int64_t search_slots(const Index &ix, int64_t m);

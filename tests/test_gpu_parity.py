@@ -290,3 +290,45 @@ def test_batch_device_tensors():
     torch.cuda.synchronize()
     gr = pf.SearchResult(r.ids.cpu().numpy(), r.ips.cpu().numpy(), r.stats.cpu().numpy())
     _assert_batch_equal(gr, oids, oips, ost, obd, "device")
+
+
+def _build_pool(X, L, pool, seed=42, K=24, M=32, hash_mode=pf.PF_HASH_BF16X3, budget=0):
+    print(f"[build pool] n={len(X)} d={X.shape[1]} L={L} pool={pool} K={K} M={M} mode={hash_mode}", flush=True)
+    g = pf.Index(X, budget, seed=seed, K=K, M=M, hash_mode=hash_mode, L=L, pool=pool)
+    o = oracle.OracleIndex(X, budget, seed=seed, K=K, M=M, L=g.L, pool=pool)
+    return g, o
+
+
+@pytest.mark.parametrize("n,d,L,pool,K,M,mode", [(3000, 64, 20, 256, 24, 32, pf.PF_HASH_BF16X3),
+                                                 (2500, 100, 40, 3072, 24, 4, pf.PF_HASH_BF16X3),
+                                                 (1200, 33, 9, 64, 13, 2, pf.PF_HASH_FP64),
+                                                 (900, 300, 5, 32, 32, 1, pf.PF_HASH_BF16X3)])
+def test_pool_build_bit_exact(n, d, L, pool, K, M, mode):
+    """Pooling (Sec. 3.2): pool and sketch hyperplanes, each table's sampled functions,
+    codes gathered from the pool bits, sorted tables, prefix tables and sketches."""
+    X = workloads.gaussian_unit(n, d, n + pool)
+    g, o = _build_pool(X, L, pool, seed=n + d, K=K, M=M, hash_mode=mode)
+    assert g.pool == pool
+    assert np.array_equal(g.export(pf.PF_EXPORT_POOL_SEL), o.sel), "pool selection"
+    _assert_index_equal(g, o)
+
+
+def test_pool_search_parity():
+    X = workloads.gaussian_unit(6000, 48, 61)
+    Q = workloads.gaussian_unit(300, 48, 62)
+    g, o = _build_pool(X, 40, 512, seed=63)
+    for k, rec, kw in [(10, 0.9, {"rule": pf.PF_RULE_POOL}), (1, 0.5, {"rule": pf.PF_RULE_POOL}),
+                       (10, 0.9, {}), (20, 0.99, {"rule": pf.PF_RULE_EXACT}),
+                       (10, 0.9, {"rule": pf.PF_RULE_POOL, "filter": False})]:
+        okw = dict(kw)
+        if "filter" in okw:
+            okw["filter_on"] = okw.pop("filter")
+        _assert_search_equal(g.search(Q, k, rec, **kw), o.search(Q, k, rec, **okw), f"pool k={k} {kw}")
+    # the pooled budget rule, and the POOL rule refused on an index without a pool
+    gb = pf.Index(X, 64 << 20, seed=63, pool=3072)
+    assert gb.L == oracle.num_tables(len(X), 48, 64 << 20, pool=3072)
+    plain = pf.Index(X[:500], 0, L=4)
+    with pytest.raises(pf.PfError):
+        plain.search(Q[:5], 5, 0.9, rule=pf.PF_RULE_POOL)
+    with pytest.raises(pf.PfError):
+        pf.Index(X[:500], 0, L=4, pool=40)
