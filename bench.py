@@ -187,6 +187,38 @@ def exact_topk_gpu(Xd, Qd, k: int, extra: int = 8):
     return out
 
 
+def pooled_index(X, Q, k, recall, budget, dev, truth_ids):
+    """The same workload on an index built with pooling (Sec. 3.2: 3,072 shared functions,
+    each table sampling its 24): build time, query hashing time, and the batched search
+    under the default stopping rule and under Algorithm 3's test."""
+    import torch
+
+    Xd = torch.from_numpy(X).to(dev)
+    ix = pf.Index(Xd, budget, seed=workloads.INDEX_SEED, pool=3072)
+    del Xd
+    info = ix.info()
+    m = len(Q)
+    Qd = torch.from_numpy(Q).to(dev)
+    ks = torch.full((m,), k, dtype=torch.int32, device=dev)
+    rec = torch.full((m,), recall, dtype=torch.float64, device=dev)
+    ix.search_batch(Qd, ks, rec, k, autotune=True)
+    out = {"pool": 3072, "L": info.L, "build_ms": info.build_ms}
+    for name, rule in (("default_rule", pf.PF_RULE_FILTER), ("algorithm3_rule", pf.PF_RULE_POOL)):
+        r = ix.search_batch(Qd, ks, rec, k, rule=rule, timing=True)
+        ts = []
+        for _ in range(3):
+            r = ix.search_batch(Qd, ks, rec, k, rule=rule, timing=True)
+            t = ix.last_timing()
+            ts.append((t.hash_ms, t.search_ms, t.total_ms))
+        ids = r.ids.cpu().numpy()[:len(truth_ids)]
+        recm = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(ids, truth_ids)]))
+        out[name] = {"normalize+hash_ms": float(np.mean([a for a, _, _ in ts])),
+                     "search_kernel_ms": float(np.mean([b for _, b, _ in ts])),
+                     "qps": m / (float(np.mean([c for _, _, c in ts])) / 1e3), "recall_measured": recm}
+        log(f"pooled index, {name}: search kernel {out[name]['search_kernel_ms']:.2f} ms, recall {recm:.4f}")
+    return out
+
+
 def workload_c5(args):
     """Configuration 5: n = 10,000,000 clustered unit vectors in d = 128 (100,000 clusters),
     16 GiB budget; the scheduler is trained on 1,000,000 plain-method traces and the three
@@ -301,6 +333,7 @@ def main():
                     help="query paths to time (comma separated); the last one is the headline")
     ap.add_argument("--train-frac", type=float, default=2.0,
                     help="scheduler training queries as a multiple of the benchmark query count")
+    ap.add_argument("--no-pool", action="store_true", help="skip the pooled-index measurement")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed 100,000-query batch (per-query k and recall, queue orders)")
     ap.add_argument("--workload", default="mixture-1M-d100", choices=["mixture-1M-d100", "mixture-10M-d128"],
@@ -444,6 +477,9 @@ def main():
     }
     log(f"recall {rec:.4f} on {ns} queries")
     line["mixed_batch"] = None if args.no_mixed else mixed_batch(ix, dev, args)
+    if not args.no_pool:
+        del ix
+        line["pooled_index"] = pooled_index(X, Q, k, recall, budget, dev, truth)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(X, Q, budget, k, recall, args.cpu_seconds)
     print(json.dumps(line), flush=True)
