@@ -86,10 +86,28 @@ def cpu_baseline(points, queries, budget, k, recall, seconds):
         el += time.time() - t
         done += len(q)
         chunk = min(2048, chunk * 2)
-    return {"value": done / el, "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # one thread, one query at a time (the paper's single-core setting), on a smaller sample
+    oracle.set_threads(1)
+    n1, el1 = 0, 0.0
+    while n1 < len(queries) and el1 < seconds / 4:
+        q = queries[n1:n1 + 16]
+        t = time.time()
+        ix.search(q, k, recall)
+        el1 += time.time() - t
+        n1 += len(q)
+    oracle.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": done / el, "unit": "queries/s", "cores": cores, "kind": "oracle",
             "sample": f"first {done} of {len(queries)} queries of the same workload on the oracle's "
                       f"own index (oracle build {build_s:.1f} s, not timed)",
-            "seconds": el}
+            "seconds": el, "single_thread_qps": n1 / el1, "single_thread_sample": n1,
+            "host_cpu": model, "host_nproc": os.cpu_count()}
 
 
 def mixed_batch(ix, dev, args):

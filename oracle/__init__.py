@@ -92,6 +92,8 @@ def lib():
         L.oracle_bruteforce.restype = ctypes.c_int
         L.oracle_bruteforce.argtypes = [_P, _I64, _I32, _P, _I64, _I32, _P, _P]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.restype = None
+        L.oracle_set_threads.argtypes = [_I32]
         L.oracle_num_threads.argtypes = []
         _lib = L
     return _lib
@@ -221,6 +223,11 @@ def bruteforce(points_n: np.ndarray, queries_n: np.ndarray, k: int):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(t: int) -> None:
+    """Threads of the following oracle calls (timing only)."""
+    lib().oracle_set_threads(int(t))
 
 
 # ----------------------------------------------------------------------------- index

@@ -729,3 +729,12 @@ int oracle_num_threads(void) {
     return 1;
 #endif
 }
+
+/* threads of the following oracle calls (timing only; results do not depend on it) */
+void oracle_set_threads(int32_t t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}

@@ -7,35 +7,54 @@
 
 namespace pf {
 
+// A workgroup normalises a tile of rows: the tile is read into LDS with coalesced loads,
+// one thread per row sums its squares sequentially from LDS (row stride d + 1 against
+// bank conflicts), and the quotients are written back coalesced.
 __global__ __launch_bounds__(256) void k_normalize(const float *__restrict__ x, int64_t n, int32_t d,
                                                    int32_t ld_in, float *__restrict__ out,
-                                                   int32_t dpad, unsigned long long *bad) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float *row = x + i * (int64_t)ld_in;
-    double s = 0.0;
-    for (int32_t c = 0; c < d; ++c) {
-        const double v = (double)row[c];
-        s = s + v * v;
+                                                   int32_t dpad, int32_t rows_per_block,
+                                                   unsigned long long *bad) {
+    extern __shared__ float tile[];
+    double *nrm = reinterpret_cast<double *>(tile + (((size_t)rows_per_block * (d + 1) + 1) & ~(size_t)1));
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int rows = (int)min((int64_t)rows_per_block, n - r0);
+    const int ld = d + 1;
+    for (int64_t t = tid; t < (int64_t)rows * d; t += blockDim.x) {
+        const int r = (int)(t / d), c = (int)(t - (int64_t)r * d);
+        tile[r * ld + c] = x[(r0 + r) * (int64_t)ld_in + c];
     }
-    const double nrm = sqrt(s);
-    float *o = out + i * (int64_t)dpad;
-    if (!(nrm > 0.0) || !isfinite(nrm)) {
-        atomicMin(bad, (unsigned long long)i);
-        for (int32_t c = 0; c < dpad; ++c) o[c] = 0.0f;
-        return;
+    __syncthreads();
+    for (int r = tid; r < rows; r += blockDim.x) {
+        double s = 0.0;
+        for (int32_t c = 0; c < d; ++c) {
+            const double v = (double)tile[r * ld + c];
+            s = s + v * v;
+        }
+        const double q = sqrt(s);
+        const bool ok = q > 0.0 && isfinite(q);
+        if (!ok) atomicMin(bad, (unsigned long long)(r0 + r));
+        nrm[r] = ok ? q : 0.0;
     }
-    // x and out may alias (same stride): read the element before writing it
-    for (int32_t c = 0; c < d; ++c) o[c] = (float)((double)row[c] / nrm);
-    for (int32_t c = d; c < dpad; ++c) o[c] = 0.0f;
+    __syncthreads();
+    // x and out may alias (same stride): every element was read into LDS above
+    for (int64_t t = tid; t < (int64_t)rows * dpad; t += blockDim.x) {
+        const int r = (int)(t / dpad), c = (int)(t - (int64_t)r * dpad);
+        const double q = nrm[r];
+        out[(r0 + r) * (int64_t)dpad + c] = (c < d && q > 0.0) ? (float)((double)tile[r * ld + c] / q) : 0.0f;
+    }
 }
 
 void launch_normalize(const float *x, int64_t n, int32_t d, int32_t ld_in, float *out, int32_t dpad,
                       unsigned long long *bad, hipStream_t s) {
     if (n <= 0) return;
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_normalize, dim3((unsigned)blocks), dim3(256), 0, s, x, n, d, ld_in, out,
-                       dpad, bad);
+    // about 64 KB of LDS per workgroup: at most 256 rows, at least one
+    const int32_t rpb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, 16000 / (d + 1)));
+    const size_t lds = (((size_t)rpb * (d + 1) + 1) & ~(size_t)1) * sizeof(float) + (size_t)rpb * sizeof(double);
+    PF_HIP(hipFuncSetAttribute((const void *)k_normalize, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int64_t blocks = (n + rpb - 1) / rpb;
+    hipLaunchKernelGGL(k_normalize, dim3((unsigned)blocks), dim3(256), lds, s, x, n, d, ld_in, out, dpad, rpb,
+                       bad);
     PF_HIP(hipGetLastError());
 }
 
