@@ -62,7 +62,17 @@ def lib():
         L.oracle_normalize.restype = _I64
         L.oracle_normalize.argtypes = [_P, _I64, _I32]
         L.oracle_num_tables.restype = _I64
-        L.oracle_num_tables.argtypes = [_I64, _I32, _I32, _I32, _I32, _U64]
+        L.oracle_num_tables.argtypes = [_I64, _I32, _I32, _I32, _I32, _I32, _U64]
+        L.oracle_cp_dims.restype = _I32
+        L.oracle_cp_dims.argtypes = [_I32, _P, _P]
+        L.oracle_cp_value.restype = ctypes.c_uint32
+        L.oracle_cp_value.argtypes = [_P, _I32, _U64, _U64]
+        L.oracle_cp_hash.restype = None
+        L.oracle_cp_hash.argtypes = [_P, _I64, _I32, _U64, _I32, _I32, _P]
+        L.oracle_cp_table.restype = None
+        L.oracle_cp_table.argtypes = [_U64, _I32, _I32, _P]
+        L.oracle_cp_prob.restype = _D
+        L.oracle_cp_prob.argtypes = [_P, _I32, ctypes.c_float, _I32]
         L.oracle_pool_select.restype = ctypes.c_int
         L.oracle_pool_select.argtypes = [_U64, _I32, _I32, _I32, _P]
         L.oracle_hash.restype = None
@@ -80,12 +90,13 @@ def lib():
         L.oracle_tau.restype = _D
         L.oracle_tau.argtypes = [ctypes.c_float, _D]
         L.oracle_stop.restype = ctypes.c_int
-        L.oracle_stop.argtypes = [ctypes.c_float, _I32, _I32, _I32, _D, _I32, _I32, _I32, ctypes.POINTER(_D)]
+        L.oracle_stop.argtypes = [ctypes.c_float, _I32, _I32, _I32, _D, _I32, _I32, _I32, _P, _I32,
+                                  ctypes.POINTER(_D)]
         L.oracle_binom_cdf64.restype = _D
         L.oracle_binom_cdf64.argtypes = [_D, _I32]
         L.oracle_search.restype = ctypes.c_int
         L.oracle_search.argtypes = [
-            _P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P, _I32,
+            _P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P, _I32, _P, _U64,
             _P, _I64, _I32, _D, _D, _I32, _I32, _I32,
             _P, _P, _P, _P, _P, _P, _P, _P, _P,
         ]
@@ -125,8 +136,47 @@ def normalize(x: np.ndarray) -> np.ndarray:
     return y
 
 
-def num_tables(n: int, d: int, budget: int, K: int = DEFAULT_K, M: int = DEFAULT_M, pool: int = 0) -> int:
-    return int(lib().oracle_num_tables(n, d, K, M, pool, budget))
+def num_tables(n: int, d: int, budget: int, K: int = DEFAULT_K, M: int = DEFAULT_M, pool: int = 0,
+               cp: bool = False) -> int:
+    return int(lib().oracle_num_tables(n, d, K, M, pool, 1 if cp else 0, budget))
+
+
+CP_MC_DRAWS = 1000   # Monte Carlo functions per tabulated similarity (Sec. 4.3)
+CP_GRID = 41         # similarities -1, -0.95, ..., 1
+
+
+def cp_dims(d: int):
+    """(d', ell): the padded power-of-two dimension and the bits of one FHT-CP value."""
+    dp, ell = ctypes.c_int32(), ctypes.c_int32()
+    lib().oracle_cp_dims(d, ctypes.byref(dp), ctypes.byref(ell))
+    return dp.value, ell.value
+
+
+def cp_value(x: np.ndarray, seed: int, fn: int) -> int:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    return int(lib().oracle_cp_value(_ptr(x), x.shape[0], seed, fn))
+
+
+def cp_hash(x: np.ndarray, seed: int, L: int, K: int) -> np.ndarray:
+    """codes[L][n] of normalised rows x under FHT cross-polytope tables."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    n, d = x.shape
+    codes = np.empty((L, n), dtype=np.uint32)
+    lib().oracle_cp_hash(_ptr(x), n, d, seed, L, K, _ptr(codes))
+    return codes
+
+
+def cp_table(seed: int, d: int, draws: int = CP_MC_DRAWS) -> np.ndarray:
+    """tab[g][b]: collision probability of b-bit prefixes at similarity -1 + 0.05 g."""
+    _, ell = cp_dims(d)
+    tab = np.empty((CP_GRID, ell + 1), dtype=np.float64)
+    lib().oracle_cp_table(seed, d, draws, _ptr(tab))
+    return tab
+
+
+def cp_prob(tab: np.ndarray, ip: float, i: int) -> float:
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    return float(lib().oracle_cp_prob(_ptr(tab), tab.shape[1] - 1, ip, i))
 
 
 def pool_select(seed: int, pool: int, L: int, K: int) -> np.ndarray:
@@ -198,9 +248,11 @@ def tau(ip_k: float, eps: float = 0.0) -> float:
 
 
 def stop(ip_k: float, i: int, L: int, delta: float, rule: int = RULE_EXACT, M: int = DEFAULT_M,
-         tau_int: int = 64, pool: int = 0):
+         tau_int: int = 64, pool: int = 0, cptab: np.ndarray | None = None):
     m = _D()
-    r = lib().oracle_stop(ip_k, i, L, M, delta, rule, tau_int, pool, ctypes.byref(m))
+    tab = None if cptab is None else np.ascontiguousarray(cptab, dtype=np.float64)
+    ell = 0 if tab is None else tab.shape[1] - 1
+    r = lib().oracle_stop(ip_k, i, L, M, delta, rule, tau_int, pool, _ptr(tab), ell, ctypes.byref(m))
     return bool(r), float(m.value)
 
 
@@ -248,15 +300,28 @@ class OracleIndex:
     """The index of Sec. 4.1-4.2 built step by step on the CPU."""
 
     def __init__(self, points: np.ndarray, budget: int, seed: int = 42, K: int = DEFAULT_K,
-                 M: int = DEFAULT_M, L: int | None = None, pool: int = 0):
-        """pool = m > 0: the tries sample their K functions from a pool of m (Sec. 3.2)."""
+                 M: int = DEFAULT_M, L: int | None = None, pool: int = 0, cp: bool = False):
+        """pool = m > 0: the tries sample their K functions from a pool of m (Sec. 3.2);
+        cp: FHT cross-polytope codes with Monte Carlo collision tables (Sec. 4.3)."""
         pts = np.ascontiguousarray(points, dtype=np.float32)
         self.n, self.d = pts.shape
-        self.K, self.M, self.pool = K, M, int(pool)
-        self.L = num_tables(self.n, self.d, budget, K, M, self.pool) if L is None else int(L)
+        self.K, self.M, self.pool, self.cp, self.seed = K, M, int(pool), bool(cp), seed
+        if self.cp and self.pool:
+            raise ValueError("pooling is for hyperplane functions here")
+        self.L = num_tables(self.n, self.d, budget, K, M, self.pool, self.cp) if L is None else int(L)
         if self.L < 1:
             raise ValueError("memory budget holds no table")
         self.points = normalize(pts)
+        self.cptab = None
+        if self.cp:
+            self.sel = None
+            self.hp = hyperplanes(seed, 64 * M, self.d)
+            self.cptab = cp_table(seed, self.d)
+            self.codes = cp_hash(self.points, seed, self.L, K)
+            _, self.sketches = hash_codes(self.points, self.hp, 0, K, M)
+            self.tcode, self.tidx, self.off = build_tables(self.codes, K)
+            self.tsk = table_sketches(self.tidx, self.sketches)
+            return
         if self.pool:
             self.sel = pool_select(seed, self.pool, self.L, K)
             self.hp = hyperplanes(seed, self.pool + 64 * M, self.d)
@@ -285,6 +350,7 @@ class OracleIndex:
         rc = lib().oracle_search(
             _ptr(self.points), self.n, self.d, _ptr(self.hp), _ptr(self.tcode), _ptr(self.tidx),
             _ptr(self.tsk), self.L, self.K, self.M, _ptr(getattr(self, "sel", None)), getattr(self, "pool", 0),
+            _ptr(getattr(self, "cptab", None)), getattr(self, "seed", 0),
             _ptr(q), m, k, recall, eps, B, rule,
             1 if filter_on else 0, _ptr(ids), _ptr(ips), _ptr(ips64), _ptr(sl), _ptr(cs),
             _ptr(cp), _ptr(cr), _ptr(bd), _ptr(tr))

@@ -101,15 +101,24 @@ int64_t oracle_normalize(float *x, int64_t n, int32_t d) {
  *             + 4 (2^P + 1)      (prefix-position table, P = min(13, K))
  *             + 4 K d            (independent functions: the K hyperplanes of the table)
  *               or 4 K           (pooling: the indices of its K pool functions)
+ *               or 3 c d' / 8    (FHT cross-polytope: c functions of three d'-bit sign vectors)
  * L = floor((budget - fixed) / per_table); 0 when the budget holds no table.
  * pool = m (0: independent functions, Alg. 1).
  * ---------------------------------------------------------------------------------- */
-int64_t oracle_num_tables(int64_t n, int32_t d, int32_t K, int32_t M, int32_t pool, uint64_t budget) {
+int32_t oracle_cp_dims(int32_t d, int32_t *dprime, int32_t *ell);
+
+int64_t oracle_num_tables(int64_t n, int32_t d, int32_t K, int32_t M, int32_t pool, int32_t cp, uint64_t budget) {
     int32_t P = K < 13 ? K : 13;
     uint64_t fixed = 4ull * (uint64_t)n * (uint64_t)d + 4ull * 64ull * (uint64_t)M * (uint64_t)d +
                      4ull * (uint64_t)(pool > 0 ? pool : 0) * (uint64_t)d;
-    uint64_t per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) +
-                   (pool > 0 ? 4ull * (uint64_t)K : 4ull * (uint64_t)K * (uint64_t)d);
+    uint64_t fn_bytes = pool > 0 ? 4ull * (uint64_t)K : 4ull * (uint64_t)K * (uint64_t)d;
+    if (cp) {
+        /* FHT cross-polytope: c = ceil(K / ell) functions, three sign vectors of d' bits each */
+        int32_t dp, ell;
+        oracle_cp_dims(d, &dp, &ell);
+        fn_bytes = (uint64_t)((K + ell - 1) / ell) * 3ull * (uint64_t)dp / 8ull;
+    }
+    uint64_t per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) + fn_bytes;
     if (budget <= fixed) return 0;
     return (int64_t)((budget - fixed) / per);
 }
@@ -212,6 +221,138 @@ void oracle_hash(const float *x, int64_t n, int32_t d, const float *hp, int32_t 
         }
         free(bit);
     }
+}
+
+/* ------------------------------------------------------------------------------------
+ * Cross-polytope LSH with the pseudorandom rotation of three Hadamard transforms (Sec.
+ * 2.2; Sec. 4.3 "Supported LSH Functions"; Andoni et al. 2015).  A function rotates x,
+ * zero padded to d' = the smallest power of two >= d, by y = H D3 H D2 H D1 x (H the
+ * Walsh-Hadamard matrix, unnormalised -- scaling does not move the argmax; D_k random
+ * +-1 diagonals) and maps it to the closest of the 2d' signed basis vectors: index
+ * i = argmax |y_i| (the smallest i on ties) and sign s = [y_i < 0].  Its value is the
+ * ell = log2(2 d')-bit string v = s d' + i, the sign as the most significant bit (a
+ * reading: the paper drops the last bit when the prefix shrinks; with the sign last,
+ * antipodal points would collide once the sign is dropped and the collision
+ * probability would not grow with similarity, which the stopping argument needs).
+ * A table's K-bit code is the first K bits of the concatenation of its c = ceil(K/ell)
+ * functions' values, function 1 first.
+ * Signs: D_k[c] of function fn is -1 when the top bit of output (3 fn + k) d' + c of the
+ * SplitMix64 stream seeded with sseed is set; the index uses seed + 3 (fn = j c + f for
+ * function f of table j) and the Monte Carlo tables seed + 2.
+ * The transform is FP64: butterflies for h = 1, 2, 4, ... replace (y[j], y[j+h]), bit h of
+ * j clear, by (a + b, a - b) -- one fixed set of operations, so a GPU following it gets
+ * the same bits.
+ * ---------------------------------------------------------------------------------- */
+#define OR_CP_GRID 41 /* tabulated similarities alpha_g = -1 + 0.05 g, g = 0..40 */
+
+int32_t oracle_cp_dims(int32_t d, int32_t *dprime, int32_t *ell) {
+    int32_t dp = 1, l = 1;
+    while (dp < d) dp <<= 1, ++l;
+    if (dprime) *dprime = dp;
+    if (ell) *ell = l; /* log2(2 dp) */
+    return dp;
+}
+
+static void fht64(double *y, int32_t dp) {
+    for (int32_t h = 1; h < dp; h <<= 1)
+        for (int32_t j = 0; j < dp; ++j)
+            if (!(j & h)) {
+                const double a = y[j], b = y[j + h];
+                y[j] = a + b;
+                y[j + h] = a - b;
+            }
+}
+
+static uint32_t cp_value(const float *x, int32_t d, int32_t dp, uint64_t sseed, uint64_t fn, double *y) {
+    for (int32_t c = 0; c < dp; ++c) y[c] = c < d ? (double)x[c] : 0.0;
+    for (int32_t k = 0; k < 3; ++k) {
+        for (int32_t c = 0; c < dp; ++c)
+            if (oracle_splitmix64(sseed, (fn * 3u + (uint64_t)k) * (uint64_t)dp + (uint64_t)c) >> 63) y[c] = -y[c];
+        fht64(y, dp);
+    }
+    int32_t best = 0;
+    for (int32_t c = 1; c < dp; ++c)
+        if (fabs(y[c]) > fabs(y[best])) best = c;
+    return (uint32_t)((y[best] < 0.0 ? dp : 0) + best);
+}
+
+/* value of CP function fn (stream seed + 3) at x; exported for the tests */
+uint32_t oracle_cp_value(const float *x, int32_t d, uint64_t seed, uint64_t fn) {
+    int32_t dp;
+    oracle_cp_dims(d, &dp, NULL);
+    double *y = (double *)malloc((size_t)dp * sizeof(double));
+    const uint32_t v = cp_value(x, d, dp, seed + 3u, fn, y);
+    free(y);
+    return v;
+}
+
+/* codes[j][i] of the rows x under FHT-CP tables (K-bit codes, see above) */
+void oracle_cp_hash(const float *x, int64_t n, int32_t d, uint64_t seed, int32_t L, int32_t K, uint32_t *codes) {
+    int32_t dp, ell;
+    oracle_cp_dims(d, &dp, &ell);
+    const int32_t c = (K + ell - 1) / ell;
+#pragma omp parallel
+    {
+        double *y = (double *)malloc((size_t)dp * sizeof(double));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            for (int32_t j = 0; j < L; ++j) {
+                uint64_t cat = 0;
+                for (int32_t f = 0; f < c; ++f)
+                    cat = (cat << ell) | cp_value(x + i * (int64_t)d, d, dp, seed + 3u, (uint64_t)j * c + f, y);
+                codes[(int64_t)j * n + i] = (uint32_t)(cat >> (c * ell - K));
+            }
+        }
+        free(y);
+    }
+}
+
+/* Monte Carlo collision table (Sec. 4.3 "Estimating Collision Probabilities"): for each
+ * alpha_g the pair x = e_1, y = (alpha, sqrt(1 - alpha^2), 0, ...) is hashed by R random
+ * functions (stream seed + 2, fn = 0..R-1) and tab[g][b] is the fraction whose values
+ * agree in their first b bits (tab[g][0] = 1).  The estimate is then made non-decreasing
+ * in alpha by taking, at each g, the minimum over all g' >= g (a lower bound is what the
+ * stopping rule needs, and the rule's argument needs monotonicity). */
+void oracle_cp_table(uint64_t seed, int32_t d, int32_t R, double *tab) {
+    int32_t dp, ell;
+    oracle_cp_dims(d, &dp, &ell);
+    float *px = (float *)calloc((size_t)dp, sizeof(float)), *py = (float *)calloc((size_t)dp, sizeof(float));
+    double *y = (double *)malloc((size_t)dp * sizeof(double));
+    for (int32_t g = 0; g < OR_CP_GRID; ++g) {
+        const double alpha = -1.0 + 0.05 * (double)g;
+        px[0] = 1.0f;
+        py[0] = (float)alpha;
+        py[1] = (float)sqrt(fmax(0.0, 1.0 - alpha * alpha));
+        double *row = tab + (int64_t)g * (ell + 1);
+        int64_t cnt[33] = {0};
+        for (int32_t r = 0; r < R; ++r) {
+            const uint32_t vx = cp_value(px, dp, dp, seed + 2u, (uint64_t)r, y);
+            const uint32_t vy = cp_value(py, dp, dp, seed + 2u, (uint64_t)r, y);
+            for (int32_t b = 1; b <= ell; ++b)
+                if ((vx >> (ell - b)) == (vy >> (ell - b))) ++cnt[b];
+        }
+        row[0] = 1.0;
+        for (int32_t b = 1; b <= ell; ++b) row[b] = (double)cnt[b] / (double)R;
+    }
+    for (int32_t g = OR_CP_GRID - 2; g >= 0; --g)
+        for (int32_t b = 0; b <= ell; ++b) {
+            double *a = tab + (int64_t)g * (ell + 1), *up = tab + (int64_t)(g + 1) * (ell + 1);
+            if (up[b] < a[b]) a[b] = up[b];
+        }
+    free(px), free(py), free(y);
+}
+
+/* Collision probability of an i-bit prefix at inner product ip under FHT-CP: the
+ * similarity is rounded down to the grid (g = floor((ip + 1) * 20), clamped to 0..40,
+ * FP64), and with i = a ell + b the a whole functions and the first b bits of the next
+ * one must agree: P = tab[g][ell]^a * tab[g][b], the power as exp(a log tab). */
+double oracle_cp_prob(const double *tab, int32_t ell, float ip, int32_t i) {
+    double gv = floor(((double)ip + 1.0) * 20.0);
+    int32_t g = gv < 0.0 ? 0 : (gv > 40.0 ? 40 : (int32_t)gv);
+    const double *row = tab + (int64_t)g * (ell + 1);
+    const int32_t a = i / ell, b = i % ell;
+    const double full = a > 0 ? exp((double)a * log(row[ell])) : 1.0;
+    return full * row[b];
 }
 
 /* ------------------------------------------------------------------------------------
@@ -371,13 +512,17 @@ double oracle_binom_cdf64(double t, int32_t T) {
  * most 1/2 with it, for any delta): after all L tries, stop when the expected number of
  * collisions with the k-th neighbour is at least two, L p^i >= 2, and the pool is large
  * enough for Cantelli's inequality, pool >= 5 i^2 / p (evaluated as pool p >= 5 i^2).
- * delta is not used.  *margin receives the signed distance of the two sides (term -
+ * delta is not used.  With FHT cross-polytope codes (cptab != NULL) p^i is replaced by
+ * the tabulated collision probability of the i-bit prefix (oracle_cp_prob); the filter's
+ * q stays the hyperplane sketches' own.  *margin receives the signed distance of the two sides (term -
  * threshold; for OR_RULE_POOL minus the smaller of the two slacks), <= 0 to stop. */
 int oracle_stop(float ip_k, int32_t i, int32_t L, int32_t M, double delta, int32_t rule,
-                int32_t tau_int, int32_t pool, double *margin) {
+                int32_t tau_int, int32_t pool, const double *cptab, int32_t ell, double *margin) {
     double theta = acos(clamp1((double)ip_k));
     double lnp = log1p(-theta / OR_PI);
-    double pi_ = exp((double)i * lnp);
+    /* collision probability of an i-bit prefix: p^i for hyperplane bits, the Monte Carlo
+       table for FHT cross-polytope codes (cptab != NULL) */
+    double pi_ = cptab ? oracle_cp_prob(cptab, ell, ip_k, i) : exp((double)i * lnp);
     double lnd = log(delta);
     if (rule == OR_RULE_POOL) {
         const double p = 1.0 - theta / OR_PI;
@@ -488,6 +633,8 @@ typedef struct {
     const uint64_t *tsk;
     int32_t L, K, M;
     int32_t pool; /* pool size m for OR_RULE_POOL (0: independent functions) */
+    const double *cptab; /* FHT cross-polytope collision table (NULL: hyperplane codes) */
+    int32_t ell;
 } or_index;
 
 /* trace (optional, one query): per level i (row i of K+1) and table j:
@@ -581,8 +728,14 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
         if (accumulate(top, fresh, k)) return OR_ENOMEM;
         if (top->len == k) {
             double margin;
-            int stop = oracle_stop(top->v[k - 1].ip, i, L, ix->M, delta, rule, tau_int, ix->pool, &margin);
+            int stop = oracle_stop(top->v[k - 1].ip, i, L, ix->M, delta, rule, tau_int, ix->pool, ix->cptab, ix->ell,
+                                   &margin);
             if (fabs(margin) < 1e-9 * (1.0 + fabs(log(delta)))) *boundary = 1;
+            if (ix->cptab) {
+                /* the table lookup changes cell at grid points of the similarity */
+                const double gv = ((double)top->v[k - 1].ip + 1.0) * 20.0;
+                if (fabs(gv - floor(gv + 0.5)) < 1e-9) *boundary = 1;
+            }
             if (stop) {
                 *stop_level = i;
                 return OR_OK;
@@ -606,7 +759,8 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
  * normalised data rows, hp the hyperplanes, (tcode, tidx, tsk) the L sorted tables.
  * recall in (0,1] gives delta = 1 - recall (Sec. 2.1: expected recall (1 - delta)).
  * sel / pool: the tries' pool functions (NULL / 0 for independent functions); pool is
- * also the m of OR_RULE_POOL.
+ * also the m of OR_RULE_POOL.  cptab != NULL: FHT cross-polytope codes with seed cp_seed
+ * and that collision table (hp then holds the sketch hyperplanes only).
  * Outputs per query: ids[k], ips[k] (FP32 order above), ips64[k], stop level, the three
  * counters, and boundary = 1 when a decision came within 1e-9 of flipping (a test of an
  * FP32 ip against an FP64 threshold computed with a different libm may then differ).
@@ -614,14 +768,14 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
  * Returns 0, OR_EINVAL (bad arguments or a zero / non-finite query row), OR_ENOMEM. */
 int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, const uint32_t *tcode,
                   const uint32_t *tidx, const uint64_t *tsk, int32_t L, int32_t K, int32_t M,
-                  const int32_t *sel, int32_t pool,
+                  const int32_t *sel, int32_t pool, const double *cptab, uint64_t cp_seed,
                   const float *queries, int64_t m, int32_t k, double recall, double eps, int32_t B,
                   int32_t rule, int32_t filter_on, int32_t *ids, float *ips, double *ips64,
                   int32_t *stop_level, int64_t *c_scan, int64_t *c_pass, int64_t *c_rerank,
                   int32_t *boundary, int64_t *trace) {
     if (n < 1 || d < 1 || L < 1 || K < 1 || K > 32 || M < 1 || m < 0 || k < 1 || k > n || B < 1)
         return OR_EINVAL;
-    if (rule == OR_RULE_POOL && pool < 1) return OR_EINVAL;
+    if (rule == OR_RULE_POOL && (pool < 1 || cptab)) return OR_EINVAL;
     if (!(recall > 0.0 && recall <= 1.0)) return OR_EINVAL;
     float *qn = (float *)malloc((size_t)(m > 0 ? m : 1) * (size_t)d * sizeof(float));
     uint32_t *qc = (uint32_t *)malloc((size_t)(m > 0 ? m : 1) * (size_t)L * sizeof(uint32_t));
@@ -636,8 +790,16 @@ int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, co
         return OR_EINVAL;
     }
     /* query codes: table-major like the data codes */
-    oracle_hash(qn, m, d, hp, L, K, M, sel, pool, qc, qs);
-    or_index ix = {points, n, d, tcode, tidx, tsk, L, K, M, pool};
+    int32_t ell = 0;
+    if (cptab) {
+        /* FHT cross-polytope codes; hp then holds only the 64 M sketch hyperplanes */
+        oracle_cp_dims(d, NULL, &ell);
+        oracle_cp_hash(qn, m, d, cp_seed, L, K, qc);
+        oracle_hash(qn, m, d, hp, 0, K, M, NULL, 0, NULL, qs);
+    } else {
+        oracle_hash(qn, m, d, hp, L, K, M, sel, pool, qc, qs);
+    }
+    or_index ix = {points, n, d, tcode, tidx, tsk, L, K, M, pool, cptab, ell};
     const double delta = 1.0 - recall;
     int err = OR_OK;
 #pragma omp parallel

@@ -667,3 +667,111 @@ def test_pool_guarantee_statistical(oracle_mod):
             hits[t] += np.isin(true_ids[t], r.ids[t])
     rate = hits / seeds
     assert np.all(rate >= 0.5 - 4 * math.sqrt(0.25 / seeds)), rate
+
+
+# ----------------------------------------------------------------------- FHT cross-polytope (Sec. 2.2, 4.3)
+def _cp_signs(oracle_mod, sseed, fn, dp):
+    return np.array([[-1.0 if oracle_mod.splitmix64(sseed, (fn * 3 + k) * dp + c) >> 63 else 1.0
+                      for c in range(dp)] for k in range(3)])
+
+
+def test_cp_value_is_argmax_of_rotation(oracle_mod):
+    """A function's value is s d' + i for i = argmax |H D3 H D2 H D1 x| and s the sign
+    there, recomputed with scipy's Hadamard matrix (a dense product, not the transform)."""
+    from scipy.linalg import hadamard
+
+    for d in (100, 64, 5):
+        dp, ell = oracle_mod.cp_dims(d)
+        assert dp == 1 << (ell - 1) and dp >= d > dp // 2
+        H = hadamard(dp).astype(np.float64)
+        X = oracle_mod.normalize(workloads.gaussian_unit(40, d, d))
+        for fn in (0, 7, 123):
+            D = _cp_signs(oracle_mod, 9 + 3, fn, dp)
+            for x in X:
+                y = np.zeros(dp)
+                y[:d] = x
+                for k in range(3):
+                    y = H @ (D[k] * y)
+                i = int(np.argmax(np.abs(y)))
+                assert oracle_mod.cp_value(x, 9, fn) == (dp if y[i] < 0 else 0) + i
+
+
+def test_cp_code_layout(oracle_mod):
+    """A table's K-bit code is the first K bits of its functions' values concatenated,
+    function 1 first (ell = 8 for d = 100: three values; ell = 7 for d = 64: four values,
+    the last cut after 3 bits)."""
+    for d, ell, c in ((100, 8, 3), (64, 7, 4)):
+        X = oracle_mod.normalize(workloads.gaussian_unit(30, d, 3 * d))
+        codes = oracle_mod.cp_hash(X, 5, 4, 24)
+        for i, x in enumerate(X):
+            for j in range(4):
+                cat = 0
+                for f in range(c):
+                    cat = (cat << ell) | oracle_mod.cp_value(x, 5, j * c + f)
+                assert codes[j, i] == cat >> (c * ell - 24)
+
+
+def test_cp_table_recount_and_special_values(oracle_mod):
+    """The Monte Carlo table recounted here from single function values (stream seed + 2,
+    the pair e_1 and (alpha, sqrt(1 - alpha^2))), then made non-decreasing in alpha;
+    tab[g][0] = 1, identical points always collide, antipodal points never agree in the
+    sign bit."""
+    d, seed, R = 20, 3, 60
+    dp, ell = oracle_mod.cp_dims(d)
+    lib = oracle_mod.lib()
+    tab = np.empty((41, ell + 1))
+    lib.oracle_cp_table(seed, d, R, tab.ctypes.data_as(__import__("ctypes").c_void_p))
+    raw = np.zeros((41, ell + 1))
+    for g in range(41):
+        a = -1.0 + 0.05 * g
+        x = np.zeros(dp, dtype=np.float32)
+        y = np.zeros(dp, dtype=np.float32)
+        x[0], y[0], y[1] = 1.0, np.float32(a), np.float32(math.sqrt(max(0.0, 1 - a * a)))
+        for r in range(R):
+            vx, vy = oracle_mod.cp_value(x, seed - 1, r), oracle_mod.cp_value(y, seed - 1, r)
+            for b in range(ell + 1):
+                raw[g, b] += (vx >> (ell - b)) == (vy >> (ell - b))
+    raw /= R
+    want = np.minimum.accumulate(raw[::-1], axis=0)[::-1]
+    assert np.array_equal(tab, want)
+    full = oracle_mod.cp_table(42, 100)
+    assert np.all(full[:, 0] == 1.0) and np.all(full[40] == 1.0) and np.all(full[0, 1:] == 0.0)
+    assert np.all(np.diff(full, axis=0) >= 0) and np.all(np.diff(full, axis=1) <= 0)
+
+
+def test_cp_prob_lookup(oracle_mod):
+    """P(i) = tab[g][ell]^a * tab[g][b], i = a ell + b, g = floor((ip + 1) * 20): hand cases."""
+    tab = oracle_mod.cp_table(42, 100)
+    ell = tab.shape[1] - 1
+    for ip, g in ((0.337, 26), (-1.0, 0), (1.0, 40), (0.0, 20), (-0.26, 14)):
+        ipf = float(np.float32(ip))
+        for i in (0, 1, 5, 8, 13, 19, 24):
+            a, b = divmod(i, ell)
+            assert abs(oracle_mod.cp_prob(tab, ipf, i) - tab[g, ell] ** a * tab[g, b]) <= 1e-15, (ip, i)
+
+
+def test_cp_budget_closed_form(oracle_mod):
+    """FHT-CP tables store three d'-bit sign vectors per function: n 1,000,000, d 100 (d' 128,
+    ell 8, three functions), 2 GiB: per table 16,000,000 + 32,772 + 144 bytes."""
+    assert oracle_mod.num_tables(1_000_000, 100, 2 << 30, cp=True) == \
+        (2_147_483_648 - 400_000_000 - 819_200) // 16_032_916 == 108
+
+
+def test_cp_lemma1_guarantee_statistical(oracle_mod):
+    """Lemma 1 with FHT cross-polytope codes and the Monte Carlo collision tables (filter
+    off, the paper's bound): each true neighbour found with probability at least
+    1 - delta, up to the tables' sampling error (150 index seeds)."""
+    X = workloads.gaussian_unit(500, 24, 91)
+    Q = workloads.gaussian_unit(3, 24, 92)
+    k, recall = 3, 0.8
+    true_ids, _ = oracle_mod.bruteforce(oracle_mod.normalize(X), oracle_mod.normalize(Q), k)
+    seeds = 150
+    hits = np.zeros((len(Q), k))
+    for s in range(seeds):
+        ix = oracle_mod.OracleIndex(X, 0, seed=9000 + s, L=10, M=2, cp=True)
+        r = ix.search(Q, k, recall, rule=oracle_mod.RULE_EXACT, filter_on=False)
+        for t in range(len(Q)):
+            hits[t] += np.isin(true_ids[t], r.ids[t])
+    rate = hits / seeds
+    sd = math.sqrt(0.2 * 0.8 / seeds)
+    assert np.all(rate >= 0.8 - 4 * sd - 0.03), rate
