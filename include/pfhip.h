@@ -59,6 +59,13 @@ extern "C" {
 #define PF_EXPORT_SKETCHES 4    /* L x n u64, table-local sketches                     */
 #define PF_EXPORT_OFFSETS 5     /* L x (2^P + 1) u32, P = min(13, K), prefix table     */
 #define PF_EXPORT_POOL_SEL 6    /* L x K int32: pool index of h_{t+1,j} (pooled index) */
+#define PF_EXPORT_CP_TABLE 7    /* 41 x (ell + 1) FP64: Monte Carlo collision probability of
+                                   b-bit prefixes at similarity -1 + 0.05 g (FHT-CP index) */
+
+/* hash families of the table codes (the sketches are always random-hyperplane bits) */
+#define PF_FAMILY_HP 0    /* random hyperplanes (Sec. 2.2), one bit per function          */
+#define PF_FAMILY_FHTCP 1 /* cross-polytope with three Hadamard rotations (Sec. 2.2, 4.3),
+                             ell = log2(2 d') bits per function, d' the power of two >= d  */
 
 /* limits of this implementation */
 #define PF_MAX_TABLES 512
@@ -76,6 +83,7 @@ typedef struct {
     int32_t pool;       /* 0: K independent functions per table (Algorithm 1);
                            m > 0: pooling (Sec. 3.2), every table samples K of m shared
                            functions without replacement; m a multiple of 32 in [K, 65536] */
+    int32_t family;     /* PF_FAMILY_HP (default) or PF_FAMILY_FHTCP (no pool)          */
 } pf_build_opts;
 
 /* All-zero options are the defaults. */
@@ -106,6 +114,7 @@ typedef struct {
 typedef struct {
     int64_t n;
     int32_t d, L, K, M, P, pool; /* pool: m of a pooled index, 0 otherwise */
+    int32_t family;              /* PF_FAMILY_* of the table codes               */
     uint64_t bytes_budget_rule; /* bytes the budget rule counts for this index        */
     uint64_t bytes_device;      /* device bytes the index actually holds              */
     double build_ms;            /* device time of the last build, if measured         */
@@ -141,6 +150,12 @@ int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, 
  *  functions drawn from them without replacement (Fisher-Yates on the SplitMix64 stream
  *  seeded with seed + 1), and the budget counts 4md once and 4K per table instead of
  *  4Kd.
+ *  With opts->family = PF_FAMILY_FHTCP: each table's code is the first K bits of c =
+ *  ceil(K / ell) cross-polytope values (rotation H D3 H D2 H D1 of the zero-padded point,
+ *  FP64; value = sign of the largest coordinate as the top bit, then its index), the
+ *  stopping rules read the collision probability of a prefix from a Monte Carlo table
+ *  (1,000 functions per similarity -1, -0.95, ..., 1, made non-decreasing, similarity
+ *  rounded down; Sec. 4.3), and the budget counts 3 c d' / 8 bytes of signs per table.
  * `points` n x d (caller-owned, copied).  Errors: PF_EINVAL (n < 1, n >= 2^31, d < 1,
  * d > PF_MAX_DIM, bad row, K, M or pool out of range), PF_EBUDGET, PF_ENOMEM, PF_EDEVICE.
  * Synchronises the stream before returning. */

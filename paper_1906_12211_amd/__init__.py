@@ -22,7 +22,8 @@ PF_HOST, PF_DEVICE = 0, 1
 PF_RULE_FILTER, PF_RULE_EXACT, PF_RULE_ALG1, PF_RULE_POOL = 0, 1, 2, 3
 PF_HASH_BF16X3, PF_HASH_FP64 = 0, 1
 (PF_EXPORT_POINTS, PF_EXPORT_HYPERPLANES, PF_EXPORT_CODES, PF_EXPORT_IDX,
- PF_EXPORT_SKETCHES, PF_EXPORT_OFFSETS, PF_EXPORT_POOL_SEL) = range(7)
+ PF_EXPORT_SKETCHES, PF_EXPORT_OFFSETS, PF_EXPORT_POOL_SEL, PF_EXPORT_CP_TABLE) = range(8)
+PF_FAMILY_HP, PF_FAMILY_FHTCP = 0, 1
 PF_MAX_TABLES, PF_MAX_K, PF_MAX_DIM = 512, 256, 4096
 
 PF_BATCH_LEARNED, PF_BATCH_AUTOTUNE = 1, 2
@@ -43,7 +44,8 @@ class PfError(RuntimeError):
 
 class pf_build_opts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("K", ctypes.c_int32), ("M", ctypes.c_int32),
-                ("hash_mode", ctypes.c_int32), ("L_override", ctypes.c_int32), ("pool", ctypes.c_int32)]
+                ("hash_mode", ctypes.c_int32), ("L_override", ctypes.c_int32), ("pool", ctypes.c_int32),
+                ("family", ctypes.c_int32)]
 
 
 class pf_search_opts(ctypes.Structure):
@@ -60,7 +62,7 @@ class pf_query_stats(ctypes.Structure):
 class pf_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("M", ctypes.c_int32), ("P", ctypes.c_int32),
-                ("pool", ctypes.c_int32), ("bytes_budget_rule", ctypes.c_uint64),
+                ("pool", ctypes.c_int32), ("family", ctypes.c_int32), ("bytes_budget_rule", ctypes.c_uint64),
                 ("bytes_device", ctypes.c_uint64), ("build_ms", ctypes.c_double)]
 
 
@@ -220,10 +222,11 @@ class Index:
     """An index over the rows of `points` (numpy on the host or a torch device tensor)."""
 
     def __init__(self, points, budget: int, seed: int = 42, K: int = 24, M: int = 32,
-                 hash_mode: int = PF_HASH_BF16X3, L: int | None = None, pool: int = 0):
+                 hash_mode: int = PF_HASH_BF16X3, L: int | None = None, pool: int = 0,
+                 family: int = PF_FAMILY_HP):
         pts = _f32(points)
         n, d = pts.shape
-        opts = pf_build_opts(seed, K, M, hash_mode, int(L or 0), int(pool))
+        opts = pf_build_opts(seed, K, M, hash_mode, int(L or 0), int(pool), int(family))
         pp, mem, st = _buf(pts)
         h = ctypes.c_void_p()
         _check(lib().pf_build_index(pp, n, d, int(budget), ctypes.byref(opts), mem, st, ctypes.byref(h)))
@@ -231,6 +234,11 @@ class Index:
         self.n, self.d = n, d
         info = self.info()
         self.L, self.K, self.M, self.P, self.pool = info.L, info.K, info.M, info.P, info.pool
+        self.family = info.family
+        dp = 1
+        while dp < d:
+            dp <<= 1
+        self.cp_ell = dp.bit_length()  # log2(2 d')
 
     def close(self):
         if getattr(self, "_h", None):
@@ -336,12 +344,14 @@ class Index:
 
     _EXPORT = {
         PF_EXPORT_POINTS: (np.float32, lambda s: (s.n, s.d)),
-        PF_EXPORT_HYPERPLANES: (np.float32, lambda s: ((s.pool or s.L * s.K) + 64 * s.M, s.d)),
+        PF_EXPORT_HYPERPLANES: (np.float32, lambda s: ((0 if s.family == PF_FAMILY_FHTCP else (s.pool or s.L * s.K))
+                                                        + 64 * s.M, s.d)),
         PF_EXPORT_CODES: (np.uint32, lambda s: (s.L, s.n)),
         PF_EXPORT_IDX: (np.uint32, lambda s: (s.L, s.n)),
         PF_EXPORT_SKETCHES: (np.uint64, lambda s: (s.L, s.n)),
         PF_EXPORT_OFFSETS: (np.uint32, lambda s: (s.L, (1 << s.P) + 1)),
         PF_EXPORT_POOL_SEL: (np.int32, lambda s: (s.L, s.K)),
+        PF_EXPORT_CP_TABLE: (np.float64, lambda s: (41, s.cp_ell + 1)),
     }
 
     def export(self, what: int) -> np.ndarray:

@@ -235,6 +235,85 @@ __global__ __launch_bounds__(256) void k_pool_codes(const uint32_t *__restrict__
 static void hash_gemm(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint32_t *skw, uint32_t kmask,
                       const int32_t *colrow, DevBuf &scratch, hipStream_t s);
 
+// Cross-polytope codes with three Hadamard rotations (Sec. 2.2, Sec. 4.3): one wave per
+// point (four per workgroup), the point zero padded to d' in the wave's LDS as FP64.  For
+// each function: flip the coordinates whose sign bit is set, apply the Walsh-Hadamard
+// butterflies h = 1, 2, 4, ... ((y[j], y[j+h]) -> (a + b, a - b) for bit h of j clear,
+// the same operations in the same precision as the definition), three rounds; then the
+// largest |y_i| (smallest i on ties) by a wave reduction, value = [y_i < 0] d' + i.  The
+// code is the first K bits of the table's c values concatenated.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void k_cp_hash(const float *__restrict__ X, int64_t n, int32_t dpad, int32_t d,
+                                                 int32_t dp, int32_t ell, int32_t c, int32_t L, int32_t K,
+                                                 const uint32_t *__restrict__ sign, uint32_t *__restrict__ codes) {
+    extern __shared__ double cp_lds[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    if (i >= n) return; // the whole wave leaves; only wave-local LDS is used below
+    double *y = cp_lds + (int64_t)w * dp;
+    const float *xr = X + i * (int64_t)dpad;
+    const int32_t sw = (dp + 31) / 32;
+    for (int32_t j = 0; j < L; ++j) {
+        uint64_t cat = 0;
+        for (int32_t f = 0; f < c; ++f) {
+            const int64_t fn = (int64_t)j * c + f;
+            for (int e = lane; e < dp; e += 64) y[e] = e < d ? (double)xr[e] : 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const uint32_t *sg = sign + (fn * 3 + k) * sw;
+                wave_lds_sync();
+                for (int e = lane; e < dp; e += 64)
+                    if ((sg[e >> 5] >> (e & 31)) & 1u) y[e] = -y[e];
+                for (int h = 1; h < dp; h <<= 1) {
+                    wave_lds_sync();
+                    for (int q = lane; q < dp / 2; q += 64) {
+                        const int jj = (q / h) * 2 * h + (q % h);
+                        const double a = y[jj], b = y[jj + h];
+                        y[jj] = a + b;
+                        y[jj + h] = a - b;
+                    }
+                }
+            }
+            wave_lds_sync();
+            double best = -1.0;
+            int bi = 0;
+            for (int e = lane; e < dp; e += 64) {
+                const double v = fabs(y[e]);
+                if (v > best) {
+                    best = v;
+                    bi = e;
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ob = __shfl_xor(best, o);
+                const int oi = __shfl_xor(bi, o);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            const uint32_t v = (y[bi] < 0.0 ? (uint32_t)dp : 0u) + (uint32_t)bi;
+            cat = (cat << ell) | v;
+            wave_lds_sync();
+        }
+        if (lane == 0) codes[(int64_t)j * n + i] = (uint32_t)(cat >> (c * ell - K));
+    }
+}
+
+void cp_codes(const Index &ix, const float *X, int64_t n, uint32_t *codes, hipStream_t s) {
+    if (n <= 0) return;
+    const size_t lds = (size_t)4 * ix.cp_dp * sizeof(double);
+    PF_HIP(hipFuncSetAttribute((const void *)k_cp_hash, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_cp_hash, dim3((unsigned)((n + 3) / 4)), dim3(256), lds, s, X, n, ix.dpad, ix.d, ix.cp_dp,
+                       ix.cp_ell, ix.cp_c, ix.L, ix.K, ix.cpsign.as<uint32_t>(), codes);
+    PF_HIP(hipGetLastError());
+}
+
+
 void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
                DevBuf &scratch, hipStream_t s) {
     if (n <= 0) return;
@@ -259,6 +338,7 @@ void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint
     } else {
         hash_gemm(ix, X, n, codes, skw, kmask, colrow, scratch, s);
     }
+    if (ix.family == PF_FAMILY_FHTCP) cp_codes(ix, X, n, table_codes, s);
     if (hp.pool) {
         hipLaunchKernelGGL(k_pool_codes, dim3((unsigned)((n + 255) / 256), (unsigned)hp.L), dim3(256), 0, s,
                            (const uint32_t *)codes, n, ix.psel.as<int32_t>(), hp.L, hp.K, table_codes);

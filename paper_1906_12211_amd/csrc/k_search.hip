@@ -145,13 +145,27 @@ __device__ double binom_cdf64(double t, int T) {
 // levels) or none of the g_s tables reading sketch s (j mod M = s) holds it in its
 // window (probability (1 - p^i)^{g_s}); each factor 1 - q + q (1 - p^i)^{g_s} is
 // evaluated without cancellation.  p = 1 - theta_k/pi, FP64.
+// Collision probability of an i-bit prefix under FHT cross-polytope codes (Sec. 4.3): the
+// Monte Carlo table at the similarity rounded down to the grid -1, -0.95, ..., 1, with
+// i = a ell + b: tab[g][ell]^a tab[g][b].
+__device__ double cp_prob(const double *tab, int ell, float ip, int i) {
+    const double gv = floor(((double)ip + 1.0) * 20.0);
+    const int g = gv < 0.0 ? 0 : (gv > 40.0 ? 40 : (int)gv);
+    const double *row = tab + (int64_t)g * (ell + 1);
+    const int a = i / ell, b = i % ell;
+    const double full = a > 0 ? exp((double)a * log(row[ell])) : 1.0;
+    return full * row[b];
+}
+
 // POOL: Algorithm 3's test (pooling, App. B): L p^i >= 2 and pool p >= 5 i^2.
-__device__ bool stop_of(float ip, int i, int T, double lndelta, int rule, int L, int M, int pool) {
+// cptab != nullptr: p^i is the cross-polytope table's prefix probability.
+__device__ bool stop_of(float ip, int i, int T, double lndelta, int rule, int L, int M, int pool,
+                        const double *cptab, int ell) {
     double v = (double)ip;
     v = v > 1.0 ? 1.0 : (v < -1.0 ? -1.0 : v);
     const double theta = acos(v);
     const double lnp = log1p(-theta / kPi);
-    const double pw = exp((double)i * lnp);
+    const double pw = cptab ? cp_prob(cptab, ell, ip, i) : exp((double)i * lnp);
     if (rule == PF_RULE_POOL)
         return (double)L * pw >= 2.0 && (double)pool * (1.0 - theta / kPi) >= 5.0 * (double)i * (double)i;
     if (rule == PF_RULE_ALG1) return (double)L * pw >= -lndelta;
@@ -170,7 +184,8 @@ __device__ bool stop_of(float ip, int i, int T, double lndelta, int rule, int L,
 
 __global__ __launch_bounds__(64) void k_rule_tables(const double *__restrict__ lndeltas, int32_t ndelta,
                                                     double eps, int32_t rule, int32_t L, int32_t M,
-                                                    int32_t K, int32_t pool, float *__restrict__ tauv,
+                                                    int32_t K, int32_t pool, const double *__restrict__ cptab,
+                                                    int32_t ell, float *__restrict__ tauv,
                                                     float *__restrict__ stopw) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t olo = ord_of(-1.0f), ohi = ord_of(1.0f);
@@ -203,15 +218,15 @@ __global__ __launch_bounds__(64) void k_rule_tables(const double *__restrict__ l
     const int32_t T = rem % kTauCols - 1;
     const double lnd = lndeltas[dl];
     float w;
-    if (stop_of(-1.0f, i, T, lnd, rule, L, M, pool)) {
+    if (stop_of(-1.0f, i, T, lnd, rule, L, M, pool, cptab, ell)) {
         w = -2.0f;
-    } else if (!stop_of(1.0f, i, T, lnd, rule, L, M, pool)) {
+    } else if (!stop_of(1.0f, i, T, lnd, rule, L, M, pool, cptab, ell)) {
         w = 2.0f;
     } else {
         uint32_t lo = olo, hi = ohi; // stop(lo) false, stop(hi) true
         while (hi - lo > 1) {
             const uint32_t mid = lo + (hi - lo) / 2;
-            if (stop_of(float_of(mid), i, T, lnd, rule, L, M, pool))
+            if (stop_of(float_of(mid), i, T, lnd, rule, L, M, pool, cptab, ell))
                 hi = mid;
             else
                 lo = mid;
@@ -222,10 +237,11 @@ __global__ __launch_bounds__(64) void k_rule_tables(const double *__restrict__ l
 }
 
 void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, int32_t rule, int32_t L,
-                        int32_t M, int32_t K, int32_t pool, float *tauv, float *stopw, hipStream_t s) {
+                        int32_t M, int32_t K, int32_t pool, const double *cptab, int32_t ell, float *tauv,
+                        float *stopw, hipStream_t s) {
     const int64_t total = 65 + (int64_t)ndelta * K * kTauCols;
     hipLaunchKernelGGL(k_rule_tables, dim3((unsigned)((total + 63) / 64)), dim3(64), 0, s, lndeltas_dev, ndelta,
-                       eps, rule, L, M, K, pool, tauv, stopw);
+                       eps, rule, L, M, K, pool, cptab, ell, tauv, stopw);
     PF_HIP(hipGetLastError());
 }
 

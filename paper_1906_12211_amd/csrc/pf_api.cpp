@@ -97,10 +97,13 @@ static void build_plan(Index &ix, const std::vector<float> &hp) {
     p.K = ix.K;
     p.M = ix.M;
     p.pool = ix.pool;
-    p.cw = ix.pool ? ix.pool / 32 : ix.L;
+    // code words: the table codes (one per table), the pool bits, or none when the codes
+    // are cross-polytope values computed by their own kernel
+    p.cw = ix.family == PF_FAMILY_FHTCP ? 0 : (ix.pool ? ix.pool / 32 : ix.L);
     p.words = p.cw + 2 * ix.M;
     p.ncols = 32 * p.words;
-    const int64_t srow = ix.pool ? (int64_t)ix.pool : (int64_t)ix.L * ix.K; // first sketch row
+    const int64_t srow = ix.family == PF_FAMILY_FHTCP ? 0
+                         : (ix.pool ? (int64_t)ix.pool : (int64_t)ix.L * ix.K); // first sketch row
     std::vector<int32_t> colrow(p.ncols, -1);
     std::vector<float> beta(p.ncols, -1.0f);
     for (int32_t wb = 0; wb < p.words; ++wb)
@@ -142,14 +145,87 @@ static void build_plan(Index &ix, const std::vector<float> &hp) {
     PF_HIP(hipMemcpy(ix.hbf.p, hb.data(), hb.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
 }
 
+// FHT cross-polytope: d' = the smallest power of two >= d, ell = log2(2 d') bits per value
+static void cp_dims(int32_t d, int32_t &dp, int32_t &ell) {
+    dp = 1;
+    ell = 1;
+    while (dp < d) dp <<= 1, ++ell;
+}
+
 // budget rule: bytes of the vectors, sketch functions and (pooled) pool functions, and
-// bytes per table (its K functions, or with a pool their K indices)
-static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, int32_t pool, uint64_t &fixed, uint64_t &per) {
+// bytes per table (its K functions, with a pool their K indices, with cross-polytope
+// codes the three d'-bit sign vectors of each of its c functions)
+static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, int32_t pool, int32_t family, uint64_t &fixed,
+                         uint64_t &per) {
     const int32_t P = std::min(13, K);
     fixed = 4ull * (uint64_t)n * (uint64_t)d + 4ull * 64ull * (uint64_t)M * (uint64_t)d +
             4ull * (uint64_t)pool * (uint64_t)d;
-    per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) +
-          (pool ? 4ull * (uint64_t)K : 4ull * (uint64_t)K * (uint64_t)d);
+    uint64_t fn = pool ? 4ull * (uint64_t)K : 4ull * (uint64_t)K * (uint64_t)d;
+    if (family == PF_FAMILY_FHTCP) {
+        int32_t dp, ell;
+        cp_dims(d, dp, ell);
+        fn = (uint64_t)((K + ell - 1) / ell) * 3ull * (uint64_t)dp / 8ull;
+    }
+    per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) + fn;
+}
+
+// sign bit of coordinate c of rotation round k of cross-polytope function fn: the top bit
+// of output (3 fn + k) d' + c of the SplitMix64 stream seeded with sseed
+static inline bool cp_sign(uint64_t sseed, uint64_t fn, int32_t k, int32_t c, int32_t dp) {
+    return (splitmix64_at(sseed, (fn * 3u + (uint64_t)k) * (uint64_t)dp + (uint64_t)c) >> 63) != 0;
+}
+
+// value of one cross-polytope function on the host (Monte Carlo estimation), FP64, the
+// same butterflies as the device kernel
+static uint32_t cp_value_host(const std::vector<float> &x, int32_t dp, uint64_t sseed, uint64_t fn,
+                              std::vector<double> &y) {
+    for (int32_t c = 0; c < dp; ++c) y[c] = (double)x[c];
+    for (int32_t k = 0; k < 3; ++k) {
+        for (int32_t c = 0; c < dp; ++c)
+            if (cp_sign(sseed, fn, k, c, dp)) y[c] = -y[c];
+        for (int32_t h = 1; h < dp; h <<= 1)
+            for (int32_t j = 0; j < dp; ++j)
+                if (!(j & h)) {
+                    const double a = y[j], b = y[j + h];
+                    y[j] = a + b;
+                    y[j + h] = a - b;
+                }
+    }
+    int32_t best = 0;
+    for (int32_t c = 1; c < dp; ++c)
+        if (std::fabs(y[c]) > std::fabs(y[best])) best = c;
+    return (uint32_t)((y[best] < 0.0 ? dp : 0) + best);
+}
+
+// Monte Carlo collision table (Sec. 4.3): at similarity alpha_g = -1 + 0.05 g the pair e_1,
+// (alpha, sqrt(1 - alpha^2)) is hashed by 1,000 functions of the stream seeded with
+// seed + 2; tab[g][b] = fraction agreeing in the first b bits, then made non-decreasing
+// in alpha (the minimum over all g' >= g), a lower bound for the stopping rule.
+static std::vector<double> cp_table_host(uint64_t seed, int32_t dp, int32_t ell) {
+    constexpr int kGrid = 41, kDraws = 1000;
+    std::vector<double> tab((size_t)kGrid * (ell + 1));
+    std::vector<float> px(dp, 0.0f), py(dp, 0.0f);
+    std::vector<double> y(dp);
+    for (int g = 0; g < kGrid; ++g) {
+        const double alpha = -1.0 + 0.05 * (double)g;
+        px[0] = 1.0f;
+        py[0] = (float)alpha;
+        py[1] = (float)std::sqrt(std::fmax(0.0, 1.0 - alpha * alpha));
+        std::vector<int64_t> cnt(ell + 1, 0);
+        for (int r = 0; r < kDraws; ++r) {
+            const uint32_t vx = cp_value_host(px, dp, seed + 2u, (uint64_t)r, y);
+            const uint32_t vy = cp_value_host(py, dp, seed + 2u, (uint64_t)r, y);
+            for (int b = 1; b <= ell; ++b)
+                if ((vx >> (ell - b)) == (vy >> (ell - b))) ++cnt[b];
+        }
+        tab[(size_t)g * (ell + 1)] = 1.0;
+        for (int b = 1; b <= ell; ++b) tab[(size_t)g * (ell + 1) + b] = (double)cnt[b] / (double)kDraws;
+    }
+    for (int g = kGrid - 2; g >= 0; --g)
+        for (int b = 0; b <= ell; ++b)
+            tab[(size_t)g * (ell + 1) + b] =
+                std::min(tab[(size_t)g * (ell + 1) + b], tab[(size_t)(g + 1) * (ell + 1) + b]);
+    return tab;
 }
 
 // Pooling (Sec. 3.2): table j's K functions, h_{t+1,j} = pool function sel[j K + t],
@@ -237,8 +313,11 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
                  "pf_build_index: bad hash_mode");
         PF_CHECK(o.pool == 0 || (o.pool >= K && o.pool <= 65536 && o.pool % 32 == 0), PF_EINVAL,
                  "pf_build_index: pool must be 0 or a multiple of 32 in [K, 65536]");
+        PF_CHECK(o.family == PF_FAMILY_HP || o.family == PF_FAMILY_FHTCP, PF_EINVAL, "pf_build_index: bad family");
+        PF_CHECK(o.family == PF_FAMILY_HP || o.pool == 0, PF_EINVAL,
+                 "pf_build_index: pooling is implemented for hyperplane functions");
         uint64_t fixed, per;
-        budget_terms(n, d, K, M, o.pool, fixed, per);
+        budget_terms(n, d, K, M, o.pool, o.family, fixed, per);
         int64_t L = o.L_override;
         if (L <= 0) L = budget > fixed ? (int64_t)((budget - fixed) / per) : 0;
         PF_CHECK(L >= 1, PF_EBUDGET, "pf_build_index: the memory budget holds no table");
@@ -262,6 +341,11 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         ix->seed = o.seed;
         ix->hash_mode = o.hash_mode;
         ix->pool = o.pool;
+        ix->family = o.family;
+        if (o.family == PF_FAMILY_FHTCP) {
+            cp_dims(d, ix->cp_dp, ix->cp_ell);
+            ix->cp_c = (K + ix->cp_ell - 1) / ix->cp_ell;
+        }
         ix->bytes_rule = fixed + (uint64_t)L * per;
 
         hipEvent_t e0, e1;
@@ -274,11 +358,28 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         normalize_into(points, n, d, mem, X.as<float>(), ix->dpad, ix->tmp, ix->flags, s);
         ix->tmp.release();
         // a3: hyperplanes (host generator), device copies and hash plan
-        const int64_t rows = (o.pool ? (int64_t)o.pool : L * K) + 64ll * M;
+        const int64_t rows = (o.family == PF_FAMILY_FHTCP ? 0 : (o.pool ? (int64_t)o.pool : L * K)) + 64ll * M;
         std::vector<float> hp((size_t)rows * d);
         make_hyperplanes(o.seed, rows, d, hp.data());
         ix->hp.alloc(hp.size() * sizeof(float));
         PF_HIP(hipMemcpy(ix->hp.p, hp.data(), hp.size() * sizeof(float), hipMemcpyHostToDevice));
+        if (o.family == PF_FAMILY_FHTCP) {
+            // sign bits of every function's three rotations (stream seed + 3), and the
+            // Monte Carlo collision table (stream seed + 2)
+            const int32_t dp = ix->cp_dp, sw = (dp + 31) / 32;
+            const int64_t nfn = L * (int64_t)ix->cp_c;
+            std::vector<uint32_t> sg((size_t)nfn * 3 * sw, 0u);
+            for (int64_t fn = 0; fn < nfn; ++fn)
+                for (int32_t k = 0; k < 3; ++k)
+                    for (int32_t c = 0; c < dp; ++c)
+                        if (cp_sign(o.seed + 3u, (uint64_t)fn, k, c, dp))
+                            sg[(size_t)(fn * 3 + k) * sw + c / 32] |= 1u << (c % 32);
+            ix->cpsign.alloc(sg.size() * sizeof(uint32_t));
+            PF_HIP(hipMemcpy(ix->cpsign.p, sg.data(), sg.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+            const std::vector<double> tab = cp_table_host(o.seed, dp, ix->cp_ell);
+            ix->cptab.alloc(tab.size() * sizeof(double));
+            PF_HIP(hipMemcpy(ix->cptab.p, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
         if (o.pool) {
             const std::vector<int32_t> sel = pool_select(o.seed, o.pool, (int32_t)L, K);
             ix->psel.alloc(sel.size() * sizeof(int32_t));
@@ -457,6 +558,8 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     if (o.B == 0) o.B = 12;
     PF_CHECK(o.B >= 1, PF_EINVAL, "search: B must be >= 1");
     PF_CHECK(o.rule != PF_RULE_POOL || ix->pool > 0, PF_EINVAL, "search: PF_RULE_POOL needs a pooled index");
+    PF_CHECK(o.rule != PF_RULE_POOL || ix->family == PF_FAMILY_HP, PF_EINVAL,
+             "search: PF_RULE_POOL is for hyperplane codes");
     PF_CHECK(o.rule == PF_RULE_FILTER || o.rule == PF_RULE_EXACT || o.rule == PF_RULE_ALG1 || o.rule == PF_RULE_POOL,
              PF_EINVAL,
              "search: bad rule");
@@ -520,7 +623,9 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         double *dl = reinterpret_cast<double *>(ix->rule_tab.as<char>() + dl_off);
         PF_HIP(hipMemcpyAsync(dl, lnd.data(), lnd.size() * sizeof(double), h2d, s));
         float *tab = ix->rule_tab.as<float>();
-        launch_rule_tables(dl, (int32_t)lnd.size(), o.eps, o.rule, ix->L, ix->M, ix->K, ix->pool, tab, tab + 65, s);
+        launch_rule_tables(dl, (int32_t)lnd.size(), o.eps, o.rule, ix->L, ix->M, ix->K, ix->pool,
+                           ix->family == PF_FAMILY_FHTCP ? ix->cptab.as<double>() : nullptr, ix->cp_ell, tab,
+                           tab + 65, s);
         PF_HIP(hipStreamSynchronize(s));
         ix->rule_key_rule = o.rule;
         ix->rule_key_eps = o.eps;
@@ -711,7 +816,8 @@ PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_by
             break;
         }
         case PF_EXPORT_HYPERPLANES: {
-            const int64_t b = ((ix->pool ? (int64_t)ix->pool : (int64_t)ix->L * ix->K) + 64ll * ix->M) * ix->d * 4;
+            const int64_t b = ((ix->family == PF_FAMILY_FHTCP ? 0 : ix->pool ? (int64_t)ix->pool : (int64_t)ix->L * ix->K) +
+                               64ll * ix->M) * ix->d * 4;
             need(b);
             PF_HIP(hipMemcpyAsync(dst, ix->hp.p, (size_t)b, kind, s));
             break;
@@ -732,6 +838,13 @@ PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_by
             const int64_t b = (int64_t)ix->L * ((1ll << ix->P) + 1) * 4;
             need(b);
             PF_HIP(hipMemcpyAsync(dst, ix->off.p, (size_t)b, kind, s));
+            break;
+        }
+        case PF_EXPORT_CP_TABLE: {
+            PF_CHECK(ix->family == PF_FAMILY_FHTCP, PF_EINVAL, "pf_export: the index has no cross-polytope table");
+            const int64_t b = 41ll * (ix->cp_ell + 1) * 8;
+            need(b);
+            PF_HIP(hipMemcpyAsync(dst, ix->cptab.p, (size_t)b, kind, s));
             break;
         }
         case PF_EXPORT_POOL_SEL: {
@@ -759,9 +872,10 @@ PF_API int pf_index_info(const pf_index *ix, pf_info *info) {
         r.M = ix->M;
         r.P = ix->P;
         r.pool = ix->pool;
+        r.family = ix->family;
         r.bytes_budget_rule = ix->bytes_rule;
         r.bytes_device = ix->Xh.bytes + ix->Xl.bytes + ix->hp.bytes + ix->hcolrow.bytes + ix->hbf.bytes + ix->hbeta.bytes +
-                         ix->psel.bytes + ix->tcode.bytes + ix->tidx.bytes + ix->tsk.bytes + ix->off.bytes;
+                         ix->psel.bytes + ix->cpsign.bytes + ix->cptab.bytes + ix->tcode.bytes + ix->tidx.bytes + ix->tsk.bytes + ix->off.bytes;
         r.build_ms = ix->build_ms;
         *info = r;
     });

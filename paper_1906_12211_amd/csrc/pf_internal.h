@@ -77,6 +77,8 @@ struct Index {
     int32_t d = 0, dpad = 0, L = 0, K = 0, M = 0, P = 0;
     int32_t hash_mode = PF_HASH_BF16X3;
     int32_t pool = 0; // m of a pooled index (0: independent functions)
+    int32_t family = PF_FAMILY_HP;
+    int32_t cp_dp = 0, cp_ell = 0, cp_c = 0; // FHT-CP: padded dimension, bits per value, values per code
     uint64_t seed = 0;
     uint64_t bytes_rule = 0;
     double build_ms = 0.0;
@@ -94,6 +96,8 @@ struct Index {
     int32_t hs = 0, ls = 0;
     DevBuf hp;     // (L*K + 64*M) x d FP32 hyperplanes (paper order); pooled: (m + 64*M) x d
     DevBuf psel;   // pooled: L x K int32, pool index of h_{t+1,j}
+    DevBuf cpsign; // FHT-CP: (L c) x 3 x d'/32 u32 sign bits (bit set = -1)
+    DevBuf cptab;  // FHT-CP: 41 x (ell + 1) FP64 collision table
     DevBuf hcolrow;// ncols int32: hyperplane row of each GEMM column (-1 = padding)
     DevBuf hbf;    // ncols x kp bf16 hi parts, then ncols x kp bf16 lo parts
     DevBuf hbeta;  // ncols FP32 flag bounds (negative = never flagged)
@@ -193,7 +197,10 @@ struct SearchArgs {
 };
 void launch_ranges(const Index &ix, const SearchArgs &a, uint32_t *ranges, hipStream_t s);
 void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, int32_t rule, int32_t L,
-                        int32_t M, int32_t K, int32_t pool, float *tauv, float *stopw, hipStream_t s);
+                        int32_t M, int32_t K, int32_t pool, const double *cptab, int32_t ell, float *tauv,
+                        float *stopw, hipStream_t s);
+// FHT-CP table codes of rows X (n x dpad) into codes (L x n); see k_hash.hip
+void cp_codes(const Index &ix, const float *X, int64_t n, uint32_t *codes, hipStream_t s);
 int32_t rule_table_cols();
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s);
 int64_t search_slots(const Index &ix, int64_t m);

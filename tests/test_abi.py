@@ -46,7 +46,7 @@ def test_binding_constants_match_header():
         if hasattr(pf, name):
             assert getattr(pf, name) == val, name
     for name in ["PF_OK", "PF_EINVAL", "PF_EBUDGET", "PF_HOST", "PF_DEVICE", "PF_HASH_FP64",
-                 "PF_EXPORT_OFFSETS", "PF_EXPORT_POOL_SEL", "PF_RULE_POOL", "PF_MAX_TABLES", "PF_MAX_K"]:
+                 "PF_EXPORT_OFFSETS", "PF_EXPORT_POOL_SEL", "PF_RULE_POOL", "PF_EXPORT_CP_TABLE", "PF_FAMILY_FHTCP", "PF_MAX_TABLES", "PF_MAX_K"]:
         assert getattr(pf, name) == d[name]
 
 

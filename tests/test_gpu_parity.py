@@ -332,3 +332,35 @@ def test_pool_search_parity():
         plain.search(Q[:5], 5, 0.9, rule=pf.PF_RULE_POOL)
     with pytest.raises(pf.PfError):
         pf.Index(X[:500], 0, L=4, pool=40)
+
+
+@pytest.mark.parametrize("n,d,L,K,M", [(3000, 100, 12, 24, 4), (2000, 64, 10, 24, 2), (800, 5, 6, 13, 1),
+                                       (700, 300, 4, 32, 1)])
+def test_cp_build_bit_exact(n, d, L, K, M):
+    """FHT cross-polytope codes (Sec. 2.2, 4.3): the FP64 rotations on the GPU give the
+    oracle's values, hence its codes and tables; the Monte Carlo table is the oracle's."""
+    X = workloads.gaussian_unit(n, d, 5 * n + d)
+    print(f"[build cp] n={n} d={d} L={L} K={K} M={M}", flush=True)
+    g = pf.Index(X, 0, seed=d, K=K, M=M, L=L, family=pf.PF_FAMILY_FHTCP)
+    o = oracle.OracleIndex(X, 0, seed=d, K=K, M=M, L=L, cp=True)
+    assert g.family == pf.PF_FAMILY_FHTCP
+    assert np.array_equal(g.export(pf.PF_EXPORT_CP_TABLE), o.cptab), "collision table"
+    _assert_index_equal(g, o)
+
+
+def test_cp_search_parity():
+    X = workloads.gaussian_unit(6000, 100, 71)
+    Q = workloads.gaussian_unit(300, 100, 72)
+    print("[build cp] n=6000 d=100 L=30", flush=True)
+    g = pf.Index(X, 0, seed=73, L=30, family=pf.PF_FAMILY_FHTCP)
+    o = oracle.OracleIndex(X, 0, seed=73, L=30, cp=True)
+    for k, rec, kw in [(10, 0.9, {}), (10, 0.9, {"rule": pf.PF_RULE_EXACT}), (1, 0.5, {"rule": pf.PF_RULE_ALG1}),
+                       (20, 0.99, {"filter": False, "rule": pf.PF_RULE_EXACT})]:
+        okw = dict(kw)
+        if "filter" in okw:
+            okw["filter_on"] = okw.pop("filter")
+        _assert_search_equal(g.search(Q, k, rec, **kw), o.search(Q, k, rec, **okw), f"cp k={k} {kw}")
+    with pytest.raises(pf.PfError):
+        g.search(Q[:4], 5, 0.9, rule=pf.PF_RULE_POOL)
+    gb = pf.Index(X, 64 << 20, seed=73, family=pf.PF_FAMILY_FHTCP)
+    assert gb.L == oracle.num_tables(len(X), 100, 64 << 20, cp=True)
