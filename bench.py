@@ -205,6 +205,41 @@ def exact_topk_gpu(Xd, Qd, k: int, extra: int = 8):
     return out
 
 
+def cp_index(X, Q, k, recall, budget, dev, truth_ids):
+    """The same workload on an index whose table codes are FHT cross-polytope values
+    (Sec. 2.2, 4.3; the sketches stay hyperplane bits): build time (the FP64 rotations),
+    query hashing time, and the batched search under the default rule."""
+    import torch
+
+    Xd = torch.from_numpy(X).to(dev)
+    ix = pf.Index(Xd, budget, seed=workloads.INDEX_SEED, family=pf.PF_FAMILY_FHTCP)
+    del Xd
+    info = ix.info()
+    m = len(Q)
+    Qd = torch.from_numpy(Q).to(dev)
+    ks = torch.full((m,), k, dtype=torch.int32, device=dev)
+    rec = torch.full((m,), recall, dtype=torch.float64, device=dev)
+    ix.search_batch(Qd, ks, rec, k, autotune=True)
+    r = ix.search_batch(Qd, ks, rec, k, timing=True)
+    ts = []
+    for _ in range(3):
+        r = ix.search_batch(Qd, ks, rec, k, timing=True)
+        t = ix.last_timing()
+        ts.append((t.hash_ms, t.search_ms, t.total_ms))
+    ids = r.ids.cpu().numpy()[:len(truth_ids)]
+    st = r.stats.cpu().numpy()
+    recm = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(ids, truth_ids)]))
+    out = {"family": "fht-cross-polytope", "L": info.L, "build_ms": info.build_ms,
+           "normalize+hash_ms": float(np.mean([a for a, _, _ in ts])),
+           "search_kernel_ms": float(np.mean([b for _, b, _ in ts])),
+           "qps": m / (float(np.mean([c for _, _, c in ts])) / 1e3), "recall_measured": recm,
+           "mean_counts": {"c_scan": float(st[:, 1].mean()), "c_pass": float(st[:, 2].mean())},
+           "stop_level_hist": np.bincount(st[:, 0], minlength=info.K + 1).tolist()}
+    log(f"cross-polytope index: build {info.build_ms:.0f} ms, search kernel {out['search_kernel_ms']:.2f} ms, "
+        f"recall {recm:.4f}")
+    return out
+
+
 def pooled_index(X, Q, k, recall, budget, dev, truth_ids):
     """The same workload on an index built with pooling (Sec. 3.2: 3,072 shared functions,
     each table sampling its 24): build time, query hashing time, and the batched search
@@ -498,6 +533,7 @@ def main():
     if not args.no_pool:
         del ix
         line["pooled_index"] = pooled_index(X, Q, k, recall, budget, dev, truth)
+        line["cross_polytope_index"] = cp_index(X, Q, k, recall, budget, dev, truth)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(X, Q, budget, k, recall, args.cpu_seconds)
     print(json.dumps(line), flush=True)
