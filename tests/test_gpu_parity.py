@@ -364,3 +364,51 @@ def test_cp_search_parity():
         g.search(Q[:4], 5, 0.9, rule=pf.PF_RULE_POOL)
     gb = pf.Index(X, 64 << 20, seed=73, family=pf.PF_FAMILY_FHTCP)
     assert gb.L == oracle.num_tables(len(X), 100, 64 << 20, cp=True)
+
+
+def test_edge_cases():
+    """Empty batches, a single point, identical points (every code and inner product tied:
+    order by position), queries equal to data points, the largest k, the table cap."""
+    X = workloads.gaussian_unit(500, 16, 201)
+    g = pf.Index(X, 0, seed=3, L=8)
+    r = g.search(np.zeros((0, 16), dtype=np.float32), 5, 0.9)
+    assert r.ids.shape == (0, 5)
+    rb = g.search_batch(np.zeros((0, 16), dtype=np.float32), np.zeros(0, np.int32), np.zeros(0), 5)
+    assert rb.ids.shape == (0, 5)
+    # one point
+    one = pf.Index(X[:1], 0, seed=3, L=3)
+    r = one.search(X[:4], 1, 0.9)
+    assert np.all(r.ids == 0)
+    # identical points: all ties, ids ascending
+    same = np.repeat(X[:1], 300, axis=0)
+    gs, os_ = _build_both(same, L=6, seed=4)
+    _assert_search_equal(gs.search(X[:20], 7, 0.9), os_.search(X[:20], 7, 0.9), "identical points")
+    assert np.all(gs.search(X[:20], 7, 0.9).ids == np.arange(7))
+    # queries that are data points come back first with inner product 1 (up to rounding)
+    r = g.search(X[:50], 3, 0.99)
+    assert np.all(r.ids[:, 0] == np.arange(50))
+    # the largest k (PF_MAX_K) in a batch with mixed k, and k > PF_MAX_K refused
+    Xb = workloads.gaussian_unit(3000, 24, 202)
+    gb, ob = _build_both(Xb, L=12, seed=5)
+    Q = workloads.gaussian_unit(40, 24, 203)
+    ks = np.where(np.arange(40) % 2 == 0, 256, 1).astype(np.int32)
+    rec = np.full(40, 0.9)
+    oids, oips, ost, obd = _oracle_per_query(ob, Q, ks, rec, 256)
+    _assert_batch_equal(gb.search_batch(Q, ks, rec, 256), oids, oips, ost, obd, "k=256")
+    with pytest.raises(pf.PfError):
+        gb.search(Q, 257, 0.9)
+    # a budget for more than 512 tables is capped at 512
+    cap = pf.Index(X[:200], 1 << 40, seed=6)
+    assert cap.L == 512
+
+
+def test_max_dimension_parity():
+    """d = 4096 (the largest supported): rows longer than any specialised re-rank length,
+    hash reduction beyond the GEMM path (FP64 hashing), exact against the oracle."""
+    X = workloads.gaussian_unit(600, 4096, 204)
+    Q = workloads.gaussian_unit(20, 4096, 205)
+    g, o = _build_both(X, L=6, seed=7, M=2)
+    _assert_index_equal(g, o)
+    _assert_search_equal(g.search(Q, 5, 0.9), o.search(Q, 5, 0.9), "d=4096")
+    with pytest.raises(pf.PfError):
+        pf.Index(workloads.gaussian_unit(10, 4097, 206), 0, L=2)
