@@ -304,8 +304,115 @@ __global__ __launch_bounds__(256) void k_cp_hash(const float *__restrict__ X, in
     }
 }
 
+// The same codes with the point in registers, for d' <= 256: lane l holds elements
+// l + 64 t (t < E = max(1, d'/64)); butterflies of stride h < 64 pair lanes l and l^h
+// (exchanged across lanes), larger strides pair registers of one lane.  The lane whose
+// element has bit h clear computes a + b, its partner a - b, with a, b the same operands as
+// in the definition.  A table's sign words are loaded once, before its first function.
+template <int E>
+__global__ __launch_bounds__(256) void k_cp_hash_reg(const float *__restrict__ X, int64_t n, int32_t dpad, int32_t d,
+                                                     int32_t dp, int32_t ell, int32_t c, int32_t L, int32_t K,
+                                                     const uint32_t *__restrict__ sign,
+                                                     uint32_t *__restrict__ codes) {
+    constexpr int CMAX = 32; // functions per table (c = ceil(K / ell) <= 32)
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const float *xr = X + i * (int64_t)dpad;
+    const bool live = lane < dp; // d' < 64 leaves lanes idle
+    double x0[E];
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int e = lane + 64 * t;
+        x0[t] = (live && e < d) ? (double)xr[e] : 0.0;
+    }
+    const int32_t sw = (dp + 31) / 32;
+    for (int32_t j = 0; j < L; ++j) {
+        // this lane's sign bits of the table's functions: bit (f, k, t)
+        uint32_t sbits[CMAX];
+#pragma unroll
+        for (int f = 0; f < CMAX; ++f) sbits[f] = 0;
+        for (int f = 0; f < c; ++f) {
+            uint32_t b = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int t = 0; t < E; ++t) {
+                    const int e = lane + 64 * t;
+                    const uint32_t wv = live ? sign[((int64_t)j * c + f) * 3 * sw + k * sw + (e >> 5)] : 0u;
+                    b |= ((wv >> (e & 31)) & 1u) << (k * E + t);
+                }
+            sbits[f] = b;
+        }
+        uint64_t cat = 0;
+        for (int f = 0; f < c; ++f) {
+            double y[E];
+#pragma unroll
+            for (int t = 0; t < E; ++t) y[t] = x0[t];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+#pragma unroll
+                for (int t = 0; t < E; ++t)
+                    if ((sbits[f] >> (k * E + t)) & 1u) y[t] = -y[t];
+                for (int h = 1; h < dp && h < 64; h <<= 1) {
+                    const bool upper = (lane & h) != 0;
+#pragma unroll
+                    for (int t = 0; t < E; ++t) {
+                        const double o = __shfl_xor(y[t], h);
+                        y[t] = upper ? (o - y[t]) : (y[t] + o);
+                    }
+                }
+#pragma unroll
+                for (int hb = 1; hb < E; hb <<= 1)
+#pragma unroll
+                    for (int t = 0; t < E; ++t)
+                        if (!(t & hb)) {
+                            const double a = y[t], b = y[t + hb];
+                            y[t] = a + b;
+                            y[t + hb] = a - b;
+                        }
+            }
+            double best = -1.0, bv = 0.0;
+            int bi = 0;
+#pragma unroll
+            for (int t = 0; t < E; ++t)
+                if (live && fabs(y[t]) > best) {
+                    best = fabs(y[t]);
+                    bv = y[t];
+                    bi = lane + 64 * t;
+                }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ob = __shfl_xor(best, o);
+                const double ov = __shfl_xor(bv, o);
+                const int oi = __shfl_xor(bi, o);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            cat = (cat << ell) | ((bv < 0.0 ? (uint32_t)dp : 0u) + (uint32_t)bi);
+        }
+        if (lane == 0) codes[(int64_t)j * n + i] = (uint32_t)(cat >> (c * ell - K));
+    }
+}
+
 void cp_codes(const Index &ix, const float *X, int64_t n, uint32_t *codes, hipStream_t s) {
     if (n <= 0) return;
+    if (ix.cp_dp <= 256 && ix.cp_c <= 32) {
+        const dim3 grid((unsigned)((n + 3) / 4));
+        if (ix.cp_dp <= 64)
+            hipLaunchKernelGGL(k_cp_hash_reg<1>, grid, dim3(256), 0, s, X, n, ix.dpad, ix.d, ix.cp_dp, ix.cp_ell,
+                               ix.cp_c, ix.L, ix.K, ix.cpsign.as<uint32_t>(), codes);
+        else if (ix.cp_dp <= 128)
+            hipLaunchKernelGGL(k_cp_hash_reg<2>, grid, dim3(256), 0, s, X, n, ix.dpad, ix.d, ix.cp_dp, ix.cp_ell,
+                               ix.cp_c, ix.L, ix.K, ix.cpsign.as<uint32_t>(), codes);
+        else
+            hipLaunchKernelGGL(k_cp_hash_reg<4>, grid, dim3(256), 0, s, X, n, ix.dpad, ix.d, ix.cp_dp, ix.cp_ell,
+                               ix.cp_c, ix.L, ix.K, ix.cpsign.as<uint32_t>(), codes);
+        PF_HIP(hipGetLastError());
+        return;
+    }
     const size_t lds = (size_t)4 * ix.cp_dp * sizeof(double);
     PF_HIP(hipFuncSetAttribute((const void *)k_cp_hash, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_cp_hash, dim3((unsigned)((n + 3) / 4)), dim3(256), lds, s, X, n, ix.dpad, ix.d, ix.cp_dp,
