@@ -309,6 +309,47 @@ __global__ __launch_bounds__(256) void k_cp_hash(const float *__restrict__ X, in
 // (exchanged across lanes), larger strides pair registers of one lane.  The lane whose
 // element has bit h clear computes a + b, its partner a - b, with a, b the same operands as
 // in the definition.  A table's sign words are loaded once, before its first function.
+// value of lane l ^ H for a 64-bit value: DPP for H <= 8 (quad_perm; row_shl:H hands lane
+// l the value of lane l + H, row_shr:H that of l - H, within rows of 16), ds_swizzle for
+// H = 16 (xor within 32 lanes), a lane permute for H = 32.  Called with every lane of the
+// wave active.
+template <int CTRL> __device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int H> __device__ __forceinline__ uint32_t xor_lane32(uint32_t v, int lane) {
+    if constexpr (H == 1) return dpp32<0xB1>(v);
+    else if constexpr (H == 2) return dpp32<0x4E>(v);
+    else if constexpr (H == 4 || H == 8) {
+        // both moves on every lane (a DPP read of a lane outside the active mask is not
+        // defined), then a select
+        const uint32_t up = dpp32<0x100 + H>(v), down = dpp32<0x110 + H>(v);
+        return (lane & H) ? down : up;
+    }
+    else if constexpr (H == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+    else return (uint32_t)__shfl_xor((int)v, 32);
+}
+template <int H> __device__ __forceinline__ double xor_lane(double v, int lane) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = xor_lane32<H>((uint32_t)u, lane), hi = xor_lane32<H>((uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <int H> __device__ __forceinline__ void fht_stage(double *y, int E, int lane) {
+    const bool upper = (lane & H) != 0;
+    for (int t = 0; t < E; ++t) {
+        const double o = xor_lane<H>(y[t], lane);
+        y[t] = upper ? (o - y[t]) : (y[t] + o);
+    }
+}
+template <int H> __device__ __forceinline__ void argmax_step(double &best, double &bv, int &bi, int lane) {
+    const double ob = xor_lane<H>(best, lane), ov = xor_lane<H>(bv, lane);
+    const int oi = (int)xor_lane32<H>((uint32_t)bi, lane);
+    if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bv = ov;
+        bi = oi;
+    }
+}
+
 template <int E>
 __global__ __launch_bounds__(256) void k_cp_hash_reg(const float *__restrict__ X, int64_t n, int32_t dpad, int32_t d,
                                                      int32_t dp, int32_t ell, int32_t c, int32_t L, int32_t K,
@@ -354,14 +395,14 @@ __global__ __launch_bounds__(256) void k_cp_hash_reg(const float *__restrict__ X
 #pragma unroll
                 for (int t = 0; t < E; ++t)
                     if ((sbits[f] >> (k * E + t)) & 1u) y[t] = -y[t];
-                for (int h = 1; h < dp && h < 64; h <<= 1) {
-                    const bool upper = (lane & h) != 0;
-#pragma unroll
-                    for (int t = 0; t < E; ++t) {
-                        const double o = __shfl_xor(y[t], h);
-                        y[t] = upper ? (o - y[t]) : (y[t] + o);
-                    }
-                }
+                // strides below 64 pair lanes (d' < 64: only strides below d', whose partners
+                // stay among the live lanes)
+                if (dp > 1) fht_stage<1>(y, E, lane);
+                if (dp > 2) fht_stage<2>(y, E, lane);
+                if (dp > 4) fht_stage<4>(y, E, lane);
+                if (dp > 8) fht_stage<8>(y, E, lane);
+                if (dp > 16) fht_stage<16>(y, E, lane);
+                if (dp > 32) fht_stage<32>(y, E, lane);
 #pragma unroll
                 for (int hb = 1; hb < E; hb <<= 1)
 #pragma unroll
@@ -381,16 +422,12 @@ __global__ __launch_bounds__(256) void k_cp_hash_reg(const float *__restrict__ X
                     bv = y[t];
                     bi = lane + 64 * t;
                 }
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ob = __shfl_xor(best, o);
-                const double ov = __shfl_xor(bv, o);
-                const int oi = __shfl_xor(bi, o);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bv = ov;
-                    bi = oi;
-                }
-            }
+            argmax_step<32>(best, bv, bi, lane);
+            argmax_step<16>(best, bv, bi, lane);
+            argmax_step<8>(best, bv, bi, lane);
+            argmax_step<4>(best, bv, bi, lane);
+            argmax_step<2>(best, bv, bi, lane);
+            argmax_step<1>(best, bv, bi, lane);
             cat = (cat << ell) | ((bv < 0.0 ? (uint32_t)dp : 0u) + (uint32_t)bi);
         }
         if (lane == 0) codes[(int64_t)j * n + i] = (uint32_t)(cat >> (c * ell - K));
