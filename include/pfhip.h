@@ -97,6 +97,11 @@ typedef struct {
     int32_t no_prefilter; /* 1: compute every re-ranked inner product from both 16-bit
                              planes (the upper-plane bound rules nothing out); results
                              are the same either way, only the bytes read differ       */
+    int32_t tile;      /* 0: the default kernel tile shape (pf_search: the library's default;
+                          pf_search_batch: the autotuned or cached one, else the default);
+                          t + 1: shape t, 0 <= t < pf_tile_count()
+                          (results are the same for every shape, only the speed differs);
+                          PF_EINVAL beyond the count                                      */
 } pf_search_opts;
 
 typedef struct {
@@ -125,6 +130,11 @@ typedef struct {
     int32_t tile;         /* tile shape the search kernel ran with (batched calls) */
     int32_t waves_per_cu; /* cap on resident query waves per CU (0 = occupancy limit) */
 } pf_timing;
+
+/* Number of kernel tile shapes the library is built with, and the name of shape t
+ * (a static string; "?" when t is out of range). */
+int32_t pf_tile_count(void);
+const char *pf_tile_name(int32_t t);
 
 /* pf_search_batch flags */
 #define PF_BATCH_LEARNED 1  /* order the work queue longest-predicted-first by the

@@ -32,6 +32,7 @@ PF_SCHED_IN, PF_SCHED_OUT, PF_SCHED_PARAMS = 98, 2, 29442
 
 EXPORTED = ["pf_normalize", "pf_build_index", "pf_search", "pf_search_ex", "pf_search_batch", "pf_hash",
             "pf_export", "pf_index_info", "pf_last_timing", "pf_free_index", "pf_last_error", "pf_version",
+            "pf_tile_count", "pf_tile_name",
             "pf_sched_create", "pf_sched_free", "pf_sched_params", "pf_features", "pf_sched_predict",
             "pf_sched_grad", "pf_sched_train", "pf_sched_save", "pf_sched_load", "pf_index_set_scheduler"]
 
@@ -50,7 +51,8 @@ class pf_build_opts(ctypes.Structure):
 
 class pf_search_opts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("B", ctypes.c_int32), ("rule", ctypes.c_int32),
-                ("no_filter", ctypes.c_int32), ("timing", ctypes.c_int32), ("no_prefilter", ctypes.c_int32)]
+                ("no_filter", ctypes.c_int32), ("timing", ctypes.c_int32), ("no_prefilter", ctypes.c_int32),
+                ("tile", ctypes.c_int32)]
 
 
 class pf_query_stats(ctypes.Structure):
@@ -95,6 +97,10 @@ def lib():
         L.pf_last_error.argtypes = []
         L.pf_version.restype = ctypes.c_char_p
         L.pf_version.argtypes = []
+        L.pf_tile_count.restype = _I32
+        L.pf_tile_count.argtypes = []
+        L.pf_tile_name.restype = ctypes.c_char_p
+        L.pf_tile_name.argtypes = [_I32]
         L.pf_normalize.restype = ctypes.c_int
         L.pf_normalize.argtypes = [_P, _I64, _I32, _P, _I32, _P]
         L.pf_build_index.restype = ctypes.c_int
@@ -187,6 +193,14 @@ def pf_version() -> str:
     return lib().pf_version().decode()
 
 
+def pf_tile_count() -> int:
+    return int(lib().pf_tile_count())
+
+
+def pf_tile_name(t: int) -> str:
+    return lib().pf_tile_name(t).decode()
+
+
 def pf_normalize(x):
     x = _f32(x)
     out = _empty_like_input(x, tuple(x.shape), np.float32, x.dtype if _is_torch(x) else None)
@@ -263,13 +277,16 @@ class Index:
 
     def search(self, queries, k: int, recall: float, eps: float = 0.0, B: int = 12,
                rule: int = PF_RULE_FILTER, filter: bool = True, timing: bool = False,
-               want_ips: bool = True, want_stats: bool = True, prefilter: bool = True) -> SearchResult:
+               want_ips: bool = True, want_stats: bool = True, prefilter: bool = True,
+               tile: int = None) -> SearchResult:
+        """tile: kernel tile shape index (None: the default shape)."""
         q = _f32(queries)
         m = q.shape[0]
         ids = _empty_like_input(q, (m, k), np.int32, _torch_dtype("int32"))
         ips = _empty_like_input(q, (m, k), np.float32, _torch_dtype("float32")) if want_ips else None
         st = _empty_like_input(q, (m, 5), np.int64, _torch_dtype("int64")) if want_stats else None
-        opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1)
+        opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1,
+                              0 if tile is None else tile + 1)
         pq, mem, stream = _buf(q)
         _check(lib().pf_search_ex(self._h, pq, m, k, recall, ctypes.byref(opts), _buf(ids)[0],
                                   _buf(ips)[0], _buf(st)[0], mem, stream))
@@ -277,8 +294,10 @@ class Index:
 
     def search_batch(self, queries, ks, recalls, kmax: int, order=None, learned: bool = False,
                      autotune: bool = False, eps: float = 0.0, B: int = 12, rule: int = PF_RULE_FILTER,
-                     filter: bool = True, timing: bool = False, prefilter: bool = True) -> SearchResult:
-        """One persistent launch over all queries with per-query k and recall (work queue)."""
+                     filter: bool = True, timing: bool = False, prefilter: bool = True,
+                     tile: int = None) -> SearchResult:
+        """One persistent launch over all queries with per-query k and recall (work queue);
+        tile: kernel tile shape index (None: the autotuned or cached shape)."""
         q = _f32(queries)
         m = q.shape[0]
         torch_in = _is_torch(q)
@@ -298,7 +317,8 @@ class Index:
         ids = _empty_like_input(q, (m, kmax), np.int32, _torch_dtype("int32"))
         ips = _empty_like_input(q, (m, kmax), np.float32, _torch_dtype("float32"))
         st = _empty_like_input(q, (m, 5), np.int64, _torch_dtype("int64"))
-        opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1)
+        opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1,
+                              0 if tile is None else tile + 1)
         flags = (PF_BATCH_LEARNED if learned else 0) | (PF_BATCH_AUTOTUNE if autotune else 0)
         pq, mem, stream = _buf(q)
         _check(lib().pf_search_batch(self._h, pq, m, _buf(ks_a)[0], _buf(rec_a)[0], kmax, ctypes.byref(opts),

@@ -6,7 +6,7 @@
 // sketch) <= tau (Sec. 4.2 "Filtering candidate points", tau from Sec. 5.1, fixed for
 // the round); passing points not yet re-ranked get their exact FP32 inner product and
 // enter the top-k; after all tables the stopping bound of Lemma 1 is tested in FP64.
-// Round 0 is a linear scan.
+// The last round, i = 0, is a linear scan.
 //
 // k_ranges: for every (query, table) the bounds [lo_i, hi_i) of the entries sharing the
 // query's i-bit prefix for the levels i > P that the P-bit prefix table cannot answer.
@@ -259,15 +259,19 @@ int32_t rule_table_cols() { return kTauCols; }
 //
 // Tile shape: EPT sketch loads in flight per lane in a filter chunk, U rows in flight
 // per 16-lane group in the re-rank, WPE the query waves per SIMD the register allocation
-// must allow (1 = no constraint); DT = 64-float chunks per row (0 = any length).
+// must allow (1 = no constraint), LATE: point ids read for passing entries only, one
+// chunk late (else for every scanned entry, with its sketch); DT = 64-float chunks per
+// row (0 = any length).
 static constexpr int WV = 64; // lanes per query wave
-template <int EPT_, int U_, int WPE_ = 1> struct Tile {
+template <int EPT_, int U_, int WPE_ = 1, bool LATE_ = false> struct Tile {
     static constexpr int EPT = EPT_;
     static constexpr int U = U_;
     static constexpr int WPE = WPE_;
+    static constexpr bool LATE = LATE_;
     static constexpr int WCH = WV * EPT;       // entries per filter chunk
     static constexpr int RB = 64;              // re-rank once this many candidates wait
-    static constexpr int PCAP = WCH + RB;      // pending capacity
+    static constexpr int UCAP = LATE ? WV : 0; // passing entries whose point id is still being read
+    static constexpr int PCAP = WCH + RB + UCAP; // pending capacity
     static constexpr int CW = U >= 8 ? 256 : 128; // candidate buffer (power of two)
     static constexpr int RROWS = 4 * U;        // rows re-ranked per wave iteration
     static_assert(PCAP % WV == 0, "pending capacity must be a multiple of the wave size");
@@ -332,7 +336,7 @@ __device__ __forceinline__ int count_greater(const unsigned long long *arr, int 
 
 struct WLds {
     unsigned long long *top, *ntop, *cand, *tq;
-    uint32_t *pending, *clo, *chi, *qc, *segBeg, *segStart, *segTab;
+    uint32_t *pending, *upos, *clo, *chi, *qc, *segBeg, *segStart, *segTab;
     uint32_t *qb, *qba; // query as bfloat16 pairs (round to nearest even) and their magnitudes
     float *qv;
 };
@@ -341,11 +345,11 @@ __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t
 
 // Byte offsets of the wave's LDS arrays in the dynamic shared memory block.
 struct LdsOff {
-    uint32_t top, ntop, cand, tq, pending, clo, chi, qc, segBeg, segStart, segTab, qb, qba, qv, total;
+    uint32_t top, ntop, cand, tq, pending, upos, clo, chi, qc, segBeg, segStart, segTab, qb, qba, qv, total;
 };
 
-// pcap, cw: the tile's pending and candidate capacities
-__host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad, int pcap, int cw) {
+// pcap, cw, ucap: the tile's pending, candidate and late-id capacities
+__host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad, int pcap, int cw, int ucap) {
     LdsOff o;
     uint32_t off = 0;
     auto take = [&](size_t bytes) {
@@ -358,6 +362,7 @@ __host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad, 
     o.cand = take(sizeof(unsigned long long) * cw);
     o.tq = take(sizeof(unsigned long long) * L);
     o.pending = take(sizeof(uint32_t) * pcap);
+    o.upos = take(sizeof(uint32_t) * ucap);
     o.clo = take(sizeof(uint32_t) * L);
     o.chi = take(sizeof(uint32_t) * L);
     o.qc = take(sizeof(uint32_t) * L);
@@ -759,13 +764,14 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
     // compiler keeps them in the LDS address space (ds_read / ds_write, counted by
     // lgkmcnt alone); a generic pointer would turn each LDS access into a flat access
     // that also waits for every global load in flight
-    const LdsOff lo_ = search_lds_offsets(p.L, p.kmax, p.dpad, TL::PCAP, TL::CW);
+    const LdsOff lo_ = search_lds_offsets(p.L, p.kmax, p.dpad, TL::PCAP, TL::CW, TL::UCAP);
     WLds l;
     l.top = reinterpret_cast<unsigned long long *>(smem + lo_.top);
     l.ntop = reinterpret_cast<unsigned long long *>(smem + lo_.ntop);
     l.cand = reinterpret_cast<unsigned long long *>(smem + lo_.cand);
     l.tq = reinterpret_cast<unsigned long long *>(smem + lo_.tq);
     l.pending = reinterpret_cast<uint32_t *>(smem + lo_.pending);
+    l.upos = reinterpret_cast<uint32_t *>(smem + lo_.upos);
     l.clo = reinterpret_cast<uint32_t *>(smem + lo_.clo);
     l.chi = reinterpret_cast<uint32_t *>(smem + lo_.chi);
     l.qc = reinterpret_cast<uint32_t *>(smem + lo_.qc);
@@ -862,15 +868,20 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             int sg = -1;
             uint32_t segEnd = 0, ebase = 0;
             int32_t tjc = 0;
+            // LATE tiles: the previous chunk's passing entries (at most UCAP) wait in upos
+            // as table positions, and their point ids are read together with this chunk's
+            // sketches, so that positions are read for passing entries only and no load
+            // waits for another.  Other tiles read the position of every entry with its
+            // sketch.
+            int nu = 0;
             for (uint32_t base = 0; base < total; base += WCH) {
-                uint32_t xv[EPT];
+                uint32_t ev[EPT];
                 int32_t tj[EPT];
                 uint64_t skv[EPT];
-                // sketches and positions of the chunk's entries, all loads in flight together
-                // (a position load made to wait for its sketch test costs a second memory
-                // round trip per chunk, more than the position bytes it saves)
                 // (entries past the end load entry 0 of table 0 and are masked out, so that
-                // every load is unconditional and none waits for another)
+                // every load is unconditional)
+                uint32_t uid = 0;
+                if constexpr (TL::LATE) uid = p.tidx[lane < nu ? l.upos[lane] : 0u];
                 uint32_t valid = 0;
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
@@ -888,20 +899,57 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                     tj[u] = tjc;
                     const uint32_t e = in ? ebase + f : 0u;
                     skv[u] = p.tsk[e];
-                    xv[u] = p.tidx[e];
+                    ev[u] = TL::LATE ? e : p.tidx[e];
                 }
+                if constexpr (TL::LATE) {
+                    if (lane < nu) l.pending[st.pend + lane] = uid;
+                    st.pend += nu;
+                }
+                uint32_t pm = 0;
+                uint64_t mk[EPT];
+                int np = 0;
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
                     const bool pass = ((valid >> u) & 1u) && __popcll(skv[u] ^ l.tq[tj[u]]) <= tau;
-                    const uint64_t mk = __ballot(pass);
-                    if (pass) l.pending[st.pend + __popcll(mk & lt)] = xv[u];
-                    st.pend += __popcll(mk);
+                    pm |= (pass ? 1u : 0u) << u;
+                    mk[u] = __ballot(pass);
+                    np += __popcll(mk[u]);
+                }
+                if (TL::LATE && np <= TL::UCAP) {
+                    wsync();
+                    int at = 0;
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) {
+                        if ((pm >> u) & 1u) l.upos[at + __popcll(mk[u] & lt)] = ev[u];
+                        at += __popcll(mk[u]);
+                    }
+                    nu = np;
+                } else {
+                    // (LATE: more passing entries than upos holds, as on a level where the
+                    // filter passes nearly everything: their ids are read now, all loads in
+                    // flight)
+                    if constexpr (TL::LATE) {
+#pragma unroll
+                        for (int u = 0; u < EPT; ++u) ev[u] = p.tidx[((pm >> u) & 1u) ? ev[u] : 0u];
+                        nu = 0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < EPT; ++u) {
+                        if ((pm >> u) & 1u) l.pending[st.pend + __popcll(mk[u] & lt)] = ev[u];
+                        st.pend += __popcll(mk[u]);
+                    }
                 }
                 if (st.pend >= RB) {
                     st.c_pass += st.pend;
                     wsync();
                     wave_process<DT, TL>(p, l, st);
                 }
+            }
+            if (TL::LATE && nu > 0) {
+                wsync();
+                const uint32_t uid = p.tidx[lane < nu ? l.upos[lane] : 0u];
+                if (lane < nu) l.pending[st.pend + lane] = uid;
+                st.pend += nu;
             }
             if (st.pend > 0) {
                 st.c_pass += st.pend;
@@ -979,11 +1027,13 @@ using T48 = Tile<4, 8>;
 using T168 = Tile<16, 8>;
 using T84 = Tile<8, 4>;
 using T84o4 = Tile<8, 4, 4>; // registers capped for 4 waves per SIMD (16 per CU)
-static constexpr int kNumTiles = 5;
-static const char *kTileNames[kNumTiles] = {"ept8-u8", "ept4-u8", "ept16-u8", "ept8-u4", "ept8-u4-o4"};
+using T84o4l = Tile<8, 4, 4, true>;
+static constexpr int kNumTiles = 6;
+static const char *kTileNames[kNumTiles] = {"ept8-u8", "ept4-u8", "ept16-u8", "ept8-u4", "ept8-u4-o4",
+                                            "ept8-u4-o4-late"};
 
 template <class TL> static size_t tile_lds(const Index &ix, int32_t kmax) {
-    return search_lds_offsets(ix.L, kmax, ix.dpad, TL::PCAP, TL::CW).total;
+    return search_lds_offsets(ix.L, kmax, ix.dpad, TL::PCAP, TL::CW, TL::UCAP).total;
 }
 static size_t search_lds_bytes(const Index &ix, int32_t kmax, int tile) {
     switch (tile) {
@@ -991,6 +1041,7 @@ static size_t search_lds_bytes(const Index &ix, int32_t kmax, int tile) {
     case 2: return tile_lds<T168>(ix, kmax);
     case 3: return tile_lds<T84>(ix, kmax);
     case 4: return tile_lds<T84o4>(ix, kmax);
+    case 5: return tile_lds<T84o4l>(ix, kmax);
     default: return tile_lds<T88>(ix, kmax);
     }
 }
@@ -1001,6 +1052,7 @@ template <int DT> static const void *search_kernel_dt(int tile) {
     case 2: return (const void *)k_search<DT, T168>;
     case 3: return (const void *)k_search<DT, T84>;
     case 4: return (const void *)k_search<DT, T84o4>;
+    case 5: return (const void *)k_search<DT, T84o4l>;
     default: return (const void *)k_search<DT, T88>;
     }
 }
@@ -1015,6 +1067,9 @@ static const void *search_kernel(int dt, int tile) {
 }
 
 int32_t search_tile_count() { return kNumTiles; }
+// the shape used when none is given or tuned: the fastest on the 1 M-point, d = 100
+// mixture at k = 10 both with static query slots and with the work queue
+int32_t search_default_tile() { return 5; }
 const char *search_tile_name(int32_t t) { return (t >= 0 && t < kNumTiles) ? kTileNames[t] : "?"; }
 
 // resident query waves per CU for a tile shape (occupancy from registers and LDS)
@@ -1029,13 +1084,14 @@ int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile) {
 }
 
 int64_t search_slots(const Index &ix, int64_t m) {
-    return std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)ix.num_cus * search_waves_per_cu(ix, PF_MAX_K, 0)));
+    return std::max<int64_t>(1, std::min<int64_t>(
+                                    m, (int64_t)ix.num_cus * search_waves_per_cu(ix, PF_MAX_K, search_default_tile())));
 }
 
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s) {
     if (a.m <= 0) return;
     const int dt = row_chunks(ix.dpad);
-    const int tile = (a.tile >= 0 && a.tile < kNumTiles) ? a.tile : 0;
+    const int tile = (a.tile >= 0 && a.tile < kNumTiles) ? a.tile : search_default_tile();
     const size_t lds = search_lds_bytes(ix, a.kmax, tile);
     const void *fn = search_kernel(dt, tile);
     PF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

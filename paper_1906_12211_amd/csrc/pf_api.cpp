@@ -276,6 +276,10 @@ using namespace pf;
 PF_API const char *pf_last_error(void) { return g_err.c_str(); }
 PF_API const char *pf_version(void) { return "pfhip 0.1 (gfx950)"; }
 
+PF_API int32_t pf_tile_count(void) { return pf::search_tile_count(); }
+
+PF_API const char *pf_tile_name(int32_t t) { return pf::search_tile_name(t); }
+
 PF_API int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, void *stream) {
     return guard([&] {
         PF_CHECK(x && out && n >= 0 && d >= 1 && d <= PF_MAX_DIM, PF_EINVAL, "pf_normalize: bad arguments");
@@ -445,7 +449,7 @@ std::vector<int32_t> learned_order(Index &ix, const uint32_t *qcode, const uint6
 // fastest is kept per (architecture, n, d, L, kmax) in memory and, when the environment
 // variable PF_TUNE_CACHE names a file, in that file as JSON lines.
 struct TuneChoice {
-    int32_t tile = 0, waves = 0;
+    int32_t tile = search_default_tile(), waves = 0;
     double us_per_query = 0.0;
 };
 
@@ -564,6 +568,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
              PF_EINVAL,
              "search: bad rule");
     PF_CHECK(std::isfinite(o.eps) && o.eps > -1.0, PF_EINVAL, "search: eps must be finite and > -1");
+    PF_CHECK(o.tile >= 0 && o.tile <= search_tile_count(), PF_EINVAL, "search: tile must be in [0, pf_tile_count()]");
     if (!recalls)
         PF_CHECK(recall_const > 0.0 && recall_const <= 1.0, PF_EINVAL, "search: recall must be in (0, 1]");
     if (m == 0) return;
@@ -675,7 +680,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     a.prefilter = o.no_prefilter ? 0 : 1;
     a.queue = nullptr;
     a.order = nullptr;
-    a.tile = 0;
+    a.tile = o.tile > 0 ? o.tile - 1 : search_default_tile();
     a.waves_per_cu = 0;
     a.out_ids = oid;
     a.out_ips = oip;
@@ -712,9 +717,11 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
             PF_HIP(hipMemcpyAsync(dorder.p, ord.data(), (size_t)m * sizeof(int32_t), h2d, s));
             a.order = dorder.as<int32_t>();
         }
-        const TuneChoice tc = bc.autotune ? autotune(*ix, a, kmax, s) : cached_tuning(*ix, kmax);
-        a.tile = tc.tile;
-        a.waves_per_cu = tc.waves;
+        if (o.tile == 0) {
+            const TuneChoice tc = bc.autotune ? autotune(*ix, a, kmax, s) : cached_tuning(*ix, kmax);
+            a.tile = tc.tile;
+            a.waves_per_cu = tc.waves;
+        }
     }
     if (o.timing) PF_HIP(hipEventRecord(ev[2], s));
     launch_search(*ix, a, rg, s);

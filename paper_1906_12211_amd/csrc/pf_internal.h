@@ -205,6 +205,7 @@ int32_t rule_table_cols();
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s);
 int64_t search_slots(const Index &ix, int64_t m);
 int32_t search_tile_count();
+int32_t search_default_tile();
 const char *search_tile_name(int32_t t);
 int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile);
 

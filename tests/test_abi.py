@@ -38,6 +38,9 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n)
     assert sorted(pf.EXPORTED) == names
     assert pf.pf_version().startswith("pfhip")
+    names = [pf.pf_tile_name(t) for t in range(pf.pf_tile_count())]
+    assert len(names) >= 1 and len(set(names)) == len(names) and "?" not in names
+    assert pf.pf_tile_name(-1) == "?" and pf.pf_tile_name(len(names)) == "?"
 
 
 def test_binding_constants_match_header():

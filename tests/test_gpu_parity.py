@@ -268,13 +268,42 @@ def test_batch_per_query_params_and_order():
     _assert_batch_equal(g.search_batch(Q, ks, recalls, 100, autotune=True, timing=True), oids, oips, ost, obd,
                         "autotuned")
     t = g.last_timing()
-    assert 0 <= t.tile < 5 and t.waves_per_cu >= 1
+    assert 0 <= t.tile < pf.pf_tile_count() and t.waves_per_cu >= 1
     with pytest.raises(pf.PfError):
         g.search_batch(Q, ks, recalls, 100, order=np.zeros(len(Q), dtype=np.int32))
     bad = ks.copy()
     bad[3] = 101
     with pytest.raises(pf.PfError):
         g.search_batch(Q, bad, recalls, 100)
+
+
+@pytest.mark.parametrize("d", [40, 100, 200, 300])
+def test_every_tile_shape(d):
+    """Every built kernel tile shape (sketch loads per lane, rows in flight, register cap,
+    point ids read with every sketch or only for passing entries) at every row-length
+    specialisation (d = 40, 100, 200, 300: one, two, four and any number of 64-float
+    chunks) gives the oracle's answers, single and batched."""
+    X = workloads.gaussian_unit(3000, d, 300 + d)
+    Q = workloads.gaussian_unit(160, d, 400 + d)
+    rng = np.random.default_rng(d)
+    ks = rng.choice(np.array([1, 10, 40], dtype=np.int32), size=len(Q))
+    recalls = rng.choice(np.array([0.7, 0.95]), size=len(Q))
+    g, o = _build_both(X, L=40, seed=23)
+    oids, oips, ost, obd = _oracle_per_query(o, Q, ks, recalls, 40)
+    r10 = o.search(Q, 10, 0.9)
+    ok10 = r10.boundary == 0
+    names = [pf.pf_tile_name(t) for t in range(pf.pf_tile_count())]
+    assert len(set(names)) == len(names) and pf.pf_tile_name(len(names)) == "?"
+    for t, name in enumerate(names):
+        print(f"[tile] d={d} shape {t} {name}", flush=True)
+        _assert_batch_equal(g.search_batch(Q, ks, recalls, 40, tile=t, timing=True), oids, oips, ost, obd,
+                            f"tile {name}")
+        assert g.last_timing().tile == t
+        r = g.search(Q, 10, 0.9, tile=t)
+        assert np.array_equal(r.ids[ok10], r10.ids[ok10]), name
+        assert np.array_equal(r.ips[ok10].view(np.uint32), r10.ips[ok10].view(np.uint32)), name
+    with pytest.raises(pf.PfError):
+        g.search(Q, 10, 0.9, tile=len(names))
 
 
 def test_batch_device_tensors():
