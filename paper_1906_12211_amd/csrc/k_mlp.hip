@@ -1,6 +1,7 @@
 // Kernels of the learned scheduler: per-query features and a 98-128-128-2 FP32 MLP
 // (forward, mean-squared-error gradient, backward, Adam).  The network only orders the
 // batched search's work queue; the stopping rule alone decides when a query ends.
+#include "pf_device.h"
 #include "pf_internal.h"
 
 namespace pf {
@@ -158,6 +159,23 @@ void mlp_backward(const float *params, const float *x, const int32_t *rows, cons
                        h1, kSchedHidden, kSchedHidden, B, dh1);
     hipLaunchKernelGGL(k_dense_wgrad, dim3(grid_for((int64_t)kSchedIn * kSchedHidden + kSchedHidden)), dim3(256),
                        0, s, x, rows, (const float *)dh1, kSchedIn, kSchedHidden, B, grad + kOffW1, grad + kOffB1);
+    PF_HIP(hipGetLastError());
+}
+
+// Sort keys of the longest-predicted-first order: ascending unsigned keys = descending
+// predicted cost (column 1 of y, B x 2); the map is monotone on the FP32 total order, and
+// a NaN prediction sorts last.
+__global__ __launch_bounds__(256) void k_lpt_keys(const float *__restrict__ y, int64_t B,
+                                                  uint32_t *__restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    const float v = y[i * 2 + 1];
+    keys[i] = isnan(v) ? 0xFFFFFFFFu : ~ord_of(v);
+}
+
+void launch_lpt_keys(const float *y, int64_t B, uint32_t *keys, hipStream_t s) {
+    if (B <= 0) return;
+    hipLaunchKernelGGL(k_lpt_keys, dim3(grid_for(B)), dim3(256), 0, s, y, B, keys);
     PF_HIP(hipGetLastError());
 }
 

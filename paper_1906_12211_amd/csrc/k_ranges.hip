@@ -1,0 +1,178 @@
+// Prefix ranges of the level-synchronous walk (Sec. 4.2 "Retrieving candidate points"):
+// for every (query q, table j) and level i = P+1..K, the entries of table j whose codes
+// share the query's i-bit prefix form the range [lo_i, hi_i) of the query's P-bit prefix
+// bucket [B0, B1) (the P-bit prefix table answers the levels i <= P directly).  With
+// lcp(c) the common prefix length of code c and the query code (at least P inside the
+// bucket) and lt(c) = [c < query code]:
+//   lo_i = B0 + #{lt, lcp < i},   hi_i = B0 + #{lt} + #{not lt, lcp >= i}.
+// ranges[q][j][i - P - 1] = (lo_i, hi_i).
+#include "pf_internal.h"
+
+namespace pf {
+
+static constexpr int kGroupMax = 4080; // buckets up to this size: one 16-lane group per pair, else
+                                       // one binary search per bound and level
+
+template <int CTRL> __device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+// sum over the 16 lanes of a DPP row, in every lane of the row
+__device__ __forceinline__ uint32_t row_sum16u(uint32_t s) {
+    s += dpp_u<0x128>(s); // row_ror:8
+    s += dpp_u<0x124>(s); // row_ror:4
+    s += dpp_u<0x122>(s); // row_ror:2
+    s += dpp_u<0x121>(s); // row_ror:1
+    return s;
+}
+
+// One 16-lane group (a DPP row) per (q, j) pair: the group reads its bucket 64 entries
+// at a time (16 consecutive codes per load instruction, four loads in flight), each lane
+// counts its entries per (lcp - P, lt) in 8-bit fields of NR registers per flag (bin b
+// in byte b & 3 of register b >> 2; at most ceil(kGroupMax / 16) = 255 entries per lane),
+// the fields are widened to 16 bits and summed over the row, and lane r writes level
+// P + 1 + r.  Pairs with larger buckets are appended to the list for k_ranges_wave.
+template <int NR>
+__global__ __launch_bounds__(256) void k_ranges_group(const uint32_t *__restrict__ tcode,
+                                                      const uint32_t *__restrict__ off, int64_t n, int32_t L,
+                                                      int32_t K, int32_t P, const uint32_t *__restrict__ qcode,
+                                                      int64_t m, uint32_t *__restrict__ ranges,
+                                                      uint32_t *__restrict__ big, uint32_t *__restrict__ nbig) {
+    const int g = threadIdx.x & 15;
+    const int64_t t = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+    if (t >= m * L) return; // whole rows leave together
+    const int64_t q = t / L;
+    const int32_t j = (int32_t)(t - q * L);
+    const int32_t nl = K - P;
+    const uint32_t qc = qcode[(int64_t)j * m + q];
+    const int64_t np1 = ((int64_t)1 << P) + 1;
+    const uint32_t b = qc >> (K - P);
+    const uint32_t B0 = off[(int64_t)j * np1 + b];
+    const uint32_t B1 = off[(int64_t)j * np1 + b + 1];
+    if (B1 - B0 > (uint32_t)kGroupMax) {
+        if (g == 0) big[atomicAdd(nbig, 1u)] = (uint32_t)t;
+        return;
+    }
+    const uint32_t *tc = tcode + (int64_t)j * n;
+    const int sh = 32 - K;
+    uint32_t clt[NR], cge[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) clt[r] = cge[r] = 0;
+    for (uint32_t e0 = B0 + g; e0 < B1; e0 += 64) {
+        uint32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = tc[e0 + 16 * u < B1 ? e0 + 16 * u : B0];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (e0 + 16 * u < B1) {
+                const uint32_t x = (c[u] ^ qc) << sh;
+                const int bin = (x ? __clz(x) : K) - P;
+                const uint32_t inc = 1u << (8 * (bin & 3));
+                const bool lt = c[u] < qc;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const uint32_t v = (bin >> 2) == r ? inc : 0u;
+                    clt[r] += lt ? v : 0u;
+                    cge[r] += lt ? 0u : v;
+                }
+            }
+        }
+    }
+    // widen to 16-bit fields (even bytes, odd bytes) and sum over the row
+    uint32_t lte[NR], lto[NR], gee[NR], geo[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        lte[r] = row_sum16u(clt[r] & 0x00FF00FFu);
+        lto[r] = row_sum16u((clt[r] >> 8) & 0x00FF00FFu);
+        gee[r] = row_sum16u(cge[r] & 0x00FF00FFu);
+        geo[r] = row_sum16u((cge[r] >> 8) & 0x00FF00FFu);
+    }
+    // lane g writes levels g and g + 16: lo counts lt with bin <= level index, hi counts
+    // not-lt with bin > level index
+    uint32_t *out = ranges + t * (int64_t)nl * 2;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int ri = g + 16 * half;
+        if (ri < nl) {
+            uint32_t lo = B0, hi = B0;
+#pragma unroll
+            for (int bb = 0; bb < 4 * NR; ++bb) {
+                const int sft = 16 * ((bb & 3) >> 1);
+                const uint32_t nlt = (((bb & 1) ? lto[bb >> 2] : lte[bb >> 2]) >> sft) & 0xFFFFu;
+                const uint32_t nge = (((bb & 1) ? geo[bb >> 2] : gee[bb >> 2]) >> sft) & 0xFFFFu;
+                hi += nlt;
+                if (bb <= ri) lo += nlt;
+                if (bb > ri) hi += nge;
+            }
+            out[2 * ri] = lo;
+            out[2 * ri + 1] = hi;
+        }
+    }
+}
+
+// one wave per listed (q, j) pair (bucket above kGroupMax entries), waves striding over
+// the list: lane 2r + s binary-searches bound s (0: lo, 1: hi) of level P + 1 + r
+__global__ __launch_bounds__(256) void k_ranges_wave(const uint32_t *__restrict__ tcode,
+                                                     const uint32_t *__restrict__ off, int64_t n, int32_t L,
+                                                     int32_t K, int32_t P, const uint32_t *__restrict__ qcode,
+                                                     int64_t m, uint32_t *__restrict__ ranges,
+                                                     const uint32_t *__restrict__ big,
+                                                     const uint32_t *__restrict__ nbig) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t count = *nbig;
+    const uint32_t nw = gridDim.x * 4;
+    for (uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6); w < count; w += nw) {
+        const int64_t t = big[w];
+        const int64_t q = t / L;
+        const int32_t j = (int32_t)(t - q * L);
+        const int32_t nl = K - P;
+        if (lane >= 2 * nl) continue;
+        const uint32_t qc = qcode[(int64_t)j * m + q];
+        const int64_t np1 = ((int64_t)1 << P) + 1;
+        const uint32_t b = qc >> (K - P);
+        const uint32_t *tc = tcode + (int64_t)j * n;
+        const int lev = P + 1 + (lane >> 1);
+        const uint64_t pre = (uint64_t)(qc >> (K - lev));
+        const uint64_t target = (lane & 1) ? ((pre + 1) << (K - lev)) : (pre << (K - lev));
+        uint32_t lo = off[(int64_t)j * np1 + b], hi = off[(int64_t)j * np1 + b + 1];
+        while (lo < hi) {
+            const uint32_t mid = lo + ((hi - lo) >> 1);
+            if ((uint64_t)tc[mid] < target)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        ranges[t * (int64_t)nl * 2 + lane] = lo;
+    }
+}
+
+template <int NR> static const void *group_kernel() { return (const void *)k_ranges_group<NR>; }
+
+void launch_ranges(Index &ix, const SearchArgs &a, uint32_t *ranges, hipStream_t s) {
+    if (ix.K <= ix.P || a.m <= 0) return;
+    const int64_t pairs = a.m * ix.L;
+    PF_CHECK(pairs < ((int64_t)1 << 32), PF_EINVAL, "search: more than 2^32 (query, table) pairs in one call");
+    ix.rlist.ensure((size_t)(pairs + 1) * sizeof(uint32_t));
+    uint32_t *nbig = ix.rlist.as<uint32_t>();
+    uint32_t *big = nbig + 1;
+    launch_fill_u32(nbig, 1, 0u, s);
+    // registers of 8-bit bin counters per flag: bins lcp - P = 0 .. K - P
+    const int nr = (ix.K - ix.P + 1 + 3) / 4;
+    const void *fn = nr <= 1 ? group_kernel<1>() : nr <= 2 ? group_kernel<2>() : nr <= 3 ? group_kernel<3>()
+                   : nr <= 4 ? group_kernel<4>() : group_kernel<5>();
+    const uint32_t *tc = ix.tcode.as<uint32_t>();
+    const uint32_t *of = ix.off.as<uint32_t>();
+    int64_t n = ix.n;
+    int32_t L = ix.L, K = ix.K, P = ix.P;
+    const uint32_t *qc = a.qcode;
+    int64_t m = a.m;
+    void *args[] = {(void *)&tc, (void *)&of, (void *)&n, (void *)&L, (void *)&K, (void *)&P,
+                    (void *)&qc, (void *)&m, (void *)&ranges, (void *)&big, (void *)&nbig};
+    PF_HIP(hipLaunchKernel(fn, dim3((unsigned)((pairs * 16 + 255) / 256)), dim3(256), args, 0, s));
+    // the list's length is known only on the device: a fixed grid strides over it
+    const int64_t wg = std::min<int64_t>((pairs + 3) / 4, (int64_t)ix.num_cus * 8);
+    hipLaunchKernelGGL(k_ranges_wave, dim3((unsigned)std::max<int64_t>(1, wg)), dim3(256), 0, s, tc, of, n, L, K,
+                       P, qc, m, ranges, big, nbig);
+    PF_HIP(hipGetLastError());
+}
+
+} // namespace pf

@@ -107,7 +107,13 @@ struct Index {
     DevBuf off;    // L x (2^P + 1) u32
 
     // search scratch (grown on demand)
-    DevBuf qX, qcode, qsk, ranges, bitmap, rlist, qstats, flags, tmp;
+    DevBuf qX, qcode, qsk, ranges, qstats, flags, tmp;
+    DevBuf rlist; // count, then the (query, table) pairs whose prefix bucket is large
+    // learned queue order scratch: features, per-query parameters (and their host copy,
+    // kept until the next call so that its asynchronous upload never reads freed memory),
+    // sort keys, sort scratch
+    DevBuf sfeat, sqp, skeys, ssort;
+    std::vector<float> sqph;
     // decision tables of the last (rule, eps, deltas) searched
     DevBuf rule_tab;
     int32_t rule_key_rule = -1, rule_key_filter = -1;
@@ -148,6 +154,8 @@ void mlp_backward(const float *params, const float *x, const int32_t *rows, cons
                   const float *h1, const float *h2, const float *y, float *dy, float *dh2, float *dh1, float *grad,
                   double *loss_acc, hipStream_t s);
 void mlp_adam(float *params, const float *grad, float *m1, float *m2, float lr, int32_t t, hipStream_t s);
+// keys whose ascending order is the descending order of column 1 of y (B x 2); NaN last
+void launch_lpt_keys(const float *y, int64_t B, uint32_t *keys, hipStream_t s);
 
 // ----------------------------------------------------------------- launchers
 // normalise: out[i][0..d) = x[i]/|x[i]|, zero-filled to dpad; *bad = min bad row (or n)
@@ -195,7 +203,7 @@ struct SearchArgs {
     float *out_ips;        // m x kmax (nullable)
     pf_query_stats *stats; // m (nullable)
 };
-void launch_ranges(const Index &ix, const SearchArgs &a, uint32_t *ranges, hipStream_t s);
+void launch_ranges(Index &ix, const SearchArgs &a, uint32_t *ranges, hipStream_t s);
 void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, int32_t rule, int32_t L,
                         int32_t M, int32_t K, int32_t pool, const double *cptab, int32_t ell, float *tauv,
                         float *stopw, hipStream_t s);

@@ -114,23 +114,27 @@ std::vector<float> sched_qparams(int64_t m, const int32_t *ks_host, int32_t kcon
     return v;
 }
 
-std::vector<int32_t> learned_order(Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m,
-                                   const int32_t *ks_host, int32_t kconst, const double *rec_host,
-                                   double recall_const, hipStream_t s) {
+void learned_order(Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m, const int32_t *ks_host,
+                   int32_t kconst, const double *rec_host, double recall_const, int32_t *order, hipStream_t s) {
     Sched &sc = *ix.sched;
-    DevBuf feat, qp;
-    feat.alloc((size_t)m * kSchedIn * sizeof(float));
-    const std::vector<float> qph = sched_qparams(m, ks_host, kconst, rec_host, recall_const);
-    qp.alloc(qph.size() * sizeof(float));
-    PF_HIP(hipMemcpyAsync(qp.p, qph.data(), qph.size() * sizeof(float), hipMemcpyHostToDevice, s));
-    launch_features(ix, qcode, qsk, m, qp.as<float>(), feat.as<float>(), s);
-    const std::vector<float> y = predict_host(sc, feat.as<float>(), m, s);
-    std::vector<int32_t> order(m);
-    std::iota(order.begin(), order.end(), 0);
-    // longest predicted first (LPT); ties by query index
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return y[(size_t)a * kSchedOut + 1] > y[(size_t)b * kSchedOut + 1]; });
-    return order;
+    ix.sqph = sched_qparams(m, ks_host, kconst, rec_host, recall_const);
+    ix.sfeat.ensure((size_t)m * kSchedIn * sizeof(float));
+    ix.sqp.ensure(ix.sqph.size() * sizeof(float));
+    ix.skeys.ensure((size_t)m * 2 * sizeof(uint32_t));
+    PF_HIP(hipMemcpyAsync(ix.sqp.p, ix.sqph.data(), ix.sqph.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    const float *feat = ix.sfeat.as<float>();
+    launch_features(ix, qcode, qsk, m, ix.sqp.as<float>(), ix.sfeat.as<float>(), s);
+    uint32_t *k = ix.skeys.as<uint32_t>();
+    const int64_t chunk = 65536;
+    sc.ensure_act(std::min(m, chunk));
+    for (int64_t r0 = 0; r0 < m; r0 += chunk) {
+        const int64_t B = std::min(chunk, m - r0);
+        mlp_forward(sc.params.as<float>(), feat + r0 * kSchedIn, nullptr, B, sc.h1(), sc.h2(), sc.y(), s);
+        launch_lpt_keys(sc.y(), B, k + r0, s);
+    }
+    // longest predicted first (LPT), ties by query index: the stable radix sort of the
+    // table builder, on one table of 32-bit keys
+    sort_tables(k, m, 1, 32, k + m, reinterpret_cast<uint32_t *>(order), ix.ssort, s);
 }
 
 } // namespace pf

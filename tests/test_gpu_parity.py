@@ -165,6 +165,32 @@ def test_prefilter_low_bits_and_subnormals():
         _assert_search_equal(g.search(Q, k, rec), o.search(Q, k, rec), f"low bits k={k}")
 
 
+def test_large_prefix_buckets():
+    """Clusters of near-identical points fill single 13-bit prefix buckets with about
+    4,000 (both sides of the 4,080-entry limit of the 16-lane range count) up to 12,000
+    entries (binary-searched ranges), around a Gaussian background."""
+    d = 32
+    rng = np.random.default_rng(601)
+    centers = workloads.gaussian_unit(4, d, 602)
+    parts = [workloads.gaussian_unit(4000, d, 603)]
+    for c, size in zip(centers, [3900, 4200, 6000, 12000]):
+        parts.append((c[None, :] + np.float32(2e-3) * rng.standard_normal((size, d))).astype(np.float32))
+    X = np.concatenate(parts)
+    Q = np.concatenate([(centers + np.float32(1e-2) * rng.standard_normal((4, d))).astype(np.float32)
+                        for _ in range(8)] + [workloads.gaussian_unit(32, d, 604)])
+    g, o = _build_both(X, L=16, seed=606)
+    off = g.export(pf.PF_EXPORT_OFFSETS)
+    sizes = np.diff(off.astype(np.int64), axis=1)
+    print(f"[buckets] largest 13-bit buckets {np.sort(sizes.ravel())[-6:]}", flush=True)
+    assert sizes.max() > 4080 and ((sizes > 3000) & (sizes <= 4080)).any()
+    for k, rec in [(1, 0.9), (10, 0.9), (50, 0.99)]:
+        _assert_search_equal(g.search(Q, k, rec), o.search(Q, k, rec), f"large buckets k={k}")
+        ks = np.full(len(Q), k, np.int32)
+        recs = np.full(len(Q), rec)
+        oids, oips, ost, obd = _oracle_per_query(o, Q, ks, recs, k)
+        _assert_batch_equal(g.search_batch(Q, ks, recs, k), oids, oips, ost, obd, f"large buckets batch k={k}")
+
+
 def test_linear_scan_equals_bruteforce():
     """recall 1: every query walks to level 0 and returns the exact k-NN (Lemma 1)."""
     X = workloads.gaussian_unit(3000, 32, 31)
