@@ -44,12 +44,14 @@ SEARCH_SRC = os.path.join(ROOT, "paper_1906_12211_amd", "csrc", "k_search.hip")
 
 def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> float:
     """Bytes the method must move for the queries of one launch of the search kernel:
-    8 B per scanned table-local sketch, 4 B per position of a passing entry, the upper
-    16-bit plane (2d B) of every re-ranked vector and the lower plane (2d B) of those
+    8 B per scanned table-local sketch, 4 B per position of a passing entry, the 8-bit
+    summary (8 + d B) of every candidate bounded from it, the upper 16-bit plane (2d B)
+    of every candidate whose upper plane was read and the lower plane (2d B) of those
     whose exact inner product was needed, the query (4d) and its result (8k), and the
     two range bounds (8 B) of every table at every visited level."""
     stop = stats[:, 0].astype(np.float64)
-    per_q = (8.0 * stats[:, 1] + 4.0 * stats[:, 2] + 2.0 * d * (stats[:, 3] + stats[:, 4]) + 4.0 * d
+    per_q = (8.0 * stats[:, 1] + 4.0 * stats[:, 2] + (8.0 + d) * stats[:, 6] + 2.0 * d * (stats[:, 5] + stats[:, 4])
+             + 4.0 * d
              + 8.0 * k + 8.0 * L * (K + 1 - np.maximum(stop, 1)))
     return float(per_q.sum())
 
@@ -177,7 +179,7 @@ def mixed_batch(ix, dev, args):
                           "loss_last": float(losses[-1])},
             "tile": {"tile": t.tile, "waves_per_cu": t.waves_per_cu},
             "mean_counts": {"c_scan": float(sb[:, 1].mean()), "c_pass": float(sb[:, 2].mean()),
-                            "c_exact": float(sb[:, 4].mean())},
+                            "c_upper": float(sb[:, 5].mean()), "c_exact": float(sb[:, 4].mean())},
             "cost_spread_log2_scan": {"p10": float(np.percentile(cost, 10)), "p50": float(np.percentile(cost, 50)),
                                       "p90": float(np.percentile(cost, 90)), "max": float(cost.max())}}
 
@@ -364,7 +366,8 @@ def workload_c5(args):
         "bytes_device": info.bytes_device,
         "stop_level_hist": np.bincount(stats[:, 0], minlength=info.K + 1).tolist(),
         "mean_counts": {"c_scan": float(stats[:, 1].mean()), "c_pass": float(stats[:, 2].mean()),
-                        "c_rerank": float(stats[:, 3].mean()), "c_exact": float(stats[:, 4].mean())},
+                        "c_rerank": float(stats[:, 3].mean()), "c_q8": float(stats[:, 6].mean()),
+                        "c_upper": float(stats[:, 5].mean()), "c_exact": float(stats[:, 4].mean())},
         "roofline": {"kernel": "k_search", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": A, "avg_launch_ms": kms},
@@ -522,7 +525,8 @@ def main():
                      "search": avg_search_ms},
         "stop_level_hist": np.bincount(stats[:, 0], minlength=info.K + 1).tolist(),
         "mean_counts": {"c_scan": float(stats[:, 1].mean()), "c_pass": float(stats[:, 2].mean()),
-                        "c_rerank": float(stats[:, 3].mean()), "c_exact": float(stats[:, 4].mean())},
+                        "c_rerank": float(stats[:, 3].mean()), "c_q8": float(stats[:, 6].mean()),
+                        "c_upper": float(stats[:, 5].mean()), "c_exact": float(stats[:, 4].mean())},
         "roofline": {"kernel": "k_search", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
                      "algorithmic_bytes_per_launch": A, "avg_launch_ms": avg_search_ms},

@@ -61,6 +61,11 @@ extern "C" {
 #define PF_EXPORT_POOL_SEL 6    /* L x K int32: pool index of h_{t+1,j} (pooled index) */
 #define PF_EXPORT_CP_TABLE 7    /* 41 x (ell + 1) FP64: Monte Carlo collision probability of
                                    b-bit prefixes at similarity -1 + 0.05 g (FHT-CP index) */
+#define PF_EXPORT_ROWS8 8       /* n x r bytes, r = 128 ceil((8 + dpad) / 128), dpad = 4 ceil(d / 4):
+                                   the 8-bit row summaries the re-rank bounds candidates
+                                   with; row: FP32 scale s = max_i |x_i| / 127, int32
+                                   A = sum_i |c_i|, then int8 c_i = rint(x_i / s), zero
+                                   padded (x the normalised vector; IEEE FP32 division)  */
 
 /* hash families of the table codes (the sketches are always random-hyperplane bits) */
 #define PF_FAMILY_HP 0    /* random hyperplanes (Sec. 2.2), one bit per function          */
@@ -111,9 +116,11 @@ typedef struct {
     int64_t c_pass;   /* entries that passed the sketch filter (with multiplicity)   */
     int64_t c_rerank; /* candidates re-ranked (with multiplicity; + n at a linear scan) */
     int64_t c_exact;  /* of those, the ones whose exact FP32 inner product was needed:
-                         the rest were ruled out by the bound from the upper 16-bit
-                         plane alone (not part of the method's definition; depends on
-                         the order in which the kernel met the candidates)              */
+                         the rest were ruled out by an upper bound of the inner product
+                         (not part of the method's definition; depends on the order in
+                         which the kernel met the candidates)                           */
+    int64_t c_upper;  /* re-ranked candidates whose upper 16-bit plane was read        */
+    int64_t c_q8;     /* re-ranked candidates bounded from their 8-bit row summary     */
 } pf_query_stats;
 
 typedef struct {

@@ -22,7 +22,7 @@ PF_HOST, PF_DEVICE = 0, 1
 PF_RULE_FILTER, PF_RULE_EXACT, PF_RULE_ALG1, PF_RULE_POOL = 0, 1, 2, 3
 PF_HASH_BF16X3, PF_HASH_FP64 = 0, 1
 (PF_EXPORT_POINTS, PF_EXPORT_HYPERPLANES, PF_EXPORT_CODES, PF_EXPORT_IDX,
- PF_EXPORT_SKETCHES, PF_EXPORT_OFFSETS, PF_EXPORT_POOL_SEL, PF_EXPORT_CP_TABLE) = range(8)
+ PF_EXPORT_SKETCHES, PF_EXPORT_OFFSETS, PF_EXPORT_POOL_SEL, PF_EXPORT_CP_TABLE, PF_EXPORT_ROWS8) = range(9)
 PF_FAMILY_HP, PF_FAMILY_FHTCP = 0, 1
 PF_MAX_TABLES, PF_MAX_K, PF_MAX_DIM = 512, 256, 4096
 
@@ -58,7 +58,7 @@ class pf_search_opts(ctypes.Structure):
 class pf_query_stats(ctypes.Structure):
     _fields_ = [("stop_level", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("c_scan", ctypes.c_int64), ("c_pass", ctypes.c_int64), ("c_rerank", ctypes.c_int64),
-                ("c_exact", ctypes.c_int64)]
+                ("c_exact", ctypes.c_int64), ("c_upper", ctypes.c_int64), ("c_q8", ctypes.c_int64)]
 
 
 class pf_info(ctypes.Structure):
@@ -214,7 +214,7 @@ def pf_normalize(x):
 class SearchResult:
     ids: object
     ips: object
-    stats: object  # (m, 5) int64: stop_level, c_scan, c_pass, c_rerank, c_exact
+    stats: object  # (m, 7) int64: stop_level, c_scan, c_pass, c_rerank, c_exact, c_upper, c_q8
 
     @property
     def stop_level(self):
@@ -222,7 +222,7 @@ class SearchResult:
 
 
 def _stats_view(raw):
-    """pf_query_stats array (m x 40 bytes) as (m, 5) int64 columns."""
+    """pf_query_stats array (m x 56 bytes) as (m, 7) int64 columns."""
     if _is_torch(raw):
         s = raw.clone()
         s[:, 0] = s[:, 0] & 0xFFFFFFFF
@@ -284,7 +284,7 @@ class Index:
         m = q.shape[0]
         ids = _empty_like_input(q, (m, k), np.int32, _torch_dtype("int32"))
         ips = _empty_like_input(q, (m, k), np.float32, _torch_dtype("float32")) if want_ips else None
-        st = _empty_like_input(q, (m, 5), np.int64, _torch_dtype("int64")) if want_stats else None
+        st = _empty_like_input(q, (m, 7), np.int64, _torch_dtype("int64")) if want_stats else None
         opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1,
                               0 if tile is None else tile + 1)
         pq, mem, stream = _buf(q)
@@ -316,7 +316,7 @@ class Index:
         ord_a = arr(order, np.int32, "int32")
         ids = _empty_like_input(q, (m, kmax), np.int32, _torch_dtype("int32"))
         ips = _empty_like_input(q, (m, kmax), np.float32, _torch_dtype("float32"))
-        st = _empty_like_input(q, (m, 5), np.int64, _torch_dtype("int64"))
+        st = _empty_like_input(q, (m, 7), np.int64, _torch_dtype("int64"))
         opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1,
                               0 if tile is None else tile + 1)
         flags = (PF_BATCH_LEARNED if learned else 0) | (PF_BATCH_AUTOTUNE if autotune else 0)
@@ -372,6 +372,7 @@ class Index:
         PF_EXPORT_OFFSETS: (np.uint32, lambda s: (s.L, (1 << s.P) + 1)),
         PF_EXPORT_POOL_SEL: (np.int32, lambda s: (s.L, s.K)),
         PF_EXPORT_CP_TABLE: (np.float64, lambda s: (41, s.cp_ell + 1)),
+        PF_EXPORT_ROWS8: (np.uint8, lambda s: (s.n, 128 * ((8 + 4 * ((s.d + 3) // 4) + 127) // 128))),
     }
 
     def export(self, what: int) -> np.ndarray:

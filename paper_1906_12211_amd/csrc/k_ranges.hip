@@ -6,24 +6,13 @@
 // bucket) and lt(c) = [c < query code]:
 //   lo_i = B0 + #{lt, lcp < i},   hi_i = B0 + #{lt} + #{not lt, lcp >= i}.
 // ranges[q][j][i - P - 1] = (lo_i, hi_i).
+#include "pf_device.h"
 #include "pf_internal.h"
 
 namespace pf {
 
 static constexpr int kGroupMax = 4080; // buckets up to this size: one 16-lane group per pair, else
                                        // one binary search per bound and level
-
-template <int CTRL> __device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
-}
-// sum over the 16 lanes of a DPP row, in every lane of the row
-__device__ __forceinline__ uint32_t row_sum16u(uint32_t s) {
-    s += dpp_u<0x128>(s); // row_ror:8
-    s += dpp_u<0x124>(s); // row_ror:4
-    s += dpp_u<0x122>(s); // row_ror:2
-    s += dpp_u<0x121>(s); // row_ror:1
-    return s;
-}
 
 // One 16-lane group (a DPP row) per (q, j) pair: the group reads its bucket 64 entries
 // at a time (16 consecutive codes per load instruction, four loads in flight), each lane

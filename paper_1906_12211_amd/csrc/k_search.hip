@@ -48,6 +48,8 @@ struct SearchK {
     int32_t hs, ls, spare;   // plane row lengths; lower halves of elements < spare sit in
                              // the upper row after its dpad upper halves
     int32_t prefilter;
+    const uint8_t *Xq; // 8-bit row summaries (scale, sum of |codes|, int8 codes), rq bytes per row
+    int32_t rq;
     const uint32_t *tidx, *off;
     const uint64_t *tsk;
     int64_t n;
@@ -103,6 +105,7 @@ struct WLds {
     unsigned long long *top, *ntop, *cand, *tq;
     uint32_t *pending, *upos, *clo, *chi, *qc, *segBeg, *segStart, *segTab;
     uint32_t *qb, *qba; // query as bfloat16 pairs (round to nearest even) and their magnitudes
+    uint32_t *q8;       // query int8 codes laid out like a summary row (8 zero bytes first)
     float *qv;
 };
 
@@ -110,11 +113,13 @@ __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t
 
 // Byte offsets of the wave's LDS arrays in the dynamic shared memory block.
 struct LdsOff {
-    uint32_t top, ntop, cand, tq, pending, upos, clo, chi, qc, segBeg, segStart, segTab, qb, qba, qv, total;
+    uint32_t top, ntop, cand, tq, pending, upos, clo, chi, qc, segBeg, segStart, segTab, qb, qba, q8, qv, total;
 };
 
-// pcap, cw, ucap: the tile's pending, candidate and late-id capacities
-__host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad, int pcap, int cw, int ucap) {
+// pcap, cw, ucap: the tile's pending, candidate and late-id capacities; rq: bytes of an
+// 8-bit summary row
+__host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad, int pcap, int cw, int ucap,
+                                                     int rq) {
     LdsOff o;
     uint32_t off = 0;
     auto take = [&](size_t bytes) {
@@ -136,6 +141,7 @@ __host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad, 
     o.segTab = take(sizeof(uint32_t) * 2 * L);
     o.qb = take(sizeof(uint32_t) * (dpad / 2));
     o.qba = take(sizeof(uint32_t) * (dpad / 2));
+    o.q8 = take(rq);
     o.qv = take(sizeof(float) * dpad);
     o.total = off;
     return o;
@@ -148,7 +154,9 @@ struct QState {
     int k;
     int pend, cand, top;
     unsigned long long thr;
-    long long c_scan, c_pass, c_rerank, c_exact;
+    float qt;    // query int8 scale t (q_i ~ t b_i)
+    int32_t qB;  // sum_i |b_i|
+    long long c_scan, c_pass, c_rerank, c_exact, c_upper, c_q8;
 };
 
 // top <- best k distinct points of top u cand[0..cand) (the accumulator's flush; cand
@@ -408,6 +416,126 @@ __device__ __forceinline__ void bound_rows(const SearchK &p, const WLds &l, cons
     for (int u = 0; u < U; ++u) ub[u] = row_sum16(acc[u]) + row_sum16(mag[u]) * kBoundRel + kBoundAbs;
 }
 
+// The query as int8 codes for the 8-bit row summaries: t = max_i |q_i| / 127, b_i =
+// rint(q_i / t) (|q_i - t b_i| <= t (1/2 + 2^-16), as for the rows), laid out like a
+// summary row (word w holds the codes of elements 4w - 8 .. 4w - 5; the first 8 bytes,
+// facing the row's scale and sum, are zero); st.qt = t, st.qB = sum_i |b_i|.
+__device__ void query_rows8(const SearchK &p, WLds &l, QState &st) {
+    const int lane = threadIdx.x;
+    float mx = 0.0f;
+    for (int c = lane; c < p.dpad; c += WV) mx = fmaxf(mx, fabsf(l.qv[c]));
+    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    const float t = mx / 127.0f;
+    int32_t bsum = 0;
+    for (int w = lane; w < p.rq / 4; w += WV) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int c = 4 * w - 8 + b;
+            int32_t v = 0;
+            if (c >= 0 && c < p.dpad && t > 0.0f) v = (int32_t)fminf(127.0f, fmaxf(-127.0f, rintf(l.qv[c] / t)));
+            bsum += v < 0 ? -v : v;
+            word |= (uint32_t)(uint8_t)(int8_t)v << (8 * b);
+        }
+        l.q8[w] = word;
+    }
+    for (int o = 32; o >= 1; o >>= 1) bsum += __shfl_xor(bsum, o);
+    // wave-uniform: kept in scalar registers
+    st.qt = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(t)));
+    st.qB = __builtin_amdgcn_readfirstlane(bsum);
+}
+
+// Upper bound of the exact inner product of row r of the group's U rows (lane r of the
+// group; the other lanes' result is unused) from the 8-bit summaries.  With
+// x_i = s c_i + e_i, |e_i| <= h s, q_i = t b_i + f_i, |f_i| <= h t, h = 1/2 + 2^-16,
+// A = sum |c_i|, B = sum |b_i|, C = sum c_i b_i (exact, v_dot4_i32_i8):
+//   <x, q> <= s t (C + h (A + B) + dpad h^2).
+// The FP32 evaluation errs by less than 2^-21 (|s t C| <= 1.02, s t h (A + B) < 0.1), and
+// the kernel's exact FP32 inner product exceeds <x, q> by less than 2^-16 (unit vectors,
+// d <= 4096); kAbs8 = 2^-15 covers both.  Lane r of a group reads bytes 8r .. 8r + 7 of
+// each 128-byte chunk of every row (chunk 0's first 8 bytes, the header (s, A), face zero
+// query bytes) and the header of its own row.
+constexpr float kH8 = 0.5f + 1.52587890625e-05f;
+constexpr float kAbs8 = 3.0517578125e-05f;
+template <int U>
+__device__ __forceinline__ float bound8_row(const SearchK &p, const WLds &l, const uint32_t *ids, int cnt, int r,
+                                            float qt, int32_t qB) {
+    const uint8_t *q8 = reinterpret_cast<const uint8_t *>(l.q8);
+    int32_t acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0;
+    uint32_t myid = ids[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u)
+        if (r == u) myid = ids[u];
+    const uint2 hdr = r < cnt ? *reinterpret_cast<const uint2 *>(p.Xq + (int64_t)myid * p.rq) : make_uint2(0u, 0u);
+    for (int off = 8 * r; off < p.rq; off += 128) {
+        const uint2 qq = *reinterpret_cast<const uint2 *>(q8 + off);
+        uint2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            v[u] = u < cnt ? *reinterpret_cast<const uint2 *>(p.Xq + (int64_t)ids[u] * p.rq + off)
+                           : make_uint2(0u, 0u);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            acc[u] = __builtin_amdgcn_sdot4((int)v[u].x, (int)qq.x, acc[u], false);
+            acc[u] = __builtin_amdgcn_sdot4((int)v[u].y, (int)qq.y, acc[u], false);
+        }
+    }
+    int32_t C = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t cu = (int32_t)row_sum16u((uint32_t)acc[u]);
+        if (r == u) C = cu;
+    }
+    const float sc = __uint_as_float(hdr.x);
+    const int32_t A = (int32_t)hdr.y;
+    const float inner = (float)C + (kH8 * (float)(A + qB) + (float)p.dpad * (kH8 * kH8));
+    return (sc * qt) * inner + kAbs8;
+}
+
+// One pruning pass over ids[0..rc): rows whose bound (from the 8-bit summaries, Q8, or
+// from the upper plane) is below the k-th inner product ipk could not enter the top-k;
+// the rest are compacted, in order, to the front of ids.  Returns their count.
+template <int DT, int U, bool Q8>
+__device__ int prune_rows(const SearchK &p, const WLds &l, uint32_t *ids, int rc, float ipk, const QState &st) {
+    constexpr int RROWS = 4 * U;
+    const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
+    const uint64_t lt = lanemask_lt(lane);
+    int w = 0;
+    for (int t0 = 0; t0 < rc; t0 += RROWS) {
+        const int first = t0 + g * U;
+        const int cnt = max(0, min(U, rc - first));
+        uint32_t x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = u < cnt ? ids[first + u] : 0u;
+        bool keep = false;
+        uint32_t myx = x[0];
+        if constexpr (Q8) {
+            const float ub = bound8_row<U>(p, l, x, cnt, r, st.qt, st.qB);
+#pragma unroll
+            for (int u = 1; u < U; ++u)
+                if (r == u) myx = x[u];
+            keep = r < cnt && ub >= ipk;
+        } else {
+            float ub[U];
+            bound_rows<DT, U>(p, l, x, cnt, r, ub);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (r == u) {
+                    keep = u < cnt && ub[u] >= ipk;
+                    myx = x[u];
+                }
+        }
+        const uint64_t mk = __ballot(keep);
+        wsync();
+        if (keep) ids[w + __popcll(mk & lt)] = myx;
+        w += __popcll(mk);
+        wsync();
+    }
+    return w;
+}
+
 // Re-rank rows ids[0..rc); candidates better than the current k-th enter the buffer,
 // which is merged into the top-k whenever it could overflow.  Once the top-k is full,
 // a first pass over the upper plane drops every row whose bound is below the k-th inner
@@ -422,31 +550,15 @@ __device__ void wave_rerank(const SearchK &p, WLds &l, uint32_t *ids, int rc, QS
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
     const uint64_t lt = lanemask_lt(lane);
     if (p.prefilter && st.top == st.k) {
+        // 8-bit summaries first (one 128-byte line per row of up to 120 elements), then
+        // the upper plane for the rows they cannot rule out
         const float ipk = key_ip(st.thr);
-        int w = 0;
-        for (int t0 = 0; t0 < rc; t0 += RROWS) {
-            const int first = t0 + g * U;
-            const int cnt = max(0, min(U, rc - first));
-            uint32_t x[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) x[u] = u < cnt ? ids[first + u] : 0u;
-            float ub[U];
-            bound_rows<DT, U>(p, l, x, cnt, r, ub);
-            bool keep = false;
-            uint32_t myx = x[0];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (r == u) {
-                    keep = u < cnt && ub[u] >= ipk;
-                    myx = x[u];
-                }
-            const uint64_t mk = __ballot(keep);
-            wsync();
-            if (keep) ids[w + __popcll(mk & lt)] = myx;
-            w += __popcll(mk);
-            wsync();
-        }
-        rc = w;
+        st.c_q8 += rc;
+        rc = prune_rows<DT, U, true>(p, l, ids, rc, ipk, st);
+        st.c_upper += rc;
+        rc = prune_rows<DT, U, false>(p, l, ids, rc, ipk, st);
+    } else {
+        st.c_upper += rc;
     }
     st.c_exact += rc;
     for (int t0 = 0; t0 < rc; t0 += RROWS) {
@@ -529,7 +641,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
     // compiler keeps them in the LDS address space (ds_read / ds_write, counted by
     // lgkmcnt alone); a generic pointer would turn each LDS access into a flat access
     // that also waits for every global load in flight
-    const LdsOff lo_ = search_lds_offsets(p.L, p.kmax, p.dpad, TL::PCAP, TL::CW, TL::UCAP);
+    const LdsOff lo_ = search_lds_offsets(p.L, p.kmax, p.dpad, TL::PCAP, TL::CW, TL::UCAP, p.rq);
     WLds l;
     l.top = reinterpret_cast<unsigned long long *>(smem + lo_.top);
     l.ntop = reinterpret_cast<unsigned long long *>(smem + lo_.ntop);
@@ -545,6 +657,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
     l.segTab = reinterpret_cast<uint32_t *>(smem + lo_.segTab);
     l.qb = reinterpret_cast<uint32_t *>(smem + lo_.qb);
     l.qba = reinterpret_cast<uint32_t *>(smem + lo_.qba);
+    l.q8 = reinterpret_cast<uint32_t *>(smem + lo_.q8);
     l.qv = reinterpret_cast<float *>(smem + lo_.qv);
     const int lane = threadIdx.x;
     const uint64_t lt = lanemask_lt(lane);
@@ -559,7 +672,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
         st.k = p.ks ? max(1, min(p.ks[q], p.kmax)) : p.kconst;
         st.pend = st.cand = st.top = 0;
         st.thr = 0;
-        st.c_scan = st.c_pass = st.c_rerank = st.c_exact = 0;
+        st.c_scan = st.c_pass = st.c_rerank = st.c_exact = st.c_upper = st.c_q8 = 0;
         const float *stopw = p.stopw + (int64_t)(p.qtab ? p.qtab[q] : 0) * K * kTauCols;
         for (int c = lane; c < p.dpad; c += WV) l.qv[c] = p.Q[q * p.dpad + c];
         for (int c = lane; c < p.dpad / 2; c += WV) {
@@ -567,6 +680,8 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             l.qb[c] = w;
             l.qba[c] = w & 0x7FFF7FFFu;
         }
+        wsync();
+        query_rows8(p, l, st);
         for (int32_t j = lane; j < L; j += WV) {
             const uint32_t qc = p.qcode[(int64_t)j * p.qstride + q];
             l.qc[j] = qc;
@@ -770,6 +885,8 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             s.c_pass = st.c_pass;
             s.c_rerank = st.c_rerank;
             s.c_exact = st.c_exact;
+            s.c_upper = st.c_upper;
+            s.c_q8 = st.c_q8;
             p.stats[q] = s;
         }
         wsync();
@@ -798,7 +915,7 @@ static const char *kTileNames[kNumTiles] = {"ept8-u8", "ept4-u8", "ept16-u8", "e
                                             "ept8-u4-o4-late"};
 
 template <class TL> static size_t tile_lds(const Index &ix, int32_t kmax) {
-    return search_lds_offsets(ix.L, kmax, ix.dpad, TL::PCAP, TL::CW, TL::UCAP).total;
+    return search_lds_offsets(ix.L, kmax, ix.dpad, TL::PCAP, TL::CW, TL::UCAP, ix.rq).total;
 }
 static size_t search_lds_bytes(const Index &ix, int32_t kmax, int tile) {
     switch (tile) {
@@ -870,6 +987,8 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     p.ls = ix.ls;
     p.spare = ix.hs - ix.dpad;
     p.prefilter = a.prefilter;
+    p.Xq = ix.Xq.as<uint8_t>();
+    p.rq = ix.rq;
     p.tidx = ix.tidx.as<uint32_t>();
     p.off = ix.off.as<uint32_t>();
     p.tsk = ix.tsk.as<uint64_t>();

@@ -19,4 +19,17 @@ __device__ __forceinline__ float float_of(uint32_t o) {
     return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
 }
 
+// integer sum over the 16 lanes of a DPP row, in every lane of the row (every lane of
+// the row must be active)
+template <int CTRL> __device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t row_sum16u(uint32_t s) {
+    s += dpp_u<0x128>(s); // row_ror:8
+    s += dpp_u<0x124>(s); // row_ror:4
+    s += dpp_u<0x122>(s); // row_ror:2
+    s += dpp_u<0x121>(s); // row_ror:1
+    return s;
+}
+
 } // namespace pf

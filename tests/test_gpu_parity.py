@@ -45,8 +45,9 @@ def _assert_search_equal(gr, orr, label=""):
         assert bad.size == 0, f"{label} {name}: {bad.size} mismatches, q={bad[:5]} gpu={gv[bad[:5]]} oracle={ov[bad[:5]]}"
     bad = np.nonzero(np.any(gr.ids != orr.ids, axis=1) & ok)[0]
     assert bad.size == 0, f"{label} ids differ for {bad.size} queries, first {bad[:5]}"
-    # exact inner products: at most one per re-ranked candidate
-    assert np.all((st[:, 4] >= 0) & (st[:, 4] <= st[:, 3])), f"{label} c_exact"
+    # bounds only rule candidates out: c_exact <= c_upper <= c_rerank, c_q8 <= c_rerank
+    assert np.all((st[:, 4] >= 0) & (st[:, 4] <= st[:, 5]) & (st[:, 5] <= st[:, 3])), f"{label} c_exact/c_upper"
+    assert np.all((st[:, 6] >= 0) & (st[:, 6] <= st[:, 3])), f"{label} c_q8"
     assert np.array_equal(gr.ips[ok].view(np.uint32), orr.ips[ok].view(np.uint32)), f"{label} ips"
     assert ok.mean() > 0.99
 
@@ -123,7 +124,8 @@ def test_search_variants(k, recall, kw):
     orr = o.search(Q, k, recall, **okw)
     _assert_search_equal(gr, orr, f"k={k} r={recall} {kw}")
     if kw.get("prefilter", True) is False:
-        assert np.array_equal(gr.stats[:, 4], gr.stats[:, 3])
+        assert np.array_equal(gr.stats[:, 4], gr.stats[:, 3]) and np.array_equal(gr.stats[:, 5], gr.stats[:, 3])
+        assert np.all(gr.stats[:, 6] == 0)
 
 
 @pytest.mark.parametrize("d", [48, 100, 200, 300])
@@ -141,8 +143,44 @@ def test_prefilter_exact_and_effective(d):
     _assert_search_equal(off, orr, f"prefilter off d={d}")
     assert np.array_equal(off.stats[:, 4], off.stats[:, 3])
     frac = on.stats[:, 4].sum() / on.stats[:, 3].sum()
-    print(f"[prefilter d={d}] exact inner products: {frac:.4f} of re-ranked", flush=True)
-    assert frac < 0.5
+    up = on.stats[:, 5].sum() / on.stats[:, 3].sum()
+    q8 = on.stats[:, 6].sum() / on.stats[:, 3].sum()
+    print(f"[prefilter d={d}] of re-ranked: 8-bit bounds {q8:.4f}, upper planes read {up:.4f}, "
+          f"exact inner products {frac:.4f}", flush=True)
+    assert frac < 0.5 and up < 0.5 and q8 > 0.5
+
+
+def test_rows8_summaries_and_bound():
+    """The 8-bit row summaries follow their definition (FP32 scale max|x_i| / 127, int8
+    codes rint(x_i / s), sum of |codes|; IEEE FP32 division), and the bound the re-rank
+    takes from them, s t (C + h (A + B) + dpad h^2) with the query coded the same way,
+    dominates the FP64 inner product on every pair tried, with a slack of a few 1e-2."""
+    for d in (5, 100, 128, 300):
+        X = workloads.gaussian_unit(3000, d, 700 + d)
+        X[:50, : d // 2] = 0.0
+        g = pf.Index(X, 0, seed=7, L=4)
+        rows = g.export(pf.PF_EXPORT_ROWS8)
+        dpad = 4 * ((d + 3) // 4)
+        assert rows.shape == (3000, 128 * ((8 + dpad + 127) // 128))
+        Xn = g.export(pf.PF_EXPORT_POINTS)
+        s = np.abs(Xn).max(1).astype(np.float32) / np.float32(127)
+        c = np.clip(np.rint(Xn / s[:, None]), -127, 127).astype(np.int64)
+        assert np.array_equal(rows[:, :4].copy().view(np.float32)[:, 0], s), f"d={d} scale"
+        assert np.array_equal(rows[:, 4:8].copy().view(np.int32)[:, 0], np.abs(c).sum(1)), f"d={d} sum"
+        assert np.array_equal(rows[:, 8:8 + d].view(np.int8).astype(np.int64), c), f"d={d} codes"
+        assert not rows[:, 8 + d:].any(), f"d={d} padding"
+        Q = oracle.normalize(workloads.gaussian_unit(200, d, 800 + d))
+        t = np.abs(Q).max(1).astype(np.float32) / np.float32(127)
+        b = np.clip(np.rint(Q / t[:, None]), -127, 127).astype(np.int64)
+        h = 0.5 + 2.0 ** -16
+        C = b @ c.T
+        ub = (s[None, :].astype(np.float64) * t[:, None]) * (C + h * (np.abs(c).sum(1)[None, :] + np.abs(b).sum(1)[:, None])
+                                                          + dpad * h * h)
+        ip = Q.astype(np.float64) @ Xn.astype(np.float64).T
+        slack = ub - ip
+        print(f"[rows8 d={d}] bound slack min {slack.min():.2e} mean {slack.mean():.3e} max {slack.max():.3e}",
+              flush=True)
+        assert slack.min() >= 0.0 and slack.mean() < 0.1
 
 
 def test_prefilter_low_bits_and_subnormals():
