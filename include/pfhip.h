@@ -61,11 +61,11 @@ extern "C" {
 #define PF_EXPORT_POOL_SEL 6    /* L x K int32: pool index of h_{t+1,j} (pooled index) */
 #define PF_EXPORT_CP_TABLE 7    /* 41 x (ell + 1) FP64: Monte Carlo collision probability of
                                    b-bit prefixes at similarity -1 + 0.05 g (FHT-CP index) */
-#define PF_EXPORT_ROWS8 8       /* n x r bytes, r = 128 ceil((8 + dpad) / 128), dpad = 4 ceil(d / 4):
-                                   the 8-bit row summaries the re-rank bounds candidates
-                                   with; row: FP32 scale s = max_i |x_i| / 127, int32
-                                   A = sum_i |c_i|, then int8 c_i = rint(x_i / s), zero
-                                   padded (x the normalised vector; IEEE FP32 division)  */
+#define PF_EXPORT_ROWS8 8       /* n x (8 + dpad) bytes, dpad = 4 ceil(d / 4): the 8-bit
+                                   row summaries the re-rank bounds candidates with; row:
+                                   FP32 scale s = max_i |x_i| / 127, int32 A = sum_i |c_i|,
+                                   then int8 c_i = rint(x_i / s), zero padded (x the
+                                   normalised vector; IEEE FP32 division)                 */
 
 /* hash families of the table codes (the sketches are always random-hyperplane bits) */
 #define PF_FAMILY_HP 0    /* random hyperplanes (Sec. 2.2), one bit per function          */

@@ -372,7 +372,7 @@ class Index:
         PF_EXPORT_OFFSETS: (np.uint32, lambda s: (s.L, (1 << s.P) + 1)),
         PF_EXPORT_POOL_SEL: (np.int32, lambda s: (s.L, s.K)),
         PF_EXPORT_CP_TABLE: (np.float64, lambda s: (41, s.cp_ell + 1)),
-        PF_EXPORT_ROWS8: (np.uint8, lambda s: (s.n, 128 * ((8 + 4 * ((s.d + 3) // 4) + 127) // 128))),
+        PF_EXPORT_ROWS8: (np.uint8, lambda s: (s.n, 8 + 4 * ((s.d + 3) // 4))),
     }
 
     def export(self, what: int) -> np.ndarray:

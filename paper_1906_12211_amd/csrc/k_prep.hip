@@ -133,13 +133,15 @@ void launch_join_planes(const uint16_t *hi, const uint16_t *lo, int64_t n, int32
     PF_HIP(hipGetLastError());
 }
 
-// 8-bit row summaries for the re-rank's first bound: row r (rq bytes, a multiple of 128)
-// holds the FP32 scale s = max_i |x_i| / 127, the int32 A = sum_i |c_i| and the int8
-// c_i = rint(x_i / s), i < dpad, zero padded.  With the FP32 divisions correctly rounded,
-// |x_i / s| <= 127 (1 + 2^-24), so |c_i| <= 127 and |x_i - s c_i| <= s (1/2 + 2^-16).
-// One 64-lane wave per row.
+// 8-bit row summaries for the re-rank's first bound: the FP32 scale s = max_i |x_i| / 127,
+// the int32 A = sum_i |c_i| (the 8-byte header) and the int8 c_i = rint(x_i / s), i < dpad.
+// Row r of out (rq bytes, a multiple of 128) holds the codes from byte co on, zero padded;
+// the header is the row's first 8 bytes when they fit in front of the codes without
+// another 128-byte line (co = 8), else row r of hdr (co = 0).  With the FP32 divisions
+// correctly rounded, |x_i / s| <= 127 (1 + 2^-24), so |c_i| <= 127 and
+// |x_i - s c_i| <= s (1/2 + 2^-16).  One 64-lane wave per row.
 __global__ __launch_bounds__(256) void k_rows8(const float *__restrict__ X, int64_t n, int32_t dpad, int32_t rq,
-                                               uint8_t *__restrict__ out) {
+                                               int32_t co, uint8_t *__restrict__ out, uint8_t *__restrict__ hdr) {
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= n) return;
@@ -150,27 +152,34 @@ __global__ __launch_bounds__(256) void k_rows8(const float *__restrict__ X, int6
     const float sc = mx / 127.0f;
     uint8_t *row = out + r * (int64_t)rq;
     int32_t asum = 0;
-    for (int c = lane; c < rq - 8; c += 64) {
+    for (int c = lane; c < rq - co; c += 64) {
         int32_t q = 0;
         if (c < dpad && sc > 0.0f) {
             const float v = rintf(x[c] / sc);
             q = (int32_t)fminf(127.0f, fmaxf(-127.0f, v));
         }
-        row[8 + c] = (uint8_t)(int8_t)q;
+        row[co + c] = (uint8_t)(int8_t)q;
         asum += q < 0 ? -q : q;
     }
     for (int o = 32; o >= 1; o >>= 1) asum += __shfl_xor(asum, o);
     if (lane == 0) {
-        *reinterpret_cast<float *>(row) = sc;
-        *reinterpret_cast<int32_t *>(row + 4) = asum;
+        uint8_t *h = co ? row : hdr + r * 8;
+        *reinterpret_cast<float *>(h) = sc;
+        *reinterpret_cast<int32_t *>(h + 4) = asum;
     }
 }
 
-int32_t rows8_stride(int32_t dpad) { return (8 + dpad + 127) / 128 * 128; }
+void rows8_layout(int32_t dpad, int32_t *rq, int32_t *co) {
+    const int32_t lines = (dpad + 127) / 128 * 128;
+    *co = 8 + dpad <= lines ? 8 : 0;
+    *rq = (*co + dpad + 127) / 128 * 128;
+}
 
-void launch_rows8(const float *X, int64_t n, int32_t dpad, uint8_t *out, hipStream_t s) {
+void launch_rows8(const float *X, int64_t n, int32_t dpad, uint8_t *out, uint8_t *hdr, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_rows8, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, dpad, rows8_stride(dpad), out);
+    int32_t rq, co;
+    rows8_layout(dpad, &rq, &co);
+    hipLaunchKernelGGL(k_rows8, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, dpad, rq, co, out, hdr);
     PF_HIP(hipGetLastError());
 }
 

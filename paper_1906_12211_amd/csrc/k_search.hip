@@ -48,8 +48,9 @@ struct SearchK {
     int32_t hs, ls, spare;   // plane row lengths; lower halves of elements < spare sit in
                              // the upper row after its dpad upper halves
     int32_t prefilter;
-    const uint8_t *Xq; // 8-bit row summaries (scale, sum of |codes|, int8 codes), rq bytes per row
-    int32_t rq;
+    const uint8_t *Xq;  // 8-bit row summaries: rq bytes per row, int8 codes from byte qco,
+    const uint8_t *Xqh; // headers (FP32 scale, int32 sum of |codes|) at the row's start
+    int32_t rq, qco;    // (qco = 8) or, when qco = 0, in Xqh (8 bytes per row)
     const uint32_t *tidx, *off;
     const uint64_t *tsk;
     int64_t n;
@@ -418,8 +419,8 @@ __device__ __forceinline__ void bound_rows(const SearchK &p, const WLds &l, cons
 
 // The query as int8 codes for the 8-bit row summaries: t = max_i |q_i| / 127, b_i =
 // rint(q_i / t) (|q_i - t b_i| <= t (1/2 + 2^-16), as for the rows), laid out like a
-// summary row (word w holds the codes of elements 4w - 8 .. 4w - 5; the first 8 bytes,
-// facing the row's scale and sum, are zero); st.qt = t, st.qB = sum_i |b_i|.
+// summary row (byte qco + i holds b_i; bytes before qco, facing an inline header, are
+// zero); st.qt = t, st.qB = sum_i |b_i|.
 __device__ void query_rows8(const SearchK &p, WLds &l, QState &st) {
     const int lane = threadIdx.x;
     float mx = 0.0f;
@@ -431,7 +432,7 @@ __device__ void query_rows8(const SearchK &p, WLds &l, QState &st) {
         uint32_t word = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int c = 4 * w - 8 + b;
+            const int c = 4 * w - p.qco + b;
             int32_t v = 0;
             if (c >= 0 && c < p.dpad && t > 0.0f) v = (int32_t)fminf(127.0f, fmaxf(-127.0f, rintf(l.qv[c] / t)));
             bsum += v < 0 ? -v : v;
@@ -453,8 +454,8 @@ __device__ void query_rows8(const SearchK &p, WLds &l, QState &st) {
 // The FP32 evaluation errs by less than 2^-21 (|s t C| <= 1.02, s t h (A + B) < 0.1), and
 // the kernel's exact FP32 inner product exceeds <x, q> by less than 2^-16 (unit vectors,
 // d <= 4096); kAbs8 = 2^-15 covers both.  Lane r of a group reads bytes 8r .. 8r + 7 of
-// each 128-byte chunk of every row (chunk 0's first 8 bytes, the header (s, A), face zero
-// query bytes) and the header of its own row.
+// each 128-byte chunk of every row (an inline header faces zero query bytes) and the
+// header (s, A) of its own row.
 constexpr float kH8 = 0.5f + 1.52587890625e-05f;
 constexpr float kAbs8 = 3.0517578125e-05f;
 template <int U>
@@ -468,7 +469,8 @@ __device__ __forceinline__ float bound8_row(const SearchK &p, const WLds &l, con
 #pragma unroll
     for (int u = 1; u < U; ++u)
         if (r == u) myid = ids[u];
-    const uint2 hdr = r < cnt ? *reinterpret_cast<const uint2 *>(p.Xq + (int64_t)myid * p.rq) : make_uint2(0u, 0u);
+    const uint8_t *hp = p.Xqh ? p.Xqh + (int64_t)myid * 8 : p.Xq + (int64_t)myid * p.rq;
+    const uint2 hdr = r < cnt ? *reinterpret_cast<const uint2 *>(hp) : make_uint2(0u, 0u);
     for (int off = 8 * r; off < p.rq; off += 128) {
         const uint2 qq = *reinterpret_cast<const uint2 *>(q8 + off);
         uint2 v[U];
@@ -988,7 +990,9 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     p.spare = ix.hs - ix.dpad;
     p.prefilter = a.prefilter;
     p.Xq = ix.Xq.as<uint8_t>();
+    p.Xqh = ix.qco ? nullptr : ix.Xqh.as<uint8_t>();
     p.rq = ix.rq;
+    p.qco = ix.qco;
     p.tidx = ix.tidx.as<uint32_t>();
     p.off = ix.off.as<uint32_t>();
     p.tsk = ix.tsk.as<uint64_t>();

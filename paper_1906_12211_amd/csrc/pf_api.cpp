@@ -399,9 +399,10 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         ix->Xh.alloc((size_t)n * ix->hs * sizeof(uint16_t));
         ix->Xl.alloc((size_t)n * std::max(ix->ls, 1) * sizeof(uint16_t));
         launch_split_planes(X.as<float>(), n, ix->dpad, ix->Xh.as<uint16_t>(), ix->Xl.as<uint16_t>(), s);
-        ix->rq = rows8_stride(ix->dpad);
+        rows8_layout(ix->dpad, &ix->rq, &ix->qco);
         ix->Xq.alloc((size_t)n * ix->rq);
-        launch_rows8(X.as<float>(), n, ix->dpad, ix->Xq.as<uint8_t>(), s);
+        if (ix->qco == 0) ix->Xqh.alloc((size_t)n * 8);
+        launch_rows8(X.as<float>(), n, ix->dpad, ix->Xq.as<uint8_t>(), ix->Xqh.as<uint8_t>(), s);
         // a6: sorted tables
         ix->tcode.alloc((size_t)L * n * sizeof(uint32_t));
         ix->tidx.alloc((size_t)L * n * sizeof(uint32_t));
@@ -866,9 +867,15 @@ PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_by
             break;
         }
         case PF_EXPORT_ROWS8: {
-            const int64_t b = n * (int64_t)ix->rq;
-            need(b);
-            PF_HIP(hipMemcpyAsync(dst, ix->Xq.p, (size_t)b, kind, s));
+            const size_t w = 8 + (size_t)ix->dpad;
+            need(n * (int64_t)w);
+            char *o = static_cast<char *>(dst);
+            if (ix->qco) {
+                PF_HIP(hipMemcpy2DAsync(o, w, ix->Xq.p, (size_t)ix->rq, w, (size_t)n, kind, s));
+            } else {
+                PF_HIP(hipMemcpy2DAsync(o, w, ix->Xqh.p, 8, 8, (size_t)n, kind, s));
+                PF_HIP(hipMemcpy2DAsync(o + 8, w, ix->Xq.p, (size_t)ix->rq, (size_t)ix->dpad, (size_t)n, kind, s));
+            }
             break;
         }
         case PF_EXPORT_POOL_SEL: {
@@ -898,7 +905,7 @@ PF_API int pf_index_info(const pf_index *ix, pf_info *info) {
         r.pool = ix->pool;
         r.family = ix->family;
         r.bytes_budget_rule = ix->bytes_rule;
-        r.bytes_device = ix->Xh.bytes + ix->Xl.bytes + ix->Xq.bytes + ix->hp.bytes + ix->hcolrow.bytes + ix->hbf.bytes + ix->hbeta.bytes +
+        r.bytes_device = ix->Xh.bytes + ix->Xl.bytes + ix->Xq.bytes + ix->Xqh.bytes + ix->hp.bytes + ix->hcolrow.bytes + ix->hbf.bytes + ix->hbeta.bytes +
                          ix->psel.bytes + ix->cpsign.bytes + ix->cptab.bytes + ix->tcode.bytes + ix->tidx.bytes + ix->tsk.bytes + ix->off.bytes;
         r.build_ms = ix->build_ms;
         *info = r;

@@ -128,7 +128,7 @@ def test_search_variants(k, recall, kw):
         assert np.all(gr.stats[:, 6] == 0)
 
 
-@pytest.mark.parametrize("d", [48, 100, 200, 300])
+@pytest.mark.parametrize("d", [48, 100, 128, 200, 300])
 def test_prefilter_exact_and_effective(d):
     """The upper-plane bound only decides which inner products are computed: ids, inner
     products and counters equal the oracle's with it on and off, for every row-length
@@ -155,13 +155,13 @@ def test_rows8_summaries_and_bound():
     codes rint(x_i / s), sum of |codes|; IEEE FP32 division), and the bound the re-rank
     takes from them, s t (C + h (A + B) + dpad h^2) with the query coded the same way,
     dominates the FP64 inner product on every pair tried, with a slack of a few 1e-2."""
-    for d in (5, 100, 128, 300):
+    for d in (5, 100, 124, 128, 256, 300):
         X = workloads.gaussian_unit(3000, d, 700 + d)
         X[:50, : d // 2] = 0.0
         g = pf.Index(X, 0, seed=7, L=4)
         rows = g.export(pf.PF_EXPORT_ROWS8)
         dpad = 4 * ((d + 3) // 4)
-        assert rows.shape == (3000, 128 * ((8 + dpad + 127) // 128))
+        assert rows.shape == (3000, 8 + dpad)
         Xn = g.export(pf.PF_EXPORT_POINTS)
         s = np.abs(Xn).max(1).astype(np.float32) / np.float32(127)
         c = np.clip(np.rint(Xn / s[:, None]), -127, 127).astype(np.int64)
