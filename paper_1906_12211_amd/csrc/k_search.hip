@@ -953,7 +953,7 @@ static const void *search_kernel(int dt, int tile) {
 int32_t search_tile_count() { return kNumTiles; }
 // the shape used when none is given or tuned: the fastest on the 1 M-point, d = 100
 // mixture at k = 10 both with static query slots and with the work queue
-int32_t search_default_tile() { return 5; }
+int32_t search_default_tile() { return 4; }
 const char *search_tile_name(int32_t t) { return (t >= 0 && t < kNumTiles) ? kTileNames[t] : "?"; }
 
 // resident query waves per CU for a tile shape (occupancy from registers and LDS)
