@@ -56,14 +56,23 @@ def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> floa
     return float(per_q.sum())
 
 
+HOST_MARK = b"// ====================================================================== host side"
+
+
+def search_device_sha() -> str:
+    """Fingerprint of the search kernel's device source: k_search.hip up to its host-side
+    section, so that host-only edits (tile table, launch) keep the counters valid."""
+    src = open(SEARCH_SRC, "rb").read()
+    return hashlib.sha256(src.split(HOST_MARK)[0]).hexdigest()
+
+
 def traffic_entry():
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
     taken on the current search kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE))
-    sha = hashlib.sha256(open(SEARCH_SRC, "rb").read()).hexdigest()
-    if t.get("k_search_sha256") != sha:
+    if t.get("k_search_device_sha256") != search_device_sha():
         return None
     return t.get("bytes_per_launch")
 

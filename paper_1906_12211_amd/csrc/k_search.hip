@@ -899,6 +899,9 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
     }
 }
 
+// ====================================================================== host side
+// (tile table, occupancy, launch; everything above this line is device code)
+
 // chunks of 64 floats per row, as a kernel specialisation (0 = any length)
 static int row_chunks(int32_t dpad) {
     const int t = (dpad + 63) / 64;
