@@ -970,11 +970,6 @@ int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile) {
     return per_cu;
 }
 
-int64_t search_slots(const Index &ix, int64_t m) {
-    return std::max<int64_t>(1, std::min<int64_t>(
-                                    m, (int64_t)ix.num_cus * search_waves_per_cu(ix, PF_MAX_K, search_default_tile())));
-}
-
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s) {
     if (a.m <= 0) return;
     const int dt = row_chunks(ix.dpad);

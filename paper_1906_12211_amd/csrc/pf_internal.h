@@ -221,7 +221,6 @@ void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, 
 void cp_codes(const Index &ix, const float *X, int64_t n, uint32_t *codes, hipStream_t s);
 int32_t rule_table_cols();
 void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s);
-int64_t search_slots(const Index &ix, int64_t m);
 int32_t search_tile_count();
 int32_t search_default_tile();
 const char *search_tile_name(int32_t t);
