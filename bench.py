@@ -66,6 +66,15 @@ def search_device_sha() -> str:
     return hashlib.sha256(src.split(HOST_MARK)[0]).hexdigest()
 
 
+def plain_gather_bytes(stats: np.ndarray, d: int, k: int, L: int) -> float:
+    """The same launch counted as if every re-ranked candidate's FP32 vector were gathered
+    (4d B), with the prefix-table reads (4L), sketches (8 B per scanned entry), positions
+    of passing entries (4 B), the query and the result: the bytes a re-rank without the
+    8-bit and 16-bit bounds would move (reported beside the roofline, not in it)."""
+    per_q = 4.0 * L + 8.0 * stats[:, 1] + 4.0 * stats[:, 2] + 4.0 * d * stats[:, 3] + 4.0 * d + 8.0 * k
+    return float(per_q.sum())
+
+
 def traffic_entry():
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
     taken on the current search kernel source."""
@@ -379,7 +388,8 @@ def workload_c5(args):
                         "c_upper": float(stats[:, 5].mean()), "c_exact": float(stats[:, 4].mean())},
         "roofline": {"kernel": "k_search", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": A, "avg_launch_ms": kms},
+                     "algorithmic_bytes_per_launch": A, "avg_launch_ms": kms,
+                     "fp32_gather_bytes_per_launch": plain_gather_bytes(stats, d, k, info.L)},
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
@@ -538,7 +548,8 @@ def main():
                         "c_upper": float(stats[:, 5].mean()), "c_exact": float(stats[:, 4].mean())},
         "roofline": {"kernel": "k_search", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
-                     "algorithmic_bytes_per_launch": A, "avg_launch_ms": avg_search_ms},
+                     "algorithmic_bytes_per_launch": A, "avg_launch_ms": avg_search_ms,
+                     "fp32_gather_bytes_per_launch": plain_gather_bytes(stats, d, k, info.L)},
         "cpu_baseline": None,
     }
     log(f"recall {rec:.4f} on {ns} queries")
