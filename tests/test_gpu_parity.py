@@ -183,6 +183,23 @@ def test_rows8_summaries_and_bound():
         assert slack.min() >= 0.0 and slack.mean() < 0.1
 
 
+def test_prefilter_spiky_rows():
+    """Rows dominated by one coordinate (the 8-bit codes of the others round to zero) and
+    queries along the same axes: candidates' inner products differ by less than the 8-bit
+    bound's slack, so every bound stage is exercised on near-ties."""
+    rng = np.random.default_rng(901)
+    n, d = 8000, 100
+    X = (np.float32(1e-3) * rng.standard_normal((n, d))).astype(np.float32)
+    axes = rng.integers(0, 8, size=n)
+    X[np.arange(n), axes] += np.float32(1.0)
+    X[: n // 4] += np.float32(0.02) * workloads.gaussian_unit(n // 4, d, 902)
+    Q = (np.float32(1e-3) * rng.standard_normal((120, d))).astype(np.float32)
+    Q[np.arange(120), rng.integers(0, 8, size=120)] += np.float32(1.0)
+    g, o = _build_both(X, L=20, seed=903)
+    for k, rec in [(1, 0.9), (10, 0.9), (40, 0.99)]:
+        _assert_search_equal(g.search(Q, k, rec), o.search(Q, k, rec), f"spiky k={k}")
+
+
 def test_prefilter_low_bits_and_subnormals():
     """Points that differ only in the lower 16 bits of their coordinates (identical upper
     planes, so the bound cannot separate them), exact zeros and subnormal coordinates."""
