@@ -23,14 +23,15 @@ namespace pf {
 // order array), which balances queries of very different cost.
 //
 // Tile shape: EPT sketch loads in flight per lane in a filter chunk, U rows in flight
-// per 16-lane group in the re-rank, WPE the query waves per SIMD the register allocation
-// must allow (1 = no constraint), LATE: point ids read for passing entries only, one
-// chunk late (else for every scanned entry, with its sketch); DT = 64-float chunks per
-// row (0 = any length).
+// per 16-lane group in the re-rank (UQ when bounding from the 8-bit summaries), WPE the
+// query waves per SIMD the register allocation must allow (1 = no constraint), LATE:
+// point ids read for passing entries only, one chunk late (else for every scanned
+// entry, with its sketch); DT = 64-float chunks per row (0 = any length).
 static constexpr int WV = 64; // lanes per query wave
-template <int EPT_, int U_, int WPE_ = 1, bool LATE_ = false> struct Tile {
+template <int EPT_, int U_, int WPE_ = 1, bool LATE_ = false, int UQ_ = U_> struct Tile {
     static constexpr int EPT = EPT_;
     static constexpr int U = U_;
+    static constexpr int UQ = UQ_; // rows in flight per 16-lane group when bounding from 8-bit summaries
     static constexpr int WPE = WPE_;
     static constexpr bool LATE = LATE_;
     static constexpr int WCH = WV * EPT;       // entries per filter chunk
@@ -556,7 +557,7 @@ __device__ void wave_rerank(const SearchK &p, WLds &l, uint32_t *ids, int rc, QS
         // the upper plane for the rows they cannot rule out
         const float ipk = key_ip(st.thr);
         st.c_q8 += rc;
-        rc = prune_rows<DT, U, true>(p, l, ids, rc, ipk, st);
+        rc = prune_rows<DT, TL::UQ, true>(p, l, ids, rc, ipk, st);
         st.c_upper += rc;
         rc = prune_rows<DT, U, false>(p, l, ids, rc, ipk, st);
     } else {
@@ -915,9 +916,10 @@ using T168 = Tile<16, 8>;
 using T84 = Tile<8, 4>;
 using T84o4 = Tile<8, 4, 4>; // registers capped for 4 waves per SIMD (16 per CU)
 using T84o4l = Tile<8, 4, 4, true>;
-static constexpr int kNumTiles = 6;
+using T84o4q8 = Tile<8, 4, 4, false, 8>;   // 8 summary rows in flight per group
+static constexpr int kNumTiles = 7;
 static const char *kTileNames[kNumTiles] = {"ept8-u8", "ept4-u8", "ept16-u8", "ept8-u4", "ept8-u4-o4",
-                                            "ept8-u4-o4-late"};
+                                            "ept8-u4-o4-late", "ept8-u4q8-o4"};
 
 template <class TL> static size_t tile_lds(const Index &ix, int32_t kmax) {
     return search_lds_offsets(ix.L, kmax, ix.dpad, TL::PCAP, TL::CW, TL::UCAP, ix.rq).total;
@@ -929,6 +931,7 @@ static size_t search_lds_bytes(const Index &ix, int32_t kmax, int tile) {
     case 3: return tile_lds<T84>(ix, kmax);
     case 4: return tile_lds<T84o4>(ix, kmax);
     case 5: return tile_lds<T84o4l>(ix, kmax);
+    case 6: return tile_lds<T84o4q8>(ix, kmax);
     default: return tile_lds<T88>(ix, kmax);
     }
 }
@@ -940,6 +943,7 @@ template <int DT> static const void *search_kernel_dt(int tile) {
     case 3: return (const void *)k_search<DT, T84>;
     case 4: return (const void *)k_search<DT, T84o4>;
     case 5: return (const void *)k_search<DT, T84o4l>;
+    case 6: return (const void *)k_search<DT, T84o4q8>;
     default: return (const void *)k_search<DT, T88>;
     }
 }
@@ -956,7 +960,7 @@ static const void *search_kernel(int dt, int tile) {
 int32_t search_tile_count() { return kNumTiles; }
 // the shape used when none is given or tuned: the fastest on the 1 M-point, d = 100
 // mixture at k = 10 both with static query slots and with the work queue
-int32_t search_default_tile() { return 4; }
+int32_t search_default_tile() { return 6; }
 const char *search_tile_name(int32_t t) { return (t >= 0 && t < kNumTiles) ? kTileNames[t] : "?"; }
 
 // resident query waves per CU for a tile shape (occupancy from registers and LDS)
