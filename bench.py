@@ -75,13 +75,13 @@ def plain_gather_bytes(stats: np.ndarray, d: int, k: int, L: int) -> float:
     return float(per_q.sum())
 
 
-def traffic_entry():
+def traffic_entry(tile_name: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current search kernel source."""
+    taken on the current search kernel source with the tile shape this run launched."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE))
-    if t.get("k_search_device_sha256") != search_device_sha():
+    if t.get("k_search_device_sha256") != search_device_sha() or t.get("tile_name") != tile_name:
         return None
     return t.get("bytes_per_launch")
 
@@ -513,7 +513,7 @@ def main():
     A = algorithmic_bytes(stats, d, k, info.L, info.K)
     avg_search_ms = float(np.mean(search_ms))
     achieved = A / (avg_search_ms * 1e-3) / 1e9
-    tr = traffic_entry()
+    tr = traffic_entry(pf.pf_tile_name(head["tile"]))
     line = {
         "metric": METRIC,
         "value": qps,
@@ -534,7 +534,7 @@ def main():
         "paths_search_kernel_ms": {name: float(np.mean(v["search_ms"])) for name, v in res.items()},
         "learned_vs_plain": (res["learned_batched"]["ms"] and res["plain"]["ms"] / res["learned_batched"]["ms"])
         if "plain" in res and "learned_batched" in res else None,
-        "batched_tile": {"tile": head["tile"], "waves_per_cu": head["waves"]},
+        "batched_tile": {"tile": head["tile"], "name": pf.pf_tile_name(head["tile"]), "waves_per_cu": head["waves"]},
         "scheduler": {"train_queries": int(len(Qtr)), "train_s": train_s, "loss_first": float(losses[0]),
                       "loss_last": float(losses[-1])},
         "recall_measured": rec,

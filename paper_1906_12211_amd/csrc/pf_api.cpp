@@ -512,8 +512,8 @@ static TuneChoice autotune(Index &ix, SearchArgs a, int32_t kmax, hipStream_t s)
     const int64_t sample = std::min<int64_t>(a.m, 8192);
     a.qstride = a.m; // query codes were computed for the whole batch
     a.m = sample;    // time the first queries of the batch (in queue order)
-    TuneChoice best;
-    best.us_per_query = 1e300;
+    TuneChoice best, best_default;
+    best.us_per_query = best_default.us_per_query = 1e300;
     hipEvent_t e0, e1;
     PF_HIP(hipEventCreate(&e0));
     PF_HIP(hipEventCreate(&e1));
@@ -541,11 +541,19 @@ static TuneChoice autotune(Index &ix, SearchArgs a, int32_t kmax, hipStream_t s)
                 best.waves = w;
                 best.us_per_query = us;
             }
+            if (t == search_default_tile() && us < best_default.us_per_query) {
+                best_default.tile = t;
+                best_default.waves = w;
+                best_default.us_per_query = us;
+            }
             if (w == 1) break;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // another shape replaces the default only if it is clearly faster on the sample (timings
+    // of near-equal shapes differ by about a percent from run to run)
+    if (best.us_per_query > 0.98 * best_default.us_per_query) best = best_default;
     ix.tuned[key] = {best.tile, best.waves, best.us_per_query};
     tune_cache_write(key, best);
     return best;
