@@ -25,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -59,11 +60,17 @@ def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> floa
 HOST_MARK = b"// ====================================================================== host side"
 
 
-def search_device_sha() -> str:
-    """Fingerprint of the search kernel's device source: k_search.hip up to its host-side
-    section, so that host-only edits (tile table, launch) keep the counters valid."""
-    src = open(SEARCH_SRC, "rb").read()
-    return hashlib.sha256(src.split(HOST_MARK)[0]).hexdigest()
+def search_device_sha(src: bytes = None) -> str:
+    """Fingerprint of the search kernel's device code: k_search.hip up to its host-side
+    section, without comments and blank space, so that host-only and comment edits keep
+    the counters valid."""
+    if src is None:
+        src = open(SEARCH_SRC, "rb").read()
+    code = src.split(HOST_MARK)[0].decode()
+    code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+    code = re.sub(r"//[^\n]*", " ", code)
+    code = " ".join(code.split())
+    return hashlib.sha256(code.encode()).hexdigest()
 
 
 def plain_gather_bytes(stats: np.ndarray, d: int, k: int, L: int) -> float:

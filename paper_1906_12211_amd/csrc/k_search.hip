@@ -4,8 +4,9 @@
 // segments of B entries (Sec. 4.2, App. C) while the next entry shares the query's
 // i-bit prefix; candidates pass the sketch filter when popcount(sketch xor query
 // sketch) <= tau (Sec. 4.2 "Filtering candidate points", tau from Sec. 5.1, fixed for
-// the round); passing points not yet re-ranked get their exact FP32 inner product and
-// enter the top-k; after all tables the stopping bound of Lemma 1 is tested in FP64.
+// the round); passing points get their exact FP32 inner product (unless an upper bound
+// of it from an 8-bit or the 16-bit copy of the row shows they cannot enter the top-k)
+// and enter the top-k; after all tables the stopping bound of Lemma 1 is tested in FP64.
 // The last round, i = 0, is a linear scan.  The ranges of the levels i > P (k_ranges.hip)
 // and the decision tables of a round (k_rules.hip) are computed before the walk.
 #include "pf_device.h"
@@ -540,10 +541,10 @@ __device__ int prune_rows(const SearchK &p, const WLds &l, uint32_t *ids, int rc
 }
 
 // Re-rank rows ids[0..rc); candidates better than the current k-th enter the buffer,
-// which is merged into the top-k whenever it could overflow.  Once the top-k is full,
-// a first pass over the upper plane drops every row whose bound is below the k-th inner
-// product (it could not enter the top-k) and compacts the rest, in order, to the front
-// of ids; only those are read from both planes.
+// which is merged into the top-k whenever it could overflow.  Once the top-k is full, a
+// pass over the 8-bit summaries and then one over the upper plane drop every row whose
+// bound is below the k-th inner product (it could not enter the top-k), each compacting
+// the rest, in order, to the front of ids; only those are read from both planes.
 template <int DT, class TL>
 __device__ void wave_rerank(const SearchK &p, WLds &l, uint32_t *ids, int rc, QState &st) {
     // rows of 256 floats (DT = 4) or of any length (DT = 0) take at most 4 rows per group in
