@@ -232,6 +232,48 @@ def exact_topk_gpu(Xd, Qd, k: int, extra: int = 8):
     return out
 
 
+def paper_synthetic(dev):
+    """The paper's synthetic set (Sec. 5): 1,000,000 points in 3 x 100 dimensions whose last
+    row is every query's nearest neighbour, 1,000 queries, 2 GiB, k = 1: per recall target
+    the fraction of queries that return it, the stop levels and the search time (plain
+    single launch and batched work queue)."""
+    import torch
+
+    X, Q = workloads.paper_synthetic(1_000_000, 100, 1000, 78)
+    Xd = torch.from_numpy(X).to(dev)
+    ix = pf.Index(Xd, 2 << 30, seed=workloads.INDEX_SEED)
+    del Xd
+    info = ix.info()
+    m = len(Q)
+    Qd = torch.from_numpy(Q).to(dev)
+    out = {"workload": "paper-synthetic-1M-3x100", "n": len(X), "d": X.shape[1], "queries": m, "k": 1,
+           "L": info.L, "build_ms": info.build_ms, "targets": {}}
+    for rec in (0.5, 0.9, 0.99):
+        ks = torch.ones((m,), dtype=torch.int32, device=dev)
+        rc = torch.full((m,), rec, dtype=torch.float64, device=dev)
+        ix.search(Qd, 1, rec)
+        plain = []
+        for _ in range(3):
+            r = ix.search(Qd, 1, rec, timing=True)
+            plain.append(ix.last_timing().search_ms)
+        ix.search_batch(Qd, ks, rc, 1, autotune=True)
+        batched = []
+        for _ in range(3):
+            rb = ix.search_batch(Qd, ks, rc, 1, timing=True)
+            batched.append(ix.last_timing().search_ms)
+        hit = float(np.mean(r.ids.cpu().numpy()[:, 0] == len(X) - 1))
+        hit_b = float(np.mean(rb.ids.cpu().numpy()[:, 0] == len(X) - 1))
+        st = r.stats.cpu().numpy()
+        out["targets"][str(rec)] = {"x_n_found": hit, "x_n_found_batched": hit_b,
+                                    "mean_stop_level": float(st[:, 0].mean()),
+                                    "mean_c_scan": float(st[:, 1].mean()),
+                                    "search_kernel_ms_plain": float(np.mean(plain)),
+                                    "search_kernel_ms_batched": float(np.mean(batched))}
+        log(f"paper synthetic, recall {rec}: x_n found {hit:.4f}, kernel {np.mean(plain):.2f} ms plain, "
+            f"{np.mean(batched):.2f} ms batched")
+    return out
+
+
 def cp_index(X, Q, k, recall, budget, dev, truth_ids):
     """The same workload on an index whose table codes are FHT cross-polytope values
     (Sec. 2.2, 4.3; the sketches stay hyperplane bits): build time (the FP64 rotations),
@@ -415,7 +457,8 @@ def main():
                     help="query paths to time (comma separated); the last one is the headline")
     ap.add_argument("--train-frac", type=float, default=2.0,
                     help="scheduler training queries as a multiple of the benchmark query count")
-    ap.add_argument("--no-pool", action="store_true", help="skip the pooled-index measurement")
+    ap.add_argument("--no-pool", action="store_true",
+                    help="skip the pooled, cross-polytope and paper-synthetic measurements")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed 100,000-query batch (per-query k and recall, queue orders)")
     ap.add_argument("--workload", default="mixture-1M-d100", choices=["mixture-1M-d100", "mixture-10M-d128"],
@@ -565,6 +608,7 @@ def main():
         del ix
         line["pooled_index"] = pooled_index(X, Q, k, recall, budget, dev, truth)
         line["cross_polytope_index"] = cp_index(X, Q, k, recall, budget, dev, truth)
+        line["paper_synthetic"] = paper_synthetic(dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(X, Q, budget, k, recall, args.cpu_seconds)
     print(json.dumps(line), flush=True)
