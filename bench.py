@@ -465,6 +465,9 @@ def main():
                     help="mixture-10M-d128: the learned scheduler's 10 M-point configuration (separate line)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
+    ap.add_argument("--compare-tiles", default="",
+                    help="only run the batched search of the benchmark workload with each listed tile "
+                         "shape (comma-separated indexes), twice in turn, and exit (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the search path runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -486,6 +489,19 @@ def main():
 
     if args.workload == "mixture-10M-d128":
         workload_c5(args)
+        return
+
+    if args.compare_tiles:
+        tiles = [int(t) for t in args.compare_tiles.split(",")]
+        c = workloads.config(2, scale=args.scale)
+        ix = pf.Index(torch.from_numpy(c["points"]).cuda(), c["budget"], seed=workloads.INDEX_SEED)
+        Qd = torch.from_numpy(c["queries"]).cuda()
+        ks = torch.full((len(Qd),), c["k"], dtype=torch.int32, device="cuda")
+        rc = torch.full((len(Qd),), c["recall"], dtype=torch.float64, device="cuda")
+        for t in tiles + tiles:
+            ix.search_batch(Qd, ks, rc, c["k"], timing=True, tile=t)
+            print(json.dumps({"tile": t, "name": pf.pf_tile_name(t), "search_ms": ix.last_timing().search_ms}),
+                  flush=True)
         return
 
     log("generating workload")
