@@ -751,7 +751,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             // once per level, keeping the current one's end and base offset in registers
             int sg = -1;
             uint32_t segEnd = 0, ebase = 0;
-            int32_t tjc = 0;
+            uint64_t tqc = 0; // the query's sketch for the current segment's table
             // LATE tiles: the previous chunk's passing entries (at most UCAP) wait in upos
             // as table positions, and their point ids are read together with this chunk's
             // sketches, so that positions are read for passing entries only and no load
@@ -760,7 +760,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             int nu = 0;
             for (uint32_t base = 0; base < total; base += WCH) {
                 uint32_t ev[EPT];
-                int32_t tj[EPT];
+                uint64_t tqv[EPT];
                 uint64_t skv[EPT];
                 // (entries past the end load entry 0 of table 0 and are masked out, so that
                 // every load is unconditional)
@@ -776,11 +776,12 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                             ++sg;
                             segEnd = l.segStart[sg + 1];
                         } while (f >= segEnd);
-                        tjc = (int32_t)l.segTab[sg];
-                        ebase = (uint32_t)tjc * (uint32_t)n + l.segBeg[sg] - l.segStart[sg];
+                        const uint32_t tjc = l.segTab[sg];
+                        tqc = l.tq[tjc];
+                        ebase = tjc * (uint32_t)n + l.segBeg[sg] - l.segStart[sg];
                     }
                     valid |= (in ? 1u : 0u) << u;
-                    tj[u] = tjc;
+                    tqv[u] = tqc;
                     const uint32_t e = in ? ebase + f : 0u;
                     skv[u] = p.tsk[e];
                     ev[u] = TL::LATE ? e : p.tidx[e];
@@ -794,7 +795,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                 int np = 0;
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
-                    const bool pass = ((valid >> u) & 1u) && __popcll(skv[u] ^ l.tq[tj[u]]) <= tau;
+                    const bool pass = ((valid >> u) & 1u) && __popcll(skv[u] ^ tqv[u]) <= tau;
                     pm |= (pass ? 1u : 0u) << u;
                     mk[u] = __ballot(pass);
                     np += __popcll(mk[u]);
