@@ -548,7 +548,7 @@ def main():
         for _ in range(args.warmup):
             r = fn()
         torch.cuda.synchronize()
-        search_ms, hash_ms, ranges_ms = [], [], []
+        search_ms, hash_ms, ranges_ms, order_ms = [], [], [], []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             r = fn()
@@ -556,16 +556,17 @@ def main():
             search_ms.append(tm.search_ms)
             hash_ms.append(tm.hash_ms)
             ranges_ms.append(tm.ranges_ms)
+            order_ms.append(tm.order_ms)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         res[name] = dict(r=r, ms=wall / args.steps * 1e3, search_ms=search_ms, hash_ms=hash_ms,
-                         ranges_ms=ranges_ms, tile=tm.tile, waves=tm.waves_per_cu)
+                         ranges_ms=ranges_ms, order_ms=order_ms, tile=tm.tile, waves=tm.waves_per_cu)
         log(f"{name}: {res[name]['ms']:.3f} ms/step, search kernel {np.mean(search_ms):.3f} ms")
     head = res[wanted[-1]]
     r = head["r"]
     ms_per_step = head["ms"]
     qps = m / (ms_per_step / 1e3)
-    search_ms, hash_ms, ranges_ms = head["search_ms"], head["hash_ms"], head["ranges_ms"]
+    search_ms, hash_ms, ranges_ms, order_ms = head["search_ms"], head["hash_ms"], head["ranges_ms"], head["order_ms"]
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
     stats = r.stats.cpu().numpy()
     ids = r.ids.cpu().numpy()
@@ -607,7 +608,7 @@ def main():
         "recall_sample": ns,
         "build_ms": info.build_ms,
         "phase_ms": {"normalize+hash": float(np.mean(hash_ms)), "ranges": float(np.mean(ranges_ms)),
-                     "search": avg_search_ms},
+                     "queue_order": float(np.mean(order_ms)), "search": avg_search_ms},
         "stop_level_hist": np.bincount(stats[:, 0], minlength=info.K + 1).tolist(),
         "mean_counts": {"c_scan": float(stats[:, 1].mean()), "c_pass": float(stats[:, 2].mean()),
                         "c_rerank": float(stats[:, 3].mean()), "c_q8": float(stats[:, 6].mean()),

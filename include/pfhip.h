@@ -136,6 +136,10 @@ typedef struct {
     double normalize_ms, hash_ms, ranges_ms, search_ms, total_ms;
     int32_t tile;         /* tile shape the search kernel ran with (batched calls) */
     int32_t waves_per_cu; /* cap on resident query waves per CU (0 = occupancy limit) */
+    double order_ms;      /* batched calls: the work queue's order (the learned scheduler's
+                             features, network and sort, or the upload of a caller's order)
+                             and the autotuner when asked; ranges_ms covers the decision
+                             tables and the prefix ranges                                 */
 } pf_timing;
 
 /* Number of kernel tile shapes the library is built with, and the name of shape t

@@ -71,7 +71,8 @@ class pf_info(ctypes.Structure):
 class pf_timing(ctypes.Structure):
     _fields_ = [("normalize_ms", ctypes.c_double), ("hash_ms", ctypes.c_double),
                 ("ranges_ms", ctypes.c_double), ("search_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double), ("tile", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
+                ("total_ms", ctypes.c_double), ("tile", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("order_ms", ctypes.c_double)]
 
 
 _lib = None

@@ -11,11 +11,12 @@
 
 namespace pf {
 
+static constexpr int kLoads = 8;       // code loads in flight per lane
 static constexpr int kGroupMax = 4080; // buckets up to this size: one 16-lane group per pair, else
                                        // one binary search per bound and level
 
-// One 16-lane group (a DPP row) per (q, j) pair: the group reads its bucket 64 entries
-// at a time (16 consecutive codes per load instruction, four loads in flight), each lane
+// One 16-lane group (a DPP row) per (q, j) pair: the group reads its bucket 16 kLoads
+// entries at a time (16 consecutive codes per load instruction, kLoads in flight), each lane
 // counts its entries per (lcp - P, lt) in 8-bit fields of NR registers per flag (bin b
 // in byte b & 3 of register b >> 2; at most ceil(kGroupMax / 16) = 255 entries per lane),
 // the fields are widened to 16 bits and summed over the row, and lane r writes level
@@ -46,12 +47,12 @@ __global__ __launch_bounds__(256) void k_ranges_group(const uint32_t *__restrict
     uint32_t clt[NR], cge[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) clt[r] = cge[r] = 0;
-    for (uint32_t e0 = B0 + g; e0 < B1; e0 += 64) {
-        uint32_t c[4];
+    for (uint32_t e0 = B0 + g; e0 < B1; e0 += 16 * kLoads) {
+        uint32_t c[kLoads];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = tc[e0 + 16 * u < B1 ? e0 + 16 * u : B0];
+        for (int u = 0; u < kLoads; ++u) c[u] = tc[e0 + 16 * u < B1 ? e0 + 16 * u : B0];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kLoads; ++u) {
             if (e0 + 16 * u < B1) {
                 const uint32_t x = (c[u] ^ qc) << sh;
                 const int bin = (x ? __clz(x) : K) - P;

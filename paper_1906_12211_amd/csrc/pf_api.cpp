@@ -709,6 +709,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         rg = ix->ranges.as<uint32_t>();
     }
     launch_ranges(*ix, a, rg, s);
+    if (o.timing) PF_HIP(hipEventRecord(ev[4], s));
     DevBuf dqueue, dorder;
     if (bc.queue) {
         dqueue.alloc(64);
@@ -756,14 +757,16 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     // temporaries above are released on return: the kernels must be done
     PF_HIP(hipStreamSynchronize(s));
     if (o.timing) {
-        float t01, t12, t23, t03;
+        float t01, t14, t42, t23, t03;
         PF_HIP(hipEventElapsedTime(&t01, ev[0], ev[1]));
-        PF_HIP(hipEventElapsedTime(&t12, ev[1], ev[2]));
+        PF_HIP(hipEventElapsedTime(&t14, ev[1], ev[4]));
+        PF_HIP(hipEventElapsedTime(&t42, ev[4], ev[2]));
         PF_HIP(hipEventElapsedTime(&t23, ev[2], ev[3]));
         PF_HIP(hipEventElapsedTime(&t03, ev[0], ev[3]));
         ix->timing.normalize_ms = 0.0;
         ix->timing.hash_ms = t01;
-        ix->timing.ranges_ms = t12;
+        ix->timing.ranges_ms = t14;
+        ix->timing.order_ms = t42;
         ix->timing.search_ms = t23;
         ix->timing.total_ms = t03;
         ix->timing.tile = a.tile;
