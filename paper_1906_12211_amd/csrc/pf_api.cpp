@@ -541,7 +541,7 @@ static TuneChoice autotune(Index &ix, SearchArgs a, int32_t kmax, hipStream_t s)
                 best.waves = w;
                 best.us_per_query = us;
             }
-            if (t == search_default_tile() && us < best_default.us_per_query) {
+            if (t == search_default_tile() && w == wmax) { // the default: shape and occupancy limit
                 best_default.tile = t;
                 best_default.waves = w;
                 best_default.us_per_query = us;
@@ -551,9 +551,9 @@ static TuneChoice autotune(Index &ix, SearchArgs a, int32_t kmax, hipStream_t s)
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // another shape replaces the default only if it is clearly faster on the sample (one
-    // launch's time varies by a few percent from run to run, so near-equal shapes would
-    // otherwise alternate)
+    // another shape or occupancy cap replaces the default (the default shape at its
+    // occupancy limit) only if it is clearly faster on the sample: one launch's time varies
+    // by a few percent from run to run, so near-equal choices would otherwise alternate
     if (best.us_per_query > 0.95 * best_default.us_per_query) best = best_default;
     ix.tuned[key] = {best.tile, best.waves, best.us_per_query};
     tune_cache_write(key, best);
