@@ -475,11 +475,13 @@ static bool tune_cache_read(const std::string &key, TuneChoice &out) {
     char line[512];
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
-        char k[256];
+        char k[256], name[64];
         TuneChoice t;
-        if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"tile\": %d, \"waves\": %d, \"us_per_query\": %lf}", k,
-                        &t.tile, &t.waves, &t.us_per_query) == 4 &&
-            key == k) {
+        // an entry counts only if its shape index still names the same shape in this build
+        if (std::sscanf(line,
+                        "{\"key\": \"%255[^\"]\", \"tile\": %d, \"waves\": %d, \"us_per_query\": %lf, \"name\": \"%63[^\"]\"",
+                        k, &t.tile, &t.waves, &t.us_per_query, name) == 5 &&
+            key == k && t.tile >= 0 && t.tile < search_tile_count() && std::strcmp(name, search_tile_name(t.tile)) == 0) {
             out = t;
             found = true;
         }

@@ -387,6 +387,39 @@ def test_every_tile_shape(d):
         g.search(Q, 10, 0.9, tile=len(names))
 
 
+def test_tune_cache_file(tmp_path, monkeypatch):
+    """The autotuner's choice is written to the JSON-lines file named by PF_TUNE_CACHE and
+    read back by a fresh index of the same shape; an entry whose shape name does not match
+    this build's shape table is ignored (the default shape is used)."""
+    import json
+
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("PF_TUNE_CACHE", str(cache))
+    X = workloads.gaussian_unit(4000, 32, 951)
+    Q = workloads.gaussian_unit(300, 32, 952)
+    ks = np.full(len(Q), 10, np.int32)
+    rec = np.full(len(Q), 0.9)
+    g = pf.Index(X, 0, seed=9, L=20)
+    g.search_batch(Q, ks, rec, 10, autotune=True, timing=True)
+    tuned = g.last_timing()
+    entry = json.loads(cache.read_text().splitlines()[-1])
+    assert entry["tile"] == tuned.tile and entry["waves"] == tuned.waves_per_cu
+    assert entry["name"] == pf.pf_tile_name(tuned.tile)
+    g2 = pf.Index(X, 0, seed=9, L=20)
+    g2.search_batch(Q, ks, rec, 10, timing=True)
+    assert (g2.last_timing().tile, g2.last_timing().waves_per_cu) == (tuned.tile, tuned.waves_per_cu)
+    # a stale entry: the index now names another shape
+    other = (tuned.tile + 1) % pf.pf_tile_count()
+    entry.update(tile=other, waves=1)
+    cache.write_text(json.dumps(entry) + "\n")
+    g3 = pf.Index(X, 0, seed=9, L=20)
+    r3 = g3.search_batch(Q, ks, rec, 10, timing=True)
+    assert g3.last_timing().waves_per_cu != 1  # the stale entry was not used
+    o = oracle.OracleIndex(X, 0, seed=9, L=20)
+    oids, oips, ost, obd = _oracle_per_query(o, Q, ks, rec, 10)
+    _assert_batch_equal(r3, oids, oips, ost, obd, "after a stale cache entry")
+
+
 def test_batch_device_tensors():
     torch = pytest.importorskip("torch")
     X = workloads.gaussian_unit(3000, 100, 91)
