@@ -35,22 +35,6 @@ __global__ __launch_bounds__(256) void k_features(const uint32_t *__restrict__ q
     feat[t] = v;
 }
 
-// out[r][o] = act(sum_i in[row(r)][i] W[i][o] + b[o]); row(r) = rows ? rows[r] : r
-__global__ __launch_bounds__(256) void k_dense(const float *__restrict__ in, const int32_t *__restrict__ rows,
-                                               int32_t nin, const float *__restrict__ W,
-                                               const float *__restrict__ b, int32_t nout, int64_t B, int32_t relu,
-                                               float *__restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= B * nout) return;
-    const int64_t r = t / nout;
-    const int o = (int)(t - r * nout);
-    const float *x = in + (rows ? (int64_t)rows[r] : r) * nin;
-    float s = 0.0f;
-    for (int i = 0; i < nin; ++i) s = s + x[i] * W[(int64_t)i * nout + o];
-    s = s + b[o];
-    out[t] = (relu && s < 0.0f) ? 0.0f : s;
-}
-
 // dy = d(loss)/dy for loss = mean over the B x 2 outputs of (y - target)^2; loss summed
 // into *acc (FP64) in one fixed order by a single wave
 __global__ __launch_bounds__(64) void k_mse(const float *__restrict__ y, const float *__restrict__ tgt,
@@ -121,6 +105,70 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, const float
 
 static unsigned grid_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
+// The whole forward pass for kFwdRows rows per workgroup: the rows, h1 and h2 stay in LDS
+// and every output out[r][o] = act(sum_i in[r][i] W[i][o] + b[o]) is summed in one fixed
+// order (i ascending, FP32, then the bias).  Thread t owns column t % 128 of rows t / 128,
+// t / 128 + 2, ...
+constexpr int kFwdRows = 32;
+__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ x, const int32_t *__restrict__ rows,
+                                                     const float *__restrict__ params, int64_t B,
+                                                     float *__restrict__ h1, float *__restrict__ h2,
+                                                     float *__restrict__ y) {
+    __shared__ float sx[kFwdRows * kSchedIn];
+    __shared__ float sh1[kFwdRows * kSchedHidden];
+    __shared__ float sh2[kFwdRows * kSchedHidden];
+    const float *W1 = params + kOffW1, *b1 = params + kOffB1, *W2 = params + kOffW2, *b2 = params + kOffB2,
+                *W3 = params + kOffW3, *b3 = params + kOffB3;
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kFwdRows;
+    const int nr = (int)min((int64_t)kFwdRows, B - r0);
+    for (int t = tid; t < nr * kSchedIn; t += 256) {
+        const int r = t / kSchedIn, i = t - r * kSchedIn;
+        sx[t] = x[(rows ? (int64_t)rows[r0 + r] : r0 + r) * kSchedIn + i];
+    }
+    __syncthreads();
+    constexpr int kPer = kFwdRows * kSchedHidden / 256; // rows per thread
+    const int o = tid % kSchedHidden, rb = tid / kSchedHidden;
+    float acc[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) acc[j] = 0.0f;
+    for (int i = 0; i < kSchedIn; ++i) {
+        const float w = W1[i * kSchedHidden + o];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) acc[j] = acc[j] + sx[(rb + 2 * j) * kSchedIn + i] * w;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int r = rb + 2 * j;
+        float v = acc[j] + b1[o];
+        v = v < 0.0f ? 0.0f : v;
+        sh1[r * kSchedHidden + o] = v;
+        if (r < nr) h1[(r0 + r) * kSchedHidden + o] = v;
+        acc[j] = 0.0f;
+    }
+    __syncthreads();
+    for (int i = 0; i < kSchedHidden; ++i) {
+        const float w = W2[i * kSchedHidden + o];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) acc[j] = acc[j] + sh1[(rb + 2 * j) * kSchedHidden + i] * w;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int r = rb + 2 * j;
+        float v = acc[j] + b2[o];
+        v = v < 0.0f ? 0.0f : v;
+        sh2[r * kSchedHidden + o] = v;
+        if (r < nr) h2[(r0 + r) * kSchedHidden + o] = v;
+    }
+    __syncthreads();
+    if (tid < nr * kSchedOut) {
+        const int r = tid / kSchedOut, oo = tid - r * kSchedOut;
+        float v = 0.0f;
+        for (int i = 0; i < kSchedHidden; ++i) v = v + sh2[r * kSchedHidden + i] * W3[i * kSchedOut + oo];
+        y[(r0 + r) * kSchedOut + oo] = v + b3[oo];
+    }
+}
+
 void launch_features(const Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_t m,
                      const float *qparam, float *feat, hipStream_t s) {
     if (m <= 0) return;
@@ -131,14 +179,9 @@ void launch_features(const Index &ix, const uint32_t *qcode, const uint64_t *qsk
 
 void mlp_forward(const float *params, const float *x, const int32_t *rows, int64_t B, float *h1, float *h2,
                  float *y, hipStream_t s) {
-    const float *W1 = params + kOffW1, *b1 = params + kOffB1, *W2 = params + kOffW2, *b2 = params + kOffB2,
-                *W3 = params + kOffW3, *b3 = params + kOffB3;
-    hipLaunchKernelGGL(k_dense, dim3(grid_for(B * kSchedHidden)), dim3(256), 0, s, x, rows, kSchedIn, W1, b1,
-                       kSchedHidden, B, 1, h1);
-    hipLaunchKernelGGL(k_dense, dim3(grid_for(B * kSchedHidden)), dim3(256), 0, s, (const float *)h1,
-                       (const int32_t *)nullptr, kSchedHidden, W2, b2, kSchedHidden, B, 1, h2);
-    hipLaunchKernelGGL(k_dense, dim3(grid_for(B * kSchedOut)), dim3(256), 0, s, (const float *)h2,
-                       (const int32_t *)nullptr, kSchedHidden, W3, b3, kSchedOut, B, 0, y);
+    if (B <= 0) return;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((B + kFwdRows - 1) / kFwdRows)), dim3(256), 0, s, x, rows,
+                       params, B, h1, h2, y);
     PF_HIP(hipGetLastError());
 }
 
