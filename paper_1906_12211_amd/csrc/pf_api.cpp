@@ -658,29 +658,30 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         ix->rule_key_lndeltas = lnd;
     }
 
-    // outputs and per-query parameters on the device
-    DevBuf dids, dips, dstats, dks, dqtab;
+    // outputs and per-query parameters on the device (the index's grow-only call buffers,
+    // so that a call allocates nothing once they are large enough)
+    DevBuf &dids = ix->c_ids, &dips = ix->c_ips, &dstats = ix->c_stats, &dks = ix->c_ks, &dqtab = ix->c_qtab;
     int32_t *oid = out_ids;
     float *oip = out_ips;
     pf_query_stats *ost = stats;
     if (mem == PF_HOST) {
-        dids.alloc((size_t)m * kmax * sizeof(int32_t));
+        dids.ensure((size_t)m * kmax * sizeof(int32_t));
         oid = dids.as<int32_t>();
         if (out_ips) {
-            dips.alloc((size_t)m * kmax * sizeof(float));
+            dips.ensure((size_t)m * kmax * sizeof(float));
             oip = dips.as<float>();
         }
         if (stats) {
-            dstats.alloc((size_t)m * sizeof(pf_query_stats));
+            dstats.ensure((size_t)m * sizeof(pf_query_stats));
             ost = dstats.as<pf_query_stats>();
         }
     }
     if (ks) {
-        dks.alloc((size_t)m * sizeof(int32_t));
+        dks.ensure((size_t)m * sizeof(int32_t));
         PF_HIP(hipMemcpyAsync(dks.p, ks_host.data(), (size_t)m * sizeof(int32_t), h2d, s));
     }
     if (!qtab_host.empty()) {
-        dqtab.alloc(qtab_host.size() * sizeof(int32_t));
+        dqtab.ensure(qtab_host.size() * sizeof(int32_t));
         PF_HIP(hipMemcpyAsync(dqtab.p, qtab_host.data(), qtab_host.size() * sizeof(int32_t), h2d, s));
     }
     SearchArgs a;
@@ -713,9 +714,9 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     }
     launch_ranges(*ix, a, rg, s);
     if (o.timing) PF_HIP(hipEventRecord(ev[4], s));
-    DevBuf dqueue, dorder;
+    DevBuf &dqueue = ix->c_queue, &dorder = ix->c_order;
     if (bc.queue) {
-        dqueue.alloc(64);
+        dqueue.ensure(64);
         a.queue = dqueue.as<unsigned int>();
         std::vector<int32_t> ord;
         if (bc.order) {
@@ -725,7 +726,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         } else if (bc.learned) {
             // computed and sorted on the device; a permutation by construction
             PF_CHECK(ix->sched, PF_EINVAL, "search_batch: PF_BATCH_LEARNED needs an attached scheduler");
-            dorder.alloc((size_t)m * sizeof(int32_t));
+            dorder.ensure((size_t)m * sizeof(int32_t));
             learned_order(*ix, qcode, qsk, m, ks ? ks_host.data() : nullptr, kconst,
                           recalls ? rec_host.data() : nullptr, recall_const, dorder.as<int32_t>(), s);
             a.order = dorder.as<int32_t>();
@@ -737,7 +738,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
                          "search_batch: order must be a permutation of 0..m-1");
                 seen[ord[i]] = 1;
             }
-            dorder.alloc((size_t)m * sizeof(int32_t));
+            dorder.ensure((size_t)m * sizeof(int32_t));
             PF_HIP(hipMemcpyAsync(dorder.p, ord.data(), (size_t)m * sizeof(int32_t), h2d, s));
             a.order = dorder.as<int32_t>();
         }

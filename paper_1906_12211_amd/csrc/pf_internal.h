@@ -115,6 +115,9 @@ struct Index {
     // search scratch (grown on demand)
     DevBuf qX, qcode, qsk, ranges, qstats, flags, tmp;
     DevBuf rlist; // count, then the (query, table) pairs whose prefix bucket is large
+    // per-call buffers of the search (outputs for host callers, per-query k and decision
+    // rows, work-queue counter and order), grown on demand and kept
+    DevBuf c_ids, c_ips, c_stats, c_ks, c_qtab, c_queue, c_order;
     // learned queue order scratch: features, per-query parameters (and their host copy,
     // kept until the next call so that its asynchronous upload never reads freed memory),
     // sort keys, sort scratch
