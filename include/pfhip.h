@@ -16,6 +16,9 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Streams must
  *    have the default priority.
  *  - An index is not thread-safe: calls on the same index must not overlap.
+ *  - An index keeps the device buffers its searches need, grown on demand, until
+ *    pf_free_index: a search allocates device memory only when it is larger (more
+ *    queries, larger k, more distinct recalls) than every earlier one on the index.
  *  - Layouts are row-major; "n x d" means n rows of d contiguous FP32 values.
  */
 #ifndef PFHIP_H

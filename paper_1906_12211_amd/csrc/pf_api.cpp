@@ -644,7 +644,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         ix->rule_key_lndeltas != lnd) {
         const size_t tab_floats = 65 + (size_t)lnd.size() * ix->K * cols;
         const size_t dl_off = (tab_floats * sizeof(float) + 15) & ~(size_t)15;
-        ix->rule_tab.alloc(dl_off + lnd.size() * sizeof(double));
+        ix->rule_tab.ensure(dl_off + lnd.size() * sizeof(double));
         double *dl = reinterpret_cast<double *>(ix->rule_tab.as<char>() + dl_off);
         PF_HIP(hipMemcpyAsync(dl, lnd.data(), lnd.size() * sizeof(double), h2d, s));
         float *tab = ix->rule_tab.as<float>();
