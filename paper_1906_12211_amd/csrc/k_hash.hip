@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_pool_codes(const uint32_t *__restrict__
 }
 
 static void hash_gemm(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint32_t *skw, uint32_t kmask,
-                      const int32_t *colrow, DevBuf &scratch, hipStream_t s);
+                      const int32_t *colrow, char *scratch, uint32_t fcap, hipStream_t s);
 
 // Cross-polytope codes with three Hadamard rotations (Sec. 2.2, Sec. 4.3): one wave per
 // point (four per workgroup), the point zero padded to d' in the wave's LDS as FP64.  For
@@ -462,13 +462,14 @@ void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint
                DevBuf &scratch, hipStream_t s) {
     if (n <= 0) return;
     const HashPlan &hp = ix.plan;
-    DevBuf pool_bits;
+    // scratch: the pool bits (with a pool), then the GEMM's list of flagged bits; it is the
+    // caller's and outlives the queued kernels
+    const size_t pool_bytes = hp.pool ? ((size_t)n * hp.cw * sizeof(uint32_t) + 255) / 256 * 256 : 0;
+    const uint64_t want = (uint64_t)n * (uint64_t)hp.ncols / 64u + 65536u;
+    const uint32_t fcap = (uint32_t)std::min<uint64_t>(want, 1ull << 30);
+    scratch.ensure(pool_bytes + 256 + (size_t)fcap * 8);
     uint32_t *table_codes = codes;
-    if (hp.pool) {
-        // the GEMM writes the pool bits; the codes are gathered from them at the end
-        pool_bits.alloc((size_t)n * hp.cw * sizeof(uint32_t));
-        codes = pool_bits.as<uint32_t>();
-    }
+    if (hp.pool) codes = scratch.as<uint32_t>(); // the GEMM writes the pool bits; codes are gathered at the end
     launch_fill_u32(codes, n * (int64_t)hp.cw, 0u, s);
     launch_fill_u32(reinterpret_cast<uint32_t *>(sketches), 2 * n * (int64_t)hp.M, 0u, s);
     const uint32_t kmask = (hp.pool || hp.K >= 32) ? 0xFFFFFFFFu : ((1u << hp.K) - 1u);
@@ -480,28 +481,24 @@ void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint
                            ix.dpad, hp.d, ix.hp.as<float>(), colrow, hp.words, hp.cw, kmask, codes, skw);
         PF_HIP(hipGetLastError());
     } else {
-        hash_gemm(ix, X, n, codes, skw, kmask, colrow, scratch, s);
+        hash_gemm(ix, X, n, codes, skw, kmask, colrow, static_cast<char *>(scratch.p) + pool_bytes, fcap, s);
     }
     if (ix.family == PF_FAMILY_FHTCP) cp_codes(ix, X, n, table_codes, s);
     if (hp.pool) {
         hipLaunchKernelGGL(k_pool_codes, dim3((unsigned)((n + 255) / 256), (unsigned)hp.L), dim3(256), 0, s,
                            (const uint32_t *)codes, n, ix.psel.as<int32_t>(), hp.L, hp.K, table_codes);
         PF_HIP(hipGetLastError());
-        // pool_bits must outlive the kernels that read it
-        PF_HIP(hipStreamSynchronize(s));
     }
 }
 
 // split-BF16 GEMM of the rows against the plan's columns, then the FP64 fix of the
 // flagged bits
 static void hash_gemm(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint32_t *skw, uint32_t kmask,
-                      const int32_t *colrow, DevBuf &scratch, hipStream_t s) {
+                      const int32_t *colrow, char *scratch, uint32_t fcap, hipStream_t s) {
     const HashPlan &hp = ix.plan;
-    const uint64_t want = (uint64_t)n * (uint64_t)hp.ncols / 64u + 65536u;
-    const uint32_t fcap = (uint32_t)std::min<uint64_t>(want, 1ull << 30);
-    scratch.ensure(256 + (size_t)fcap * 8);
-    unsigned int *fcount = reinterpret_cast<unsigned int *>(scratch.p);
-    uint32_t *flist = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch.p) + 256);
+    // scratch: the flagged-bit count, then room for fcap flagged (row, column) pairs
+    unsigned int *fcount = reinterpret_cast<unsigned int *>(scratch);
+    uint32_t *flist = reinterpret_cast<uint32_t *>(scratch + 256);
     launch_fill_u32(reinterpret_cast<uint32_t *>(fcount), 1, 0u, s);
 
     const uint16_t *Hhi = ix.hbf.as<uint16_t>();

@@ -434,10 +434,7 @@ void prepare_rows_for(Index &ixr, const float *x, int64_t m, int32_t mem, hipStr
     normalize_into(x, m, ix->d, mem, ix->qX.as<float>(), ix->dpad, ix->tmp, ix->flags, s);
     ix->qcode.ensure((size_t)m * ix->L * sizeof(uint32_t));
     ix->qsk.ensure((size_t)m * ix->M * sizeof(uint64_t));
-    DevBuf scratch;
-    hash_rows(*ix, ix->qX.as<float>(), m, ix->qcode.as<uint32_t>(), ix->qsk.as<uint64_t>(), scratch, s);
-    // scratch must outlive the queued kernels
-    PF_HIP(hipStreamSynchronize(s));
+    hash_rows(*ix, ix->qX.as<float>(), m, ix->qcode.as<uint32_t>(), ix->qsk.as<uint64_t>(), ix->hscratch, s);
     *qX = ix->qX.as<float>();
     *qcode = ix->qcode.as<uint32_t>();
     *qsk = ix->qsk.as<uint64_t>();

@@ -49,8 +49,12 @@ struct DevBuf {
     void ensure(size_t b) {
         if (bytes < b) alloc(b);
     }
+    // kernels queued on any stream may still use the buffer: wait for them before freeing
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -118,6 +122,7 @@ struct Index {
     // per-call buffers of the search (outputs for host callers, per-query k and decision
     // rows, work-queue counter and order), grown on demand and kept
     DevBuf c_ids, c_ips, c_stats, c_ks, c_qtab, c_queue, c_order;
+    DevBuf hscratch; // hashing scratch of query rows (pool bits, cross-polytope temporaries)
     // learned queue order scratch: features, per-query parameters (and their host copy,
     // kept until the next call so that its asynchronous upload never reads freed memory),
     // sort keys, sort scratch
