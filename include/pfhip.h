@@ -198,7 +198,9 @@ int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t memory_bu
  * length 0 the query is a linear scan.  `queries` m x d; out_ids m x k (int32, best first: inner product
  * descending, position ascending); out_ips m x k FP32 (nullable); stats m (nullable).
  * Errors: PF_EINVAL (k < 1, k > n, k > PF_MAX_K, recall outside (0, 1], bad row, d
- * mismatch), PF_ENOMEM, PF_EDEVICE.  With PF_HOST the call synchronises. */
+ * mismatch), PF_ENOMEM, PF_EDEVICE.  The call synchronises `stream` before returning, with
+ * PF_DEVICE too: the rows are checked for zero and non-finite values first, and the
+ * next call on the index reuses its device buffers. */
 int pf_search(pf_index *ix, const float *queries, int64_t m, int32_t k, double recall,
               int32_t *out_ids, float *out_ips, pf_query_stats *stats, int32_t mem,
               void *stream);
@@ -224,7 +226,7 @@ int pf_search_batch(pf_index *ix, const float *queries, int64_t m, const int32_t
 /* Hash m rows with the index's functions (Sec. 2.2: bit = 1 iff <a, x> >= 0) after
  * normalising them: codes L x m (u32, table-major, h_{1,j} the most significant of the
  * K bits), sketches M x m (u64, bit b from sketch hyperplane b).  Either output may be
- * NULL.  Errors: PF_EINVAL, PF_ENOMEM, PF_EDEVICE. */
+ * NULL.  Errors: PF_EINVAL, PF_ENOMEM, PF_EDEVICE.  Synchronises. */
 int pf_hash(pf_index *ix, const float *x, int64_t m, uint32_t *codes, uint64_t *sketches,
             int32_t mem, void *stream);
 

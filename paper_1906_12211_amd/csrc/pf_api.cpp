@@ -755,7 +755,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         if (stats)
             PF_HIP(hipMemcpyAsync(stats, ost, (size_t)m * sizeof(pf_query_stats), hipMemcpyDeviceToHost, s));
     }
-    // temporaries above are released on return: the kernels must be done
+    // results are complete on return, and the next call may reuse the index's buffers
     PF_HIP(hipStreamSynchronize(s));
     if (o.timing) {
         float t01, t14, t42, t23, t03;
