@@ -639,6 +639,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     const int32_t filt = o.no_filter ? 0 : 1;
     if (ix->rule_key_rule != o.rule || ix->rule_key_eps != o.eps || ix->rule_key_filter != filt ||
         ix->rule_key_lndeltas != lnd) {
+        ix->rule_key_lndeltas.clear(); // (no call's key matches while the tables are rebuilt)
         const size_t tab_floats = 65 + (size_t)lnd.size() * ix->K * cols;
         const size_t dl_off = (tab_floats * sizeof(float) + 15) & ~(size_t)15;
         ix->rule_tab.ensure(dl_off + lnd.size() * sizeof(double));

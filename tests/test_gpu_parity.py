@@ -358,6 +358,33 @@ def test_batch_per_query_params_and_order():
         g.search_batch(Q, bad, recalls, 100)
 
 
+def test_index_buffers_reused_across_call_sizes():
+    """An index keeps its per-call device buffers (query rows, codes, decision tables, queue,
+    outputs) and grows them on demand: calls that shrink and grow m, k and the number of
+    distinct recalls, with hashing in between, each give the oracle's answers."""
+    X = workloads.gaussian_unit(5000, 56, 91)
+    Q = workloads.gaussian_unit(900, 56, 92)
+    rng = np.random.default_rng(93)
+    g, o = _build_both(X, L=36, seed=19)
+    calls = [("batch", 600, 100, [0.5, 0.9, 0.99]), ("single", 40, 10, [0.9]), ("hash", 900, 0, []),
+             ("batch", 150, 10, [0.8]), ("single", 900, 1, [0.7]), ("batch", 7, 37, [0.6, 0.95]),
+             ("single", 300, 100, [0.99])]
+    for kind, m, kmax, recs in calls:
+        print(f"[call] {kind} m={m} kmax={kmax} recalls={recs}", flush=True)
+        Qm = Q[:m]
+        if kind == "hash":
+            gc, gs = g.hash(Qm)
+            oc, os_ = oracle.hash_codes(oracle.normalize(Qm), o.hp, o.L, o.K, o.M)
+            assert np.array_equal(gc, oc) and np.array_equal(gs, os_)
+        elif kind == "single":
+            _assert_search_equal(g.search(Qm, kmax, recs[0]), o.search(Qm, kmax, recs[0]), f"m={m} k={kmax}")
+        else:
+            ks = rng.choice(np.unique(np.array([1, max(1, kmax // 3), kmax], dtype=np.int32)), size=m)
+            recalls = rng.choice(np.array(recs), size=m)
+            oids, oips, ost, obd = _oracle_per_query(o, Qm, ks, recalls, kmax)
+            _assert_batch_equal(g.search_batch(Qm, ks, recalls, kmax), oids, oips, ost, obd, f"m={m} kmax={kmax}")
+
+
 @pytest.mark.parametrize("d", [40, 100, 200, 300])
 def test_every_tile_shape(d):
     """Every built kernel tile shape (sketch loads per lane, rows in flight, register cap,
