@@ -89,7 +89,10 @@ __device__ __forceinline__ void wsync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
+// number of set bits of a wave mask in the lanes below this one (v_mbcnt)
+__device__ __forceinline__ int lanes_below(uint64_t mk) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+}
 
 // number of elements of the descending array arr[0..len) that are greater than key
 __device__ __forceinline__ int count_greater(const unsigned long long *arr, int len, unsigned long long key) {
@@ -196,7 +199,6 @@ __device__ void wave_merge(WLds &l, QState &st) {
     const int tc = st.top, k = st.k;
     {
         // drop copies; in place, one 64-element block at a time (reads before writes)
-        const uint64_t lt = lanemask_lt(lane);
         int w = 0;
         for (int t0 = 0; t0 < c; t0 += WV) {
             const int t = t0 + lane;
@@ -212,7 +214,7 @@ __device__ void wave_merge(WLds &l, QState &st) {
             }
             wsync();
             const uint64_t mk = __ballot(keep);
-            if (keep) cand[w + __popcll(mk & lt)] = key;
+            if (keep) cand[w + lanes_below(mk)] = key;
             w += __popcll(mk);
             wsync();
         }
@@ -505,7 +507,6 @@ template <int DT, int U, bool Q8>
 __device__ int prune_rows(const SearchK &p, const WLds &l, uint32_t *ids, int rc, float ipk, const QState &st) {
     constexpr int RROWS = 4 * U;
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
-    const uint64_t lt = lanemask_lt(lane);
     int w = 0;
     for (int t0 = 0; t0 < rc; t0 += RROWS) {
         const int first = t0 + g * U;
@@ -533,7 +534,7 @@ __device__ int prune_rows(const SearchK &p, const WLds &l, uint32_t *ids, int rc
         }
         const uint64_t mk = __ballot(keep);
         wsync();
-        if (keep) ids[w + __popcll(mk & lt)] = myx;
+        if (keep) ids[w + lanes_below(mk)] = myx;
         w += __popcll(mk);
         wsync();
     }
@@ -552,7 +553,6 @@ __device__ void wave_rerank(const SearchK &p, WLds &l, uint32_t *ids, int rc, QS
     constexpr int U = (DT == 4 || DT == 0) && TL::U > 4 ? 4 : TL::U;
     constexpr int RROWS = 4 * U, CW = TL::CW;
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
-    const uint64_t lt = lanemask_lt(lane);
     if (p.prefilter && st.top == st.k) {
         // 8-bit summaries first (one 128-byte line per row of up to 120 elements), then
         // the upper plane for the rows they cannot rule out
@@ -588,7 +588,7 @@ __device__ void wave_rerank(const SearchK &p, WLds &l, uint32_t *ids, int rc, QS
             emit = st.top < st.k || key > st.thr;
         }
         const uint64_t mk = __ballot(emit);
-        if (emit) l.cand[st.cand + __popcll(mk & lt)] = key;
+        if (emit) l.cand[st.cand + lanes_below(mk)] = key;
         st.cand += __popcll(mk);
         if (st.cand > CW - RROWS) wave_merge(l, st);
     }
@@ -664,7 +664,6 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
     l.q8 = reinterpret_cast<uint32_t *>(smem + lo_.q8);
     l.qv = reinterpret_cast<float *>(smem + lo_.qv);
     const int lane = threadIdx.x;
-    const uint64_t lt = lanemask_lt(lane);
     const int32_t L = p.L, K = p.K;
     const int64_t n = p.n;
 
@@ -729,7 +728,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                 }
                 const bool left = na < a, right = nb > b;
                 const uint64_t ml = __ballot(left), mr = __ballot(right);
-                uint32_t at = nseg + (uint32_t)(__popcll(ml & lt) + __popcll(mr & lt));
+                uint32_t at = nseg + (uint32_t)(lanes_below(ml) + lanes_below(mr));
                 if (left) {
                     l.segBeg[at] = na;
                     l.segTab[at] = (uint32_t)j;
@@ -766,7 +765,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                 // every load is unconditional)
                 uint32_t uid = 0;
                 if constexpr (TL::LATE) uid = p.tidx[lane < nu ? l.upos[lane] : 0u];
-                uint32_t valid = 0;
+                int lim[EPT]; // the entry's threshold: tau, or -1 past the end
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
                     const uint32_t f = base + u * WV + lane;
@@ -780,7 +779,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                         tqc = l.tq[tjc];
                         ebase = tjc * (uint32_t)n + l.segBeg[sg] - l.segStart[sg];
                     }
-                    valid |= (in ? 1u : 0u) << u;
+                    lim[u] = in ? tau : -1;
                     tqv[u] = tqc;
                     const uint32_t e = in ? ebase + f : 0u;
                     skv[u] = p.tsk[e];
@@ -790,14 +789,15 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                     if (lane < nu) l.pending[st.pend + lane] = uid;
                     st.pend += nu;
                 }
-                uint32_t pm = 0;
+                // (every entry is tested, without a branch: an entry past the end fails
+                // against -1)
+                bool ps[EPT];
                 uint64_t mk[EPT];
                 int np = 0;
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
-                    const bool pass = ((valid >> u) & 1u) && __popcll(skv[u] ^ tqv[u]) <= tau;
-                    pm |= (pass ? 1u : 0u) << u;
-                    mk[u] = __ballot(pass);
+                    ps[u] = (int)__popcll(skv[u] ^ tqv[u]) <= lim[u];
+                    mk[u] = __ballot(ps[u]);
                     np += __popcll(mk[u]);
                 }
                 if (TL::LATE && np <= TL::UCAP) {
@@ -805,7 +805,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                     int at = 0;
 #pragma unroll
                     for (int u = 0; u < EPT; ++u) {
-                        if ((pm >> u) & 1u) l.upos[at + __popcll(mk[u] & lt)] = ev[u];
+                        if (ps[u]) l.upos[at + lanes_below(mk[u])] = ev[u];
                         at += __popcll(mk[u]);
                     }
                     nu = np;
@@ -815,12 +815,12 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                     // flight)
                     if constexpr (TL::LATE) {
 #pragma unroll
-                        for (int u = 0; u < EPT; ++u) ev[u] = p.tidx[((pm >> u) & 1u) ? ev[u] : 0u];
+                        for (int u = 0; u < EPT; ++u) ev[u] = p.tidx[ps[u] ? ev[u] : 0u];
                         nu = 0;
                     }
 #pragma unroll
                     for (int u = 0; u < EPT; ++u) {
-                        if ((pm >> u) & 1u) l.pending[st.pend + __popcll(mk[u] & lt)] = ev[u];
+                        if (ps[u]) l.pending[st.pend + lanes_below(mk[u])] = ev[u];
                         st.pend += __popcll(mk[u]);
                     }
                 }
