@@ -142,9 +142,9 @@ __host__ __device__ inline LdsOff search_lds_offsets(int L, int kmax, int dpad, 
     o.clo = take(sizeof(uint32_t) * L);
     o.chi = take(sizeof(uint32_t) * L);
     o.qc = take(sizeof(uint32_t) * L);
-    o.segBeg = take(sizeof(uint32_t) * 2 * L);
-    o.segStart = take(sizeof(uint32_t) * (2 * L + 1));
-    o.segTab = take(sizeof(uint32_t) * 2 * L);
+    o.segBeg = take(sizeof(uint32_t) * (2 * L + 1));
+    o.segStart = take(sizeof(uint32_t) * (2 * L + 2));
+    o.segTab = take(sizeof(uint32_t) * (2 * L + 1));
     o.qb = take(sizeof(uint32_t) * (dpad / 2));
     o.qba = take(sizeof(uint32_t) * (dpad / 2));
     o.q8 = take(rq);
@@ -450,8 +450,37 @@ __device__ void query_rows8(const SearchK &p, WLds &l, QState &st) {
     st.qB = __builtin_amdgcn_readfirstlane(bsum);
 }
 
-// Upper bound of the exact inner product of row r of the group's U rows (lane r of the
-// group; the other lanes' result is unused) from the 8-bit summaries.  With
+// Integer sums of U rows over the 16 lanes of a DPP row, transposed: step S pairs lane r
+// with lane r ^ m_S (m = 8, 7, 2, 1: row_ror:8, row_half_mirror, quad_perm [2,3,0,1],
+// quad_perm [1,0,3,2]); while a lane holds n > 1 partial rows it keeps the half selected by
+// bit 3 - S of r and adds the partner's partial of the same rows.  The four masks are
+// independent over GF(2)^4, so every lane ends with the sum over all 16 lanes of row
+// r / (16 / U).
+template <int S> __device__ __forceinline__ int32_t dpp_step(int32_t v) {
+    constexpr int ctrl = S == 0 ? 0x128 : S == 1 ? 0x141 : S == 2 ? 0x4E : 0xB1;
+    return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, false);
+}
+template <int S, int N> __device__ __forceinline__ void tsum_rows(int32_t *a, int r) {
+    if constexpr (S < 4) {
+        if constexpr (N > 1) {
+            const bool hi = (r >> (3 - S)) & 1;
+#pragma unroll
+            for (int j = 0; j < N / 2; ++j) {
+                const int32_t keep = hi ? a[j + N / 2] : a[j];
+                const int32_t send = hi ? a[j] : a[j + N / 2];
+                a[j] = keep + dpp_step<S>(send);
+            }
+            tsum_rows<S + 1, N / 2>(a, r);
+        } else {
+            a[0] += dpp_step<S>(a[0]);
+            tsum_rows<S + 1, 1>(a, r);
+        }
+    }
+}
+
+// Upper bound of the exact inner product of row r / (16 / U) of the group's U rows (in
+// lane r of the group) from the 8-bit summaries; the caller passes row 0 for missing rows
+// and ignores their results.  With
 // x_i = s c_i + e_i, |e_i| <= h s, q_i = t b_i + f_i, |f_i| <= h t, h = 1/2 + 2^-16,
 // A = sum |c_i|, B = sum |b_i|, C = sum c_i b_i (exact, v_dot4_i32_i8):
 //   <x, q> <= s t (C + h (A + B) + dpad h^2).
@@ -459,41 +488,37 @@ __device__ void query_rows8(const SearchK &p, WLds &l, QState &st) {
 // the kernel's exact FP32 inner product exceeds <x, q> by less than 2^-16 (unit vectors,
 // d <= 4096); kAbs8 = 2^-15 covers both.  Lane r of a group reads bytes 8r .. 8r + 7 of
 // each 128-byte chunk of every row (an inline header faces zero query bytes) and the
-// header (s, A) of its own row.
+// header (s, A) of the row it ends with.
 constexpr float kH8 = 0.5f + 1.52587890625e-05f;
 constexpr float kAbs8 = 3.0517578125e-05f;
 template <int U>
-__device__ __forceinline__ float bound8_row(const SearchK &p, const WLds &l, const uint32_t *ids, int cnt, int r,
+__device__ __forceinline__ float bound8_row(const SearchK &p, const WLds &l, const uint32_t *ids, int r,
                                             float qt, int32_t qB) {
     const uint8_t *q8 = reinterpret_cast<const uint8_t *>(l.q8);
     int32_t acc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[u] = 0;
+    static_assert(U == 2 || U == 4 || U == 8 || U == 16, "rows per group");
+    const int row = r / (16 / U);
     uint32_t myid = ids[0];
 #pragma unroll
     for (int u = 1; u < U; ++u)
-        if (r == u) myid = ids[u];
+        if (row == u) myid = ids[u];
     const uint8_t *hp = p.Xqh ? p.Xqh + (int64_t)myid * 8 : p.Xq + (int64_t)myid * p.rq;
-    const uint2 hdr = r < cnt ? *reinterpret_cast<const uint2 *>(hp) : make_uint2(0u, 0u);
+    const uint2 hdr = *reinterpret_cast<const uint2 *>(hp);
     for (int off = 8 * r; off < p.rq; off += 128) {
         const uint2 qq = *reinterpret_cast<const uint2 *>(q8 + off);
         uint2 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            v[u] = u < cnt ? *reinterpret_cast<const uint2 *>(p.Xq + (int64_t)ids[u] * p.rq + off)
-                           : make_uint2(0u, 0u);
+        for (int u = 0; u < U; ++u) v[u] = *reinterpret_cast<const uint2 *>(p.Xq + (int64_t)ids[u] * p.rq + off);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             acc[u] = __builtin_amdgcn_sdot4((int)v[u].x, (int)qq.x, acc[u], false);
             acc[u] = __builtin_amdgcn_sdot4((int)v[u].y, (int)qq.y, acc[u], false);
         }
     }
-    int32_t C = 0;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int32_t cu = (int32_t)row_sum16u((uint32_t)acc[u]);
-        if (r == u) C = cu;
-    }
+    tsum_rows<0, U>(acc, r);
+    const int32_t C = acc[0];
     const float sc = __uint_as_float(hdr.x);
     const int32_t A = (int32_t)hdr.y;
     const float inner = (float)C + (kH8 * (float)(A + qB) + (float)p.dpad * (kH8 * kH8));
@@ -517,11 +542,13 @@ __device__ int prune_rows(const SearchK &p, const WLds &l, uint32_t *ids, int rc
         bool keep = false;
         uint32_t myx = x[0];
         if constexpr (Q8) {
-            const float ub = bound8_row<U>(p, l, x, cnt, r, st.qt, st.qB);
+            // row r / (16 / U) ends in lanes r; the first of them keeps it
+            const float ub = bound8_row<U>(p, l, x, r, st.qt, st.qB);
+            const int row = r / (16 / U);
 #pragma unroll
             for (int u = 1; u < U; ++u)
-                if (r == u) myx = x[u];
-            keep = r < cnt && ub >= ipk;
+                if (row == u) myx = x[u];
+            keep = r % (16 / U) == 0 && row < cnt && ub >= ipk;
         } else {
             float ub[U];
             bound_rows<DT, U>(p, l, x, cnt, r, ub);
@@ -745,6 +772,14 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             wsync();
             wave_scan_incl(l.segStart + 1, (int)nseg);
             const uint32_t total = l.segStart[nseg];
+            // a last segment without end, so that the walk below stops there without a
+            // bounds test (entries past the end are masked)
+            if (lane == 0) {
+                l.segStart[nseg + 1] = 0xFFFFFFFFu;
+                l.segBeg[nseg] = 0;
+                l.segTab[nseg] = 0;
+            }
+            wsync();
             st.c_scan += total;
             // each lane's entries f = base + u * 64 + lane only grow, so it walks the segments
             // once per level, keeping the current one's end and base offset in registers
@@ -770,7 +805,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                 for (int u = 0; u < EPT; ++u) {
                     const uint32_t f = base + u * WV + lane;
                     const bool in = f < total;
-                    if (in && f >= segEnd) {
+                    if (f >= segEnd) {
                         do {
                             ++sg;
                             segEnd = l.segStart[sg + 1];
