@@ -952,11 +952,11 @@ using T48 = Tile<4, 8>;
 using T168 = Tile<16, 8>;
 using T84 = Tile<8, 4>;
 using T84o4 = Tile<8, 4, 4>; // registers capped for 4 waves per SIMD (16 per CU)
-using T84o4l = Tile<8, 4, 4, true>;
+using T84o4l = Tile<8, 4, 4, true, 8>;  // ids read for passing entries only, one chunk late
 using T84o4q8 = Tile<8, 4, 4, false, 8>;   // 8 summary rows in flight per group
 static constexpr int kNumTiles = 7;
 static const char *kTileNames[kNumTiles] = {"ept8-u8", "ept4-u8", "ept16-u8", "ept8-u4", "ept8-u4-o4",
-                                            "ept8-u4-o4-late", "ept8-u4q8-o4"};
+                                            "ept8-u4q8-o4-late", "ept8-u4q8-o4"};
 
 template <class TL> static size_t tile_lds(const Index &ix, int32_t kmax) {
     return search_lds_offsets(ix.L, kmax, ix.dpad, TL::PCAP, TL::CW, TL::UCAP, ix.rq).total;
@@ -997,7 +997,7 @@ static const void *search_kernel(int dt, int tile) {
 int32_t search_tile_count() { return kNumTiles; }
 // the shape used when none is given or tuned: the fastest on the 1 M-point, d = 100
 // mixture at k = 10 both with static query slots and with the work queue
-int32_t search_default_tile() { return 6; }
+int32_t search_default_tile() { return 5; }
 const char *search_tile_name(int32_t t) { return (t >= 0 && t < kNumTiles) ? kTileNames[t] : "?"; }
 
 // resident query waves per CU for a tile shape (occupancy from registers and LDS)
