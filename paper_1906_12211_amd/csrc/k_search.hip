@@ -12,6 +12,8 @@
 #include "pf_device.h"
 #include "pf_internal.h"
 
+#include <type_traits>
+
 namespace pf {
 
 // --------------------------------------------------------------------------- search
@@ -792,7 +794,10 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             // waits for another.  Other tiles read the position of every entry with its
             // sketch.
             int nu = 0;
-            for (uint32_t base = 0; base < total; base += WCH) {
+            // one chunk of WCH entries from base; FULL: every entry lies before total (all
+            // chunks but a level's last), so no entry needs the end test
+            auto chunk = [&](auto full, uint32_t base) {
+                constexpr bool FULL = decltype(full)::value;
                 uint32_t ev[EPT];
                 uint64_t tqv[EPT];
                 uint64_t skv[EPT];
@@ -804,7 +809,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
                     const uint32_t f = base + u * WV + lane;
-                    const bool in = f < total;
+                    const bool in = FULL || f < total;
                     if (f >= segEnd) {
                         do {
                             ++sg;
@@ -859,6 +864,12 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                         st.pend += __popcll(mk[u]);
                     }
                 }
+            };
+            for (uint32_t base = 0; base < total; base += WCH) {
+                if (base + WCH <= total)
+                    chunk(std::true_type{}, base);
+                else
+                    chunk(std::false_type{}, base);
                 if (st.pend >= RB) {
                     st.c_pass += st.pend;
                     wsync();
