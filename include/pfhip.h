@@ -181,7 +181,8 @@ int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, 
  *  (1,000 functions per similarity -1, -0.95, ..., 1, made non-decreasing, similarity
  *  rounded down; Sec. 4.3), and the budget counts 3 c d' / 8 bytes of signs per table.
  * `points` n x d (caller-owned, copied).  Errors: PF_EINVAL (n < 1, n >= 2^31, d < 1,
- * d > PF_MAX_DIM, bad row, K, M or pool out of range), PF_EBUDGET, PF_ENOMEM, PF_EDEVICE.
+ * d > PF_MAX_DIM, bad row, K, M or pool out of range), PF_EBUDGET, PF_EUNSUPPORTED
+ * (L n >= 2^32 - 2^16 table entries), PF_ENOMEM, PF_EDEVICE.
  * Synchronises the stream before returning. */
 int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t memory_budget_bytes,
                    const pf_build_opts *opts, int32_t mem, void *stream, pf_index **out);

@@ -326,8 +326,10 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         if (L <= 0) L = budget > fixed ? (int64_t)((budget - fixed) / per) : 0;
         PF_CHECK(L >= 1, PF_EBUDGET, "pf_build_index: the memory budget holds no table");
         L = std::min<int64_t>(L, PF_MAX_TABLES);
-        PF_CHECK((uint64_t)L * (uint64_t)n < (1ull << 32), PF_EUNSUPPORTED,
-                 "pf_build_index: L * n must be below 2^32");
+        // table positions, and the search's entry counters (which run up to a chunk past a
+        // level's last entry), are 32-bit
+        PF_CHECK((uint64_t)L * (uint64_t)n < (1ull << 32) - (1ull << 16), PF_EUNSUPPORTED,
+                 "pf_build_index: L * n must be below 2^32 - 2^16");
 
         auto ix = std::make_unique<pf_index>();
         hipStream_t s = as_stream(stream);

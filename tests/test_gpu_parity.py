@@ -107,7 +107,7 @@ def test_config1_parity():
 
 
 @pytest.mark.parametrize("k,recall,kw", [
-    (1, 0.9, {}), (10, 0.5, {}), (10, 0.99, {}), (37, 0.9, {}), (10, 0.9, {"B": 1}),
+    (1, 0.9, {}), (10, 0.5, {}), (10, 0.99, {}), (37, 0.9, {}), (10, 0.9, {"B": 1}), (10, 0.9, {"B": 512}),
     (10, 0.9, {"filter": False}), (10, 0.9, {"rule": pf.PF_RULE_ALG1}), (10, 0.9, {"eps": 0.1}),
     (10, 0.9, {"rule": pf.PF_RULE_EXACT}), (10, 0.8, {"rule": pf.PF_RULE_EXACT, "eps": 0.3}),
     (5, 1.0, {}), (128, 0.7, {}), (10, 0.9, {"prefilter": False}), (10, 1.0, {"prefilter": False}),
