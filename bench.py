@@ -46,12 +46,16 @@ SEARCH_SRC = os.path.join(ROOT, "paper_1906_12211_amd", "csrc", "k_search.hip")
 def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> float:
     """Bytes the method must move for the queries of one launch of the search kernel:
     8 B per scanned table-local sketch, 4 B per position of a passing entry, the 8-bit
-    summary (8 + d B) of every candidate bounded from it, the upper 16-bit plane (2d B)
+    summary (8 + d B, or d B where the rows share one scale and carry no header: 8 + dpad
+    bytes would take another 128-byte line) of every candidate bounded from it, the upper
+    16-bit plane (2d B)
     of every candidate whose upper plane was read and the lower plane (2d B) of those
     whose exact inner product was needed, the query (4d) and its result (8k), and the
     two range bounds (8 B) of every table at every visited level."""
     stop = stats[:, 0].astype(np.float64)
-    per_q = (8.0 * stats[:, 1] + 4.0 * stats[:, 2] + (8.0 + d) * stats[:, 6] + 2.0 * d * (stats[:, 5] + stats[:, 4])
+    dpad = 4 * ((d + 3) // 4)
+    hdr = 8.0 if 8 + dpad <= (dpad + 127) // 128 * 128 else 0.0
+    per_q = (8.0 * stats[:, 1] + 4.0 * stats[:, 2] + (hdr + d) * stats[:, 6] + 2.0 * d * (stats[:, 5] + stats[:, 4])
              + 4.0 * d
              + 8.0 * k + 8.0 * L * (K + 1 - np.maximum(stop, 1)))
     return float(per_q.sum())

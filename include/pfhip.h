@@ -68,7 +68,11 @@ extern "C" {
                                    row summaries the re-rank bounds candidates with; row:
                                    FP32 scale s = max_i |x_i| / 127, int32 A = sum_i |c_i|,
                                    then int8 c_i = rint(x_i / s), zero padded (x the
-                                   normalised vector; IEEE FP32 division)                 */
+                                   normalised vector; IEEE FP32 division).  Where 8 + dpad
+                                   bytes take another 128-byte line than dpad (dpad = 121
+                                   .. 128, 249 .. 256, ...) every row has the scale of the
+                                   largest |x_i| of all rows, and the search bounds with
+                                   the largest A of all rows                              */
 
 /* hash families of the table codes (the sketches are always random-hyperplane bits) */
 #define PF_FAMILY_HP 0    /* random hyperplanes (Sec. 2.2), one bit per function          */

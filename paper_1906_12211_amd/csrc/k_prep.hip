@@ -133,15 +133,29 @@ void launch_join_planes(const uint16_t *hi, const uint16_t *lo, int64_t n, int32
     PF_HIP(hipGetLastError());
 }
 
-// 8-bit row summaries for the re-rank's first bound: the FP32 scale s = max_i |x_i| / 127,
-// the int32 A = sum_i |c_i| (the 8-byte header) and the int8 c_i = rint(x_i / s), i < dpad.
-// Row r of out (rq bytes, a multiple of 128) holds the codes from byte co on, zero padded;
-// the header is the row's first 8 bytes when they fit in front of the codes without
-// another 128-byte line (co = 8), else row r of hdr (co = 0).  With the FP32 divisions
-// correctly rounded, |x_i / s| <= 127 (1 + 2^-24), so |c_i| <= 127 and
-// |x_i - s c_i| <= s (1/2 + 2^-16).  One 64-lane wave per row.
+// Largest |x_i| over every row, into *gmax as FP32 bits (which order like the values for
+// x >= 0; *gmax starts at 0): one atomic per wave.
+__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ X, int64_t total, uint32_t *gmax) {
+    float m = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+        m = fmaxf(m, fabsf(X[i]));
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(gmax, __float_as_uint(m));
+}
+
+// 8-bit row summaries for the re-rank's first bound: an FP32 scale s, the int32 A =
+// sum_i |c_i| (the 8-byte header) and the int8 c_i = rint(x_i / s), i < dpad.  Row r of
+// out (rq bytes, a multiple of 128) holds the codes from byte co on, zero padded.  When
+// the header fits in front of the codes without another 128-byte line (co = 8) it is the
+// row's first 8 bytes and s = max_i |x_i| / 127 of the row; otherwise (co = 0) every row
+// takes the same s = G / 127, G the largest |x_i| of all rows (gmax[0]), gmax[1] receives
+// the largest A of any row, so that a bound needs no per-row header read, and the headers
+// go to row r of hdr for the export only.  With the FP32 divisions correctly rounded,
+// |x_i / s| <= 127 (1 + 2^-24), so |c_i| <= 127 and |x_i - s c_i| <= s (1/2 + 2^-16).
+// One 64-lane wave per row.
 __global__ __launch_bounds__(256) void k_rows8(const float *__restrict__ X, int64_t n, int32_t dpad, int32_t rq,
-                                               int32_t co, uint8_t *__restrict__ out, uint8_t *__restrict__ hdr) {
+                                               int32_t co, uint32_t *__restrict__ gmax,
+                                               uint8_t *__restrict__ out, uint8_t *__restrict__ hdr) {
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= n) return;
@@ -149,7 +163,7 @@ __global__ __launch_bounds__(256) void k_rows8(const float *__restrict__ X, int6
     float mx = 0.0f;
     for (int c = lane; c < dpad; c += 64) mx = fmaxf(mx, fabsf(x[c]));
     for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-    const float sc = mx / 127.0f;
+    const float sc = (co ? mx : __uint_as_float(*gmax)) / 127.0f;
     uint8_t *row = out + r * (int64_t)rq;
     int32_t asum = 0;
     for (int c = lane; c < rq - co; c += 64) {
@@ -166,6 +180,7 @@ __global__ __launch_bounds__(256) void k_rows8(const float *__restrict__ X, int6
         uint8_t *h = co ? row : hdr + r * 8;
         *reinterpret_cast<float *>(h) = sc;
         *reinterpret_cast<int32_t *>(h + 4) = asum;
+        if (!co) atomicMax(gmax + 1, (uint32_t)asum);
     }
 }
 
@@ -175,11 +190,20 @@ void rows8_layout(int32_t dpad, int32_t *rq, int32_t *co) {
     *rq = (*co + dpad + 127) / 128 * 128;
 }
 
-void launch_rows8(const float *X, int64_t n, int32_t dpad, uint8_t *out, uint8_t *hdr, hipStream_t s) {
+void launch_rows8(const float *X, int64_t n, int32_t dpad, uint8_t *out, uint8_t *hdr, uint32_t *gmax,
+                  hipStream_t s) {
     if (n <= 0) return;
     int32_t rq, co;
     rows8_layout(dpad, &rq, &co);
-    hipLaunchKernelGGL(k_rows8, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, dpad, rq, co, out, hdr);
+    if (co == 0) {
+        launch_fill_u32(gmax, 2, 0u, s);
+        const int64_t total = n * (int64_t)dpad;
+        const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_absmax, dim3((unsigned)blocks), dim3(256), 0, s, X, total, gmax);
+        PF_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_rows8, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, dpad, rq, co,
+                       gmax, out, hdr);
     PF_HIP(hipGetLastError());
 }
 

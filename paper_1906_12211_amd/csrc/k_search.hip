@@ -31,8 +31,9 @@ namespace pf {
 // point ids read for passing entries only, one chunk late (else for every scanned
 // entry, with its sketch); DT = 64-float chunks per row (0 = any length).
 static constexpr int WV = 64; // lanes per query wave
-template <int EPT_, int U_, int WPE_ = 1, bool LATE_ = false, int UQ_ = U_> struct Tile {
+template <int EPT_, int U_, int WPE_ = 1, bool LATE_ = false, int UQ_ = U_, bool SH_ = false> struct Tile {
     static constexpr int EPT = EPT_;
+    static constexpr bool SH = SH_; // summary rows without header: one scale s8, sums up to a8
     static constexpr int U = U_;
     static constexpr int UQ = UQ_; // rows in flight per 16-lane group when bounding from 8-bit summaries
     static constexpr int WPE = WPE_;
@@ -54,7 +55,9 @@ struct SearchK {
     int32_t prefilter;
     const uint8_t *Xq;  // 8-bit row summaries: rq bytes per row, int8 codes from byte qco,
     const uint8_t *Xqh; // headers (FP32 scale, int32 sum of |codes|) at the row's start
-    int32_t rq, qco;    // (qco = 8) or, when qco = 0, in Xqh (8 bytes per row)
+    int32_t rq, qco;    // (qco = 8) or, when qco = 0, in Xqh (8 bytes per row; every row's
+    float s8;           // scale is then s8 and no row's sum exceeds a8, which kernels built
+    int32_t a8;         // for that layout take instead of reading Xqh)
     const uint32_t *tidx, *off;
     const uint64_t *tsk;
     int64_t n;
@@ -482,7 +485,9 @@ template <int S, int N> __device__ __forceinline__ void tsum_rows(int32_t *a, in
 
 // Upper bound of the exact inner product of row r / (16 / U) of the group's U rows (in
 // lane r of the group) from the 8-bit summaries; the caller passes row 0 for missing rows
-// and ignores their results.  With
+// and ignores their results.  SH (rows without a header in their lines): the common
+// scale p.s8 and, for A, the largest sum p.a8 of any row (the bound grows with A), so that
+// no header is read.  With
 // x_i = s c_i + e_i, |e_i| <= h s, q_i = t b_i + f_i, |f_i| <= h t, h = 1/2 + 2^-16,
 // A = sum |c_i|, B = sum |b_i|, C = sum c_i b_i (exact, v_dot4_i32_i8):
 //   <x, q> <= s t (C + h (A + B) + dpad h^2).
@@ -493,7 +498,7 @@ template <int S, int N> __device__ __forceinline__ void tsum_rows(int32_t *a, in
 // header (s, A) of the row it ends with.
 constexpr float kH8 = 0.5f + 1.52587890625e-05f;
 constexpr float kAbs8 = 3.0517578125e-05f;
-template <int U>
+template <int U, bool SH>
 __device__ __forceinline__ float bound8_row(const SearchK &p, const WLds &l, const uint32_t *ids, int r,
                                             float qt, int32_t qB) {
     const uint8_t *q8 = reinterpret_cast<const uint8_t *>(l.q8);
@@ -506,8 +511,11 @@ __device__ __forceinline__ float bound8_row(const SearchK &p, const WLds &l, con
 #pragma unroll
     for (int u = 1; u < U; ++u)
         if (row == u) myid = ids[u];
-    const uint8_t *hp = p.Xqh ? p.Xqh + (int64_t)myid * 8 : p.Xq + (int64_t)myid * p.rq;
-    const uint2 hdr = *reinterpret_cast<const uint2 *>(hp);
+    uint2 hdr = make_uint2(__float_as_uint(p.s8), (uint32_t)p.a8);
+    if constexpr (!SH) {
+        const uint8_t *hp = p.Xqh ? p.Xqh + (int64_t)myid * 8 : p.Xq + (int64_t)myid * p.rq;
+        hdr = *reinterpret_cast<const uint2 *>(hp);
+    }
     for (int off = 8 * r; off < p.rq; off += 128) {
         const uint2 qq = *reinterpret_cast<const uint2 *>(q8 + off);
         uint2 v[U];
@@ -530,7 +538,7 @@ __device__ __forceinline__ float bound8_row(const SearchK &p, const WLds &l, con
 // One pruning pass over ids[0..rc): rows whose bound (from the 8-bit summaries, Q8, or
 // from the upper plane) is below the k-th inner product ipk could not enter the top-k;
 // the rest are compacted, in order, to the front of ids.  Returns their count.
-template <int DT, int U, bool Q8>
+template <int DT, int U, bool Q8, bool SH = false>
 __device__ int prune_rows(const SearchK &p, const WLds &l, uint32_t *ids, int rc, float ipk, const QState &st) {
     constexpr int RROWS = 4 * U;
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
@@ -545,7 +553,7 @@ __device__ int prune_rows(const SearchK &p, const WLds &l, uint32_t *ids, int rc
         uint32_t myx = x[0];
         if constexpr (Q8) {
             // row r / (16 / U) ends in lanes r; the first of them keeps it
-            const float ub = bound8_row<U>(p, l, x, r, st.qt, st.qB);
+            const float ub = bound8_row<U, SH>(p, l, x, r, st.qt, st.qB);
             const int row = r / (16 / U);
 #pragma unroll
             for (int u = 1; u < U; ++u)
@@ -587,7 +595,7 @@ __device__ void wave_rerank(const SearchK &p, WLds &l, uint32_t *ids, int rc, QS
         // the upper plane for the rows they cannot rule out
         const float ipk = key_ip(st.thr);
         st.c_q8 += rc;
-        rc = prune_rows<DT, TL::UQ, true>(p, l, ids, rc, ipk, st);
+        rc = prune_rows<DT, TL::UQ, true, TL::SH>(p, l, ids, rc, ipk, st);
         st.c_upper += rc;
         rc = prune_rows<DT, U, false>(p, l, ids, rc, ipk, st);
     } else {
@@ -794,10 +802,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             // waits for another.  Other tiles read the position of every entry with its
             // sketch.
             int nu = 0;
-            // one chunk of WCH entries from base; FULL: every entry lies before total (all
-            // chunks but a level's last), so no entry needs the end test
-            auto chunk = [&](auto full, uint32_t base) {
-                constexpr bool FULL = decltype(full)::value;
+            for (uint32_t base = 0; base < total; base += WCH) {
                 uint32_t ev[EPT];
                 uint64_t tqv[EPT];
                 uint64_t skv[EPT];
@@ -809,7 +814,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
                     const uint32_t f = base + u * WV + lane;
-                    const bool in = FULL || f < total;
+                    const bool in = f < total;
                     if (f >= segEnd) {
                         do {
                             ++sg;
@@ -864,12 +869,6 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                         st.pend += __popcll(mk[u]);
                     }
                 }
-            };
-            for (uint32_t base = 0; base < total; base += WCH) {
-                if (base + WCH <= total)
-                    chunk(std::true_type{}, base);
-                else
-                    chunk(std::false_type{}, base);
                 if (st.pend >= RB) {
                     st.c_pass += st.pend;
                     wsync();
@@ -984,24 +983,30 @@ static size_t search_lds_bytes(const Index &ix, int32_t kmax, int tile) {
     }
 }
 
-template <int DT> static const void *search_kernel_dt(int tile) {
+// the same shape for summary rows without header (one scale for all rows)
+template <class TL> using SharedScale = Tile<TL::EPT, TL::U, TL::WPE, TL::LATE, TL::UQ, true>;
+
+template <int DT, bool SH> static const void *search_kernel_dt(int tile) {
     switch (tile) {
-    case 1: return (const void *)k_search<DT, T48>;
-    case 2: return (const void *)k_search<DT, T168>;
-    case 3: return (const void *)k_search<DT, T84>;
-    case 4: return (const void *)k_search<DT, T84o4>;
-    case 5: return (const void *)k_search<DT, T84o4l>;
-    case 6: return (const void *)k_search<DT, T84o4q8>;
-    default: return (const void *)k_search<DT, T88>;
+    case 1: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T48>, T48>>;
+    case 2: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T168>, T168>>;
+    case 3: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84>, T84>>;
+    case 4: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4>, T84o4>>;
+    case 5: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4l>, T84o4l>>;
+    case 6: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4q8>, T84o4q8>>;
+    default: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T88>, T88>>;
     }
 }
 
-static const void *search_kernel(int dt, int tile) {
+// kernels for rows of at most 64, 128 or 256 floats, or any length; rows of 121 .. 128
+// and 249 .. 256 floats have summaries without header (shared scale), others of at most
+// 256 floats their header inline; longer rows read a separate header when they have one
+static const void *search_kernel(int dt, int tile, bool shared) {
     switch (dt) {
-    case 1: return search_kernel_dt<1>(tile);
-    case 2: return search_kernel_dt<2>(tile);
-    case 4: return search_kernel_dt<4>(tile);
-    default: return search_kernel_dt<0>(tile);
+    case 1: return search_kernel_dt<1, false>(tile);
+    case 2: return shared ? search_kernel_dt<2, true>(tile) : search_kernel_dt<2, false>(tile);
+    case 4: return shared ? search_kernel_dt<4, true>(tile) : search_kernel_dt<4, false>(tile);
+    default: return search_kernel_dt<0, false>(tile);
     }
 }
 
@@ -1015,7 +1020,7 @@ const char *search_tile_name(int32_t t) { return (t >= 0 && t < kNumTiles) ? kTi
 int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile) {
     int per_cu = 0;
     const size_t lds = search_lds_bytes(ix, kmax, tile);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel(row_chunks(ix.dpad), tile), WV, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel(row_chunks(ix.dpad), tile, ix.qco == 0), WV, lds) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 4;
@@ -1027,7 +1032,7 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     const int dt = row_chunks(ix.dpad);
     const int tile = (a.tile >= 0 && a.tile < kNumTiles) ? a.tile : search_default_tile();
     const size_t lds = search_lds_bytes(ix, a.kmax, tile);
-    const void *fn = search_kernel(dt, tile);
+    const void *fn = search_kernel(dt, tile, ix.qco == 0);
     PF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = search_waves_per_cu(ix, a.kmax, tile);
     if (a.waves_per_cu > 0) per_cu = std::min(per_cu, a.waves_per_cu);
@@ -1041,6 +1046,8 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     p.prefilter = a.prefilter;
     p.Xq = ix.Xq.as<uint8_t>();
     p.Xqh = ix.qco ? nullptr : ix.Xqh.as<uint8_t>();
+    p.s8 = ix.s8;
+    p.a8 = ix.a8;
     p.rq = ix.rq;
     p.qco = ix.qco;
     p.tidx = ix.tidx.as<uint32_t>();

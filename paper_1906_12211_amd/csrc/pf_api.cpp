@@ -404,7 +404,13 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         rows8_layout(ix->dpad, &ix->rq, &ix->qco);
         ix->Xq.alloc((size_t)n * ix->rq);
         if (ix->qco == 0) ix->Xqh.alloc((size_t)n * 8);
-        launch_rows8(X.as<float>(), n, ix->dpad, ix->Xq.as<uint8_t>(), ix->Xqh.as<uint8_t>(), s);
+        DevBuf gmax;
+        gmax.alloc(2 * sizeof(uint32_t));
+        launch_rows8(X.as<float>(), n, ix->dpad, ix->Xq.as<uint8_t>(), ix->Xqh.as<uint8_t>(), gmax.as<uint32_t>(), s);
+        if (ix->qco == 0) { // the common scale as the kernel computed it (row 0's header), largest sum
+            PF_HIP(hipMemcpyAsync(&ix->s8, ix->Xqh.p, sizeof(float), hipMemcpyDeviceToHost, s));
+            PF_HIP(hipMemcpyAsync(&ix->a8, gmax.as<uint32_t>() + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        }
         // a6: sorted tables
         ix->tcode.alloc((size_t)L * n * sizeof(uint32_t));
         ix->tidx.alloc((size_t)L * n * sizeof(uint32_t));

@@ -99,11 +99,14 @@ struct Index {
     DevBuf Xh, Xl;
     int32_t hs = 0, ls = 0;
     // 8-bit summary of every row (scale, sum of |codes|, int8 codes; rq bytes per row,
-    // codes from byte qco; qco = 0: the 8-byte headers in Xqh), read first by the
-    // re-rank: a candidate whose bound from it is below the current k-th inner product
-    // is ruled out without reading either plane
+    // codes from byte qco), read first by the re-rank: a candidate whose bound from it is
+    // below the current k-th inner product is ruled out without reading either plane.
+    // qco = 0: every row has the scale s8, no row's sum of |codes| exceeds a8, and the
+    // 8-byte headers sit in Xqh for the export
     DevBuf Xq, Xqh;
     int32_t rq = 0, qco = 0;
+    float s8 = 0.0f;
+    int32_t a8 = 0;
     DevBuf hp;     // (L*K + 64*M) x d FP32 hyperplanes (paper order); pooled: (m + 64*M) x d
     DevBuf psel;   // pooled: L x K int32, pool index of h_{t+1,j}
     DevBuf cpsign; // FHT-CP: (L c) x 3 x d'/32 u32 sign bits (bit set = -1)
@@ -185,7 +188,8 @@ void launch_join_planes(const uint16_t *hi, const uint16_t *lo, int64_t n, int32
 // 8-bit row summaries (layout in k_prep.hip) of X (n x dpad FP32, normalised): rq bytes
 // per row, codes from byte co; co = 0: the 8-byte headers in hdr (n x 8), else unused
 void rows8_layout(int32_t dpad, int32_t *rq, int32_t *co);
-void launch_rows8(const float *X, int64_t n, int32_t dpad, uint8_t *out, uint8_t *hdr, hipStream_t s);
+void launch_rows8(const float *X, int64_t n, int32_t dpad, uint8_t *out, uint8_t *hdr, uint32_t *gmax,
+                  hipStream_t s);
 
 // hashing of rows X (n x dpad) into code words; see k_hash.hip
 void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
