@@ -392,12 +392,14 @@ def test_index_buffers_reused_across_call_sizes():
             _assert_batch_equal(g.search_batch(Qm, ks, recalls, kmax), oids, oips, ost, obd, f"m={m} kmax={kmax}")
 
 
-@pytest.mark.parametrize("d", [40, 100, 200, 300])
+@pytest.mark.parametrize("d", [40, 100, 128, 200, 256, 300, 384])
 def test_every_tile_shape(d):
     """Every built kernel tile shape (sketch loads per lane, rows in flight, register cap,
     point ids read with every sketch or only for passing entries) at every row-length
     specialisation (d = 40, 100, 200, 300: one, two, four and any number of 64-float
-    chunks) gives the oracle's answers, single and batched."""
+    chunks; d = 128, 256: the kernels for summary rows without header, one shared scale;
+    d = 384: any length with the headers read from their own array) gives the oracle's
+    answers, single and batched."""
     X = workloads.gaussian_unit(3000, d, 300 + d)
     Q = workloads.gaussian_unit(160, d, 400 + d)
     rng = np.random.default_rng(d)
