@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -86,3 +87,19 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_bench_algorithmic_bytes_formula():
+    """The search kernel's algorithmic bytes per query: 8 per scanned sketch, 4 per passing
+    position, the summary row (8 + d, or d where the rows carry no header: 8 + dpad would take
+    another 128-byte line), 2d per upper and per lower plane read, the query, the result and
+    two range bounds per table and visited level."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    # stats columns: stop level, c_scan, c_pass, c_rerank, c_exact, c_upper, c_q8
+    st = np.array([[3, 1000, 50, 50, 2, 5, 40]], dtype=np.int64)
+    L, K, k = 10, 24, 10
+    for d, hdr in ((100, 8), (120, 8), (124, 0), (128, 0), (200, 8), (256, 0)):
+        want = 8 * 1000 + 4 * 50 + (hdr + d) * 40 + 2 * d * (5 + 2) + 4 * d + 8 * k + 8 * L * (K + 1 - 3)
+        assert bench.algorithmic_bytes(st, d, k, L, K) == want, d
