@@ -39,7 +39,7 @@ template <int EPT_, int U_, int WPE_ = 1, bool LATE_ = false, int UQ_ = U_, bool
     static constexpr int WPE = WPE_;
     static constexpr bool LATE = LATE_;
     static constexpr int WCH = WV * EPT;       // entries per filter chunk
-    static constexpr int RB = 64;              // re-rank once this many candidates wait
+    static constexpr int RB = 128;             // re-rank once this many candidates wait
     static constexpr int UCAP = LATE ? WV : 0; // passing entries whose point id is still being read
     static constexpr int PCAP = WCH + RB + UCAP; // pending capacity
     static constexpr int CW = U >= 8 ? 256 : 128; // candidate buffer (power of two)
