@@ -29,7 +29,8 @@ namespace pf {
 // per 16-lane group in the re-rank (UQ when bounding from the 8-bit summaries), WPE the
 // query waves per SIMD the register allocation must allow (1 = no constraint), LATE:
 // point ids read for passing entries only, one chunk late (else for every scanned
-// entry, with its sketch); DT = 64-float chunks per row (0 = any length).
+// entry, with its sketch); SH: the kernel is built for summary rows without header (one
+// scale for all rows); DT = 64-float chunks per row (0 = any length).
 static constexpr int WV = 64; // lanes per query wave
 template <int EPT_, int U_, int WPE_ = 1, bool LATE_ = false, int UQ_ = U_, bool SH_ = false> struct Tile {
     static constexpr int EPT = EPT_;
