@@ -98,7 +98,7 @@ def lib():
         L.oracle_search.argtypes = [
             _P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P, _I32, _P, _U64,
             _P, _I64, _I32, _D, _D, _I32, _I32, _I32,
-            _P, _P, _P, _P, _P, _P, _P, _P, _P,
+            _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
         ]
         L.oracle_bruteforce.restype = ctypes.c_int
         L.oracle_bruteforce.argtypes = [_P, _I64, _I32, _P, _I64, _I32, _P, _P]
@@ -294,6 +294,7 @@ class SearchResult:
     c_rerank: np.ndarray
     boundary: np.ndarray
     trace: np.ndarray | None = None
+    levels: np.ndarray | None = None  # (K+1) x 8, see level_trace()
 
 
 class OracleIndex:
@@ -336,24 +337,53 @@ class OracleIndex:
     def search(self, queries: np.ndarray, k: int, recall: float, eps: float = 0.0,
                B: int = DEFAULT_B, rule: int = RULE_FILTER, filter_on: bool = True,
                trace: bool = False) -> SearchResult:
-        q = np.ascontiguousarray(queries, dtype=np.float32)
-        m = q.shape[0]
-        ids = np.empty((m, k), dtype=np.int32)
-        ips = np.empty((m, k), dtype=np.float32)
-        ips64 = np.empty((m, k), dtype=np.float64)
-        sl = np.empty(m, dtype=np.int32)
-        cs = np.empty(m, dtype=np.int64)
-        cp = np.empty(m, dtype=np.int64)
-        cr = np.empty(m, dtype=np.int64)
-        bd = np.empty(m, dtype=np.int32)
-        tr = np.zeros((self.K + 1, self.L, 4), dtype=np.int64) if trace else None
-        rc = lib().oracle_search(
-            _ptr(self.points), self.n, self.d, _ptr(self.hp), _ptr(self.tcode), _ptr(self.tidx),
-            _ptr(self.tsk), self.L, self.K, self.M, _ptr(getattr(self, "sel", None)), getattr(self, "pool", 0),
-            _ptr(getattr(self, "cptab", None)), getattr(self, "seed", 0),
-            _ptr(q), m, k, recall, eps, B, rule,
-            1 if filter_on else 0, _ptr(ids), _ptr(ips), _ptr(ips64), _ptr(sl), _ptr(cs),
-            _ptr(cp), _ptr(cr), _ptr(bd), _ptr(tr))
-        if rc:
-            raise ValueError(f"oracle_search rc={rc}")
-        return SearchResult(ids, ips, ips64, sl, cs, cp, cr, bd, tr)
+        return search_tables(self.points, self.hp, self.tcode, self.tidx, self.tsk, self.K, self.M, queries, k,
+                             recall, eps=eps, B=B, rule=rule, filter_on=filter_on, trace=trace,
+                             sel=getattr(self, "sel", None), pool=getattr(self, "pool", 0),
+                             cptab=getattr(self, "cptab", None), seed=getattr(self, "seed", 0))
+
+
+LEVEL_TRACE_W = 8  # columns of SearchResult.levels
+
+
+def search_tables(points: np.ndarray, hp: np.ndarray, tcode: np.ndarray, tidx: np.ndarray, tsk: np.ndarray,
+                  K: int, M: int, queries: np.ndarray, k: int, recall: float, eps: float = 0.0,
+                  B: int = DEFAULT_B, rule: int = RULE_FILTER, filter_on: bool = True, trace: bool = False,
+                  sel: np.ndarray | None = None, pool: int = 0, cptab: np.ndarray | None = None,
+                  seed: int = 0) -> SearchResult:
+    """The adaptive query over given tables: normalised points (n x d), the hyperplanes
+    the queries are hashed with, and the L sorted tables (codes, positions, table-local
+    sketches).  With trace=True the walk of query 0 is recorded: ``trace`` per level and
+    table (lo_i, hi_i, c_lo, c_hi), ``levels`` per level (threshold used, masks of the new,
+    passing and top-k point ids, c_scan, c_pass, c_rerank, stopped)."""
+    points = np.ascontiguousarray(points, dtype=np.float32)
+    n, d = points.shape
+    tcode = np.ascontiguousarray(tcode, dtype=np.uint32)
+    tidx = np.ascontiguousarray(tidx, dtype=np.uint32)
+    tsk = np.ascontiguousarray(tsk, dtype=np.uint64)
+    L = tcode.shape[0]
+    assert tcode.shape == tidx.shape == tsk.shape == (L, n)
+    hp = np.ascontiguousarray(hp, dtype=np.float32)
+    q = np.ascontiguousarray(queries, dtype=np.float32)
+    assert q.ndim == 2 and q.shape[1] == d
+    m = q.shape[0]
+    ids = np.empty((m, k), dtype=np.int32)
+    ips = np.empty((m, k), dtype=np.float32)
+    ips64 = np.empty((m, k), dtype=np.float64)
+    sl = np.empty(m, dtype=np.int32)
+    cs = np.empty(m, dtype=np.int64)
+    cp = np.empty(m, dtype=np.int64)
+    cr = np.empty(m, dtype=np.int64)
+    bd = np.empty(m, dtype=np.int32)
+    tr = np.zeros((K + 1, L, 4), dtype=np.int64) if trace else None
+    lt = np.zeros((K + 1, LEVEL_TRACE_W), dtype=np.int64) if trace else None
+    sel = None if sel is None else np.ascontiguousarray(sel, dtype=np.int32)
+    tab = None if cptab is None else np.ascontiguousarray(cptab, dtype=np.float64)
+    rc = lib().oracle_search(
+        _ptr(points), n, d, _ptr(hp), _ptr(tcode), _ptr(tidx), _ptr(tsk), L, K, M, _ptr(sel), pool,
+        _ptr(tab), seed, _ptr(q), m, k, recall, eps, B, rule,
+        1 if filter_on else 0, _ptr(ids), _ptr(ips), _ptr(ips64), _ptr(sl), _ptr(cs),
+        _ptr(cp), _ptr(cr), _ptr(bd), _ptr(tr), _ptr(lt))
+    if rc:
+        raise ValueError(f"oracle_search rc={rc}")
+    return SearchResult(ids, ips, ips64, sl, cs, cp, cr, bd, tr, lt)

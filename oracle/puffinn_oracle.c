@@ -638,7 +638,15 @@ typedef struct {
 } or_index;
 
 /* trace (optional, one query): per level i (row i of K+1) and table j:
- * [0] lo_i [1] hi_i [2] c_lo after level i [3] c_hi after level i */
+ * [0] lo_i [1] hi_i [2] c_lo after level i [3] c_hi after level i
+ * ltrace (optional, the same query): per level i, row i of K+1 rows of OR_LT_W int64:
+ * [0] the filter threshold the level used (64: no filtering), -2 when the level was not
+ *     reached, -1 for the linear scan; [1] the set of point ids among the level's new
+ *     entries, [2] the set among those that passed the filter, [6] the set of the top-k
+ *     after the level, each as a bit mask (bit x for point x; meaningful for n <= 64);
+ *     [3] c_scan, [4] c_pass, [5] c_rerank after the level; [7] 1 when the query stopped
+ *     there. */
+#define OR_LT_W 8
 /* top <- best k distinct points of top u fresh (the accumulator's flush): sort by
  * (ip desc, id asc); copies of one point carry the same inner product, so they are
  * adjacent and all but the first are dropped. */
@@ -656,12 +664,18 @@ static int accumulate(or_list *top, const or_list *fresh, int32_t k) {
 static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, const uint64_t *qsk,
                     int32_t k, double delta, double eps, int32_t B, int32_t rule, int32_t filter_on,
                     int64_t *clo, int64_t *chi, or_list *top, or_list *fresh,
-                    int32_t *stop_level, int64_t *cnt, int32_t *boundary, int64_t *trace) {
+                    int32_t *stop_level, int64_t *cnt, int32_t *boundary, int64_t *trace,
+                    int64_t *ltrace) {
     const int64_t n = ix->n;
     const int32_t L = ix->L, K = ix->K, d = ix->d;
     top->len = 0;
     cnt[0] = cnt[1] = cnt[2] = 0;
     *boundary = 0;
+    if (ltrace)
+        for (int32_t i = 0; i <= K; ++i) {
+            memset(ltrace + (int64_t)i * OR_LT_W, 0, OR_LT_W * sizeof(int64_t));
+            ltrace[(int64_t)i * OR_LT_W] = -2;
+        }
     for (int32_t j = 0; j < L; ++j) {
         int64_t lk = prefix_bound(ix->tcode + (int64_t)j * n, n, K, K, qcode[j], 1);
         clo[j] = chi[j] = lk;
@@ -676,6 +690,8 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
             if (fr < 1e-9 || fr > 1.0 - 1e-9) *boundary = 1;
             tau_int = tau >= 64.0 ? 64 : (tau < -1.0 ? -1 : (int32_t)floor(tau));
         }
+        int64_t *lt = ltrace ? ltrace + (int64_t)i * OR_LT_W : NULL;
+        if (lt) lt[0] = tau_int;
         fresh->len = 0;
         for (int32_t j = 0; j < L; ++j) {
             const uint32_t *tc = ix->tcode + (int64_t)j * n;
@@ -715,10 +731,12 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
                 for (int64_t e = seg[s][0]; e < seg[s][1]; ++e) {
                     cnt[0]++;
                     int h = __builtin_popcountll(ts[e] ^ qs);
+                    if (lt && ti[e] < 64) lt[1] |= (int64_t)1 << ti[e];
                     if ((double)h > tau) continue;
                     cnt[1]++;
                     cnt[2]++;
                     uint32_t x = ti[e];
+                    if (lt && x < 64) lt[2] |= (int64_t)1 << x;
                     const float *px = ix->points + (int64_t)x * d;
                     or_cand c = {oracle_ip32(px, q, d), oracle_ip64(px, q, d), (int32_t)x};
                     if (list_push(fresh, c)) return OR_ENOMEM;
@@ -726,6 +744,11 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
             }
         }
         if (accumulate(top, fresh, k)) return OR_ENOMEM;
+        if (lt) {
+            lt[3] = cnt[0], lt[4] = cnt[1], lt[5] = cnt[2];
+            for (int64_t t = 0; t < top->len; ++t)
+                if (top->v[t].id < 64) lt[6] |= (int64_t)1 << top->v[t].id;
+        }
         if (top->len == k) {
             double margin;
             int stop = oracle_stop(top->v[k - 1].ip, i, L, ix->M, delta, rule, tau_int, ix->pool, ix->cptab, ix->ell,
@@ -738,6 +761,7 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
             }
             if (stop) {
                 *stop_level = i;
+                if (lt) lt[7] = 1;
                 return OR_OK;
             }
         }
@@ -751,6 +775,16 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
         if (list_push(fresh, c)) return OR_ENOMEM;
     }
     if (accumulate(top, fresh, k)) return OR_ENOMEM;
+    if (ltrace) {
+        int64_t *lt = ltrace;
+        lt[0] = -1;
+        for (int64_t x = 0; x < n && x < 64; ++x) lt[1] |= (int64_t)1 << x;
+        lt[2] = lt[1];
+        lt[3] = cnt[0], lt[4] = cnt[1], lt[5] = cnt[2];
+        for (int64_t t = 0; t < top->len; ++t)
+            if (top->v[t].id < 64) lt[6] |= (int64_t)1 << top->v[t].id;
+        lt[7] = 1;
+    }
     *stop_level = 0;
     return OR_OK;
 }
@@ -764,7 +798,8 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
  * Outputs per query: ids[k], ips[k] (FP32 order above), ips64[k], stop level, the three
  * counters, and boundary = 1 when a decision came within 1e-9 of flipping (a test of an
  * FP32 ip against an FP64 threshold computed with a different libm may then differ).
- * trace (nullable) records the walk of query 0 only: (K+1) x L x 4 int64.
+ * trace (nullable) records the walk of query 0 only: (K+1) x L x 4 int64; ltrace
+ * (nullable) the same query's levels, (K+1) x OR_LT_W int64 (see walk_one).
  * Returns 0, OR_EINVAL (bad arguments or a zero / non-finite query row), OR_ENOMEM. */
 int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, const uint32_t *tcode,
                   const uint32_t *tidx, const uint64_t *tsk, int32_t L, int32_t K, int32_t M,
@@ -772,7 +807,7 @@ int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, co
                   const float *queries, int64_t m, int32_t k, double recall, double eps, int32_t B,
                   int32_t rule, int32_t filter_on, int32_t *ids, float *ips, double *ips64,
                   int32_t *stop_level, int64_t *c_scan, int64_t *c_pass, int64_t *c_rerank,
-                  int32_t *boundary, int64_t *trace) {
+                  int32_t *boundary, int64_t *trace, int64_t *ltrace) {
     if (n < 1 || d < 1 || L < 1 || K < 1 || K > 32 || M < 1 || m < 0 || k < 1 || k > n || B < 1)
         return OR_EINVAL;
     if (rule == OR_RULE_POOL && (pool < 1 || cptab)) return OR_EINVAL;
@@ -818,7 +853,8 @@ int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, co
             int64_t cnt[3];
             int32_t sl = 0, bd = 0;
             int rc = walk_one(&ix, qn + t * d, mycode, mysk, k, delta, eps, B, rule, filter_on, clo, chi,
-                              &top, &fresh, &sl, cnt, &bd, t == 0 ? trace : NULL);
+                              &top, &fresh, &sl, cnt, &bd, t == 0 ? trace : NULL,
+                              t == 0 ? ltrace : NULL);
             if (rc) {
                 err = rc;
                 continue;
