@@ -647,13 +647,16 @@ typedef struct {
  *     [3] c_scan, [4] c_pass, [5] c_rerank after the level; [7] 1 when the query stopped
  *     there. */
 #define OR_LT_W 8
+/* bit x of a trace mask (x < 64), formed unsigned so that bit 63 is no signed overflow */
+static int64_t or_bit(int64_t x) { return (int64_t)((uint64_t)1 << x); }
 /* top <- best k distinct points of top u fresh (the accumulator's flush): sort by
  * (ip desc, id asc); copies of one point carry the same inner product, so they are
  * adjacent and all but the first are dropped. */
 static int accumulate(or_list *top, const or_list *fresh, int32_t k) {
     for (int64_t t = 0; t < fresh->len; ++t)
         if (list_push(top, fresh->v[t])) return OR_ENOMEM;
-    qsort(top->v, (size_t)top->len, sizeof(or_cand), cmp_cand);
+    if (top->len > 1) /* (an empty list may have no storage yet: qsort needs a non-null array) */
+        qsort(top->v, (size_t)top->len, sizeof(or_cand), cmp_cand);
     int64_t w = 0;
     for (int64_t t = 0; t < top->len && w < k; ++t)
         if (w == 0 || top->v[t].id != top->v[w - 1].id) top->v[w++] = top->v[t];
@@ -731,12 +734,12 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
                 for (int64_t e = seg[s][0]; e < seg[s][1]; ++e) {
                     cnt[0]++;
                     int h = __builtin_popcountll(ts[e] ^ qs);
-                    if (lt && ti[e] < 64) lt[1] |= (int64_t)1 << ti[e];
+                    if (lt && ti[e] < 64) lt[1] |= or_bit(ti[e]);
                     if ((double)h > tau) continue;
                     cnt[1]++;
                     cnt[2]++;
                     uint32_t x = ti[e];
-                    if (lt && x < 64) lt[2] |= (int64_t)1 << x;
+                    if (lt && x < 64) lt[2] |= or_bit(x);
                     const float *px = ix->points + (int64_t)x * d;
                     or_cand c = {oracle_ip32(px, q, d), oracle_ip64(px, q, d), (int32_t)x};
                     if (list_push(fresh, c)) return OR_ENOMEM;
@@ -747,7 +750,7 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
         if (lt) {
             lt[3] = cnt[0], lt[4] = cnt[1], lt[5] = cnt[2];
             for (int64_t t = 0; t < top->len; ++t)
-                if (top->v[t].id < 64) lt[6] |= (int64_t)1 << top->v[t].id;
+                if (top->v[t].id < 64) lt[6] |= or_bit(top->v[t].id);
         }
         if (top->len == k) {
             double margin;
@@ -778,11 +781,11 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
     if (ltrace) {
         int64_t *lt = ltrace;
         lt[0] = -1;
-        for (int64_t x = 0; x < n && x < 64; ++x) lt[1] |= (int64_t)1 << x;
+        for (int64_t x = 0; x < n && x < 64; ++x) lt[1] |= or_bit(x);
         lt[2] = lt[1];
         lt[3] = cnt[0], lt[4] = cnt[1], lt[5] = cnt[2];
         for (int64_t t = 0; t < top->len; ++t)
-            if (top->v[t].id < 64) lt[6] |= (int64_t)1 << top->v[t].id;
+            if (top->v[t].id < 64) lt[6] |= or_bit(top->v[t].id);
         lt[7] = 1;
     }
     *stop_level = 0;
