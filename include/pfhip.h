@@ -134,8 +134,10 @@ typedef struct {
     int64_t n;
     int32_t d, L, K, M, P, pool; /* pool: m of a pooled index, 0 otherwise */
     int32_t family;              /* PF_FAMILY_* of the table codes               */
-    uint64_t bytes_budget_rule; /* bytes the budget rule counts for this index        */
-    uint64_t bytes_device;      /* device bytes the index actually holds              */
+    uint64_t bytes_budget_rule; /* bytes the budget rule counts for this index (fixed +
+                                   L per_table, see pf_build_index)                      */
+    uint64_t bytes_device;      /* device bytes the index actually holds (equal to
+                                   bytes_budget_rule)                                    */
     double build_ms;            /* device time of the last build, if measured         */
 } pf_info;
 
@@ -148,6 +150,15 @@ typedef struct {
                              and the autotuner when asked; ranges_ms covers the decision
                              tables and the prefix ranges                                 */
 } pf_timing;
+
+/* Measurement aid (not part of the method): the best read rate, in GB/s (10^9 bytes per
+ * second), of `reps` timed launches (after one warm-up) of a plain read-only streaming
+ * kernel over a device buffer of `bytes` bytes that the call allocates, fills and frees
+ * on the current device -- the read bandwidth that the device's memory system delivers
+ * to a fully coalesced access pattern, against which the search kernel's rate is also
+ * reported.  PF_EINVAL for bytes < 1 MiB, reps < 1 or gbs NULL; PF_ENOMEM, PF_EDEVICE.
+ * Synchronises `stream`. */
+int pf_read_bandwidth(uint64_t bytes, int32_t reps, double *gbs, void *stream);
 
 /* Number of kernel tile shapes the library is built with, and the name of shape t
  * (a static string; "?" when t is out of range). */
@@ -168,28 +179,44 @@ const char *pf_tile_name(int32_t t);
 int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, void *stream);
 
 /* Build the index of Sec. 4.1-4.2 over n points of dimension d:
- *  L = floor((budget - 4nd - 4*64*M*d) / (16n + 4*(2^P+1) + 4Kd)) tables (the budget
- *  counts the vectors, the hash functions, the sorted (code, position) arrays, the
- *  table-local sketches and the prefix tables; Sec. 5.2), capped at PF_MAX_TABLES;
+ *  L = floor((budget - fixed) / per_table) tables, capped at PF_MAX_TABLES, where the
+ *  budget counts every byte the index keeps on the device (Sec. 1, Sec. 5.2: the data
+ *  set and the hash functions are part of the index size): fixed = the vectors (two
+ *  16-bit planes, 4 dpad bytes per row up to line padding) and their 8-bit summaries
+ *  (PF_EXPORT_ROWS8 layout, whole 128-byte lines per row, + 8 bytes per row when the rows
+ *  share one scale), the 64 M sketch hyperplanes and their BF16 GEMM copies; per_table =
+ *  the sorted codes, positions and table-local sketches (16n), the prefix table
+ *  (4 (2^P + 1)), the table's K hyperplanes (4Kd) and their GEMM copy.  For n = 10^6,
+ *  d = 100, 2 GiB this gives L = 100 (the paper's count of vectors, functions and tables
+ *  alone would give 108); pf_info.bytes_device <= budget always holds;
  *  K random-hyperplane functions per table (Sec. 2.2), M 64-bit sketches per point
  *  (Sec. 4.2), each table sorted by its K-bit code with equal codes by position, and a
  *  table of the positions of every P-bit prefix (Sec. 4.2, P = min(13, K)).
  *  With opts->pool = m (Sec. 3.2 "Pooling"): m shared hyperplanes, each table's K
  *  functions drawn from them without replacement (Fisher-Yates on the SplitMix64 stream
- *  seeded with seed + 1), and the budget counts 4md once and 4K per table instead of
- *  4Kd.
+ *  seeded with seed + 1), and the budget counts the m pool hyperplanes (with their GEMM
+ *  copies) once and 4K bytes of indices per table instead of 4Kd.
  *  With opts->family = PF_FAMILY_FHTCP: each table's code is the first K bits of c =
  *  ceil(K / ell) cross-polytope values (rotation H D3 H D2 H D1 of the zero-padded point,
  *  FP64; value = sign of the largest coordinate as the top bit, then its index), the
  *  stopping rules read the collision probability of a prefix from a Monte Carlo table
  *  (1,000 functions per similarity -1, -0.95, ..., 1, made non-decreasing, similarity
- *  rounded down; Sec. 4.3), and the budget counts 3 c d' / 8 bytes of signs per table.
+ *  rounded down; Sec. 4.3), and the budget counts 3 c ceil(d' / 32) 32-bit words of
+ *  signs per table and the collision table once.
  * `points` n x d (caller-owned, copied).  Errors: PF_EINVAL (n < 1, n >= 2^31, d < 1,
  * d > PF_MAX_DIM, bad row, K, M or pool out of range), PF_EBUDGET, PF_EUNSUPPORTED
  * (L n >= 2^32 - 2^16 table entries), PF_ENOMEM, PF_EDEVICE.
  * Synchronises the stream before returning. */
 int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t memory_budget_bytes,
                    const pf_build_opts *opts, int32_t mem, void *stream, pf_index **out);
+
+/* The table count L and the device bytes (fixed + L per_table) that pf_build_index would
+ * use for n points of dimension d under `budget` and `opts` (nullable = defaults): the
+ * budget rule above, evaluated on the host without touching a device.  L and
+ * bytes_device are nullable.  Errors as pf_build_index's argument checks (PF_EINVAL,
+ * PF_EBUDGET, PF_EUNSUPPORTED). */
+int pf_plan_index(int64_t n, int32_t d, uint64_t budget, const pf_build_opts *opts, int32_t *L,
+                  uint64_t *bytes_device);
 
 /* Answer m queries (Algorithm 1, adaptive-kNN(q, k, delta), with delta = 1 - recall,
  * Sec. 2.1), level-synchronously as in Sec. 4.1: in each round every table contributes

@@ -30,9 +30,9 @@ PF_BATCH_LEARNED, PF_BATCH_AUTOTUNE = 1, 2
 
 PF_SCHED_IN, PF_SCHED_OUT, PF_SCHED_PARAMS = 98, 2, 29442
 
-EXPORTED = ["pf_normalize", "pf_build_index", "pf_search", "pf_search_ex", "pf_search_batch", "pf_hash",
+EXPORTED = ["pf_normalize", "pf_build_index", "pf_plan_index", "pf_search", "pf_search_ex", "pf_search_batch", "pf_hash",
             "pf_export", "pf_index_info", "pf_last_timing", "pf_free_index", "pf_last_error", "pf_version",
-            "pf_tile_count", "pf_tile_name",
+            "pf_tile_count", "pf_tile_name", "pf_read_bandwidth",
             "pf_sched_create", "pf_sched_free", "pf_sched_params", "pf_features", "pf_sched_predict",
             "pf_sched_grad", "pf_sched_train", "pf_sched_save", "pf_sched_load", "pf_index_set_scheduler"]
 
@@ -107,6 +107,11 @@ def lib():
         L.pf_build_index.restype = ctypes.c_int
         L.pf_build_index.argtypes = [_P, _I64, _I32, _U64, ctypes.POINTER(pf_build_opts), _I32, _P,
                                      ctypes.POINTER(_P)]
+        L.pf_read_bandwidth.restype = ctypes.c_int
+        L.pf_read_bandwidth.argtypes = [_U64, _I32, ctypes.POINTER(_D), _P]
+        L.pf_plan_index.restype = ctypes.c_int
+        L.pf_plan_index.argtypes = [_I64, _I32, _U64, ctypes.POINTER(pf_build_opts), ctypes.POINTER(_I32),
+                                    ctypes.POINTER(_U64)]
         L.pf_search.restype = ctypes.c_int
         L.pf_search.argtypes = [_P, _P, _I64, _I32, _D, _P, _P, _P, _I32, _P]
         L.pf_search_ex.restype = ctypes.c_int
@@ -209,6 +214,23 @@ def pf_normalize(x):
     po, _, _ = _buf(out)
     _check(lib().pf_normalize(px, x.shape[0], x.shape[1], po, mem, st))
     return out
+
+
+def pf_read_bandwidth(nbytes: int = 4 << 30, reps: int = 5) -> float:
+    """GB/s of a plain read-only streaming kernel on the current device (measurement aid)."""
+    g = _D()
+    _check(lib().pf_read_bandwidth(int(nbytes), int(reps), ctypes.byref(g), None))
+    return float(g.value)
+
+
+def pf_plan_index(n: int, d: int, budget: int, K: int = 24, M: int = 32, L: int | None = None, pool: int = 0,
+                  family: int = PF_FAMILY_HP):
+    """(L, device bytes) that pf_build_index would use (host only, no device call)."""
+    opts = pf_build_opts(0, K, M, PF_HASH_BF16X3, int(L or 0), int(pool), int(family))
+    nl, nb = _I32(), _U64()
+    _check(lib().pf_plan_index(int(n), int(d), int(budget), ctypes.byref(opts), ctypes.byref(nl),
+                               ctypes.byref(nb)))
+    return int(nl.value), int(nb.value)
 
 
 @dataclass

@@ -458,18 +458,39 @@ void cp_codes(const Index &ix, const float *X, int64_t n, uint32_t *codes, hipSt
 }
 
 
+// scratch of hash_rows_into for n rows: the pool bits (with a pool), then the GEMM's
+// flagged-bit count and list of at most fcap (row, column) pairs
+static void hash_scratch_parts(const Index &ix, int64_t n, size_t *pool_bytes, uint32_t *fcap) {
+    const HashPlan &hp = ix.plan;
+    *pool_bytes = hp.pool ? ((size_t)n * hp.cw * sizeof(uint32_t) + 255) / 256 * 256 : 0;
+    const uint64_t want = (uint64_t)n * (uint64_t)hp.ncols / 64u + 65536u;
+    *fcap = (uint32_t)std::min<uint64_t>(want, 1ull << 30);
+}
+
+size_t hash_scratch_bytes(const Index &ix, int64_t n) {
+    size_t pool_bytes;
+    uint32_t fcap;
+    hash_scratch_parts(ix, n, &pool_bytes, &fcap);
+    return pool_bytes + 256 + (size_t)fcap * 8;
+}
+
 void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
                DevBuf &scratch, hipStream_t s) {
     if (n <= 0) return;
+    // the scratch is the caller's and outlives the queued kernels
+    scratch.ensure(hash_scratch_bytes(ix, n));
+    hash_rows_into(ix, X, n, codes, sketches, scratch.as<char>(), s);
+}
+
+void hash_rows_into(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
+                    char *scratch, hipStream_t s) {
+    if (n <= 0) return;
     const HashPlan &hp = ix.plan;
-    // scratch: the pool bits (with a pool), then the GEMM's list of flagged bits; it is the
-    // caller's and outlives the queued kernels
-    const size_t pool_bytes = hp.pool ? ((size_t)n * hp.cw * sizeof(uint32_t) + 255) / 256 * 256 : 0;
-    const uint64_t want = (uint64_t)n * (uint64_t)hp.ncols / 64u + 65536u;
-    const uint32_t fcap = (uint32_t)std::min<uint64_t>(want, 1ull << 30);
-    scratch.ensure(pool_bytes + 256 + (size_t)fcap * 8);
+    size_t pool_bytes;
+    uint32_t fcap;
+    hash_scratch_parts(ix, n, &pool_bytes, &fcap);
     uint32_t *table_codes = codes;
-    if (hp.pool) codes = scratch.as<uint32_t>(); // the GEMM writes the pool bits; codes are gathered at the end
+    if (hp.pool) codes = reinterpret_cast<uint32_t *>(scratch); // the GEMM writes the pool bits; codes are gathered at the end
     launch_fill_u32(codes, n * (int64_t)hp.cw, 0u, s);
     launch_fill_u32(reinterpret_cast<uint32_t *>(sketches), 2 * n * (int64_t)hp.M, 0u, s);
     const uint32_t kmask = (hp.pool || hp.K >= 32) ? 0xFFFFFFFFu : ((1u << hp.K) - 1u);
@@ -481,7 +502,7 @@ void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint
                            ix.dpad, hp.d, ix.hp.as<float>(), colrow, hp.words, hp.cw, kmask, codes, skw);
         PF_HIP(hipGetLastError());
     } else {
-        hash_gemm(ix, X, n, codes, skw, kmask, colrow, static_cast<char *>(scratch.p) + pool_bytes, fcap, s);
+        hash_gemm(ix, X, n, codes, skw, kmask, colrow, scratch + pool_bytes, fcap, s);
     }
     if (ix.family == PF_FAMILY_FHTCP) cp_codes(ix, X, n, table_codes, s);
     if (hp.pool) {

@@ -137,12 +137,19 @@ __global__ __launch_bounds__(256) void k_ranges_wave(const uint32_t *__restrict_
 
 template <int NR> static const void *group_kernel() { return (const void *)k_ranges_group<NR>; }
 
+size_t ranges_list_bytes(int64_t m, int32_t L) { return (size_t)(m * L + 1) * sizeof(uint32_t); }
+
 void launch_ranges(Index &ix, const SearchArgs &a, uint32_t *ranges, hipStream_t s) {
+    if (ix.K <= ix.P || a.m <= 0) return;
+    ix.rlist.ensure(ranges_list_bytes(a.m, ix.L));
+    launch_ranges_into(ix, a, ranges, ix.rlist.as<uint32_t>(), s);
+}
+
+void launch_ranges_into(const Index &ix, const SearchArgs &a, uint32_t *ranges, uint32_t *rlist, hipStream_t s) {
     if (ix.K <= ix.P || a.m <= 0) return;
     const int64_t pairs = a.m * ix.L;
     PF_CHECK(pairs < ((int64_t)1 << 32), PF_EINVAL, "search: more than 2^32 (query, table) pairs in one call");
-    ix.rlist.ensure((size_t)(pairs + 1) * sizeof(uint32_t));
-    uint32_t *nbig = ix.rlist.as<uint32_t>();
+    uint32_t *nbig = rlist;
     uint32_t *big = nbig + 1;
     launch_fill_u32(nbig, 1, 0u, s);
     // registers of 8-bit bin counters per flag: bins lcp - P = 0 .. K - P

@@ -152,21 +152,42 @@ static void cp_dims(int32_t d, int32_t &dp, int32_t &ell) {
     while (dp < d) dp <<= 1, ++ell;
 }
 
-// budget rule: bytes of the vectors, sketch functions and (pooled) pool functions, and
-// bytes per table (its K functions, with a pool their K indices, with cross-polytope
-// codes the three d'-bit sign vectors of each of its c functions)
+// Budget rule: every byte the index keeps on the device, split into the part that does
+// not depend on L and the bytes each table adds (Sec. 1 and Sec. 5.2: the budget covers
+// the data set and the hash functions as well as the tables).  The terms mirror the
+// allocations of pf_build_index and build_plan one for one:
+//   fixed: the vectors as two 16-bit planes, their 8-bit summaries (+ the 8-byte headers
+//          when rows share one scale), the sketch (and pool) hyperplanes, their GEMM
+//          copies (BF16 hi + lo, column rows, flag bounds; 32 columns per word), and the
+//          cross-polytope collision table;
+//   per table: sorted codes, positions and table-local sketches (16n), the prefix table,
+//          the table's K hyperplanes and their GEMM word (independent functions), its K
+//          pool indices (pooling) or its cross-polytope sign words.
 static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, int32_t pool, int32_t family, uint64_t &fixed,
                          uint64_t &per) {
+    const uint64_t un = (uint64_t)n, ud = (uint64_t)d;
     const int32_t P = std::min(13, K);
-    fixed = 4ull * (uint64_t)n * (uint64_t)d + 4ull * 64ull * (uint64_t)M * (uint64_t)d +
-            4ull * (uint64_t)pool * (uint64_t)d;
-    uint64_t fn = pool ? 4ull * (uint64_t)K : 4ull * (uint64_t)K * (uint64_t)d;
-    if (family == PF_FAMILY_FHTCP) {
+    const int32_t dpad = (d + 3) / 4 * 4;
+    int32_t hs, ls, rq, co;
+    plane_strides(dpad, &hs, &ls);
+    rows8_layout(dpad, &rq, &co);
+    const uint64_t kp = (uint64_t)((d + 15) / 16 * 16);
+    const uint64_t word = 32ull * (4ull * kp + 8ull); // hbf hi + lo, hcolrow, hbeta of 32 columns
+    const bool cp = family == PF_FAMILY_FHTCP;
+    fixed = 2ull * un * (uint64_t)(hs + std::max(ls, 1)) + un * (uint64_t)rq + (co == 0 ? 8ull * un : 0ull) +
+            4ull * 64ull * (uint64_t)M * ud + 4ull * (uint64_t)pool * ud +
+            (2ull * (uint64_t)M + (uint64_t)(pool / 32)) * word;
+    per = 16ull * un + 4ull * ((1ull << P) + 1ull);
+    if (cp) {
         int32_t dp, ell;
         cp_dims(d, dp, ell);
-        fn = (uint64_t)((K + ell - 1) / ell) * 3ull * (uint64_t)dp / 8ull;
+        fixed += 41ull * (uint64_t)(ell + 1) * 8ull;
+        per += (uint64_t)((K + ell - 1) / ell) * 3ull * (uint64_t)((dp + 31) / 32) * 4ull;
+    } else if (pool) {
+        per += 4ull * (uint64_t)K;
+    } else {
+        per += 4ull * (uint64_t)K * ud + word;
     }
-    per = 16ull * (uint64_t)n + 4ull * ((1ull << P) + 1ull) + fn;
 }
 
 // sign bit of coordinate c of rotation round k of cross-polytope function fn: the top bit
@@ -276,6 +297,18 @@ using namespace pf;
 PF_API const char *pf_last_error(void) { return g_err.c_str(); }
 PF_API const char *pf_version(void) { return "pfhip 0.1 (gfx950)"; }
 
+PF_API int pf_read_bandwidth(uint64_t bytes, int32_t reps, double *gbs, void *stream) {
+    return guard([&] {
+        PF_CHECK(gbs && bytes >= (1ull << 20) && reps >= 1, PF_EINVAL,
+                 "pf_read_bandwidth: need gbs, bytes >= 1 MiB and reps >= 1");
+        int dev = 0;
+        PF_HIP(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        PF_HIP(hipGetDeviceProperties(&prop, dev));
+        *gbs = pf::read_bandwidth_gbs(bytes, reps, prop.multiProcessorCount, as_stream(stream));
+    });
+}
+
 PF_API int32_t pf_tile_count(void) { return pf::search_tile_count(); }
 
 PF_API const char *pf_tile_name(int32_t t) { return pf::search_tile_name(t); }
@@ -300,36 +333,66 @@ PF_API int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_
     });
 }
 
+// Options with defaults filled in, checked, and the table count of the budget rule
+// (host only; shared by pf_plan_index and pf_build_index).
+struct BuildPlan {
+    pf_build_opts o;
+    int32_t K, M;
+    int64_t L;
+    uint64_t fixed, per;
+};
+
+static BuildPlan plan_build(int64_t n, int32_t d, uint64_t budget, const pf_build_opts *opts) {
+    PF_CHECK(n >= 1 && n < (1ll << 31), PF_EINVAL, "pf_build_index: n must be in [1, 2^31)");
+    PF_CHECK(d >= 1 && d <= PF_MAX_DIM, PF_EINVAL, "pf_build_index: d out of range");
+    BuildPlan b;
+    b.o = pf_build_opts{};
+    if (opts) b.o = *opts;
+    const pf_build_opts &o = b.o;
+    b.K = o.K ? o.K : 24;
+    b.M = o.M ? o.M : 32;
+    const int32_t K = b.K, M = b.M;
+    PF_CHECK(K >= 1 && K <= 32, PF_EINVAL, "pf_build_index: K must be in [1, 32]");
+    PF_CHECK(M >= 1 && M <= 64, PF_EINVAL, "pf_build_index: M must be in [1, 64]");
+    PF_CHECK(o.hash_mode == PF_HASH_BF16X3 || o.hash_mode == PF_HASH_FP64, PF_EINVAL,
+             "pf_build_index: bad hash_mode");
+    PF_CHECK(o.pool == 0 || (o.pool >= K && o.pool <= 65536 && o.pool % 32 == 0), PF_EINVAL,
+             "pf_build_index: pool must be 0 or a multiple of 32 in [K, 65536]");
+    PF_CHECK(o.family == PF_FAMILY_HP || o.family == PF_FAMILY_FHTCP, PF_EINVAL, "pf_build_index: bad family");
+    PF_CHECK(o.family == PF_FAMILY_HP || o.pool == 0, PF_EINVAL,
+             "pf_build_index: pooling is implemented for hyperplane functions");
+    budget_terms(n, d, K, M, o.pool, o.family, b.fixed, b.per);
+    int64_t L = o.L_override;
+    if (L <= 0) L = budget > b.fixed ? (int64_t)((budget - b.fixed) / b.per) : 0;
+    PF_CHECK(L >= 1, PF_EBUDGET, "pf_build_index: the memory budget holds no table");
+    L = std::min<int64_t>(L, PF_MAX_TABLES);
+    // table positions, and the search's entry counters (which run up to a chunk past a
+    // level's last entry), are 32-bit
+    PF_CHECK((uint64_t)L * (uint64_t)n < (1ull << 32) - (1ull << 16), PF_EUNSUPPORTED,
+             "pf_build_index: L * n must be below 2^32 - 2^16");
+    b.L = L;
+    return b;
+}
+
+PF_API int pf_plan_index(int64_t n, int32_t d, uint64_t budget, const pf_build_opts *opts, int32_t *L,
+                         uint64_t *bytes_device) {
+    return guard([&] {
+        const BuildPlan b = plan_build(n, d, budget, opts);
+        if (L) *L = (int32_t)b.L;
+        if (bytes_device) *bytes_device = b.fixed + (uint64_t)b.L * b.per;
+    });
+}
+
 PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t budget,
                           const pf_build_opts *opts, int32_t mem, void *stream, pf_index **out) {
     return guard([&] {
         PF_CHECK(out && points, PF_EINVAL, "pf_build_index: null argument");
-        PF_CHECK(n >= 1 && n < (1ll << 31), PF_EINVAL, "pf_build_index: n must be in [1, 2^31)");
-        PF_CHECK(d >= 1 && d <= PF_MAX_DIM, PF_EINVAL, "pf_build_index: d out of range");
         PF_CHECK(mem == PF_HOST || mem == PF_DEVICE, PF_EINVAL, "pf_build_index: bad mem");
-        pf_build_opts o{};
-        if (opts) o = *opts;
-        const int32_t K = o.K ? o.K : 24;
-        const int32_t M = o.M ? o.M : 32;
-        PF_CHECK(K >= 1 && K <= 32, PF_EINVAL, "pf_build_index: K must be in [1, 32]");
-        PF_CHECK(M >= 1 && M <= 64, PF_EINVAL, "pf_build_index: M must be in [1, 64]");
-        PF_CHECK(o.hash_mode == PF_HASH_BF16X3 || o.hash_mode == PF_HASH_FP64, PF_EINVAL,
-                 "pf_build_index: bad hash_mode");
-        PF_CHECK(o.pool == 0 || (o.pool >= K && o.pool <= 65536 && o.pool % 32 == 0), PF_EINVAL,
-                 "pf_build_index: pool must be 0 or a multiple of 32 in [K, 65536]");
-        PF_CHECK(o.family == PF_FAMILY_HP || o.family == PF_FAMILY_FHTCP, PF_EINVAL, "pf_build_index: bad family");
-        PF_CHECK(o.family == PF_FAMILY_HP || o.pool == 0, PF_EINVAL,
-                 "pf_build_index: pooling is implemented for hyperplane functions");
-        uint64_t fixed, per;
-        budget_terms(n, d, K, M, o.pool, o.family, fixed, per);
-        int64_t L = o.L_override;
-        if (L <= 0) L = budget > fixed ? (int64_t)((budget - fixed) / per) : 0;
-        PF_CHECK(L >= 1, PF_EBUDGET, "pf_build_index: the memory budget holds no table");
-        L = std::min<int64_t>(L, PF_MAX_TABLES);
-        // table positions, and the search's entry counters (which run up to a chunk past a
-        // level's last entry), are 32-bit
-        PF_CHECK((uint64_t)L * (uint64_t)n < (1ull << 32) - (1ull << 16), PF_EUNSUPPORTED,
-                 "pf_build_index: L * n must be below 2^32 - 2^16");
+        const BuildPlan bp = plan_build(n, d, budget, opts);
+        const pf_build_opts &o = bp.o;
+        const int32_t K = bp.K, M = bp.M;
+        const int64_t L = bp.L;
+        const uint64_t fixed = bp.fixed, per = bp.per;
 
         auto ix = std::make_unique<pf_index>();
         hipStream_t s = as_stream(stream);
@@ -519,42 +582,43 @@ static TuneChoice autotune(Index &ix, SearchArgs a, int32_t kmax, hipStream_t s)
     const int64_t sample = std::min<int64_t>(a.m, 8192);
     a.qstride = a.m; // query codes were computed for the whole batch
     a.m = sample;    // time the first queries of the batch (in queue order)
-    TuneChoice best, best_default;
-    best.us_per_query = best_default.us_per_query = 1e300;
     hipEvent_t e0, e1;
     PF_HIP(hipEventCreate(&e0));
     PF_HIP(hipEventCreate(&e1));
     const int32_t nl = ix.K - ix.P;
-    for (int32_t t = 0; t < search_tile_count(); ++t) {
-        const int32_t wmax = search_waves_per_cu(ix, kmax, t);
-        for (int32_t w : {wmax, std::max(1, (3 * wmax) / 4), std::max(1, wmax / 2)}) {
-            a.tile = t;
-            a.waves_per_cu = w;
-            launch_search(ix, a, nl > 0 ? ix.ranges.as<uint32_t>() : nullptr, s); // warm-up
-            // the faster of two timed launches (one launch's time varies by a few percent)
-            float best_ms = 0;
-            for (int rep = 0; rep < 2; ++rep) {
-                PF_HIP(hipEventRecord(e0, s));
-                launch_search(ix, a, nl > 0 ? ix.ranges.as<uint32_t>() : nullptr, s);
-                PF_HIP(hipEventRecord(e1, s));
-                PF_HIP(hipEventSynchronize(e1));
-                float ms = 0;
-                PF_HIP(hipEventElapsedTime(&ms, e0, e1));
-                best_ms = rep == 0 ? ms : std::min(best_ms, ms);
-            }
-            const double us = best_ms * 1e3 / (double)sample;
-            if (us < best.us_per_query) {
-                best.tile = t;
-                best.waves = w;
-                best.us_per_query = us;
-            }
-            if (t == search_default_tile() && w == wmax) { // the default: shape and occupancy limit
-                best_default.tile = t;
-                best_default.waves = w;
-                best_default.us_per_query = us;
-            }
-            if (w == 1) break;
+    const uint32_t *rg = nl > 0 ? ix.ranges.as<uint32_t>() : nullptr;
+    // microseconds per query of shape t at w resident waves per CU: the faster of two timed
+    // launches after a warm-up (one launch's time varies by a few percent)
+    auto time_of = [&](int32_t t, int32_t w) {
+        a.tile = t;
+        a.waves_per_cu = w;
+        launch_search(ix, a, rg, s);
+        float best_ms = 0;
+        for (int rep = 0; rep < 2; ++rep) {
+            PF_HIP(hipEventRecord(e0, s));
+            launch_search(ix, a, rg, s);
+            PF_HIP(hipEventRecord(e1, s));
+            PF_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            PF_HIP(hipEventElapsedTime(&ms, e0, e1));
+            best_ms = rep == 0 ? ms : std::min(best_ms, ms);
         }
+        return best_ms * 1e3 / (double)sample;
+    };
+    // every shape at its occupancy limit, then lower occupancy caps for the fastest shape
+    TuneChoice best, best_default;
+    best.us_per_query = 1e300;
+    for (int32_t t = 0; t < search_tile_count(); ++t) {
+        const int32_t w = search_waves_per_cu(ix, kmax, t);
+        const double us = time_of(t, w);
+        if (us < best.us_per_query) best = TuneChoice{t, w, us};
+        if (t == search_default_tile()) best_default = TuneChoice{t, w, us}; // the default
+    }
+    const int32_t wmax = best.waves;
+    for (int32_t w : {(3 * wmax) / 4, wmax / 2}) {
+        if (w < 1 || w == wmax) continue;
+        const double us = time_of(best.tile, w);
+        if (us < best.us_per_query) best = TuneChoice{best.tile, w, us};
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -191,9 +191,16 @@ void rows8_layout(int32_t dpad, int32_t *rq, int32_t *co);
 void launch_rows8(const float *X, int64_t n, int32_t dpad, uint8_t *out, uint8_t *hdr, uint32_t *gmax,
                   hipStream_t s);
 
-// hashing of rows X (n x dpad) into code words; see k_hash.hip
+// best rate (GB/s) of `reps` launches of a read-only streaming kernel over `bytes` bytes
+double read_bandwidth_gbs(uint64_t bytes, int32_t reps, int32_t num_cus, hipStream_t s);
+
+// hashing of rows X (n x dpad) into code words; see k_hash.hip.  hash_rows grows `scratch`
+// to hash_scratch_bytes(ix, n); hash_rows_into takes a device scratch of that size
 void hash_rows(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
                DevBuf &scratch, hipStream_t s);
+size_t hash_scratch_bytes(const Index &ix, int64_t n);
+void hash_rows_into(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint64_t *sketches,
+                    char *scratch, hipStream_t s);
 
 // sorting and derived tables; see k_sort.hip
 void sort_tables(const uint32_t *codes, int64_t n, int32_t L, int32_t K, uint32_t *tcode,
@@ -226,6 +233,9 @@ struct SearchArgs {
     pf_query_stats *stats; // m (nullable)
 };
 void launch_ranges(Index &ix, const SearchArgs &a, uint32_t *ranges, hipStream_t s);
+// the same with the list of large prefix buckets in rlist (ranges_list_bytes(m, L) bytes)
+size_t ranges_list_bytes(int64_t m, int32_t L);
+void launch_ranges_into(const Index &ix, const SearchArgs &a, uint32_t *ranges, uint32_t *rlist, hipStream_t s);
 void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, int32_t rule, int32_t L,
                         int32_t M, int32_t K, int32_t pool, const double *cptab, int32_t ell, float *tauv,
                         float *stopw, hipStream_t s);

@@ -103,3 +103,38 @@ def test_bench_algorithmic_bytes_formula():
     for d, hdr in ((100, 8), (120, 8), (124, 0), (128, 0), (200, 8), (256, 0)):
         want = 8 * 1000 + 4 * 50 + (hdr + d) * 40 + 2 * d * (5 + 2) + 4 * d + 8 * k + 8 * L * (K + 1 - 3)
         assert bench.algorithmic_bytes(st, d, k, L, K) == want, d
+
+
+def test_plan_index_charges_every_resident_byte():
+    """The budget rule as pf_build_index applies it, evaluated on the host (no device):
+    L is the largest table count whose device bytes fit the budget; one more table
+    would not fit; each table adds its sorted arrays, prefix table, K hyperplanes and
+    their BF16 GEMM word (32 columns of kp = ceil(d/16)*16 hi + lo BF16 values, a row
+    index and a flag bound each); the index holds at least what the paper's count covers
+    (vectors, functions, tables), so L never exceeds the oracle's count."""
+    import oracle
+
+    cases = [(10_000, 64, 64 << 20, 299), (1_000_000, 100, 2 << 30, 100), (1_000_000, 256, 2 << 30, 53),
+             (10_000_000, 128, 16 << 30, 66), (1_000_000, 300, 2 << 30, 34)]
+    for n, d, budget, want_L in cases:
+        L, nbytes = pf.pf_plan_index(n, d, budget)
+        assert L == want_L, (n, d)
+        assert nbytes <= budget
+        L1, nbytes1 = pf.pf_plan_index(n, d, budget, L=L + 1)
+        assert L1 == L + 1 and nbytes1 > budget
+        kp = (d + 15) // 16 * 16
+        per = 16 * n + 4 * ((1 << 13) + 1) + 4 * 24 * d + 32 * (4 * kp + 8)
+        assert nbytes1 - nbytes == per
+        paper_fixed = 4 * n * d + 4 * 64 * 32 * d
+        assert nbytes - L * per >= paper_fixed + n * d  # + at least one byte per coordinate of summaries
+        assert L <= oracle.num_tables(n, d, budget)
+    # pooled and cross-polytope indexes fit their budgets too
+    for kw in (dict(pool=3072), dict(family=pf.PF_FAMILY_FHTCP)):
+        L, nbytes = pf.pf_plan_index(1_000_000, 100, 2 << 30, **kw)
+        assert 1 <= L and nbytes <= 2 << 30 < pf.pf_plan_index(1_000_000, 100, 2 << 30, L=L + 1, **kw)[1]
+    with pytest.raises(pf.PfError) as e:
+        pf.pf_plan_index(1_000_000, 100, 100 << 20)
+    assert e.value.code == pf.PF_EBUDGET
+    with pytest.raises(pf.PfError) as e:
+        pf.pf_plan_index(0, 100, 2 << 30)
+    assert e.value.code == pf.PF_EINVAL

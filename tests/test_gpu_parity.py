@@ -96,10 +96,14 @@ def test_hash_queries_bit_exact():
 
 
 def test_config1_parity():
-    """gauss-10k-d64, 64 MiB budget -> L = 321, 1000 queries, k = 10, recall .9"""
+    """gauss-10k-d64, 64 MiB budget -> L = 299 (every resident byte charged), 1000 queries,
+    k = 10, recall .9; the index's device bytes are the planned ones and fit the budget"""
     c = workloads.config(1)
     g, o = _build_both(c["points"], budget=c["budget"])
-    assert g.L == 321
+    assert g.L == 299
+    info = g.info()
+    assert info.bytes_device == info.bytes_budget_rule == pf.pf_plan_index(10_000, 64, c["budget"])[1]
+    assert info.bytes_device <= c["budget"]
     _assert_index_equal(g, o)
     gr = g.search(c["queries"], 10, 0.9)
     orr = o.search(c["queries"], 10, 0.9)
@@ -505,7 +509,9 @@ def test_pool_search_parity():
         _assert_search_equal(g.search(Q, k, rec, **kw), o.search(Q, k, rec, **okw), f"pool k={k} {kw}")
     # the pooled budget rule, and the POOL rule refused on an index without a pool
     gb = pf.Index(X, 64 << 20, seed=63, pool=3072)
-    assert gb.L == oracle.num_tables(len(X), 48, 64 << 20, pool=3072)
+    info = gb.info()
+    assert (gb.L, info.bytes_device) == pf.pf_plan_index(len(X), 48, 64 << 20, pool=3072)
+    assert info.bytes_device <= 64 << 20 and gb.L <= oracle.num_tables(len(X), 48, 64 << 20, pool=3072)
     plain = pf.Index(X[:500], 0, L=4)
     with pytest.raises(pf.PfError):
         plain.search(Q[:5], 5, 0.9, rule=pf.PF_RULE_POOL)
@@ -542,7 +548,9 @@ def test_cp_search_parity():
     with pytest.raises(pf.PfError):
         g.search(Q[:4], 5, 0.9, rule=pf.PF_RULE_POOL)
     gb = pf.Index(X, 64 << 20, seed=73, family=pf.PF_FAMILY_FHTCP)
-    assert gb.L == oracle.num_tables(len(X), 100, 64 << 20, cp=True)
+    info = gb.info()
+    assert (gb.L, info.bytes_device) == pf.pf_plan_index(len(X), 100, 64 << 20, family=pf.PF_FAMILY_FHTCP)
+    assert info.bytes_device <= 64 << 20 and gb.L <= oracle.num_tables(len(X), 100, 64 << 20, cp=True)
 
 
 def test_edge_cases():
