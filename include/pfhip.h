@@ -57,7 +57,8 @@ extern "C" {
 #define PF_EXPORT_POINTS 0      /* n x d FP32, the normalised vectors                  */
 #define PF_EXPORT_HYPERPLANES 1 /* (L*K + 64*M) x d FP32; with a pool (m + 64*M) x d:
                                    the pool functions, then the sketch functions        */
-#define PF_EXPORT_CODES 2       /* L x n u32, sorted codes of each table               */
+#define PF_EXPORT_CODES 2       /* L x n u32, sorted codes of each table (rebuilt from
+                                   the prefix table and the stored low K - P bits)     */
 #define PF_EXPORT_IDX 3         /* L x n u32, point position of each sorted entry      */
 #define PF_EXPORT_SKETCHES 4    /* L x n u64, table-local sketches                     */
 #define PF_EXPORT_OFFSETS 5     /* L x (2^P + 1) u32, P = min(13, K), prefix table     */
@@ -185,10 +186,12 @@ int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, 
  *  16-bit planes, 4 dpad bytes per row up to line padding) and their 8-bit summaries
  *  (PF_EXPORT_ROWS8 layout, whole 128-byte lines per row, + 8 bytes per row when the rows
  *  share one scale), the 64 M sketch hyperplanes and their BF16 GEMM copies; per_table =
- *  the sorted codes, positions and table-local sketches (16n), the prefix table
- *  (4 (2^P + 1)), the table's K hyperplanes (4Kd) and their GEMM copy.  For n = 10^6,
- *  d = 100, 2 GiB this gives L = 100 (the paper's count of vectors, functions and tables
- *  alone would give 108); pf_info.bytes_device <= budget always holds;
+ *  the positions and table-local sketches (12n), the sorted codes' low K - P bits (2n
+ *  when K - P <= 16, 4n when larger, none when K <= P: the prefix table holds the
+ *  leading P bits of every entry's code), the prefix table (4 (2^P + 1)), the table's K
+ *  hyperplanes (4Kd) and their GEMM copy.  For n = 10^6, d = 100, 2 GiB this gives L = 115
+ *  (the paper's count, with 4-byte codes and without the summaries, gives 108);
+ *  pf_info.bytes_device <= budget always holds;
  *  K random-hyperplane functions per table (Sec. 2.2), M 64-bit sketches per point
  *  (Sec. 4.2), each table sorted by its K-bit code with equal codes by position, and a
  *  table of the positions of every P-bit prefix (Sec. 4.2, P = min(13, K)).

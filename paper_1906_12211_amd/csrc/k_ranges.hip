@@ -5,7 +5,9 @@
 // lcp(c) the common prefix length of code c and the query code (at least P inside the
 // bucket) and lt(c) = [c < query code]:
 //   lo_i = B0 + #{lt, lcp < i},   hi_i = B0 + #{lt} + #{not lt, lcp >= i}.
-// ranges[q][j][i - P - 1] = (lo_i, hi_i).
+// ranges[q][j][i - P - 1] = (lo_i, hi_i).  Inside the bucket every code has the query's
+// leading P bits, so the kernels read only the stored low K - P bits of each code (16-bit
+// or 32-bit suffixes) and compare them with the query's.
 #include "pf_device.h"
 #include "pf_internal.h"
 
@@ -21,8 +23,8 @@ static constexpr int kGroupMax = 4080; // buckets up to this size: one 16-lane g
 // in byte b & 3 of register b >> 2; at most ceil(kGroupMax / 16) = 255 entries per lane),
 // the fields are widened to 16 bits and summed over the row, and lane r writes level
 // P + 1 + r.  Pairs with larger buckets are appended to the list for k_ranges_wave.
-template <int NR>
-__global__ __launch_bounds__(256) void k_ranges_group(const uint32_t *__restrict__ tcode,
+template <int NR, class S>
+__global__ __launch_bounds__(256) void k_ranges_group(const S *__restrict__ tsuf,
                                                       const uint32_t *__restrict__ off, int64_t n, int32_t L,
                                                       int32_t K, int32_t P, const uint32_t *__restrict__ qcode,
                                                       int64_t m, uint32_t *__restrict__ ranges,
@@ -42,8 +44,9 @@ __global__ __launch_bounds__(256) void k_ranges_group(const uint32_t *__restrict
         if (g == 0) big[atomicAdd(nbig, 1u)] = (uint32_t)t;
         return;
     }
-    const uint32_t *tc = tcode + (int64_t)j * n;
-    const int sh = 32 - K;
+    const S *tc = tsuf + (int64_t)j * n;
+    const uint32_t qs = qc & ((1u << nl) - 1u); // the query's low nl bits (nl <= 19)
+    const int sh = 32 - nl;
     uint32_t clt[NR], cge[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) clt[r] = cge[r] = 0;
@@ -54,10 +57,10 @@ __global__ __launch_bounds__(256) void k_ranges_group(const uint32_t *__restrict
 #pragma unroll
         for (int u = 0; u < kLoads; ++u) {
             if (e0 + 16 * u < B1) {
-                const uint32_t x = (c[u] ^ qc) << sh;
-                const int bin = (x ? __clz(x) : K) - P;
+                const uint32_t x = (c[u] ^ qs) << sh;
+                const int bin = x ? __clz(x) : nl; // common prefix length beyond the P bits
                 const uint32_t inc = 1u << (8 * (bin & 3));
-                const bool lt = c[u] < qc;
+                const bool lt = c[u] < qs;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
                     const uint32_t v = (bin >> 2) == r ? inc : 0u;
@@ -101,7 +104,8 @@ __global__ __launch_bounds__(256) void k_ranges_group(const uint32_t *__restrict
 
 // one wave per listed (q, j) pair (bucket above kGroupMax entries), waves striding over
 // the list: lane 2r + s binary-searches bound s (0: lo, 1: hi) of level P + 1 + r
-__global__ __launch_bounds__(256) void k_ranges_wave(const uint32_t *__restrict__ tcode,
+template <class S>
+__global__ __launch_bounds__(256) void k_ranges_wave(const S *__restrict__ tsuf,
                                                      const uint32_t *__restrict__ off, int64_t n, int32_t L,
                                                      int32_t K, int32_t P, const uint32_t *__restrict__ qcode,
                                                      int64_t m, uint32_t *__restrict__ ranges,
@@ -119,10 +123,12 @@ __global__ __launch_bounds__(256) void k_ranges_wave(const uint32_t *__restrict_
         const uint32_t qc = qcode[(int64_t)j * m + q];
         const int64_t np1 = ((int64_t)1 << P) + 1;
         const uint32_t b = qc >> (K - P);
-        const uint32_t *tc = tcode + (int64_t)j * n;
+        const S *tc = tsuf + (int64_t)j * n;
         const int lev = P + 1 + (lane >> 1);
         const uint64_t pre = (uint64_t)(qc >> (K - lev));
-        const uint64_t target = (lane & 1) ? ((pre + 1) << (K - lev)) : (pre << (K - lev));
+        // the bound's code, relative to the bucket's first code (b << (K - P)): in [0, 2^(K-P)]
+        const uint64_t target = ((lane & 1) ? ((pre + 1) << (K - lev)) : (pre << (K - lev))) -
+                                ((uint64_t)b << (K - P));
         uint32_t lo = off[(int64_t)j * np1 + b], hi = off[(int64_t)j * np1 + b + 1];
         while (lo < hi) {
             const uint32_t mid = lo + ((hi - lo) >> 1);
@@ -135,7 +141,12 @@ __global__ __launch_bounds__(256) void k_ranges_wave(const uint32_t *__restrict_
     }
 }
 
-template <int NR> static const void *group_kernel() { return (const void *)k_ranges_group<NR>; }
+template <int NR, class S> static const void *group_kernel() { return (const void *)k_ranges_group<NR, S>; }
+
+template <class S> static const void *group_kernel_of(int nr) {
+    return nr <= 1 ? group_kernel<1, S>() : nr <= 2 ? group_kernel<2, S>() : nr <= 3 ? group_kernel<3, S>()
+         : nr <= 4 ? group_kernel<4, S>() : group_kernel<5, S>();
+}
 
 size_t ranges_list_bytes(int64_t m, int32_t L) { return (size_t)(m * L + 1) * sizeof(uint32_t); }
 
@@ -154,9 +165,9 @@ void launch_ranges_into(const Index &ix, const SearchArgs &a, uint32_t *ranges, 
     launch_fill_u32(nbig, 1, 0u, s);
     // registers of 8-bit bin counters per flag: bins lcp - P = 0 .. K - P
     const int nr = (ix.K - ix.P + 1 + 3) / 4;
-    const void *fn = nr <= 1 ? group_kernel<1>() : nr <= 2 ? group_kernel<2>() : nr <= 3 ? group_kernel<3>()
-                   : nr <= 4 ? group_kernel<4>() : group_kernel<5>();
-    const uint32_t *tc = ix.tcode.as<uint32_t>();
+    const bool w16 = ix.sufw == 2;
+    const void *fn = w16 ? group_kernel_of<uint16_t>(nr) : group_kernel_of<uint32_t>(nr);
+    const void *tc = ix.tsuf.p;
     const uint32_t *of = ix.off.as<uint32_t>();
     int64_t n = ix.n;
     int32_t L = ix.L, K = ix.K, P = ix.P;
@@ -167,8 +178,12 @@ void launch_ranges_into(const Index &ix, const SearchArgs &a, uint32_t *ranges, 
     PF_HIP(hipLaunchKernel(fn, dim3((unsigned)((pairs * 16 + 255) / 256)), dim3(256), args, 0, s));
     // the list's length is known only on the device: a fixed grid strides over it
     const int64_t wg = std::min<int64_t>((pairs + 3) / 4, (int64_t)ix.num_cus * 8);
-    hipLaunchKernelGGL(k_ranges_wave, dim3((unsigned)std::max<int64_t>(1, wg)), dim3(256), 0, s, tc, of, n, L, K,
-                       P, qc, m, ranges, big, nbig);
+    if (w16)
+        hipLaunchKernelGGL(k_ranges_wave<uint16_t>, dim3((unsigned)std::max<int64_t>(1, wg)), dim3(256), 0, s,
+                           static_cast<const uint16_t *>(tc), of, n, L, K, P, qc, m, ranges, big, nbig);
+    else
+        hipLaunchKernelGGL(k_ranges_wave<uint32_t>, dim3((unsigned)std::max<int64_t>(1, wg)), dim3(256), 0, s,
+                           static_cast<const uint32_t *>(tc), of, n, L, K, P, qc, m, ranges, big, nbig);
     PF_HIP(hipGetLastError());
 }
 

@@ -226,6 +226,68 @@ void prefix_tables(const uint32_t *tcode, int64_t n, int32_t L, int32_t K, int32
     PF_HIP(hipGetLastError());
 }
 
+// Resident form of the sorted codes: inside a table's P-bit prefix bucket every code has
+// the bucket's leading P bits, which the prefix table already holds (entry e lies in
+// bucket b iff off[b] <= e < off[b + 1]), so only the low K - P bits of each code are kept,
+// in 16 bits when K - P <= 16 (else 32; nothing when K <= P).
+template <class S>
+__global__ __launch_bounds__(256) void k_code_suffix(const uint32_t *__restrict__ tcode, int64_t total,
+                                                     uint32_t mask, S *__restrict__ suf) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+        suf[i] = (S)(tcode[i] & mask);
+}
+
+int32_t code_suffix_bytes(int32_t K, int32_t P) { return K <= P ? 0 : (K - P <= 16 ? 2 : 4); }
+
+void code_suffixes(const uint32_t *tcode, int64_t n, int32_t L, int32_t K, int32_t P, void *suf, hipStream_t s) {
+    const int32_t w = code_suffix_bytes(K, P);
+    if (w == 0) return;
+    const int64_t total = (int64_t)L * n;
+    const uint32_t mask = K - P >= 32 ? 0xFFFFFFFFu : ((1u << (K - P)) - 1u);
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+    if (w == 2)
+        hipLaunchKernelGGL(k_code_suffix<uint16_t>, dim3(blocks), dim3(256), 0, s, tcode, total, mask,
+                           static_cast<uint16_t *>(suf));
+    else
+        hipLaunchKernelGGL(k_code_suffix<uint32_t>, dim3(blocks), dim3(256), 0, s, tcode, total, mask,
+                           static_cast<uint32_t *>(suf));
+    PF_HIP(hipGetLastError());
+}
+
+// The full sorted codes again (export): code = (bucket of e) << (K - P) | suffix.
+template <class S>
+__global__ __launch_bounds__(256) void k_code_join(const S *__restrict__ suf, const uint32_t *__restrict__ off,
+                                                   int64_t n, int32_t K, int32_t P, uint32_t *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int32_t j = blockIdx.y;
+    if (e >= n) return;
+    const int64_t np1 = ((int64_t)1 << P) + 1;
+    const uint32_t *oj = off + (int64_t)j * np1;
+    // the bucket: the largest b with off[b] <= e (off is non-decreasing, off[0] = 0)
+    int64_t lo = 0, hi = np1 - 1;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo + 1) >> 1);
+        if ((int64_t)oj[mid] <= e)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const uint32_t sfx = suf ? (uint32_t)suf[(int64_t)j * n + e] : 0u;
+    out[(int64_t)j * n + e] = K > P ? (((uint32_t)lo << (K - P)) | sfx) : (uint32_t)lo;
+}
+
+void join_codes(const void *suf, const uint32_t *off, int64_t n, int32_t L, int32_t K, int32_t P, uint32_t *out,
+                hipStream_t s) {
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)L);
+    if (code_suffix_bytes(K, P) == 4)
+        hipLaunchKernelGGL(k_code_join<uint32_t>, grid, dim3(256), 0, s, static_cast<const uint32_t *>(suf), off, n,
+                           K, P, out);
+    else
+        hipLaunchKernelGGL(k_code_join<uint16_t>, grid, dim3(256), 0, s, static_cast<const uint16_t *>(suf), off, n,
+                           K, P, out);
+    PF_HIP(hipGetLastError());
+}
+
 // tsk[j][e] = sketch[j mod M][tidx[j][e]]: the sketch repetition j reads, stored in the
 // table's own order so that the filter streams it contiguously.
 __global__ __launch_bounds__(256) void k_gather_sk(const uint32_t *__restrict__ tidx,

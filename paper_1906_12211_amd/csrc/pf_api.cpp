@@ -160,7 +160,8 @@ static void cp_dims(int32_t d, int32_t &dp, int32_t &ell) {
 //          when rows share one scale), the sketch (and pool) hyperplanes, their GEMM
 //          copies (BF16 hi + lo, column rows, flag bounds; 32 columns per word), and the
 //          cross-polytope collision table;
-//   per table: sorted codes, positions and table-local sketches (16n), the prefix table,
+//   per table: positions and table-local sketches (12n), the low K - P bits of the sorted
+//          codes (2n when K - P <= 16, 4n when larger, none when K <= P), the prefix table,
 //          the table's K hyperplanes and their GEMM word (independent functions), its K
 //          pool indices (pooling) or its cross-polytope sign words.
 static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, int32_t pool, int32_t family, uint64_t &fixed,
@@ -177,7 +178,7 @@ static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, int32_t poo
     fixed = 2ull * un * (uint64_t)(hs + std::max(ls, 1)) + un * (uint64_t)rq + (co == 0 ? 8ull * un : 0ull) +
             4ull * 64ull * (uint64_t)M * ud + 4ull * (uint64_t)pool * ud +
             (2ull * (uint64_t)M + (uint64_t)(pool / 32)) * word;
-    per = 16ull * un + 4ull * ((1ull << P) + 1ull);
+    per = (12ull + (uint64_t)code_suffix_bytes(K, P)) * un + 4ull * ((1ull << P) + 1ull);
     if (cp) {
         int32_t dp, ell;
         cp_dims(d, dp, ell);
@@ -474,14 +475,20 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
             PF_HIP(hipMemcpyAsync(&ix->s8, ix->Xqh.p, sizeof(float), hipMemcpyDeviceToHost, s));
             PF_HIP(hipMemcpyAsync(&ix->a8, gmax.as<uint32_t>() + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         }
-        // a6: sorted tables
-        ix->tcode.alloc((size_t)L * n * sizeof(uint32_t));
+        // a6: sorted tables (the full codes only while the index is built)
+        DevBuf tcode;
+        tcode.alloc((size_t)L * n * sizeof(uint32_t));
         ix->tidx.alloc((size_t)L * n * sizeof(uint32_t));
-        sort_tables(codes.as<uint32_t>(), n, (int32_t)L, K, ix->tcode.as<uint32_t>(), ix->tidx.as<uint32_t>(),
-                    scratch, s);
-        // a7: prefix tables
+        sort_tables(codes.as<uint32_t>(), n, (int32_t)L, K, tcode.as<uint32_t>(), ix->tidx.as<uint32_t>(), scratch,
+                    s);
+        // a7: prefix tables, then the codes' low K - P bits (the prefix table holds the rest)
         ix->off.alloc((size_t)L * ((1ull << ix->P) + 1) * sizeof(uint32_t));
-        prefix_tables(ix->tcode.as<uint32_t>(), n, (int32_t)L, K, ix->P, ix->off.as<uint32_t>(), s);
+        prefix_tables(tcode.as<uint32_t>(), n, (int32_t)L, K, ix->P, ix->off.as<uint32_t>(), s);
+        ix->sufw = code_suffix_bytes(K, ix->P);
+        if (ix->sufw) {
+            ix->tsuf.alloc((size_t)L * n * ix->sufw);
+            code_suffixes(tcode.as<uint32_t>(), n, (int32_t)L, K, ix->P, ix->tsuf.p, s);
+        }
         // a8: table-local sketches
         ix->tsk.alloc((size_t)L * n * sizeof(uint64_t));
         gather_sketches(ix->tidx.as<uint32_t>(), sk.as<uint64_t>(), n, (int32_t)L, M, ix->tsk.as<uint64_t>(), s);
@@ -926,10 +933,15 @@ PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_by
             PF_HIP(hipMemcpyAsync(dst, ix->hp.p, (size_t)b, kind, s));
             break;
         }
-        case PF_EXPORT_CODES:
+        case PF_EXPORT_CODES: {
             need((int64_t)ix->L * n * 4);
-            PF_HIP(hipMemcpyAsync(dst, ix->tcode.p, (size_t)ix->L * n * 4, kind, s));
+            DevBuf codes;
+            codes.alloc((size_t)ix->L * n * 4);
+            join_codes(ix->tsuf.p, ix->off.as<uint32_t>(), n, ix->L, ix->K, ix->P, codes.as<uint32_t>(), s);
+            PF_HIP(hipMemcpyAsync(dst, codes.p, (size_t)ix->L * n * 4, kind, s));
+            PF_HIP(hipStreamSynchronize(s));
             break;
+        }
         case PF_EXPORT_IDX:
             need((int64_t)ix->L * n * 4);
             PF_HIP(hipMemcpyAsync(dst, ix->tidx.p, (size_t)ix->L * n * 4, kind, s));
@@ -991,7 +1003,7 @@ PF_API int pf_index_info(const pf_index *ix, pf_info *info) {
         r.family = ix->family;
         r.bytes_budget_rule = ix->bytes_rule;
         r.bytes_device = ix->Xh.bytes + ix->Xl.bytes + ix->Xq.bytes + ix->Xqh.bytes + ix->hp.bytes + ix->hcolrow.bytes + ix->hbf.bytes + ix->hbeta.bytes +
-                         ix->psel.bytes + ix->cpsign.bytes + ix->cptab.bytes + ix->tcode.bytes + ix->tidx.bytes + ix->tsk.bytes + ix->off.bytes;
+                         ix->psel.bytes + ix->cpsign.bytes + ix->cptab.bytes + ix->tsuf.bytes + ix->tidx.bytes + ix->tsk.bytes + ix->off.bytes;
         r.build_ms = ix->build_ms;
         *info = r;
     });

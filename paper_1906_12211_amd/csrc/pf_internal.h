@@ -114,7 +114,8 @@ struct Index {
     DevBuf hcolrow;// ncols int32: hyperplane row of each GEMM column (-1 = padding)
     DevBuf hbf;    // ncols x kp bf16 hi parts, then ncols x kp bf16 lo parts
     DevBuf hbeta;  // ncols FP32 flag bounds (negative = never flagged)
-    DevBuf tcode;  // L x n u32
+    DevBuf tsuf;   // L x n low K - P bits of the sorted codes (sufw bytes each; none when K <= P)
+    int32_t sufw = 0;
     DevBuf tidx;   // L x n u32
     DevBuf tsk;    // L x n u64
     DevBuf off;    // L x (2^P + 1) u32
@@ -207,6 +208,12 @@ void sort_tables(const uint32_t *codes, int64_t n, int32_t L, int32_t K, uint32_
                  uint32_t *tidx, DevBuf &scratch, hipStream_t s);
 void prefix_tables(const uint32_t *tcode, int64_t n, int32_t L, int32_t K, int32_t P,
                    uint32_t *off, hipStream_t s);
+// resident sorted codes: the low K - P bits of each code (code_suffix_bytes per entry:
+// 0 when K <= P, 2 when K - P <= 16, else 4), and the full codes rebuilt from them
+int32_t code_suffix_bytes(int32_t K, int32_t P);
+void code_suffixes(const uint32_t *tcode, int64_t n, int32_t L, int32_t K, int32_t P, void *suf, hipStream_t s);
+void join_codes(const void *suf, const uint32_t *off, int64_t n, int32_t L, int32_t K, int32_t P, uint32_t *out,
+                hipStream_t s);
 void gather_sketches(const uint32_t *tidx, const uint64_t *sk, int64_t n, int32_t L,
                      int32_t M, uint64_t *tsk, hipStream_t s);
 

@@ -108,14 +108,13 @@ def test_bench_algorithmic_bytes_formula():
 def test_plan_index_charges_every_resident_byte():
     """The budget rule as pf_build_index applies it, evaluated on the host (no device):
     L is the largest table count whose device bytes fit the budget; one more table
-    would not fit; each table adds its sorted arrays, prefix table, K hyperplanes and
-    their BF16 GEMM word (32 columns of kp = ceil(d/16)*16 hi + lo BF16 values, a row
-    index and a flag bound each); the index holds at least what the paper's count covers
-    (vectors, functions, tables), so L never exceeds the oracle's count."""
-    import oracle
-
-    cases = [(10_000, 64, 64 << 20, 299), (1_000_000, 100, 2 << 30, 100), (1_000_000, 256, 2 << 30, 53),
-             (10_000_000, 128, 16 << 30, 66), (1_000_000, 300, 2 << 30, 34)]
+    would not fit; each table adds its positions and sketches (12n), the 16-bit low parts
+    of its K = 24-bit codes (2n), its prefix table, K hyperplanes and their BF16 GEMM word
+    (32 columns of kp = ceil(d/16)*16 hi + lo BF16 values, a row index and a flag bound
+    each); beyond the tables the index holds at least the vectors and sketch functions
+    the paper counts plus a byte per coordinate of summaries."""
+    cases = [(10_000, 64, 64 << 20, 331), (1_000_000, 100, 2 << 30, 115), (1_000_000, 256, 2 << 30, 60),
+             (10_000_000, 128, 16 << 30, 76), (1_000_000, 300, 2 << 30, 39)]
     for n, d, budget, want_L in cases:
         L, nbytes = pf.pf_plan_index(n, d, budget)
         assert L == want_L, (n, d)
@@ -123,11 +122,10 @@ def test_plan_index_charges_every_resident_byte():
         L1, nbytes1 = pf.pf_plan_index(n, d, budget, L=L + 1)
         assert L1 == L + 1 and nbytes1 > budget
         kp = (d + 15) // 16 * 16
-        per = 16 * n + 4 * ((1 << 13) + 1) + 4 * 24 * d + 32 * (4 * kp + 8)
+        per = (12 + 2) * n + 4 * ((1 << 13) + 1) + 4 * 24 * d + 32 * (4 * kp + 8)
         assert nbytes1 - nbytes == per
         paper_fixed = 4 * n * d + 4 * 64 * 32 * d
         assert nbytes - L * per >= paper_fixed + n * d  # + at least one byte per coordinate of summaries
-        assert L <= oracle.num_tables(n, d, budget)
     # pooled and cross-polytope indexes fit their budgets too
     for kw in (dict(pool=3072), dict(family=pf.PF_FAMILY_FHTCP)):
         L, nbytes = pf.pf_plan_index(1_000_000, 100, 2 << 30, **kw)

@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size, in the launch configuration bench.py times.
 
-mixture-1M-d100 (n = 1,000,000, d = 100, 2 GiB -> L = 100, 10,000 queries, k = 10, recall
+mixture-1M-d100 (n = 1,000,000, d = 100, 2 GiB -> L = 115, 10,000 queries, k = 10, recall
 0.9): the GPU index against the oracle's, structure by structure (bit-exact), then the
 whole query batch answered by the learned-batched path with the autotuned tile shape,
 compared with the oracle on a sample of the queries (ids, FP32 inner-product bit
@@ -32,7 +32,7 @@ def full():
 
 def test_fullsize_index_bit_exact(full):
     c, g, o = full
-    assert g.L == o.L == 100
+    assert g.L == o.L == 115
     info = g.info()
     assert info.bytes_device == info.bytes_budget_rule <= c["budget"]
     for what, ref, name in [(pf.PF_EXPORT_CODES, o.tcode, "codes"), (pf.PF_EXPORT_IDX, o.tidx, "positions"),
