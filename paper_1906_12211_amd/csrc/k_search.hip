@@ -269,10 +269,15 @@ __device__ __forceinline__ float row_sum16(float s) {
     return s;
 }
 
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-// c + a.lo * b.lo + a.hi * b.hi on bfloat16 pairs (v_dot2c_f32_bf16)
+// (c + a.lo * b.lo) + a.hi * b.hi on bfloat16 pairs in IEEE FP32: a bfloat16 widens to
+// FP32 exactly, the product of two has at most 16 significant bits and is exact (unless
+// it underflows), and each addition rounds to nearest (the library is built without
+// multiply-add contraction), so the error of a chain of such steps follows from the
+// documented FP32 rounding alone
 __device__ __forceinline__ float dot2bf(uint32_t a, uint32_t b, float c) {
-    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
+    const float a0 = __uint_as_float(a << 16), a1 = __uint_as_float(a & 0xFFFF0000u);
+    const float b0 = __uint_as_float(b << 16), b1 = __uint_as_float(b & 0xFFFF0000u);
+    return (c + a0 * b0) + a1 * b1;
 }
 // bfloat16 bits of a finite FP32 value, rounded to nearest even
 __device__ __forceinline__ uint32_t bf16_rne(float v) {
@@ -363,12 +368,14 @@ __device__ __forceinline__ void dot_rows(const SearchK &p, const float *qv, cons
 // to 8 significant bits, so |x_i - hi_i| <= 2^-7 |hi_i| (hi_i normal; a zero or subnormal
 // hi_i leaves less than 2^-126).  With M = sum_i |hi_i q_b,i|,
 //   |<x, q> - sum_i hi_i q_b,i| <= (2^-7 + 2^-8) M / (1 - 2^-8) + 2 d 2^-126.
-// Rounding: a v_dot2c_f32_bf16 step errs by at most 4 units of 2^-24 of the sum of its
-// terms' magnitudes (measured worst case 2.6), a chain of at most 128 of them per lane and
-// the 4 butterfly additions stay below 2^-15 M for both sums; the kernel's exact FP32
-// inner product differs from <x, q> by at most gamma_260 sum |x_i q_i| < 2^-16 M (unit
-// vectors, d <= 4096).  kBoundRel adds these to 0.0117647 and kBoundAbs covers the
-// subnormal terms and the two roundings of the final expression (|ub| <= 1.02).
+// Rounding: each sum is a chain of at most 256 FP32 additions of exact products per lane
+// (d <= 4096) and 4 butterfly additions, so it errs by at most gamma_260 M < 2^-15 M
+// (Higham's bound, gamma_n = n u / (1 - n u), u = 2^-24); the kernel's exact FP32 inner
+// product differs from <x, q> by at most gamma_260 sum |x_i q_i| < 2^-16 M (unit vectors).
+// kBoundRel adds these to 0.0117647 with room to spare (0.0118800 - 0.0117647 = 1.15e-4
+// > 2^-15 + 2^-16 + the relative error of M itself times 0.012), and kBoundAbs covers
+// the subnormal terms, underflowed products and the two roundings of the final expression
+// (|ub| <= 1.02).
 constexpr float kBoundRel = 0.011880f;
 constexpr float kBoundAbs = 9.5367431640625e-07f; // 2^-20
 template <int DT, int U>
