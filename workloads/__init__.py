@@ -17,6 +17,9 @@ Workloads (all FP32, rows are points):
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 DATA_SEED = 1000
@@ -31,17 +34,33 @@ def _unit_rows(a: np.ndarray) -> np.ndarray:
     return (a / nrm).astype(np.float32)
 
 
-def _chunked(n: int, d: int, rng: np.random.Generator, fn, chunk: int = 1 << 18) -> np.ndarray:
+_CHUNK = 1 << 17
+
+
+def _chunked(n: int, d: int, seed: int, fn) -> np.ndarray:
+    """Rows [s, s + _CHUNK) come from their own PCG64 stream (child s / _CHUNK of the seed's
+    SeedSequence), so that chunks are drawn in parallel threads and the result does not
+    depend on the thread count."""
     out = np.empty((n, d), dtype=np.float32)
-    for s in range(0, n, chunk):
-        e = min(n, s + chunk)
-        out[s:e] = fn(rng, e - s)
+    starts = list(range(0, n, _CHUNK))
+    kids = np.random.SeedSequence(seed).spawn(len(starts))
+
+    def one(i):
+        s = starts[i]
+        e = min(n, s + _CHUNK)
+        out[s:e] = fn(np.random.default_rng(kids[i]), e - s)
+
+    if len(starts) <= 1:
+        for i in range(len(starts)):
+            one(i)
+    else:
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1, len(starts))) as ex:
+            list(ex.map(one, range(len(starts))))
     return out
 
 
 def gaussian_unit(n: int, d: int, seed: int) -> np.ndarray:
-    rng = np.random.default_rng(seed)
-    return _chunked(n, d, rng, lambda r, c: _unit_rows(r.standard_normal((c, d), dtype=np.float32)))
+    return _chunked(n, d, seed, lambda r, c: _unit_rows(r.standard_normal((c, d), dtype=np.float32)))
 
 
 def mixture_centers(n_clusters: int, d: int, seed: int) -> np.ndarray:
@@ -50,7 +69,6 @@ def mixture_centers(n_clusters: int, d: int, seed: int) -> np.ndarray:
 
 def mixture(n: int, d: int, centers: np.ndarray, sigma: float, seed: int,
             sigma_mode: str = "coord") -> np.ndarray:
-    rng = np.random.default_rng(seed)
     scale = sigma if sigma_mode == "coord" else sigma / np.sqrt(d)
 
     def fn(r, c):
@@ -58,7 +76,7 @@ def mixture(n: int, d: int, centers: np.ndarray, sigma: float, seed: int,
         g = r.standard_normal((c, d), dtype=np.float32)
         return _unit_rows(centers[lab] + np.float32(scale) * g)
 
-    return _chunked(n, d, rng, fn)
+    return _chunked(n, d, seed, fn)
 
 
 def planted(n: int, d: int, n_groups: int, per_group: int, decoys: int, seed: int):
@@ -125,11 +143,13 @@ def paper_synthetic(n: int, d: int, m: int, seed: int):
 
 
 # ------------------------------------------------------------------ the five configurations
-def config(c: int, scale: float = 1.0, sigma_mode: str = "coord", query_seed_offset: int = 0):
+def config(c: int, scale: float = 1.0, sigma_mode: str = "coord", query_seed_offset: int = 0,
+           with_train: bool = True):
     """Points, queries and parameters of configuration c (1..5).
 
     scale < 1 shrinks n and the query count (for quick tests); sizes otherwise as
-    stated in the workload descriptions.
+    stated in the workload descriptions.  with_train=False leaves out configuration 5's
+    1,000,000 training queries.
     """
     def sz(v):
         return max(1, int(round(v * scale)))
@@ -161,10 +181,12 @@ def config(c: int, scale: float = 1.0, sigma_mode: str = "coord", query_seed_off
     if c == 5:
         n, d = sz(10_000_000), 128
         cen = mixture_centers(100_000, d, CENTER_SEED + 5)
-        return dict(points=mixture(n, d, cen, 0.3, DATA_SEED + 5, sigma_mode),
-                    train_queries=mixture(sz(1_000_000), d, cen, 0.3, QUERY_SEED + 5, sigma_mode),
-                    queries=mixture(sz(100_000), d, cen, 0.3, QUERY_SEED + 50, sigma_mode),
-                    k=10, recall=0.9, budget=16 << 30, name="mixture-10M-d128")
+        out = dict(points=mixture(n, d, cen, 0.3, DATA_SEED + 5, sigma_mode),
+                   queries=mixture(sz(100_000), d, cen, 0.3, QUERY_SEED + 50, sigma_mode),
+                   k=10, recall=0.9, budget=16 << 30, name="mixture-10M-d128")
+        if with_train:
+            out["train_queries"] = mixture(sz(1_000_000), d, cen, 0.3, QUERY_SEED + 5, sigma_mode)
+        return out
     raise ValueError(c)
 
 
