@@ -1,23 +1,27 @@
 """Throughput of the adaptive k-NN query path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--legs LIST] [--extras]
 
-Workload (default): mixture-1M-d100 -- n = 1,000,000 unit vectors in d = 100 drawn from
-a mixture of 10,000 Gaussian clusters (centres uniform on the sphere, sigma = 0.3 per
-coordinate, then normalised), 10,000 queries from the same mixture, k = 10, recall 0.9,
-memory budget 2 GiB (L = 108 tables of K = 24 bits, M = 32 sketches).
+Headline workload (`value`): mixture-10M-d128 -- n = 10,000,000 unit vectors in d = 128 drawn
+from a mixture of 100,000 Gaussian clusters (centres uniform on the sphere, sigma = 0.3 per
+coordinate, then normalised), memory budget 16 GiB (every resident byte charged: L = 66
+tables of K = 24 bits, M = 32 sketches); a scheduler network is trained on 1,000,000 traces of
+the plain method, then 100,000 further queries are answered at k = 10, recall 0.9 by the
+learned-batched path (persistent kernel, work queue ordered longest-predicted-first).  One
+step is the whole query path over the batch (normalisation, hashing, decision tables, prefix
+ranges, queue order, search) with the queries already in HBM; W untimed and K timed steps.
 
-The index is built once (its device time is reported as build_ms) and stays resident
-in HBM with the queries; one timed step answers the whole batch of queries: query
-normalisation, hashing, prefix ranges and the adaptive search kernel.
-Four query paths are timed on the same batch: the plain search (static query slots),
-the persistent batched search with a FIFO work queue (with every re-ranked vector read
-from both 16-bit planes, and with the upper-plane bound first), and the learned-batched
-search (work queue ordered longest-predicted-first by the scheduler network, trained
-first on traces of the plain method for other queries of the same distribution).
-`value` is the learned-batched rate; the others are reported beside it.
-Prints one JSON line.  The roofline entry is for the search kernel in the learned-batched
-path, whose average launch duration is measured with HIP events on the launch stream.
+Printed: one JSON line.  Beside the headline it carries, as named legs (fewer steps each):
+the same batch by the plain method and by the batched FIFO and true-cost-ordered queues; the
+paper's own stopping rule (Lemma 1, epsilon slack of Sec. 5.1) at epsilon 0, 0.1, 0.2, 0.5;
+the noise-norm reading of sigma (clusters of cosine about 0.9) for the same configuration;
+mixture-1M-d100 (1 M x 100, 10,000 queries, 2 GiB) under both readings; the planted instance
+(1 M x 256, k = 1, recall 0.5 / 0.9 / 0.99); and the mixed batch (100,000 queries with
+per-query k and recall) with its measured recall per (k, recall) against exact k-NN.
+`roofline` is for the search kernel of the headline path: algorithmic bytes per launch over
+its HIP-event launch time, against 8 TB/s and against the read rate of a plain streaming
+kernel measured on the same device; `cpu_baseline` times the CPU oracle on a bounded sample
+of the headline batch (its index is built in a child process while the GPU legs run).
 """
 from __future__ import annotations
 
@@ -26,6 +30,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -39,8 +44,13 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "queries/sec at k=10, recall≥0.9: learned-batched vs plain GPU; filter HBM GB/s"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_mixture-1M-d100_traffic.json")
+HEADLINE = "mixture-10M-d128"
 SEARCH_SRC = os.path.join(ROOT, "paper_1906_12211_amd", "csrc", "k_search.hip")
+DEFAULT_LEGS = "c5_paths,paper_rule,c5_norm,c2,c2_norm,c3,c4"
+
+
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"search_{workload}_traffic.json")
 
 
 def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> float:
@@ -61,6 +71,21 @@ def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> floa
     return float(per_q.sum())
 
 
+def filter_bytes(stats: np.ndarray) -> float:
+    """The filter's share of the algorithmic bytes: 8 B per scanned sketch and 4 B per
+    position of a passing entry."""
+    return float((8.0 * stats[:, 1] + 4.0 * stats[:, 2]).sum())
+
+
+def plain_gather_bytes(stats: np.ndarray, d: int, k: int, L: int) -> float:
+    """The same launch counted as if every re-ranked candidate's FP32 vector were gathered
+    (4d B), with the prefix-table reads (4L), sketches (8 B per scanned entry), positions
+    of passing entries (4 B), the query and the result: the bytes a re-rank without the
+    8-bit and 16-bit bounds would move (reported beside the roofline, not in it)."""
+    per_q = 4.0 * L + 8.0 * stats[:, 1] + 4.0 * stats[:, 2] + 4.0 * d * stats[:, 3] + 4.0 * d + 8.0 * k
+    return float(per_q.sum())
+
+
 HOST_MARK = b"// ====================================================================== host side"
 
 
@@ -77,22 +102,16 @@ def search_device_sha(src: bytes = None) -> str:
     return hashlib.sha256(code.encode()).hexdigest()
 
 
-def plain_gather_bytes(stats: np.ndarray, d: int, k: int, L: int) -> float:
-    """The same launch counted as if every re-ranked candidate's FP32 vector were gathered
-    (4d B), with the prefix-table reads (4L), sketches (8 B per scanned entry), positions
-    of passing entries (4 B), the query and the result: the bytes a re-rank without the
-    8-bit and 16-bit bounds would move (reported beside the roofline, not in it)."""
-    per_q = 4.0 * L + 8.0 * stats[:, 1] + 4.0 * stats[:, 2] + 4.0 * d * stats[:, 3] + 4.0 * d + 8.0 * k
-    return float(per_q.sum())
-
-
-def traffic_entry(tile_name: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current search kernel source with the tile shape this run launched."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_entry(workload: str, tile_name: str, L: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this workload,
+    if it was taken on the current search kernel source, with the tile shape and table
+    count this run launched."""
+    path = traffic_file(workload)
+    if not os.path.exists(path):
         return None
-    t = json.load(open(TRAFFIC_FILE))
-    if t.get("k_search_device_sha256") != search_device_sha() or t.get("tile_name") != tile_name:
+    t = json.load(open(path))
+    if (t.get("k_search_device_sha256") != search_device_sha() or t.get("tile_name") != tile_name
+            or t.get("L") != L):
         return None
     return t.get("bytes_per_launch")
 
@@ -101,116 +120,104 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(points, queries, budget, k, recall, seconds):
-    """The oracle, as it stands, on the host cores over a bounded sample of the queries."""
-    import oracle
-
-    t0 = time.time()
-    ix = oracle.OracleIndex(points, budget, seed=workloads.INDEX_SEED)
-    build_s = time.time() - t0
-    log(f"oracle index built in {build_s:.1f} s")
-    done, el, chunk = 0, 0.0, 64
-    while done < len(queries) and el < seconds:
-        q = queries[done:done + chunk]
-        t = time.time()
-        ix.search(q, k, recall)
-        el += time.time() - t
-        done += len(q)
-        chunk = min(2048, chunk * 2)
-    cores = oracle.num_threads()
-    # one thread, one query at a time (the paper's single-core setting), on a smaller sample
-    oracle.set_threads(1)
-    n1, el1 = 0, 0.0
-    while n1 < len(queries) and el1 < seconds / 4:
-        q = queries[n1:n1 + 16]
-        t = time.time()
-        ix.search(q, k, recall)
-        el1 += time.time() - t
-        n1 += len(q)
-    oracle.set_threads(cores)
+def host_cpu():
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
             model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": done / el, "unit": "queries/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {done} of {len(queries)} queries of the same workload on the oracle's "
-                      f"own index (oracle build {build_s:.1f} s, not timed)",
-            "seconds": el, "single_thread_qps": n1 / el1, "single_thread_sample": n1,
-            "host_cpu": model, "host_nproc": os.cpu_count()}
+    return model
 
 
-def mixed_batch(ix, dev, args):
-    """Configuration 4 on the same index: 100,000 queries, half from the mixture and half
-    uniform, with per-query k in {1, 10, 100} and recall in {0.5, 0.9, 0.99}, answered by
-    the persistent batched search under four queue orders: as given (FIFO), the learned
-    order (longest predicted first; network trained on traces of the plain method for
-    another batch of the same distribution), the order of the true costs (the plain
-    method's scanned-entry counts of this batch; a bound no predictor can beat) and the
-    reverse of the learned order (shortest predicted first)."""
+# ------------------------------------------------------------------ CPU baseline (child)
+def cpu_worker(cfg: int, L: int, seconds: float, build_threads: int):
+    """Child process: generate the headline workload, build the oracle's index at the
+    GPU's table count with `build_threads` threads (while the parent times the GPU), print
+    "ready", wait for "go" on stdin, then time the oracle on the first queries of the
+    headline batch with every host thread (and one thread on a smaller sample)."""
+    import oracle
+
+    c = workloads.config(cfg, with_train=False)
+    total = oracle.num_threads()
+    oracle.set_threads(max(1, min(build_threads, total)))
+    t0 = time.time()
+    ix = oracle.OracleIndex(c["points"], c["budget"], seed=workloads.INDEX_SEED, L=L)
+    build_s = time.time() - t0
+    del c["points"]
+    print(json.dumps({"ready": True, "build_s": build_s}), flush=True)
+    sys.stdin.readline()
+    oracle.set_threads(total)
+    Q, k, recall = c["queries"], c["k"], c["recall"]
+    done, el, chunk = 0, 0.0, 32
+    while done < len(Q) and el < seconds:
+        q = Q[done:done + chunk]
+        t = time.time()
+        ix.search(q, k, recall)
+        el += time.time() - t
+        done += len(q)
+        chunk = min(1024, chunk * 2)
+    oracle.set_threads(1)
+    n1, el1 = 0, 0.0
+    while n1 < len(Q) and el1 < seconds / 4:
+        q = Q[n1:n1 + 4]
+        t = time.time()
+        ix.search(q, k, recall)
+        el1 += time.time() - t
+        n1 += len(q)
+    print(json.dumps({"value": done / el, "unit": "queries/s", "cores": total, "kind": "oracle",
+                      "sample": f"first {done} of {len(Q)} queries of the {c['name']} batch on the oracle's own "
+                                f"index (n = {ix.n:,}, L = {L}; built in {build_s:.0f} s with {build_threads} "
+                                f"threads while the GPU legs ran, not timed)",
+                      "seconds": el, "single_thread_qps": n1 / el1, "single_thread_sample": n1,
+                      "host_cpu": host_cpu(), "host_nproc": os.cpu_count(), "oracle_build_s": build_s}),
+          flush=True)
+
+
+class CpuBaseline:
+    def __init__(self, cfg: int, L: int, seconds: float):
+        threads = max(1, (os.cpu_count() or 4) - 4)
+        self.p = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(cfg),
+                                   "--cpu-L", str(L), "--cpu-seconds", str(seconds),
+                                   "--cpu-build-threads", str(threads)],
+                                  stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True)
+        log(f"oracle index for the CPU baseline: building in a child process ({threads} threads)")
+
+    def result(self):
+        ready = json.loads(self.p.stdout.readline() or "{}")
+        if not ready.get("ready"):
+            self.p.kill()
+            raise RuntimeError("CPU baseline worker failed")
+        log(f"oracle index was built in {ready['build_s']:.0f} s; timing the oracle")
+        self.p.stdin.write("go\n")
+        self.p.stdin.flush()
+        out = json.loads(self.p.stdout.readline())
+        self.p.wait()
+        return out
+
+
+# ------------------------------------------------------------------ helpers
+def timed(fn, ix, warmup: int, steps: int):
+    """Run fn warmup + steps times; returns (wall ms per timed step, per-phase mean ms of the
+    timed steps from the library's HIP events, last result)."""
     import torch
 
-    m = max(1, int(round(100_000 * args.scale)))
-    Q, ks, rec = workloads.mixed_queries(m)
-    Qt, kst, rect = workloads.mixed_queries(max(1, int(round(m * args.train_frac))), seed_offset=100)
-    kmax = 100
-    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    Qd, ksd, recd = to(Q), to(ks), to(rec)
-    Qtd, kstd, rectd = to(Qt), to(kst), to(rect)
+    r = None
+    for _ in range(warmup):
+        r = fn()
+    torch.cuda.synchronize()
+    ph = {"normalize+hash": [], "ranges": [], "queue_order": [], "search": []}
     t0 = time.perf_counter()
-    st = ix.search_batch(Qtd, kstd, rectd, kmax).stats.cpu().numpy()
-    target = np.stack([st[:, 0], np.log2(1.0 + st[:, 1])], 1).astype(np.float32)
-    sched = pf.Scheduler(seed=2)
-    losses = sched.train(ix.features(Qtd, kstd, rectd), to(target), epochs=20, batch=512, lr=2e-3)
-    ix.set_scheduler(sched)
-    train_s = time.perf_counter() - t0
-    log(f"mixed batch: scheduler trained on {len(Qt)} traces in {train_s:.1f} s, "
-        f"loss {losses[0]:.3f} -> {losses[-1]:.3f}")
-    ix.search_batch(Qd, ksd, recd, kmax, autotune=True)
-    base = ix.search_batch(Qd, ksd, recd, kmax)
-    cost = np.log2(1.0 + base.stats.cpu().numpy()[:, 1])
-    pred = sched.predict(ix.features(Qd, ksd, recd)).cpu().numpy()[:, 1]
-    rank = lambda v: np.argsort(np.argsort(v))
-    rho = float(np.corrcoef(rank(pred), rank(cost))[0, 1])
-    lpt_true = np.argsort(-cost, kind="stable").astype(np.int32)
-    spt_pred = np.argsort(pred, kind="stable").astype(np.int32)
-    orders = {
-        "fifo": dict(),
-        "learned": dict(learned=True),
-        "true_cost_lpt": dict(order=to(lpt_true)),
-        "shortest_predicted_first": dict(order=to(spt_pred)),
-    }
-    out = {}
-    steps = max(1, min(args.steps, 5))
-    for name, kw in orders.items():
-        for _ in range(max(1, min(args.warmup, 2))):
-            r = ix.search_batch(Qd, ksd, recd, kmax, timing=True, **kw)
-        torch.cuda.synchronize()
-        ks_ms = []
-        t = time.perf_counter()
-        for _ in range(steps):
-            r = ix.search_batch(Qd, ksd, recd, kmax, timing=True, **kw)
-            ks_ms.append(ix.last_timing().search_ms)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t) / steps * 1e3
-        same = bool(torch.equal(r.ids, base.ids))
-        out[name] = {"ms_per_step": wall, "qps": m / (wall / 1e3), "search_kernel_ms": float(np.mean(ks_ms)),
-                     "ids_equal_fifo": same}
-        log(f"mixed batch {name}: {wall:.2f} ms/step, search kernel {np.mean(ks_ms):.2f} ms, ids equal {same}")
-    t = ix.last_timing()
-    sb = base.stats.cpu().numpy()
-    return {"workload": "mixed-100k-on-1M-d100", "queries": m, "kmax": kmax, "steps": steps,
-            "orders": out,
-            "learned_vs_fifo": out["fifo"]["search_kernel_ms"] / out["learned"]["search_kernel_ms"],
-            "spearman_pred_vs_true_cost": rho,
-            "scheduler": {"train_queries": int(len(Qt)), "train_s": train_s, "loss_first": float(losses[0]),
-                          "loss_last": float(losses[-1])},
-            "tile": {"tile": t.tile, "waves_per_cu": t.waves_per_cu},
-            "mean_counts": {"c_scan": float(sb[:, 1].mean()), "c_pass": float(sb[:, 2].mean()),
-                            "c_upper": float(sb[:, 5].mean()), "c_exact": float(sb[:, 4].mean())},
-            "cost_spread_log2_scan": {"p10": float(np.percentile(cost, 10)), "p50": float(np.percentile(cost, 50)),
-                                      "p90": float(np.percentile(cost, 90)), "max": float(cost.max())}}
+    for _ in range(steps):
+        r = fn()
+        t = ix.last_timing()
+        ph["normalize+hash"].append(t.hash_ms)
+        ph["ranges"].append(t.ranges_ms)
+        ph["queue_order"].append(t.order_ms)
+        ph["search"].append(t.search_ms)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    return wall, {k: float(np.mean(v)) for k, v in ph.items()}, r
 
 
 def exact_topk_gpu(Xd, Qd, k: int, extra: int = 8):
@@ -220,7 +227,6 @@ def exact_topk_gpu(Xd, Qd, k: int, extra: int = 8):
     query ordered on the host."""
     import torch
 
-    Xd64 = None
     out = np.empty((Qd.shape[0], k), dtype=np.int64)
     step = max(1, int(2e9 // (8 * Xd.shape[0])))
     for s in range(0, Qd.shape[0], step):
@@ -236,216 +242,401 @@ def exact_topk_gpu(Xd, Qd, k: int, extra: int = 8):
     return out
 
 
-def paper_synthetic(dev):
-    """The paper's synthetic set (Sec. 5): 1,000,000 points in 3 x 100 dimensions whose last
-    row is every query's nearest neighbour, 1,000 queries, 2 GiB, k = 1: per recall target
-    the fraction of queries that return it, the stop levels and the search time (plain
-    single launch and batched work queue)."""
+def truth_of(ix, Q, k: int, dev):
+    """Exact top-k of the normalised queries Q over the index's normalised points (exported
+    once per index and kept on the device beside it)."""
     import torch
 
-    X, Q = workloads.paper_synthetic(1_000_000, 100, 1000, 78)
-    Xd = torch.from_numpy(X).to(dev)
-    ix = pf.Index(Xd, 2 << 30, seed=workloads.INDEX_SEED)
-    del Xd
-    info = ix.info()
-    m = len(Q)
-    Qd = torch.from_numpy(Q).to(dev)
-    out = {"workload": "paper-synthetic-1M-3x100", "n": len(X), "d": X.shape[1], "queries": m, "k": 1,
-           "L": info.L, "build_ms": info.build_ms, "targets": {}}
-    for rec in (0.5, 0.9, 0.99):
-        ks = torch.ones((m,), dtype=torch.int32, device=dev)
-        rc = torch.full((m,), rec, dtype=torch.float64, device=dev)
-        ix.search(Qd, 1, rec)
-        plain = []
-        for _ in range(3):
-            r = ix.search(Qd, 1, rec, timing=True)
-            plain.append(ix.last_timing().search_ms)
-        ix.search_batch(Qd, ks, rc, 1, autotune=True)
-        batched = []
-        for _ in range(3):
-            rb = ix.search_batch(Qd, ks, rc, 1, timing=True)
-            batched.append(ix.last_timing().search_ms)
-        hit = float(np.mean(r.ids.cpu().numpy()[:, 0] == len(X) - 1))
-        hit_b = float(np.mean(rb.ids.cpu().numpy()[:, 0] == len(X) - 1))
-        st = r.stats.cpu().numpy()
-        out["targets"][str(rec)] = {"x_n_found": hit, "x_n_found_batched": hit_b,
-                                    "mean_stop_level": float(st[:, 0].mean()),
-                                    "mean_c_scan": float(st[:, 1].mean()),
-                                    "search_kernel_ms_plain": float(np.mean(plain)),
-                                    "search_kernel_ms_batched": float(np.mean(batched))}
-        log(f"paper synthetic, recall {rec}: x_n found {hit:.4f}, kernel {np.mean(plain):.2f} ms plain, "
-            f"{np.mean(batched):.2f} ms batched")
-    return out
+    if getattr(ix, "_bench_points", None) is None:
+        ix._bench_points = torch.from_numpy(ix.export(pf.PF_EXPORT_POINTS)).to(dev)
+    Qn = torch.from_numpy(pf.pf_normalize(np.ascontiguousarray(Q))).to(dev)
+    return exact_topk_gpu(ix._bench_points, Qn, k)
 
 
-def cp_index(X, Q, k, recall, budget, dev, truth_ids):
-    """The same workload on an index whose table codes are FHT cross-polytope values
-    (Sec. 2.2, 4.3; the sketches stay hyperplane bits): build time (the FP64 rotations),
-    query hashing time, and the batched search under the default rule."""
+def recall_of(ids: np.ndarray, truth: np.ndarray, k: int) -> float:
+    return float(np.mean([len(set(a[:k]) & set(b[:k])) / k for a, b in zip(ids, truth)]))
+
+
+def counts(st: np.ndarray) -> dict:
+    return {"c_scan": float(st[:, 1].mean()), "c_pass": float(st[:, 2].mean()), "c_rerank": float(st[:, 3].mean()),
+            "c_q8": float(st[:, 6].mean()), "c_upper": float(st[:, 5].mean()), "c_exact": float(st[:, 4].mean())}
+
+
+def spearman(a, b) -> float:
+    rk = lambda v: np.argsort(np.argsort(v, kind="stable"), kind="stable")
+    return float(np.corrcoef(rk(a), rk(b))[0, 1])
+
+
+def train_scheduler(ix, Qtr, k, recall, dev, seed, epochs, batch, chunk=100_000):
+    """Traces of the plain method on the training queries (in chunks of `chunk`, so that the
+    index's call buffers stay at the evaluation batch's size), then training on the GPU."""
     import torch
 
-    Xd = torch.from_numpy(X).to(dev)
-    ix = pf.Index(Xd, budget, seed=workloads.INDEX_SEED, family=pf.PF_FAMILY_FHTCP)
-    del Xd
-    info = ix.info()
-    m = len(Q)
-    Qd = torch.from_numpy(Q).to(dev)
-    ks = torch.full((m,), k, dtype=torch.int32, device=dev)
-    rec = torch.full((m,), recall, dtype=torch.float64, device=dev)
-    ix.search_batch(Qd, ks, rec, k, autotune=True)
-    r = ix.search_batch(Qd, ks, rec, k, timing=True)
-    ts = []
-    for _ in range(3):
-        r = ix.search_batch(Qd, ks, rec, k, timing=True)
-        t = ix.last_timing()
-        ts.append((t.hash_ms, t.search_ms, t.total_ms))
-    ids = r.ids.cpu().numpy()[:len(truth_ids)]
-    st = r.stats.cpu().numpy()
-    recm = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(ids, truth_ids)]))
-    out = {"family": "fht-cross-polytope", "L": info.L, "build_ms": info.build_ms,
-           "normalize+hash_ms": float(np.mean([a for a, _, _ in ts])),
-           "search_kernel_ms": float(np.mean([b for _, b, _ in ts])),
-           "qps": m / (float(np.mean([c for _, _, c in ts])) / 1e3), "recall_measured": recm,
-           "mean_counts": {"c_scan": float(st[:, 1].mean()), "c_pass": float(st[:, 2].mean())},
-           "stop_level_hist": np.bincount(st[:, 0], minlength=info.K + 1).tolist()}
-    log(f"cross-polytope index: build {info.build_ms:.0f} ms, search kernel {out['search_kernel_ms']:.2f} ms, "
-        f"recall {recm:.4f}")
-    return out
-
-
-def pooled_index(X, Q, k, recall, budget, dev, truth_ids):
-    """The same workload on an index built with pooling (Sec. 3.2: 3,072 shared functions,
-    each table sampling its 24): build time, query hashing time, and the batched search
-    under the default stopping rule and under Algorithm 3's test."""
-    import torch
-
-    Xd = torch.from_numpy(X).to(dev)
-    ix = pf.Index(Xd, budget, seed=workloads.INDEX_SEED, pool=3072)
-    del Xd
-    info = ix.info()
-    m = len(Q)
-    Qd = torch.from_numpy(Q).to(dev)
-    ks = torch.full((m,), k, dtype=torch.int32, device=dev)
-    rec = torch.full((m,), recall, dtype=torch.float64, device=dev)
-    ix.search_batch(Qd, ks, rec, k, autotune=True)
-    out = {"pool": 3072, "L": info.L, "build_ms": info.build_ms}
-    for name, rule in (("default_rule", pf.PF_RULE_FILTER), ("algorithm3_rule", pf.PF_RULE_POOL)):
-        r = ix.search_batch(Qd, ks, rec, k, rule=rule, timing=True)
-        ts = []
-        for _ in range(3):
-            r = ix.search_batch(Qd, ks, rec, k, rule=rule, timing=True)
-            t = ix.last_timing()
-            ts.append((t.hash_ms, t.search_ms, t.total_ms))
-        ids = r.ids.cpu().numpy()[:len(truth_ids)]
-        recm = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(ids, truth_ids)]))
-        out[name] = {"normalize+hash_ms": float(np.mean([a for a, _, _ in ts])),
-                     "search_kernel_ms": float(np.mean([b for _, b, _ in ts])),
-                     "qps": m / (float(np.mean([c for _, _, c in ts])) / 1e3), "recall_measured": recm}
-        log(f"pooled index, {name}: search kernel {out[name]['search_kernel_ms']:.2f} ms, recall {recm:.4f}")
-    return out
-
-
-def workload_c5(args):
-    """Configuration 5: n = 10,000,000 clustered unit vectors in d = 128 (100,000 clusters),
-    16 GiB budget; the scheduler is trained on 1,000,000 plain-method traces and the three
-    query paths are timed on 100,000 further queries (k = 10, recall 0.9)."""
-    import torch
-
-    dev = torch.device("cuda:0")
-    log("generating mixture-10M-d128")
-    c = workloads.config(5, scale=args.scale)
-    X, Qtr, Q = c["points"], c["train_queries"], c["queries"]
-    n, d = X.shape
-    m = len(Q)
-    k, recall = c["k"], c["recall"]
-    Xd = torch.from_numpy(X).to(dev)
-    del X
-    ix = pf.Index(Xd, c["budget"], seed=workloads.INDEX_SEED)
-    info = ix.info()
-    log(f"index built: L={info.L} device build {info.build_ms:.1f} ms, {info.bytes_device / 2**30:.2f} GiB")
     t0 = time.perf_counter()
-    Qtrd = torch.from_numpy(Qtr).to(dev)
-    ks_t = torch.full((len(Qtr),), k, dtype=torch.int32, device=dev)
-    rec_t = torch.full((len(Qtr),), recall, dtype=torch.float64, device=dev)
-    st = ix.search_batch(Qtrd, ks_t, rec_t, k).stats.cpu().numpy()
+    st, feats = [], []
+    for s in range(0, len(Qtr), chunk):
+        q = torch.from_numpy(Qtr[s:s + chunk]).to(dev)
+        st.append(ix.search(q, k, recall).stats.cpu().numpy())
+        feats.append(ix.features(q, k=k, recall=recall))
+    st = np.concatenate(st)
+    feat = torch.cat(feats)
     trace_s = time.perf_counter() - t0
     target = np.stack([st[:, 0], np.log2(1.0 + st[:, 1])], 1).astype(np.float32)
-    sched = pf.Scheduler(seed=5)
+    sched = pf.Scheduler(seed=seed)
     t0 = time.perf_counter()
-    losses = sched.train(ix.features(Qtrd), torch.from_numpy(target).to(dev), epochs=5, batch=1024, lr=2e-3)
+    losses = sched.train(feat, torch.from_numpy(target).to(dev), epochs=epochs, batch=batch, lr=2e-3)
     train_s = time.perf_counter() - t0
     ix.set_scheduler(sched)
-    del Qtrd
-    log(f"{len(Qtr)} traces in {trace_s:.1f} s; scheduler trained in {train_s:.1f} s, "
-        f"loss {losses[0]:.3f} -> {losses[-1]:.3f}")
-    Qd = torch.from_numpy(Q).to(dev)
-    ks_d = torch.full((m,), k, dtype=torch.int32, device=dev)
-    rec_d = torch.full((m,), recall, dtype=torch.float64, device=dev)
-    ix.search_batch(Qd, ks_d, rec_d, k, autotune=True)
+    del feat
+    return sched, {"traces": int(len(Qtr)), "trace_s": trace_s, "train_s": train_s,
+                   "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+
+
+def order_paths(ix, Qd, k, recall, sched, dev, steps, warmup=1):
+    """The batch under the plain method (static slots) and the batched queue in FIFO,
+    learned and true-cost (longest scanned first; a bound no predictor can beat) order."""
+    import torch
+
+    m = Qd.shape[0]
+    ks = torch.full((m,), k, dtype=torch.int32, device=dev)
+    rc = torch.full((m,), recall, dtype=torch.float64, device=dev)
+    base = ix.search_batch(Qd, ks, rc, k)
+    bst = base.stats.cpu().numpy()
+    lpt = torch.from_numpy(np.argsort(-bst[:, 1], kind="stable").astype(np.int32)).to(dev)
     modes = {
         "plain": lambda: ix.search(Qd, k, recall, timing=True),
-        "batched_fifo": lambda: ix.search_batch(Qd, ks_d, rec_d, k, timing=True),
-        "learned_batched": lambda: ix.search_batch(Qd, ks_d, rec_d, k, learned=True, timing=True),
+        "batched_fifo": lambda: ix.search_batch(Qd, ks, rc, k, timing=True),
+        "learned_batched": lambda: ix.search_batch(Qd, ks, rc, k, learned=True, timing=True),
+        "true_cost_lpt": lambda: ix.search_batch(Qd, ks, rc, k, order=lpt, timing=True),
     }
-    res = {}
-    steps = max(1, min(args.steps, 5))
+    out = {}
     for name, fn in modes.items():
-        r = fn()
-        torch.cuda.synchronize()
-        ks_ms = []
-        t = time.perf_counter()
-        for _ in range(steps):
-            r = fn()
-            ks_ms.append(ix.last_timing().search_ms)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t) / steps * 1e3
-        res[name] = {"ms_per_step": wall, "qps": m / (wall / 1e3), "search_kernel_ms": float(np.mean(ks_ms)),
-                     "r": r}
-        log(f"{name}: {wall:.2f} ms/step, search kernel {np.mean(ks_ms):.2f} ms")
-    r = res["learned_batched"].pop("r")
-    for v in res.values():
-        v.pop("r", None)
+        wall, ph, r = timed(fn, ix, warmup, steps)
+        out[name] = {"ms_per_step": wall, "qps": m / (wall / 1e3), "search_kernel_ms": ph["search"],
+                     "phase_ms": ph, "ids_equal_fifo": bool(torch.equal(r.ids, base.ids))}
+        log(f"  {name}: {wall:.2f} ms/step, phases " + ", ".join(f"{a} {b:.2f}" for a, b in ph.items()))
+    pred = sched.predict(ix.features(Qd, k=k, recall=recall)).cpu().numpy()[:, 1]
+    cost = np.log2(1.0 + bst[:, 1])
+    extra = {"learned_vs_plain": out["plain"]["ms_per_step"] / out["learned_batched"]["ms_per_step"],
+             "learned_vs_fifo": out["batched_fifo"]["search_kernel_ms"] / out["learned_batched"]["search_kernel_ms"],
+             "true_lpt_vs_fifo": out["batched_fifo"]["search_kernel_ms"] / out["true_cost_lpt"]["search_kernel_ms"],
+             "spearman_pred_vs_true_cost": spearman(pred, cost),
+             "cost_spread_log2_scan": {p: float(np.percentile(cost, q)) for p, q in
+                                       (("p1", 1), ("p10", 10), ("p50", 50), ("p90", 90), ("p99", 99))},
+             "stop_level_hist": np.bincount(bst[:, 0], minlength=ix.K + 1).tolist(),
+             "mean_counts": counts(bst)}
+    return out, extra, base
+
+
+WORKLOADS = {"mixture-10M-d128": 5, "mixture-1M-d100": 2}
+
+
+# ------------------------------------------------------------------ headline
+def headline(args, dev):
+    """The learned-batched path on configuration 5 (or, for counter runs, configuration 2)."""
+    import torch
+
+    cfg = WORKLOADS[args.workload]
+    log(f"generating {args.workload}")
+    t0 = time.perf_counter()
+    c = workloads.config(cfg)
+    Qtr = c.pop("train_queries") if cfg == 5 else workloads.queries_like(2, 20_000, seed_offset=100)
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    X, Q = c.pop("points"), c["queries"]
+    n, d = X.shape
+    m, k, recall = len(Q), c["k"], c["recall"]
+    ix = pf.Index(torch.from_numpy(X).to(dev), c["budget"], seed=workloads.INDEX_SEED)
+    del X
+    info = ix.info()
+    log(f"index built: L={info.L}, {info.bytes_device / 2**30:.2f} GiB on the device "
+        f"(budget {c['budget'] / 2**30:.0f} GiB), device build {info.build_ms:.0f} ms")
+    sched, sch = train_scheduler(ix, Qtr, k, recall, dev, seed=cfg, epochs=5 if cfg == 5 else 20,
+                                 batch=1024 if cfg == 5 else 512)
+    del Qtr
+    log(f"scheduler: {sch['traces']} traces in {sch['trace_s']:.1f} s, trained in {sch['train_s']:.1f} s, "
+        f"loss {sch['loss_first']:.3f} -> {sch['loss_last']:.3f}")
+    Qd = torch.from_numpy(Q).to(dev)
+    ks = torch.full((m,), k, dtype=torch.int32, device=dev)
+    rc = torch.full((m,), recall, dtype=torch.float64, device=dev)
+    ix.search_batch(Qd, ks, rc, k, autotune=True)
+    fn = lambda: ix.search_batch(Qd, ks, rc, k, learned=True, timing=True)
+    # the headline: W untimed and K timed steps of the learned-batched path
+    wall, ph, r = timed(fn, ix, args.warmup, args.steps)
+    qps = m / (wall / 1e3)
+    log(f"learned-batched: {wall:.1f} ms/step ({qps:.0f} queries/s), search kernel {ph['search']:.1f} ms")
+    tile = ix.last_timing().tile
+    waves = ix.last_timing().waves_per_cu
     stats = r.stats.cpu().numpy()
-    cost = np.log2(1.0 + stats[:, 1])
-    pred = sched.predict(ix.features(Qd)).cpu().numpy()[:, 1]
-    rank = lambda v: np.argsort(np.argsort(v))
-    ns = min(args.recall_sample, m)
-    Xn = torch.from_numpy(ix.export(pf.PF_EXPORT_POINTS)).to(dev)
-    Qn = torch.from_numpy(pf.pf_normalize(Q[:ns])).to(dev)
-    truth = exact_topk_gpu(Xn, Qn, k)
-    del Xn
     ids = r.ids.cpu().numpy()
-    rec = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(ids[:ns], truth)]))
+    ns = min(args.recall_sample, m)
+    truth = truth_of(ix, Q[:ns], k, dev)
+    rec = recall_of(ids[:ns], truth, k)
     log(f"recall {rec:.4f} on {ns} queries")
     A = algorithmic_bytes(stats, d, k, info.L, info.K)
-    kms = res["learned_batched"]["search_kernel_ms"]
+    F = filter_bytes(stats)
+    kms = ph["search"]
     achieved = A / (kms * 1e-3) / 1e9
+    read_gbs = pf.pf_read_bandwidth(4 << 30, 5)
+    log(f"read-only streaming kernel: {read_gbs:.0f} GB/s")
+    tname = pf.pf_tile_name(tile)
     line = {
-        "metric": METRIC, "value": res["learned_batched"]["qps"], "unit": "queries/s", "n_gpus": 1,
-        "steps": steps, "warmup": 1, "ms_per_step": res["learned_batched"]["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": c["name"], "n": n, "d": d, "queries": m, "k": k, "recall_target": recall,
+        "metric": METRIC, "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d, "queries": m, "k": k, "recall_target": recall,
                    "budget_bytes": c["budget"], "L": info.L, "K": info.K, "M": info.M, "B": 12,
-                   "train_traces": len(Qtr), "path": "learned_batched"},
-        "paths": res,
-        "learned_vs_plain": res["plain"]["ms_per_step"] / res["learned_batched"]["ms_per_step"],
-        "learned_vs_fifo": res["batched_fifo"]["search_kernel_ms"] / kms,
-        "scheduler": {"trace_s": trace_s, "train_s": train_s, "loss_first": float(losses[0]),
-                      "loss_last": float(losses[-1]),
-                      "spearman_pred_vs_true_cost": float(np.corrcoef(rank(pred), rank(cost))[0, 1])},
-        "recall_measured": rec, "recall_sample": ns, "build_ms": info.build_ms,
-        "bytes_device": info.bytes_device,
+                   "sigma_reading": "per coordinate", "train_traces": sch["traces"], "path": "learned_batched"},
+        "recall_measured": rec, "recall_sample": ns,
+        "bytes_device": info.bytes_device, "build_ms": info.build_ms,
+        "phase_ms": ph,
+        "batched_tile": {"tile": tile, "name": tname, "waves_per_cu": waves},
+        "scheduler": sch,
         "stop_level_hist": np.bincount(stats[:, 0], minlength=info.K + 1).tolist(),
-        "mean_counts": {"c_scan": float(stats[:, 1].mean()), "c_pass": float(stats[:, 2].mean()),
-                        "c_rerank": float(stats[:, 3].mean()), "c_q8": float(stats[:, 6].mean()),
-                        "c_upper": float(stats[:, 5].mean()), "c_exact": float(stats[:, 4].mean())},
+        "mean_counts": counts(stats),
+        "filter_gbs": F / (kms * 1e-3) / 1e9,
+        "filter_share_of_bytes": F / A,
         "roofline": {"kernel": "k_search", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": A, "avg_launch_ms": kms,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_entry(args.workload, tname, info.L),
+                     "measured_read_gbs": read_gbs, "frac_of_measured_read": achieved / read_gbs,
+                     "algorithmic_bytes_per_launch": A, "avg_launch_ms": kms, "queries_per_launch": m,
                      "fp32_gather_bytes_per_launch": plain_gather_bytes(stats, d, k, info.L)},
         "cpu_baseline": None,
     }
-    print(json.dumps(line), flush=True)
+    tr = line["roofline"]["traffic"]
+    if tr:
+        line["roofline"]["traffic_gbs"] = tr / (kms * 1e-3) / 1e9
+    legs = set(args.legs.split(",")) if args.legs else set()
+    steps2 = max(1, min(3, args.steps))
+    if "c5_paths" in legs:
+        log("headline batch under the other query paths")
+        paths, extra, _ = order_paths(ix, Qd, k, recall, sched, dev, steps2)
+        line["paths"] = paths
+        line.update({"learned_vs_plain": paths["plain"]["ms_per_step"] / wall,
+                     "learned_vs_fifo": paths["batched_fifo"]["search_kernel_ms"] / kms,
+                     "true_lpt_vs_fifo": extra["true_lpt_vs_fifo"],
+                     "spearman_pred_vs_true_cost": extra["spearman_pred_vs_true_cost"],
+                     "cost_spread_log2_scan": extra["cost_spread_log2_scan"]})
+    if "paper_rule" in legs:
+        line["paper_rule"] = paper_rule(ix, Qd, Q[:ns], truth, k, recall, dev)
+    del ix, sched, Qd
+    torch.cuda.empty_cache()
+    return line
+
+
+def paper_rule(ix, Qd, Qs, truth, k, recall, dev):
+    """The paper's own method on the headline batch: Lemma 1's bound (1 - p^i)^L <= delta
+    with the filter threshold (1 + eps) 64 theta_k / pi of Sec. 5.1, eps from the sweep
+    {0, 0.1, 0.2, 0.5}; the smallest eps whose measured recall reaches the target is the
+    paper's operating point."""
+    import torch
+
+    m = Qd.shape[0]
+    ks = torch.full((m,), k, dtype=torch.int32, device=dev)
+    rc = torch.full((m,), recall, dtype=torch.float64, device=dev)
+    out = {"rule": "PF_RULE_EXACT (Lemma 1, filter not accounted)", "sweep": {}}
+    chosen = None
+    for eps in (0.0, 0.1, 0.2, 0.5):
+        fn = lambda: ix.search_batch(Qd, ks, rc, k, rule=pf.PF_RULE_EXACT, eps=eps, learned=True, timing=True)
+        wall, ph, r = timed(fn, ix, 1, 1)
+        rec = recall_of(r.ids.cpu().numpy()[:len(truth)], truth, k)
+        st = r.stats.cpu().numpy()
+        out["sweep"][str(eps)] = {"qps": m / (wall / 1e3), "ms_per_step": wall, "search_kernel_ms": ph["search"],
+                                  "recall_measured": rec, "mean_stop_level": float(st[:, 0].mean()),
+                                  "mean_c_scan": float(st[:, 1].mean())}
+        log(f"  paper rule eps {eps}: {m / (wall / 1e3):.0f} queries/s, kernel {ph['search']:.1f} ms, recall {rec:.4f}")
+        if chosen is None and rec >= recall:
+            chosen = eps
+    out["eps_reaching_target"] = chosen
+    if chosen is not None:
+        out["at_target"] = dict(out["sweep"][str(chosen)], eps=chosen)
+    return out
+
+
+# ------------------------------------------------------------------ legs
+def leg_mixture(cfg, sigma_mode, args, dev, ntrain):
+    """Configuration 2 or 5 under a sigma reading: learned-batched, FIFO, plain and true-cost
+    order on its own index, with the scheduler trained on `ntrain` traces."""
+    import torch
+
+    t0 = time.perf_counter()
+    c = workloads.config(cfg, sigma_mode=sigma_mode, with_train=False)
+    Qtr = workloads.queries_like(cfg, ntrain, seed_offset=100, sigma_mode=sigma_mode)
+    X, Q = c.pop("points"), c["queries"]
+    n, d = X.shape
+    m, k, recall = len(Q), c["k"], c["recall"]
+    ix = pf.Index(torch.from_numpy(X).to(dev), c["budget"], seed=workloads.INDEX_SEED)
+    del X
+    info = ix.info()
+    log(f"{c['name']} ({sigma_mode}): L={info.L}, generated and built in {time.perf_counter() - t0:.1f} s")
+    sched, sch = train_scheduler(ix, Qtr, k, recall, dev, seed=cfg, epochs=20 if ntrain <= 50_000 else 5,
+                                 batch=512 if ntrain <= 50_000 else 1024)
+    Qd = torch.from_numpy(Q).to(dev)
+    m_ = Qd.shape[0]
+    ks = torch.full((m_,), k, dtype=torch.int32, device=dev)
+    rc = torch.full((m_,), recall, dtype=torch.float64, device=dev)
+    ix.search_batch(Qd, ks, rc, k, autotune=True)
+    paths, extra, base = order_paths(ix, Qd, k, recall, sched, dev, max(1, min(3, args.steps)))
+    ns = min(1000, m)
+    truth = truth_of(ix, Q[:ns], k, dev)
+    rec = recall_of(base.ids.cpu().numpy()[:ns], truth, k)
+    st = base.stats.cpu().numpy()
+    t = ix.last_timing()
+    out = {"workload": c["name"], "sigma_reading": "per coordinate" if sigma_mode == "coord" else "noise norm",
+           "n": n, "d": d, "queries": m, "L": info.L, "bytes_device": info.bytes_device, "paths": paths,
+           "scheduler": sch, "recall_measured": rec, "recall_sample": ns,
+           "batched_tile": {"tile": t.tile, "name": pf.pf_tile_name(t.tile), "waves_per_cu": t.waves_per_cu},
+           "algorithmic_gbs": algorithmic_bytes(st, d, k, info.L, info.K)
+           / (paths["learned_batched"]["search_kernel_ms"] * 1e-3) / 1e9}
+    out.update(extra)
+    log(f"{c['name']} ({sigma_mode}): recall {rec:.4f}; learned/fifo {extra['learned_vs_fifo']:.3f}, "
+        f"true-LPT/fifo {extra['true_lpt_vs_fifo']:.3f}, rho {extra['spearman_pred_vs_true_cost']:.2f}")
+    return out, ix, sched
+
+
+def leg_planted(args, dev):
+    """Configuration 3: 1 M uniform unit vectors in d = 256 with planted neighbours (100 groups
+    of 100 queries, 2,000 decoys near 60 degrees per group, one neighbour at 30 degrees per
+    query), 2 GiB, k = 1: per recall target the planted-neighbour hit rate, stop levels and
+    the batched search's rate."""
+    import torch
+
+    c = workloads.config(3)
+    X, Q, pid = c["points"], c["queries"], c["planted"]
+    ix = pf.Index(torch.from_numpy(X).to(dev), c["budget"], seed=workloads.INDEX_SEED)
+    del X
+    info = ix.info()
+    m = len(Q)
+    Qd = torch.from_numpy(Q).to(dev)
+    ks = torch.ones((m,), dtype=torch.int32, device=dev)
+    out = {"workload": c["name"], "n": info.n, "d": info.d, "queries": m, "k": 1, "L": info.L,
+           "bytes_device": info.bytes_device, "targets": {}}
+    for rec in (0.5, 0.9, 0.99):
+        rc = torch.full((m,), rec, dtype=torch.float64, device=dev)
+        ix.search_batch(Qd, ks, rc, 1, autotune=True)
+        wall, ph, r = timed(lambda: ix.search_batch(Qd, ks, rc, 1, timing=True), ix, 1, max(1, min(3, args.steps)))
+        st = r.stats.cpu().numpy()
+        hit = float(np.mean(r.ids.cpu().numpy()[:, 0] == pid))
+        out["targets"][str(rec)] = {"qps": m / (wall / 1e3), "ms_per_step": wall, "search_kernel_ms": ph["search"],
+                                    "planted_found": hit, "mean_stop_level": float(st[:, 0].mean()),
+                                    "stop_level_hist": np.bincount(st[:, 0], minlength=info.K + 1).tolist(),
+                                    "mean_counts": counts(st)}
+        log(f"planted, recall {rec}: {m / (wall / 1e3):.0f} queries/s, planted found {hit:.4f}, "
+            f"mean stop level {st[:, 0].mean():.2f}")
+    del ix
+    torch.cuda.empty_cache()
+    return out
+
+
+def leg_mixed(ix, args, dev):
+    """Configuration 4 on mixture-1M-d100's index: 100,000 queries, half from the mixture and
+    half uniform, per-query k in {1, 10, 100} and recall in {0.5, 0.9, 0.99}; the queue in
+    FIFO, learned (network trained on traces of another batch of the same distribution),
+    true-cost and shortest-predicted-first order; measured recall per (k, recall) against
+    exact k-NN on a sample."""
+    import torch
+
+    m = 100_000
+    Q, ks, rec = workloads.mixed_queries(m)
+    Qt, kst, rect = workloads.mixed_queries(200_000, seed_offset=100)
+    kmax = 100
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    Qd, ksd, recd = to(Q), to(ks), to(rec)
+    t0 = time.perf_counter()
+    st, feats = [], []
+    for s in range(0, len(Qt), m):
+        q, kk, rr = to(Qt[s:s + m]), to(kst[s:s + m]), to(rect[s:s + m])
+        st.append(ix.search_batch(q, kk, rr, kmax).stats.cpu().numpy())
+        feats.append(ix.features(q, kk, rr))
+    st = np.concatenate(st)
+    target = np.stack([st[:, 0], np.log2(1.0 + st[:, 1])], 1).astype(np.float32)
+    sched = pf.Scheduler(seed=2)
+    losses = sched.train(torch.cat(feats), to(target), epochs=20, batch=512, lr=2e-3)
+    ix.set_scheduler(sched)
+    train_s = time.perf_counter() - t0
+    ix.search_batch(Qd, ksd, recd, kmax, autotune=True)
+    base = ix.search_batch(Qd, ksd, recd, kmax)
+    bst = base.stats.cpu().numpy()
+    cost = np.log2(1.0 + bst[:, 1])
+    pred = sched.predict(ix.features(Qd, ksd, recd)).cpu().numpy()[:, 1]
+    orders = {"fifo": dict(), "learned": dict(learned=True),
+              "true_cost_lpt": dict(order=to(np.argsort(-cost, kind="stable").astype(np.int32))),
+              "shortest_predicted_first": dict(order=to(np.argsort(pred, kind="stable").astype(np.int32)))}
+    out = {}
+    for name, kw in orders.items():
+        wall, ph, r = timed(lambda: ix.search_batch(Qd, ksd, recd, kmax, timing=True, **kw), ix, 1,
+                            max(1, min(3, args.steps)))
+        out[name] = {"ms_per_step": wall, "qps": m / (wall / 1e3), "search_kernel_ms": ph["search"],
+                     "ids_equal_fifo": bool(torch.equal(r.ids, base.ids))}
+        log(f"mixed batch {name}: {wall:.2f} ms/step, search kernel {ph['search']:.2f} ms")
+    # measured recall per (k, recall) against exact k-NN, on a stratified sample
+    ids = base.ids.cpu().numpy()
+    rng = np.random.default_rng(44)
+    per = {}
+    for k in (1, 10, 100):
+        for rc in (0.5, 0.9, 0.99):
+            sel = np.flatnonzero((ks == k) & (rec == rc))
+            sel = np.sort(rng.choice(sel, size=min(300, len(sel)), replace=False))
+            truth = truth_of(ix, Q[sel], k, dev)
+            per[f"k{k}_r{rc}"] = {"recall_measured": recall_of(ids[sel], truth, k), "sample": int(len(sel)),
+                                  "mean_stop_level": float(bst[sel, 0].mean())}
+    worst = min(v["recall_measured"] - float(key.split("_r")[1]) for key, v in per.items())
+    log("mixed batch recall per (k, recall): " + ", ".join(f"{a} {v['recall_measured']:.3f}" for a, v in per.items()))
+    return {"workload": "mixed-100k-on-1M-d100", "queries": m, "kmax": kmax, "orders": out,
+            "learned_vs_fifo": out["fifo"]["search_kernel_ms"] / out["learned"]["search_kernel_ms"],
+            "true_lpt_vs_fifo": out["fifo"]["search_kernel_ms"] / out["true_cost_lpt"]["search_kernel_ms"],
+            "spearman_pred_vs_true_cost": spearman(pred, cost),
+            "scheduler": {"train_queries": int(len(Qt)), "train_s": train_s, "loss_first": float(losses[0]),
+                          "loss_last": float(losses[-1])},
+            "recall_by_k_and_target": per, "min_recall_margin": worst,
+            "mean_counts": counts(bst),
+            "cost_spread_log2_scan": {p: float(np.percentile(cost, q)) for p, q in
+                                      (("p10", 10), ("p50", 50), ("p90", 90), ("max", 100))}}
+
+
+def leg_extras(dev, k, recall):
+    """Index options on mixture-1M-d100 (pooling, FHT cross-polytope codes) and the paper's
+    synthetic set."""
+    import torch
+
+    c = workloads.config(2, with_train=False)
+    X, Q, budget = c["points"], c["queries"], c["budget"]
+    out = {}
+    for name, kw in (("pooled_index", dict(pool=3072)), ("cross_polytope_index", dict(family=pf.PF_FAMILY_FHTCP))):
+        ix = pf.Index(torch.from_numpy(X).to(dev), budget, seed=workloads.INDEX_SEED, **kw)
+        info = ix.info()
+        m = len(Q)
+        Qd = torch.from_numpy(Q).to(dev)
+        ks = torch.full((m,), k, dtype=torch.int32, device=dev)
+        rc = torch.full((m,), recall, dtype=torch.float64, device=dev)
+        truth = truth_of(ix, Q[:1000], k, dev)
+        ix.search_batch(Qd, ks, rc, k, autotune=True)
+        res = {"L": info.L, "build_ms": info.build_ms}
+        rules = [("default_rule", pf.PF_RULE_FILTER)] + ([("algorithm3_rule", pf.PF_RULE_POOL)] if "pool" in kw else [])
+        for rname, rule in rules:
+            wall, ph, r = timed(lambda: ix.search_batch(Qd, ks, rc, k, rule=rule, timing=True), ix, 1, 3)
+            res[rname] = {"qps": m / (wall / 1e3), "search_kernel_ms": ph["search"],
+                          "normalize+hash_ms": ph["normalize+hash"],
+                          "recall_measured": recall_of(r.ids.cpu().numpy()[:1000], truth, k)}
+            log(f"{name} {rname}: kernel {ph['search']:.2f} ms, recall {res[rname]['recall_measured']:.4f}")
+        out[name] = res
+        del ix
+        torch.cuda.empty_cache()
+    X, Q = workloads.paper_synthetic(1_000_000, 100, 1000, 78)
+    ix = pf.Index(torch.from_numpy(X).to(dev), 2 << 30, seed=workloads.INDEX_SEED)
+    m = len(Q)
+    Qd = torch.from_numpy(Q).to(dev)
+    ks = torch.ones((m,), dtype=torch.int32, device=dev)
+    syn = {"workload": "paper-synthetic-1M-3x100", "L": ix.L, "targets": {}}
+    for rec in (0.5, 0.9, 0.99):
+        rc = torch.full((m,), rec, dtype=torch.float64, device=dev)
+        ix.search_batch(Qd, ks, rc, 1, autotune=True)
+        wall, ph, r = timed(lambda: ix.search_batch(Qd, ks, rc, 1, timing=True), ix, 1, 3)
+        st = r.stats.cpu().numpy()
+        syn["targets"][str(rec)] = {"x_n_found": float(np.mean(r.ids.cpu().numpy()[:, 0] == len(X) - 1)),
+                                    "mean_stop_level": float(st[:, 0].mean()), "search_kernel_ms": ph["search"]}
+    out["paper_synthetic"] = syn
+    return out
 
 
 def main():
@@ -453,29 +644,30 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--scale", type=float, default=1.0, help="shrink n and m (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--recall-sample", type=int, default=1000)
-    ap.add_argument("--paths", default="plain,batched_fifo_both_planes,batched_fifo,learned_batched",
-                    help="query paths to time (comma separated); the last one is the headline")
-    ap.add_argument("--train-frac", type=float, default=2.0,
-                    help="scheduler training queries as a multiple of the benchmark query count")
-    ap.add_argument("--no-pool", action="store_true",
-                    help="skip the pooled, cross-polytope and paper-synthetic measurements")
-    ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the mixed 100,000-query batch (per-query k and recall, queue orders)")
-    ap.add_argument("--workload", default="mixture-1M-d100", choices=["mixture-1M-d100", "mixture-10M-d128"],
-                    help="mixture-10M-d128: the learned scheduler's 10 M-point configuration (separate line)")
+    ap.add_argument("--legs", default=DEFAULT_LEGS,
+                    help="secondary measurements (comma separated; '' for none): " + DEFAULT_LEGS)
+    ap.add_argument("--extras", action="store_true",
+                    help="also the pooled and cross-polytope indexes and the paper's synthetic set")
+    ap.add_argument("--workload", default=HEADLINE, choices=sorted(WORKLOADS),
+                    help="headline workload (mixture-1M-d100: for counter runs of configuration 2)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
-    ap.add_argument("--compare-tiles", default="",
-                    help="only run the batched search of the benchmark workload with each listed tile "
-                         "shape (comma-separated indexes), twice in turn, and exit (for counter runs)")
+    ap.add_argument("--cpu-worker", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-L", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-build-threads", type=int, default=12, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker(args.cpu_worker, args.cpu_L, args.cpu_seconds, args.cpu_build_threads)
+        return
     if args.gpus != 1:
         print(f"bench.py: the search path runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not an implemented path", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py: --steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -491,147 +683,46 @@ def main():
         print(json.dumps({"copy_probe_bytes": x.numel() * 4}))
         return
 
-    if args.workload == "mixture-10M-d128":
-        workload_c5(args)
-        return
-
-    if args.compare_tiles:
-        tiles = [int(t) for t in args.compare_tiles.split(",")]
-        c = workloads.config(2, scale=args.scale)
-        ix = pf.Index(torch.from_numpy(c["points"]).cuda(), c["budget"], seed=workloads.INDEX_SEED)
-        Qd = torch.from_numpy(c["queries"]).cuda()
-        ks = torch.full((len(Qd),), c["k"], dtype=torch.int32, device="cuda")
-        rc = torch.full((len(Qd),), c["recall"], dtype=torch.float64, device="cuda")
-        for t in tiles + tiles:
-            ix.search_batch(Qd, ks, rc, c["k"], timing=True, tile=t)
-            print(json.dumps({"tile": t, "name": pf.pf_tile_name(t), "search_ms": ix.last_timing().search_ms}),
-                  flush=True)
-        return
-
-    log("generating workload")
-    c = workloads.config(2, scale=args.scale)
-    X, Q, k, recall, budget = c["points"], c["queries"], c["k"], c["recall"], c["budget"]
-    n, d = X.shape
-    m = len(Q)
     dev = torch.device("cuda:0")
-    Xd = torch.from_numpy(X).to(dev)
-    Qd = torch.from_numpy(Q).to(dev)
-    torch.cuda.synchronize()
-    ix = pf.Index(Xd, budget, seed=workloads.INDEX_SEED)
-    info = ix.info()
-    del Xd
-    log(f"index built: L={info.L} device build {info.build_ms:.1f} ms")
-
-    # learned scheduler: traces of the plain method on training queries from the same
-    # distribution (their own seed), features, training on the GPU (not timed)
-    t0 = time.perf_counter()
-    Qtr = workloads.queries_like(2, max(1, int(round(m * args.train_frac))), seed_offset=100)
-    rtr = ix.search(torch.from_numpy(Qtr).to(dev), k, recall)
-    st_tr = rtr.stats.cpu().numpy()
-    target = np.stack([st_tr[:, 0], np.log2(1.0 + st_tr[:, 1])], 1).astype(np.float32)
-    sched = pf.Scheduler(seed=1)
-    losses = sched.train(ix.features(torch.from_numpy(Qtr).to(dev)), torch.from_numpy(target).to(dev),
-                         epochs=20, batch=512, lr=2e-3)
-    ix.set_scheduler(sched)
-    train_s = time.perf_counter() - t0
-    log(f"scheduler trained on {len(Qtr)} traces in {train_s:.1f} s, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
-
-    ks_d = torch.full((m,), k, dtype=torch.int32, device=dev)
-    rec_d = torch.full((m,), recall, dtype=torch.float64, device=dev)
-    modes = {
-        "plain": lambda: ix.search(Qd, k, recall, timing=True),
-        "batched_fifo": lambda: ix.search_batch(Qd, ks_d, rec_d, k, timing=True),
-        "batched_fifo_both_planes": lambda: ix.search_batch(Qd, ks_d, rec_d, k, timing=True, prefilter=False),
-        "learned_batched": lambda: ix.search_batch(Qd, ks_d, rec_d, k, learned=True, timing=True),
-    }
-    ix.search_batch(Qd, ks_d, rec_d, k, autotune=True)  # pick the batched tile shape once
-    res = {}
-    wanted = [p for p in args.paths.split(",") if p]
-    for name in wanted:
-        fn = modes[name]
-        for _ in range(args.warmup):
-            r = fn()
-        torch.cuda.synchronize()
-        search_ms, hash_ms, ranges_ms, order_ms = [], [], [], []
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            r = fn()
-            tm = ix.last_timing()
-            search_ms.append(tm.search_ms)
-            hash_ms.append(tm.hash_ms)
-            ranges_ms.append(tm.ranges_ms)
-            order_ms.append(tm.order_ms)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        res[name] = dict(r=r, ms=wall / args.steps * 1e3, search_ms=search_ms, hash_ms=hash_ms,
-                         ranges_ms=ranges_ms, order_ms=order_ms, tile=tm.tile, waves=tm.waves_per_cu)
-        log(f"{name}: {res[name]['ms']:.3f} ms/step, search kernel {np.mean(search_ms):.3f} ms")
-    head = res[wanted[-1]]
-    r = head["r"]
-    ms_per_step = head["ms"]
-    qps = m / (ms_per_step / 1e3)
-    search_ms, hash_ms, ranges_ms, order_ms = head["search_ms"], head["hash_ms"], head["ranges_ms"], head["order_ms"]
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
-    stats = r.stats.cpu().numpy()
-    ids = r.ids.cpu().numpy()
-    ns = min(args.recall_sample, m)
-    Xn = torch.from_numpy(ix.export(pf.PF_EXPORT_POINTS)).to(dev)
-    Qn = torch.from_numpy(pf.pf_normalize(Q[:ns])).to(dev)
-    truth = exact_topk_gpu(Xn, Qn, k)
-    del Xn
-    rec = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(ids[:ns], truth)]))
-
-    A = algorithmic_bytes(stats, d, k, info.L, info.K)
-    avg_search_ms = float(np.mean(search_ms))
-    achieved = A / (avg_search_ms * 1e-3) / 1e9
-    tr = traffic_entry(pf.pf_tile_name(head["tile"]))
-    line = {
-        "metric": METRIC,
-        "value": qps,
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": c["name"], "n": n, "d": d, "queries": m, "k": k, "recall_target": recall,
-                   "budget_bytes": budget, "L": info.L, "K": info.K, "M": info.M, "B": 12,
-                   "path": wanted[-1]},
-        "paths_qps": {name: m / (v["ms"] / 1e3) for name, v in res.items()},
-        "paths_search_kernel_ms": {name: float(np.mean(v["search_ms"])) for name, v in res.items()},
-        "learned_vs_plain": (res["learned_batched"]["ms"] and res["plain"]["ms"] / res["learned_batched"]["ms"])
-        if "plain" in res and "learned_batched" in res else None,
-        "batched_tile": {"tile": head["tile"], "name": pf.pf_tile_name(head["tile"]), "waves_per_cu": head["waves"]},
-        "scheduler": {"train_queries": int(len(Qtr)), "train_s": train_s, "loss_first": float(losses[0]),
-                      "loss_last": float(losses[-1])},
-        "recall_measured": rec,
-        "recall_sample": ns,
-        "build_ms": info.build_ms,
-        "phase_ms": {"normalize+hash": float(np.mean(hash_ms)), "ranges": float(np.mean(ranges_ms)),
-                     "queue_order": float(np.mean(order_ms)), "search": avg_search_ms},
-        "stop_level_hist": np.bincount(stats[:, 0], minlength=info.K + 1).tolist(),
-        "mean_counts": {"c_scan": float(stats[:, 1].mean()), "c_pass": float(stats[:, 2].mean()),
-                        "c_rerank": float(stats[:, 3].mean()), "c_q8": float(stats[:, 6].mean()),
-                        "c_upper": float(stats[:, 5].mean()), "c_exact": float(stats[:, 4].mean())},
-        "roofline": {"kernel": "k_search", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
-                     "algorithmic_bytes_per_launch": A, "avg_launch_ms": avg_search_ms,
-                     "fp32_gather_bytes_per_launch": plain_gather_bytes(stats, d, k, info.L)},
-        "cpu_baseline": None,
-    }
-    log(f"recall {rec:.4f} on {ns} queries")
-    line["mixed_batch"] = None if args.no_mixed else mixed_batch(ix, dev, args)
-    if not args.no_pool:
-        del ix
-        line["pooled_index"] = pooled_index(X, Q, k, recall, budget, dev, truth)
-        line["cross_polytope_index"] = cp_index(X, Q, k, recall, budget, dev, truth)
-        line["paper_synthetic"] = paper_synthetic(dev)
+    t_start = time.perf_counter()
+    cpu = None
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(X, Q, budget, k, recall, args.cpu_seconds)
+        cfg = WORKLOADS[args.workload]
+        n, d = (10_000_000, 128) if cfg == 5 else (1_000_000, 100)
+        L, _ = pf.pf_plan_index(n, d, 16 << 30 if cfg == 5 else 2 << 30)
+        cpu = CpuBaseline(cfg, L, args.cpu_seconds)
+    line = headline(args, dev)
+    legs = set(args.legs.split(",")) if args.legs else set()
+    if args.workload != HEADLINE:
+        legs -= {"c2", "c5_norm"}
+    if "c5_norm" in legs:
+        out, ix, _ = leg_mixture(5, "norm", args, dev, 200_000)
+        line["c5_noise_norm"] = out
+        del ix
+        torch.cuda.empty_cache()
+    c2ix = None
+    if "c2" in legs:
+        line["c2"], c2ix, _ = leg_mixture(2, "coord", args, dev, 20_000)
+    if "c4" in legs:
+        if c2ix is None:
+            c2 = workloads.config(2, with_train=False)
+            c2ix = pf.Index(torch.from_numpy(c2["points"]).to(dev), c2["budget"], seed=workloads.INDEX_SEED)
+        line["c4_mixed"] = leg_mixed(c2ix, args, dev)
+    del c2ix
+    torch.cuda.empty_cache()
+    if "c2_norm" in legs:
+        out, ix, _ = leg_mixture(2, "norm", args, dev, 20_000)
+        line["c2_noise_norm"] = out
+        del ix
+        torch.cuda.empty_cache()
+    if "c3" in legs:
+        line["c3_planted"] = leg_planted(args, dev)
+    if args.extras:
+        line["extras"] = leg_extras(dev, 10, 0.9)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu.result()
+        line["gpu_vs_cpu_oracle"] = line["value"] / line["cpu_baseline"]["value"]
+    line["bench_wall_s"] = time.perf_counter() - t_start
     print(json.dumps(line), flush=True)
 
 
