@@ -240,6 +240,21 @@ int pf_search(pf_index *ix, const float *queries, int64_t m, int32_t k, double r
               int32_t *out_ids, float *out_ips, pf_query_stats *stats, int32_t mem,
               void *stream);
 
+/* pf_search without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as pf_search with default options, but every per-call device
+ * buffer (normalised and hashed queries, hashing scratch, decision tables, prefix ranges)
+ * lives in one static device array of the library, 64 MiB on each device that calls it,
+ * held until the process ends.  queries (m x d), out_ids (m x k), out_ips (m x k,
+ * nullable) and stats (m, nullable) are device pointers on the index's device; the call is
+ * ordered on `stream` and synchronises it before returning.  All calls on one device share
+ * that device's array: calls that overlap in time on one device race (one at a time per
+ * device).  Errors: as pf_search; PF_EUNSUPPORTED when the m queries' buffers exceed the
+ * 64 MiB array (e.g. about 6,000 queries at n = 10^6, d = 100, L = 100: split the batch);
+ * PF_EINVAL when the current device is not the index's. */
+int pf_search_noalloc(pf_index *ix, const float *queries, int64_t m, int32_t k, double recall,
+                      int32_t *out_ids, float *out_ips, pf_query_stats *stats, void *stream);
+
 /* pf_search with explicit options (opts may be NULL for the defaults). */
 int pf_search_ex(pf_index *ix, const float *queries, int64_t m, int32_t k, double recall,
                  const pf_search_opts *opts, int32_t *out_ids, float *out_ips,

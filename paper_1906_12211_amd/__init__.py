@@ -30,7 +30,7 @@ PF_BATCH_LEARNED, PF_BATCH_AUTOTUNE = 1, 2
 
 PF_SCHED_IN, PF_SCHED_OUT, PF_SCHED_PARAMS = 98, 2, 29442
 
-EXPORTED = ["pf_normalize", "pf_build_index", "pf_plan_index", "pf_search", "pf_search_ex", "pf_search_batch", "pf_hash",
+EXPORTED = ["pf_normalize", "pf_build_index", "pf_plan_index", "pf_search", "pf_search_ex", "pf_search_batch", "pf_search_noalloc", "pf_hash",
             "pf_export", "pf_index_info", "pf_last_timing", "pf_free_index", "pf_last_error", "pf_version",
             "pf_tile_count", "pf_tile_name", "pf_read_bandwidth",
             "pf_sched_create", "pf_sched_free", "pf_sched_params", "pf_features", "pf_sched_predict",
@@ -117,6 +117,8 @@ def lib():
         L.pf_search_ex.restype = ctypes.c_int
         L.pf_search_ex.argtypes = [_P, _P, _I64, _I32, _D, ctypes.POINTER(pf_search_opts), _P, _P, _P,
                                    _I32, _P]
+        L.pf_search_noalloc.restype = ctypes.c_int
+        L.pf_search_noalloc.argtypes = [_P, _P, _I64, _I32, _D, _P, _P, _P, _P]
         L.pf_search_batch.restype = ctypes.c_int
         L.pf_search_batch.argtypes = [_P, _P, _I64, _P, _P, _I32, ctypes.POINTER(pf_search_opts), _P, _P, _P,
                                       _P, _I32, _I32, _P]
@@ -314,6 +316,14 @@ class Index:
         _check(lib().pf_search_ex(self._h, pq, m, k, recall, ctypes.byref(opts), _buf(ids)[0],
                                   _buf(ips)[0], _buf(st)[0], mem, stream))
         return SearchResult(ids, ips, _stats_view(st) if st is not None else None)
+
+    def search_noalloc(self, queries, k: int, recall: float, out_ids, out_ips=None, stats=None) -> None:
+        """pf_search_noalloc: device tensors only; the caller provides the outputs (ids m x k
+        int32, ips m x k float32, stats m x 7 int64, the last two optional)."""
+        assert _is_torch(queries) and queries.is_cuda and queries.dtype == _torch_dtype("float32")
+        pq, _, stream = _buf(queries)
+        _check(lib().pf_search_noalloc(self._h, pq, queries.shape[0], int(k), float(recall), _buf(out_ids)[0],
+                                       _buf(out_ips)[0], _buf(stats)[0], stream))
 
     def search_batch(self, queries, ks, recalls, kmax: int, order=None, learned: bool = False,
                      autotune: bool = False, eps: float = 0.0, B: int = 12, rule: int = PF_RULE_FILTER,
