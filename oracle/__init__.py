@@ -25,6 +25,7 @@ DEFAULT_POOL = 3072
 DEFAULT_K = 24
 DEFAULT_M = 32
 DEFAULT_B = 12
+DEFAULT_GROUPS = 16  # stopping tests per level (at most L): the method's default parameter
 
 
 def build(verbose: bool = False) -> str:
@@ -92,12 +93,15 @@ def lib():
         L.oracle_stop.restype = ctypes.c_int
         L.oracle_stop.argtypes = [ctypes.c_float, _I32, _I32, _I32, _D, _I32, _I32, _I32, _P, _I32,
                                   ctypes.POINTER(_D)]
+        L.oracle_stop_partial.restype = ctypes.c_int
+        L.oracle_stop_partial.argtypes = [ctypes.c_float, _I32, _I32, _I32, _I32, _I32, _D, _I32, _I32, _I32, _P,
+                                          _I32, ctypes.POINTER(_D)]
         L.oracle_binom_cdf64.restype = _D
         L.oracle_binom_cdf64.argtypes = [_D, _I32]
         L.oracle_search.restype = ctypes.c_int
         L.oracle_search.argtypes = [
             _P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P, _I32, _P, _U64,
-            _P, _I64, _I32, _D, _D, _I32, _I32, _I32,
+            _P, _I64, _I32, _D, _D, _I32, _I32, _I32, _I32,
             _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
         ]
         L.oracle_bruteforce.restype = ctypes.c_int
@@ -256,6 +260,17 @@ def stop(ip_k: float, i: int, L: int, delta: float, rule: int = RULE_EXACT, M: i
     return bool(r), float(m.value)
 
 
+def stop_partial(ip_k: float, i: int, a: int, L: int, K: int, delta: float, rule: int = RULE_EXACT,
+                 M: int = DEFAULT_M, tau_int: int = 64, pool: int = 0, cptab: np.ndarray | None = None):
+    """The stopping test with the first a of L repetitions at level i and the rest at level
+    i + 1 (none taken when i = K)."""
+    m = _D()
+    tab = None if cptab is None else np.ascontiguousarray(cptab, dtype=np.float64)
+    ell = 0 if tab is None else tab.shape[1] - 1
+    r = lib().oracle_stop_partial(ip_k, i, a, L, M, K, delta, rule, tau_int, pool, _ptr(tab), ell, ctypes.byref(m))
+    return bool(r), float(m.value)
+
+
 def binom_cdf64(t: float, T: int) -> float:
     return float(lib().oracle_binom_cdf64(t, T))
 
@@ -336,9 +351,12 @@ class OracleIndex:
 
     def search(self, queries: np.ndarray, k: int, recall: float, eps: float = 0.0,
                B: int = DEFAULT_B, rule: int = RULE_FILTER, filter_on: bool = True,
-               trace: bool = False) -> SearchResult:
+               trace: bool = False, groups: int | None = None) -> SearchResult:
+        """groups: stopping tests per level (None: min(L, DEFAULT_GROUPS))."""
+        if groups is None:
+            groups = min(self.L, DEFAULT_GROUPS)
         return search_tables(self.points, self.hp, self.tcode, self.tidx, self.tsk, self.K, self.M, queries, k,
-                             recall, eps=eps, B=B, rule=rule, filter_on=filter_on, trace=trace,
+                             recall, eps=eps, B=B, rule=rule, filter_on=filter_on, trace=trace, groups=groups,
                              sel=getattr(self, "sel", None), pool=getattr(self, "pool", 0),
                              cptab=getattr(self, "cptab", None), seed=getattr(self, "seed", 0))
 
@@ -350,10 +368,12 @@ def search_tables(points: np.ndarray, hp: np.ndarray, tcode: np.ndarray, tidx: n
                   K: int, M: int, queries: np.ndarray, k: int, recall: float, eps: float = 0.0,
                   B: int = DEFAULT_B, rule: int = RULE_FILTER, filter_on: bool = True, trace: bool = False,
                   sel: np.ndarray | None = None, pool: int = 0, cptab: np.ndarray | None = None,
-                  seed: int = 0) -> SearchResult:
+                  seed: int = 0, groups: int = 1) -> SearchResult:
     """The adaptive query over given tables: normalised points (n x d), the hyperplanes
     the queries are hashed with, and the L sorted tables (codes, positions, table-local
-    sketches).  With trace=True the walk of query 0 is recorded: ``trace`` per level and
+    sketches).  groups: the stopping test runs after each of that many consecutive groups
+    of tables in a level (1: once per level).  With trace=True the walk of query 0 is
+    recorded: ``trace`` per level and
     table (lo_i, hi_i, c_lo, c_hi), ``levels`` per level (threshold used, masks of the new,
     passing and top-k point ids, c_scan, c_pass, c_rerank, stopped)."""
     points = np.ascontiguousarray(points, dtype=np.float32)
@@ -382,7 +402,7 @@ def search_tables(points: np.ndarray, hp: np.ndarray, tcode: np.ndarray, tidx: n
     rc = lib().oracle_search(
         _ptr(points), n, d, _ptr(hp), _ptr(tcode), _ptr(tidx), _ptr(tsk), L, K, M, _ptr(sel), pool,
         _ptr(tab), seed, _ptr(q), m, k, recall, eps, B, rule,
-        1 if filter_on else 0, _ptr(ids), _ptr(ips), _ptr(ips64), _ptr(sl), _ptr(cs),
+        1 if filter_on else 0, int(groups), _ptr(ids), _ptr(ips), _ptr(ips64), _ptr(sl), _ptr(cs),
         _ptr(cp), _ptr(cr), _ptr(bd), _ptr(tr), _ptr(lt))
     if rc:
         raise ValueError(f"oracle_search rc={rc}")

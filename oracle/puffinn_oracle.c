@@ -490,8 +490,12 @@ double oracle_binom_cdf64(double t, int32_t T) {
     return s < 1.0 ? s : 1.0;
 }
 
-/* Stopping test after all L repetitions of level i have been inspected (Sec. 4.1: "the
- * termination criterion is checked after all repetitions are inspected").
+/* Stopping test once the first a of the L repetitions have taken level i's entries and
+ * the other L - a are still at level i + 1 (none taken yet when i = K); a = L is the test
+ * after all repetitions of the level have been inspected (Sec. 4.1), a < L the test that
+ * Algorithm 1 makes after each repetition j = a.  Each repetition contributes the
+ * collision probability of its own prefix length: p^i for the first a, p^(i+1) for the
+ * rest (the windows of Lemma 1's proof are independent across repetitions).
  * OR_RULE_EXACT stops when the failure bound of Lemma 1's proof, (1 - p^i)^L, is at
  * most delta, evaluated as L * log1p(-p^i) <= ln(delta) with ln p = log1p(-theta/pi)
  * and p^i = exp(i ln p).  OR_RULE_ALG1 stops when L >= ln(1/delta) / p^i, the test
@@ -516,50 +520,66 @@ double oracle_binom_cdf64(double t, int32_t T) {
  * the tabulated collision probability of the i-bit prefix (oracle_cp_prob); the filter's
  * q stays the hyperplane sketches' own.  *margin receives the signed distance of the two sides (term -
  * threshold; for OR_RULE_POOL minus the smaller of the two slacks), <= 0 to stop. */
-int oracle_stop(float ip_k, int32_t i, int32_t L, int32_t M, double delta, int32_t rule,
-                int32_t tau_int, int32_t pool, const double *cptab, int32_t ell, double *margin) {
+int oracle_stop_partial(float ip_k, int32_t i, int32_t a, int32_t L, int32_t M, int32_t K, double delta,
+                        int32_t rule, int32_t tau_int, int32_t pool, const double *cptab, int32_t ell,
+                        double *margin) {
     double theta = acos(clamp1((double)ip_k));
     double lnp = log1p(-theta / OR_PI);
     /* collision probability of an i-bit prefix: p^i for hyperplane bits, the Monte Carlo
        table for FHT cross-polytope codes (cptab != NULL) */
     double pi_ = cptab ? oracle_cp_prob(cptab, ell, ip_k, i) : exp((double)i * lnp);
+    /* the tables after the first a are at level i + 1 (nothing taken yet when i = K) */
+    const int32_t rest = L - a;
+    const int deeper = rest > 0 && i < K;
+    double pi1 = 0.0;
+    if (deeper) pi1 = cptab ? oracle_cp_prob(cptab, ell, ip_k, i + 1) : exp((double)(i + 1) * lnp);
     double lnd = log(delta);
     if (rule == OR_RULE_POOL) {
+        /* Algorithm 3's test counts the tries inspected at the current prefix length */
         const double p = 1.0 - theta / OR_PI;
-        const double a = (double)L * pi_ - 2.0, b = (double)pool * p - 5.0 * (double)i * (double)i;
-        const double slack = a < b ? a : b;
+        const double sa = (double)a * pi_ - 2.0, sb = (double)pool * p - 5.0 * (double)i * (double)i;
+        const double slack = sa < sb ? sa : sb;
         if (margin) *margin = -slack;
         return slack >= 0.0;
     }
     if (rule == OR_RULE_ALG1) {
-        /* L * p^i >= -ln(delta) */
-        double lhs = (double)L * pi_;
+        /* Algorithm 1's test with j = a repetitions done at prefix length i: j p^i >= -ln(delta) */
+        double lhs = (double)a * pi_;
         if (margin) *margin = -lnd - lhs;
         return lhs >= -lnd;
     }
+    const double l1p = log1p(-pi_), l1p1 = deeper ? log1p(-pi1) : 0.0;
     if (rule == OR_RULE_FILTER) {
         const double q = oracle_binom_cdf64(theta / OR_PI, tau_int);
-        const double l1p = log1p(-pi_);
         double term = 0.0;
         for (int32_t s = 0; s < M && s < L; ++s) {
+            /* tables j = s, s + M, ... read sketch s: those below a are at level i */
             const int32_t g = L / M + (s < L % M ? 1 : 0);
-            const double a = (double)g * l1p;
-            const double x = q * expm1(a);
-            term += (x > -0.5) ? log1p(x) : log((1.0 - q) + q * exp(a));
+            const int32_t gi = a / M + (s < a % M ? 1 : 0);
+            /* (a count of zero contributes nothing, also where log1p(-p^l) = -inf at p = 1) */
+            const double e = (gi > 0 ? (double)gi * l1p : 0.0) + (g - gi > 0 ? (double)(g - gi) * l1p1 : 0.0);
+            const double x = q * expm1(e);
+            term += (x > -0.5) ? log1p(x) : log((1.0 - q) + q * exp(e));
         }
         if (margin) *margin = term - lnd;
         return term <= lnd;
     }
-    double term = (double)L * log1p(-pi_);
+    double term = (a > 0 ? (double)a * l1p : 0.0) + (rest > 0 ? (double)rest * l1p1 : 0.0);
     if (margin) *margin = term - lnd;
     return term <= lnd;
+}
+
+int oracle_stop(float ip_k, int32_t i, int32_t L, int32_t M, double delta, int32_t rule,
+                int32_t tau_int, int32_t pool, const double *cptab, int32_t ell, double *margin) {
+    return oracle_stop_partial(ip_k, i, L, L, M, i, delta, rule, tau_int, pool, cptab, ell, margin);
 }
 
 /* ------------------------------------------------------------------------------------
  * The adaptive query (Algorithm 1, adaptive-kNN(q, k, delta), realised on sorted arrays
  * as in Sec. 4.1-4.2).  Readings taken where the paper leaves freedom:
  *  - rounds are level-synchronous: in level i every repetition j = 1..L contributes its
- *    new entries, then the stopping test runs once (Sec. 4.1);
+ *    new entries, with the stopping test after each of `groups` consecutive groups of
+ *    repetitions (once per level, as in Sec. 4.1, when groups = 1);
  *  - the filter threshold tau_i is fixed for the whole level from the top-k as it stood
  *    before the level (64, i.e. no filtering, while fewer than k points are known);
  *  - retrieval (Sec. 4.2 and App. C): per repetition a consumed window [c_lo, c_hi)
@@ -666,7 +686,7 @@ static int accumulate(or_list *top, const or_list *fresh, int32_t k) {
 
 static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, const uint64_t *qsk,
                     int32_t k, double delta, double eps, int32_t B, int32_t rule, int32_t filter_on,
-                    int64_t *clo, int64_t *chi, or_list *top, or_list *fresh,
+                    int32_t groups, int64_t *clo, int64_t *chi, or_list *top, or_list *fresh,
                     int32_t *stop_level, int64_t *cnt, int32_t *boundary, int64_t *trace,
                     int64_t *ltrace) {
     const int64_t n = ix->n;
@@ -695,8 +715,11 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
         }
         int64_t *lt = ltrace ? ltrace + (int64_t)i * OR_LT_W : NULL;
         if (lt) lt[0] = tau_int;
+        /* the repetitions in `groups` consecutive groups; the stopping test after each */
+        for (int32_t gi = 0; gi < groups; ++gi) {
+        const int32_t j0 = (int32_t)((int64_t)gi * L / groups), j1 = (int32_t)((int64_t)(gi + 1) * L / groups);
         fresh->len = 0;
-        for (int32_t j = 0; j < L; ++j) {
+        for (int32_t j = j0; j < j1; ++j) {
             const uint32_t *tc = ix->tcode + (int64_t)j * n;
             const uint32_t *ti = ix->tidx + (int64_t)j * n;
             const uint64_t *ts = ix->tsk + (int64_t)j * n;
@@ -754,8 +777,8 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
         }
         if (top->len == k) {
             double margin;
-            int stop = oracle_stop(top->v[k - 1].ip, i, L, ix->M, delta, rule, tau_int, ix->pool, ix->cptab, ix->ell,
-                                   &margin);
+            int stop = oracle_stop_partial(top->v[k - 1].ip, i, j1, L, ix->M, K, delta, rule, tau_int, ix->pool,
+                                           ix->cptab, ix->ell, &margin);
             if (fabs(margin) < 1e-9 * (1.0 + fabs(log(delta)))) *boundary = 1;
             if (ix->cptab) {
                 /* the table lookup changes cell at grid points of the similarity */
@@ -767,6 +790,7 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
                 if (lt) lt[7] = 1;
                 return OR_OK;
             }
+        }
         }
     }
     /* level 0: linear scan, every point re-ranked */
@@ -803,15 +827,21 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
  * FP32 ip against an FP64 threshold computed with a different libm may then differ).
  * trace (nullable) records the walk of query 0 only: (K+1) x L x 4 int64; ltrace
  * (nullable) the same query's levels, (K+1) x OR_LT_W int64 (see walk_one).
+ * groups (1..L): the repetitions of a level are taken in `groups` consecutive groups,
+ * group g holding repetitions floor(g L / groups) .. floor((g+1) L / groups) - 1, and the
+ * stopping test (oracle_stop_partial, a = the repetitions done) runs after each group: 1
+ * is the test once per level of Sec. 4.1, L the test after every repetition of
+ * Algorithm 1.  The filter threshold stays fixed for the whole level.
  * Returns 0, OR_EINVAL (bad arguments or a zero / non-finite query row), OR_ENOMEM. */
 int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, const uint32_t *tcode,
                   const uint32_t *tidx, const uint64_t *tsk, int32_t L, int32_t K, int32_t M,
                   const int32_t *sel, int32_t pool, const double *cptab, uint64_t cp_seed,
                   const float *queries, int64_t m, int32_t k, double recall, double eps, int32_t B,
-                  int32_t rule, int32_t filter_on, int32_t *ids, float *ips, double *ips64,
+                  int32_t rule, int32_t filter_on, int32_t groups, int32_t *ids, float *ips, double *ips64,
                   int32_t *stop_level, int64_t *c_scan, int64_t *c_pass, int64_t *c_rerank,
                   int32_t *boundary, int64_t *trace, int64_t *ltrace) {
-    if (n < 1 || d < 1 || L < 1 || K < 1 || K > 32 || M < 1 || m < 0 || k < 1 || k > n || B < 1)
+    if (n < 1 || d < 1 || L < 1 || K < 1 || K > 32 || M < 1 || m < 0 || k < 1 || k > n || B < 1 || groups < 1 ||
+        groups > L)
         return OR_EINVAL;
     if (rule == OR_RULE_POOL && (pool < 1 || cptab)) return OR_EINVAL;
     if (!(recall > 0.0 && recall <= 1.0)) return OR_EINVAL;
@@ -855,7 +885,7 @@ int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, co
             for (int32_t s = 0; s < M; ++s) mysk[s] = qs[(int64_t)s * m + t];
             int64_t cnt[3];
             int32_t sl = 0, bd = 0;
-            int rc = walk_one(&ix, qn + t * d, mycode, mysk, k, delta, eps, B, rule, filter_on, clo, chi,
+            int rc = walk_one(&ix, qn + t * d, mycode, mysk, k, delta, eps, B, rule, filter_on, groups, clo, chi,
                               &top, &fresh, &sl, cnt, &bd, t == 0 ? trace : NULL,
                               t == 0 ? ltrace : NULL);
             if (rc) {

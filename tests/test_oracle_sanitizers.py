@@ -2,7 +2,8 @@
 only): a small driver links puffinn_oracle.c, builds indexes (independent, pooled and
 cross-polytope functions) over seeded random points and runs searches under every stopping
 rule, at B = 1, 12 and a segment larger than the table, with the filter on and off, k = 1
-and k = n, recall 1 (linear scan), and the level trace; any invalid access, leak or
+and k = n, recall 1 (linear scan), the stopping test after 1 to L groups of tables, and
+the level trace; any invalid access, leak or
 undefined operation aborts the run with a sanitizer report."""
 import os
 import shutil
@@ -35,7 +36,8 @@ void oracle_table_sketches(const uint32_t *tidx, const uint64_t *sketches, int64
 int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, const uint32_t *tcode,
                   const uint32_t *tidx, const uint64_t *tsk, int32_t L, int32_t K, int32_t M, const int32_t *sel,
                   int32_t pool, const double *cptab, uint64_t cp_seed, const float *queries, int64_t m, int32_t k,
-                  double recall, double eps, int32_t B, int32_t rule, int32_t filter_on, int32_t *ids, float *ips,
+                  double recall, double eps, int32_t B, int32_t rule, int32_t filter_on, int32_t groups,
+                  int32_t *ids, float *ips,
                   double *ips64, int32_t *stop_level, int64_t *c_scan, int64_t *c_pass, int64_t *c_rerank,
                   int32_t *boundary, int64_t *trace, int64_t *ltrace);
 int oracle_bruteforce(const float *points, int64_t n, int32_t d, const float *queries, int64_t m, int32_t k,
@@ -98,7 +100,7 @@ int main(void) {
                     const double rc = rule == 3 ? 0.5 : recs[b];
                     const int rc_ = oracle_search(X, n, d, hp, tcode, tidx, tsk, L, K, M, sel, pool, cptab, 42, Q, m,
                                                   k, rc, 0.1 * b, Bs[(a + b) % 3], rule, (a + b + rule) % 2 == 0,
-                                                  ids, ips, ip64, stop, cs, cp, cr, bd, tr, lt);
+                                                  1 + (a * 3 + b) % L, ids, ips, ip64, stop, cs, cp, cr, bd, tr, lt);
                     if (rc_) return 6;
                     ++runs;
                 }
