@@ -115,11 +115,20 @@ typedef struct {
                           t + 1: shape t, 0 <= t < pf_tile_count()
                           (results are the same for every shape, only the speed differs);
                           PF_EINVAL beyond the count                                      */
+    int32_t groups;    /* G: the L repetitions of a level are taken in G consecutive groups
+                          (group g: repetitions floor(g L / G) .. floor((g+1) L / G) - 1)
+                          and the stopping test runs after each group, with the
+                          repetitions not yet at the level counted at the previous one:
+                          1 = once per level (Sec. 4.1), L = after every repetition
+                          (Algorithm 1); 0 selects the default, min(L, 16); at most
+                          min(L, 64), PF_EINVAL beyond                                    */
 } pf_search_opts;
 
 typedef struct {
     int32_t stop_level; /* prefix length at which the query stopped (0 = linear scan) */
-    int32_t reserved;
+    int32_t wave_us;    /* microseconds the query occupied its wave (from taking it off the
+                           queue to writing its results; the device's constant clock; not
+                           part of the method) */
     int64_t c_scan;   /* entries taken from the sorted arrays                        */
     int64_t c_pass;   /* entries that passed the sketch filter (with multiplicity)   */
     int64_t c_rerank; /* candidates re-ranked (with multiplicity; + n at a linear scan) */
@@ -150,14 +159,17 @@ typedef struct {
                              features, network and sort, or the upload of a caller's order)
                              and the autotuner when asked; ranges_ms covers the decision
                              tables and the prefix ranges                                 */
+    int64_t slots;        /* query waves the search kernel was launched with             */
+    int32_t groups;       /* stopping tests per level the call used (pf_search_opts.groups) */
 } pf_timing;
 
 /* Measurement aid (not part of the method): the best read rate, in GB/s (10^9 bytes per
- * second), of `reps` timed launches (after one warm-up) of a plain read-only streaming
- * kernel over a device buffer of `bytes` bytes that the call allocates, fills and frees
- * on the current device -- the read bandwidth that the device's memory system delivers
- * to a fully coalesced access pattern, against which the search kernel's rate is also
- * reported.  PF_EINVAL for bytes < 1 MiB, reps < 1 or gbs NULL; PF_ENOMEM, PF_EDEVICE.
+ * second), of a plain read-only streaming kernel (16-byte loads, four in flight per lane,
+ * plain or non-temporal, 2, 8 or 32 workgroups of 256 lanes per CU; `reps` timed launches
+ * of each after one warm-up) over a device buffer of `bytes` bytes that the call
+ * allocates, fills and frees on the current device -- the read bandwidth that the
+ * device's memory system delivers to a fully coalesced access pattern, against which the
+ * search kernel's rate is also reported.  PF_EINVAL for bytes < 1 MiB, reps < 1 or gbs NULL; PF_ENOMEM, PF_EDEVICE.
  * Synchronises `stream`. */
 int pf_read_bandwidth(uint64_t bytes, int32_t reps, double *gbs, void *stream);
 

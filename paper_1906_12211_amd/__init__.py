@@ -52,11 +52,11 @@ class pf_build_opts(ctypes.Structure):
 class pf_search_opts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("B", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("no_filter", ctypes.c_int32), ("timing", ctypes.c_int32), ("no_prefilter", ctypes.c_int32),
-                ("tile", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("groups", ctypes.c_int32)]
 
 
 class pf_query_stats(ctypes.Structure):
-    _fields_ = [("stop_level", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("stop_level", ctypes.c_int32), ("wave_us", ctypes.c_int32),
                 ("c_scan", ctypes.c_int64), ("c_pass", ctypes.c_int64), ("c_rerank", ctypes.c_int64),
                 ("c_exact", ctypes.c_int64), ("c_upper", ctypes.c_int64), ("c_q8", ctypes.c_int64)]
 
@@ -72,7 +72,7 @@ class pf_timing(ctypes.Structure):
     _fields_ = [("normalize_ms", ctypes.c_double), ("hash_ms", ctypes.c_double),
                 ("ranges_ms", ctypes.c_double), ("search_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("tile", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("order_ms", ctypes.c_double)]
+                ("order_ms", ctypes.c_double), ("slots", ctypes.c_int64), ("groups", ctypes.c_int32)]
 
 
 _lib = None
@@ -240,6 +240,7 @@ class SearchResult:
     ids: object
     ips: object
     stats: object  # (m, 7) int64: stop_level, c_scan, c_pass, c_rerank, c_exact, c_upper, c_q8
+    wave_us: object = None  # (m,) int64: microseconds each query occupied its wave
 
     @property
     def stop_level(self):
@@ -247,7 +248,8 @@ class SearchResult:
 
 
 def _stats_view(raw):
-    """pf_query_stats array (m x 56 bytes) as (m, 7) int64 columns."""
+    """pf_query_stats array (m x 56 bytes) as (m, 7) int64 columns (the first holds the
+    stop level; the wave time, in its upper 32 bits, is split off by _wave_us)."""
     if _is_torch(raw):
         s = raw.clone()
         s[:, 0] = s[:, 0] & 0xFFFFFFFF
@@ -255,6 +257,10 @@ def _stats_view(raw):
     s = raw.copy()
     s[:, 0] &= 0xFFFFFFFF
     return s
+
+
+def _wave_us(raw):
+    return raw[:, 0] >> 32
 
 
 class Index:
@@ -303,19 +309,21 @@ class Index:
     def search(self, queries, k: int, recall: float, eps: float = 0.0, B: int = 12,
                rule: int = PF_RULE_FILTER, filter: bool = True, timing: bool = False,
                want_ips: bool = True, want_stats: bool = True, prefilter: bool = True,
-               tile: int = None) -> SearchResult:
-        """tile: kernel tile shape index (None: the default shape)."""
+               tile: int = None, groups: int = 0) -> SearchResult:
+        """tile: kernel tile shape index (None: the default shape); groups: stopping tests per
+        level (0: the library's default)."""
         q = _f32(queries)
         m = q.shape[0]
         ids = _empty_like_input(q, (m, k), np.int32, _torch_dtype("int32"))
         ips = _empty_like_input(q, (m, k), np.float32, _torch_dtype("float32")) if want_ips else None
         st = _empty_like_input(q, (m, 7), np.int64, _torch_dtype("int64")) if want_stats else None
         opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1,
-                              0 if tile is None else tile + 1)
+                              0 if tile is None else tile + 1, int(groups))
         pq, mem, stream = _buf(q)
         _check(lib().pf_search_ex(self._h, pq, m, k, recall, ctypes.byref(opts), _buf(ids)[0],
                                   _buf(ips)[0], _buf(st)[0], mem, stream))
-        return SearchResult(ids, ips, _stats_view(st) if st is not None else None)
+        return SearchResult(ids, ips, _stats_view(st) if st is not None else None,
+                            _wave_us(st) if st is not None else None)
 
     def search_noalloc(self, queries, k: int, recall: float, out_ids, out_ips=None, stats=None) -> None:
         """pf_search_noalloc: device tensors only; the caller provides the outputs (ids m x k
@@ -328,7 +336,7 @@ class Index:
     def search_batch(self, queries, ks, recalls, kmax: int, order=None, learned: bool = False,
                      autotune: bool = False, eps: float = 0.0, B: int = 12, rule: int = PF_RULE_FILTER,
                      filter: bool = True, timing: bool = False, prefilter: bool = True,
-                     tile: int = None) -> SearchResult:
+                     tile: int = None, groups: int = 0) -> SearchResult:
         """One persistent launch over all queries with per-query k and recall (work queue);
         tile: kernel tile shape index (None: the autotuned or cached shape)."""
         q = _f32(queries)
@@ -351,13 +359,13 @@ class Index:
         ips = _empty_like_input(q, (m, kmax), np.float32, _torch_dtype("float32"))
         st = _empty_like_input(q, (m, 7), np.int64, _torch_dtype("int64"))
         opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1,
-                              0 if tile is None else tile + 1)
+                              0 if tile is None else tile + 1, int(groups))
         flags = (PF_BATCH_LEARNED if learned else 0) | (PF_BATCH_AUTOTUNE if autotune else 0)
         pq, mem, stream = _buf(q)
         _check(lib().pf_search_batch(self._h, pq, m, _buf(ks_a)[0], _buf(rec_a)[0], kmax, ctypes.byref(opts),
                                      _buf(ord_a)[0], _buf(ids)[0], _buf(ips)[0], _buf(st)[0], flags, mem,
                                      stream))
-        return SearchResult(ids, ips, _stats_view(st))
+        return SearchResult(ids, ips, _stats_view(st), _wave_us(st))
 
     def hash(self, x):
         x = _f32(x)

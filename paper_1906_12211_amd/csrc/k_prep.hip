@@ -209,20 +209,27 @@ void launch_rows8(const float *X, int64_t n, int32_t dpad, uint8_t *out, uint8_t
 
 // Read-only streaming kernel (a measurement aid, not part of the method): every lane reads
 // 16-byte words, four in flight, grid-stride over the buffer, and folds them into one
-// word that is stored only if it equals a constant, so the loads cannot be removed.  Its
-// rate is the read bandwidth a plain streaming access pattern reaches on the device.
+// word that is stored only if it equals a constant, so the loads cannot be removed.  NT:
+// non-temporal loads (streamed past the caches).  Its rate is the read bandwidth a plain
+// streaming access pattern reaches on the device.
+template <bool NT>
 __global__ __launch_bounds__(256) void k_read_stream(const uint4 *__restrict__ p, int64_t n16,
                                                      uint32_t *__restrict__ sink) {
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const v4u *q = reinterpret_cast<const v4u *>(p);
     const int64_t stride = (int64_t)gridDim.x * 256;
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     uint32_t acc = 0;
     for (; i + 3 * stride < n16; i += 4 * stride) {
-        const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
-        acc ^= (a.x ^ a.y ^ a.z ^ a.w) ^ (b.x ^ b.y ^ b.z ^ b.w) ^ (c.x ^ c.y ^ c.z ^ c.w) ^ (d.x ^ d.y ^ d.z ^ d.w);
+        v4u v[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) v[f] = NT ? __builtin_nontemporal_load(q + i + f * stride) : q[i + f * stride];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc ^= v[f].x ^ v[f].y ^ v[f].z ^ v[f].w;
     }
     for (; i < n16; i += stride) {
-        const uint4 a = p[i];
-        acc ^= a.x ^ a.y ^ a.z ^ a.w;
+        const v4u v = q[i];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
     if (acc == 0x9E3779B9u) sink[threadIdx.x] = acc;
 }
@@ -233,22 +240,30 @@ double read_bandwidth_gbs(uint64_t bytes, int32_t reps, int32_t num_cus, hipStre
     buf.alloc((size_t)n16 * 16);
     sink.alloc(256 * sizeof(uint32_t));
     launch_fill_u32(buf.as<uint32_t>(), n16 * 4, 0x01020304u, s);
-    const unsigned blocks = (unsigned)std::max(1, num_cus) * 8u;
     hipEvent_t e0, e1;
     PF_HIP(hipEventCreate(&e0));
     PF_HIP(hipEventCreate(&e1));
     float best = 0.0f;
-    for (int32_t r = 0; r <= reps; ++r) { // launch 0 warms up
-        PF_HIP(hipEventRecord(e0, s));
-        hipLaunchKernelGGL(k_read_stream, dim3(blocks), dim3(256), 0, s, buf.as<const uint4>(), n16,
-                           sink.as<uint32_t>());
-        PF_HIP(hipGetLastError());
-        PF_HIP(hipEventRecord(e1, s));
-        PF_HIP(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        PF_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (r > 0 && (best == 0.0f || ms < best)) best = ms;
-    }
+    // the best of plain and non-temporal loads at 2, 8 and 32 workgroups per CU
+    for (int nt = 0; nt < 2; ++nt)
+        for (int per_cu : {2, 8, 32}) {
+            const unsigned blocks = (unsigned)std::max(1, num_cus) * (unsigned)per_cu;
+            for (int32_t r = 0; r <= reps; ++r) { // launch 0 warms up
+                PF_HIP(hipEventRecord(e0, s));
+                if (nt)
+                    hipLaunchKernelGGL(k_read_stream<true>, dim3(blocks), dim3(256), 0, s, buf.as<const uint4>(), n16,
+                                       sink.as<uint32_t>());
+                else
+                    hipLaunchKernelGGL(k_read_stream<false>, dim3(blocks), dim3(256), 0, s, buf.as<const uint4>(),
+                                       n16, sink.as<uint32_t>());
+                PF_HIP(hipGetLastError());
+                PF_HIP(hipEventRecord(e1, s));
+                PF_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                PF_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (r > 0 && (best == 0.0f || ms < best)) best = ms;
+            }
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return (double)n16 * 16.0 / ((double)best * 1e-3) / 1e9;

@@ -30,10 +30,14 @@ namespace pf {
 // query waves per SIMD the register allocation must allow (1 = no constraint), LATE:
 // point ids read for passing entries only, one chunk late (else for every scanned
 // entry, with its sketch); SH: the kernel is built for summary rows without header (one
-// scale for all rows); DT = 64-float chunks per row (0 = any length).
+// scale for all rows); NT: sketches and summary rows are read with non-temporal loads
+// (streamed past the caches: neither is read again by the same query); DT = 64-float
+// chunks per row (0 = any length).
 static constexpr int WV = 64; // lanes per query wave
-template <int EPT_, int U_, int WPE_ = 1, bool LATE_ = false, int UQ_ = U_, bool SH_ = false> struct Tile {
+template <int EPT_, int U_, int WPE_ = 1, bool LATE_ = false, int UQ_ = U_, bool SH_ = false, int NT_ = 0>
+struct Tile {
     static constexpr int EPT = EPT_;
+    static constexpr int NT = NT_; // 1: sketch loads non-temporal, 2: sketch and summary-row loads
     static constexpr bool SH = SH_; // summary rows without header: one scale s8, sums up to a8
     static constexpr int U = U_;
     static constexpr int UQ = UQ_; // rows in flight per 16-lane group when bounding from 8-bit summaries
@@ -73,13 +77,33 @@ struct SearchK {
     int32_t kconst, kmax;
     const int32_t *qtab; // per-query row of stopw (nullable: 0)
     const float *tauv, *stopw;
+    int32_t G;           // groups of repetitions per level, the stopping test after each (1..64)
     int32_t filter;
     unsigned int *queue;  // work-queue counter (nullable: static assignment)
     const int32_t *order; // queue position -> query (nullable: identity)
     int32_t *out_ids;
     float *out_ips;
     pf_query_stats *stats;
+    float us_per_tick; // microseconds per tick of the device's constant clock (wall_clock64)
 };
+
+// loads that stream past the caches when NT is set (each sketch and summary row is read
+// once per query)
+template <bool NT> __device__ __forceinline__ uint64_t ld_u64(const uint64_t *ptr) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(ptr);
+    else
+        return *ptr;
+}
+template <bool NT> __device__ __forceinline__ uint2 ld_u2(const uint8_t *ptr) {
+    if constexpr (NT) {
+        typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+        const v2u t = __builtin_nontemporal_load(reinterpret_cast<const v2u *>(ptr));
+        return make_uint2(t.x, t.y);
+    } else {
+        return *reinterpret_cast<const uint2 *>(ptr);
+    }
+}
 
 __device__ __forceinline__ float key_ip(unsigned long long key) { return float_of((uint32_t)(key >> 32)); }
 __device__ __forceinline__ uint32_t key_id(unsigned long long key) { return 0xFFFFFFFFu - (uint32_t)key; }
@@ -506,7 +530,7 @@ template <int S, int N> __device__ __forceinline__ void tsum_rows(int32_t *a, in
 // header (s, A) of the row it ends with.
 constexpr float kH8 = 0.5f + 1.52587890625e-05f;
 constexpr float kAbs8 = 3.0517578125e-05f;
-template <int U, bool SH>
+template <int U, bool SH, bool NT>
 __device__ __forceinline__ float bound8_row(const SearchK &p, const WLds &l, const uint32_t *ids, int r,
                                             float qt, int32_t qB) {
     const uint8_t *q8 = reinterpret_cast<const uint8_t *>(l.q8);
@@ -528,7 +552,7 @@ __device__ __forceinline__ float bound8_row(const SearchK &p, const WLds &l, con
         const uint2 qq = *reinterpret_cast<const uint2 *>(q8 + off);
         uint2 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = *reinterpret_cast<const uint2 *>(p.Xq + (int64_t)ids[u] * p.rq + off);
+        for (int u = 0; u < U; ++u) v[u] = ld_u2<NT>(p.Xq + (int64_t)ids[u] * p.rq + off);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             acc[u] = __builtin_amdgcn_sdot4((int)v[u].x, (int)qq.x, acc[u], false);
@@ -546,7 +570,7 @@ __device__ __forceinline__ float bound8_row(const SearchK &p, const WLds &l, con
 // One pruning pass over ids[0..rc): rows whose bound (from the 8-bit summaries, Q8, or
 // from the upper plane) is below the k-th inner product ipk could not enter the top-k;
 // the rest are compacted, in order, to the front of ids.  Returns their count.
-template <int DT, int U, bool Q8, bool SH = false>
+template <int DT, int U, bool Q8, bool SH = false, bool NT = false>
 __device__ int prune_rows(const SearchK &p, const WLds &l, uint32_t *ids, int rc, float ipk, const QState &st) {
     constexpr int RROWS = 4 * U;
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
@@ -561,7 +585,7 @@ __device__ int prune_rows(const SearchK &p, const WLds &l, uint32_t *ids, int rc
         uint32_t myx = x[0];
         if constexpr (Q8) {
             // row r / (16 / U) ends in lanes r; the first of them keeps it
-            const float ub = bound8_row<U, SH>(p, l, x, r, st.qt, st.qB);
+            const float ub = bound8_row<U, SH, NT>(p, l, x, r, st.qt, st.qB);
             const int row = r / (16 / U);
 #pragma unroll
             for (int u = 1; u < U; ++u)
@@ -603,7 +627,7 @@ __device__ void wave_rerank(const SearchK &p, WLds &l, uint32_t *ids, int rc, QS
         // the upper plane for the rows they cannot rule out
         const float ipk = key_ip(st.thr);
         st.c_q8 += rc;
-        rc = prune_rows<DT, TL::UQ, true, TL::SH>(p, l, ids, rc, ipk, st);
+        rc = prune_rows<DT, TL::UQ, true, TL::SH, (TL::NT >= 2)>(p, l, ids, rc, ipk, st);
         st.c_upper += rc;
         rc = prune_rows<DT, U, false>(p, l, ids, rc, ipk, st);
     } else {
@@ -716,12 +740,13 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
     if (p.queue) qi = __shfl((int64_t)(lane == 0 ? atomicAdd(p.queue, 1u) : 0u), 0);
     while (qi < p.m) {
         const int64_t q = p.order ? (int64_t)p.order[qi] : qi;
+        const uint64_t t_begin = wall_clock64();
         QState st;
         st.k = p.ks ? max(1, min(p.ks[q], p.kmax)) : p.kconst;
         st.pend = st.cand = st.top = 0;
         st.thr = 0;
         st.c_scan = st.c_pass = st.c_rerank = st.c_exact = st.c_upper = st.c_q8 = 0;
-        const float *stopw = p.stopw + (int64_t)(p.qtab ? p.qtab[q] : 0) * K * kTauCols;
+        const float *stopw = p.stopw + (int64_t)(p.qtab ? p.qtab[q] : 0) * K * p.G * kTauCols;
         for (int c = lane; c < p.dpad; c += WV) l.qv[c] = p.Q[q * p.dpad + c];
         for (int c = lane; c < p.dpad / 2; c += WV) {
             const uint32_t w = bf16_rne(p.Q[q * p.dpad + 2 * c]) | (bf16_rne(p.Q[q * p.dpad + 2 * c + 1]) << 16);
@@ -797,32 +822,57 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                 l.segBeg[nseg] = 0;
                 l.segTab[nseg] = 0;
             }
+            // groups of repetitions: lane g < G finds the segments of the tables before
+            // the end of group g (segments are listed in table order) and their entries
+            uint32_t gseg_mine = nseg, gend_mine = total;
+            if (lane < p.G) {
+                const uint32_t a_end = (uint32_t)(((int64_t)(lane + 1) * L) / p.G);
+                uint32_t lo = 0, hi = nseg;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (l.segTab[mid] < a_end)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                gseg_mine = lo;
+                gend_mine = l.segStart[lo];
+            }
             wsync();
-            st.c_scan += total;
-            // each lane's entries f = base + u * 64 + lane only grow, so it walks the segments
-            // once per level, keeping the current one's end and base offset in registers
+            // each lane's entries f = base + u * 64 + lane only grow within a group, so it
+            // walks the group's segments once, keeping the current one's end and base
+            // offset in registers
             int sg = -1;
             uint32_t segEnd = 0, ebase = 0;
             uint64_t tqc = 0; // the query's sketch for the current segment's table
+            uint32_t gbeg = 0;
+            bool stop = false;
+            for (int32_t g = 0; g < p.G; ++g) {
+            const uint32_t gend = __builtin_amdgcn_readfirstlane(__shfl(gend_mine, g));
+            if (g > 0) {
+                sg = (int)__builtin_amdgcn_readfirstlane(__shfl(gseg_mine, g - 1)) - 1;
+                segEnd = 0;
+            }
+            st.c_scan += gend - gbeg;
             // LATE tiles: the previous chunk's passing entries (at most UCAP) wait in upos
             // as table positions, and their point ids are read together with this chunk's
             // sketches, so that positions are read for passing entries only and no load
             // waits for another.  Other tiles read the position of every entry with its
             // sketch.
             int nu = 0;
-            for (uint32_t base = 0; base < total; base += WCH) {
+            for (uint32_t base = gbeg; base < gend; base += WCH) {
                 uint32_t ev[EPT];
                 uint64_t tqv[EPT];
                 uint64_t skv[EPT];
-                // (entries past the end load entry 0 of table 0 and are masked out, so that
-                // every load is unconditional)
+                // (entries past the group's end load entry 0 of table 0 and are masked out,
+                // so that every load is unconditional)
                 uint32_t uid = 0;
                 if constexpr (TL::LATE) uid = p.tidx[lane < nu ? l.upos[lane] : 0u];
                 int lim[EPT]; // the entry's threshold: tau, or -1 past the end
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
                     const uint32_t f = base + u * WV + lane;
-                    const bool in = f < total;
+                    const bool in = f < gend;
                     if (f >= segEnd) {
                         do {
                             ++sg;
@@ -835,7 +885,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                     lim[u] = in ? tau : -1;
                     tqv[u] = tqc;
                     const uint32_t e = in ? ebase + f : 0u;
-                    skv[u] = p.tsk[e];
+                    skv[u] = ld_u64<(TL::NT >= 1)>(p.tsk + e);
                     ev[u] = TL::LATE ? e : p.tidx[e];
                 }
                 if constexpr (TL::LATE) {
@@ -895,15 +945,17 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                 wave_process<DT, TL>(p, l, st);
             }
             wave_merge(l, st);
-            bool stop = false;
             if (st.top == st.k) {
                 const float ipk = key_ip(l.top[st.k - 1]);
-                stop = ipk >= stopw[(i - 1) * kTauCols + (tau + 1)];
-                if (!stop && p.filter) {
+                stop = ipk >= stopw[((i - 1) * p.G + g) * kTauCols + (tau + 1)];
+                if (!stop && g == p.G - 1 && p.filter) {
                     // largest h with ipk <= tauv[h] (-1 if none): lanes test h = lane, one load each
                     const uint64_t mk = __ballot(ipk <= p.tauv[lane]);
                     tau = (ipk <= p.tauv[64]) ? 64 : (mk ? 63 - __clzll((long long)mk) : -1);
                 }
+            }
+            if (stop) break;
+            gbeg = gend;
             }
             if (stop) {
                 stopped = true;
@@ -938,7 +990,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
         if (lane == 0 && p.stats) {
             pf_query_stats s;
             s.stop_level = stop_level;
-            s.reserved = 0;
+            s.wave_us = (int32_t)fminf((float)(wall_clock64() - t_begin) * p.us_per_tick, 2.0e9f);
             s.c_scan = st.c_scan;
             s.c_pass = st.c_pass;
             s.c_rerank = st.c_rerank;
@@ -972,9 +1024,12 @@ using T84 = Tile<8, 4>;
 using T84o4 = Tile<8, 4, 4>; // registers capped for 4 waves per SIMD (16 per CU)
 using T84o4l = Tile<8, 4, 4, true, 8>;  // ids read for passing entries only, one chunk late
 using T84o4q8 = Tile<8, 4, 4, false, 8>;   // 8 summary rows in flight per group
-static constexpr int kNumTiles = 7;
+using T84o4lN1 = Tile<8, 4, 4, true, 8, false, 1>; // the late shape, sketches non-temporal
+using T84o4lN2 = Tile<8, 4, 4, true, 8, false, 2>; // ... and summary rows non-temporal too
+static constexpr int kNumTiles = 9;
 static const char *kTileNames[kNumTiles] = {"ept8-u8", "ept4-u8", "ept16-u8", "ept8-u4", "ept8-u4-o4",
-                                            "ept8-u4q8-o4-late", "ept8-u4q8-o4"};
+                                            "ept8-u4q8-o4-late", "ept8-u4q8-o4", "ept8-u4q8-o4-late-nts",
+                                            "ept8-u4q8-o4-late-nt"};
 
 template <class TL> static size_t tile_lds(const Index &ix, int32_t kmax) {
     return search_lds_offsets(ix.L, kmax, ix.dpad, TL::PCAP, TL::CW, TL::UCAP, ix.rq).total;
@@ -987,12 +1042,14 @@ static size_t search_lds_bytes(const Index &ix, int32_t kmax, int tile) {
     case 4: return tile_lds<T84o4>(ix, kmax);
     case 5: return tile_lds<T84o4l>(ix, kmax);
     case 6: return tile_lds<T84o4q8>(ix, kmax);
+    case 7: return tile_lds<T84o4lN1>(ix, kmax);
+    case 8: return tile_lds<T84o4lN2>(ix, kmax);
     default: return tile_lds<T88>(ix, kmax);
     }
 }
 
 // the same shape for summary rows without header (one scale for all rows)
-template <class TL> using SharedScale = Tile<TL::EPT, TL::U, TL::WPE, TL::LATE, TL::UQ, true>;
+template <class TL> using SharedScale = Tile<TL::EPT, TL::U, TL::WPE, TL::LATE, TL::UQ, true, TL::NT>;
 
 template <int DT, bool SH> static const void *search_kernel_dt(int tile) {
     switch (tile) {
@@ -1002,6 +1059,8 @@ template <int DT, bool SH> static const void *search_kernel_dt(int tile) {
     case 4: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4>, T84o4>>;
     case 5: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4l>, T84o4l>>;
     case 6: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4q8>, T84o4q8>>;
+    case 7: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4lN1>, T84o4lN1>>;
+    case 8: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4lN2>, T84o4lN2>>;
     default: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T88>, T88>>;
     }
 }
@@ -1021,7 +1080,7 @@ static const void *search_kernel(int dt, int tile, bool shared) {
 int32_t search_tile_count() { return kNumTiles; }
 // the shape used when none is given or tuned: the fastest on the 1 M-point, d = 100
 // mixture at k = 10 both with static query slots and with the work queue
-int32_t search_default_tile() { return 5; }
+int32_t search_default_tile() { return 7; }
 const char *search_tile_name(int32_t t) { return (t >= 0 && t < kNumTiles) ? kTileNames[t] : "?"; }
 
 // resident query waves per CU for a tile shape (occupancy from registers and LDS)
@@ -1035,8 +1094,8 @@ int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile) {
     return per_cu;
 }
 
-void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s) {
-    if (a.m <= 0) return;
+int64_t launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s) {
+    if (a.m <= 0) return 0;
     const int dt = row_chunks(ix.dpad);
     const int tile = (a.tile >= 0 && a.tile < kNumTiles) ? a.tile : search_default_tile();
     const size_t lds = search_lds_bytes(ix, a.kmax, tile);
@@ -1080,15 +1139,18 @@ void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipSt
     p.qtab = a.qtab;
     p.tauv = a.tauv;
     p.stopw = a.stopw;
+    p.G = a.groups;
     p.filter = a.filter;
     p.queue = a.queue;
     p.order = a.order;
     p.out_ids = a.out_ids;
     p.out_ips = a.out_ips;
     p.stats = a.stats;
+    p.us_per_tick = ix.wall_khz > 0 ? (float)(1000.0 / ix.wall_khz) : 0.0f;
     if (a.queue) launch_fill_u32(a.queue, 1, 0u, s);
     void *args[] = {&p};
     PF_HIP(hipLaunchKernel(fn, dim3((unsigned)slots), dim3(WV), args, lds, s));
+    return slots;
 }
 
 } // namespace pf

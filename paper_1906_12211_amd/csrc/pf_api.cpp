@@ -401,6 +401,9 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         hipDeviceProp_t prop;
         PF_HIP(hipGetDeviceProperties(&prop, ix->device));
         ix->num_cus = prop.multiProcessorCount;
+        int wall_khz = 0;
+        if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, ix->device) == hipSuccess)
+            ix->wall_khz = wall_khz;
         ix->n = n;
         ix->d = d;
         ix->dpad = (d + 3) / 4 * 4;
@@ -665,6 +668,9 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
              "search: bad rule");
     PF_CHECK(std::isfinite(o.eps) && o.eps > -1.0, PF_EINVAL, "search: eps must be finite and > -1");
     PF_CHECK(o.tile >= 0 && o.tile <= search_tile_count(), PF_EINVAL, "search: tile must be in [0, pf_tile_count()]");
+    const int32_t G = o.groups > 0 ? o.groups : default_groups(ix->L);
+    PF_CHECK(o.groups >= 0 && G <= std::min<int32_t>(ix->L, 64), PF_EINVAL,
+             "search: groups must be in [0, min(L, 64)]");
     if (!recalls)
         PF_CHECK(recall_const > 0.0 && recall_const <= 1.0, PF_EINVAL, "search: recall must be in (0, 1]");
     if (m == 0) return;
@@ -717,21 +723,22 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     const int32_t cols = rule_table_cols();
     const int32_t filt = o.no_filter ? 0 : 1;
     if (ix->rule_key_rule != o.rule || ix->rule_key_eps != o.eps || ix->rule_key_filter != filt ||
-        ix->rule_key_lndeltas != lnd) {
+        ix->rule_key_groups != G || ix->rule_key_lndeltas != lnd) {
         ix->rule_key_lndeltas.clear(); // (no call's key matches while the tables are rebuilt)
-        const size_t tab_floats = 65 + (size_t)lnd.size() * ix->K * cols;
+        const size_t tab_floats = 65 + (size_t)lnd.size() * ix->K * G * cols;
         const size_t dl_off = (tab_floats * sizeof(float) + 15) & ~(size_t)15;
         ix->rule_tab.ensure(dl_off + lnd.size() * sizeof(double));
         double *dl = reinterpret_cast<double *>(ix->rule_tab.as<char>() + dl_off);
         PF_HIP(hipMemcpyAsync(dl, lnd.data(), lnd.size() * sizeof(double), h2d, s));
         float *tab = ix->rule_tab.as<float>();
-        launch_rule_tables(dl, (int32_t)lnd.size(), o.eps, o.rule, ix->L, ix->M, ix->K, ix->pool,
+        launch_rule_tables(dl, (int32_t)lnd.size(), o.eps, o.rule, ix->L, ix->M, ix->K, G, ix->pool,
                            ix->family == PF_FAMILY_FHTCP ? ix->cptab.as<double>() : nullptr, ix->cp_ell, tab,
                            tab + 65, s);
         PF_HIP(hipStreamSynchronize(s));
         ix->rule_key_rule = o.rule;
         ix->rule_key_eps = o.eps;
         ix->rule_key_filter = filt;
+        ix->rule_key_groups = G;
         ix->rule_key_lndeltas = lnd;
     }
 
@@ -774,6 +781,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     a.tauv = ix->rule_tab.as<float>();
     a.stopw = ix->rule_tab.as<float>() + 65;
     a.B = o.B;
+    a.groups = G;
     a.filter = filt;
     a.prefilter = o.no_prefilter ? 0 : 1;
     a.queue = nullptr;
@@ -826,7 +834,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         }
     }
     if (o.timing) PF_HIP(hipEventRecord(ev[2], s));
-    launch_search(*ix, a, rg, s);
+    const int64_t slots = launch_search(*ix, a, rg, s);
     if (o.timing) PF_HIP(hipEventRecord(ev[3], s));
     if (mem == PF_HOST) {
         PF_HIP(hipMemcpyAsync(out_ids, oid, (size_t)m * kmax * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -852,6 +860,8 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
         ix->timing.total_ms = t03;
         ix->timing.tile = a.tile;
         ix->timing.waves_per_cu = a.waves_per_cu;
+        ix->timing.slots = slots;
+        ix->timing.groups = G;
         for (auto &e : ev) (void)hipEventDestroy(e);
     }
 }

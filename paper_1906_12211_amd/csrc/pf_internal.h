@@ -89,6 +89,7 @@ struct Index {
     HashPlan plan;
     int device = 0;
     int num_cus = 0;
+    double wall_khz = 0.0; // rate of the device's constant clock (wall_clock64)
 
     // n x dpad FP32 normalised vectors (zero padded), stored as two 16-bit planes: the
     // upper halves of the bit patterns (the vectors truncated to bfloat16; rows of hs
@@ -134,7 +135,7 @@ struct Index {
     std::vector<float> sqph;
     // decision tables of the last (rule, eps, deltas) searched
     DevBuf rule_tab;
-    int32_t rule_key_rule = -1, rule_key_filter = -1;
+    int32_t rule_key_rule = -1, rule_key_filter = -1, rule_key_groups = -1;
     double rule_key_eps = 0.0;
     std::vector<double> rule_key_lndeltas;
     pf_timing timing{};
@@ -228,7 +229,8 @@ struct SearchArgs {
     int32_t kconst, kmax;
     const int32_t *qtab;   // per-query row of stopw (nullable: row 0)
     const float *tauv;     // 65 filter-threshold boundaries (see k_search.hip)
-    const float *stopw;    // ndelta x K x 66 stopping thresholds
+    const float *stopw;    // ndelta x K x groups x 66 stopping thresholds
+    int32_t groups;        // groups of repetitions per level, the stopping test after each
     int32_t B, filter;
     int32_t prefilter;     // 1: rule candidates out on the upper-plane inner product bound
     unsigned int *queue;   // device work-queue counter (nullable: static assignment)
@@ -244,12 +246,15 @@ void launch_ranges(Index &ix, const SearchArgs &a, uint32_t *ranges, hipStream_t
 size_t ranges_list_bytes(int64_t m, int32_t L);
 void launch_ranges_into(const Index &ix, const SearchArgs &a, uint32_t *ranges, uint32_t *rlist, hipStream_t s);
 void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, int32_t rule, int32_t L,
-                        int32_t M, int32_t K, int32_t pool, const double *cptab, int32_t ell, float *tauv,
-                        float *stopw, hipStream_t s);
+                        int32_t M, int32_t K, int32_t G, int32_t pool, const double *cptab, int32_t ell,
+                        float *tauv, float *stopw, hipStream_t s);
+// groups of repetitions per level when a call asks for the default (0)
+int32_t default_groups(int32_t L);
 // FHT-CP table codes of rows X (n x dpad) into codes (L x n); see k_hash.hip
 void cp_codes(const Index &ix, const float *X, int64_t n, uint32_t *codes, hipStream_t s);
 int32_t rule_table_cols();
-void launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s);
+// returns the number of query waves launched
+int64_t launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hipStream_t s);
 int32_t search_tile_count();
 int32_t search_default_tile();
 const char *search_tile_name(int32_t t);

@@ -59,7 +59,7 @@ static NoAllocLayout noalloc_layout(const Index &ix, int64_t m) {
     };
     o.flag = take(sizeof(unsigned long long));
     o.dl = take(sizeof(double));
-    o.tab = take((65 + (size_t)ix.K * rule_table_cols()) * sizeof(float));
+    o.tab = take((65 + (size_t)ix.K * default_groups(ix.L) * rule_table_cols()) * sizeof(float));
     o.qX = take((size_t)m * ix.dpad * sizeof(float));
     o.qcode = take((size_t)m * ix.L * sizeof(uint32_t));
     o.qsk = take((size_t)m * ix.M * sizeof(uint64_t));
@@ -110,9 +110,10 @@ static void noalloc_search(pf_index *ix, const float *queries, int64_t m, int32_
     launch_fill_u32(dlw, 1, (uint32_t)(lbits & 0xFFFFFFFFu), s);
     launch_fill_u32(dlw + 1, 1, (uint32_t)(lbits >> 32), s);
     float *tab = reinterpret_cast<float *>(base + lay.tab);
-    launch_rule_tables(reinterpret_cast<const double *>(dlw), 1, 0.0, PF_RULE_FILTER, ix->L, ix->M, ix->K, ix->pool,
-                       ix->family == PF_FAMILY_FHTCP ? ix->cptab.as<double>() : nullptr, ix->cp_ell, tab, tab + 65,
-                       s);
+    const int32_t G = default_groups(ix->L);
+    launch_rule_tables(reinterpret_cast<const double *>(dlw), 1, 0.0, PF_RULE_FILTER, ix->L, ix->M, ix->K, G,
+                       ix->pool, ix->family == PF_FAMILY_FHTCP ? ix->cptab.as<double>() : nullptr, ix->cp_ell, tab,
+                       tab + 65, s);
 
     SearchArgs a;
     a.Q = qX;
@@ -127,6 +128,7 @@ static void noalloc_search(pf_index *ix, const float *queries, int64_t m, int32_
     a.tauv = tab;
     a.stopw = tab + 65;
     a.B = 12;
+    a.groups = G;
     a.filter = 1;
     a.prefilter = 1;
     a.queue = nullptr;

@@ -115,6 +115,9 @@ def test_config1_parity():
     (10, 0.9, {"filter": False}), (10, 0.9, {"rule": pf.PF_RULE_ALG1}), (10, 0.9, {"eps": 0.1}),
     (10, 0.9, {"rule": pf.PF_RULE_EXACT}), (10, 0.8, {"rule": pf.PF_RULE_EXACT, "eps": 0.3}),
     (5, 1.0, {}), (128, 0.7, {}), (10, 0.9, {"prefilter": False}), (10, 1.0, {"prefilter": False}),
+    (10, 0.9, {"groups": 1}), (10, 0.9, {"groups": 4}), (10, 0.9, {"groups": 40}), (1, 0.99, {"groups": 3, "B": 1}),
+    (10, 0.9, {"groups": 7, "rule": pf.PF_RULE_EXACT}), (5, 0.99, {"groups": 13, "rule": pf.PF_RULE_ALG1}),
+    (37, 0.8, {"groups": 40, "rule": pf.PF_RULE_EXACT, "eps": 0.2}),
 ])
 def test_search_variants(k, recall, kw):
     X = workloads.gaussian_unit(5000, 48, 21)
@@ -315,7 +318,7 @@ def test_errors():
     assert np.all(r.ids[:, 0] == np.arange(3))
 
 
-def _oracle_per_query(o, Q, ks, recalls, kmax):
+def _oracle_per_query(o, Q, ks, recalls, kmax, groups=None):
     """Oracle answers for per-query (k, recall): one oracle call per distinct pair."""
     m = len(Q)
     ids = np.full((m, kmax), -1, dtype=np.int32)
@@ -327,7 +330,7 @@ def _oracle_per_query(o, Q, ks, recalls, kmax):
             sel = np.nonzero((ks == k) & (recalls == rec))[0]
             if len(sel) == 0:
                 continue
-            r = o.search(Q[sel], int(k), float(rec))
+            r = o.search(Q[sel], int(k), float(rec), groups=groups)
             ids[sel, :k] = r.ids
             ips[sel, :k] = r.ips
             st[sel] = np.stack([r.stop_level, r.c_scan, r.c_pass, r.c_rerank], 1)
@@ -361,6 +364,13 @@ def test_batch_per_query_params_and_order():
                         "autotuned")
     t = g.last_timing()
     assert 0 <= t.tile < pf.pf_tile_count() and t.waves_per_cu >= 1
+    # the stopping test after each of 6 groups of tables, every tile shape's kernel
+    gids, gips, gst, gbd = _oracle_per_query(o, Q, ks, recalls, 100, groups=6)
+    for tile in range(pf.pf_tile_count()):
+        _assert_batch_equal(g.search_batch(Q, ks, recalls, 100, groups=6, tile=tile), gids, gips, gst, gbd,
+                            f"groups 6 tile {pf.pf_tile_name(tile)}")
+    with pytest.raises(pf.PfError):
+        g.search_batch(Q, ks, recalls, 100, groups=51)
     with pytest.raises(pf.PfError):
         g.search_batch(Q, ks, recalls, 100, order=np.zeros(len(Q), dtype=np.int32))
     bad = ks.copy()
