@@ -71,6 +71,20 @@ def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> floa
     return float(per_q.sum())
 
 
+def line_model_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int, line: int = 128) -> float:
+    """The algorithmic bytes with each passing entry's 4-byte position priced as the memory
+    system moves it: a scattered read brings in the whole line (line / 4 consecutive
+    positions of the table) that holds it, so a query pays, per line of its scanned
+    entries, one line if any of them passes -- expected (c_scan / (line / 4)) (1 - (1 -
+    c_pass / c_scan)^(line / 4)) lines with passes spread independently -- instead of 4 B
+    per passing entry."""
+    per = line // 4
+    scan = np.maximum(stats[:, 1].astype(np.float64), 1.0)
+    frac = np.clip(stats[:, 2] / scan, 0.0, 1.0)
+    lines = stats[:, 1] / per * (1.0 - (1.0 - frac) ** per)
+    return algorithmic_bytes(stats, d, k, L, K) + float((line * lines - 4.0 * stats[:, 2]).sum())
+
+
 def filter_bytes(stats: np.ndarray) -> float:
     """The filter's share of the algorithmic bytes: 8 B per scanned sketch and 4 B per
     position of a passing entry."""
@@ -395,6 +409,8 @@ def headline(args, dev):
     achieved = A / (kms * 1e-3) / 1e9
     read_gbs = pf.pf_read_bandwidth(4 << 30, 5)
     log(f"read-only streaming kernel: {read_gbs:.0f} GB/s")
+    rr = pf.pf_random_read_rate(4 << 30, 3)
+    log(f"scattered 4-byte reads: {rr / 1e9:.1f} G/s, each the streaming bandwidth of {read_gbs * 1e9 / rr:.0f} bytes")
     tname = pf.pf_tile_name(tile)
     line = {
         "metric": METRIC, "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -419,7 +435,9 @@ def headline(args, dev):
                      "traffic": traffic_entry(args.workload, tname, info.L),
                      "measured_read_gbs": read_gbs, "frac_of_measured_read": achieved / read_gbs,
                      "algorithmic_bytes_per_launch": A, "avg_launch_ms": kms, "queries_per_launch": m,
-                     "fp32_gather_bytes_per_launch": plain_gather_bytes(stats, d, k, info.L)},
+                     "fp32_gather_bytes_per_launch": plain_gather_bytes(stats, d, k, info.L),
+                     "line_model_bytes_per_launch": line_model_bytes(stats, d, k, info.L, info.K),
+                     "scattered_4b_reads_per_s": rr, "bytes_per_scattered_read": read_gbs * 1e9 / rr},
         "cpu_baseline": None,
     }
     tr = line["roofline"]["traffic"]
@@ -679,6 +697,8 @@ def main():
                     help="train the scheduler on only this many traces (counter runs; 0 = the configuration's)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
+    ap.add_argument("--random-read-probe", action="store_true",
+                    help="only run the scattered 4-byte read probe (for counter calibration) and exit")
     ap.add_argument("--cpu-worker", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-L", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-build-threads", type=int, default=12, help=argparse.SUPPRESS)
@@ -705,6 +725,14 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": x.numel() * 4}))
+        return
+    if args.random_read_probe:
+        # scattered 4-byte reads (plain and non-temporal, one warm-up and one timed launch
+        # each): what FETCH_SIZE reads per load for them prices the search kernel's reads of
+        # passing entries' positions
+        rate = pf.pf_random_read_rate(4 << 30, 1)
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        print(json.dumps({"random_read_loads_per_launch": cus * 64 * 256 * 64, "loads_per_s": rate}))
         return
 
     dev = torch.device("cuda:0")

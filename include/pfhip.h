@@ -173,6 +173,18 @@ typedef struct {
  * Synchronises `stream`. */
 int pf_read_bandwidth(uint64_t bytes, int32_t reps, double *gbs, void *stream);
 
+/* Measurement aid (not part of the method): the best rate, in loads per second, of a
+ * kernel whose every lane issues 64 scattered 4-byte reads (eight in flight; word
+ * indices from SplitMix64, masked to the largest power-of-two word count that fits in
+ * `bytes`; plain or non-temporal loads; 64 workgroups of 256 lanes per CU; `reps` timed
+ * launches of each after one warm-up) over a device buffer the call allocates, fills and
+ * frees on the current device.  The streaming read rate of pf_read_bandwidth divided by
+ * this rate is the memory traffic one scattered 4-byte read costs, as the search kernel
+ * pays it for the point id of each entry that passes the sketch filter.  PF_EINVAL for
+ * bytes < 1 MiB, reps < 1 or loads_per_s NULL; PF_ENOMEM, PF_EDEVICE.  Synchronises
+ * `stream`. */
+int pf_random_read_rate(uint64_t bytes, int32_t reps, double *loads_per_s, void *stream);
+
 /* Number of kernel tile shapes the library is built with, and the name of shape t
  * (a static string; "?" when t is out of range). */
 int32_t pf_tile_count(void);

@@ -32,7 +32,7 @@ PF_SCHED_IN, PF_SCHED_OUT, PF_SCHED_PARAMS = 98, 2, 29442
 
 EXPORTED = ["pf_normalize", "pf_build_index", "pf_plan_index", "pf_search", "pf_search_ex", "pf_search_batch", "pf_search_noalloc", "pf_hash",
             "pf_export", "pf_index_info", "pf_last_timing", "pf_free_index", "pf_last_error", "pf_version",
-            "pf_tile_count", "pf_tile_name", "pf_read_bandwidth",
+            "pf_tile_count", "pf_tile_name", "pf_read_bandwidth", "pf_random_read_rate",
             "pf_sched_create", "pf_sched_free", "pf_sched_params", "pf_features", "pf_sched_predict",
             "pf_sched_grad", "pf_sched_train", "pf_sched_save", "pf_sched_load", "pf_index_set_scheduler"]
 
@@ -109,6 +109,8 @@ def lib():
                                      ctypes.POINTER(_P)]
         L.pf_read_bandwidth.restype = ctypes.c_int
         L.pf_read_bandwidth.argtypes = [_U64, _I32, ctypes.POINTER(_D), _P]
+        L.pf_random_read_rate.restype = ctypes.c_int
+        L.pf_random_read_rate.argtypes = [_U64, _I32, ctypes.POINTER(_D), _P]
         L.pf_plan_index.restype = ctypes.c_int
         L.pf_plan_index.argtypes = [_I64, _I32, _U64, ctypes.POINTER(pf_build_opts), ctypes.POINTER(_I32),
                                     ctypes.POINTER(_U64)]
@@ -222,6 +224,13 @@ def pf_read_bandwidth(nbytes: int = 4 << 30, reps: int = 5) -> float:
     """GB/s of a plain read-only streaming kernel on the current device (measurement aid)."""
     g = _D()
     _check(lib().pf_read_bandwidth(int(nbytes), int(reps), ctypes.byref(g), None))
+    return float(g.value)
+
+
+def pf_random_read_rate(nbytes: int = 4 << 30, reps: int = 5) -> float:
+    """Scattered 4-byte loads per second on the current device (measurement aid)."""
+    g = _D()
+    _check(lib().pf_random_read_rate(int(nbytes), int(reps), ctypes.byref(g), None))
     return float(g.value)
 
 

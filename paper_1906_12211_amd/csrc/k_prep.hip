@@ -269,4 +269,68 @@ double read_bandwidth_gbs(uint64_t bytes, int32_t reps, int32_t num_cus, hipStre
     return (double)n16 * 16.0 / ((double)best * 1e-3) / 1e9;
 }
 
+// Random-read kernel (a measurement aid, not part of the method): every lane issues R
+// 4-byte loads, eight in flight, at word indices drawn from SplitMix64 of (seed, lane,
+// load) and masked to the buffer's power-of-two word count, so every load is in bounds
+// and hits a line no neighbouring lane reads.  NT: non-temporal loads.  Its rate, against
+// the streaming read rate, gives the memory traffic one scattered 4-byte read costs.
+__device__ __forceinline__ uint64_t probe_mix(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+template <bool NT>
+__global__ __launch_bounds__(256) void k_read_random(const uint32_t *__restrict__ p, uint64_t mask, int32_t R,
+                                                     uint64_t seed, uint32_t *__restrict__ sink) {
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t acc = 0;
+    for (int32_t r = 0; r < R; r += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint64_t i = probe_mix(seed ^ ((t << 20) + (uint64_t)(r + u))) & mask;
+            v[u] = NT ? __builtin_nontemporal_load(p + i) : p[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    if (acc == 0x9E3779B9u) sink[threadIdx.x] = acc;
+}
+
+double random_read_rate(uint64_t bytes, int32_t reps, int32_t num_cus, hipStream_t s) {
+    uint64_t words = 1;
+    while (words * 2 <= bytes / 4) words *= 2;
+    constexpr int32_t R = 64;
+    const unsigned blocks = (unsigned)std::max(1, num_cus) * 64u;
+    DevBuf buf, sink;
+    buf.alloc((size_t)words * 4);
+    sink.alloc(256 * sizeof(uint32_t));
+    launch_fill_u32(buf.as<uint32_t>(), (int64_t)words, 0x01020304u, s);
+    hipEvent_t e0, e1;
+    PF_HIP(hipEventCreate(&e0));
+    PF_HIP(hipEventCreate(&e1));
+    float best = 0.0f;
+    for (int nt = 0; nt < 2; ++nt)
+        for (int32_t r = 0; r <= reps; ++r) { // launch 0 warms up
+            PF_HIP(hipEventRecord(e0, s));
+            if (nt)
+                hipLaunchKernelGGL(k_read_random<true>, dim3(blocks), dim3(256), 0, s, buf.as<const uint32_t>(),
+                                   words - 1, R, (uint64_t)(2 * r + nt), sink.as<uint32_t>());
+            else
+                hipLaunchKernelGGL(k_read_random<false>, dim3(blocks), dim3(256), 0, s, buf.as<const uint32_t>(),
+                                   words - 1, R, (uint64_t)(2 * r + nt), sink.as<uint32_t>());
+            PF_HIP(hipGetLastError());
+            PF_HIP(hipEventRecord(e1, s));
+            PF_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            PF_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0 && (best == 0.0f || ms < best)) best = ms;
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return (double)blocks * 256.0 * R / ((double)best * 1e-3);
+}
+
+
 } // namespace pf

@@ -838,6 +838,9 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                 gseg_mine = lo;
                 gend_mine = l.segStart[lo];
             }
+            // lane g < G: the stopping threshold after group g at this level and filter
+            // threshold (tau changes only at the end of a level); +2 (never) elsewhere
+            const float thr_mine = lane < p.G ? stopw[((i - 1) * p.G + lane) * kTauCols + (tau + 1)] : 2.0f;
             wsync();
             // each lane's entries f = base + u * 64 + lane only grow within a group, so it
             // walks the group's segments once, keeping the current one's end and base
@@ -847,7 +850,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             uint64_t tqc = 0; // the query's sketch for the current segment's table
             uint32_t gbeg = 0;
             bool stop = false;
-            for (int32_t g = 0; g < p.G; ++g) {
+            for (int32_t g = 0; g < p.G;) {
             const uint32_t gend = __builtin_amdgcn_readfirstlane(__shfl(gend_mine, g));
             if (g > 0) {
                 sg = (int)__builtin_amdgcn_readfirstlane(__shfl(gseg_mine, g - 1)) - 1;
@@ -945,10 +948,15 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                 wave_process<DT, TL>(p, l, st);
             }
             wave_merge(l, st);
+            // the next group with entries (G if none): the groups before it add nothing, so
+            // the tests after g and after each of them see the same k-th inner product and
+            // one ballot takes them in order
+            const uint64_t more = __ballot(lane > g && lane < p.G && gend_mine > gend);
+            const int32_t nxt = more ? (int32_t)__builtin_ctzll(more) : p.G;
             if (st.top == st.k) {
                 const float ipk = key_ip(l.top[st.k - 1]);
-                stop = ipk >= stopw[((i - 1) * p.G + g) * kTauCols + (tau + 1)];
-                if (!stop && g == p.G - 1 && p.filter) {
+                stop = __ballot(lane >= g && lane < nxt && ipk >= thr_mine) != 0;
+                if (!stop && nxt == p.G && p.filter) {
                     // largest h with ipk <= tauv[h] (-1 if none): lanes test h = lane, one load each
                     const uint64_t mk = __ballot(ipk <= p.tauv[lane]);
                     tau = (ipk <= p.tauv[64]) ? 64 : (mk ? 63 - __clzll((long long)mk) : -1);
@@ -956,6 +964,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             }
             if (stop) break;
             gbeg = gend;
+            g = nxt;
             }
             if (stop) {
                 stopped = true;

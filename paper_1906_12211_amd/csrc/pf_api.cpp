@@ -310,6 +310,18 @@ PF_API int pf_read_bandwidth(uint64_t bytes, int32_t reps, double *gbs, void *st
     });
 }
 
+PF_API int pf_random_read_rate(uint64_t bytes, int32_t reps, double *loads_per_s, void *stream) {
+    return guard([&] {
+        PF_CHECK(loads_per_s && bytes >= (1ull << 20) && reps >= 1, PF_EINVAL,
+                 "pf_random_read_rate: need loads_per_s, bytes >= 1 MiB and reps >= 1");
+        int dev = 0;
+        PF_HIP(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        PF_HIP(hipGetDeviceProperties(&prop, dev));
+        *loads_per_s = pf::random_read_rate(bytes, reps, prop.multiProcessorCount, as_stream(stream));
+    });
+}
+
 PF_API int32_t pf_tile_count(void) { return pf::search_tile_count(); }
 
 PF_API const char *pf_tile_name(int32_t t) { return pf::search_tile_name(t); }

@@ -195,6 +195,7 @@ void launch_rows8(const float *X, int64_t n, int32_t dpad, uint8_t *out, uint8_t
 
 // best rate (GB/s) of `reps` launches of a read-only streaming kernel over `bytes` bytes
 double read_bandwidth_gbs(uint64_t bytes, int32_t reps, int32_t num_cus, hipStream_t s);
+double random_read_rate(uint64_t bytes, int32_t reps, int32_t num_cus, hipStream_t s);
 
 // hashing of rows X (n x dpad) into code words; see k_hash.hip.  hash_rows grows `scratch`
 // to hash_scratch_bytes(ix, n); hash_rows_into takes a device scratch of that size

@@ -136,3 +136,12 @@ def test_plan_index_charges_every_resident_byte():
     with pytest.raises(pf.PfError) as e:
         pf.pf_plan_index(0, 100, 2 << 30)
     assert e.value.code == pf.PF_EINVAL
+
+
+def test_measurement_aids_reject_bad_arguments_before_any_device_call():
+    """The read-rate probes check their arguments on the host (no device needed)."""
+    for fn in (pf.pf_read_bandwidth, pf.pf_random_read_rate):
+        for nbytes, reps in ((1 << 19, 1), (1 << 20, 0)):
+            with pytest.raises(pf.PfError) as e:
+                fn(nbytes, reps)
+            assert e.value.code == pf.PF_EINVAL
