@@ -69,22 +69,86 @@ __global__ __launch_bounds__(256) void k_dense_bwd_in(const float *__restrict__ 
     din[t] = h[t] > 0.0f ? s : 0.0f;
 }
 
-// dW[i][o] = sum_r in[row(r)][i] dout[r][o],  db[o] = sum_r dout[r][o]  (r in order)
-__global__ __launch_bounds__(256) void k_dense_wgrad(const float *__restrict__ in, const int32_t *__restrict__ rows,
-                                                     const float *__restrict__ dout, int32_t nin, int32_t nout,
-                                                     int64_t B, float *__restrict__ dW, float *__restrict__ db) {
+// Weight gradient of a dense layer, dW[i][o] = sum_r in[row(r)][i] dout[r][o] and db[o] =
+// sum_r dout[r][o], in two deterministic stages.  Workgroup (x, y, c) takes the 32 x 32 tile
+// i0 = 32x, o0 = 32y over the rows of chunk c (rows c cr .. min(B, (c + 1) cr) - 1), staging 64
+// rows of both operands at a time in LDS and adding them in row order (lane t: input i0 + t / 8,
+// outputs o0 + 4 (t % 8) .. + 3; the y = 0 workgroups also sum the bias columns); the chunks'
+// partial sums are then added in chunk order.
+constexpr int kWgTile = 32, kWgRows = 64;
+__global__ __launch_bounds__(256) void k_dense_wgrad_part(const float *__restrict__ in,
+                                                          const int32_t *__restrict__ rows,
+                                                          const float *__restrict__ dout, int32_t nin, int32_t nout,
+                                                          int64_t B, int64_t cr, float *__restrict__ part,
+                                                          float *__restrict__ partb) {
+    __shared__ float s_in[kWgRows][kWgTile + 1];
+    __shared__ float s_out[kWgRows][kWgTile + 1];
+    const int t = threadIdx.x;
+    const int i0 = (int)blockIdx.x * kWgTile, o0 = (int)blockIdx.y * kWgTile;
+    const int64_t c = blockIdx.z, r0 = c * cr, r1 = min(B, r0 + cr);
+    const int ii = t >> 3, oq = (t & 7) * 4;
+    const bool bias = blockIdx.x == 0 && t < kWgTile;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+    for (int64_t rb = r0; rb < r1; rb += kWgRows) {
+        const int rn = (int)min((int64_t)kWgRows, r1 - rb);
+        for (int e = t; e < kWgRows * kWgTile; e += 256) {
+            const int r = e / kWgTile, cc = e % kWgTile;
+            float a = 0.0f, b = 0.0f;
+            if (r < rn) {
+                const int64_t src = rows ? (int64_t)rows[rb + r] : rb + r;
+                if (i0 + cc < nin) a = in[src * nin + i0 + cc];
+                if (o0 + cc < nout) b = dout[(rb + r) * nout + o0 + cc];
+            }
+            s_in[r][cc] = a;
+            s_out[r][cc] = b;
+        }
+        __syncthreads();
+        for (int r = 0; r < rn; ++r) {
+            const float a = s_in[r][ii];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = acc[u] + a * s_out[r][oq + u];
+        }
+        if (bias)
+            for (int r = 0; r < rn; ++r) bsum = bsum + s_out[r][t];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = i0 + ii, o = o0 + oq + u;
+        if (i < nin && o < nout) part[(c * nin + i) * nout + o] = acc[u];
+    }
+    if (bias && o0 + t < nout) partb[c * nout + o0 + t] = bsum;
+}
+
+__global__ __launch_bounds__(256) void k_dense_wgrad_sum(const float *__restrict__ part,
+                                                         const float *__restrict__ partb, int32_t nin, int32_t nout,
+                                                         int32_t nc, float *__restrict__ dW, float *__restrict__ db) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < (int64_t)nin * nout) {
-        const int i = (int)(t / nout), o = (int)(t - (int64_t)(t / nout) * nout);
+    const int64_t nw = (int64_t)nin * nout;
+    if (t < nw) {
         float s = 0.0f;
-        for (int64_t r = 0; r < B; ++r) s = s + in[(rows ? (int64_t)rows[r] : r) * nin + i] * dout[r * nout + o];
+        for (int32_t c = 0; c < nc; ++c) s = s + part[c * nw + t];
         dW[t] = s;
-    } else if (t < (int64_t)nin * nout + nout) {
-        const int o = (int)(t - (int64_t)nin * nout);
+    } else if (t < nw + nout) {
+        const int64_t o = t - nw;
         float s = 0.0f;
-        for (int64_t r = 0; r < B; ++r) s = s + dout[r * nout + o];
+        for (int32_t c = 0; c < nc; ++c) s = s + partb[c * nout + o];
         db[o] = s;
     }
+}
+
+static void dense_wgrad(const float *in, const int32_t *rows, const float *dout, int32_t nin, int32_t nout,
+                        int64_t B, float *dW, float *db, float *scratch, hipStream_t s) {
+    const int64_t nc = std::min<int64_t>(kWgradChunks, (B + 127) / 128);
+    const int64_t cr = (B + nc - 1) / nc;
+    float *part = scratch, *partb = scratch + nc * nin * nout;
+    const dim3 grid((unsigned)((nin + kWgTile - 1) / kWgTile), (unsigned)((nout + kWgTile - 1) / kWgTile),
+                    (unsigned)nc);
+    hipLaunchKernelGGL(k_dense_wgrad_part, grid, dim3(256), 0, s, in, rows, dout, nin, nout, B, cr, part, partb);
+    const int64_t n = (int64_t)nin * nout + nout;
+    hipLaunchKernelGGL(k_dense_wgrad_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const float *)part,
+                       (const float *)partb, nin, nout, (int32_t)nc, dW, db);
 }
 
 // Adam (Kingma, Ba 2015) with bias correction, step t >= 1
@@ -187,21 +251,16 @@ void mlp_forward(const float *params, const float *x, const int32_t *rows, int64
 
 void mlp_backward(const float *params, const float *x, const int32_t *rows, const float *tgt, int64_t B,
                   const float *h1, const float *h2, const float *y, float *dy, float *dh2, float *dh1, float *grad,
-                  double *loss_acc, hipStream_t s) {
+                  double *loss_acc, float *wscratch, hipStream_t s) {
     const float *W2 = params + kOffW2, *W3 = params + kOffW3;
     hipLaunchKernelGGL(k_mse, dim3(1), dim3(64), 0, s, y, tgt, rows, B, dy, loss_acc);
-    hipLaunchKernelGGL(k_dense_wgrad, dim3(grid_for((int64_t)kSchedHidden * kSchedOut + kSchedOut)), dim3(256), 0,
-                       s, h2, (const int32_t *)nullptr, (const float *)dy, kSchedHidden, kSchedOut, B,
-                       grad + kOffW3, grad + kOffB3);
+    dense_wgrad(h2, nullptr, dy, kSchedHidden, kSchedOut, B, grad + kOffW3, grad + kOffB3, wscratch, s);
     hipLaunchKernelGGL(k_dense_bwd_in, dim3(grid_for(B * kSchedHidden)), dim3(256), 0, s, (const float *)dy, W3, h2,
                        kSchedHidden, kSchedOut, B, dh2);
-    hipLaunchKernelGGL(k_dense_wgrad, dim3(grid_for((int64_t)kSchedHidden * kSchedHidden + kSchedHidden)),
-                       dim3(256), 0, s, h1, (const int32_t *)nullptr, (const float *)dh2, kSchedHidden,
-                       kSchedHidden, B, grad + kOffW2, grad + kOffB2);
+    dense_wgrad(h1, nullptr, dh2, kSchedHidden, kSchedHidden, B, grad + kOffW2, grad + kOffB2, wscratch, s);
     hipLaunchKernelGGL(k_dense_bwd_in, dim3(grid_for(B * kSchedHidden)), dim3(256), 0, s, (const float *)dh2, W2,
                        h1, kSchedHidden, kSchedHidden, B, dh1);
-    hipLaunchKernelGGL(k_dense_wgrad, dim3(grid_for((int64_t)kSchedIn * kSchedHidden + kSchedHidden)), dim3(256),
-                       0, s, x, rows, (const float *)dh1, kSchedIn, kSchedHidden, B, grad + kOffW1, grad + kOffB1);
+    dense_wgrad(x, rows, dh1, kSchedIn, kSchedHidden, B, grad + kOffW1, grad + kOffB1, wscratch, s);
     PF_HIP(hipGetLastError());
 }
 

@@ -159,6 +159,9 @@ constexpr int64_t kOffB2 = kOffW2 + (int64_t)kSchedHidden * kSchedHidden;
 constexpr int64_t kOffW3 = kOffB2 + kSchedHidden;
 constexpr int64_t kOffB3 = kOffW3 + (int64_t)kSchedHidden * kSchedOut;
 constexpr int64_t kSchedParams = kOffB3 + kSchedOut; // 29,186
+// chunk partial sums of the weight gradient: at most kWgradChunks chunks of the largest layer
+constexpr int64_t kWgradChunks = 64;
+constexpr int64_t kWgradScratch = kWgradChunks * ((int64_t)kSchedHidden * kSchedHidden + kSchedHidden);
 
 struct Index;
 // features of m queries; qparam: m x 2 (log2 k, log2(1/delta)) on the device
@@ -171,7 +174,7 @@ void mlp_forward(const float *params, const float *x, const int32_t *rows, int64
                  float *y, hipStream_t s);
 void mlp_backward(const float *params, const float *x, const int32_t *rows, const float *tgt, int64_t B,
                   const float *h1, const float *h2, const float *y, float *dy, float *dh2, float *dh1, float *grad,
-                  double *loss_acc, hipStream_t s);
+                  double *loss_acc, float *wscratch, hipStream_t s);
 void mlp_adam(float *params, const float *grad, float *m1, float *m2, float lr, int32_t t, hipStream_t s);
 // keys whose ascending order is the descending order of column 1 of y (B x 2); NaN last
 void launch_lpt_keys(const float *y, int64_t B, uint32_t *keys, hipStream_t s);

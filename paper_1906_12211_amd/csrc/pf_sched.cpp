@@ -24,6 +24,7 @@ struct Sched {
     DevBuf params, grad, m1, m2;
     DevBuf act;   // h1, h2, y, dy, dh2, dh1 for one batch
     DevBuf loss;  // FP64 accumulator
+    DevBuf wscr;  // chunk partial sums of the weight gradients
     int64_t act_rows = 0;
     int32_t step = 0;
     uint64_t seed = 0;
@@ -154,6 +155,7 @@ PF_API int pf_sched_create(uint64_t seed, pf_sched **out) {
         sc->m1.alloc(kSchedParams * sizeof(float));
         sc->m2.alloc(kSchedParams * sizeof(float));
         sc->loss.alloc(sizeof(double));
+        sc->wscr.alloc((size_t)kWgradScratch * sizeof(float));
         PF_HIP(hipMemcpy(sc->params.p, p.data(), kSchedParams * sizeof(float), hipMemcpyHostToDevice));
         PF_HIP(hipMemset(sc->m1.p, 0, kSchedParams * sizeof(float)));
         PF_HIP(hipMemset(sc->m2.p, 0, kSchedParams * sizeof(float)));
@@ -243,7 +245,7 @@ PF_API int pf_sched_grad(pf_sched *sc, const float *feat, const float *target, i
         PF_HIP(hipMemsetAsync(sc->loss.p, 0, sizeof(double), s));
         mlp_forward(sc->params.as<float>(), x, nullptr, m, sc->h1(), sc->h2(), sc->y(), s);
         mlp_backward(sc->params.as<float>(), x, nullptr, t, m, sc->h1(), sc->h2(), sc->y(), sc->dy(), sc->dh2(),
-                     sc->dh1(), sc->grad.as<float>(), sc->loss.as<double>(), s);
+                     sc->dh1(), sc->grad.as<float>(), sc->loss.as<double>(), sc->wscr.as<float>(), s);
         PF_HIP(hipMemcpyAsync(grad, sc->grad.p, kSchedParams * sizeof(float),
                               mem == PF_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
         double l = 0;
@@ -281,7 +283,7 @@ PF_API int pf_sched_train(pf_sched *sc, const float *feat, const float *target, 
                 const int32_t *rows = perm.as<int32_t>() + r0;
                 mlp_forward(sc->params.as<float>(), x, rows, B, sc->h1(), sc->h2(), sc->y(), s);
                 mlp_backward(sc->params.as<float>(), x, rows, t, B, sc->h1(), sc->h2(), sc->y(), sc->dy(), sc->dh2(),
-                             sc->dh1(), sc->grad.as<float>(), sc->loss.as<double>(), s);
+                             sc->dh1(), sc->grad.as<float>(), sc->loss.as<double>(), sc->wscr.as<float>(), s);
                 mlp_adam(sc->params.as<float>(), sc->grad.as<float>(), sc->m1.as<float>(), sc->m2.as<float>(), lr,
                          ++sc->step, s);
             }

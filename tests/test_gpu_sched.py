@@ -41,18 +41,20 @@ def test_forward_and_gradient_match_fp64_reference():
     p = (rng.standard_normal(pf.PF_SCHED_PARAMS) * 0.05).astype(np.float32)
     s.set_params(p)
     assert np.array_equal(s.params(), p)
-    x = rng.standard_normal((257, pf.PF_SCHED_IN)).astype(np.float32)
-    t = rng.standard_normal((257, 2)).astype(np.float32)
-    y_ref, _ = mlp.forward(p.astype(np.float64), x)
-    y = s.predict(x)
-    assert np.allclose(y, y_ref, rtol=1e-5, atol=1e-5)
-    g, loss = s.grad(x, t)
-    loss_ref, g_ref = mlp.loss_and_grad(p.astype(np.float64), x, t)
-    assert abs(loss - loss_ref) <= 1e-5 * loss_ref
-    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
-    print(f"[grad] relative error {rel:.2e}", flush=True)
-    assert rel <= 1e-4
-    assert np.allclose(g, g_ref, rtol=1e-3, atol=1e-6 * np.abs(g_ref).max())
+    # 1 row, a ragged 257 (3 chunks of the weight gradient), 3,001 (24) and 20,000 (64, the most)
+    for m in (1, 257, 3001, 20000):
+        x = rng.standard_normal((m, pf.PF_SCHED_IN)).astype(np.float32)
+        t = rng.standard_normal((m, 2)).astype(np.float32)
+        y_ref, _ = mlp.forward(p.astype(np.float64), x)
+        y = s.predict(x)
+        assert np.allclose(y, y_ref, rtol=1e-5, atol=1e-5)
+        g, loss = s.grad(x, t)
+        loss_ref, g_ref = mlp.loss_and_grad(p.astype(np.float64), x, t)
+        assert abs(loss - loss_ref) <= 1e-5 * loss_ref
+        rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+        print(f"[grad] m={m}: relative error {rel:.2e}", flush=True)
+        assert rel <= 1e-4
+        assert np.allclose(g, g_ref, rtol=1e-3, atol=1e-6 * np.abs(g_ref).max())
 
 
 def test_training_learns_query_cost_and_keeps_results(tmp_path):
