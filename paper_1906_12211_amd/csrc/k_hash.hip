@@ -140,9 +140,187 @@ __global__ __launch_bounds__(256) void k_hash_bf16x3(
     }
 }
 
+// Rows of at most 128 padded elements (kp <= 128): a workgroup takes 128 rows, 32 per
+// wave, against the word blocks [blockIdx.y * wpy, ...), all four waves on the same word
+// block.  Each wave keeps its rows' A fragments (BF16 hi and lo of every k step) in
+// registers for the whole launch.  A word block's B fragments (32 columns x kp, hi and lo)
+// are copied once per workgroup, with coalesced 16-byte loads, into LDS; the next block's
+// copy is loaded into registers while the current one is multiplied.  Every load of the
+// loop is unconditional (the last block loads itself again, missing chunks load chunk 0)
+// and the flag bound is read before the next block's loads, so that no wait in the loop
+// covers them.  The products and their order are those of k_hash_bf16x3 (per k step, k
+// ascending: hi.hi, hi.lo, lo.hi), so every projection, flag and bit is the same.  A
+// workgroup meets about n_cols / 1,000 flagged bits per row on unit vectors, so its LDS
+// buffer holds 4,096 of them (global appends, whose wait would cover the next block's
+// loads, are then rare).
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+static constexpr int kArRows = 128, kArKS = 8;
+static constexpr int kArStride = kArKS * 16 + 8; // LDS elements per B column (16 bytes of padding)
+static constexpr int kArFlags = 4096;
+
+__device__ __forceinline__ uint32_t bf16_pair(float v0, float v1, bool lo_part) {
+    const uint16_t h0 = bf16_rne(v0), h1 = bf16_rne(v1);
+    if (!lo_part) return (uint32_t)h0 | ((uint32_t)h1 << 16);
+    const uint16_t l0 = bf16_rne(v0 - __uint_as_float((uint32_t)h0 << 16));
+    const uint16_t l1 = bf16_rne(v1 - __uint_as_float((uint32_t)h1 << 16));
+    return (uint32_t)l0 | ((uint32_t)l1 << 16);
+}
+
+__global__ __launch_bounds__(256, 3) void k_hash_bf16x3_ar(
+    const float *__restrict__ X, int64_t n, int32_t dpad, int32_t kp, const uint16_t *__restrict__ Hhi,
+    const uint16_t *__restrict__ Hlo, const float *__restrict__ beta, int32_t words, int32_t L,
+    uint32_t kmask, int32_t wpy, uint32_t *__restrict__ codes, uint32_t *__restrict__ skw,
+    uint32_t *__restrict__ flist, unsigned int *__restrict__ fcount, uint32_t fcap) {
+    __shared__ __align__(16) uint16_t bsh[2][32 * kArStride];
+    __shared__ uint32_t fbuf[2 * kArFlags];
+    __shared__ unsigned int fcnt, fbase;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int cl = lane & 31, kh = lane >> 5;
+    const int ksn = kp / 16;
+    const int64_t row0 = (int64_t)blockIdx.x * kArRows + 32 * w;
+
+    // A fragments: lane l holds row row0 + l % 32, elements 16 ks + 8 (l / 32) .. + 7
+    u32x4_t a_h[kArKS], a_l[kArKS];
+    {
+        const int64_t gr = row0 + cl;
+#pragma unroll
+        for (int ks = 0; ks < kArKS; ++ks) {
+            float v[8];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int c = ks * 16 + 8 * kh + 4 * h;
+                float4 f = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (ks < ksn && gr < n && c < dpad) f = *reinterpret_cast<const float4 *>(X + gr * dpad + c);
+                v[4 * h] = f.x;
+                v[4 * h + 1] = f.y;
+                v[4 * h + 2] = f.z;
+                v[4 * h + 3] = f.w;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                a_h[ks][e] = bf16_pair(v[2 * e], v[2 * e + 1], false);
+                a_l[ks][e] = bf16_pair(v[2 * e], v[2 * e + 1], true);
+            }
+        }
+    }
+    if (tid == 0) fcnt = 0;
+
+    // B staging: 16-byte chunk q of a plane's word block (4 kp chunks) goes to column q / (kp / 8);
+    // thread t moves chunks t and t + 256 of both planes
+    const int nq = 4 * kp, qpc = kp / 8;
+    const int q0 = tid, q1 = tid + 256;
+    const bool has0 = q0 < nq, has1 = q1 < nq;
+    const int c0 = q0 / qpc, c1 = q1 / qpc;
+    const int d0 = c0 * kArStride + (q0 - c0 * qpc) * 8, d1 = c1 * kArStride + (q1 - c1 * qpc) * 8;
+    uint4 sh0, sh1, sl0, sl1;
+    auto load_b = [&](int wb) {
+        const uint4 *bh = reinterpret_cast<const uint4 *>(Hhi + (int64_t)wb * 32 * kp);
+        const uint4 *bl = reinterpret_cast<const uint4 *>(Hlo + (int64_t)wb * 32 * kp);
+        sh0 = bh[has0 ? q0 : 0];
+        sl0 = bl[has0 ? q0 : 0];
+        sh1 = bh[has1 ? q1 : 0];
+        sl1 = bl[has1 ? q1 : 0];
+    };
+
+    const int wb0 = blockIdx.y * wpy;
+    const int wb1 = min(words, wb0 + wpy);
+    load_b(wb0);
+    for (int wb = wb0; wb < wb1; ++wb) {
+        __syncthreads(); // every wave is done with the previous block's B
+        if (has0) {
+            *reinterpret_cast<uint4 *>(&bsh[0][d0]) = sh0;
+            *reinterpret_cast<uint4 *>(&bsh[1][d0]) = sl0;
+        }
+        if (has1) {
+            *reinterpret_cast<uint4 *>(&bsh[0][d1]) = sh1;
+            *reinterpret_cast<uint4 *>(&bsh[1][d1]) = sl1;
+        }
+        __syncthreads();
+        const int col = wb * 32 + cl;
+        const float bta = beta[col];
+        load_b(min(wb + 1, wb1 - 1));
+        f32x16_t acc;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < kArKS; ++ks) {
+            if (ks < ksn) {
+                const int bo = cl * kArStride + 16 * ks + 8 * kh;
+                const bf16x8_t b_h = *reinterpret_cast<const bf16x8_t *>(&bsh[0][bo]);
+                const bf16x8_t b_l = *reinterpret_cast<const bf16x8_t *>(&bsh[1][bo]);
+                const bf16x8_t ah = __builtin_bit_cast(bf16x8_t, a_h[ks]);
+                const bf16x8_t al = __builtin_bit_cast(bf16x8_t, a_l[ks]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b_h, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, b_l, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b_h, acc, 0, 0, 0);
+            }
+        }
+        uint32_t wordv = 0, fl = 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float P = acc[r];
+            const uint64_t mb = __ballot(P >= 0.0f);
+            // lane t < 32 assembles the word of tile row t (register 4 (t / 8) + t % 4, half (t / 4) % 2)
+            if ((cl >> 3) == (r >> 2) && (lane & 3) == (r & 3))
+                wordv = ((lane >> 2) & 1) ? (uint32_t)(mb >> 32) : (uint32_t)mb;
+            fl |= (fabsf(P) <= bta ? 1u : 0u) << r;
+        }
+        if (fl) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if ((fl >> r) & 1u) {
+                    const int64_t grow = row0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                    if (grow < n) {
+                        const unsigned pos = atomicAdd(&fcnt, 1u);
+                        if (pos < (unsigned)kArFlags) {
+                            fbuf[2 * pos] = (uint32_t)grow;
+                            fbuf[2 * pos + 1] = (uint32_t)col;
+                        } else {
+                            const unsigned gp = atomicAdd(fcount, 1u);
+                            if (gp < fcap) {
+                                flist[2 * (int64_t)gp] = (uint32_t)grow;
+                                flist[2 * (int64_t)gp + 1] = (uint32_t)col;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        const int64_t grow = row0 + lane;
+        if (lane < 32 && grow < n) {
+            uint32_t *wp = word_ptr(codes, skw, n, L, wb, grow);
+            *wp = (wb < L) ? (wordv & kmask) : wordv;
+        }
+    }
+    __syncthreads();
+    const unsigned nf = min(fcnt, (unsigned)kArFlags);
+    if (tid == 0) fbase = nf ? atomicAdd(fcount, nf) : 0u;
+    __syncthreads();
+    for (unsigned t = tid; t < nf; t += 256) {
+        const unsigned gp = fbase + t;
+        if (gp < fcap) {
+            flist[2 * (int64_t)gp] = fbuf[2 * t];
+            flist[2 * (int64_t)gp + 1] = fbuf[2 * t + 1];
+        }
+    }
+}
+
 __device__ __forceinline__ double dot_seq64(const float *__restrict__ a, const float *__restrict__ x,
                                             int32_t d) {
     double s = 0.0;
+    if ((d & 3) == 0) {
+        // the same sequence of additions, the operands read four at a time (rows of a
+        // multiple of 4 floats start 16-byte aligned)
+        const float4 *a4 = reinterpret_cast<const float4 *>(a), *x4 = reinterpret_cast<const float4 *>(x);
+        for (int32_t c = 0; c < d / 4; ++c) {
+            const float4 u = a4[c], v = x4[c];
+            s = s + (double)u.x * (double)v.x;
+            s = s + (double)u.y * (double)v.y;
+            s = s + (double)u.z * (double)v.z;
+            s = s + (double)u.w * (double)v.w;
+        }
+        return s;
+    }
     for (int32_t c = 0; c < d; ++c) s = s + (double)a[c] * (double)x[c];
     return s;
 }
@@ -234,6 +412,9 @@ __global__ __launch_bounds__(256) void k_pool_codes(const uint32_t *__restrict__
 
 static void hash_gemm(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint32_t *skw, uint32_t kmask,
                       const int32_t *colrow, char *scratch, uint32_t fcap, hipStream_t s);
+static void hash_gemm_wide(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint32_t *skw,
+                           uint32_t kmask, const uint16_t *Hhi, const uint16_t *Hlo, uint32_t *flist,
+                           unsigned int *fcount, uint32_t fcap, hipStream_t s);
 
 // Cross-polytope codes with three Hadamard rotations (Sec. 2.2, Sec. 4.3): one wave per
 // point (four per workgroup), the point zero padded to d' in the wave's LDS as FP64.  For
@@ -524,6 +705,29 @@ static void hash_gemm(const Index &ix, const float *X, int64_t n, uint32_t *code
 
     const uint16_t *Hhi = ix.hbf.as<uint16_t>();
     const uint16_t *Hlo = Hhi + (size_t)hp.ncols * hp.kp;
+    if (hp.kp <= 16 * kArKS) {
+        const int64_t bx = (n + kArRows - 1) / kArRows;
+        int32_t gy = 1;
+        if (bx < 4096) gy = (int32_t)std::min<int64_t>((hp.words + 3) / 4, (4096 + bx - 1) / bx);
+        const int32_t wpy = (hp.words + gy - 1) / gy;
+        gy = (hp.words + wpy - 1) / wpy;
+        hipLaunchKernelGGL(k_hash_bf16x3_ar, dim3((unsigned)bx, (unsigned)gy), dim3(256), 0, s, X, n, ix.dpad,
+                           hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.cw, kmask, wpy, codes, skw, flist,
+                           fcount, fcap);
+        PF_HIP(hipGetLastError());
+    } else {
+        hash_gemm_wide(ix, X, n, codes, skw, kmask, Hhi, Hlo, flist, fcount, fcap, s);
+    }
+    hipLaunchKernelGGL(k_hash_fix, dim3(1024), dim3(256), 0, s, X, n, ix.dpad, hp.d, ix.hp.as<float>(),
+                       colrow, hp.words, hp.cw, kmask, codes, skw, flist, fcount, fcap);
+    PF_HIP(hipGetLastError());
+}
+
+// rows of more than 128 padded elements: the row tile in LDS, B fragments from global memory
+static void hash_gemm_wide(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint32_t *skw,
+                           uint32_t kmask, const uint16_t *Hhi, const uint16_t *Hlo, uint32_t *flist,
+                           unsigned int *fcount, uint32_t fcap, hipStream_t s) {
+    const HashPlan &hp = ix.plan;
     const bool big = hp.kp > 256;
     const int rows = big ? 32 : 64;
     const int64_t bx = (n + rows - 1) / rows;
@@ -545,9 +749,6 @@ static void hash_gemm(const Index &ix, const float *X, int64_t n, uint32_t *code
                            ix.dpad, hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.cw, kmask, wpy,
                            codes, skw, flist, fcount, fcap);
     }
-    PF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_hash_fix, dim3(1024), dim3(256), 0, s, X, n, ix.dpad, hp.d, ix.hp.as<float>(),
-                       colrow, hp.words, hp.cw, kmask, codes, skw, flist, fcount, fcap);
     PF_HIP(hipGetLastError());
 }
 

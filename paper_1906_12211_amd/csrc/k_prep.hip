@@ -152,36 +152,43 @@ __global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ X, int
 // the largest A of any row, so that a bound needs no per-row header read, and the headers
 // go to row r of hdr for the export only.  With the FP32 divisions correctly rounded,
 // |x_i / s| <= 127 (1 + 2^-24), so |c_i| <= 127 and |x_i - s c_i| <= s (1/2 + 2^-16).
-// One 64-lane wave per row.
+// One 64-lane wave per row, the waves striding over the rows; a wave folds its rows' sums
+// into one register and makes one atomic update of gmax[1] at its end.
 __global__ __launch_bounds__(256) void k_rows8(const float *__restrict__ X, int64_t n, int32_t dpad, int32_t rq,
                                                int32_t co, uint32_t *__restrict__ gmax,
                                                uint8_t *__restrict__ out, uint8_t *__restrict__ hdr) {
     const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= n) return;
-    const float *x = X + r * dpad;
-    float mx = 0.0f;
-    for (int c = lane; c < dpad; c += 64) mx = fmaxf(mx, fabsf(x[c]));
-    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-    const float sc = (co ? mx : __uint_as_float(*gmax)) / 127.0f;
-    uint8_t *row = out + r * (int64_t)rq;
-    int32_t asum = 0;
-    for (int c = lane; c < rq - co; c += 64) {
-        int32_t q = 0;
-        if (c < dpad && sc > 0.0f) {
-            const float v = rintf(x[c] / sc);
-            q = (int32_t)fminf(127.0f, fmaxf(-127.0f, v));
+    const float gsc = co ? 0.0f : __uint_as_float(*gmax) / 127.0f;
+    int32_t amax = 0;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < n; r += (int64_t)gridDim.x * 4) {
+        const float *x = X + r * dpad;
+        float sc = gsc;
+        if (co) {
+            float mx = 0.0f;
+            for (int c = lane; c < dpad; c += 64) mx = fmaxf(mx, fabsf(x[c]));
+            for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+            sc = mx / 127.0f;
         }
-        row[co + c] = (uint8_t)(int8_t)q;
-        asum += q < 0 ? -q : q;
+        uint8_t *row = out + r * (int64_t)rq;
+        int32_t asum = 0;
+        for (int c = lane; c < rq - co; c += 64) {
+            int32_t q = 0;
+            if (c < dpad && sc > 0.0f) {
+                const float v = rintf(x[c] / sc);
+                q = (int32_t)fminf(127.0f, fmaxf(-127.0f, v));
+            }
+            row[co + c] = (uint8_t)(int8_t)q;
+            asum += q < 0 ? -q : q;
+        }
+        for (int o = 32; o >= 1; o >>= 1) asum += __shfl_xor(asum, o);
+        if (lane == 0) {
+            uint8_t *h = co ? row : hdr + r * 8;
+            *reinterpret_cast<float *>(h) = sc;
+            *reinterpret_cast<int32_t *>(h + 4) = asum;
+        }
+        amax = max(amax, asum);
     }
-    for (int o = 32; o >= 1; o >>= 1) asum += __shfl_xor(asum, o);
-    if (lane == 0) {
-        uint8_t *h = co ? row : hdr + r * 8;
-        *reinterpret_cast<float *>(h) = sc;
-        *reinterpret_cast<int32_t *>(h + 4) = asum;
-        if (!co) atomicMax(gmax + 1, (uint32_t)asum);
-    }
+    if (!co && lane == 0) atomicMax(gmax + 1, (uint32_t)amax);
 }
 
 void rows8_layout(int32_t dpad, int32_t *rq, int32_t *co) {
@@ -202,7 +209,7 @@ void launch_rows8(const float *X, int64_t n, int32_t dpad, uint8_t *out, uint8_t
         hipLaunchKernelGGL(k_absmax, dim3((unsigned)blocks), dim3(256), 0, s, X, total, gmax);
         PF_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_rows8, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, dpad, rq, co,
+    hipLaunchKernelGGL(k_rows8, dim3((unsigned)std::min<int64_t>((n + 3) / 4, 16384)), dim3(256), 0, s, X, n, dpad, rq, co,
                        gmax, out, hdr);
     PF_HIP(hipGetLastError());
 }
