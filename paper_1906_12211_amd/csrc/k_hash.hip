@@ -140,7 +140,8 @@ __global__ __launch_bounds__(256) void k_hash_bf16x3(
     }
 }
 
-// Rows of at most 128 padded elements (kp <= 128): a workgroup takes 128 rows, 32 per
+// Rows of at most 16 KS padded elements (kp <= 16 KS; KS = 8 or 16, the latter with two
+// waves per SIMD for the registers): a workgroup takes 128 rows, 32 per
 // wave, against the word blocks [blockIdx.y * wpy, ...), all four waves on the same word
 // block.  Each wave keeps its rows' A fragments (BF16 hi and lo of every k step) in
 // registers for the whole launch.  A word block's B fragments (32 columns x kp, hi and lo)
@@ -154,9 +155,7 @@ __global__ __launch_bounds__(256) void k_hash_bf16x3(
 // buffer holds 4,096 of them (global appends, whose wait would cover the next block's
 // loads, are then rare).
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-static constexpr int kArRows = 128, kArKS = 8;
-static constexpr int kArStride = kArKS * 16 + 8; // LDS elements per B column (16 bytes of padding)
-static constexpr int kArFlags = 4096;
+static constexpr int kArRows = 128, kArFlags = 4096;
 
 __device__ __forceinline__ uint32_t bf16_pair(float v0, float v1, bool lo_part) {
     const uint16_t h0 = bf16_rne(v0), h1 = bf16_rne(v1);
@@ -166,11 +165,13 @@ __device__ __forceinline__ uint32_t bf16_pair(float v0, float v1, bool lo_part) 
     return (uint32_t)l0 | ((uint32_t)l1 << 16);
 }
 
-__global__ __launch_bounds__(256, 3) void k_hash_bf16x3_ar(
+template <int KS, int WPE>
+__global__ __launch_bounds__(256, WPE) void k_hash_bf16x3_ar(
     const float *__restrict__ X, int64_t n, int32_t dpad, int32_t kp, const uint16_t *__restrict__ Hhi,
     const uint16_t *__restrict__ Hlo, const float *__restrict__ beta, int32_t words, int32_t L,
     uint32_t kmask, int32_t wpy, uint32_t *__restrict__ codes, uint32_t *__restrict__ skw,
     uint32_t *__restrict__ flist, unsigned int *__restrict__ fcount, uint32_t fcap) {
+    constexpr int kArStride = KS * 16 + 8; // LDS elements per B column (16 bytes of padding)
     __shared__ __align__(16) uint16_t bsh[2][32 * kArStride];
     __shared__ uint32_t fbuf[2 * kArFlags];
     __shared__ unsigned int fcnt, fbase;
@@ -180,11 +181,11 @@ __global__ __launch_bounds__(256, 3) void k_hash_bf16x3_ar(
     const int64_t row0 = (int64_t)blockIdx.x * kArRows + 32 * w;
 
     // A fragments: lane l holds row row0 + l % 32, elements 16 ks + 8 (l / 32) .. + 7
-    u32x4_t a_h[kArKS], a_l[kArKS];
+    u32x4_t a_h[KS], a_l[KS];
     {
         const int64_t gr = row0 + cl;
 #pragma unroll
-        for (int ks = 0; ks < kArKS; ++ks) {
+        for (int ks = 0; ks < KS; ++ks) {
             float v[8];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -206,44 +207,65 @@ __global__ __launch_bounds__(256, 3) void k_hash_bf16x3_ar(
     if (tid == 0) fcnt = 0;
 
     // B staging: 16-byte chunk q of a plane's word block (4 kp chunks) goes to column q / (kp / 8);
-    // thread t moves chunks t and t + 256 of both planes
+    // thread t moves chunks t, t + 256 (and t + 512, t + 768 when KS = 16) of both planes,
+    // chunks past the block's end loading chunk 0 and storing nothing
+    static_assert(KS == 8 || KS == 16, "k steps");
     const int nq = 4 * kp, qpc = kp / 8;
-    const int q0 = tid, q1 = tid + 256;
-    const bool has0 = q0 < nq, has1 = q1 < nq;
-    const int c0 = q0 / qpc, c1 = q1 / qpc;
-    const int d0 = c0 * kArStride + (q0 - c0 * qpc) * 8, d1 = c1 * kArStride + (q1 - c1 * qpc) * 8;
-    uint4 sh0, sh1, sl0, sl1;
-    auto load_b = [&](int wb) {
-        const uint4 *bh = reinterpret_cast<const uint4 *>(Hhi + (int64_t)wb * 32 * kp);
-        const uint4 *bl = reinterpret_cast<const uint4 *>(Hlo + (int64_t)wb * 32 * kp);
-        sh0 = bh[has0 ? q0 : 0];
-        sl0 = bl[has0 ? q0 : 0];
-        sh1 = bh[has1 ? q1 : 0];
-        sl1 = bl[has1 ? q1 : 0];
+    auto chunk = [&](int i, int &q, int &d) {
+        const int qq = tid + 256 * i;
+        q = qq < nq ? qq : 0;
+        const int c = q / qpc;
+        d = qq < nq ? c * kArStride + (q - c * qpc) * 8 : -1;
     };
+    int q0, q1, q2 = 0, q3 = 0, d0, d1, d2 = -1, d3 = -1;
+    chunk(0, q0, d0);
+    chunk(1, q1, d1);
+    if constexpr (KS == 16) {
+        chunk(2, q2, d2);
+        chunk(3, q3, d3);
+    }
+    uint4 sh0, sh1, sh2, sh3, sl0, sl1, sl2, sl3;
+#define PF_LOAD_B(WB)                                                                                  \
+    {                                                                                                  \
+        const uint4 *bh_ = reinterpret_cast<const uint4 *>(Hhi + (int64_t)(WB) * 32 * kp);                \
+        const uint4 *bl_ = reinterpret_cast<const uint4 *>(Hlo + (int64_t)(WB) * 32 * kp);                \
+        sh0 = bh_[q0];                                                                                 \
+        sl0 = bl_[q0];                                                                                 \
+        sh1 = bh_[q1];                                                                                 \
+        sl1 = bl_[q1];                                                                                 \
+        if constexpr (KS == 16) {                                                                      \
+            sh2 = bh_[q2];                                                                             \
+            sl2 = bl_[q2];                                                                             \
+            sh3 = bh_[q3];                                                                             \
+            sl3 = bl_[q3];                                                                             \
+        }                                                                                              \
+    }
+#define PF_STORE_B(D, H, LO)                                                                           \
+    if ((D) >= 0) {                                                                                    \
+        *reinterpret_cast<uint4 *>(&bsh[0][(D)]) = (H);                                                \
+        *reinterpret_cast<uint4 *>(&bsh[1][(D)]) = (LO);                                               \
+    }
 
     const int wb0 = blockIdx.y * wpy;
     const int wb1 = min(words, wb0 + wpy);
-    load_b(wb0);
+    PF_LOAD_B(wb0);
     for (int wb = wb0; wb < wb1; ++wb) {
         __syncthreads(); // every wave is done with the previous block's B
-        if (has0) {
-            *reinterpret_cast<uint4 *>(&bsh[0][d0]) = sh0;
-            *reinterpret_cast<uint4 *>(&bsh[1][d0]) = sl0;
-        }
-        if (has1) {
-            *reinterpret_cast<uint4 *>(&bsh[0][d1]) = sh1;
-            *reinterpret_cast<uint4 *>(&bsh[1][d1]) = sl1;
+        PF_STORE_B(d0, sh0, sl0)
+        PF_STORE_B(d1, sh1, sl1)
+        if constexpr (KS == 16) {
+            PF_STORE_B(d2, sh2, sl2)
+            PF_STORE_B(d3, sh3, sl3)
         }
         __syncthreads();
         const int col = wb * 32 + cl;
         const float bta = beta[col];
-        load_b(min(wb + 1, wb1 - 1));
+        PF_LOAD_B(min(wb + 1, wb1 - 1));
         f32x16_t acc;
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll
-        for (int ks = 0; ks < kArKS; ++ks) {
+        for (int ks = 0; ks < KS; ++ks) {
             if (ks < ksn) {
                 const int bo = cl * kArStride + 16 * ks + 8 * kh;
                 const bf16x8_t b_h = *reinterpret_cast<const bf16x8_t *>(&bsh[0][bo]);
@@ -304,6 +326,9 @@ __global__ __launch_bounds__(256, 3) void k_hash_bf16x3_ar(
         }
     }
 }
+
+#undef PF_LOAD_B
+#undef PF_STORE_B
 
 __device__ __forceinline__ double dot_seq64(const float *__restrict__ a, const float *__restrict__ x,
                                             int32_t d) {
@@ -705,15 +730,20 @@ static void hash_gemm(const Index &ix, const float *X, int64_t n, uint32_t *code
 
     const uint16_t *Hhi = ix.hbf.as<uint16_t>();
     const uint16_t *Hlo = Hhi + (size_t)hp.ncols * hp.kp;
-    if (hp.kp <= 16 * kArKS) {
+    if (hp.kp <= 256) {
         const int64_t bx = (n + kArRows - 1) / kArRows;
         int32_t gy = 1;
         if (bx < 4096) gy = (int32_t)std::min<int64_t>((hp.words + 3) / 4, (4096 + bx - 1) / bx);
         const int32_t wpy = (hp.words + gy - 1) / gy;
         gy = (hp.words + wpy - 1) / wpy;
-        hipLaunchKernelGGL(k_hash_bf16x3_ar, dim3((unsigned)bx, (unsigned)gy), dim3(256), 0, s, X, n, ix.dpad,
-                           hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.cw, kmask, wpy, codes, skw, flist,
-                           fcount, fcap);
+        if (hp.kp <= 128)
+            hipLaunchKernelGGL((k_hash_bf16x3_ar<8, 3>), dim3((unsigned)bx, (unsigned)gy), dim3(256), 0, s, X, n,
+                               ix.dpad, hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.cw, kmask, wpy, codes,
+                               skw, flist, fcount, fcap);
+        else
+            hipLaunchKernelGGL((k_hash_bf16x3_ar<16, 2>), dim3((unsigned)bx, (unsigned)gy), dim3(256), 0, s, X, n,
+                               ix.dpad, hp.kp, Hhi, Hlo, ix.hbeta.as<float>(), hp.words, hp.cw, kmask, wpy, codes,
+                               skw, flist, fcount, fcap);
         PF_HIP(hipGetLastError());
     } else {
         hash_gemm_wide(ix, X, n, codes, skw, kmask, Hhi, Hlo, flist, fcount, fcap, s);
@@ -723,7 +753,7 @@ static void hash_gemm(const Index &ix, const float *X, int64_t n, uint32_t *code
     PF_HIP(hipGetLastError());
 }
 
-// rows of more than 128 padded elements: the row tile in LDS, B fragments from global memory
+// rows of more than 256 padded elements: the row tile in LDS, B fragments from global memory
 static void hash_gemm_wide(const Index &ix, const float *X, int64_t n, uint32_t *codes, uint32_t *skw,
                            uint32_t kmask, const uint16_t *Hhi, const uint16_t *Hlo, uint32_t *flist,
                            unsigned int *fcount, uint32_t fcap, hipStream_t s) {
