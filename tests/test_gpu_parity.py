@@ -76,10 +76,13 @@ def test_build_small_bit_exact(mode):
 
 
 @pytest.mark.parametrize("n,d,K,M,L", [(4097, 17, 24, 3, 9), (50, 3, 8, 1, 5), (1200, 100, 13, 2, 7),
-                                       (900, 33, 32, 1, 3), (4096, 130, 24, 2, 4), (700, 300, 20, 1, 3)])
+                                       (900, 33, 32, 1, 3), (4096, 130, 24, 2, 4), (700, 300, 20, 1, 3),
+                                       (1000, 128, 24, 2, 5), (333, 129, 24, 1, 3), (515, 256, 24, 2, 3),
+                                       (300, 257, 24, 1, 2)])
 def test_build_shapes_bit_exact(n, d, K, M, L):
     """ragged tiles, d not a multiple of 4 / 16, K below and at the 13-bit prefix,
-    K = 32 (no padding bits), d above 256 (32-row GEMM tiles)"""
+    K = 32 (no padding bits), d above 256 (32-row GEMM tiles), and d = 128 / 129 / 256 / 257
+    at the bounds of the GEMM kernel that keeps the rows in registers (8 or 16 k steps)"""
     X = workloads.gaussian_unit(n, d, n + d)
     g, o = _build_both(X, L=L, seed=n, K=K, M=M)
     _assert_index_equal(g, o)
@@ -609,3 +612,12 @@ def test_max_dimension_parity():
     _assert_search_equal(g.search(Q, 5, 0.9), o.search(Q, 5, 0.9), "d=4096")
     with pytest.raises(pf.PfError):
         pf.Index(workloads.gaussian_unit(10, 4097, 206), 0, L=2)
+
+
+def test_measurement_aids_run():
+    """The read-rate probes return finite positive rates (64 MiB buffers, one timed launch)."""
+    gbs = pf.pf_read_bandwidth(64 << 20, 1)
+    rate = pf.pf_random_read_rate(64 << 20, 1)
+    print(f"[probes] streaming read {gbs:.0f} GB/s, scattered 4-byte reads {rate / 1e9:.1f} G/s", flush=True)
+    assert np.isfinite(gbs) and gbs > 0
+    assert np.isfinite(rate) and rate > 0
