@@ -443,6 +443,8 @@ def headline(args, dev):
     tr = line["roofline"]["traffic"]
     if tr:
         line["roofline"]["traffic_gbs"] = tr / (kms * 1e-3) / 1e9
+        # algorithmic bytes over the bytes the counters saw move (the cache-line waste)
+        line["roofline"]["useful_over_moved"] = A / tr
     legs = set(args.legs.split(",")) if args.legs else set()
     steps2 = max(1, min(3, args.steps))
     if "c5_paths" in legs:
