@@ -8,8 +8,9 @@
 namespace pf {
 
 // A workgroup normalises a tile of rows: the tile is read into LDS with coalesced loads,
-// one thread per row sums its squares sequentially from LDS (row stride d + 1 against
-// bank conflicts), and the quotients are written back coalesced.
+// eight in flight per thread, one thread per row sums its squares sequentially from LDS
+// (row stride d + 1 against bank conflicts), and the quotients are written back coalesced.
+// Tile positions fit 32 bits (rows_per_block * (d + 1) elements of LDS).
 __global__ __launch_bounds__(256) void k_normalize(const float *__restrict__ x, int64_t n, int32_t d,
                                                    int32_t ld_in, float *__restrict__ out,
                                                    int32_t dpad, int32_t rows_per_block,
@@ -20,9 +21,26 @@ __global__ __launch_bounds__(256) void k_normalize(const float *__restrict__ x, 
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int rows = (int)min((int64_t)rows_per_block, n - r0);
     const int ld = d + 1;
-    for (int64_t t = tid; t < (int64_t)rows * d; t += blockDim.x) {
-        const int r = (int)(t / d), c = (int)(t - (int64_t)r * d);
-        tile[r * ld + c] = x[(r0 + r) * (int64_t)ld_in + c];
+    const float *xb = x + r0 * (int64_t)ld_in;
+    const int total = rows * d;
+    for (int t0 = tid; t0 < total; t0 += 8 * 256) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + 256 * u;
+            if (t < total) {
+                const int r = t / d, c = t - r * d;
+                v[u] = xb[(int64_t)r * ld_in + c];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + 256 * u;
+            if (t < total) {
+                const int r = t / d, c = t - r * d;
+                tile[r * ld + c] = v[u];
+            }
+        }
     }
     __syncthreads();
     for (int r = tid; r < rows; r += blockDim.x) {
@@ -38,10 +56,11 @@ __global__ __launch_bounds__(256) void k_normalize(const float *__restrict__ x, 
     }
     __syncthreads();
     // x and out may alias (same stride): every element was read into LDS above
-    for (int64_t t = tid; t < (int64_t)rows * dpad; t += blockDim.x) {
-        const int r = (int)(t / dpad), c = (int)(t - (int64_t)r * dpad);
+    float *ob = out + r0 * (int64_t)dpad;
+    for (int t = tid; t < rows * dpad; t += 256) {
+        const int r = t / dpad, c = t - r * dpad;
         const double q = nrm[r];
-        out[(r0 + r) * (int64_t)dpad + c] = (c < d && q > 0.0) ? (float)((double)tile[r * ld + c] / q) : 0.0f;
+        ob[t] = (c < d && q > 0.0) ? (float)((double)tile[r * ld + c] / q) : 0.0f;
     }
 }
 
