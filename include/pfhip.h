@@ -204,7 +204,8 @@ const char *pf_tile_name(int32_t t);
 int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, void *stream);
 
 /* Build the index of Sec. 4.1-4.2 over n points of dimension d:
- *  L = floor((budget - fixed) / per_table) tables, capped at PF_MAX_TABLES, where the
+ *  L = floor((budget - fixed) / per_table) tables, capped at PF_MAX_TABLES and at
+ *  floor((2^32 - 2^16 - 1) / n) (32-bit table positions), where the
  *  budget counts every byte the index keeps on the device (Sec. 1, Sec. 5.2: the data
  *  set and the hash functions are part of the index size): fixed = the vectors (two
  *  16-bit planes, 4 dpad bytes per row up to line padding) and their 8-bit summaries
@@ -232,7 +233,7 @@ int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, 
  *  signs per table and the collision table once.
  * `points` n x d (caller-owned, copied).  Errors: PF_EINVAL (n < 1, n >= 2^31, d < 1,
  * d > PF_MAX_DIM, bad row, K, M or pool out of range), PF_EBUDGET, PF_EUNSUPPORTED
- * (L n >= 2^32 - 2^16 table entries), PF_ENOMEM, PF_EDEVICE.
+ * (an explicit L_override with L n >= 2^32 - 2^16 table entries), PF_ENOMEM, PF_EDEVICE.
  * Synchronises the stream before returning. */
 int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t memory_budget_bytes,
                    const pf_build_opts *opts, int32_t mem, void *stream, pf_index **out);

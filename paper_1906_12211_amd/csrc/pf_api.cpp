@@ -380,7 +380,10 @@ static BuildPlan plan_build(int64_t n, int32_t d, uint64_t budget, const pf_buil
     PF_CHECK(L >= 1, PF_EBUDGET, "pf_build_index: the memory budget holds no table");
     L = std::min<int64_t>(L, PF_MAX_TABLES);
     // table positions, and the search's entry counters (which run up to a chunk past a
-    // level's last entry), are 32-bit
+    // level's last entry), are 32-bit: a table count from the budget stops below 2^32 - 2^16
+    // entries (at least one table, n < 2^31), an explicit one beyond it is refused
+    const int64_t entry_cap = (int64_t)(((1ull << 32) - (1ull << 16) - 1ull) / (uint64_t)n);
+    if (o.L_override <= 0) L = std::min<int64_t>(L, entry_cap);
     PF_CHECK((uint64_t)L * (uint64_t)n < (1ull << 32) - (1ull << 16), PF_EUNSUPPORTED,
              "pf_build_index: L * n must be below 2^32 - 2^16");
     b.L = L;

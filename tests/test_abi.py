@@ -145,3 +145,14 @@ def test_measurement_aids_reject_bad_arguments_before_any_device_call():
             with pytest.raises(pf.PfError) as e:
                 fn(nbytes, reps)
             assert e.value.code == pf.PF_EINVAL
+
+
+def test_plan_index_caps_tables_at_32_bit_positions():
+    """A budget that would hold more tables than 32-bit positions can address gets the most
+    that fit; an explicit table count beyond them is refused (host only)."""
+    n, d = 60_000_000, 16
+    L, nbytes = pf.pf_plan_index(n, d, 1 << 40)
+    assert L == ((1 << 32) - (1 << 16) - 1) // n and L * n < (1 << 32) - (1 << 16)
+    with pytest.raises(pf.PfError) as e:
+        pf.pf_plan_index(n, d, 0, L=L + 1)
+    assert e.value.code == pf.PF_EUNSUPPORTED
