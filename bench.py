@@ -4,7 +4,7 @@
 
 Headline workload (`value`): mixture-10M-d128 -- n = 10,000,000 unit vectors in d = 128 drawn
 from a mixture of 100,000 Gaussian clusters (centres uniform on the sphere, sigma = 0.3 per
-coordinate, then normalised), memory budget 16 GiB (every resident byte charged: L = 66
+coordinate, then normalised), memory budget 16 GiB (every resident byte charged: L = 82
 tables of K = 24 bits, M = 32 sketches); a scheduler network is trained on 1,000,000 traces of
 the plain method, then 100,000 further queries are answered at k = 10, recall 0.9 by the
 learned-batched path (persistent kernel, work queue ordered longest-predicted-first).  One
@@ -14,6 +14,7 @@ ranges, queue order, search) with the queries already in HBM; W untimed and K ti
 Printed: one JSON line.  Beside the headline it carries, as named legs (fewer steps each):
 the same batch by the plain method and by the batched FIFO and true-cost-ordered queues; the
 paper's own stopping rule (Lemma 1, epsilon slack of Sec. 5.1) at epsilon 0, 0.1, 0.2, 0.5;
+the same workload on an index with 3-byte table positions (more tables for the budget);
 the noise-norm reading of sigma (clusters of cosine about 0.9) for the same configuration;
 mixture-1M-d100 (1 M x 100, 10,000 queries, 2 GiB) under both readings; the planted instance
 (1 M x 256, k = 1, recall 0.5 / 0.9 / 0.99); and the mixed batch (100,000 queries with
@@ -46,16 +47,17 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "queries/sec at k=10, recall≥0.9: learned-batched vs plain GPU; filter HBM GB/s"
 HEADLINE = "mixture-10M-d128"
 SEARCH_SRC = os.path.join(ROOT, "paper_1906_12211_amd", "csrc", "k_search.hip")
-DEFAULT_LEGS = "c5_paths,paper_rule,c5_norm,c2,c2_norm,c3,c4"
+DEFAULT_LEGS = "c5_paths,paper_rule,c5_pos3,c5_norm,c2,c2_norm,c3,c4"
 
 
 def traffic_file(workload: str) -> str:
     return os.path.join(ROOT, "profiles", f"search_{workload}_traffic.json")
 
 
-def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> float:
+def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int, posb: int = 4) -> float:
     """Bytes the method must move for the queries of one launch of the search kernel:
-    8 B per scanned table-local sketch, 4 B per position of a passing entry, the 8-bit
+    8 B per scanned table-local sketch, posb B (3 or 4) per table position of a passing
+    entry, the 8-bit
     summary (8 + d B, or d B where the rows share one scale and carry no header: 8 + dpad
     bytes would take another 128-byte line) of every candidate bounded from it, the upper
     16-bit plane (2d B)
@@ -65,38 +67,41 @@ def algorithmic_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int) -> floa
     stop = stats[:, 0].astype(np.float64)
     dpad = 4 * ((d + 3) // 4)
     hdr = 8.0 if 8 + dpad <= (dpad + 127) // 128 * 128 else 0.0
-    per_q = (8.0 * stats[:, 1] + 4.0 * stats[:, 2] + (hdr + d) * stats[:, 6] + 2.0 * d * (stats[:, 5] + stats[:, 4])
+    per_q = (8.0 * stats[:, 1] + float(posb) * stats[:, 2] + (hdr + d) * stats[:, 6] + 2.0 * d * (stats[:, 5] + stats[:, 4])
              + 4.0 * d
              + 8.0 * k + 8.0 * L * (K + 1 - np.maximum(stop, 1)))
     return float(per_q.sum())
 
 
-def line_model_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int, line: int = 128) -> float:
-    """The algorithmic bytes with each passing entry's 4-byte position priced as the memory
-    system moves it: a scattered read brings in the whole line (line / 4 consecutive
-    positions of the table) that holds it, so a query pays, per line of its scanned
-    entries, one line if any of them passes -- expected (c_scan / (line / 4)) (1 - (1 -
-    c_pass / c_scan)^(line / 4)) lines with passes spread independently -- instead of 4 B
-    per passing entry."""
-    per = line // 4
+def line_model_bytes(stats: np.ndarray, d: int, k: int, L: int, K: int, line: int = 128,
+                     posb: int = 4) -> float:
+    """The algorithmic bytes with each passing entry's posb-byte position priced as the
+    memory system moves it: a scattered read brings in the whole line (line / posb
+    consecutive positions of the table) that holds it, so a query pays, per line of its
+    scanned entries, one line if any of them passes -- expected (c_scan / (line / posb))
+    (1 - (1 - c_pass / c_scan)^(line / posb)) lines with passes spread independently --
+    instead of posb B per passing entry."""
+    per = line / posb
     scan = np.maximum(stats[:, 1].astype(np.float64), 1.0)
     frac = np.clip(stats[:, 2] / scan, 0.0, 1.0)
     lines = stats[:, 1] / per * (1.0 - (1.0 - frac) ** per)
-    return algorithmic_bytes(stats, d, k, L, K) + float((line * lines - 4.0 * stats[:, 2]).sum())
+    return (algorithmic_bytes(stats, d, k, L, K, posb)
+            + float((line * lines - float(posb) * stats[:, 2]).sum()))
 
 
-def filter_bytes(stats: np.ndarray) -> float:
-    """The filter's share of the algorithmic bytes: 8 B per scanned sketch and 4 B per
+def filter_bytes(stats: np.ndarray, posb: int = 4) -> float:
+    """The filter's share of the algorithmic bytes: 8 B per scanned sketch and posb B per
     position of a passing entry."""
-    return float((8.0 * stats[:, 1] + 4.0 * stats[:, 2]).sum())
+    return float((8.0 * stats[:, 1] + float(posb) * stats[:, 2]).sum())
 
 
-def plain_gather_bytes(stats: np.ndarray, d: int, k: int, L: int) -> float:
+def plain_gather_bytes(stats: np.ndarray, d: int, k: int, L: int, posb: int = 4) -> float:
     """The same launch counted as if every re-ranked candidate's FP32 vector were gathered
     (4d B), with the prefix-table reads (4L), sketches (8 B per scanned entry), positions
-    of passing entries (4 B), the query and the result: the bytes a re-rank without the
+    of passing entries (posb B), the query and the result: the bytes a re-rank without the
     8-bit and 16-bit bounds would move (reported beside the roofline, not in it)."""
-    per_q = 4.0 * L + 8.0 * stats[:, 1] + 4.0 * stats[:, 2] + 4.0 * d * stats[:, 3] + 4.0 * d + 8.0 * k
+    per_q = (4.0 * L + 8.0 * stats[:, 1] + float(posb) * stats[:, 2] + 4.0 * d * stats[:, 3] + 4.0 * d
+             + 8.0 * k)
     return float(per_q.sum())
 
 
@@ -116,16 +121,16 @@ def search_device_sha(src: bytes = None) -> str:
     return hashlib.sha256(code.encode()).hexdigest()
 
 
-def traffic_entry(workload: str, tile_name: str, L: int):
+def traffic_entry(workload: str, tile_name: str, L: int, pos_bytes: int, prefix_bits: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary of this workload,
-    if it was taken on the current search kernel source, with the tile shape and table
-    count this run launched."""
+    if it was taken on the current search kernel source, with the tile shape, table count
+    and table layout (position and prefix widths) this run launched."""
     path = traffic_file(workload)
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
     if (t.get("k_search_device_sha256") != search_device_sha() or t.get("tile_name") != tile_name
-            or t.get("L") != L):
+            or t.get("L") != L or t.get("pos_bytes") != pos_bytes or t.get("prefix_bits") != prefix_bits):
         return None
     return t.get("bytes_per_launch")
 
@@ -375,7 +380,8 @@ def headline(args, dev):
     X, Q = c.pop("points"), c["queries"]
     n, d = X.shape
     m, k, recall = len(Q), c["k"], c["recall"]
-    ix = pf.Index(torch.from_numpy(X).to(dev), c["budget"], seed=workloads.INDEX_SEED)
+    ix = pf.Index(torch.from_numpy(X).to(dev), c["budget"], seed=workloads.INDEX_SEED, pos_bytes=args.pos_bytes,
+                  prefix_bits=args.prefix_bits)
     del X
     info = ix.info()
     log(f"index built: L={info.L}, {info.bytes_device / 2**30:.2f} GiB on the device "
@@ -403,8 +409,8 @@ def headline(args, dev):
     truth = truth_of(ix, Q[:ns], k, dev)
     rec = recall_of(ids[:ns], truth, k)
     log(f"recall {rec:.4f} on {ns} queries")
-    A = algorithmic_bytes(stats, d, k, info.L, info.K)
-    F = filter_bytes(stats)
+    A = algorithmic_bytes(stats, d, k, info.L, info.K, info.pos_bytes)
+    F = filter_bytes(stats, info.pos_bytes)
     kms = ph["search"]
     achieved = A / (kms * 1e-3) / 1e9
     read_gbs = pf.pf_read_bandwidth(4 << 30, 5)
@@ -419,6 +425,7 @@ def headline(args, dev):
         "config": {"workload": args.workload, "n": n, "d": d, "queries": m, "k": k, "recall_target": recall,
                    "groups": int(ix.last_timing().groups),
                    "budget_bytes": c["budget"], "L": info.L, "K": info.K, "M": info.M, "B": 12,
+                   "pos_bytes": info.pos_bytes, "prefix_bits": info.P,
                    "sigma_reading": "per coordinate", "train_traces": sch["traces"], "path": "learned_batched"},
         "recall_measured": rec, "recall_sample": ns,
         "bytes_device": info.bytes_device, "build_ms": info.build_ms,
@@ -432,11 +439,12 @@ def headline(args, dev):
         "filter_share_of_bytes": F / A,
         "roofline": {"kernel": "k_search", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_entry(args.workload, tname, info.L),
+                     "traffic": traffic_entry(args.workload, tname, info.L, info.pos_bytes, info.P),
                      "measured_read_gbs": read_gbs, "frac_of_measured_read": achieved / read_gbs,
                      "algorithmic_bytes_per_launch": A, "avg_launch_ms": kms, "queries_per_launch": m,
-                     "fp32_gather_bytes_per_launch": plain_gather_bytes(stats, d, k, info.L),
-                     "line_model_bytes_per_launch": line_model_bytes(stats, d, k, info.L, info.K),
+                     "fp32_gather_bytes_per_launch": plain_gather_bytes(stats, d, k, info.L, info.pos_bytes),
+                     "line_model_bytes_per_launch": line_model_bytes(stats, d, k, info.L, info.K,
+                                                                     posb=info.pos_bytes),
                      "scattered_4b_reads_per_s": rr, "bytes_per_scattered_read": read_gbs * 1e9 / rr},
         "cpu_baseline": None,
     }
@@ -496,6 +504,41 @@ def paper_rule(ix, Qd, Qs, truth, k, recall, dev):
 
 
 # ------------------------------------------------------------------ legs
+def leg_positions3(args, dev):
+    """The headline workload on an index whose table positions are stored in 3 bytes
+    (pos_bytes = 3): the budget buys more tables, each passing entry's position read moves
+    a line of 42 positions instead of 32, and every position read is an unaligned load;
+    batched FIFO order (learned order = FIFO on this batch)."""
+    import torch
+
+    c = workloads.config(5, with_train=False)
+    X, Q = c.pop("points"), c["queries"]
+    m, k, recall = len(Q), c["k"], c["recall"]
+    ix = pf.Index(torch.from_numpy(X).to(dev), c["budget"], seed=workloads.INDEX_SEED, pos_bytes=3)
+    del X
+    info = ix.info()
+    Qd = torch.from_numpy(Q).to(dev)
+    ks = torch.full((m,), k, dtype=torch.int32, device=dev)
+    rc = torch.full((m,), recall, dtype=torch.float64, device=dev)
+    ix.search_batch(Qd, ks, rc, k, autotune=True)
+    wall, ph, r = timed(lambda: ix.search_batch(Qd, ks, rc, k, timing=True), ix, 1, max(1, min(3, args.steps)))
+    st = r.stats.cpu().numpy()
+    ns = min(1000, m)
+    rec = recall_of(r.ids.cpu().numpy()[:ns], truth_of(ix, Q[:ns], k, dev), k)
+    t = ix.last_timing()
+    out = {"workload": c["name"], "pos_bytes": info.pos_bytes, "prefix_bits": info.P, "L": info.L,
+           "bytes_device": info.bytes_device, "qps": m / (wall / 1e3), "ms_per_step": wall,
+           "search_kernel_ms": ph["search"], "phase_ms": ph, "recall_measured": rec, "recall_sample": ns,
+           "batched_tile": {"tile": t.tile, "name": pf.pf_tile_name(t.tile), "waves_per_cu": t.waves_per_cu},
+           "algorithmic_gbs": algorithmic_bytes(st, info.d, k, info.L, info.K, info.pos_bytes) / (ph["search"] * 1e-3) / 1e9,
+           "stop_level_hist": np.bincount(st[:, 0], minlength=info.K + 1).tolist(), "mean_counts": counts(st)}
+    log(f"3-byte positions: L={info.L}, {out['qps']:.0f} queries/s (batched FIFO), search kernel "
+        f"{ph['search']:.1f} ms, recall {rec:.4f}")
+    del ix, Qd
+    torch.cuda.empty_cache()
+    return out
+
+
 def leg_mixture(cfg, sigma_mode, args, dev, ntrain):
     """Configuration 2 or 5 under a sigma reading: learned-batched, FIFO, plain and true-cost
     order on its own index, with the scheduler trained on `ntrain` traces."""
@@ -528,7 +571,7 @@ def leg_mixture(cfg, sigma_mode, args, dev, ntrain):
            "n": n, "d": d, "queries": m, "L": info.L, "bytes_device": info.bytes_device, "paths": paths,
            "scheduler": sch, "recall_measured": rec, "recall_sample": ns,
            "batched_tile": {"tile": t.tile, "name": pf.pf_tile_name(t.tile), "waves_per_cu": t.waves_per_cu},
-           "algorithmic_gbs": algorithmic_bytes(st, d, k, info.L, info.K)
+           "algorithmic_gbs": algorithmic_bytes(st, d, k, info.L, info.K, info.pos_bytes)
            / (paths["learned_batched"]["search_kernel_ms"] * 1e-3) / 1e9}
     out.update(extra)
     log(f"{c['name']} ({sigma_mode}): recall {rec:.4f}; learned/fifo {extra['learned_vs_fifo']:.3f}, "
@@ -695,6 +738,10 @@ def main():
                     help="also the pooled and cross-polytope indexes and the paper's synthetic set")
     ap.add_argument("--workload", default=HEADLINE, choices=sorted(WORKLOADS),
                     help="headline workload (mixture-1M-d100: for counter runs of configuration 2)")
+    ap.add_argument("--pos-bytes", type=int, default=0, choices=(0, 3, 4),
+                    help="table position width of the headline index (0: the library's default)")
+    ap.add_argument("--prefix-bits", type=int, default=0,
+                    help="prefix table width of the headline index (0: the library's default)")
     ap.add_argument("--train-queries", type=int, default=0,
                     help="train the scheduler on only this many traces (counter runs; 0 = the configuration's)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -743,12 +790,15 @@ def main():
     if not args.no_cpu_baseline:
         cfg = WORKLOADS[args.workload]
         n, d = (10_000_000, 128) if cfg == 5 else (1_000_000, 100)
-        L, _ = pf.pf_plan_index(n, d, 16 << 30 if cfg == 5 else 2 << 30)
+        L, _ = pf.pf_plan_index(n, d, 16 << 30 if cfg == 5 else 2 << 30, pos_bytes=args.pos_bytes,
+                                prefix_bits=args.prefix_bits)
         cpu = CpuBaseline(cfg, L, args.cpu_seconds)
     line = headline(args, dev)
     legs = set(args.legs.split(",")) if args.legs else set()
     if args.workload != HEADLINE:
-        legs -= {"c2", "c5_norm"}
+        legs -= {"c2", "c5_norm", "c5_pos3"}
+    if "c5_pos3" in legs:
+        line["c5_pos3"] = leg_positions3(args, dev)
     if "c5_norm" in legs:
         out, ix, _ = leg_mixture(5, "norm", args, dev, 200_000)
         line["c5_noise_norm"] = out

@@ -59,9 +59,9 @@ extern "C" {
                                    the pool functions, then the sketch functions        */
 #define PF_EXPORT_CODES 2       /* L x n u32, sorted codes of each table (rebuilt from
                                    the prefix table and the stored low K - P bits)     */
-#define PF_EXPORT_IDX 3         /* L x n u32, point position of each sorted entry      */
+#define PF_EXPORT_IDX 3         /* L x n u32, point position of each sorted entry (widened from the stored bytes) */
 #define PF_EXPORT_SKETCHES 4    /* L x n u64, table-local sketches                     */
-#define PF_EXPORT_OFFSETS 5     /* L x (2^P + 1) u32, P = min(13, K), prefix table     */
+#define PF_EXPORT_OFFSETS 5     /* L x (2^P + 1) u32, P = pf_info.P, prefix table      */
 #define PF_EXPORT_POOL_SEL 6    /* L x K int32: pool index of h_{t+1,j} (pooled index) */
 #define PF_EXPORT_CP_TABLE 7    /* 41 x (ell + 1) FP64: Monte Carlo collision probability of
                                    b-bit prefixes at similarity -1 + 0.05 g (FHT-CP index) */
@@ -97,6 +97,13 @@ typedef struct {
                            m > 0: pooling (Sec. 3.2), every table samples K of m shared
                            functions without replacement; m a multiple of 32 in [K, 65536] */
     int32_t family;     /* PF_FAMILY_HP (default) or PF_FAMILY_FHTCP (no pool)          */
+    int32_t pos_bytes;  /* bytes per stored table position: 0 or 4 selects 4; 3 (n <= 2^24,
+                           else PF_EINVAL) packs them in 3 bytes, which frees n bytes per
+                           table for the budget but makes each position read an unaligned
+                           load (slower for queries that scan few entries)               */
+    int32_t prefix_bits; /* P, the width of the prefix table: 0 selects the width in
+                           [min(13, K), min(24, K)] with the fewest resident bytes per table
+                           (see pf_build_index); else a width in that range               */
 } pf_build_opts;
 
 /* All-zero options are the defaults. */
@@ -149,6 +156,7 @@ typedef struct {
     uint64_t bytes_device;      /* device bytes the index actually holds (equal to
                                    bytes_budget_rule)                                    */
     double build_ms;            /* device time of the last build, if measured         */
+    int32_t pos_bytes;          /* bytes per stored table position (3 or 4)           */
 } pf_info;
 
 typedef struct {
@@ -210,16 +218,20 @@ int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_t mem, 
  *  set and the hash functions are part of the index size): fixed = the vectors (two
  *  16-bit planes, 4 dpad bytes per row up to line padding) and their 8-bit summaries
  *  (PF_EXPORT_ROWS8 layout, whole 128-byte lines per row, + 8 bytes per row when the rows
- *  share one scale), the 64 M sketch hyperplanes and their BF16 GEMM copies; per_table =
- *  the positions and table-local sketches (12n), the sorted codes' low K - P bits (2n
- *  when K - P <= 16, 4n when larger, none when K <= P: the prefix table holds the
- *  leading P bits of every entry's code), the prefix table (4 (2^P + 1)), the table's K
- *  hyperplanes (4Kd) and their GEMM copy.  For n = 10^6, d = 100, 2 GiB this gives L = 115
- *  (the paper's count, with 4-byte codes and without the summaries, gives 108);
+ *  share one scale), the 64 M sketch hyperplanes and their BF16 GEMM copies, and 8 bytes
+ *  of padding after the positions; per_table = the table-local sketches (8n), the
+ *  positions (4n, or 3n with pos_bytes = 3), the sorted codes' low K - P bits (n when
+ *  K - P <= 8, 2n when K - P <= 16, 4n when larger, none when K <= P: the prefix table
+ *  holds the leading P bits of every entry's code), the prefix table (4 (2^P + 1)), the
+ *  table's K hyperplanes (4Kd) and their GEMM copy; by default P is the width in
+ *  [min(13, K), min(24, K)] that makes the codes' share (prefix table and low bits) the
+ *  smallest: P = 16 for K = 24 and n above about 229,000, else 13.  For n = 10^6,
+ *  d = 100, 2 GiB this gives L = 121 (the paper's count, with 4-byte codes and positions
+ *  and without the summaries, gives 108);
  *  pf_info.bytes_device <= budget always holds;
  *  K random-hyperplane functions per table (Sec. 2.2), M 64-bit sketches per point
  *  (Sec. 4.2), each table sorted by its K-bit code with equal codes by position, and a
- *  table of the positions of every P-bit prefix (Sec. 4.2, P = min(13, K)).
+ *  table of the positions of every P-bit prefix (Sec. 4.2).
  *  With opts->pool = m (Sec. 3.2 "Pooling"): m shared hyperplanes, each table's K
  *  functions drawn from them without replacement (Fisher-Yates on the SplitMix64 stream
  *  seeded with seed + 1), and the budget counts the m pool hyperplanes (with their GEMM

@@ -46,7 +46,8 @@ class PfError(RuntimeError):
 class pf_build_opts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("K", ctypes.c_int32), ("M", ctypes.c_int32),
                 ("hash_mode", ctypes.c_int32), ("L_override", ctypes.c_int32), ("pool", ctypes.c_int32),
-                ("family", ctypes.c_int32)]
+                ("family", ctypes.c_int32), ("pos_bytes", ctypes.c_int32),
+                ("prefix_bits", ctypes.c_int32)]
 
 
 class pf_search_opts(ctypes.Structure):
@@ -65,7 +66,8 @@ class pf_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("M", ctypes.c_int32), ("P", ctypes.c_int32),
                 ("pool", ctypes.c_int32), ("family", ctypes.c_int32), ("bytes_budget_rule", ctypes.c_uint64),
-                ("bytes_device", ctypes.c_uint64), ("build_ms", ctypes.c_double)]
+                ("bytes_device", ctypes.c_uint64), ("build_ms", ctypes.c_double),
+                ("pos_bytes", ctypes.c_int32)]
 
 
 class pf_timing(ctypes.Structure):
@@ -235,9 +237,10 @@ def pf_random_read_rate(nbytes: int = 4 << 30, reps: int = 5) -> float:
 
 
 def pf_plan_index(n: int, d: int, budget: int, K: int = 24, M: int = 32, L: int | None = None, pool: int = 0,
-                  family: int = PF_FAMILY_HP):
+                  family: int = PF_FAMILY_HP, pos_bytes: int = 0, prefix_bits: int = 0):
     """(L, device bytes) that pf_build_index would use (host only, no device call)."""
-    opts = pf_build_opts(0, K, M, PF_HASH_BF16X3, int(L or 0), int(pool), int(family))
+    opts = pf_build_opts(0, K, M, PF_HASH_BF16X3, int(L or 0), int(pool), int(family), int(pos_bytes),
+                         int(prefix_bits))
     nl, nb = _I32(), _U64()
     _check(lib().pf_plan_index(int(n), int(d), int(budget), ctypes.byref(opts), ctypes.byref(nl),
                                ctypes.byref(nb)))
@@ -277,10 +280,11 @@ class Index:
 
     def __init__(self, points, budget: int, seed: int = 42, K: int = 24, M: int = 32,
                  hash_mode: int = PF_HASH_BF16X3, L: int | None = None, pool: int = 0,
-                 family: int = PF_FAMILY_HP):
+                 family: int = PF_FAMILY_HP, pos_bytes: int = 0, prefix_bits: int = 0):
         pts = _f32(points)
         n, d = pts.shape
-        opts = pf_build_opts(seed, K, M, hash_mode, int(L or 0), int(pool), int(family))
+        opts = pf_build_opts(seed, K, M, hash_mode, int(L or 0), int(pool), int(family), int(pos_bytes),
+                             int(prefix_bits))
         pp, mem, st = _buf(pts)
         h = ctypes.c_void_p()
         _check(lib().pf_build_index(pp, n, d, int(budget), ctypes.byref(opts), mem, st, ctypes.byref(h)))
@@ -289,6 +293,7 @@ class Index:
         info = self.info()
         self.L, self.K, self.M, self.P, self.pool = info.L, info.K, info.M, info.P, info.pool
         self.family = info.family
+        self.pos_bytes = info.pos_bytes
         dp = 1
         while dp < d:
             dp <<= 1

@@ -15,8 +15,8 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libpfhip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_prep.hip", "k_hash.hip", "k_sort.hip", "k_ranges.hip", "k_rules.hip", "k_search.hip", "k_mlp.hip",
-           "pf_noalloc.hip", "pf_api.cpp", "pf_sched.cpp"]
+SOURCES = ["k_search.hip", "k_search_pos3.hip", "k_prep.hip", "k_hash.hip", "k_sort.hip", "k_ranges.hip",
+           "k_rules.hip", "k_mlp.hip", "pf_noalloc.hip", "pf_api.cpp", "pf_sched.cpp"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", "-fvisibility=hidden",

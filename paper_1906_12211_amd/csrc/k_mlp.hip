@@ -7,7 +7,8 @@
 namespace pf {
 
 // Features of query q (98 FP32): the 64 bits of its sketch 0 as +1 / -1, then
-// log2(1 + size of the query's 13-bit prefix bucket) in tables 0..31 (0 when L < 32),
+// log2(1 + size of the query's F-bit prefix bucket, F = min(13, K)) in tables 0..31 (0
+// when L < 32; read from the P-bit prefix table, P >= F),
 // then the query's log2 k and log2(1/delta) (qparam, computed on the host).
 __global__ __launch_bounds__(256) void k_features(const uint32_t *__restrict__ qcode,
                                                   const uint64_t *__restrict__ qsk,
@@ -27,8 +28,10 @@ __global__ __launch_bounds__(256) void k_features(const uint32_t *__restrict__ q
         const int j = f - 64;
         if (j < L) {
             const int64_t np1 = ((int64_t)1 << P) + 1;
-            const uint32_t b = qcode[(int64_t)j * m + q] >> (K - P);
-            const uint32_t sz = off[(int64_t)j * np1 + b + 1] - off[(int64_t)j * np1 + b];
+            const int32_t F = min(13, K);
+            const uint32_t b = qcode[(int64_t)j * m + q] >> (K - F);
+            const uint32_t *oj = off + (int64_t)j * np1;
+            const uint32_t sz = oj[(int64_t)(b + 1) << (P - F)] - oj[(int64_t)b << (P - F)];
             v = log2f(1.0f + (float)sz);
         }
     }

@@ -6,7 +6,7 @@
 // bucket) and lt(c) = [c < query code]:
 //   lo_i = B0 + #{lt, lcp < i},   hi_i = B0 + #{lt} + #{not lt, lcp >= i}.
 // ranges[q][j][i - P - 1] = (lo_i, hi_i).  Inside the bucket every code has the query's
-// leading P bits, so the kernels read only the stored low K - P bits of each code (16-bit
+// leading P bits, so the kernels read only the stored low K - P bits of each code (8-, 16-
 // or 32-bit suffixes) and compare them with the query's.
 #include "pf_device.h"
 #include "pf_internal.h"
@@ -165,8 +165,9 @@ void launch_ranges_into(const Index &ix, const SearchArgs &a, uint32_t *ranges, 
     launch_fill_u32(nbig, 1, 0u, s);
     // registers of 8-bit bin counters per flag: bins lcp - P = 0 .. K - P
     const int nr = (ix.K - ix.P + 1 + 3) / 4;
-    const bool w16 = ix.sufw == 2;
-    const void *fn = w16 ? group_kernel_of<uint16_t>(nr) : group_kernel_of<uint32_t>(nr);
+    const int32_t w = ix.sufw;
+    const void *fn = w == 1 ? group_kernel_of<uint8_t>(nr)
+                   : w == 2 ? group_kernel_of<uint16_t>(nr) : group_kernel_of<uint32_t>(nr);
     const void *tc = ix.tsuf.p;
     const uint32_t *of = ix.off.as<uint32_t>();
     int64_t n = ix.n;
@@ -178,7 +179,10 @@ void launch_ranges_into(const Index &ix, const SearchArgs &a, uint32_t *ranges, 
     PF_HIP(hipLaunchKernel(fn, dim3((unsigned)((pairs * 16 + 255) / 256)), dim3(256), args, 0, s));
     // the list's length is known only on the device: a fixed grid strides over it
     const int64_t wg = std::min<int64_t>((pairs + 3) / 4, (int64_t)ix.num_cus * 8);
-    if (w16)
+    if (w == 1)
+        hipLaunchKernelGGL(k_ranges_wave<uint8_t>, dim3((unsigned)std::max<int64_t>(1, wg)), dim3(256), 0, s,
+                           static_cast<const uint8_t *>(tc), of, n, L, K, P, qc, m, ranges, big, nbig);
+    else if (w == 2)
         hipLaunchKernelGGL(k_ranges_wave<uint16_t>, dim3((unsigned)std::max<int64_t>(1, wg)), dim3(256), 0, s,
                            static_cast<const uint16_t *>(tc), of, n, L, K, P, qc, m, ranges, big, nbig);
     else

@@ -63,7 +63,8 @@ struct SearchK {
     int32_t rq, qco;    // (qco = 8) or, when qco = 0, in Xqh (8 bytes per row; every row's
     float s8;           // scale is then s8 and no row's sum exceeds a8, which kernels built
     int32_t a8;         // for that layout take instead of reading Xqh)
-    const uint32_t *tidx, *off;
+    const void *pos;    // table positions, PB bytes each (the kernel's parameter)
+    const uint32_t *off;
     const uint64_t *tsk;
     int64_t n;
     int32_t dpad, L, K, M, P, B;
@@ -706,7 +707,7 @@ __device__ void wave_scan_incl(uint32_t *a, int N) {
     wsync();
 }
 
-template <int DT, class TL>
+template <int DT, class TL, int PB>
 __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) void k_search(SearchK p) {
     constexpr int EPT = TL::EPT, WCH = TL::WCH, RB = TL::RB, PCAP = TL::PCAP;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -870,7 +871,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                 // (entries past the group's end load entry 0 of table 0 and are masked out,
                 // so that every load is unconditional)
                 uint32_t uid = 0;
-                if constexpr (TL::LATE) uid = p.tidx[lane < nu ? l.upos[lane] : 0u];
+                if constexpr (TL::LATE) uid = read_pos<PB>(p.pos, lane < nu ? l.upos[lane] : 0u);
                 int lim[EPT]; // the entry's threshold: tau, or -1 past the end
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) {
@@ -889,7 +890,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                     tqv[u] = tqc;
                     const uint32_t e = in ? ebase + f : 0u;
                     skv[u] = ld_u64<(TL::NT >= 1)>(p.tsk + e);
-                    ev[u] = TL::LATE ? e : p.tidx[e];
+                    ev[u] = TL::LATE ? e : read_pos<PB>(p.pos, e);
                 }
                 if constexpr (TL::LATE) {
                     if (lane < nu) l.pending[st.pend + lane] = uid;
@@ -921,7 +922,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                     // flight)
                     if constexpr (TL::LATE) {
 #pragma unroll
-                        for (int u = 0; u < EPT; ++u) ev[u] = p.tidx[ps[u] ? ev[u] : 0u];
+                        for (int u = 0; u < EPT; ++u) ev[u] = read_pos<PB>(p.pos, ps[u] ? ev[u] : 0u);
                         nu = 0;
                     }
 #pragma unroll
@@ -938,7 +939,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             }
             if (TL::LATE && nu > 0) {
                 wsync();
-                const uint32_t uid = p.tidx[lane < nu ? l.upos[lane] : 0u];
+                const uint32_t uid = read_pos<PB>(p.pos, lane < nu ? l.upos[lane] : 0u);
                 if (lane < nu) l.pending[st.pend + lane] = uid;
                 st.pend += nu;
             }
@@ -1016,14 +1017,9 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
     }
 }
 
-// ====================================================================== host side
-// (tile table, occupancy, launch; everything above this line is device code)
-
-// chunks of 64 floats per row, as a kernel specialisation (0 = any length)
-static int row_chunks(int32_t dpad) {
-    const int t = (dpad + 63) / 64;
-    return t <= 1 ? 1 : t <= 2 ? 2 : t <= 4 ? 4 : 0;
-}
+// ---------------------------------------------------------------------- kernel table
+// (the instantiations for 4-byte positions are built here; those for 3-byte positions in
+// k_search_pos3.hip, which includes this file with PF_SEARCH_KERNELS_ONLY defined)
 
 // tile shapes the library is built with (the autotuner chooses among them)
 using T88 = Tile<8, 8>;
@@ -1035,6 +1031,47 @@ using T84o4l = Tile<8, 4, 4, true, 8>;  // ids read for passing entries only, on
 using T84o4q8 = Tile<8, 4, 4, false, 8>;   // 8 summary rows in flight per group
 using T84o4lN1 = Tile<8, 4, 4, true, 8, false, 1>; // the late shape, sketches non-temporal
 using T84o4lN2 = Tile<8, 4, 4, true, 8, false, 2>; // ... and summary rows non-temporal too
+
+// the same shape for summary rows without header (one scale for all rows)
+template <class TL> using SharedScale = Tile<TL::EPT, TL::U, TL::WPE, TL::LATE, TL::UQ, true, TL::NT>;
+
+template <int PB, int DT, bool SH> static const void *search_kernel_dt(int tile) {
+    switch (tile) {
+    case 1: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T48>, T48>, PB>;
+    case 2: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T168>, T168>, PB>;
+    case 3: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84>, T84>, PB>;
+    case 4: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4>, T84o4>, PB>;
+    case 5: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4l>, T84o4l>, PB>;
+    case 6: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4q8>, T84o4q8>, PB>;
+    case 7: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4lN1>, T84o4lN1>, PB>;
+    case 8: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4lN2>, T84o4lN2>, PB>;
+    default: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T88>, T88>, PB>;
+    }
+}
+
+// kernels for rows of at most 64, 128 or 256 floats, or any length; rows of 121 .. 128
+// and 249 .. 256 floats have summaries without header (shared scale), others of at most
+// 256 floats their header inline; longer rows read a separate header when they have one
+template <int PB> static const void *search_kernel_of(int dt, int tile, bool shared) {
+    switch (dt) {
+    case 1: return search_kernel_dt<PB, 1, false>(tile);
+    case 2: return shared ? search_kernel_dt<PB, 2, true>(tile) : search_kernel_dt<PB, 2, false>(tile);
+    case 4: return shared ? search_kernel_dt<PB, 4, true>(tile) : search_kernel_dt<PB, 4, false>(tile);
+    default: return search_kernel_dt<PB, 0, false>(tile);
+    }
+}
+
+
+#ifndef PF_SEARCH_KERNELS_ONLY
+// ====================================================================== host side
+// (tile table, occupancy, launch; everything above this line is device code)
+
+// chunks of 64 floats per row, as a kernel specialisation (0 = any length)
+static int row_chunks(int32_t dpad) {
+    const int t = (dpad + 63) / 64;
+    return t <= 1 ? 1 : t <= 2 ? 2 : t <= 4 ? 4 : 0;
+}
+
 static constexpr int kNumTiles = 9;
 static const char *kTileNames[kNumTiles] = {"ept8-u8", "ept4-u8", "ept16-u8", "ept8-u4", "ept8-u4-o4",
                                             "ept8-u4q8-o4-late", "ept8-u4q8-o4", "ept8-u4q8-o4-late-nts",
@@ -1057,33 +1094,9 @@ static size_t search_lds_bytes(const Index &ix, int32_t kmax, int tile) {
     }
 }
 
-// the same shape for summary rows without header (one scale for all rows)
-template <class TL> using SharedScale = Tile<TL::EPT, TL::U, TL::WPE, TL::LATE, TL::UQ, true, TL::NT>;
-
-template <int DT, bool SH> static const void *search_kernel_dt(int tile) {
-    switch (tile) {
-    case 1: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T48>, T48>>;
-    case 2: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T168>, T168>>;
-    case 3: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84>, T84>>;
-    case 4: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4>, T84o4>>;
-    case 5: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4l>, T84o4l>>;
-    case 6: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4q8>, T84o4q8>>;
-    case 7: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4lN1>, T84o4lN1>>;
-    case 8: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T84o4lN2>, T84o4lN2>>;
-    default: return (const void *)k_search<DT, std::conditional_t<SH, SharedScale<T88>, T88>>;
-    }
-}
-
-// kernels for rows of at most 64, 128 or 256 floats, or any length; rows of 121 .. 128
-// and 249 .. 256 floats have summaries without header (shared scale), others of at most
-// 256 floats their header inline; longer rows read a separate header when they have one
-static const void *search_kernel(int dt, int tile, bool shared) {
-    switch (dt) {
-    case 1: return search_kernel_dt<1, false>(tile);
-    case 2: return shared ? search_kernel_dt<2, true>(tile) : search_kernel_dt<2, false>(tile);
-    case 4: return shared ? search_kernel_dt<4, true>(tile) : search_kernel_dt<4, false>(tile);
-    default: return search_kernel_dt<0, false>(tile);
-    }
+// kernels for the index's position width (3-byte ones live in k_search_pos3.hip)
+static const void *search_kernel(int dt, int tile, bool shared, int32_t posb) {
+    return posb == 3 ? search_kernel_pos3(dt, tile, shared) : search_kernel_of<4>(dt, tile, shared);
 }
 
 int32_t search_tile_count() { return kNumTiles; }
@@ -1096,7 +1109,7 @@ const char *search_tile_name(int32_t t) { return (t >= 0 && t < kNumTiles) ? kTi
 int32_t search_waves_per_cu(const Index &ix, int32_t kmax, int32_t tile) {
     int per_cu = 0;
     const size_t lds = search_lds_bytes(ix, kmax, tile);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel(row_chunks(ix.dpad), tile, ix.qco == 0), WV, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel(row_chunks(ix.dpad), tile, ix.qco == 0, ix.posb), WV, lds) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 4;
@@ -1108,7 +1121,7 @@ int64_t launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hi
     const int dt = row_chunks(ix.dpad);
     const int tile = (a.tile >= 0 && a.tile < kNumTiles) ? a.tile : search_default_tile();
     const size_t lds = search_lds_bytes(ix, a.kmax, tile);
-    const void *fn = search_kernel(dt, tile, ix.qco == 0);
+    const void *fn = search_kernel(dt, tile, ix.qco == 0, ix.posb);
     PF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = search_waves_per_cu(ix, a.kmax, tile);
     if (a.waves_per_cu > 0) per_cu = std::min(per_cu, a.waves_per_cu);
@@ -1126,7 +1139,7 @@ int64_t launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hi
     p.a8 = ix.a8;
     p.rq = ix.rq;
     p.qco = ix.qco;
-    p.tidx = ix.tidx.as<uint32_t>();
+    p.pos = ix.tpos.p;
     p.off = ix.off.as<uint32_t>();
     p.tsk = ix.tsk.as<uint64_t>();
     p.n = ix.n;
@@ -1161,5 +1174,7 @@ int64_t launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hi
     PF_HIP(hipLaunchKernel(fn, dim3((unsigned)slots), dim3(WV), args, lds, s));
     return slots;
 }
+
+#endif // PF_SEARCH_KERNELS_ONLY
 
 } // namespace pf

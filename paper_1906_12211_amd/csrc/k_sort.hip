@@ -5,8 +5,9 @@
 // per-table exclusive scan over (digit, tile), then a stable scatter in which each
 // wave ranks its keys by ballot matching and the tile is reordered in LDS so that the
 // writes of one digit go out contiguously.
-// The prefix table (13-bit prefix positions, Sec. 4.2) and the table-local sketches
+// The prefix table (P-bit prefix positions, Sec. 4.2) and the table-local sketches
 // (the sketch a repetition reads, Sec. 4.2 "Filtering candidate points") follow.
+#include "pf_device.h"
 #include "pf_internal.h"
 
 namespace pf {
@@ -229,7 +230,7 @@ void prefix_tables(const uint32_t *tcode, int64_t n, int32_t L, int32_t K, int32
 // Resident form of the sorted codes: inside a table's P-bit prefix bucket every code has
 // the bucket's leading P bits, which the prefix table already holds (entry e lies in
 // bucket b iff off[b] <= e < off[b + 1]), so only the low K - P bits of each code are kept,
-// in 16 bits when K - P <= 16 (else 32; nothing when K <= P).
+// in 8 bits when K - P <= 8, 16 bits when K - P <= 16, else 32 (nothing when K <= P).
 template <class S>
 __global__ __launch_bounds__(256) void k_code_suffix(const uint32_t *__restrict__ tcode, int64_t total,
                                                      uint32_t mask, S *__restrict__ suf) {
@@ -237,7 +238,25 @@ __global__ __launch_bounds__(256) void k_code_suffix(const uint32_t *__restrict_
         suf[i] = (S)(tcode[i] & mask);
 }
 
-int32_t code_suffix_bytes(int32_t K, int32_t P) { return K <= P ? 0 : (K - P <= 16 ? 2 : 4); }
+int32_t code_suffix_bytes(int32_t K, int32_t P) { return K <= P ? 0 : K - P <= 8 ? 1 : K - P <= 16 ? 2 : 4; }
+
+int32_t prefix_bits_min(int32_t K) { return std::min(13, K); }
+int32_t prefix_bits_max(int32_t K) { return std::min(24, K); }
+
+// The prefix width with the fewest resident bytes per table: its prefix table
+// (4 (2^P + 1) bytes) and the suffixes of n codes; the narrower one on a tie.
+int32_t choose_prefix_bits(int64_t n, int32_t K) {
+    int32_t best = prefix_bits_min(K);
+    uint64_t best_b = ~0ull;
+    for (int32_t P = prefix_bits_min(K); P <= prefix_bits_max(K); ++P) {
+        const uint64_t b = 4ull * ((1ull << P) + 1ull) + (uint64_t)n * (uint64_t)code_suffix_bytes(K, P);
+        if (b < best_b) {
+            best_b = b;
+            best = P;
+        }
+    }
+    return best;
+}
 
 void code_suffixes(const uint32_t *tcode, int64_t n, int32_t L, int32_t K, int32_t P, void *suf, hipStream_t s) {
     const int32_t w = code_suffix_bytes(K, P);
@@ -245,7 +264,10 @@ void code_suffixes(const uint32_t *tcode, int64_t n, int32_t L, int32_t K, int32
     const int64_t total = (int64_t)L * n;
     const uint32_t mask = K - P >= 32 ? 0xFFFFFFFFu : ((1u << (K - P)) - 1u);
     const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-    if (w == 2)
+    if (w == 1)
+        hipLaunchKernelGGL(k_code_suffix<uint8_t>, dim3(blocks), dim3(256), 0, s, tcode, total, mask,
+                           static_cast<uint8_t *>(suf));
+    else if (w == 2)
         hipLaunchKernelGGL(k_code_suffix<uint16_t>, dim3(blocks), dim3(256), 0, s, tcode, total, mask,
                            static_cast<uint16_t *>(suf));
     else
@@ -279,8 +301,12 @@ __global__ __launch_bounds__(256) void k_code_join(const S *__restrict__ suf, co
 void join_codes(const void *suf, const uint32_t *off, int64_t n, int32_t L, int32_t K, int32_t P, uint32_t *out,
                 hipStream_t s) {
     const dim3 grid((unsigned)((n + 255) / 256), (unsigned)L);
-    if (code_suffix_bytes(K, P) == 4)
+    const int32_t w = code_suffix_bytes(K, P);
+    if (w == 4)
         hipLaunchKernelGGL(k_code_join<uint32_t>, grid, dim3(256), 0, s, static_cast<const uint32_t *>(suf), off, n,
+                           K, P, out);
+    else if (w == 1)
+        hipLaunchKernelGGL(k_code_join<uint8_t>, grid, dim3(256), 0, s, static_cast<const uint8_t *>(suf), off, n,
                            K, P, out);
     else
         hipLaunchKernelGGL(k_code_join<uint16_t>, grid, dim3(256), 0, s, static_cast<const uint16_t *>(suf), off, n,
@@ -304,6 +330,55 @@ void gather_sketches(const uint32_t *tidx, const uint64_t *sk, int64_t n, int32_
                      uint64_t *tsk, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_sk, dim3((unsigned)((n + 255) / 256), L), dim3(256), 0, s, tidx, sk, n,
                        M, tsk);
+    PF_HIP(hipGetLastError());
+}
+
+// Table positions in 3 bytes (every position below 2^24): thread t packs entries 4t .. 4t + 3
+// into the 12 bytes 12t .. 12t + 11 and writes only the words that hold bytes of its
+// entries, so that a partial last group stays inside 3 count + 4 bytes.
+__global__ __launch_bounds__(256) void k_pack_pos3(const uint32_t *__restrict__ in, int64_t count,
+                                                   uint32_t *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t e0 = 4 * t;
+    if (e0 >= count) return;
+    const int ne = (int)min((int64_t)4, count - e0);
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = u < ne ? (in[e0 + u] & 0xFFFFFFu) : 0u;
+    uint32_t *o = out + 3 * t;
+    o[0] = v[0] | (v[1] << 24);
+    if (ne >= 2) o[1] = (v[1] >> 8) | (v[2] << 16);
+    if (ne >= 3) o[2] = (v[2] >> 16) | (v[3] << 8);
+}
+
+__global__ __launch_bounds__(256) void k_unpack_pos(const uint8_t *__restrict__ in, int64_t count, int32_t posb,
+                                                    uint32_t *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < count; g += stride)
+        out[g] = posb == 4 ? read_pos<4>(in, (uint32_t)g) : read_pos<3>(in, (uint32_t)g);
+}
+
+int32_t pos_bytes_for(int64_t n, int32_t want) { return (want == 3 && n <= (1ll << 24)) ? 3 : 4; }
+
+void pack_positions(const uint32_t *in, int64_t count, int32_t posb, uint8_t *out, hipStream_t s) {
+    if (count <= 0) return;
+    // the padding after the positions reads as zeros (two words from the one holding the
+    // first padding byte; the pack below rewrites the position bytes among them)
+    launch_fill_u32(reinterpret_cast<uint32_t *>(out + (count * posb) / 4 * 4), 2, 0u, s);
+    if (posb == 4) {
+        PF_HIP(hipMemcpyAsync(out, in, (size_t)count * 4, hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    const int64_t groups = (count + 3) / 4;
+    hipLaunchKernelGGL(k_pack_pos3, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, in, count,
+                       reinterpret_cast<uint32_t *>(out));
+    PF_HIP(hipGetLastError());
+}
+
+void unpack_positions(const uint8_t *in, int64_t count, int32_t posb, uint32_t *out, hipStream_t s) {
+    if (count <= 0) return;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_unpack_pos, dim3((unsigned)blocks), dim3(256), 0, s, in, count, posb, out);
     PF_HIP(hipGetLastError());
 }
 

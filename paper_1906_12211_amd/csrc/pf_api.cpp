@@ -158,16 +158,17 @@ static void cp_dims(int32_t d, int32_t &dp, int32_t &ell) {
 // allocations of pf_build_index and build_plan one for one:
 //   fixed: the vectors as two 16-bit planes, their 8-bit summaries (+ the 8-byte headers
 //          when rows share one scale), the sketch (and pool) hyperplanes, their GEMM
-//          copies (BF16 hi + lo, column rows, flag bounds; 32 columns per word), and the
-//          cross-polytope collision table;
-//   per table: positions and table-local sketches (12n), the low K - P bits of the sorted
-//          codes (2n when K - P <= 16, 4n when larger, none when K <= P), the prefix table,
-//          the table's K hyperplanes and their GEMM word (independent functions), its K
-//          pool indices (pooling) or its cross-polytope sign words.
-static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, int32_t pool, int32_t family, uint64_t &fixed,
-                         uint64_t &per) {
+//          copies (BF16 hi + lo, column rows, flag bounds; 32 columns per word), the
+//          cross-polytope collision table, and the padding after the positions;
+//   per table: table-local sketches (8n), positions (posb n: 4 bytes, or 3 on request when
+//          n <= 2^24), the low K - P bits of the sorted codes (n when K - P <= 8, 2n when
+//          K - P <= 16, 4n when larger, none when K <= P), the P-bit prefix table
+//          (4 (2^P + 1)), the table's K hyperplanes and their GEMM word
+//          (independent functions), its K pool indices (pooling) or its cross-polytope
+//          sign words.
+static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, int32_t pool, int32_t family, int32_t posb,
+                         int32_t P, uint64_t &fixed, uint64_t &per) {
     const uint64_t un = (uint64_t)n, ud = (uint64_t)d;
-    const int32_t P = std::min(13, K);
     const int32_t dpad = (d + 3) / 4 * 4;
     int32_t hs, ls, rq, co;
     plane_strides(dpad, &hs, &ls);
@@ -177,8 +178,8 @@ static void budget_terms(int64_t n, int32_t d, int32_t K, int32_t M, int32_t poo
     const bool cp = family == PF_FAMILY_FHTCP;
     fixed = 2ull * un * (uint64_t)(hs + std::max(ls, 1)) + un * (uint64_t)rq + (co == 0 ? 8ull * un : 0ull) +
             4ull * 64ull * (uint64_t)M * ud + 4ull * (uint64_t)pool * ud +
-            (2ull * (uint64_t)M + (uint64_t)(pool / 32)) * word;
-    per = (12ull + (uint64_t)code_suffix_bytes(K, P)) * un + 4ull * ((1ull << P) + 1ull);
+            (2ull * (uint64_t)M + (uint64_t)(pool / 32)) * word + (uint64_t)kPosPad;
+    per = (8ull + (uint64_t)posb + (uint64_t)code_suffix_bytes(K, P)) * un + 4ull * ((1ull << P) + 1ull);
     if (cp) {
         int32_t dp, ell;
         cp_dims(d, dp, ell);
@@ -350,7 +351,7 @@ PF_API int pf_normalize(const float *x, int64_t n, int32_t d, float *out, int32_
 // (host only; shared by pf_plan_index and pf_build_index).
 struct BuildPlan {
     pf_build_opts o;
-    int32_t K, M;
+    int32_t K, M, posb, P;
     int64_t L;
     uint64_t fixed, per;
 };
@@ -374,7 +375,13 @@ static BuildPlan plan_build(int64_t n, int32_t d, uint64_t budget, const pf_buil
     PF_CHECK(o.family == PF_FAMILY_HP || o.family == PF_FAMILY_FHTCP, PF_EINVAL, "pf_build_index: bad family");
     PF_CHECK(o.family == PF_FAMILY_HP || o.pool == 0, PF_EINVAL,
              "pf_build_index: pooling is implemented for hyperplane functions");
-    budget_terms(n, d, K, M, o.pool, o.family, b.fixed, b.per);
+    PF_CHECK(o.pos_bytes == 0 || o.pos_bytes == 4 || (o.pos_bytes == 3 && n <= (1ll << 24)), PF_EINVAL,
+             "pf_build_index: pos_bytes must be 0, 4, or 3 with n <= 2^24");
+    PF_CHECK(o.prefix_bits == 0 || (o.prefix_bits >= prefix_bits_min(K) && o.prefix_bits <= prefix_bits_max(K)),
+             PF_EINVAL, "pf_build_index: prefix_bits must be 0 or in [min(13, K), min(24, K)]");
+    b.posb = pos_bytes_for(n, o.pos_bytes);
+    b.P = o.prefix_bits ? o.prefix_bits : choose_prefix_bits(n, K);
+    budget_terms(n, d, K, M, o.pool, o.family, b.posb, b.P, b.fixed, b.per);
     int64_t L = o.L_override;
     if (L <= 0) L = budget > b.fixed ? (int64_t)((budget - b.fixed) / b.per) : 0;
     PF_CHECK(L >= 1, PF_EBUDGET, "pf_build_index: the memory budget holds no table");
@@ -424,7 +431,7 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         ix->dpad = (d + 3) / 4 * 4;
         ix->K = K;
         ix->M = M;
-        ix->P = std::min(13, K);
+        ix->P = bp.P;
         ix->L = (int32_t)L;
         ix->seed = o.seed;
         ix->hash_mode = o.hash_mode;
@@ -494,11 +501,10 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
             PF_HIP(hipMemcpyAsync(&ix->a8, gmax.as<uint32_t>() + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         }
         // a6: sorted tables (the full codes only while the index is built)
-        DevBuf tcode;
+        DevBuf tcode, tidx;
         tcode.alloc((size_t)L * n * sizeof(uint32_t));
-        ix->tidx.alloc((size_t)L * n * sizeof(uint32_t));
-        sort_tables(codes.as<uint32_t>(), n, (int32_t)L, K, tcode.as<uint32_t>(), ix->tidx.as<uint32_t>(), scratch,
-                    s);
+        tidx.alloc((size_t)L * n * sizeof(uint32_t));
+        sort_tables(codes.as<uint32_t>(), n, (int32_t)L, K, tcode.as<uint32_t>(), tidx.as<uint32_t>(), scratch, s);
         // a7: prefix tables, then the codes' low K - P bits (the prefix table holds the rest)
         ix->off.alloc((size_t)L * ((1ull << ix->P) + 1) * sizeof(uint32_t));
         prefix_tables(tcode.as<uint32_t>(), n, (int32_t)L, K, ix->P, ix->off.as<uint32_t>(), s);
@@ -509,7 +515,12 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         }
         // a8: table-local sketches
         ix->tsk.alloc((size_t)L * n * sizeof(uint64_t));
-        gather_sketches(ix->tidx.as<uint32_t>(), sk.as<uint64_t>(), n, (int32_t)L, M, ix->tsk.as<uint64_t>(), s);
+        gather_sketches(tidx.as<uint32_t>(), sk.as<uint64_t>(), n, (int32_t)L, M, ix->tsk.as<uint64_t>(), s);
+        // the positions in the fewest whole bytes that hold them (the 4-byte array only while
+        // the index is built)
+        ix->posb = bp.posb;
+        ix->tpos.alloc((size_t)L * n * ix->posb + (size_t)kPosPad);
+        pack_positions(tidx.as<uint32_t>(), (int64_t)L * n, ix->posb, ix->tpos.as<uint8_t>(), s);
         PF_HIP(hipEventRecord(e1, s));
         PF_HIP(hipStreamSynchronize(s));
         float ms = 0;
@@ -967,10 +978,15 @@ PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_by
             PF_HIP(hipStreamSynchronize(s));
             break;
         }
-        case PF_EXPORT_IDX:
+        case PF_EXPORT_IDX: {
             need((int64_t)ix->L * n * 4);
-            PF_HIP(hipMemcpyAsync(dst, ix->tidx.p, (size_t)ix->L * n * 4, kind, s));
+            DevBuf pos;
+            pos.alloc((size_t)ix->L * n * 4);
+            unpack_positions(ix->tpos.as<uint8_t>(), (int64_t)ix->L * n, ix->posb, pos.as<uint32_t>(), s);
+            PF_HIP(hipMemcpyAsync(dst, pos.p, (size_t)ix->L * n * 4, kind, s));
+            PF_HIP(hipStreamSynchronize(s));
             break;
+        }
         case PF_EXPORT_SKETCHES:
             need((int64_t)ix->L * n * 8);
             PF_HIP(hipMemcpyAsync(dst, ix->tsk.p, (size_t)ix->L * n * 8, kind, s));
@@ -1028,8 +1044,9 @@ PF_API int pf_index_info(const pf_index *ix, pf_info *info) {
         r.family = ix->family;
         r.bytes_budget_rule = ix->bytes_rule;
         r.bytes_device = ix->Xh.bytes + ix->Xl.bytes + ix->Xq.bytes + ix->Xqh.bytes + ix->hp.bytes + ix->hcolrow.bytes + ix->hbf.bytes + ix->hbeta.bytes +
-                         ix->psel.bytes + ix->cpsign.bytes + ix->cptab.bytes + ix->tsuf.bytes + ix->tidx.bytes + ix->tsk.bytes + ix->off.bytes;
+                         ix->psel.bytes + ix->cpsign.bytes + ix->cptab.bytes + ix->tsuf.bytes + ix->tpos.bytes + ix->tsk.bytes + ix->off.bytes;
         r.build_ms = ix->build_ms;
+        r.pos_bytes = ix->posb;
         *info = r;
     });
 }

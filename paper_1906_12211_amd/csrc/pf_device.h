@@ -32,4 +32,19 @@ __device__ __forceinline__ uint32_t row_sum16u(uint32_t s) {
     return s;
 }
 
+// table position g of a positions array stored in PB bytes each (4, or 3 little endian;
+// a 3-byte array carries 8 bytes of padding so that the word after any entry's last byte
+// can be read)
+template <int PB> __device__ __forceinline__ uint32_t read_pos(const void *__restrict__ pos, uint32_t g) {
+    if constexpr (PB == 4) {
+        return static_cast<const uint32_t *>(pos)[g];
+    } else {
+        static_assert(PB == 3, "positions are stored in 3 or 4 bytes");
+        const uint64_t b = 3ull * g;
+        const uint32_t *w = static_cast<const uint32_t *>(pos) + (b >> 2);
+        const uint64_t two = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+        return (uint32_t)(two >> (8 * (b & 3))) & 0xFFFFFFu;
+    }
+}
+
 } // namespace pf

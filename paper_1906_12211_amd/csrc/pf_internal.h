@@ -117,7 +117,8 @@ struct Index {
     DevBuf hbeta;  // ncols FP32 flag bounds (negative = never flagged)
     DevBuf tsuf;   // L x n low K - P bits of the sorted codes (sufw bytes each; none when K <= P)
     int32_t sufw = 0;
-    DevBuf tidx;   // L x n u32
+    DevBuf tpos;   // L x n table positions, posb bytes each (little endian), then kPosPad bytes
+    int32_t posb = 4;
     DevBuf tsk;    // L x n u64
     DevBuf off;    // L x (2^P + 1) u32
 
@@ -214,13 +215,26 @@ void sort_tables(const uint32_t *codes, int64_t n, int32_t L, int32_t K, uint32_
 void prefix_tables(const uint32_t *tcode, int64_t n, int32_t L, int32_t K, int32_t P,
                    uint32_t *off, hipStream_t s);
 // resident sorted codes: the low K - P bits of each code (code_suffix_bytes per entry:
-// 0 when K <= P, 2 when K - P <= 16, else 4), and the full codes rebuilt from them
+// 0 when K <= P, 1 when K - P <= 8, 2 when K - P <= 16, else 4), and the full codes rebuilt
+// from them
 int32_t code_suffix_bytes(int32_t K, int32_t P);
+// prefix widths a table may use: [min(13, K), min(24, K)]; the default is the one with the
+// fewest resident bytes for n entries
+int32_t prefix_bits_min(int32_t K);
+int32_t prefix_bits_max(int32_t K);
+int32_t choose_prefix_bits(int64_t n, int32_t K);
 void code_suffixes(const uint32_t *tcode, int64_t n, int32_t L, int32_t K, int32_t P, void *suf, hipStream_t s);
 void join_codes(const void *suf, const uint32_t *off, int64_t n, int32_t L, int32_t K, int32_t P, uint32_t *out,
                 hipStream_t s);
 void gather_sketches(const uint32_t *tidx, const uint64_t *sk, int64_t n, int32_t L,
                      int32_t M, uint64_t *tsk, hipStream_t s);
+// Table positions stored in posb bytes (3: n <= 2^24, little endian; 4) and widened back
+constexpr int64_t kPosPad = 8;
+int32_t pos_bytes_for(int64_t n, int32_t want);
+// the search kernel for an index with 3-byte positions (row chunks dt, tile, shared-scale rows)
+const void *search_kernel_pos3(int dt, int tile, bool shared);
+void pack_positions(const uint32_t *in, int64_t count, int32_t posb, uint8_t *out, hipStream_t s);
+void unpack_positions(const uint8_t *in, int64_t count, int32_t posb, uint32_t *out, hipStream_t s);
 
 // search; see k_search.hip
 struct SearchArgs {

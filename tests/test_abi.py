@@ -108,24 +108,39 @@ def test_bench_algorithmic_bytes_formula():
 def test_plan_index_charges_every_resident_byte():
     """The budget rule as pf_build_index applies it, evaluated on the host (no device):
     L is the largest table count whose device bytes fit the budget; one more table
-    would not fit; each table adds its positions and sketches (12n), the 16-bit low parts
-    of its K = 24-bit codes (2n), its prefix table, K hyperplanes and their BF16 GEMM word
-    (32 columns of kp = ceil(d/16)*16 hi + lo BF16 values, a row index and a flag bound
-    each); beyond the tables the index holds at least the vectors and sketch functions
-    the paper counts plus a byte per coordinate of summaries."""
-    cases = [(10_000, 64, 64 << 20, 331), (1_000_000, 100, 2 << 30, 115), (1_000_000, 256, 2 << 30, 60),
-             (10_000_000, 128, 16 << 30, 76), (1_000_000, 300, 2 << 30, 39)]
-    for n, d, budget, want_L in cases:
-        L, nbytes = pf.pf_plan_index(n, d, budget)
-        assert L == want_L, (n, d)
-        assert nbytes <= budget
-        L1, nbytes1 = pf.pf_plan_index(n, d, budget, L=L + 1)
-        assert L1 == L + 1 and nbytes1 > budget
-        kp = (d + 15) // 16 * 16
-        per = (12 + 2) * n + 4 * ((1 << 13) + 1) + 4 * 24 * d + 32 * (4 * kp + 8)
-        assert nbytes1 - nbytes == per
-        paper_fixed = 4 * n * d + 4 * 64 * 32 * d
-        assert nbytes - L * per >= paper_fixed + n * d  # + at least one byte per coordinate of summaries
+    would not fit; each table adds its sketches (8n), its positions (4n, or 3n when 3-byte
+    positions are asked for), the low K - P bits of its K = 24-bit codes (n for P = 16, 2n
+    for P = 13), its P-bit prefix table, K hyperplanes and their BF16 GEMM word (32
+    columns of kp = ceil(d/16)*16 hi + lo BF16 values, a row index and a flag bound each);
+    beyond the tables the index holds at least the vectors and sketch functions the paper
+    counts plus a byte per coordinate of summaries.  The default prefix width is the one
+    with the fewest bytes: 16 once n passes about 229,000 entries, else 13."""
+    # n, d, budget, L by default, with 3-byte positions, with P = 13, with both
+    cases = [(10_000, 64, 64 << 20, 331, 350, 331, 350), (1_000_000, 100, 2 << 30, 121, 131, 115, 123),
+             (1_000_000, 256, 2 << 30, 64, 69, 60, 65), (10_000_000, 128, 16 << 30, 82, 88, 76, 82),
+             (1_000_000, 300, 2 << 30, 41, 45, 39, 42)]
+    for n, d, budget, *want in cases:
+        Pdef = 16 if n > 229_376 else 13
+        for (posb, P), want_L in zip(((0, 0), (3, 0), (0, 13), (3, 13)), want):
+            L, nbytes = pf.pf_plan_index(n, d, budget, pos_bytes=posb, prefix_bits=P)
+            assert L == want_L, (n, d, posb, P)
+            assert nbytes <= budget
+            L1, nbytes1 = pf.pf_plan_index(n, d, budget, L=L + 1, pos_bytes=posb, prefix_bits=P)
+            assert L1 == L + 1 and nbytes1 > budget
+            kp = (d + 15) // 16 * 16
+            Pu = P or Pdef
+            per = ((8 + (posb or 4) + (1 if Pu == 16 else 2)) * n + 4 * ((1 << Pu) + 1) + 4 * 24 * d
+                   + 32 * (4 * kp + 8))
+            assert nbytes1 - nbytes == per
+            paper_fixed = 4 * n * d + 4 * 64 * 32 * d
+            assert nbytes - L * per >= paper_fixed + n * d  # + at least one byte per coordinate of summaries
+    # the default width is the cheapest of all allowed ones, for a few sizes and code lengths
+    for n in (1, 1000, 229_375, 229_377, 10 ** 6, 10 ** 8):
+        for K in (8, 13, 14, 20, 24, 29, 32):
+            lo, hi = min(13, K), min(24, K)
+            sizes = {P: pf.pf_plan_index(n, 16, 1 << 50, K=K, L=1, prefix_bits=P)[1] for P in range(lo, hi + 1)}
+            dflt = pf.pf_plan_index(n, 16, 1 << 50, K=K, L=1)[1]
+            assert dflt == min(sizes.values()), (n, K)
     # pooled and cross-polytope indexes fit their budgets too
     for kw in (dict(pool=3072), dict(family=pf.PF_FAMILY_FHTCP)):
         L, nbytes = pf.pf_plan_index(1_000_000, 100, 2 << 30, **kw)
@@ -136,6 +151,20 @@ def test_plan_index_charges_every_resident_byte():
     with pytest.raises(pf.PfError) as e:
         pf.pf_plan_index(0, 100, 2 << 30)
     assert e.value.code == pf.PF_EINVAL
+    # 3-byte positions need every position below 2^24; other widths are refused
+    for n, posb in ((1 << 24, 3), (1 << 24, 4), ((1 << 24) + 1, 4), ((1 << 24) + 1, 0)):
+        pf.pf_plan_index(n, 16, 1 << 40, pos_bytes=posb)
+    for n, posb in (((1 << 24) + 1, 3), (1000, 2), (1000, 8), (1000, -1)):
+        with pytest.raises(pf.PfError) as e:
+            pf.pf_plan_index(n, 16, 1 << 40, pos_bytes=posb)
+        assert e.value.code == pf.PF_EINVAL, (n, posb)
+    # prefix widths: [min(13, K), min(24, K)] or 0
+    for K, P in ((24, 13), (24, 24), (10, 10), (32, 24), (14, 14)):
+        pf.pf_plan_index(1000, 16, 1 << 40, K=K, prefix_bits=P)
+    for K, P in ((24, 12), (24, 25), (10, 11), (10, 9), (32, 25), (24, -1)):
+        with pytest.raises(pf.PfError) as e:
+            pf.pf_plan_index(1000, 16, 1 << 40, K=K, prefix_bits=P)
+        assert e.value.code == pf.PF_EINVAL, (K, P)
 
 
 def test_measurement_aids_reject_bad_arguments_before_any_device_call():

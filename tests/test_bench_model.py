@@ -1,5 +1,5 @@
 """The benchmark's byte models (host only): the algorithmic bytes of a launch from the
-kernel's per-query counters, and the same bytes with each passing entry's 4-byte position
+kernel's per-query counters, and the same bytes with each passing entry's position
 priced as the 128-byte line a scattered read brings in."""
 import os
 import sys
@@ -54,3 +54,27 @@ def test_line_model_against_simulated_lines():
     model = bench.line_model_bytes(st, 128, 10, 76, 24) - bench.algorithmic_bytes(st, 128, 10, 76, 24)
     simulated = 128 * lines - 4 * npass
     assert abs(model - simulated) <= 0.01 * simulated
+
+
+def test_three_byte_positions():
+    """3-byte positions: posb B per passing entry in the algorithmic bytes, and 128 / 3
+    positions per line in the line model, against counting the lines that the 8-byte read
+    of each passing entry (the two words from the one holding its first byte) touches on
+    random pass patterns; the model ignores the reads that cross into the next line."""
+    d, k, L, K = 128, 10, 82, 24
+    st = _stats([(6, 1000, 40, 40, 3, 2)])
+    assert bench.algorithmic_bytes(st, d, k, L, K, 3) == bench.algorithmic_bytes(st, d, k, L, K) - 40
+    assert bench.filter_bytes(st, 3) == 8 * 1000 + 3 * 40
+    rng = np.random.default_rng(11)
+    scan, f = 3 * 32 * 4096, 0.037
+    first = 4 * ((3 * np.arange(scan)) // 4)
+    simulated, npass_all = [], []
+    for _ in range(10):
+        hit = rng.random(scan) < f
+        lines = np.union1d(first[hit] // 128, (first[hit] + 7) // 128)
+        simulated.append(128 * lines.size - 3 * hit.sum())
+        npass_all.append(hit.sum())
+    npass = int(round(np.mean(npass_all)))
+    st = _stats([(6, scan, npass, npass, 0, 0)])
+    model = bench.line_model_bytes(st, d, k, L, K, posb=3) - bench.algorithmic_bytes(st, d, k, L, K, 3)
+    assert -0.01 * np.mean(simulated) <= np.mean(simulated) - model <= 0.05 * np.mean(simulated)

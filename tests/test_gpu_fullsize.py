@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size, in the launch configuration bench.py times.
 
-mixture-1M-d100 (n = 1,000,000, d = 100, 2 GiB -> L = 115, 10,000 queries, k = 10, recall
+mixture-1M-d100 (n = 1,000,000, d = 100, 2 GiB -> L = 121, 10,000 queries, k = 10, recall
 0.9): the GPU index against the oracle's, structure by structure (bit-exact), then the
 whole query batch answered by the learned-batched path with the autotuned tile shape,
 compared with the oracle on a sample of the queries (ids, FP32 inner-product bit
@@ -14,6 +14,7 @@ import pytest
 import oracle
 import paper_1906_12211_amd as pf
 import workloads
+from prefix_tables import check_offsets
 
 pytestmark = pytest.mark.gpu
 
@@ -32,17 +33,19 @@ def full():
 
 def test_fullsize_index_bit_exact(full):
     c, g, o = full
-    assert g.L == o.L == 115
+    assert g.L == o.L == 121 and g.P == 16
     info = g.info()
     assert info.bytes_device == info.bytes_budget_rule <= c["budget"]
     for what, ref, name in [(pf.PF_EXPORT_CODES, o.tcode, "codes"), (pf.PF_EXPORT_IDX, o.tidx, "positions"),
-                            (pf.PF_EXPORT_OFFSETS, o.off, "prefix tables"),
                             (pf.PF_EXPORT_SKETCHES, o.tsk, "table-local sketches"),
                             (pf.PF_EXPORT_POINTS, o.points, "normalised points")]:
         got = g.export(what)
         bad = int(np.count_nonzero(got != ref))
         print(f"[fullsize] {name}: {bad} mismatches of {ref.size}", flush=True)
         assert bad == 0, name
+    bad = check_offsets(g.export(pf.PF_EXPORT_OFFSETS), o, g.P)
+    print(f"[fullsize] prefix tables (P = {g.P}): {bad} mismatches", flush=True)
+    assert bad == 0
 
 
 def _sample(m, count, seed):

@@ -2,8 +2,8 @@
 launch configuration bench.py times.
 
 planted-1M-d256 (n = 1,000,000 uniform unit vectors in d = 256 with planted neighbours,
-10,000 queries, 2 GiB -> L = 60, k = 1, recall 0.5 / 0.9 / 0.99) and mixture-10M-d128
-(n = 10,000,000, d = 128, 100,000 clusters, 16 GiB -> L = 76, 100,000 queries, k = 10, recall
+10,000 queries, 2 GiB -> L = 64, k = 1, recall 0.5 / 0.9 / 0.99) and mixture-10M-d128
+(n = 10,000,000, d = 128, 100,000 clusters, 16 GiB -> L = 82, 100,000 queries, k = 10, recall
 0.9, the learned-batched path): the oracle builds its own index from the same seeded points
 (in a thread, while the GPU works; the C library releases the interpreter lock), every
 structure is compared bit for bit, and a sample of the batch answered by the GPU is compared
@@ -18,6 +18,7 @@ import pytest
 import oracle
 import paper_1906_12211_amd as pf
 import workloads
+from prefix_tables import check_offsets
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1200)]
 
@@ -37,13 +38,16 @@ def _oracle_in_thread(X, budget, L):
 
 def _structures_equal(g, o, label):
     for what, name in [(pf.PF_EXPORT_POINTS, "points"), (pf.PF_EXPORT_CODES, "tcode"), (pf.PF_EXPORT_IDX, "tidx"),
-                       (pf.PF_EXPORT_OFFSETS, "off"), (pf.PF_EXPORT_SKETCHES, "tsk")]:
+                       (pf.PF_EXPORT_SKETCHES, "tsk")]:
         got = g.export(what)
         ref = getattr(o, name)
         bad = int(np.count_nonzero(got != ref))
         print(f"[{label}] {name}: {bad} mismatches of {ref.size}", flush=True)
         assert bad == 0, f"{label} {name}"
         del got
+    bad = check_offsets(g.export(pf.PF_EXPORT_OFFSETS), o, g.P)
+    print(f"[{label}] off (P = {g.P}): {bad} mismatches", flush=True)
+    assert bad == 0, f"{label} off"
 
 
 def _sampled_equal(ids, ips, sts, sel, orr, k, label):

@@ -12,13 +12,17 @@ import pytest
 import oracle
 import paper_1906_12211_amd as pf
 import workloads
+from prefix_tables import check_offsets
 
 pytestmark = pytest.mark.gpu
 
 
-def _build_both(X, budget=0, L=None, seed=42, K=24, M=32, hash_mode=pf.PF_HASH_BF16X3):
-    print(f"[build] n={len(X)} d={X.shape[1]} L={L} budget={budget} K={K} M={M} mode={hash_mode}", flush=True)
-    g = pf.Index(X, budget, seed=seed, K=K, M=M, hash_mode=hash_mode, L=L)
+def _build_both(X, budget=0, L=None, seed=42, K=24, M=32, hash_mode=pf.PF_HASH_BF16X3, pos_bytes=0,
+                prefix_bits=0):
+    print(f"[build] n={len(X)} d={X.shape[1]} L={L} budget={budget} K={K} M={M} mode={hash_mode} "
+          f"pos_bytes={pos_bytes} prefix_bits={prefix_bits}", flush=True)
+    g = pf.Index(X, budget, seed=seed, K=K, M=M, hash_mode=hash_mode, L=L, pos_bytes=pos_bytes,
+                 prefix_bits=prefix_bits)
     o = oracle.OracleIndex(X, budget, seed=seed, K=K, M=M, L=g.L)
     return g, o
 
@@ -31,7 +35,7 @@ def _assert_index_equal(g, o):
     bad = np.argwhere(gc != o.tcode)
     assert bad.size == 0, f"{len(bad)} code mismatches, first {bad[:5]}"
     assert np.array_equal(gi, o.tidx), "table order"
-    assert np.array_equal(g.export(pf.PF_EXPORT_OFFSETS), o.off), "prefix tables"
+    assert check_offsets(g.export(pf.PF_EXPORT_OFFSETS), o, g.P) == 0, "prefix tables"
     assert np.array_equal(g.export(pf.PF_EXPORT_SKETCHES), o.tsk), "table-local sketches"
 
 
@@ -98,19 +102,60 @@ def test_hash_queries_bit_exact():
     assert np.array_equal(gs, os_)
 
 
-def test_config1_parity():
-    """gauss-10k-d64, 64 MiB budget -> L = 331 (every resident byte charged), 1000 queries,
-    k = 10, recall .9; the index's device bytes are the planned ones and fit the budget"""
+@pytest.mark.parametrize("pos_bytes,want_L", [(0, 331), (3, 350)])
+def test_config1_parity(pos_bytes, want_L):
+    """gauss-10k-d64, 64 MiB budget -> L = 331 (every resident byte charged; 350 with 3-byte
+    table positions), 1000 queries, k = 10, recall .9; the index's device bytes are the
+    planned ones and fit the budget"""
     c = workloads.config(1)
-    g, o = _build_both(c["points"], budget=c["budget"])
-    assert g.L == 331
+    g, o = _build_both(c["points"], budget=c["budget"], pos_bytes=pos_bytes)
+    assert (g.L, g.pos_bytes, g.P) == (want_L, pos_bytes or 4, 13)
     info = g.info()
-    assert info.bytes_device == info.bytes_budget_rule == pf.pf_plan_index(10_000, 64, c["budget"])[1]
+    assert info.bytes_device == info.bytes_budget_rule == pf.pf_plan_index(10_000, 64, c["budget"],
+                                                                            pos_bytes=pos_bytes)[1]
     assert info.bytes_device <= c["budget"]
     _assert_index_equal(g, o)
     gr = g.search(c["queries"], 10, 0.9)
     orr = o.search(c["queries"], 10, 0.9)
     _assert_search_equal(gr, orr, "config1")
+
+
+@pytest.mark.parametrize("n,L", [(997, 1), (998, 3), (999, 5), (1000, 7), (4093, 9)])
+def test_table_positions_any_count(n, L):
+    """3-byte table positions for every remainder of L n modulo 4 (the last packed group
+    partly filled), against 4-byte positions of the same index and the oracle's tables;
+    the searches agree too."""
+    X = workloads.gaussian_unit(n, 40, 31)
+    Q = workloads.gaussian_unit(64, 40, 32)
+    g3, o = _build_both(X, L=L, seed=n, pos_bytes=3)
+    g4 = pf.Index(X, 0, seed=n, L=L, pos_bytes=4)
+    assert (g3.pos_bytes, g4.pos_bytes) == (3, 4)
+    _assert_index_equal(g3, o)
+    assert np.array_equal(g4.export(pf.PF_EXPORT_IDX), o.tidx)
+    assert g4.info().bytes_device - g3.info().bytes_device == L * n
+    r3, r4 = g3.search(Q, 10, 0.9), g4.search(Q, 10, 0.9)
+    assert np.array_equal(r3.ids, r4.ids) and np.array_equal(r3.stats[:, :4], r4.stats[:, :4])
+    _assert_search_equal(r3, o.search(Q, 10, 0.9), f"positions n={n} L={L}")
+
+
+@pytest.mark.parametrize("K,P,suffix", [(24, 13, 2), (24, 14, 2), (24, 16, 1), (24, 17, 1), (24, 24, 0),
+                                         (20, 13, 1), (21, 13, 1), (22, 13, 2), (32, 16, 2), (32, 15, 4),
+                                         (32, 24, 1), (14, 14, 0)])
+def test_prefix_widths(K, P, suffix):
+    """Every prefix width the index may take, on a small ragged index: the exported prefix
+    table against its definition over the oracle's codes, the codes rebuilt from prefix
+    and low bits (8-, 16- or 32-bit, or none), and the search (levels at and above P read
+    the prefix table, deeper ones the range kernels over the low bits)."""
+    X = workloads.gaussian_unit(3001, 24, 41)
+    Q = workloads.gaussian_unit(50, 24, 42)
+    g, o = _build_both(X, L=7, seed=K * 100 + P, K=K, prefix_bits=P)
+    assert g.P == P
+    per = pf.pf_plan_index(3001, 24, 0, K=K, L=2, prefix_bits=P)[1] - pf.pf_plan_index(3001, 24, 0, K=K, L=1,
+                                                                                        prefix_bits=P)[1]
+    assert per == (8 + 4 + suffix) * 3001 + 4 * ((1 << P) + 1) + 4 * K * 24 + 32 * (4 * 32 + 8)
+    _assert_index_equal(g, o)
+    for k, rec in [(1, 0.9), (10, 0.9), (10, 0.99)]:
+        _assert_search_equal(g.search(Q, k, rec), o.search(Q, k, rec), f"P={P} K={K} k={k}")
 
 
 @pytest.mark.parametrize("k,recall,kw", [
@@ -251,7 +296,7 @@ def test_large_prefix_buckets():
     Q = np.concatenate([(centers + np.float32(1e-2) * rng.standard_normal((4, d))).astype(np.float32)
                         for _ in range(8)] + [workloads.gaussian_unit(32, d, 604)])
     g, o = _build_both(X, L=16, seed=606)
-    off = g.export(pf.PF_EXPORT_OFFSETS)
+    off = g.export(pf.PF_EXPORT_OFFSETS)[:, ::1 << (g.P - 13)]
     sizes = np.diff(off.astype(np.int64), axis=1)
     print(f"[buckets] largest 13-bit buckets {np.sort(sizes.ravel())[-6:]}", flush=True)
     assert sizes.max() > 4080 and ((sizes > 3000) & (sizes <= 4080)).any()

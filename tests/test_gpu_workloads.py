@@ -38,7 +38,7 @@ def test_planted_full_recall():
     X, Q, pid = c["points"], c["queries"], c["planted"]
     g = pf.Index(torch.from_numpy(X).cuda(), c["budget"], seed=workloads.INDEX_SEED)
     print(f"[planted] n={len(X)} d={X.shape[1]} L={g.L} queries={len(Q)}", flush=True)
-    assert g.L == 60 and g.info().bytes_device <= c["budget"]
+    assert g.L == 64 and g.info().bytes_device <= c["budget"]
     Qd = torch.from_numpy(Q).cuda()
     for rec in (0.5, 0.9, 0.99):
         r = g.search(Qd, 1, rec, timing=True)
