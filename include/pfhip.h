@@ -287,7 +287,7 @@ int pf_search(pf_index *ix, const float *queries, int64_t m, int32_t k, double r
  * ordered on `stream` and synchronises it before returning.  All calls on one device share
  * that device's array: calls that overlap in time on one device race (one at a time per
  * device).  Errors: as pf_search; PF_EUNSUPPORTED when the m queries' buffers exceed the
- * 64 MiB array (e.g. about 6,000 queries at n = 10^6, d = 100, L = 100: split the batch);
+ * 64 MiB array (e.g. about 6,500 queries at n = 10^6, d = 100, L = 121: split the batch);
  * PF_EINVAL when the current device is not the index's. */
 int pf_search_noalloc(pf_index *ix, const float *queries, int64_t m, int32_t k, double recall,
                       int32_t *out_ids, float *out_ips, pf_query_stats *stats, void *stream);

@@ -414,10 +414,10 @@ int oracle_build_tables(const uint32_t *codes, int64_t n, int32_t L, int32_t K, 
     return err ? OR_ENOMEM : OR_OK;
 }
 
-/* Sketch chosen for repetition j: "a pseudorandom transformation of the repetition
- * number" (Sec. 4.2, "Filtering candidate points").  The sketch hyperplanes are
- * independent, so any fixed map is equivalent in distribution; this oracle takes
- * sigma(j) = j mod M and stores, per table, the sketch of each sorted entry. */
+/* Sketch chosen for repetition j: Sec. 4.2 ("Filtering candidate points") lets each
+ * repetition pick one of the M sketches by a fixed scrambling of its index.  The sketch
+ * hyperplanes are independent, so any fixed map is equivalent in distribution; this
+ * oracle takes sigma(j) = j mod M and stores, per table, the sketch of each sorted entry. */
 void oracle_table_sketches(const uint32_t *tidx, const uint64_t *sketches, int64_t n, int32_t L,
                            int32_t M, uint64_t *tsk) {
     for (int32_t j = 0; j < L; ++j) {
