@@ -129,6 +129,12 @@ typedef struct {
                           1 = once per level (Sec. 4.1), L = after every repetition
                           (Algorithm 1); 0 selects the default, min(L, 16); at most
                           min(L, 64), PF_EINVAL beyond                                    */
+    int32_t test_entries; /* T: a group's stopping test is taken only once at least T
+                          entries were read since the level's previous test (always after
+                          the level's last group; groups without entries that directly
+                          follow a tested group are tested with it), so that a query
+                          that reads few entries per group tests less often; 0 selects
+                          the default, 256; a negative value tests after every group    */
 } pf_search_opts;
 
 typedef struct {

@@ -26,6 +26,7 @@ DEFAULT_K = 24
 DEFAULT_M = 32
 DEFAULT_B = 12
 DEFAULT_GROUPS = 16  # stopping tests per level (at most L): the method's default parameter
+DEFAULT_TEST_ENTRIES = 256  # a group's test waits for this many entries since the previous one
 
 
 def build(verbose: bool = False) -> str:
@@ -101,7 +102,7 @@ def lib():
         L.oracle_search.restype = ctypes.c_int
         L.oracle_search.argtypes = [
             _P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P, _I32, _P, _U64,
-            _P, _I64, _I32, _D, _D, _I32, _I32, _I32, _I32,
+            _P, _I64, _I32, _D, _D, _I32, _I32, _I32, _I32, _I32,
             _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
         ]
         L.oracle_bruteforce.restype = ctypes.c_int
@@ -351,12 +352,17 @@ class OracleIndex:
 
     def search(self, queries: np.ndarray, k: int, recall: float, eps: float = 0.0,
                B: int = DEFAULT_B, rule: int = RULE_FILTER, filter_on: bool = True,
-               trace: bool = False, groups: int | None = None) -> SearchResult:
-        """groups: stopping tests per level (None: min(L, DEFAULT_GROUPS))."""
+               trace: bool = False, groups: int | None = None, test_entries: int | None = None) -> SearchResult:
+        """groups: stopping tests per level (None: min(L, DEFAULT_GROUPS)); test_entries: a
+        group's test is skipped while fewer entries were read since the previous test (None:
+        DEFAULT_TEST_ENTRIES; 0: a test after every group)."""
         if groups is None:
             groups = min(self.L, DEFAULT_GROUPS)
+        if test_entries is None:
+            test_entries = DEFAULT_TEST_ENTRIES
         return search_tables(self.points, self.hp, self.tcode, self.tidx, self.tsk, self.K, self.M, queries, k,
                              recall, eps=eps, B=B, rule=rule, filter_on=filter_on, trace=trace, groups=groups,
+                             test_entries=test_entries,
                              sel=getattr(self, "sel", None), pool=getattr(self, "pool", 0),
                              cptab=getattr(self, "cptab", None), seed=getattr(self, "seed", 0))
 
@@ -368,11 +374,12 @@ def search_tables(points: np.ndarray, hp: np.ndarray, tcode: np.ndarray, tidx: n
                   K: int, M: int, queries: np.ndarray, k: int, recall: float, eps: float = 0.0,
                   B: int = DEFAULT_B, rule: int = RULE_FILTER, filter_on: bool = True, trace: bool = False,
                   sel: np.ndarray | None = None, pool: int = 0, cptab: np.ndarray | None = None,
-                  seed: int = 0, groups: int = 1) -> SearchResult:
+                  seed: int = 0, groups: int = 1, test_entries: int = 0) -> SearchResult:
     """The adaptive query over given tables: normalised points (n x d), the hyperplanes
     the queries are hashed with, and the L sorted tables (codes, positions, table-local
     sketches).  groups: the stopping test runs after each of that many consecutive groups
-    of tables in a level (1: once per level).  With trace=True the walk of query 0 is
+    of tables in a level (1: once per level); test_entries > 0 skips a group's test while
+    fewer entries than that were read since the level's previous test.  With trace=True the walk of query 0 is
     recorded: ``trace`` per level and
     table (lo_i, hi_i, c_lo, c_hi), ``levels`` per level (threshold used, masks of the new,
     passing and top-k point ids, c_scan, c_pass, c_rerank, stopped)."""
@@ -402,7 +409,7 @@ def search_tables(points: np.ndarray, hp: np.ndarray, tcode: np.ndarray, tidx: n
     rc = lib().oracle_search(
         _ptr(points), n, d, _ptr(hp), _ptr(tcode), _ptr(tidx), _ptr(tsk), L, K, M, _ptr(sel), pool,
         _ptr(tab), seed, _ptr(q), m, k, recall, eps, B, rule,
-        1 if filter_on else 0, int(groups), _ptr(ids), _ptr(ips), _ptr(ips64), _ptr(sl), _ptr(cs),
+        1 if filter_on else 0, int(groups), int(test_entries), _ptr(ids), _ptr(ips), _ptr(ips64), _ptr(sl), _ptr(cs),
         _ptr(cp), _ptr(cr), _ptr(bd), _ptr(tr), _ptr(lt))
     if rc:
         raise ValueError(f"oracle_search rc={rc}")

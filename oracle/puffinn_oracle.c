@@ -579,7 +579,11 @@ int oracle_stop(float ip_k, int32_t i, int32_t L, int32_t M, double delta, int32
  * as in Sec. 4.1-4.2).  Readings taken where the paper leaves freedom:
  *  - rounds are level-synchronous: in level i every repetition j = 1..L contributes its
  *    new entries, with the stopping test after each of `groups` consecutive groups of
- *    repetitions (once per level, as in Sec. 4.1, when groups = 1);
+ *    repetitions (once per level, as in Sec. 4.1, when groups = 1); with test_entries =
+ *    T > 0 the test after a group is taken only when at least T entries were read since
+ *    the level's previous test, or the group is the level's last; groups without entries
+ *    that directly follow a tested group are tested with it (they add nothing, so the
+ *    k-th inner product is the same).  T = 0 tests after every group;
  *  - the filter threshold tau_i is fixed for the whole level from the top-k as it stood
  *    before the level (64, i.e. no filtering, while fewer than k points are known);
  *  - retrieval (Sec. 4.2 and App. C): per repetition a consumed window [c_lo, c_hi)
@@ -686,7 +690,8 @@ static int accumulate(or_list *top, const or_list *fresh, int32_t k) {
 
 static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, const uint64_t *qsk,
                     int32_t k, double delta, double eps, int32_t B, int32_t rule, int32_t filter_on,
-                    int32_t groups, int64_t *clo, int64_t *chi, or_list *top, or_list *fresh,
+                    int32_t groups, int32_t test_entries, int64_t *clo, int64_t *chi, or_list *top,
+                    or_list *fresh,
                     int32_t *stop_level, int64_t *cnt, int32_t *boundary, int64_t *trace,
                     int64_t *ltrace) {
     const int64_t n = ix->n;
@@ -715,9 +720,14 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
         }
         int64_t *lt = ltrace ? ltrace + (int64_t)i * OR_LT_W : NULL;
         if (lt) lt[0] = tau_int;
-        /* the repetitions in `groups` consecutive groups; the stopping test after each */
+        /* the repetitions in `groups` consecutive groups; the stopping test after a group
+           once test_entries entries were read since the level's previous test (always after
+           the last group, and after a group without entries that follows a tested one) */
+        int64_t since = 0;
+        int prev_tested = 0;
         for (int32_t gi = 0; gi < groups; ++gi) {
         const int32_t j0 = (int32_t)((int64_t)gi * L / groups), j1 = (int32_t)((int64_t)(gi + 1) * L / groups);
+        const int64_t scanned_before = cnt[0];
         fresh->len = 0;
         for (int32_t j = j0; j < j1; ++j) {
             const uint32_t *tc = ix->tcode + (int64_t)j * n;
@@ -770,6 +780,12 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
             }
         }
         if (accumulate(top, fresh, k)) return OR_ENOMEM;
+        const int64_t read = cnt[0] - scanned_before;
+        since += read;
+        const int tested = since >= test_entries || gi == groups - 1 || (read == 0 && prev_tested);
+        prev_tested = tested;
+        if (!tested) continue;
+        since = 0;
         if (lt) {
             lt[3] = cnt[0], lt[4] = cnt[1], lt[5] = cnt[2];
             for (int64_t t = 0; t < top->len; ++t)
@@ -831,17 +847,19 @@ static int walk_one(const or_index *ix, const float *q, const uint32_t *qcode, c
  * group g holding repetitions floor(g L / groups) .. floor((g+1) L / groups) - 1, and the
  * stopping test (oracle_stop_partial, a = the repetitions done) runs after each group: 1
  * is the test once per level of Sec. 4.1, L the test after every repetition of
- * Algorithm 1.  The filter threshold stays fixed for the whole level.
+ * Algorithm 1.  test_entries (>= 0): a group's test is skipped while fewer entries than
+ * that were read since the level's previous test (see walk_one; 0 tests after every
+ * group).  The filter threshold stays fixed for the whole level.
  * Returns 0, OR_EINVAL (bad arguments or a zero / non-finite query row), OR_ENOMEM. */
 int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, const uint32_t *tcode,
                   const uint32_t *tidx, const uint64_t *tsk, int32_t L, int32_t K, int32_t M,
                   const int32_t *sel, int32_t pool, const double *cptab, uint64_t cp_seed,
                   const float *queries, int64_t m, int32_t k, double recall, double eps, int32_t B,
-                  int32_t rule, int32_t filter_on, int32_t groups, int32_t *ids, float *ips, double *ips64,
-                  int32_t *stop_level, int64_t *c_scan, int64_t *c_pass, int64_t *c_rerank,
+                  int32_t rule, int32_t filter_on, int32_t groups, int32_t test_entries, int32_t *ids, float *ips,
+                  double *ips64, int32_t *stop_level, int64_t *c_scan, int64_t *c_pass, int64_t *c_rerank,
                   int32_t *boundary, int64_t *trace, int64_t *ltrace) {
     if (n < 1 || d < 1 || L < 1 || K < 1 || K > 32 || M < 1 || m < 0 || k < 1 || k > n || B < 1 || groups < 1 ||
-        groups > L)
+        groups > L || test_entries < 0)
         return OR_EINVAL;
     if (rule == OR_RULE_POOL && (pool < 1 || cptab)) return OR_EINVAL;
     if (!(recall > 0.0 && recall <= 1.0)) return OR_EINVAL;
@@ -885,8 +903,8 @@ int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, co
             for (int32_t s = 0; s < M; ++s) mysk[s] = qs[(int64_t)s * m + t];
             int64_t cnt[3];
             int32_t sl = 0, bd = 0;
-            int rc = walk_one(&ix, qn + t * d, mycode, mysk, k, delta, eps, B, rule, filter_on, groups, clo, chi,
-                              &top, &fresh, &sl, cnt, &bd, t == 0 ? trace : NULL,
+            int rc = walk_one(&ix, qn + t * d, mycode, mysk, k, delta, eps, B, rule, filter_on, groups, test_entries,
+                              clo, chi, &top, &fresh, &sl, cnt, &bd, t == 0 ? trace : NULL,
                               t == 0 ? ltrace : NULL);
             if (rc) {
                 err = rc;

@@ -53,7 +53,7 @@ class pf_build_opts(ctypes.Structure):
 class pf_search_opts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("B", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("no_filter", ctypes.c_int32), ("timing", ctypes.c_int32), ("no_prefilter", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("groups", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("groups", ctypes.c_int32), ("test_entries", ctypes.c_int32)]
 
 
 class pf_query_stats(ctypes.Structure):
@@ -323,16 +323,17 @@ class Index:
     def search(self, queries, k: int, recall: float, eps: float = 0.0, B: int = 12,
                rule: int = PF_RULE_FILTER, filter: bool = True, timing: bool = False,
                want_ips: bool = True, want_stats: bool = True, prefilter: bool = True,
-               tile: int = None, groups: int = 0) -> SearchResult:
+               tile: int = None, groups: int = 0, test_entries: int = 0) -> SearchResult:
         """tile: kernel tile shape index (None: the default shape); groups: stopping tests per
-        level (0: the library's default)."""
+        level (0: the library's default); test_entries: entries read between two of a level's
+        tests (0: the library's default, negative: a test after every group)."""
         q = _f32(queries)
         m = q.shape[0]
         ids = _empty_like_input(q, (m, k), np.int32, _torch_dtype("int32"))
         ips = _empty_like_input(q, (m, k), np.float32, _torch_dtype("float32")) if want_ips else None
         st = _empty_like_input(q, (m, 7), np.int64, _torch_dtype("int64")) if want_stats else None
         opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1,
-                              0 if tile is None else tile + 1, int(groups))
+                              0 if tile is None else tile + 1, int(groups), int(test_entries))
         pq, mem, stream = _buf(q)
         _check(lib().pf_search_ex(self._h, pq, m, k, recall, ctypes.byref(opts), _buf(ids)[0],
                                   _buf(ips)[0], _buf(st)[0], mem, stream))
@@ -350,9 +351,10 @@ class Index:
     def search_batch(self, queries, ks, recalls, kmax: int, order=None, learned: bool = False,
                      autotune: bool = False, eps: float = 0.0, B: int = 12, rule: int = PF_RULE_FILTER,
                      filter: bool = True, timing: bool = False, prefilter: bool = True,
-                     tile: int = None, groups: int = 0) -> SearchResult:
+                     tile: int = None, groups: int = 0, test_entries: int = 0) -> SearchResult:
         """One persistent launch over all queries with per-query k and recall (work queue);
-        tile: kernel tile shape index (None: the autotuned or cached shape)."""
+        tile: kernel tile shape index (None: the autotuned or cached shape); groups and
+        test_entries as for search."""
         q = _f32(queries)
         m = q.shape[0]
         torch_in = _is_torch(q)
@@ -373,7 +375,7 @@ class Index:
         ips = _empty_like_input(q, (m, kmax), np.float32, _torch_dtype("float32"))
         st = _empty_like_input(q, (m, 7), np.int64, _torch_dtype("int64"))
         opts = pf_search_opts(eps, B, rule, 0 if filter else 1, 1 if timing else 0, 0 if prefilter else 1,
-                              0 if tile is None else tile + 1, int(groups))
+                              0 if tile is None else tile + 1, int(groups), int(test_entries))
         flags = (PF_BATCH_LEARNED if learned else 0) | (PF_BATCH_AUTOTUNE if autotune else 0)
         pq, mem, stream = _buf(q)
         _check(lib().pf_search_batch(self._h, pq, m, _buf(ks_a)[0], _buf(rec_a)[0], kmax, ctypes.byref(opts),

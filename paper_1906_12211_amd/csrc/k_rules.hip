@@ -167,4 +167,6 @@ int32_t rule_table_cols() { return kTauCols; }
 // costs little against a level's work
 int32_t default_groups(int32_t L) { return L < 16 ? L : 16; }
 
+int32_t test_entries_of(int32_t opt) { return opt == 0 ? 256 : (opt < 0 ? 0 : opt); }
+
 } // namespace pf

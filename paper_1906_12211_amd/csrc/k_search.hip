@@ -79,6 +79,7 @@ struct SearchK {
     const int32_t *qtab; // per-query row of stopw (nullable: 0)
     const float *tauv, *stopw;
     int32_t G;           // groups of repetitions per level, the stopping test after each (1..64)
+    int32_t tmin;        // ... once at least tmin entries were read since the previous test
     int32_t filter;
     unsigned int *queue;  // work-queue counter (nullable: static assignment)
     const int32_t *order; // queue position -> query (nullable: identity)
@@ -852,7 +853,11 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             uint32_t gbeg = 0;
             bool stop = false;
             for (int32_t g = 0; g < p.G;) {
-            const uint32_t gend = __builtin_amdgcn_readfirstlane(__shfl(gend_mine, g));
+            // groups g .. h up to the next test: h is the first group whose end lies at least
+            // tmin entries past gbeg, else the level's last group
+            const uint64_t far = __ballot(lane >= g && lane < p.G && gend_mine - gbeg >= (uint32_t)p.tmin);
+            const int32_t h = far ? (int32_t)__builtin_ctzll(far) : p.G - 1;
+            const uint32_t gend = __builtin_amdgcn_readfirstlane(__shfl(gend_mine, h));
             if (g > 0) {
                 sg = (int)__builtin_amdgcn_readfirstlane(__shfl(gseg_mine, g - 1)) - 1;
                 segEnd = 0;
@@ -950,13 +955,13 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             }
             wave_merge(l, st);
             // the next group with entries (G if none): the groups before it add nothing, so
-            // the tests after g and after each of them see the same k-th inner product and
+            // the tests after h and after each of them see the same k-th inner product and
             // one ballot takes them in order
-            const uint64_t more = __ballot(lane > g && lane < p.G && gend_mine > gend);
+            const uint64_t more = __ballot(lane > h && lane < p.G && gend_mine > gend);
             const int32_t nxt = more ? (int32_t)__builtin_ctzll(more) : p.G;
             if (st.top == st.k) {
                 const float ipk = key_ip(l.top[st.k - 1]);
-                stop = __ballot(lane >= g && lane < nxt && ipk >= thr_mine) != 0;
+                stop = __ballot(lane >= h && lane < nxt && ipk >= thr_mine) != 0;
                 if (!stop && nxt == p.G && p.filter) {
                     // largest h with ipk <= tauv[h] (-1 if none): lanes test h = lane, one load each
                     const uint64_t mk = __ballot(ipk <= p.tauv[lane]);
@@ -1162,6 +1167,7 @@ int64_t launch_search(Index &ix, const SearchArgs &a, const uint32_t *ranges, hi
     p.tauv = a.tauv;
     p.stopw = a.stopw;
     p.G = a.groups;
+    p.tmin = a.test_entries;
     p.filter = a.filter;
     p.queue = a.queue;
     p.order = a.order;

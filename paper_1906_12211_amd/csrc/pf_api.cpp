@@ -808,6 +808,7 @@ static void search_impl(pf_index *ix, const float *queries, int64_t m, const int
     a.stopw = ix->rule_tab.as<float>() + 65;
     a.B = o.B;
     a.groups = G;
+    a.test_entries = test_entries_of(o.test_entries);
     a.filter = filt;
     a.prefilter = o.no_prefilter ? 0 : 1;
     a.queue = nullptr;

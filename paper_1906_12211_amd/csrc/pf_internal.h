@@ -249,6 +249,7 @@ struct SearchArgs {
     const float *tauv;     // 65 filter-threshold boundaries (see k_search.hip)
     const float *stopw;    // ndelta x K x groups x 66 stopping thresholds
     int32_t groups;        // groups of repetitions per level, the stopping test after each
+    int32_t test_entries;  // ... once at least this many entries were read since the previous test
     int32_t B, filter;
     int32_t prefilter;     // 1: rule candidates out on the upper-plane inner product bound
     unsigned int *queue;   // device work-queue counter (nullable: static assignment)
@@ -268,6 +269,9 @@ void launch_rule_tables(const double *lndeltas_dev, int32_t ndelta, double eps, 
                         float *tauv, float *stopw, hipStream_t s);
 // groups of repetitions per level when a call asks for the default (0)
 int32_t default_groups(int32_t L);
+// entries read between two stopping tests of a level for pf_search_opts.test_entries
+// (0: the default, 256; negative: 0, a test after every group)
+int32_t test_entries_of(int32_t opt);
 // FHT-CP table codes of rows X (n x dpad) into codes (L x n); see k_hash.hip
 void cp_codes(const Index &ix, const float *X, int64_t n, uint32_t *codes, hipStream_t s);
 int32_t rule_table_cols();

@@ -129,6 +129,7 @@ static void noalloc_search(pf_index *ix, const float *queries, int64_t m, int32_
     a.stopw = tab + 65;
     a.B = 12;
     a.groups = G;
+    a.test_entries = test_entries_of(0);
     a.filter = 1;
     a.prefilter = 1;
     a.queue = nullptr;

@@ -166,6 +166,10 @@ def test_prefix_widths(K, P, suffix):
     (10, 0.9, {"groups": 1}), (10, 0.9, {"groups": 4}), (10, 0.9, {"groups": 40}), (1, 0.99, {"groups": 3, "B": 1}),
     (10, 0.9, {"groups": 7, "rule": pf.PF_RULE_EXACT}), (5, 0.99, {"groups": 13, "rule": pf.PF_RULE_ALG1}),
     (37, 0.8, {"groups": 40, "rule": pf.PF_RULE_EXACT, "eps": 0.2}),
+    (10, 0.9, {"test_entries": -1}), (10, 0.9, {"test_entries": 1}), (10, 0.9, {"test_entries": 300}),
+    (1, 0.99, {"test_entries": 5000}), (10, 0.9, {"test_entries": 700, "groups": 7}),
+    (37, 0.8, {"test_entries": 2000, "rule": pf.PF_RULE_EXACT, "groups": 40}),
+    (5, 0.9, {"test_entries": 10 ** 7, "B": 1}),
 ])
 def test_search_variants(k, recall, kw):
     X = workloads.gaussian_unit(5000, 48, 21)
@@ -175,6 +179,8 @@ def test_search_variants(k, recall, kw):
     if "filter" in okw:
         okw["filter_on"] = okw.pop("filter")
     okw.pop("prefilter", None)
+    if okw.get("test_entries", 0) < 0:
+        okw["test_entries"] = 0  # the library's negative value: a test after every group
     gr = g.search(Q, k, recall, **kw)
     orr = o.search(Q, k, recall, **okw)
     _assert_search_equal(gr, orr, f"k={k} r={recall} {kw}")

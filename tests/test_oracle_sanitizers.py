@@ -37,7 +37,7 @@ int oracle_search(const float *points, int64_t n, int32_t d, const float *hp, co
                   const uint32_t *tidx, const uint64_t *tsk, int32_t L, int32_t K, int32_t M, const int32_t *sel,
                   int32_t pool, const double *cptab, uint64_t cp_seed, const float *queries, int64_t m, int32_t k,
                   double recall, double eps, int32_t B, int32_t rule, int32_t filter_on, int32_t groups,
-                  int32_t *ids, float *ips,
+                  int32_t test_entries, int32_t *ids, float *ips,
                   double *ips64, int32_t *stop_level, int64_t *c_scan, int64_t *c_pass, int64_t *c_rerank,
                   int32_t *boundary, int64_t *trace, int64_t *ltrace);
 int oracle_bruteforce(const float *points, int64_t n, int32_t d, const float *queries, int64_t m, int32_t k,
@@ -100,7 +100,8 @@ int main(void) {
                     const double rc = rule == 3 ? 0.5 : recs[b];
                     const int rc_ = oracle_search(X, n, d, hp, tcode, tidx, tsk, L, K, M, sel, pool, cptab, 42, Q, m,
                                                   k, rc, 0.1 * b, Bs[(a + b) % 3], rule, (a + b + rule) % 2 == 0,
-                                                  1 + (a * 3 + b) % L, ids, ips, ip64, stop, cs, cp, cr, bd, tr, lt);
+                                                  1 + (a * 3 + b) % L, (a * 300 + b * 700) % 1200, ids, ips, ip64,
+                                                  stop, cs, cp, cr, bd, tr, lt);
                     if (rc_) return 6;
                     ++runs;
                 }

@@ -67,13 +67,13 @@ def test_walk_with_groups_stops_no_later(oracle_mod):
     Q = workloads.gaussian_unit(60, 24, 32)
     ix = oracle_mod.OracleIndex(X, budget=0, L=24, seed=7, M=4)
     for rule in (oracle_mod.RULE_FILTER, oracle_mod.RULE_EXACT, oracle_mod.RULE_ALG1):
-        base = ix.search(Q, 10, 0.9, rule=rule, groups=1)
-        dflt = ix.search(Q, 10, 0.9, rule=rule)
-        assert np.array_equal(dflt.c_scan, ix.search(Q, 10, 0.9, rule=rule, groups=16).c_scan)
+        base = ix.search(Q, 10, 0.9, rule=rule, groups=1, test_entries=0)
+        dflt = ix.search(Q, 10, 0.9, rule=rule, test_entries=0)
+        assert np.array_equal(dflt.c_scan, ix.search(Q, 10, 0.9, rule=rule, groups=16, test_entries=0).c_scan)
         assert np.all(dflt.c_scan <= base.c_scan)
         earlier = 0
         for G in (2, 5, 24):
-            r = ix.search(Q, 10, 0.9, rule=rule, groups=G)
+            r = ix.search(Q, 10, 0.9, rule=rule, groups=G, test_entries=0)
             assert np.all(r.c_scan <= base.c_scan) and np.all(r.stop_level >= base.stop_level)
             earlier += int(np.sum(r.c_scan < base.c_scan))
         if rule != oracle_mod.RULE_ALG1:
@@ -82,12 +82,12 @@ def test_walk_with_groups_stops_no_later(oracle_mod):
         ix.search(Q, 10, 0.9, groups=25)
 
 
-@pytest.mark.parametrize("G", [6, 3])
-def test_lemma1_guarantee_with_groups_statistical(oracle_mod, G):
+@pytest.mark.parametrize("G,T", [(6, 0), (3, 0), (6, 40)])
+def test_lemma1_guarantee_with_groups_statistical(oracle_mod, G, T):
     """Lemma 1 with the test after each group of repetitions (G = L: after every repetition,
-    as Algorithm 1 writes it): each of the k true nearest neighbours is returned with
-    probability at least 1 - delta over 300 independent index seeds (filter off), within
-    4 sigma."""
+    as Algorithm 1 writes it), or after a group once T entries were read since the previous
+    test: each of the k true nearest neighbours is returned with probability at least
+    1 - delta over 300 independent index seeds (filter off), within 4 sigma."""
     X = workloads.gaussian_unit(400, 8, 21)
     Q = workloads.gaussian_unit(4, 8, 22)
     k, recall = 3, 0.8
@@ -97,7 +97,7 @@ def test_lemma1_guarantee_with_groups_statistical(oracle_mod, G):
     scans = []
     for s in range(seeds):
         ix = oracle_mod.OracleIndex(X, budget=0, L=6, seed=1000 + s, M=1)
-        r = ix.search(Q, k, recall, rule=oracle_mod.RULE_EXACT, filter_on=False, groups=G)
+        r = ix.search(Q, k, recall, rule=oracle_mod.RULE_EXACT, filter_on=False, groups=G, test_entries=T)
         scans.append(r.c_scan)
         for t in range(len(Q)):
             hits[t] += np.isin(true_ids[t], r.ids[t])
@@ -119,7 +119,7 @@ def test_lemma1_guarantee_filter_rule_after_every_repetition(oracle_mod):
     hits = np.zeros((len(Q), k))
     for s in range(seeds):
         ix = oracle_mod.OracleIndex(X, budget=0, L=20, seed=5000 + s, M=4)
-        r = ix.search(Q, k, recall, rule=oracle_mod.RULE_FILTER, filter_on=True, groups=20)
+        r = ix.search(Q, k, recall, rule=oracle_mod.RULE_FILTER, filter_on=True, groups=20, test_entries=0)
         for t in range(len(Q)):
             hits[t] += np.isin(true_ids[t], r.ids[t])
     rate = hits / seeds
@@ -138,3 +138,32 @@ def test_partial_bound_when_a_point_coincides_with_the_query(oracle_mod):
                 for rule in ("RULE_EXACT", "RULE_FILTER"):
                     s, m = oracle_mod.stop_partial(1.0, i, a, L, 24, 0.1, getattr(oracle_mod, rule), M=M, tau_int=30)
                     assert s and m == -math.inf, (L, i, a, rule)
+
+
+def test_test_entries_schedule(oracle_mod):
+    """The stopping test after a group only once T entries were read since the level's
+    previous test (and always after the level's last group): T = 0 is the test after every
+    group; a T above any level's entries leaves only the last group's test, which is the
+    test once per level (groups = 1) and gives the same walk; any T tests at a subset of
+    the every-group points and a superset of the per-level ones, and the walk up to a
+    common point is the same, so a query scans at least the every-group count and at most
+    the per-level count, and some T lies strictly between."""
+    X = workloads.gaussian_unit(4000, 24, 41)
+    Q = workloads.gaussian_unit(80, 24, 42)
+    ix = oracle_mod.OracleIndex(X, budget=0, L=24, seed=9, M=4)
+    for rule in (oracle_mod.RULE_FILTER, oracle_mod.RULE_EXACT):
+        every = ix.search(Q, 10, 0.9, rule=rule, test_entries=0)
+        level = ix.search(Q, 10, 0.9, rule=rule, groups=1, test_entries=0)
+        huge = ix.search(Q, 10, 0.9, rule=rule, test_entries=4000 * 24 + 1)
+        for a, b in ((huge, level),):
+            assert np.array_equal(a.ids, b.ids) and np.array_equal(a.c_scan, b.c_scan)
+            assert np.array_equal(a.stop_level, b.stop_level) and np.array_equal(a.c_pass, b.c_pass)
+        between = 0
+        for T in (1, 50, 300, 1024, 5000):
+            r = ix.search(Q, 10, 0.9, rule=rule, test_entries=T)
+            assert np.all(every.c_scan <= r.c_scan) and np.all(r.c_scan <= level.c_scan), (rule, T)
+            assert np.all(r.stop_level <= every.stop_level) and np.all(r.stop_level >= level.stop_level)
+            between += int(np.sum((every.c_scan < r.c_scan) & (r.c_scan < level.c_scan)))
+        assert between > 0
+    with pytest.raises(ValueError):
+        ix.search(Q, 10, 0.9, test_entries=-1)
