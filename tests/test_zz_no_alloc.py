@@ -2,7 +2,8 @@
 against pf_search on the same index and queries: ids, FP32 inner-product bit patterns and
 per-query statistics equal, on two calls in a row (the second smaller, so the shared
 scratch array holds the first call's contents), for a plain, a pooled and a short-code
-(K <= 13: no prefix ranges) index; oversize batches and bad rows are refused."""
+(K <= 13: no prefix ranges) index and indexes with 3-byte positions and with a 16-bit prefix
+table (8-bit code suffixes); oversize batches and bad rows are refused."""
 import numpy as np
 import pytest
 
@@ -34,7 +35,8 @@ def _same(g, Qd, k, recall, label):
           f"{np.unique(st[:, 0]).tolist()}", flush=True)
 
 
-@pytest.mark.parametrize("kw", [dict(L=40), dict(L=24, pool=512), dict(L=30, K=12)])
+@pytest.mark.parametrize("kw", [dict(L=40), dict(L=24, pool=512), dict(L=30, K=12), dict(L=40, pos_bytes=3),
+                                dict(L=40, prefix_bits=16)])
 def test_noalloc_equals_search_on_two_calls(kw):
     torch = pytest.importorskip("torch")
     X = workloads.gaussian_unit(20_000, 100, 301)
