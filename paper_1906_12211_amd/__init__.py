@@ -432,8 +432,17 @@ class Index:
         PF_EXPORT_ROWS8: (np.uint8, lambda s: (s.n, 8 + 4 * ((s.d + 3) // 4))),
     }
 
-    def export(self, what: int) -> np.ndarray:
+    def export(self, what: int, device: bool = False):
+        """A copy of an index structure: numpy on the host, or a torch tensor on the current
+        device when device=True (written on torch's current stream)."""
         dt, shp = self._EXPORT[what]
+        if device:
+            import torch
+
+            out = torch.from_numpy(np.empty(shp(self), dtype=dt)).cuda()
+            pq, _, stream = _buf(out)
+            _check(lib().pf_export(self._h, what, pq, out.numel() * out.element_size(), PF_DEVICE, stream))
+            return out
         out = np.empty(shp(self), dtype=dt)
         _check(lib().pf_export(self._h, what, _buf(out)[0], out.nbytes, PF_HOST, None))
         return out

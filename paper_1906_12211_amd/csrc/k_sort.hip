@@ -366,7 +366,8 @@ void pack_positions(const uint32_t *in, int64_t count, int32_t posb, uint8_t *ou
     // first padding byte; the pack below rewrites the position bytes among them)
     launch_fill_u32(reinterpret_cast<uint32_t *>(out + (count * posb) / 4 * 4), 2, 0u, s);
     if (posb == 4) {
-        PF_HIP(hipMemcpyAsync(out, in, (size_t)count * 4, hipMemcpyDeviceToDevice, s));
+        if (static_cast<const void *>(in) != static_cast<const void *>(out))
+            PF_HIP(hipMemcpyAsync(out, in, (size_t)count * 4, hipMemcpyDeviceToDevice, s));
         return;
     }
     const int64_t groups = (count + 3) / 4;

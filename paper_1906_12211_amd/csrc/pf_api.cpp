@@ -500,11 +500,15 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
             PF_HIP(hipMemcpyAsync(&ix->s8, ix->Xqh.p, sizeof(float), hipMemcpyDeviceToHost, s));
             PF_HIP(hipMemcpyAsync(&ix->a8, gmax.as<uint32_t>() + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         }
-        // a6: sorted tables (the full codes only while the index is built)
-        DevBuf tcode, tidx;
+        // a6: sorted tables (the full codes only while the index is built); 4-byte positions
+        // are sorted into the index's array, 3-byte ones into a 4-byte array packed below
+        DevBuf tcode, wide;
         tcode.alloc((size_t)L * n * sizeof(uint32_t));
-        tidx.alloc((size_t)L * n * sizeof(uint32_t));
-        sort_tables(codes.as<uint32_t>(), n, (int32_t)L, K, tcode.as<uint32_t>(), tidx.as<uint32_t>(), scratch, s);
+        ix->posb = bp.posb;
+        ix->tpos.alloc((size_t)L * n * ix->posb + (size_t)kPosPad);
+        if (ix->posb != 4) wide.alloc((size_t)L * n * sizeof(uint32_t));
+        uint32_t *tidx = ix->posb == 4 ? ix->tpos.as<uint32_t>() : wide.as<uint32_t>();
+        sort_tables(codes.as<uint32_t>(), n, (int32_t)L, K, tcode.as<uint32_t>(), tidx, scratch, s);
         // a7: prefix tables, then the codes' low K - P bits (the prefix table holds the rest)
         ix->off.alloc((size_t)L * ((1ull << ix->P) + 1) * sizeof(uint32_t));
         prefix_tables(tcode.as<uint32_t>(), n, (int32_t)L, K, ix->P, ix->off.as<uint32_t>(), s);
@@ -515,12 +519,9 @@ PF_API int pf_build_index(const float *points, int64_t n, int32_t d, uint64_t bu
         }
         // a8: table-local sketches
         ix->tsk.alloc((size_t)L * n * sizeof(uint64_t));
-        gather_sketches(tidx.as<uint32_t>(), sk.as<uint64_t>(), n, (int32_t)L, M, ix->tsk.as<uint64_t>(), s);
-        // the positions in the fewest whole bytes that hold them (the 4-byte array only while
-        // the index is built)
-        ix->posb = bp.posb;
-        ix->tpos.alloc((size_t)L * n * ix->posb + (size_t)kPosPad);
-        pack_positions(tidx.as<uint32_t>(), (int64_t)L * n, ix->posb, ix->tpos.as<uint8_t>(), s);
+        gather_sketches(tidx, sk.as<uint64_t>(), n, (int32_t)L, M, ix->tsk.as<uint64_t>(), s);
+        // the stored positions (in place for 4 bytes) and the padding after them
+        pack_positions(tidx, (int64_t)L * n, ix->posb, ix->tpos.as<uint8_t>(), s);
         PF_HIP(hipEventRecord(e1, s));
         PF_HIP(hipStreamSynchronize(s));
         float ms = 0;
@@ -981,11 +982,18 @@ PF_API int pf_export(const pf_index *ix, int32_t what, void *dst, int64_t dst_by
         }
         case PF_EXPORT_IDX: {
             need((int64_t)ix->L * n * 4);
-            DevBuf pos;
-            pos.alloc((size_t)ix->L * n * 4);
-            unpack_positions(ix->tpos.as<uint8_t>(), (int64_t)ix->L * n, ix->posb, pos.as<uint32_t>(), s);
-            PF_HIP(hipMemcpyAsync(dst, pos.p, (size_t)ix->L * n * 4, kind, s));
-            PF_HIP(hipStreamSynchronize(s));
+            const int64_t count = (int64_t)ix->L * n;
+            if (ix->posb == 4) {
+                PF_HIP(hipMemcpyAsync(dst, ix->tpos.p, (size_t)count * 4, kind, s));
+            } else if (mem == PF_DEVICE) {
+                unpack_positions(ix->tpos.as<uint8_t>(), count, ix->posb, static_cast<uint32_t *>(dst), s);
+            } else {
+                DevBuf pos;
+                pos.alloc((size_t)count * 4);
+                unpack_positions(ix->tpos.as<uint8_t>(), count, ix->posb, pos.as<uint32_t>(), s);
+                PF_HIP(hipMemcpyAsync(dst, pos.p, (size_t)count * 4, kind, s));
+                PF_HIP(hipStreamSynchronize(s));
+            }
             break;
         }
         case PF_EXPORT_SKETCHES:

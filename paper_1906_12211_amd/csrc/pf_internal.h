@@ -233,6 +233,7 @@ constexpr int64_t kPosPad = 8;
 int32_t pos_bytes_for(int64_t n, int32_t want);
 // the search kernel for an index with 3-byte positions (row chunks dt, tile, shared-scale rows)
 const void *search_kernel_pos3(int dt, int tile, bool shared);
+// (pack_positions with posb 4 and in == out only writes the padding)
 void pack_positions(const uint32_t *in, int64_t count, int32_t posb, uint8_t *out, hipStream_t s);
 void unpack_positions(const uint8_t *in, int64_t count, int32_t posb, uint32_t *out, hipStream_t s);
 

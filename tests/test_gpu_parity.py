@@ -132,6 +132,8 @@ def test_table_positions_any_count(n, L):
     assert (g3.pos_bytes, g4.pos_bytes) == (3, 4)
     _assert_index_equal(g3, o)
     assert np.array_equal(g4.export(pf.PF_EXPORT_IDX), o.tidx)
+    for g in (g3, g4):  # widened on the device into device memory, too
+        assert np.array_equal(g.export(pf.PF_EXPORT_IDX, device=True).cpu().numpy(), o.tidx)
     assert g4.info().bytes_device - g3.info().bytes_device == L * n
     r3, r4 = g3.search(Q, 10, 0.9), g4.search(Q, 10, 0.9)
     assert np.array_equal(r3.ids, r4.ids) and np.array_equal(r3.stats[:, :4], r4.stats[:, :4])
