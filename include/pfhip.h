@@ -155,7 +155,8 @@ typedef struct {
 
 typedef struct {
     int64_t n;
-    int32_t d, L, K, M, P, pool; /* pool: m of a pooled index, 0 otherwise */
+    int32_t d, L, K, M, P, pool; /* P: prefix-table width (pf_build_opts.prefix_bits);
+                                    pool: m of a pooled index, 0 otherwise */
     int32_t family;              /* PF_FAMILY_* of the table codes               */
     uint64_t bytes_budget_rule; /* bytes the budget rule counts for this index (fixed +
                                    L per_table, see pf_build_index)                      */
