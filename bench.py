@@ -121,16 +121,17 @@ def search_device_sha(src: bytes = None) -> str:
     return hashlib.sha256(code.encode()).hexdigest()
 
 
-def traffic_entry(workload: str, tile_name: str, L: int, pos_bytes: int, prefix_bits: int):
+def traffic_entry(workload: str, tile_name: str, L: int, pos_bytes: int, prefix_bits: int, groups: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary of this workload,
-    if it was taken on the current search kernel source, with the tile shape, table count
-    and table layout (position and prefix widths) this run launched."""
+    if it was taken on the current search kernel source, with the tile shape, table count,
+    table layout (position and prefix widths) and stopping-test groups this run launched."""
     path = traffic_file(workload)
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
     if (t.get("k_search_device_sha256") != search_device_sha() or t.get("tile_name") != tile_name
-            or t.get("L") != L or t.get("pos_bytes") != pos_bytes or t.get("prefix_bits") != prefix_bits):
+            or t.get("L") != L or t.get("pos_bytes") != pos_bytes or t.get("prefix_bits") != prefix_bits
+            or t.get("groups") != groups):
         return None
     return t.get("bytes_per_launch")
 
@@ -439,7 +440,8 @@ def headline(args, dev):
         "filter_share_of_bytes": F / A,
         "roofline": {"kernel": "k_search", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_entry(args.workload, tname, info.L, info.pos_bytes, info.P),
+                     "traffic": traffic_entry(args.workload, tname, info.L, info.pos_bytes, info.P,
+                                             int(ix.last_timing().groups)),
                      "measured_read_gbs": read_gbs, "frac_of_measured_read": achieved / read_gbs,
                      "algorithmic_bytes_per_launch": A, "avg_launch_ms": kms, "queries_per_launch": m,
                      "fp32_gather_bytes_per_launch": plain_gather_bytes(stats, d, k, info.L, info.pos_bytes),
