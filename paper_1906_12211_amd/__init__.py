@@ -439,7 +439,7 @@ class Index:
         if device:
             import torch
 
-            out = torch.from_numpy(np.empty(shp(self), dtype=dt)).cuda()
+            out = torch.empty(shp(self), dtype=getattr(torch, np.dtype(dt).name), device="cuda")
             pq, _, stream = _buf(out)
             _check(lib().pf_export(self._h, what, pq, out.numel() * out.element_size(), PF_DEVICE, stream))
             return out
