@@ -844,9 +844,9 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
             // threshold (tau changes only at the end of a level); +2 (never) elsewhere
             const float thr_mine = lane < p.G ? stopw[((i - 1) * p.G + lane) * kTauCols + (tau + 1)] : 2.0f;
             wsync();
-            // each lane's entries f = base + u * 64 + lane only grow within a group, so it
-            // walks the group's segments once, keeping the current one's end and base
-            // offset in registers
+            // each lane's entries f = base + u * 64 + lane only grow between two tests, so it
+            // walks the segments of those groups once, keeping the current one's end and
+            // base offset in registers
             int sg = -1;
             uint32_t segEnd = 0, ebase = 0;
             uint64_t tqc = 0; // the query's sketch for the current segment's table
@@ -963,7 +963,7 @@ __global__ __launch_bounds__(WV) __attribute__((amdgpu_waves_per_eu(TL::WPE))) v
                 const float ipk = key_ip(l.top[st.k - 1]);
                 stop = __ballot(lane >= h && lane < nxt && ipk >= thr_mine) != 0;
                 if (!stop && nxt == p.G && p.filter) {
-                    // largest h with ipk <= tauv[h] (-1 if none): lanes test h = lane, one load each
+                    // largest t with ipk <= tauv[t] (-1 if none): lane t tests t, one load each
                     const uint64_t mk = __ballot(ipk <= p.tauv[lane]);
                     tau = (ipk <= p.tauv[64]) ? 64 : (mk ? 63 - __clzll((long long)mk) : -1);
                 }
