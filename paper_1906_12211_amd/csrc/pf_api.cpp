@@ -555,8 +555,9 @@ void learned_order(Index &ix, const uint32_t *qcode, const uint64_t *qsk, int64_
 // ------------------------------------------------------------------ autotuner
 // Tile shapes of the batched search kernel (sketch loads and rows in flight per lane)
 // and the number of resident query waves per CU are timed on the batch itself; the
-// fastest is kept per (architecture, n, d, L, kmax) in memory and, when the environment
-// variable PF_TUNE_CACHE names a file, in that file as JSON lines.
+// fastest is kept per (architecture, n, d, L, kmax, position width: the two widths run
+// different kernels) in memory and, when the environment variable PF_TUNE_CACHE names a
+// file, in that file as JSON lines.
 struct TuneChoice {
     int32_t tile = search_default_tile(), waves = 0;
     double us_per_query = 0.0;
@@ -569,7 +570,7 @@ static std::string tune_key(const Index &ix, int32_t kmax) {
     const size_t c = arch.find(':');
     if (c != std::string::npos) arch = arch.substr(0, c);
     return arch + "|n" + std::to_string(ix.n) + "|d" + std::to_string(ix.d) + "|L" + std::to_string(ix.L) +
-           "|k" + std::to_string(kmax);
+           "|k" + std::to_string(kmax) + "|p" + std::to_string(ix.posb);
 }
 
 static bool tune_cache_read(const std::string &key, TuneChoice &out) {

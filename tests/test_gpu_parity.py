@@ -524,6 +524,11 @@ def test_tune_cache_file(tmp_path, monkeypatch):
     o = oracle.OracleIndex(X, 0, seed=9, L=20)
     oids, oips, ost, obd = _oracle_per_query(o, Q, ks, rec, 10)
     _assert_batch_equal(r3, oids, oips, ost, obd, "after a stale cache entry")
+    # an index of the same shape with 3-byte positions runs other kernels: its own entry
+    g4 = pf.Index(X, 0, seed=9, L=20, pos_bytes=3)
+    g4.search_batch(Q, ks, rec, 10, autotune=True, timing=True)
+    keys = [json.loads(line)["key"] for line in cache.read_text().splitlines()]
+    assert len(set(keys)) == 2 and any(k.endswith("|p3") for k in keys), keys
 
 
 def test_batch_device_tensors():
