@@ -209,8 +209,9 @@ const char *pf_tile_name(int32_t t);
 #define PF_BATCH_LEARNED 1  /* order the work queue longest-predicted-first by the
                                scheduler attached with pf_index_set_scheduler */
 #define PF_BATCH_AUTOTUNE 2 /* time the built tile shapes on this batch and keep the fastest
-                               (cached per architecture and index shape; also in the JSON-lines
-                               file named by the environment variable PF_TUNE_CACHE) */
+                               (cached per architecture, index shape, kmax and position width;
+                               also in the JSON-lines file named by the environment variable
+                               PF_TUNE_CACHE) */
 
 /* Normalise n rows to unit length (Sec. 4.2, "Vector storage"): squared norm summed in
  * FP64 in index order, FP64 square root and division, each quotient rounded once to
