@@ -13,25 +13,28 @@
 
 namespace pf {
 
-static constexpr int kLoads = 8;       // code loads in flight per lane
-static constexpr int kGroupMax = 4080; // buckets up to this size: one 16-lane group per pair, else
-                                       // one binary search per bound and level
+static constexpr int kLoads = 8; // code loads in flight per lane
+// buckets of at most 255 W entries (so that no lane counts more than 255 in a bin): one group
+// of W lanes per pair; larger ones: one binary search per bound and level
+template <int W> constexpr uint32_t group_max() { return 255u * W; }
 
-// One 16-lane group (a DPP row) per (q, j) pair: the group reads its bucket 16 kLoads
-// entries at a time (16 consecutive codes per load instruction, kLoads in flight), each lane
-// counts its entries per (lcp - P, lt) in 8-bit fields of NR registers per flag (bin b
-// in byte b & 3 of register b >> 2; at most ceil(kGroupMax / 16) = 255 entries per lane),
-// the fields are widened to 16 bits and summed over the row, and lane r writes level
-// P + 1 + r.  Pairs with larger buckets are appended to the list for k_ranges_wave.
-template <int NR, class S>
+// One group of W lanes (a DPP row for W = 16, half of one for W = 8) per (q, j) pair: the
+// group reads its bucket W kLoads entries at a time (W consecutive codes per load
+// instruction, kLoads in flight), each lane counts its entries per (lcp - P, lt) in 8-bit
+// fields of NR registers per flag (bin b in byte b & 3 of register b >> 2; at most 255
+// entries per lane), the fields are widened to 16 bits and summed over the group, and lane r
+// writes levels P + 1 + r, P + 1 + r + W, ...  Pairs with larger buckets are appended to the
+// list for k_ranges_wave.  W = 8 suits small buckets: twice as many pairs per wave.
+template <int NR, int W, class S>
 __global__ __launch_bounds__(256) void k_ranges_group(const S *__restrict__ tsuf,
                                                       const uint32_t *__restrict__ off, int64_t n, int32_t L,
                                                       int32_t K, int32_t P, const uint32_t *__restrict__ qcode,
                                                       int64_t m, uint32_t *__restrict__ ranges,
                                                       uint32_t *__restrict__ big, uint32_t *__restrict__ nbig) {
-    const int g = threadIdx.x & 15;
-    const int64_t t = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
-    if (t >= m * L) return; // whole rows leave together
+    static_assert(W == 8 || W == 16, "groups of 8 or 16 lanes");
+    const int g = threadIdx.x & (W - 1);
+    const int64_t t = ((int64_t)blockIdx.x * 256 + threadIdx.x) / W;
+    if (t >= m * L) return; // whole groups leave together
     const int64_t q = t / L;
     const int32_t j = (int32_t)(t - q * L);
     const int32_t nl = K - P;
@@ -40,7 +43,7 @@ __global__ __launch_bounds__(256) void k_ranges_group(const S *__restrict__ tsuf
     const uint32_t b = qc >> (K - P);
     const uint32_t B0 = off[(int64_t)j * np1 + b];
     const uint32_t B1 = off[(int64_t)j * np1 + b + 1];
-    if (B1 - B0 > (uint32_t)kGroupMax) {
+    if (B1 - B0 > group_max<W>()) {
         if (g == 0) big[atomicAdd(nbig, 1u)] = (uint32_t)t;
         return;
     }
@@ -50,13 +53,13 @@ __global__ __launch_bounds__(256) void k_ranges_group(const S *__restrict__ tsuf
     uint32_t clt[NR], cge[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) clt[r] = cge[r] = 0;
-    for (uint32_t e0 = B0 + g; e0 < B1; e0 += 16 * kLoads) {
+    for (uint32_t e0 = B0 + g; e0 < B1; e0 += W * kLoads) {
         uint32_t c[kLoads];
 #pragma unroll
-        for (int u = 0; u < kLoads; ++u) c[u] = tc[e0 + 16 * u < B1 ? e0 + 16 * u : B0];
+        for (int u = 0; u < kLoads; ++u) c[u] = tc[e0 + W * u < B1 ? e0 + W * u : B0];
 #pragma unroll
         for (int u = 0; u < kLoads; ++u) {
-            if (e0 + 16 * u < B1) {
+            if (e0 + W * u < B1) {
                 const uint32_t x = (c[u] ^ qs) << sh;
                 const int bin = x ? __clz(x) : nl; // common prefix length beyond the P bits
                 const uint32_t inc = 1u << (8 * (bin & 3));
@@ -70,21 +73,22 @@ __global__ __launch_bounds__(256) void k_ranges_group(const S *__restrict__ tsuf
             }
         }
     }
-    // widen to 16-bit fields (even bytes, odd bytes) and sum over the row
+    // widen to 16-bit fields (even bytes, odd bytes) and sum over the group
+    auto gsum = [](uint32_t v) { return W == 16 ? row_sum16u(v) : half_row_sum8u(v); };
     uint32_t lte[NR], lto[NR], gee[NR], geo[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        lte[r] = row_sum16u(clt[r] & 0x00FF00FFu);
-        lto[r] = row_sum16u((clt[r] >> 8) & 0x00FF00FFu);
-        gee[r] = row_sum16u(cge[r] & 0x00FF00FFu);
-        geo[r] = row_sum16u((cge[r] >> 8) & 0x00FF00FFu);
+        lte[r] = gsum(clt[r] & 0x00FF00FFu);
+        lto[r] = gsum((clt[r] >> 8) & 0x00FF00FFu);
+        gee[r] = gsum(cge[r] & 0x00FF00FFu);
+        geo[r] = gsum((cge[r] >> 8) & 0x00FF00FFu);
     }
-    // lane g writes levels g and g + 16: lo counts lt with bin <= level index, hi counts
-    // not-lt with bin > level index
+    // lane g writes levels g, g + W, ...: lo counts lt with bin <= level index, hi counts
+    // not-lt with bin > level index (nl <= 19 levels)
     uint32_t *out = ranges + t * (int64_t)nl * 2;
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        const int ri = g + 16 * half;
+    for (int half = 0; half < (W == 16 ? 2 : 3); ++half) {
+        const int ri = g + W * half;
         if (ri < nl) {
             uint32_t lo = B0, hi = B0;
 #pragma unroll
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(256) void k_ranges_group(const S *__restrict__ tsuf
     }
 }
 
-// one wave per listed (q, j) pair (bucket above kGroupMax entries), waves striding over
+// one wave per listed (q, j) pair (bucket above the group kernel's limit), waves striding over
 // the list: lane 2r + s binary-searches bound s (0: lo, 1: hi) of level P + 1 + r
 template <class S>
 __global__ __launch_bounds__(256) void k_ranges_wave(const S *__restrict__ tsuf,
@@ -141,12 +145,23 @@ __global__ __launch_bounds__(256) void k_ranges_wave(const S *__restrict__ tsuf,
     }
 }
 
-template <int NR, class S> static const void *group_kernel() { return (const void *)k_ranges_group<NR, S>; }
-
-template <class S> static const void *group_kernel_of(int nr) {
-    return nr <= 1 ? group_kernel<1, S>() : nr <= 2 ? group_kernel<2, S>() : nr <= 3 ? group_kernel<3, S>()
-         : nr <= 4 ? group_kernel<4, S>() : group_kernel<5, S>();
+template <int NR, int W, class S> static const void *group_kernel() {
+    return (const void *)k_ranges_group<NR, W, S>;
 }
+
+template <int W, class S> static const void *group_kernel_of(int nr) {
+    return nr <= 1 ? group_kernel<1, W, S>() : nr <= 2 ? group_kernel<2, W, S>() : nr <= 3 ? group_kernel<3, W, S>()
+         : nr <= 4 ? group_kernel<4, W, S>() : group_kernel<5, W, S>();
+}
+
+template <class S> static const void *group_kernel_of(int nr, int w) {
+    return w == 8 ? group_kernel_of<8, S>(nr) : group_kernel_of<16, S>(nr);
+}
+
+// lanes per (query, table) pair: 8 where a P-bit bucket holds at most 64 entries on average
+// (more pairs per wave: 0.14 against 0.19 ms at 1 M points, 15 entries), else 16 (3.2 against
+// 3.4 ms at 10 M points, 152 entries)
+static int group_lanes(const Index &ix) { return (ix.n >> ix.P) <= 64 ? 8 : 16; }
 
 size_t ranges_list_bytes(int64_t m, int32_t L) { return (size_t)(m * L + 1) * sizeof(uint32_t); }
 
@@ -166,8 +181,9 @@ void launch_ranges_into(const Index &ix, const SearchArgs &a, uint32_t *ranges, 
     // registers of 8-bit bin counters per flag: bins lcp - P = 0 .. K - P
     const int nr = (ix.K - ix.P + 1 + 3) / 4;
     const int32_t w = ix.sufw;
-    const void *fn = w == 1 ? group_kernel_of<uint8_t>(nr)
-                   : w == 2 ? group_kernel_of<uint16_t>(nr) : group_kernel_of<uint32_t>(nr);
+    const int W = group_lanes(ix);
+    const void *fn = w == 1 ? group_kernel_of<uint8_t>(nr, W)
+                   : w == 2 ? group_kernel_of<uint16_t>(nr, W) : group_kernel_of<uint32_t>(nr, W);
     const void *tc = ix.tsuf.p;
     const uint32_t *of = ix.off.as<uint32_t>();
     int64_t n = ix.n;
@@ -176,7 +192,7 @@ void launch_ranges_into(const Index &ix, const SearchArgs &a, uint32_t *ranges, 
     int64_t m = a.m;
     void *args[] = {(void *)&tc, (void *)&of, (void *)&n, (void *)&L, (void *)&K, (void *)&P,
                     (void *)&qc, (void *)&m, (void *)&ranges, (void *)&big, (void *)&nbig};
-    PF_HIP(hipLaunchKernel(fn, dim3((unsigned)((pairs * 16 + 255) / 256)), dim3(256), args, 0, s));
+    PF_HIP(hipLaunchKernel(fn, dim3((unsigned)((pairs * W + 255) / 256)), dim3(256), args, 0, s));
     // the list's length is known only on the device: a fixed grid strides over it
     const int64_t wg = std::min<int64_t>((pairs + 3) / 4, (int64_t)ix.num_cus * 8);
     if (w == 1)

@@ -32,6 +32,14 @@ __device__ __forceinline__ uint32_t row_sum16u(uint32_t s) {
     return s;
 }
 
+// sum over the 8 lanes of each half of a DPP row (every lane of the half gets it)
+__device__ __forceinline__ uint32_t half_row_sum8u(uint32_t s) {
+    s += dpp_u<0xB1>(s);  // quad_perm [1, 0, 3, 2]
+    s += dpp_u<0x4E>(s);  // quad_perm [2, 3, 0, 1]
+    s += dpp_u<0x141>(s); // row_half_mirror
+    return s;
+}
+
 // table position g of a positions array stored in PB bytes each (4, or 3 little endian;
 // a 3-byte array carries 8 bytes of padding so that the word after any entry's last byte
 // can be read)

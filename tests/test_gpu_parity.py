@@ -316,6 +316,19 @@ def test_large_prefix_buckets():
         _assert_batch_equal(g.search_batch(Q, ks, recs, k), oids, oips, ost, obd, f"large buckets batch k={k}")
 
 
+@pytest.mark.parametrize("P", [13, 16])
+def test_range_group_widths(P):
+    """2.2 M points: with 13-bit prefix tables a bucket averages 268 entries and the range
+    counts run on 16-lane groups, with 16-bit tables (33 entries) on 8-lane groups; the walk
+    (ranges through c_scan, ids, inner products) equals the oracle's either way."""
+    X = workloads.gaussian_unit(2_200_000, 16, 961)
+    Q = workloads.gaussian_unit(64, 16, 962)
+    g, o = _build_both(X, L=4, seed=963, M=1, prefix_bits=P)
+    assert g.P == P
+    for k, rec in [(1, 0.9), (10, 0.9)]:
+        _assert_search_equal(g.search(Q, k, rec), o.search(Q, k, rec), f"P={P} k={k}")
+
+
 def test_linear_scan_equals_bruteforce():
     """recall 1: every query walks to level 0 and returns the exact k-NN (Lemma 1)."""
     X = workloads.gaussian_unit(3000, 32, 31)
