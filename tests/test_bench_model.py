@@ -78,3 +78,25 @@ def test_three_byte_positions():
     st = _stats([(6, scan, npass, npass, 0, 0)])
     model = bench.line_model_bytes(st, d, k, L, K, posb=3) - bench.algorithmic_bytes(st, d, k, L, K, 3)
     assert -0.01 * np.mean(simulated) <= np.mean(simulated) - model <= 0.05 * np.mean(simulated)
+
+
+def test_traffic_summary_only_for_its_own_launch(tmp_path, monkeypatch):
+    """The committed counter summary is reported only for the launch it was taken on: the
+    same search-kernel source, tile shape, table count, position and prefix widths and
+    stopping-test groups; any difference gives no traffic figure."""
+    import json
+
+    entry = {"k_search_device_sha256": bench.search_device_sha(), "tile_name": "ept8-u4q8-o4-late-nts", "L": 82,
+             "pos_bytes": 4, "prefix_bits": 16, "groups": 16, "bytes_per_launch": 1.25e13}
+    monkeypatch.setattr(bench, "traffic_file", lambda w: str(tmp_path / f"{w}.json"))
+    (tmp_path / "w.json").write_text(json.dumps(entry))
+    args = ("w", "ept8-u4q8-o4-late-nts", 82, 4, 16, 16)
+    assert bench.traffic_entry(*args) == 1.25e13
+    for i, other in ((1, "ept8-u8"), (2, 88), (3, 3), (4, 13), (5, 64)):
+        changed = list(args)
+        changed[i] = other
+        assert bench.traffic_entry(*changed) is None, i
+    assert bench.traffic_entry("missing", *args[1:]) is None
+    stale = dict(entry, k_search_device_sha256="0" * 64)
+    (tmp_path / "w.json").write_text(json.dumps(stale))
+    assert bench.traffic_entry(*args) is None
